@@ -1,0 +1,289 @@
+/*
+ * mb.h -- C ABI of the MI355X (gfx950) Maxwell-Bloch library, libmbhip.so.
+ *
+ * The library advances the one-dimensional Maxwell-Bloch equations of the
+ * mbsolve paper (Sec. 2.1, eq:efield, eq:hfield, eq:master1D) on a Yee grid
+ * (Sec. 2.2, eq:ediscrete, eq:hdiscrete; update form eq:eupdate,
+ * eq:hupdate of Sec. 3.2) with the density matrices of an N-level quantum
+ * system in every grid cell, weakly coupled in time (Fig. 1: rho lives at
+ * t_{n+1/2} at the E nodes), without rotating-wave or slowly-varying
+ * envelope approximations.  The density step is the exact-step/operator
+ * splitting family of Sec. 2.2: a Strang splitting
+ *     rho^{n+1/2} = e^{L0 dt/2} W_n e^{L0 dt/2} rho^{n-1/2},
+ *     W_n(rho) = exp(+i dt E^n mu / hbar) rho exp(-i dt E^n mu / hbar),
+ * where L0 = -i/hbar [H0, .] + D and D is the relaxation superoperator given
+ * by scattering and pure-dephasing rates (eq:relax_pop and the dephasing
+ * law of Sec. 3.1.1).  The polarization current of eq:ediscrete is
+ * n3D tr{mu L0(rho^{n+1/2})} (Sec. 2; the field part drops out because
+ * tr{mu [mu, rho]} = 0).  The step order is that of Alg. 1: H and rho (and p),
+ * then E, then edges, sources and records.
+ *
+ * Conventions
+ *  - SI units.  The caller passes hbar, c0, mu0, eps0 and e explicitly.
+ *  - Operators are Hermitian N x N matrices given as a real diagonal plus the
+ *    upper triangle packed column by column, (1,2),(1,3),(2,3),(1,4),...,
+ *    each complex entry as (re, im) doubles (qm_operator, Sec. 3.1.1).
+ *  - rates[i*N + j] = gamma_ij, the scattering rate from level j into
+ *    level i (eq:relax_pop); the diagonal is ignored.  Pure dephasing rates
+ *    use the packed pair order.
+ *  - Grid: nx E nodes at x_m = m dx, dx = length/(nx-1); H nodes at
+ *    x_{m+1/2}, m = 0..nx-2.  The material of a node is the first region
+ *    with x_start <= x < x_end, else the first with x_start <= x <= x_end,
+ *    else the right-most region if x exceeds the device by under dx/2.
+ *  - Edges: reflectivity 1 is a perfect electric conductor (E = 0),
+ *    reflectivity 0 a first-order Mur absorbing boundary.  Other values are
+ *    rejected with MB_ERR_UNSUPPORTED.
+ *  - Sources act after each step at t_{n+1} = (n+1) dt: a hard source sets E
+ *    at its cell, a soft source adds to it.  A hard source also sets E^0.
+ *  - Records are sampled after step n when (n+1) is a multiple of their
+ *    interval; density quantities refer to rho^{n+1/2}, E to E^{n+1}, H to
+ *    H^{n+1/2}.  Every record value is delivered in double precision.
+ *
+ * Ownership: every host pointer passed in is read during the call only (the
+ * library copies what it keeps).  Device memory belongs to the library and is
+ * released by the matching destroy call.  Handles are not thread-safe; use one
+ * handle per thread.  The server is internally synchronised.
+ *
+ * Errors: functions return MB_OK (0), a positive warning, or a negative
+ * error code; mb_last_error() gives a thread-local message for the last
+ * non-zero status.  No C++ exception crosses this boundary.
+ */
+#ifndef MB_H
+#define MB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define MB_OK 0
+#define MB_WARN_NOT_CP 1        /* pure dephasing admits no positive semi-definite C (Sec. 3.1.1) */
+#define MB_ERR_ARG -1           /* invalid argument or inconsistent description */
+#define MB_ERR_CFL -2           /* c_max * dt > dx: time step beyond the Courant limit (Sec. 3.2) */
+#define MB_ERR_UNSUPPORTED -3   /* level count outside 2..6, reflectivity outside {0, 1}, ... */
+#define MB_ERR_OOM -4           /* device allocation failed */
+#define MB_ERR_BUDGET -5        /* a request does not fit the server's device-memory budget */
+#define MB_ERR_HIP -6           /* a HIP runtime call failed */
+#define MB_ERR_NONFINITE -7     /* a simulation produced a non-finite field value */
+#define MB_ERR_STATE -8         /* call out of order (e.g. reading a request not yet done) */
+
+/* ---- enumerations -------------------------------------------------------- */
+#define MB_SRC_SECH 0   /* s(t) = amp sech(width t' - shift) sin(2 pi freq t + phase) */
+#define MB_SRC_GAUSS 1  /* s(t) = amp exp(-(width t' - shift)^2) sin(2 pi freq t + phase) */
+                        /* t' = t - q period, summed over q = 0..count-1 */
+
+#define MB_REC_E 0       /* E at the cell                    */
+#define MB_REC_H 1       /* H at x_{cell+1/2} (0 at the last cell) */
+#define MB_REC_POP 2     /* rho_ii                           */
+#define MB_REC_INV 3     /* rho_jj - rho_ii                  */
+#define MB_REC_RHO_RE 4  /* Re rho_ij                        */
+#define MB_REC_RHO_IM 5  /* Im rho_ij                        */
+
+#define MB_VARIANT_AUTO 0     /* blocked kernel, tile shape from the tuner / defaults */
+#define MB_VARIANT_PLAIN 1    /* two launches per step (Alg. 1 as written), FP64 only */
+#define MB_VARIANT_BLOCKED 2  /* temporally blocked overlapped tiles, FP64 or FP32 */
+
+/* ---- description ------------------------------------------------------- */
+typedef struct mb_qm {
+  int32_t levels;            /* N in 2..6 */
+  int32_t two_level;         /* 1: use the simplified two-level form below, 0: general form */
+  double n3d;                /* density of quantum systems [1/m^3] */
+  /* general form (two_level == 0) */
+  const double *h0_diag;     /* N reals [J] */
+  const double *h0_off;      /* N(N-1)/2 complex (re, im) [J], packed by columns */
+  const double *mu_diag;     /* N reals [C m] (may be NULL: zero) */
+  const double *mu_off;      /* N(N-1)/2 complex (re, im) [C m] */
+  const double *rates;       /* N*N, rates[i*N+j] = gamma_ij = rate j -> i [1/s] */
+  const double *pure_deph;   /* N(N-1)/2 [1/s] */
+  /* two-level form (Sec. 3.1.1, qm_desc_2lvl): H0 = hbar w21/2 diag(-1, 1),
+   * mu = -e z21 sigma_x, gamma_12 = g1 (1-w0)/2, gamma_21 = g1 (1+w0)/2,
+   * gamma_12,p = g2 - g1/2 */
+  double omega21, z21, gamma1, gamma2, w0;
+} mb_qm;
+
+typedef struct mb_material {
+  double eps_r, mu_r;
+  double alpha0;             /* field loss [1/m]; sigma = 2 alpha0 sqrt(eps/mu) (Sec. 3.1.1) */
+  double overlap;            /* Gamma of eq:efield */
+  const mb_qm *qm;           /* NULL: no quantum system */
+} mb_material;
+
+typedef struct mb_region {
+  double x_start, x_end;     /* [m] */
+  int32_t material;          /* index into the material list */
+} mb_region;
+
+typedef struct mb_device_desc {
+  double length;             /* [m] */
+  double refl_left, refl_right;  /* 0 or 1 */
+  int32_t n_materials;       /* at most 255 */
+  const mb_material *materials;
+  int32_t n_regions;
+  const mb_region *regions;
+} mb_device_desc;
+
+typedef struct mb_source {
+  int32_t kind;              /* MB_SRC_* */
+  int32_t hard;              /* 1 hard, 0 soft */
+  int64_t cell;
+  double amp, freq, shift, width, phase, period;
+  int32_t count;             /* pulses in the train (>= 1) */
+} mb_source;
+
+typedef struct mb_record {
+  int32_t quantity;          /* MB_REC_* */
+  int32_t i, j;              /* 0-based levels */
+  int64_t cell;              /* -1: every cell (nx values per sample) */
+  int64_t interval;          /* steps between samples, >= 1 */
+} mb_record;
+
+typedef struct mb_consts {
+  double hbar, e, c0, mu0, eps0;
+} mb_consts;
+
+typedef struct mb_scenario_desc {
+  int64_t nx;                /* 1 (single-point Lindblad solve, Sec. 3.2) or >= 3 */
+  double dt;                 /* [s] */
+  int64_t n_steps;
+  int32_t precision;         /* 64 or 32: arithmetic of the bulk field and density updates */
+  int32_t variant;           /* MB_VARIANT_* */
+  int32_t block;             /* blocked variant: threads per tile (0 = default) */
+  int32_t depth;             /* blocked variant: steps per launch = halo width (0 = default) */
+  const double *rho_diag;    /* N reals: initial density matrix (ic_density_const) */
+  const double *rho_off;     /* N(N-1)/2 complex (re, im) */
+  const double *e_init;      /* nx initial E values, or NULL for zero */
+  int32_t n_sources;
+  const mb_source *sources;
+  int32_t n_records;
+  const mb_record *records;
+  mb_consts consts;
+} mb_scenario_desc;
+
+typedef struct mb_handle mb_handle;
+typedef struct mb_batch mb_batch;
+typedef struct mb_server mb_server;
+
+/* Thread-local text for the last non-zero status of this thread. */
+const char *mb_last_error(void);
+
+/* Number of HIP devices visible (0 when none). */
+int mb_device_count(void);
+
+/* ---- host-only plan queries (no GPU needed) ------------------------------ */
+
+/* Builds the FP64 plan on the host and copies the tables of material
+ * `material` in the order lam[N] (ascending eigenvalues of mu), vec[2*N*N]
+ * (the eigenvectors as the columns of a row-major complex N x N matrix V,
+ * (re, im) pairs), kappa[N-1]
+ * (dt (lam_q - lam_{q+1}) / hbar), p0, at[M], ah[M*M], bh[M], am[M*M],
+ * bf[M] with M = N*N - 1: the running state sigma (populations 0..N-2 and
+ * (Re, Im) of the packed pairs, in the eigen-basis of mu) advances as
+ * y = rotation of sigma by E (coherence (j,k) times e^{i E sum kappa}),
+ * p = at . y + p0, sigma' = y + am y + bf, and rho^{n+1/2} = ah y + bh
+ * (rho = V rho' V^+ in the original basis).
+ * Returns the plan status (MB_OK, MB_WARN_NOT_CP or an error). */
+int mb_plan_material(const mb_device_desc *dev, const mb_scenario_desc *scen, int32_t material,
+                     double *out, int64_t capacity, int64_t *n_out);
+
+/* Readout of record `record_id` for cells of material `material`:
+ * out[0] + sum_a out[1+a] y_a gives the recorded density quantity from the
+ * post-rotation state y (M+1 doubles). */
+int mb_plan_readout(const mb_device_desc *dev, const mb_scenario_desc *scen, int32_t record_id,
+                    int32_t material, double *out, int64_t capacity);
+
+/* ---- single simulation --------------------------------------------------- */
+
+/* Validates the description, computes every FP64 table on the host
+ * (coefficients a', b', c' of Sec. 3.2, the Liouvillian and its
+ * exponentials, the field eigen-basis, source values, record plan), allocates
+ * device memory on HIP device `hip_device` and uploads the initial state.
+ * Returns MB_WARN_NOT_CP (with a valid handle) when a material's dephasing
+ * rates admit no completely positive dissipator. */
+int mb_setup(int hip_device, const mb_device_desc *dev, const mb_scenario_desc *scen,
+             mb_handle **out);
+
+/* Enqueues n_steps time steps (-1: all remaining) on `hip_stream` (a
+ * hipStream_t, NULL = the legacy default stream).  Asynchronous. */
+int mb_run(mb_handle *h, int64_t n_steps, void *hip_stream);
+
+/* Steps done so far. */
+int64_t mb_steps_done(const mb_handle *h);
+
+/* Samples recorded so far for record `record_id` (per-sample width 1 or nx). */
+int mb_record_shape(const mb_handle *h, int record_id, int64_t *n_samples, int64_t *width);
+
+/* Synchronises the handle's last stream and copies the samples of
+ * `record_id` (n_samples * width doubles, sample-major) into `out`. */
+int mb_read_records(mb_handle *h, int record_id, double *out, int64_t capacity, int64_t *n_out);
+
+/* Copies the current state into host buffers (any may be NULL):
+ * e[nx], h[nx] (h[nx-1] = 0), rho[nx*N*N*2] (complex (re, im), row-major
+ * N x N per cell, zero in cells without a quantum system, rho^{n-1/2}).
+ * Synchronises first. */
+int mb_read_state(mb_handle *h, double *e, double *hfield, double *rho);
+
+/* Device-time of all kernels enqueued by mb_run so far, in milliseconds
+ * (HIP events around each mb_run call; synchronises). */
+int mb_elapsed_ms(mb_handle *h, double *ms);
+
+int mb_destroy(mb_handle *h);
+
+/* ---- batches: many independent simulations in one launch sequence -------- */
+
+/* All simulations share precision and variant; the blocked variant runs
+ * every level count in its own kernel per chunk.  Tables and state of all
+ * members live in one device allocation. */
+int mb_batch_setup(int hip_device, int32_t n, const mb_device_desc *devs,
+                   const mb_scenario_desc *scens, mb_batch **out);
+/* Runs every member to its own n_steps (uneven lengths allowed).  When
+ * use_graph != 0 the chunk launches are captured once into a HIP graph and
+ * replayed. */
+int mb_batch_run(mb_batch *b, void *hip_stream, int32_t use_graph);
+int mb_batch_record_shape(const mb_batch *b, int32_t sim, int record_id, int64_t *n_samples,
+                          int64_t *width);
+int mb_batch_read_records(mb_batch *b, int32_t sim, int record_id, double *out,
+                          int64_t capacity, int64_t *n_out);
+int mb_batch_elapsed_ms(mb_batch *b, double *ms);
+int mb_batch_destroy(mb_batch *b);
+
+/* ---- serving: continuous batching of solve requests --------------------- */
+
+/* A server owns `hbm_budget` bytes of device memory and runs up to
+ * `max_slots` solves at a time in FP32 (precision 32) or FP64 (64).  Each
+ * chunk advances every admitted solve by `chunk_steps` steps (or to its end);
+ * between chunks finished solves are retired (records copied to the host,
+ * memory freed) and queued requests whose arrival time has passed are
+ * admitted while slots and memory allow. */
+int mb_server_create(int hip_device, size_t hbm_budget, int32_t max_slots, int32_t precision,
+                     int32_t chunk_steps, mb_server **out);
+/* Queues a request; `arrival_s` is its arrival time in seconds after the
+ * server's clock start (mb_server_start).  Returns MB_ERR_BUDGET when the
+ * request alone exceeds the budget. */
+int mb_server_submit(mb_server *s, const mb_device_desc *dev, const mb_scenario_desc *scen,
+                     double arrival_s, uint64_t *ticket);
+/* Starts the clock and the worker thread that runs the chunk loop. */
+int mb_server_start(mb_server *s);
+/* Blocks until every submitted request is done (or timeout_s passes: returns
+ * MB_ERR_STATE). */
+int mb_server_drain(mb_server *s, double timeout_s);
+/* Cancels a queued or running request; it is retired at the next chunk boundary. */
+int mb_server_cancel(mb_server *s, uint64_t ticket);
+/* Status of a request: 0 queued, 1 running, 2 done, 3 cancelled, or a
+ * negative error it ended with.  Times (seconds on the server clock) may be NULL. */
+int mb_server_status(mb_server *s, uint64_t ticket, int32_t *state, double *t_arrival,
+                     double *t_admit, double *t_done);
+int mb_server_record_shape(mb_server *s, uint64_t ticket, int record_id, int64_t *n_samples,
+                           int64_t *width);
+int mb_server_read_records(mb_server *s, uint64_t ticket, int record_id, double *out,
+                           int64_t capacity, int64_t *n_out);
+/* Aggregate statistics: cell-updates done and busy wall time in seconds. */
+int mb_server_stats(mb_server *s, double *cell_updates, double *busy_s, int64_t *chunks);
+int mb_server_destroy(mb_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MB_H */

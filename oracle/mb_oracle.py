@@ -249,6 +249,8 @@ class Oracle:
         c = prob["consts"]
         self.c = c
         nx = prob["nx"]
+        if nx == 2:
+            raise ValueError("nx must be 1 or at least 3")
         self.nx = nx
         self.dt = prob["dt"]
         self.dx = prob["length"] / (nx - 1) if nx > 1 else 0.0

@@ -1,0 +1,407 @@
+// extern "C" entry points for single simulations and batches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "mb.h"
+#include "launch.hpp"
+#include "runtime.hpp"
+
+namespace mb {
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+}  // namespace mb
+
+using namespace mb;
+
+struct mb_handle {
+  int device = 0;
+  std::unique_ptr<Engine> eng;
+  int id = -1;
+  hipStream_t last_stream = nullptr;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  double ms_done = 0.0;
+};
+
+struct mb_batch {
+  int device = 0;
+  std::unique_ptr<Engine> eng;
+  std::vector<int> ids;
+  hipStream_t last_stream = nullptr;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  double ms_done = 0.0;
+};
+
+namespace {
+
+#define MB_GUARD_BEGIN try {
+#define MB_GUARD_END                                         \
+  }                                                          \
+  catch (const std::exception &ex) {                         \
+    return fail(MB_ERR_ARG, std::string("exception: ") + ex.what()); \
+  }                                                          \
+  catch (...) {                                              \
+    return fail(MB_ERR_ARG, "unknown exception");            \
+  }
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(MB_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int shape_for(const SimPlan &p, int &block, int &halo) {
+  default_shape(p.n, p.precision, block, halo);
+  if (p.block > 0) block = p.block;
+  if (p.depth > 0) halo = p.depth;
+  if (p.variant == MB_VARIANT_PLAIN) return MB_OK;
+  if (!block_supported(block) || halo < 1 || 2 * halo >= block)
+    return fail(MB_ERR_ARG, "blocked variant needs block in {64,...,1024} and 1 <= depth < block/2");
+  return MB_OK;
+}
+
+double drain_events(std::vector<std::pair<hipEvent_t, hipEvent_t>> &ev) {
+  double total = 0.0;
+  for (auto &p : ev) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.second) == hipSuccess && hipEventElapsedTime(&ms, p.first, p.second) == hipSuccess)
+      total += ms;
+    (void)hipEventDestroy(p.first);
+    (void)hipEventDestroy(p.second);
+  }
+  ev.clear();
+  return total;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mb_last_error(void) { return g_last_error.c_str(); }
+
+int mb_device_count(void) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) return 0;
+  return n;
+}
+
+int mb_plan_material(const mb_device_desc *dev, const mb_scenario_desc *scen, int32_t material, double *out,
+                     int64_t capacity, int64_t *n_out) {
+  MB_GUARD_BEGIN
+  SimPlan plan;
+  std::string err;
+  int rc = build_plan(dev, scen, plan, err);
+  if (rc < 0) return fail(rc, err);
+  if (material < 0 || material >= int(plan.mats.size())) return fail(MB_ERR_ARG, "bad material index");
+  const MaterialPlan &mp = plan.mats[material];
+  std::vector<double> v;
+  if (mp.qm) {
+    v.insert(v.end(), mp.lam.begin(), mp.lam.end());
+    for (const cd &z : mp.vec) {
+      v.push_back(z.real());
+      v.push_back(z.imag());
+    }
+    v.insert(v.end(), mp.kappa.begin(), mp.kappa.end());
+    v.push_back(mp.p0);
+    for (auto *t : {&mp.at, &mp.ah, &mp.bh, &mp.am, &mp.bf}) v.insert(v.end(), t->begin(), t->end());
+  }
+  if (int64_t(v.size()) > capacity) return fail(MB_ERR_ARG, "output buffer too small");
+  if (!v.empty()) std::memcpy(out, v.data(), v.size() * sizeof(double));
+  if (n_out) *n_out = int64_t(v.size());
+  if (rc > 0) fail(rc, "pure dephasing rates admit no completely positive dissipator");
+  return rc;
+  MB_GUARD_END
+}
+
+int mb_plan_readout(const mb_device_desc *dev, const mb_scenario_desc *scen, int32_t record_id, int32_t material,
+                    double *out, int64_t capacity) {
+  MB_GUARD_BEGIN
+  SimPlan plan;
+  std::string err;
+  int rc = build_plan(dev, scen, plan, err);
+  if (rc < 0) return fail(rc, err);
+  if (record_id < 0 || record_id >= int(plan.records.size())) return fail(MB_ERR_ARG, "bad record id");
+  if (material < 0 || material >= int(plan.mats.size())) return fail(MB_ERR_ARG, "bad material index");
+  const RecordPlan &rp = plan.records[record_id];
+  const int m1 = plan.m + 1;
+  if (rp.readout.empty() || !plan.mats[material].qm) return fail(MB_ERR_ARG, "no density readout for this pair");
+  if (capacity < m1) return fail(MB_ERR_ARG, "output buffer too small");
+  std::memcpy(out, rp.readout.data() + size_t(material) * m1, size_t(m1) * sizeof(double));
+  return MB_OK;
+  MB_GUARD_END
+}
+
+int mb_setup(int hip_device, const mb_device_desc *dev, const mb_scenario_desc *scen, mb_handle **out) {
+  MB_GUARD_BEGIN
+  if (!out) return fail(MB_ERR_ARG, "null output handle");
+  *out = nullptr;
+  SimPlan plan;
+  std::string err;
+  int rc = build_plan(dev, scen, plan, err);
+  if (rc < 0) return fail(rc, err);
+  int warn = rc;
+  int block = 0, halo = 0;
+  if ((rc = shape_for(plan, block, halo)) < 0) return rc;
+  auto h = std::make_unique<mb_handle>();
+  h->device = hip_device;
+  int variant = plan.variant == MB_VARIANT_PLAIN ? MB_VARIANT_PLAIN : MB_VARIANT_BLOCKED;
+  h->eng = std::make_unique<Engine>(hip_device, plan.precision, variant, block, halo);
+  if ((rc = h->eng->init(err)) < 0) return fail(rc, err);
+  hipStream_t st = nullptr;
+  int id = h->eng->add(std::move(plan), nullptr, st, err);
+  if (id < 0) return fail(id, err);
+  h->id = id;
+  *out = h.release();
+  if (warn > 0) return fail(warn, "pure dephasing rates admit no completely positive dissipator");
+  return MB_OK;
+  MB_GUARD_END
+}
+
+int mb_run(mb_handle *h, int64_t n_steps, void *hip_stream) {
+  MB_GUARD_BEGIN
+  if (!h) return fail(MB_ERR_ARG, "null handle");
+  if (hipSetDevice(h->device) != hipSuccess) return fail(MB_ERR_HIP, "hipSetDevice failed");
+  SimState &s = h->eng->sim(h->id);
+  int64_t remaining = s.plan.n_steps - s.done;
+  if (n_steps < 0 || n_steps > remaining) n_steps = remaining;
+  if (n_steps == 0) return MB_OK;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  h->last_stream = st;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+    return fail(MB_ERR_HIP, "hipEventCreate failed");
+  hipError_t e = h->eng->sync_tables(st);
+  if (e != hipSuccess) return hip_fail(e, "table upload");
+  (void)hipEventRecord(a, st);
+  const int k = h->eng->variant() == MB_VARIANT_PLAIN ? 1 : h->eng->depth();
+  while (n_steps > 0) {
+    int kk = int(std::min<int64_t>(k, n_steps));
+    e = h->eng->chunk(st, kk);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    n_steps -= kk;
+  }
+  (void)hipEventRecord(b, st);
+  h->events.emplace_back(a, b);
+  return MB_OK;
+  MB_GUARD_END
+}
+
+int64_t mb_steps_done(const mb_handle *h) { return h ? h->eng->sim(h->id).done : -1; }
+
+int mb_record_shape(const mb_handle *h, int record_id, int64_t *n_samples, int64_t *width) {
+  if (!h) return fail(MB_ERR_ARG, "null handle");
+  const SimState &s = h->eng->sim(h->id);
+  if (record_id < 0 || record_id >= int(s.plan.records.size())) return fail(MB_ERR_ARG, "bad record id");
+  const RecordPlan &rp = s.plan.records[record_id];
+  if (n_samples) *n_samples = std::min<int64_t>(rp.n_samples, s.done / rp.interval);
+  if (width) *width = rp.width;
+  return MB_OK;
+}
+
+int mb_read_records(mb_handle *h, int record_id, double *out, int64_t capacity, int64_t *n_out) {
+  MB_GUARD_BEGIN
+  if (!h) return fail(MB_ERR_ARG, "null handle");
+  if (hipSetDevice(h->device) != hipSuccess) return fail(MB_ERR_HIP, "hipSetDevice failed");
+  SimState &s = h->eng->sim(h->id);
+  if (record_id < 0 || record_id >= int(s.plan.records.size())) return fail(MB_ERR_ARG, "bad record id");
+  hipError_t e = hipStreamSynchronize(h->last_stream);
+  if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+  std::vector<double> buf;
+  e = h->eng->read_records(h->id, record_id, buf);
+  if (e != hipSuccess) return hip_fail(e, "record copy");
+  if (int64_t(buf.size()) > capacity) return fail(MB_ERR_ARG, "output buffer too small");
+  if (!buf.empty()) std::memcpy(out, buf.data(), buf.size() * sizeof(double));
+  if (n_out) *n_out = int64_t(buf.size());
+  std::vector<int32_t> st;
+  if (h->eng->read_status(st) == hipSuccess && st[s.status_slot])
+    return fail(MB_ERR_NONFINITE, "the simulation produced a non-finite field value");
+  return MB_OK;
+  MB_GUARD_END
+}
+
+int mb_read_state(mb_handle *h, double *e, double *hfield, double *rho) {
+  MB_GUARD_BEGIN
+  if (!h) return fail(MB_ERR_ARG, "null handle");
+  if (hipSetDevice(h->device) != hipSuccess) return fail(MB_ERR_HIP, "hipSetDevice failed");
+  hipError_t er = hipStreamSynchronize(h->last_stream);
+  if (er != hipSuccess) return hip_fail(er, "stream synchronize");
+  er = h->eng->read_state(h->id, e, hfield, rho);
+  if (er != hipSuccess) return hip_fail(er, "state copy");
+  return MB_OK;
+  MB_GUARD_END
+}
+
+int mb_elapsed_ms(mb_handle *h, double *ms) {
+  if (!h || !ms) return fail(MB_ERR_ARG, "null argument");
+  h->ms_done += drain_events(h->events);
+  *ms = h->ms_done;
+  return MB_OK;
+}
+
+int mb_destroy(mb_handle *h) {
+  if (!h) return MB_OK;
+  (void)hipSetDevice(h->device);
+  if (h->last_stream) (void)hipStreamSynchronize(h->last_stream);
+  drain_events(h->events);
+  delete h;
+  return MB_OK;
+}
+
+// ---------------------------------------------------------------- batches
+
+int mb_batch_setup(int hip_device, int32_t n, const mb_device_desc *devs, const mb_scenario_desc *scens,
+                   mb_batch **out) {
+  MB_GUARD_BEGIN
+  if (!out || n < 1 || !devs || !scens) return fail(MB_ERR_ARG, "bad batch arguments");
+  *out = nullptr;
+  std::vector<SimPlan> plans(n);
+  std::string err;
+  for (int i = 0; i < n; ++i) {
+    int rc = build_plan(&devs[i], &scens[i], plans[i], err);
+    if (rc < 0) return fail(rc, "simulation " + std::to_string(i) + ": " + err);
+    if (plans[i].precision != plans[0].precision || (plans[i].variant == MB_VARIANT_PLAIN) != (plans[0].variant == MB_VARIANT_PLAIN))
+      return fail(MB_ERR_ARG, "batch members must share precision and variant");
+  }
+  int block = 0, halo = 0, rc;
+  int nmax = 0;
+  for (auto &p : plans) nmax = std::max(nmax, p.n);
+  SimPlan probe;
+  probe.n = nmax;
+  probe.precision = plans[0].precision;
+  probe.variant = plans[0].variant;
+  probe.block = plans[0].block;
+  probe.depth = plans[0].depth;
+  if ((rc = shape_for(probe, block, halo)) < 0) return rc;
+  auto b = std::make_unique<mb_batch>();
+  b->device = hip_device;
+  int variant = plans[0].variant == MB_VARIANT_PLAIN ? MB_VARIANT_PLAIN : MB_VARIANT_BLOCKED;
+  b->eng = std::make_unique<Engine>(hip_device, plans[0].precision, variant, block, halo);
+  if ((rc = b->eng->init(err)) < 0) return fail(rc, err);
+  for (int i = 0; i < n; ++i) {
+    int id = b->eng->add(std::move(plans[i]), nullptr, nullptr, err);
+    if (id < 0) return fail(id, "simulation " + std::to_string(i) + ": " + err);
+    b->ids.push_back(id);
+  }
+  *out = b.release();
+  return MB_OK;
+  MB_GUARD_END
+}
+
+int mb_batch_run(mb_batch *b, void *hip_stream, int32_t use_graph) {
+  MB_GUARD_BEGIN
+  if (!b) return fail(MB_ERR_ARG, "null batch");
+  if (hipSetDevice(b->device) != hipSuccess) return fail(MB_ERR_HIP, "hipSetDevice failed");
+  Engine &eng = *b->eng;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  b->last_stream = st;
+  int64_t remaining = 0;
+  for (int id : b->ids) {
+    const SimState &s = eng.sim(id);
+    remaining = std::max<int64_t>(remaining, s.plan.n_steps - s.done);
+  }
+  if (remaining <= 0) return MB_OK;
+  hipError_t e = eng.sync_tables(st);
+  if (e != hipSuccess) return hip_fail(e, "table upload");
+  const bool plain = eng.variant() == MB_VARIANT_PLAIN;
+  const int k = plain ? 1 : eng.depth();
+  int64_t chunks = (remaining + k - 1) / k;
+  hipEvent_t ea, eb;
+  if (hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess)
+    return fail(MB_ERR_HIP, "hipEventCreate failed");
+  (void)hipEventRecord(ea, st);
+  if (use_graph && chunks > 1) {
+    const int64_t g = std::min<int64_t>(chunks, plain ? 32 : 64);
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap;
+    if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    for (int64_t q = 0; q < g && e == hipSuccess; ++q) e = eng.launch_only(cap, k);
+    hipError_t e2 = hipStreamEndCapture(cap, &graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipStreamDestroy(cap);
+      return hip_fail(e, "graph capture");
+    }
+    int64_t reps = chunks / g;
+    for (int64_t r = 0; r < reps && e == hipSuccess; ++r) {
+      e = hipGraphLaunch(exec, st);
+      for (int64_t q = 0; q < g; ++q) eng.commit_chunk(k);
+    }
+    for (int64_t q = reps * g; q < chunks && e == hipSuccess; ++q) {
+      e = eng.launch_only(st, k);
+      eng.commit_chunk(k);
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+  } else {
+    for (int64_t q = 0; q < chunks; ++q) {
+      e = eng.chunk(st, k);
+      if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    }
+  }
+  (void)hipEventRecord(eb, st);
+  b->events.emplace_back(ea, eb);
+  return MB_OK;
+  MB_GUARD_END
+}
+
+int mb_batch_record_shape(const mb_batch *b, int32_t sim, int record_id, int64_t *n_samples, int64_t *width) {
+  if (!b || sim < 0 || sim >= int(b->ids.size())) return fail(MB_ERR_ARG, "bad batch member");
+  const SimState &s = b->eng->sim(b->ids[sim]);
+  if (record_id < 0 || record_id >= int(s.plan.records.size())) return fail(MB_ERR_ARG, "bad record id");
+  const RecordPlan &rp = s.plan.records[record_id];
+  if (n_samples) *n_samples = std::min<int64_t>(rp.n_samples, s.done / rp.interval);
+  if (width) *width = rp.width;
+  return MB_OK;
+}
+
+int mb_batch_read_records(mb_batch *b, int32_t sim, int record_id, double *out, int64_t capacity, int64_t *n_out) {
+  MB_GUARD_BEGIN
+  if (!b || sim < 0 || sim >= int(b->ids.size())) return fail(MB_ERR_ARG, "bad batch member");
+  if (hipSetDevice(b->device) != hipSuccess) return fail(MB_ERR_HIP, "hipSetDevice failed");
+  SimState &s = b->eng->sim(b->ids[sim]);
+  if (record_id < 0 || record_id >= int(s.plan.records.size())) return fail(MB_ERR_ARG, "bad record id");
+  hipError_t e = hipStreamSynchronize(b->last_stream);
+  if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+  std::vector<double> buf;
+  e = b->eng->read_records(b->ids[sim], record_id, buf);
+  if (e != hipSuccess) return hip_fail(e, "record copy");
+  if (int64_t(buf.size()) > capacity) return fail(MB_ERR_ARG, "output buffer too small");
+  if (!buf.empty()) std::memcpy(out, buf.data(), buf.size() * sizeof(double));
+  if (n_out) *n_out = int64_t(buf.size());
+  std::vector<int32_t> st;
+  if (b->eng->read_status(st) == hipSuccess && st[s.status_slot])
+    return fail(MB_ERR_NONFINITE, "the simulation produced a non-finite field value");
+  return MB_OK;
+  MB_GUARD_END
+}
+
+int mb_batch_elapsed_ms(mb_batch *b, double *ms) {
+  if (!b || !ms) return fail(MB_ERR_ARG, "null argument");
+  b->ms_done += drain_events(b->events);
+  *ms = b->ms_done;
+  return MB_OK;
+}
+
+int mb_batch_destroy(mb_batch *b) {
+  if (!b) return MB_OK;
+  (void)hipSetDevice(b->device);
+  if (b->last_stream) (void)hipStreamSynchronize(b->last_stream);
+  drain_events(b->events);
+  delete b;
+  return MB_OK;
+}
+
+}  // extern "C"

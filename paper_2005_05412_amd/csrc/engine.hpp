@@ -1,0 +1,70 @@
+// Device-visible tables shared by the kernels and the host runtime.
+#pragma once
+
+#include <cstdint>
+
+namespace mb {
+
+// Per-material coefficient block, element type R (float or double), stride
+// mat_stride(N):  [0] a'  [1] b' Gamma  [2] b'/dx  [3] c' (for H nodes)
+// [4] 1 if the material has quantum systems, then kappa[N-1], p0, at[M],
+// bf[M], am[M*M] (row-major, e^{L0 dt} - I).
+constexpr int kCoefA = 0, kCoefBG = 1, kCoefBD = 2, kCoefH = 3, kCoefQM = 4, kCoefKap = 5;
+__host__ __device__ constexpr int mat_m(int n) { return n > 0 ? n * n - 1 : 0; }
+__host__ __device__ constexpr int coef_p0(int n) { return kCoefKap + (n > 0 ? n - 1 : 0); }
+__host__ __device__ constexpr int coef_at(int n) { return coef_p0(n) + 1; }
+__host__ __device__ constexpr int coef_bf(int n) { return coef_at(n) + mat_m(n); }
+__host__ __device__ constexpr int coef_am(int n) { return coef_bf(n) + mat_m(n); }
+__host__ __device__ constexpr int mat_stride(int n) {
+  return n > 0 ? coef_am(n) + mat_m(n) * mat_m(n) : kCoefKap;
+}
+
+struct DevSource {
+  int64_t cell;
+  int32_t hard;
+  int32_t pad;
+  const double *table;  // s(n dt), n = 0..n_steps
+};
+
+struct DevRecord {
+  int32_t quantity;
+  int32_t whole;        // 1: one value per cell per sample
+  int64_t cell;
+  int64_t interval;
+  double *out;          // samples (x nx when whole)
+  const double *readout;  // density quantities: per material (M+1) doubles
+};
+
+struct DevSim {
+  int64_t nx, n_steps;
+  int64_t start;        // engine step at which this simulation's step 0 runs
+  int32_t parity_off;   // buffer parity of the engine when the simulation joined
+  int32_t n_src;
+  int32_t edge_l, edge_r;  // 0: perfect conductor, 1: first-order Mur
+  double kap_l, kap_r;
+  void *e[2], *h[2], *x[2];  // state buffers of element type R; x: M planes of nx
+  void *p;                   // polarization scratch of the two-launch path
+  const uint8_t *mat_e, *mat_h;
+  const void *mtab;
+  const DevSource *src;
+  const DevRecord *rec;
+  int32_t n_rec, n_rec_all;
+  const int32_t *rec_first;  // nx+1 offsets into rec_ids (records at one cell), or null
+  const int32_t *rec_ids;
+  const int32_t *rec_all;    // whole-domain record ids
+  int32_t *status;           // bit 0: non-finite field seen
+  int32_t pad;
+};
+
+struct DevTile {
+  int32_t sim;  // index in the group's simulation table
+  int32_t c0;   // first output cell
+};
+
+struct DevClock {
+  int64_t n0;      // engine step at the start of the next launch
+  int32_t parity;  // engine buffer parity
+  int32_t pad;
+};
+
+}  // namespace mb

@@ -1,0 +1,722 @@
+// FP64 host plan: grid, FDTD coefficients, Liouvillian and propagators,
+// sources and records.  Written from the paper's definitions (Sec. 2-3);
+// shares nothing with the CPU oracle used by the tests.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <sstream>
+
+namespace mb {
+namespace {
+
+// ---------------------------------------------------------------- small dense helpers
+
+using Mat = std::vector<double>;  // row-major square
+
+Mat matmul(const Mat &a, const Mat &b, int n) {
+  Mat c(size_t(n) * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k) {
+      double aik = a[size_t(i) * n + k];
+      if (aik == 0.0) continue;
+      for (int j = 0; j < n; ++j) c[size_t(i) * n + j] += aik * b[size_t(k) * n + j];
+    }
+  return c;
+}
+
+double norm1(const Mat &a, int n) {
+  double best = 0.0;
+  for (int j = 0; j < n; ++j) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += std::fabs(a[size_t(i) * n + j]);
+    best = std::max(best, s);
+  }
+  return best;
+}
+
+// Matrix exponential by scaling and squaring of a truncated Taylor series
+// (Moler & Van Loan, "Nineteen dubious ways", methods 1 and 3): the scaled
+// matrix has 1-norm <= 1/4, where 30 Taylor terms leave a remainder far
+// below double rounding.
+Mat expm(const Mat &z, int n) {
+  double nrm = norm1(z, n);
+  int s = 0;
+  while (nrm > 0.25) {
+    nrm *= 0.5;
+    ++s;
+  }
+  double scale = std::ldexp(1.0, -s);
+  Mat zs(z);
+  for (double &v : zs) v *= scale;
+  Mat result(size_t(n) * n, 0.0), term(size_t(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) result[size_t(i) * n + i] = term[size_t(i) * n + i] = 1.0;
+  for (int k = 1; k <= 30; ++k) {
+    term = matmul(term, zs, n);
+    double inv = 1.0 / k, tn = 0.0;
+    for (double &v : term) {
+      v *= inv;
+      tn = std::max(tn, std::fabs(v));
+    }
+    for (size_t q = 0; q < result.size(); ++q) result[q] += term[q];
+    if (tn < 1e-300) break;
+  }
+  for (int q = 0; q < s; ++q) result = matmul(result, result, n);
+  return result;
+}
+
+// Cyclic Jacobi diagonalisation of a complex Hermitian matrix.  Each
+// rotation first removes the phase of a_pq with a diagonal unitary and then
+// applies the real symmetric 2 x 2 Jacobi rotation.  Eigenvalues ascending,
+// eigenvectors in the columns of v.
+void hermitian_eig(int n, std::vector<cd> a, std::vector<double> &lam, std::vector<cd> &v) {
+  v.assign(size_t(n) * n, cd(0, 0));
+  for (int i = 0; i < n; ++i) v[size_t(i) * n + i] = 1.0;
+  auto at = [&](std::vector<cd> &m, int i, int j) -> cd & { return m[size_t(i) * n + j]; };
+  double fro = 0.0;
+  for (auto &x : a) fro += std::norm(x);
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += std::norm(at(a, p, q));
+    if (off <= 1e-34 * fro || off == 0.0) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        cd apq = at(a, p, q);
+        double mag = std::abs(apq);
+        if (mag == 0.0) continue;
+        cd ph = apq / mag;  // e^{i phi}
+        double tau = (at(a, q, q).real() - at(a, p, p).real()) / (2.0 * mag);
+        double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
+        // G = D J with D = diag(1, conj(ph)) on (p, q); A <- G^+ A G, V <- V G
+        cd gpp = c, gpq = s, gqp = -s * std::conj(ph), gqq = c * std::conj(ph);
+        for (int k = 0; k < n; ++k) {  // columns: A G
+          cd akp = at(a, k, p), akq = at(a, k, q);
+          at(a, k, p) = akp * gpp + akq * gqp;
+          at(a, k, q) = akp * gpq + akq * gqq;
+          cd vkp = at(v, k, p), vkq = at(v, k, q);
+          at(v, k, p) = vkp * gpp + vkq * gqp;
+          at(v, k, q) = vkp * gpq + vkq * gqq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows: G^+ (A G)
+          cd apk = at(a, p, k), aqk = at(a, q, k);
+          at(a, p, k) = std::conj(gpp) * apk + std::conj(gqp) * aqk;
+          at(a, q, k) = std::conj(gpq) * apk + std::conj(gqq) * aqk;
+        }
+        at(a, p, q) = 0.0;
+        at(a, q, p) = 0.0;
+      }
+  }
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int x, int y) { return at(a, x, x).real() < at(a, y, y).real(); });
+  lam.resize(n);
+  std::vector<cd> vs(size_t(n) * n);
+  for (int k = 0; k < n; ++k) {
+    lam[k] = at(a, idx[k], idx[k]).real();
+    for (int i = 0; i < n; ++i) vs[size_t(i) * n + k] = at(v, i, idx[k]);
+  }
+  v = vs;
+}
+
+// Smallest eigenvalue of a real symmetric matrix (cyclic Jacobi).
+double sym_min_eig(int n, Mat a) {
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = 0; q < n; ++q) {
+        tot += a[p * n + q] * a[p * n + q];
+        if (p != q) off += a[p * n + q] * a[p * n + q];
+      }
+    if (off <= 1e-32 * tot || off == 0.0) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double apq = a[p * n + q];
+        if (apq == 0.0) continue;
+        double tau = (a[q * n + q] - a[p * n + p]) / (2.0 * apq);
+        double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
+        for (int k = 0; k < n; ++k) {
+          double akp = a[k * n + p], akq = a[k * n + q];
+          a[k * n + p] = c * akp - s * akq;
+          a[k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          double apk = a[p * n + k], aqk = a[q * n + k];
+          a[p * n + k] = c * apk - s * aqk;
+          a[q * n + k] = s * apk + c * aqk;
+        }
+      }
+  }
+  double m = a[0];
+  for (int i = 1; i < n; ++i) m = std::min(m, a[i * n + i]);
+  return m;
+}
+
+// ---------------------------------------------------------------- quantum description
+
+struct QmFull {
+  int n = 0;
+  double n3d = 0;
+  std::vector<cd> h0, mu;     // N x N row-major
+  std::vector<double> rates;  // N x N, rates[i*N+j] = gamma_ij (j -> i)
+  std::vector<double> deph;   // packed pairs
+};
+
+// packed index of the pair (i, j), i < j, in column order
+inline int pair_index(int i, int j) { return j * (j - 1) / 2 + i; }
+
+std::vector<cd> unpack(int n, const double *diag, const double *off) {
+  std::vector<cd> a(size_t(n) * n, cd(0, 0));
+  for (int i = 0; i < n; ++i) a[size_t(i) * n + i] = diag ? diag[i] : 0.0;
+  for (int j = 1; j < n; ++j)
+    for (int i = 0; i < j; ++i) {
+      int q = pair_index(i, j);
+      cd v = off ? cd(off[2 * q], off[2 * q + 1]) : cd(0, 0);
+      a[size_t(i) * n + j] = v;
+      a[size_t(j) * n + i] = std::conj(v);
+    }
+  return a;
+}
+
+int describe(const mb_qm &q, const mb_consts &k, QmFull &out, std::string &err) {
+  int n = q.levels;
+  if (n < 2 || n > kMaxLevels) {
+    err = "level count must be 2..6";
+    return MB_ERR_UNSUPPORTED;
+  }
+  out.n = n;
+  out.n3d = q.n3d;
+  if (q.two_level) {
+    if (n != 2) {
+      err = "two-level form needs levels == 2";
+      return MB_ERR_ARG;
+    }
+    // Sec. 3.1.1: H0 = hbar w21/2 diag(-1, 1), mu = -e z21 sigma_x
+    out.h0 = {cd(-k.hbar * q.omega21 / 2, 0), 0.0, 0.0, cd(k.hbar * q.omega21 / 2, 0)};
+    double m = -k.e * q.z21;
+    out.mu = {0.0, m, m, 0.0};
+    // R = gamma1/2 [[0, 1-w0], [1+w0, 0]], gamma_12,p = gamma2 - gamma1/2
+    out.rates = {0.0, q.gamma1 * (1.0 - q.w0) / 2.0, q.gamma1 * (1.0 + q.w0) / 2.0, 0.0};
+    out.deph = {q.gamma2 - q.gamma1 / 2.0};
+    return MB_OK;
+  }
+  if (!q.h0_diag || !q.rates || !q.pure_deph) {
+    err = "general quantum description needs h0_diag, rates and pure_deph";
+    return MB_ERR_ARG;
+  }
+  out.h0 = unpack(n, q.h0_diag, q.h0_off);
+  out.mu = unpack(n, q.mu_diag, q.mu_off);
+  out.rates.assign(q.rates, q.rates + n * n);
+  for (int i = 0; i < n; ++i) out.rates[i * n + i] = 0.0;
+  out.deph.assign(q.pure_deph, q.pure_deph + pair_count(n));
+  for (double r : out.rates)
+    if (!(r >= 0.0) || !std::isfinite(r)) {
+      err = "scattering rates must be finite and non-negative";
+      return MB_ERR_ARG;
+    }
+  return MB_OK;
+}
+
+// L0(rho) = -i/hbar [H0, rho] + D(rho), D in rate form (eq:relax_pop and the
+// dephasing law, Sec. 3.1.1).  All matrices N x N row-major, original basis.
+void apply_free(const QmFull &q, double hbar, const std::vector<cd> &rho, std::vector<cd> &out) {
+  int n = q.n;
+  out.assign(size_t(n) * n, cd(0, 0));
+  const cd mi(0.0, -1.0 / hbar);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      cd acc(0, 0);
+      for (int k = 0; k < n; ++k)
+        acc += q.h0[size_t(i) * n + k] * rho[size_t(k) * n + j] - rho[size_t(i) * n + k] * q.h0[size_t(k) * n + j];
+      out[size_t(i) * n + j] = mi * acc;
+    }
+  std::vector<double> out_rate(n, 0.0);  // 1/tau_j = sum_{i != j} gamma_ij
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i)
+      if (i != j) out_rate[j] += q.rates[i * n + j];
+  for (int i = 0; i < n; ++i) {
+    cd acc = -out_rate[i] * rho[size_t(i) * n + i];
+    for (int j = 0; j < n; ++j)
+      if (j != i) acc += q.rates[i * n + j] * rho[size_t(j) * n + j];
+    out[size_t(i) * n + i] += acc;
+  }
+  for (int j = 1; j < n; ++j)
+    for (int i = 0; i < j; ++i) {
+      double g = 0.5 * (out_rate[i] + out_rate[j]) + q.deph[pair_index(i, j)];
+      out[size_t(i) * n + j] -= g * rho[size_t(i) * n + j];
+      out[size_t(j) * n + i] -= g * rho[size_t(j) * n + i];
+    }
+}
+
+// Hermitian matrix from the full real vector v (N^2: populations then pairs)
+std::vector<cd> from_real(int n, const std::vector<double> &v) {
+  std::vector<cd> a(size_t(n) * n, cd(0, 0));
+  for (int k = 0; k < n; ++k) a[size_t(k) * n + k] = v[k];
+  for (int j = 1; j < n; ++j)
+    for (int i = 0; i < j; ++i) {
+      int q = pair_index(i, j);
+      cd z(v[n + 2 * q], v[n + 2 * q + 1]);
+      a[size_t(i) * n + j] = z;
+      a[size_t(j) * n + i] = std::conj(z);
+    }
+  return a;
+}
+
+std::vector<double> to_real(int n, const std::vector<cd> &a) {
+  std::vector<double> v(size_t(n) * n, 0.0);
+  for (int k = 0; k < n; ++k) v[k] = a[size_t(k) * n + k].real();
+  for (int j = 1; j < n; ++j)
+    for (int i = 0; i < j; ++i) {
+      int q = pair_index(i, j);
+      v[n + 2 * q] = a[size_t(i) * n + j].real();
+      v[n + 2 * q + 1] = a[size_t(i) * n + j].imag();
+    }
+  return v;
+}
+
+// B = U^+ A U  (to the eigen-basis) or U A U^+ (back)
+std::vector<cd> conj_by(int n, const std::vector<cd> &u, const std::vector<cd> &a, bool to_eig) {
+  std::vector<cd> t(size_t(n) * n, cd(0, 0)), r(size_t(n) * n, cd(0, 0));
+  auto U = [&](int i, int j) { return to_eig ? std::conj(u[size_t(j) * n + i]) : u[size_t(i) * n + j]; };
+  auto Ud = [&](int i, int j) { return to_eig ? u[size_t(i) * n + j] : std::conj(u[size_t(j) * n + i]); };
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      cd acc(0, 0);
+      for (int k = 0; k < n; ++k) acc += U(i, k) * a[size_t(k) * n + j];
+      t[size_t(i) * n + j] = acc;
+    }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      cd acc(0, 0);
+      for (int k = 0; k < n; ++k) acc += t[size_t(i) * n + k] * Ud(k, j);
+      r[size_t(i) * n + j] = acc;
+    }
+  return r;
+}
+
+// x (trace eliminated, M) <-> v (full, N^2): index a < N-1 -> a, else a + 1
+inline int full_index(int n, int a) { return a < n - 1 ? a : a + 1; }
+
+std::vector<double> x_to_full(int n, const double *x) {
+  int m = state_dim(n);
+  std::vector<double> v(size_t(n) * n, 0.0);
+  double tr = 0.0;
+  for (int a = 0; a < m; ++a) v[full_index(n, a)] = x[a];
+  for (int k = 0; k < n - 1; ++k) tr += x[k];
+  v[n - 1] = 1.0 - tr;
+  return v;
+}
+
+void build_quantum(MaterialPlan &mp, const QmFull &q, double dt, const mb_consts &k) {
+  int n = q.n, m = state_dim(n), nn = n * n;
+  mp.qm = true;
+  mp.n = n;
+  mp.n3d = q.n3d;
+  hermitian_eig(n, q.mu, mp.lam, mp.vec);
+  mp.kappa.resize(n - 1);
+  for (int i = 0; i + 1 < n; ++i) mp.kappa[i] = dt * (mp.lam[i] - mp.lam[i + 1]) / k.hbar;
+  // full real generator in the eigen-basis: column a = L0' applied to basis a
+  Mat gfull(size_t(nn) * nn, 0.0);
+  std::vector<cd> out;
+  for (int a = 0; a < nn; ++a) {
+    std::vector<double> e(nn, 0.0);
+    e[a] = 1.0;
+    std::vector<cd> rho = conj_by(n, mp.vec, from_real(n, e), false);  // to original basis
+    apply_free(q, k.hbar, rho, out);
+    std::vector<double> col = to_real(n, conj_by(n, mp.vec, out, true));
+    for (int r = 0; r < nn; ++r) gfull[size_t(r) * nn + a] = col[r];
+  }
+  // trace elimination: rho_{N-1,N-1} = 1 - sum_{k<N-1} x_k
+  mp.gen.assign(size_t(m) * m, 0.0);
+  mp.gen_off.assign(m, 0.0);
+  for (int a = 0; a < m; ++a) {
+    int ra = full_index(n, a);
+    mp.gen_off[a] = gfull[size_t(ra) * nn + (n - 1)];
+    for (int b = 0; b < m; ++b) {
+      int cb = full_index(n, b);
+      double v = gfull[size_t(ra) * nn + cb];
+      if (b < n - 1) v -= gfull[size_t(ra) * nn + (n - 1)];
+      mp.gen[size_t(a) * m + b] = v;
+    }
+  }
+  // augmented generator [[G, g], [0, 0]] -> exponentials of dt/2 and dt
+  int ma = m + 1;
+  Mat z(size_t(ma) * ma, 0.0);
+  for (int a = 0; a < m; ++a) {
+    for (int b = 0; b < m; ++b) z[size_t(a) * ma + b] = mp.gen[size_t(a) * m + b] * (dt / 2);
+    z[size_t(a) * ma + m] = mp.gen_off[a] * (dt / 2);
+  }
+  Mat half = expm(z, ma);
+  Mat full = matmul(half, half, ma);
+  mp.ah.assign(size_t(m) * m, 0.0);
+  mp.bh.assign(m, 0.0);
+  mp.am.assign(size_t(m) * m, 0.0);
+  mp.bf.assign(m, 0.0);
+  for (int a = 0; a < m; ++a) {
+    for (int b = 0; b < m; ++b) {
+      mp.ah[size_t(a) * m + b] = half[size_t(a) * ma + b];
+      mp.am[size_t(a) * m + b] = full[size_t(a) * ma + b] - (a == b ? 1.0 : 0.0);
+    }
+    mp.bh[a] = half[size_t(a) * ma + m];
+    mp.bf[a] = full[size_t(a) * ma + m];
+  }
+  // p = n3D tr{mu' L0'(rho')} = n3D sum_{k<N-1} (lam_k - lam_{N-1}) xdot_k,
+  // xdot = G (ah y + bh) + g
+  std::vector<double> c(m, 0.0);
+  for (int kk = 0; kk < n - 1; ++kk) c[kk] = q.n3d * (mp.lam[kk] - mp.lam[n - 1]);
+  std::vector<double> cg(m, 0.0);  // c^T G
+  for (int b = 0; b < m; ++b)
+    for (int a = 0; a < m; ++a) cg[b] += c[a] * mp.gen[size_t(a) * m + b];
+  mp.at.assign(m, 0.0);
+  for (int b = 0; b < m; ++b)
+    for (int a = 0; a < m; ++a) mp.at[b] += cg[a] * mp.ah[size_t(a) * m + b];
+  double p0 = 0.0;
+  for (int a = 0; a < m; ++a) p0 += cg[a] * mp.bh[a] + c[a] * mp.gen_off[a];
+  mp.p0 = p0;
+  // complete positivity of the pure dephasing: Gram matrix -1/2 J D J, D_ij = 2 gamma_ij,p
+  Mat d(size_t(n) * n, 0.0), jm(size_t(n) * n, 0.0);
+  double dmax = 0.0;
+  for (int j = 1; j < n; ++j)
+    for (int i = 0; i < j; ++i) {
+      d[i * n + j] = d[j * n + i] = 2.0 * q.deph[pair_index(i, j)];
+      dmax = std::max(dmax, std::fabs(d[i * n + j]));
+    }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) jm[i * n + j] = (i == j ? 1.0 : 0.0) - 1.0 / n;
+  Mat g = matmul(matmul(jm, d, n), jm, n);
+  for (double &v : g) v *= -0.5;
+  mp.min_gram_eig = sym_min_eig(n, g) / std::max(dmax, 1e-300);
+}
+
+// value of a density quantity for a full real vector v in the eigen-basis
+double quantity_of(const MaterialPlan &mp, int quantity, int i, int j, const std::vector<double> &v) {
+  int n = mp.n;
+  std::vector<cd> rho = conj_by(n, mp.vec, from_real(n, v), false);
+  switch (quantity) {
+    case MB_REC_POP: return rho[size_t(i) * n + i].real();
+    case MB_REC_INV: return (rho[size_t(j) * n + j] - rho[size_t(i) * n + i]).real();
+    case MB_REC_RHO_RE: return rho[size_t(i) * n + j].real();
+    case MB_REC_RHO_IM: return rho[size_t(i) * n + j].imag();
+  }
+  return 0.0;
+}
+
+// Readout (r0, r) with value = r0 + r . y for the post-rotation state y:
+// rho^{n+1/2} = ah y + bh (affine in y).
+void build_readout(const MaterialPlan &mp, int quantity, int i, int j, double *out) {
+  int n = mp.n, m = state_dim(n);
+  std::vector<double> zero(m, 0.0);
+  double base = quantity_of(mp, quantity, i, j, x_to_full(n, zero.data()));
+  std::vector<double> r(m, 0.0);
+  for (int a = 0; a < m; ++a) {
+    std::vector<double> e(m, 0.0);
+    e[a] = 1.0;
+    r[a] = quantity_of(mp, quantity, i, j, x_to_full(n, e.data())) - base;
+  }
+  double r0 = base;
+  for (int a = 0; a < m; ++a) r0 += r[a] * mp.bh[a];
+  out[0] = r0;
+  for (int b = 0; b < m; ++b) {
+    double acc = 0.0;
+    for (int a = 0; a < m; ++a) acc += r[a] * mp.ah[size_t(a) * m + b];
+    out[1 + b] = acc;
+  }
+}
+
+double source_value(const mb_source &s, double t) {
+  double env = 0.0;
+  int cnt = std::max(1, s.count);
+  for (int q = 0; q < cnt; ++q) {
+    double arg = s.width * (t - q * s.period) - s.shift;
+    if (s.kind == MB_SRC_SECH)
+      env += std::fabs(arg) < 700.0 ? 1.0 / std::cosh(arg) : 0.0;
+    else
+      env += std::exp(-arg * arg);
+  }
+  return s.amp * env * std::sin(2.0 * M_PI * s.freq * t + s.phase);
+}
+
+int region_material(const mb_device_desc *dev, double x, double dx, std::string &err) {
+  for (int r = 0; r < dev->n_regions; ++r)
+    if (dev->regions[r].x_start <= x && x < dev->regions[r].x_end) return dev->regions[r].material;
+  for (int r = 0; r < dev->n_regions; ++r)
+    if (dev->regions[r].x_start <= x && x <= dev->regions[r].x_end) return dev->regions[r].material;
+  int best = -1;
+  double end = -1e300;
+  for (int r = 0; r < dev->n_regions; ++r)
+    if (dev->regions[r].x_end > end) {
+      end = dev->regions[r].x_end;
+      best = r;
+    }
+  if (best >= 0 && x > end && x <= end + 0.5 * dx) return dev->regions[best].material;
+  std::ostringstream os;
+  os << "grid point x=" << x << " lies in no region";
+  err = os.str();
+  return -1;
+}
+
+}  // namespace
+
+bool solve_linear(int n, std::vector<double> a, std::vector<double> &b) {
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(a[size_t(r) * n + c]) > std::fabs(a[size_t(piv) * n + c])) piv = r;
+    if (a[size_t(piv) * n + c] == 0.0) return false;
+    if (piv != c) {
+      for (int k = 0; k < n; ++k) std::swap(a[size_t(c) * n + k], a[size_t(piv) * n + k]);
+      std::swap(b[c], b[piv]);
+    }
+    for (int r = c + 1; r < n; ++r) {
+      double f = a[size_t(r) * n + c] / a[size_t(c) * n + c];
+      if (f == 0.0) continue;
+      for (int k = c; k < n; ++k) a[size_t(r) * n + k] -= f * a[size_t(c) * n + k];
+      b[r] -= f * b[c];
+    }
+  }
+  for (int c = n - 1; c >= 0; --c) {
+    double acc = b[c];
+    for (int k = c + 1; k < n; ++k) acc -= a[size_t(c) * n + k] * b[k];
+    b[c] = acc / a[size_t(c) * n + c];
+  }
+  return true;
+}
+
+void state_to_rho(const MaterialPlan &mp, const double *sigma, cd *rho) {
+  int n = mp.n, m = state_dim(n);
+  std::vector<double> rhs(m);
+  for (int a = 0; a < m; ++a) rhs[a] = sigma[a] - mp.bh[a];
+  solve_linear(m, mp.ah, rhs);
+  std::vector<cd> r = conj_by(n, mp.vec, from_real(n, x_to_full(n, rhs.data())), false);
+  for (int q = 0; q < n * n; ++q) rho[q] = r[q];
+}
+
+int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan &plan,
+               std::string &err) {
+  if (!dev || !scen) {
+    err = "null description";
+    return MB_ERR_ARG;
+  }
+  const mb_consts &k = scen->consts;
+  if (!(k.hbar > 0 && k.c0 > 0 && k.mu0 > 0 && k.eps0 > 0 && k.e > 0)) {
+    err = "physical constants must be positive";
+    return MB_ERR_ARG;
+  }
+  if (scen->nx < 1 || scen->n_steps < 0 || !(scen->dt > 0) || !std::isfinite(scen->dt)) {
+    err = "need nx >= 1, n_steps >= 0 and a positive time step";
+    return MB_ERR_ARG;
+  }
+  if (scen->nx == 2) {
+    err = "nx must be 1 (single point) or at least 3 (two edge nodes and an interior)";
+    return MB_ERR_ARG;
+  }
+  if (scen->nx > (int64_t(1) << 31)) {
+    err = "nx too large";
+    return MB_ERR_ARG;
+  }
+  if (scen->precision != 64 && scen->precision != 32) {
+    err = "precision must be 64 or 32";
+    return MB_ERR_ARG;
+  }
+  if (scen->variant == MB_VARIANT_PLAIN && scen->precision != 64) {
+    err = "the plain variant runs in FP64 only";
+    return MB_ERR_UNSUPPORTED;
+  }
+  if (dev->n_materials < 1 || dev->n_materials > 255 || !dev->materials || dev->n_regions < 1 ||
+      !dev->regions) {
+    err = "need 1..255 materials and at least one region";
+    return MB_ERR_ARG;
+  }
+  for (double r : {dev->refl_left, dev->refl_right})
+    if (r != 0.0 && r != 1.0) {
+      err = "only reflectivities 0 (absorbing) and 1 (mirror) are supported";
+      return MB_ERR_UNSUPPORTED;
+    }
+  for (int r = 0; r < dev->n_regions; ++r)
+    if (dev->regions[r].material < 0 || dev->regions[r].material >= dev->n_materials) {
+      err = "region refers to a missing material";
+      return MB_ERR_ARG;
+    }
+  plan = SimPlan();
+  plan.nx = scen->nx;
+  plan.n_steps = scen->n_steps;
+  plan.dt = scen->dt;
+  plan.precision = scen->precision;
+  plan.variant = scen->variant;
+  plan.block = scen->block;
+  plan.depth = scen->depth;
+  plan.dx = scen->nx > 1 ? dev->length / double(scen->nx - 1) : 0.0;
+  if (scen->nx > 1 && !(plan.dx > 0)) {
+    err = "device length must be positive";
+    return MB_ERR_ARG;
+  }
+  const int64_t nx = plan.nx;
+  plan.mat_e.resize(nx);
+  plan.mat_h.resize(nx, 0);
+  for (int64_t c = 0; c < nx; ++c) {
+    int m = region_material(dev, double(c) * plan.dx, plan.dx, err);
+    if (m < 0) return MB_ERR_ARG;
+    plan.mat_e[c] = uint8_t(m);
+    if (c + 1 < nx) {
+      int mh = region_material(dev, (double(c) + 0.5) * plan.dx, plan.dx, err);
+      if (mh < 0) return MB_ERR_ARG;
+      plan.mat_h[c] = uint8_t(mh);
+    }
+  }
+  // FDTD coefficients per material (Sec. 3.2) and the Courant check
+  plan.mats.resize(dev->n_materials);
+  double c_max = 0.0;
+  int levels = 0;
+  std::vector<QmFull> qms(dev->n_materials);
+  for (int i = 0; i < dev->n_materials; ++i) {
+    const mb_material &mt = dev->materials[i];
+    MaterialPlan &mp = plan.mats[i];
+    if (!(mt.eps_r > 0 && mt.mu_r > 0 && mt.alpha0 >= 0 && std::isfinite(mt.overlap))) {
+      err = "material needs eps_r > 0, mu_r > 0, alpha0 >= 0";
+      return MB_ERR_ARG;
+    }
+    mp.eps_r = mt.eps_r;
+    mp.mu_r = mt.mu_r;
+    mp.alpha0 = mt.alpha0;
+    mp.overlap = mt.overlap;
+    double eps = k.eps0 * mt.eps_r, mu = k.mu0 * mt.mu_r;
+    double sigma = 2.0 * mt.alpha0 * std::sqrt(eps / mu);
+    double q = plan.dt * sigma / (2.0 * eps);
+    double bb = (plan.dt / eps) / (1.0 + q);
+    mp.ca = (1.0 - q) / (1.0 + q);
+    mp.cbg = bb * mt.overlap;
+    mp.cbd = nx > 1 ? bb / plan.dx : 0.0;
+    mp.ch = nx > 1 ? plan.dt / (plan.dx * mu) : 0.0;
+    mp.c_light = 1.0 / std::sqrt(eps * mu);
+    c_max = std::max(c_max, mp.c_light);
+    if (mt.qm) {
+      int rc = describe(*mt.qm, k, qms[i], err);
+      if (rc < 0) return rc;
+      if (levels && levels != qms[i].n) {
+        err = "all quantum materials of one device must have the same level count";
+        return MB_ERR_UNSUPPORTED;
+      }
+      levels = qms[i].n;
+    }
+  }
+  if (nx > 1 && c_max * plan.dt > plan.dx * (1.0 + 1e-12)) {
+    err = "time step exceeds the Courant limit dx / c_max";
+    return MB_ERR_CFL;
+  }
+  plan.n = levels;
+  plan.m = levels ? state_dim(levels) : 0;
+  for (int i = 0; i < dev->n_materials; ++i)
+    if (dev->materials[i].qm) {
+      build_quantum(plan.mats[i], qms[i], plan.dt, k);
+      if (plan.mats[i].min_gram_eig < -1e-9) plan.warn = MB_WARN_NOT_CP;
+    }
+  // edges
+  plan.edge_l = dev->refl_left == 1.0 ? 0 : 1;
+  plan.edge_r = dev->refl_right == 1.0 ? 0 : 1;
+  if (nx > 1) {
+    double cl = plan.mats[plan.mat_e[0]].c_light, cr = plan.mats[plan.mat_e[nx - 1]].c_light;
+    plan.kap_l = (cl * plan.dt - plan.dx) / (cl * plan.dt + plan.dx);
+    plan.kap_r = (cr * plan.dt - plan.dx) / (cr * plan.dt + plan.dx);
+  }
+  // sources: FP64 tables s(n dt), n = 0..n_steps
+  if (scen->n_sources < 0 || (scen->n_sources > 0 && !scen->sources)) {
+    err = "bad source list";
+    return MB_ERR_ARG;
+  }
+  for (int s = 0; s < scen->n_sources; ++s) {
+    const mb_source &src = scen->sources[s];
+    if (src.cell < 0 || src.cell >= nx || (src.kind != MB_SRC_SECH && src.kind != MB_SRC_GAUSS)) {
+      err = "source outside the grid or of unknown kind";
+      return MB_ERR_ARG;
+    }
+    SourcePlan sp;
+    sp.cell = src.cell;
+    sp.hard = src.hard ? 1 : 0;
+    sp.table.resize(plan.n_steps + 1);
+    for (int64_t t = 0; t <= plan.n_steps; ++t) sp.table[t] = source_value(src, double(t) * plan.dt);
+    plan.sources.push_back(std::move(sp));
+  }
+  // records
+  if (scen->n_records < 0 || (scen->n_records > 0 && !scen->records)) {
+    err = "bad record list";
+    return MB_ERR_ARG;
+  }
+  for (int r = 0; r < scen->n_records; ++r) {
+    const mb_record &rc = scen->records[r];
+    RecordPlan rp;
+    rp.quantity = rc.quantity;
+    rp.i = rc.i;
+    rp.j = rc.j;
+    rp.cell = rc.cell;
+    rp.interval = rc.interval;
+    if (rc.quantity < MB_REC_E || rc.quantity > MB_REC_RHO_IM || rc.interval < 1 || rc.cell < -1 ||
+        rc.cell >= nx) {
+      err = "record with unknown quantity, bad interval or cell";
+      return MB_ERR_ARG;
+    }
+    bool dens = rc.quantity >= MB_REC_POP;
+    if (dens && (levels == 0 || rc.i < 0 || rc.j < 0 || rc.i >= levels || rc.j >= levels)) {
+      err = "density record needs quantum cells and levels in range";
+      return MB_ERR_ARG;
+    }
+    if ((rc.quantity == MB_REC_RHO_RE || rc.quantity == MB_REC_RHO_IM) && rc.i == rc.j &&
+        rc.quantity == MB_REC_RHO_IM) {
+      // Im of a diagonal element is identically zero; allowed
+    }
+    rp.width = rc.cell < 0 ? nx : 1;
+    rp.n_samples = plan.n_steps / rp.interval;
+    if (dens) {
+      int m = plan.m;
+      rp.readout.assign(size_t(dev->n_materials) * (m + 1), 0.0);
+      for (int i = 0; i < dev->n_materials; ++i)
+        if (plan.mats[i].qm) build_readout(plan.mats[i], rc.quantity, rc.i, rc.j, &rp.readout[size_t(i) * (m + 1)]);
+    }
+    plan.records.push_back(std::move(rp));
+  }
+  // initial state: E^0 (edges, hard sources at t = 0), sigma_0 = e^{L0 dt/2} rho_init
+  plan.e0.assign(nx, 0.0);
+  if (scen->e_init)
+    for (int64_t c = 0; c < nx; ++c) plan.e0[c] = scen->e_init[c];
+  if (nx > 1) {
+    if (plan.edge_l == 0) plan.e0[0] = 0.0;
+    if (plan.edge_r == 0) plan.e0[nx - 1] = 0.0;
+  }
+  for (auto &sp : plan.sources)
+    if (sp.hard) plan.e0[sp.cell] = sp.table[0];
+  if (levels) {
+    if (!scen->rho_diag) {
+      err = "initial density matrix missing";
+      return MB_ERR_ARG;
+    }
+    int n = levels, m = plan.m;
+    std::vector<cd> rho0 = unpack(n, scen->rho_diag, scen->rho_off);
+    plan.x0.assign(size_t(m) * nx, 0.0);
+    for (int i = 0; i < dev->n_materials; ++i) {
+      const MaterialPlan &mp = plan.mats[i];
+      if (!mp.qm) continue;
+      std::vector<double> v = to_real(n, conj_by(n, mp.vec, rho0, true));
+      std::vector<double> x(m);
+      for (int a = 0; a < m; ++a) x[a] = v[full_index(n, a)];
+      std::vector<double> sig(m);
+      for (int a = 0; a < m; ++a) {
+        double acc = mp.bh[a];
+        for (int b = 0; b < m; ++b) acc += mp.ah[size_t(a) * m + b] * x[b];
+        sig[a] = acc;
+      }
+      for (int64_t c = 0; c < nx; ++c)
+        if (plan.mat_e[c] == i)
+          for (int a = 0; a < m; ++a) plan.x0[size_t(a) * nx + c] = sig[a];
+    }
+  }
+  for (double v : plan.e0)
+    if (!std::isfinite(v)) {
+      err = "non-finite initial field";
+      return MB_ERR_ARG;
+    }
+  return plan.warn;
+}
+
+}  // namespace mb

@@ -1,0 +1,539 @@
+#include "runtime.hpp"
+
+#include <algorithm>
+#include <cstring>
+
+#include "launch.hpp"
+
+namespace mb {
+
+namespace {
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+constexpr int kStatusSlots = 4096;
+
+struct Layout {
+  size_t e, h, x, p, mat_e, mat_h, mtab, src, src_tab, rec, readout, rec_first, rec_ids, rec_all;
+  size_t outputs, end_head, total;
+  std::vector<size_t> tab_off, ro_off, out_off;
+  int n_point = 0, n_all = 0;
+};
+
+Layout layout_of(const SimPlan &p, int precision, bool plain) {
+  Layout L;
+  const size_t rs = precision == 64 ? 8 : 4;
+  const size_t nx = size_t(p.nx);
+  const size_t m = size_t(p.m);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  L.e = take(2 * nx * rs);
+  L.h = take(2 * nx * rs);
+  L.x = take(std::max<size_t>(1, 2 * m * nx) * rs);
+  L.p = take(plain ? nx * rs : rs);
+  L.mat_e = take(nx);
+  L.mat_h = take(nx);
+  L.mtab = take(p.mats.size() * size_t(mat_stride(p.n)) * rs);
+  L.src = take(std::max<size_t>(1, p.sources.size()) * sizeof(DevSource));
+  for (auto &s : p.sources) L.tab_off.push_back(take(s.table.size() * sizeof(double)));
+  L.rec = take(std::max<size_t>(1, p.records.size()) * sizeof(DevRecord));
+  for (auto &r : p.records) {
+    L.ro_off.push_back(r.readout.empty() ? 0 : take(r.readout.size() * sizeof(double)));
+    if (r.cell >= 0)
+      ++L.n_point;
+    else
+      ++L.n_all;
+  }
+  L.rec_first = L.n_point ? take((nx + 1) * sizeof(int32_t)) : 0;
+  L.rec_ids = take(std::max(1, L.n_point) * sizeof(int32_t));
+  L.rec_all = take(std::max(1, L.n_all) * sizeof(int32_t));
+  L.end_head = off;
+  for (auto &r : p.records) L.out_off.push_back(take(size_t(r.n_samples) * size_t(r.width) * sizeof(double)));
+  L.total = off;
+  return L;
+}
+
+template <typename R>
+void fill_mtab(const SimPlan &p, R *out) {
+  const int n = p.n, s = mat_stride(n), m = mat_m(n);
+  for (size_t i = 0; i < p.mats.size(); ++i) {
+    const MaterialPlan &mp = p.mats[i];
+    R *t = out + i * s;
+    t[kCoefA] = R(mp.ca);
+    t[kCoefBG] = R(mp.cbg);
+    t[kCoefBD] = R(mp.cbd);
+    t[kCoefH] = R(mp.ch);
+    if (n == 0) continue;
+    t[kCoefQM] = mp.qm ? R(1) : R(0);
+    for (int q = 0; q < n - 1; ++q) t[kCoefKap + q] = mp.qm ? R(mp.kappa[q]) : R(0);
+    t[coef_p0(n)] = mp.qm ? R(mp.p0) : R(0);
+    for (int a = 0; a < m; ++a) {
+      t[coef_at(n) + a] = mp.qm ? R(mp.at[a]) : R(0);
+      t[coef_bf(n) + a] = mp.qm ? R(mp.bf[a]) : R(0);
+      for (int b = 0; b < m; ++b) t[coef_am(n) + a * m + b] = mp.qm ? R(mp.am[size_t(a) * m + b]) : R(0);
+    }
+  }
+}
+
+template <typename R>
+void fill_state(const SimPlan &p, char *head, const Layout &L) {
+  const size_t nx = size_t(p.nx);
+  R *e = reinterpret_cast<R *>(head + L.e);
+  R *h = reinterpret_cast<R *>(head + L.h);
+  R *x = reinterpret_cast<R *>(head + L.x);
+  for (size_t c = 0; c < nx; ++c) {
+    e[c] = e[nx + c] = R(p.e0[c]);
+    h[c] = h[nx + c] = R(0);
+  }
+  const size_t mn = size_t(p.m) * nx;
+  for (size_t q = 0; q < mn; ++q) x[q] = x[mn + q] = R(p.x0[q]);
+  fill_mtab<R>(p, reinterpret_cast<R *>(head + L.mtab));
+}
+
+}  // namespace
+
+size_t sim_bytes(const SimPlan &p, int precision, bool plain) { return layout_of(p, precision, plain).total; }
+
+void default_shape(int levels, int precision, int &block, int &halo) {
+  (void)precision;
+  if (levels >= 5) {
+    block = 256;
+    halo = 16;
+  } else {
+    block = 256;
+    halo = 32;
+  }
+}
+
+// ---------------------------------------------------------------- Arena
+
+Arena::~Arena() {
+  if (base_) (void)hipFree(base_);
+}
+
+int Arena::init(size_t bytes, std::string &err) {
+  bytes = align_up(bytes);
+  if (hipMalloc(&base_, bytes) != hipSuccess) {
+    base_ = nullptr;
+    err = "device allocation of the serving budget failed";
+    return MB_ERR_OOM;
+  }
+  cap_ = bytes;
+  free_[0] = bytes;
+  return MB_OK;
+}
+
+void *Arena::alloc(size_t bytes) {
+  bytes = align_up(std::max<size_t>(bytes, 1));
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    if (it->second < bytes) continue;
+    size_t off = it->first, sz = it->second;
+    free_.erase(it);
+    if (sz > bytes) free_[off + bytes] = sz - bytes;
+    live_[off] = bytes;
+    used_ += bytes;
+    return base_ + off;
+  }
+  return nullptr;
+}
+
+void Arena::release(void *p) {
+  if (!p) return;
+  size_t off = size_t(static_cast<char *>(p) - base_);
+  auto it = live_.find(off);
+  if (it == live_.end()) return;
+  size_t sz = it->second;
+  live_.erase(it);
+  used_ -= sz;
+  auto nx = free_.lower_bound(off);
+  if (nx != free_.end() && off + sz == nx->first) {
+    sz += nx->second;
+    free_.erase(nx);
+  }
+  auto pv = free_.lower_bound(off);
+  if (pv != free_.begin()) {
+    --pv;
+    if (pv->first + pv->second == off) {
+      pv->second += sz;
+      return;
+    }
+  }
+  free_[off] = sz;
+}
+
+// ---------------------------------------------------------------- Engine
+
+Engine::Engine(int device, int precision, int variant, int block, int halo)
+    : device_(device), precision_(precision), variant_(variant), block_(block), halo_(halo) {}
+
+Engine::~Engine() {
+  for (auto &s : sims_)
+    if (s && s->own_block && s->block) (void)hipFree(s->block);
+  for (auto &g : groups_) {
+    if (g.d_sims) (void)hipFree(g.d_sims);
+    if (g.d_tiles) (void)hipFree(g.d_tiles);
+  }
+  if (d_clk_) (void)hipFree(d_clk_);
+  if (d_status_) (void)hipFree(d_status_);
+}
+
+int Engine::init(std::string &err) {
+  if (hipSetDevice(device_) != hipSuccess) {
+    err = "hipSetDevice failed";
+    return MB_ERR_HIP;
+  }
+  if (variant_ != MB_VARIANT_PLAIN) {
+    if (!block_supported(block_) || halo_ < 1 || 2 * halo_ >= block_) {
+      err = "blocked variant needs block in {64,128,256,512,1024} and 1 <= depth < block/2";
+      return MB_ERR_ARG;
+    }
+  }
+  if (hipMalloc(&d_clk_, sizeof(DevClock)) != hipSuccess ||
+      hipMalloc(&d_status_, kStatusSlots * sizeof(int32_t)) != hipSuccess) {
+    err = "device allocation failed";
+    return MB_ERR_OOM;
+  }
+  DevClock c{0, 0, 0};
+  if (hipMemcpy(d_clk_, &c, sizeof(c), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(d_status_, 0, kStatusSlots * sizeof(int32_t)) != hipSuccess) {
+    err = "device initialisation failed";
+    return MB_ERR_HIP;
+  }
+  status_cap_ = kStatusSlots;
+  for (int i = kStatusSlots - 1; i >= 0; --i) free_slots_.push_back(i);
+  return MB_OK;
+}
+
+Engine::Group &Engine::group_for(int levels) {
+  for (auto &g : groups_)
+    if (g.levels == levels) return g;
+  groups_.push_back(Group());
+  groups_.back().levels = levels;
+  return groups_.back();
+}
+
+int Engine::add(SimPlan &&plan, Arena *arena, hipStream_t st, std::string &err) {
+  const bool plain = variant_ == MB_VARIANT_PLAIN;
+  if (plain && precision_ != 64) {
+    err = "the two-launch variant runs in FP64 only";
+    return MB_ERR_UNSUPPORTED;
+  }
+  if (free_slots_.empty()) {
+    err = "too many simulations in one engine";
+    return MB_ERR_BUDGET;
+  }
+  Layout L = layout_of(plan, precision_, plain);
+  char *block = nullptr;
+  if (arena) {
+    block = static_cast<char *>(arena->alloc(L.total));
+    if (!block) {
+      err = "serving budget exhausted";
+      return MB_ERR_BUDGET;
+    }
+  } else if (hipMalloc(&block, L.total) != hipSuccess) {
+    err = "device allocation failed";
+    return MB_ERR_OOM;
+  }
+  auto s = std::make_unique<SimState>();
+  s->plan = std::move(plan);
+  SimPlan &p = s->plan;
+  s->bytes = L.total;
+  s->block = block;
+  s->own_block = arena == nullptr;
+  // host image of everything before the record outputs
+  std::vector<char> head(L.end_head, 0);
+  if (precision_ == 64)
+    fill_state<double>(p, head.data(), L);
+  else
+    fill_state<float>(p, head.data(), L);
+  char *dev = s->block;
+  std::memcpy(head.data() + L.mat_e, p.mat_e.data(), p.nx);
+  std::memcpy(head.data() + L.mat_h, p.mat_h.data(), p.nx);
+  DevSource *srcs = reinterpret_cast<DevSource *>(head.data() + L.src);
+  for (size_t i = 0; i < p.sources.size(); ++i) {
+    srcs[i].cell = p.sources[i].cell;
+    srcs[i].hard = p.sources[i].hard;
+    srcs[i].table = reinterpret_cast<const double *>(dev + L.tab_off[i]);
+    std::memcpy(head.data() + L.tab_off[i], p.sources[i].table.data(), p.sources[i].table.size() * 8);
+  }
+  DevRecord *recs = reinterpret_cast<DevRecord *>(head.data() + L.rec);
+  std::vector<std::vector<int32_t>> per_cell(L.n_point ? p.nx : 0);
+  std::vector<int32_t> all_ids;
+  for (size_t r = 0; r < p.records.size(); ++r) {
+    const RecordPlan &rp = p.records[r];
+    recs[r].quantity = rp.quantity;
+    recs[r].whole = rp.cell < 0 ? 1 : 0;
+    recs[r].cell = rp.cell;
+    recs[r].interval = rp.interval;
+    recs[r].out = reinterpret_cast<double *>(dev + L.out_off[r]);
+    recs[r].readout = rp.readout.empty() ? nullptr : reinterpret_cast<const double *>(dev + L.ro_off[r]);
+    if (!rp.readout.empty()) std::memcpy(head.data() + L.ro_off[r], rp.readout.data(), rp.readout.size() * 8);
+    if (rp.cell >= 0)
+      per_cell[rp.cell].push_back(int32_t(r));
+    else
+      all_ids.push_back(int32_t(r));
+    s->rec_off.push_back(L.out_off[r]);
+  }
+  if (L.n_point) {
+    int32_t *first = reinterpret_cast<int32_t *>(head.data() + L.rec_first);
+    int32_t *ids = reinterpret_cast<int32_t *>(head.data() + L.rec_ids);
+    int32_t k = 0;
+    for (int64_t c = 0; c < p.nx; ++c) {
+      first[c] = k;
+      for (int32_t id : per_cell[c]) ids[k++] = id;
+    }
+    first[p.nx] = k;
+  }
+  std::memcpy(head.data() + L.rec_all, all_ids.data(), all_ids.size() * sizeof(int32_t));
+  hipError_t he = hipMemcpyAsync(dev, head.data(), head.size(), hipMemcpyHostToDevice, st);
+  if (he == hipSuccess && L.total > L.end_head)
+    he = hipMemsetAsync(dev + L.end_head, 0, L.total - L.end_head, st);
+  if (he == hipSuccess) he = hipStreamSynchronize(st);
+  if (he != hipSuccess) {
+    err = std::string("upload failed: ") + hipGetErrorString(he);
+    if (arena) arena->release(s->block);
+    else (void)hipFree(s->block);
+    return MB_ERR_HIP;
+  }
+  const size_t rs = precision_ == 64 ? 8 : 4;
+  const size_t nx = size_t(p.nx);
+  DevSim &d = s->ds;
+  d.nx = p.nx;
+  d.n_steps = p.n_steps;
+  d.n_src = int32_t(p.sources.size());
+  d.edge_l = p.edge_l;
+  d.edge_r = p.edge_r;
+  d.kap_l = p.kap_l;
+  d.kap_r = p.kap_r;
+  d.e[0] = dev + L.e;
+  d.e[1] = dev + L.e + nx * rs;
+  d.h[0] = dev + L.h;
+  d.h[1] = dev + L.h + nx * rs;
+  d.x[0] = dev + L.x;
+  d.x[1] = dev + L.x + size_t(p.m) * nx * rs;
+  d.p = dev + L.p;
+  d.mat_e = reinterpret_cast<const uint8_t *>(dev + L.mat_e);
+  d.mat_h = reinterpret_cast<const uint8_t *>(dev + L.mat_h);
+  d.mtab = dev + L.mtab;
+  d.src = reinterpret_cast<const DevSource *>(dev + L.src);
+  d.rec = reinterpret_cast<const DevRecord *>(dev + L.rec);
+  d.n_rec = int32_t(p.records.size());
+  d.n_rec_all = int32_t(all_ids.size());
+  d.rec_first = L.n_point ? reinterpret_cast<const int32_t *>(dev + L.rec_first) : nullptr;
+  d.rec_ids = reinterpret_cast<const int32_t *>(dev + L.rec_ids);
+  d.rec_all = reinterpret_cast<const int32_t *>(dev + L.rec_all);
+  s->status_slot = free_slots_.back();
+  free_slots_.pop_back();
+  d.status = d_status_ + s->status_slot;
+  int32_t zero = 0;
+  (void)hipMemcpy(d.status, &zero, sizeof(zero), hipMemcpyHostToDevice);
+  s->start = n0_;
+  s->parity_off = parity_;
+  d.start = s->start;
+  d.parity_off = s->parity_off;
+  s->active = true;
+  int id = int(sims_.size());
+  group_for(p.n).members.push_back(id);
+  sims_.push_back(std::move(s));
+  dirty_ = true;
+  return id;
+}
+
+void Engine::remove(int id, Arena *arena) {
+  SimState &s = *sims_[id];
+  if (s.active) {
+    for (auto &g : groups_) {
+      auto it = std::find(g.members.begin(), g.members.end(), id);
+      if (it != g.members.end()) g.members.erase(it);
+    }
+    s.active = false;
+    dirty_ = true;
+  }
+  if (s.block) {
+    if (s.own_block)
+      (void)hipFree(s.block);
+    else if (arena)
+      arena->release(s.block);
+    s.block = nullptr;
+  }
+  if (s.status_slot >= 0) {
+    free_slots_.push_back(s.status_slot);
+    s.status_slot = -1;
+  }
+  s.plan.sources.clear();
+}
+
+hipError_t Engine::upload_group(Group &g, hipStream_t st) {
+  std::vector<DevSim> hs;
+  std::vector<DevTile> ht;
+  const bool plain = variant_ == MB_VARIANT_PLAIN;
+  const int span = plain ? plain_block() : block_ - 2 * halo_;
+  for (int id : g.members) {
+    const SimState &s = *sims_[id];
+    int32_t local = int32_t(hs.size());
+    hs.push_back(s.ds);
+    for (int64_t c0 = 0; c0 < s.plan.nx; c0 += span) ht.push_back(DevTile{local, int32_t(c0)});
+  }
+  if (int(hs.size()) > g.cap_sims) {
+    if (g.d_sims) (void)hipFree(g.d_sims);
+    g.cap_sims = std::max<int>(int(hs.size()), 2 * g.cap_sims);
+    if (hipMalloc(&g.d_sims, size_t(g.cap_sims) * sizeof(DevSim)) != hipSuccess) return hipErrorOutOfMemory;
+  }
+  if (int(ht.size()) > g.cap_tiles) {
+    if (g.d_tiles) (void)hipFree(g.d_tiles);
+    g.cap_tiles = std::max<int>(int(ht.size()), 2 * g.cap_tiles);
+    if (hipMalloc(&g.d_tiles, size_t(g.cap_tiles) * sizeof(DevTile)) != hipSuccess) return hipErrorOutOfMemory;
+  }
+  hipError_t e = hipSuccess;
+  if (!hs.empty()) e = hipMemcpyAsync(g.d_sims, hs.data(), hs.size() * sizeof(DevSim), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !ht.empty())
+    e = hipMemcpyAsync(g.d_tiles, ht.data(), ht.size() * sizeof(DevTile), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  g.n_tiles = int(ht.size());
+  return e;
+}
+
+hipError_t Engine::sync_tables(hipStream_t st) {
+  if (!dirty_) return hipSuccess;
+  for (auto &g : groups_) {
+    hipError_t e = upload_group(g, st);
+    if (e != hipSuccess) return e;
+  }
+  dirty_ = false;
+  return hipSuccess;
+}
+
+hipError_t Engine::launch_only(hipStream_t st, int k) {
+  if (variant_ == MB_VARIANT_PLAIN) {
+    for (int s = 0; s < k; ++s) {
+      for (auto &g : groups_) {
+        if (g.members.empty()) continue;
+        hipError_t e = launch_plain(g.levels, g.d_sims, g.d_tiles, g.n_tiles, d_clk_, st);
+        if (e != hipSuccess) return e;
+      }
+      hipError_t e = launch_advance(d_clk_, 1, st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  for (auto &g : groups_) {
+    if (g.members.empty()) continue;
+    hipError_t e = launch_blocked(g.levels, precision_, block_, g.d_sims, g.d_tiles, g.n_tiles, d_clk_,
+                                  halo_, k, st);
+    if (e != hipSuccess) return e;
+  }
+  return launch_advance(d_clk_, k, st);
+}
+
+void Engine::commit_chunk(int k) {
+  const bool plain = variant_ == MB_VARIANT_PLAIN;
+  const int sub = plain ? k : 1;          // parity flips per launch
+  const int per = plain ? 1 : k;          // steps per launch
+  for (int q = 0; q < sub; ++q) {
+    for (auto &sp : sims_) {
+      SimState &s = *sp;
+      if (!s.active) continue;
+      int64_t ls = n0_ - s.start;
+      if (ls < 0 || ls >= s.plan.n_steps) continue;
+      int64_t ks = std::min<int64_t>(per, s.plan.n_steps - ls);
+      s.done += ks;
+      cell_updates_ += double(ks) * double(s.plan.nx);
+      int par = parity_ ^ s.parity_off;
+      if (plain) {
+        s.cur_e = par ^ 1;
+        s.cur_h = 0;
+        s.cur_x = 0;
+      } else {
+        s.cur_e = s.cur_h = s.cur_x = par ^ 1;
+      }
+    }
+    n0_ += per;
+    parity_ ^= 1;
+  }
+}
+
+hipError_t Engine::chunk(hipStream_t st, int k) {
+  if (variant_ != MB_VARIANT_PLAIN && (k < 1 || k > halo_)) return hipErrorInvalidValue;
+  hipError_t e = sync_tables(st);
+  if (e != hipSuccess) return e;
+  e = launch_only(st, k);
+  if (e != hipSuccess) return e;
+  commit_chunk(k);
+  return hipSuccess;
+}
+
+bool Engine::finished(int id) const {
+  const SimState &s = *sims_[id];
+  return s.done >= s.plan.n_steps;
+}
+
+bool Engine::all_finished() const {
+  for (auto &s : sims_)
+    if (s->active && s->done < s->plan.n_steps) return false;
+  return true;
+}
+
+hipError_t Engine::read_status(std::vector<int32_t> &out) {
+  out.assign(status_cap_, 0);
+  return hipMemcpy(out.data(), d_status_, size_t(status_cap_) * sizeof(int32_t), hipMemcpyDeviceToHost);
+}
+
+hipError_t Engine::read_records(int id, int rec, std::vector<double> &out) {
+  SimState &s = *sims_[id];
+  const RecordPlan &rp = s.plan.records[rec];
+  int64_t avail = std::min<int64_t>(rp.n_samples, s.done / rp.interval);
+  out.assign(size_t(avail) * size_t(rp.width), 0.0);
+  if (out.empty()) return hipSuccess;
+  return hipMemcpy(out.data(), s.block + s.rec_off[rec], out.size() * sizeof(double), hipMemcpyDeviceToHost);
+}
+
+hipError_t Engine::read_state(int id, double *e, double *h, double *rho) {
+  SimState &s = *sims_[id];
+  const SimPlan &p = s.plan;
+  const size_t nx = size_t(p.nx), m = size_t(p.m);
+  const bool f64 = precision_ == 64;
+  auto fetch = [&](void *src, size_t count, std::vector<double> &dst) -> hipError_t {
+    dst.resize(count);
+    if (f64) return hipMemcpy(dst.data(), src, count * 8, hipMemcpyDeviceToHost);
+    std::vector<float> tmp(count);
+    hipError_t er = hipMemcpy(tmp.data(), src, count * 4, hipMemcpyDeviceToHost);
+    for (size_t i = 0; i < count; ++i) dst[i] = tmp[i];
+    return er;
+  };
+  std::vector<double> buf;
+  hipError_t er;
+  if (e) {
+    if ((er = fetch(s.ds.e[s.cur_e], nx, buf)) != hipSuccess) return er;
+    std::copy(buf.begin(), buf.end(), e);
+  }
+  if (h) {
+    if ((er = fetch(s.ds.h[s.cur_h], nx, buf)) != hipSuccess) return er;
+    std::copy(buf.begin(), buf.end(), h);
+    if (nx) h[nx - 1] = 0.0;
+  }
+  if (rho) {
+    const int n = p.n;
+    std::fill(rho, rho + nx * n * n * 2, 0.0);
+    if (n > 0) {
+      if ((er = fetch(s.ds.x[s.cur_x], m * nx, buf)) != hipSuccess) return er;
+      std::vector<double> sig(m);
+      std::vector<cd> r(size_t(n) * n);
+      for (size_t c = 0; c < nx; ++c) {
+        const MaterialPlan &mp = p.mats[p.mat_e[c]];
+        if (!mp.qm) continue;
+        for (size_t a = 0; a < m; ++a) sig[a] = buf[a * nx + c];
+        state_to_rho(mp, sig.data(), r.data());
+        for (int q = 0; q < n * n; ++q) {
+          rho[(c * n * n + q) * 2] = r[q].real();
+          rho[(c * n * n + q) * 2 + 1] = r[q].imag();
+        }
+      }
+    }
+  }
+  return hipSuccess;
+}
+
+}  // namespace mb

@@ -1,0 +1,120 @@
+// Host runtime: simulations resident on one GPU, grouped by level count,
+// advanced chunk by chunk.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "engine.hpp"
+#include "plan.hpp"
+
+namespace mb {
+
+// First-fit allocator over one device allocation (no hipMalloc/hipFree on
+// the serving path, which would synchronise the device).
+class Arena {
+ public:
+  Arena() = default;
+  ~Arena();
+  int init(size_t bytes, std::string &err);
+  void *alloc(size_t bytes);
+  void release(void *p);
+  size_t capacity() const { return cap_; }
+  size_t used() const { return used_; }
+
+ private:
+  char *base_ = nullptr;
+  size_t cap_ = 0, used_ = 0;
+  std::map<size_t, size_t> free_;  // offset -> size
+  std::map<size_t, size_t> live_;  // offset -> size
+};
+
+struct SimState {
+  SimPlan plan;
+  size_t bytes = 0;
+  char *block = nullptr;       // device memory of this simulation
+  bool own_block = false;      // hipMalloc'ed by the engine
+  DevSim ds{};
+  int64_t start = 0;           // engine step of the simulation's step 0
+  int parity_off = 0;
+  int cur_e = 0, cur_h = 0, cur_x = 0;  // buffers holding the current state
+  int64_t done = 0;            // steps completed (host mirror)
+  std::vector<size_t> rec_off; // device offsets of record outputs inside block
+  bool active = false;
+  int status_slot = -1;
+};
+
+// Bytes of device memory one simulation needs at a given precision.
+size_t sim_bytes(const SimPlan &p, int precision, bool plain);
+
+class Engine {
+ public:
+  Engine(int device, int precision, int variant, int block, int halo);
+  ~Engine();
+  int init(std::string &err);
+
+  // Uploads a planned simulation; memory from `arena` when given, else
+  // hipMalloc.  Returns the simulation id (>= 0) or a negative error.
+  int add(SimPlan &&plan, Arena *arena, hipStream_t st, std::string &err);
+  // Frees the simulation's device memory (after its last chunk completed).
+  void remove(int id, Arena *arena);
+
+  // Advances every active simulation by up to k steps (k <= depth for the
+  // blocked variant, any k for the two-launch variant).  Asynchronous.
+  hipError_t chunk(hipStream_t st, int k);
+  // Uploads group tables if membership changed (synchronous copy).
+  hipError_t sync_tables(hipStream_t st);
+
+  // Launches of one chunk, for graph capture: tables must be current.
+  hipError_t launch_only(hipStream_t st, int k);
+  void commit_chunk(int k);  // host bookkeeping of a chunk launched via launch_only
+
+  bool finished(int id) const;
+  bool all_finished() const;
+  int64_t engine_step() const { return n0_; }
+  int depth() const { return halo_; }
+  int block() const { return block_; }
+  int variant() const { return variant_; }
+  int precision() const { return precision_; }
+  SimState &sim(int id) { return *sims_[id]; }
+  const SimState &sim(int id) const { return *sims_[id]; }
+  int n_sims() const { return int(sims_.size()); }
+  // copies the status flags of all simulations to the host (synchronous)
+  hipError_t read_status(std::vector<int32_t> &out);
+  hipError_t read_records(int id, int rec, std::vector<double> &out);
+  hipError_t read_state(int id, double *e, double *h, double *rho);
+  double cell_updates() const { return cell_updates_; }
+
+ private:
+  struct Group {
+    int levels = 0;
+    std::vector<int> members;
+    DevSim *d_sims = nullptr;
+    DevTile *d_tiles = nullptr;
+    int n_tiles = 0, cap_sims = 0, cap_tiles = 0;
+  };
+  Group &group_for(int levels);
+  hipError_t upload_group(Group &g, hipStream_t st);
+
+  int device_, precision_, variant_, block_, halo_;
+  std::vector<std::unique_ptr<SimState>> sims_;
+  std::vector<Group> groups_;
+  bool dirty_ = true;
+  DevClock *d_clk_ = nullptr;
+  int32_t *d_status_ = nullptr;
+  int status_cap_ = 0;
+  std::vector<int> free_slots_;
+  int64_t n0_ = 0;
+  int parity_ = 0;
+  double cell_updates_ = 0;
+};
+
+// default tile shape per level count and precision
+void default_shape(int levels, int precision, int &block, int &halo);
+
+}  // namespace mb

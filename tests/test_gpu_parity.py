@@ -1,0 +1,261 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (relative max-norm per recorded trace, ||x - x_ref|| / ||x_ref||):
+FP64 1e-10, FP32 1e-4.  Traces whose reference is (close to) zero are
+measured against a floor: 1e-3 for density quantities and 1e-3 of the
+largest recorded field for E and H.  The two-launch FP64 kernels and the
+blocked FP64 kernel execute the same per-cell arithmetic, so they must agree
+bit for bit whatever the tile shape.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2005_05412_amd as mb
+import workloads as W
+from oracle import mb_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+TOL = {64: 1e-10, 32: 1e-4}
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_errors(prob, got, ref):
+    """name -> relative max-norm error of each recorded trace."""
+    fmax = 0.0
+    for r in prob["records"]:
+        if r["quantity"] in ("e", "h") and ref[r["name"]].size:
+            fmax = max(fmax, float(np.max(np.abs(ref[r["name"]]))))
+    out = {}
+    for r in prob["records"]:
+        a, b = np.asarray(got[r["name"]]), np.asarray(ref[r["name"]])
+        assert a.shape == b.shape, (r["name"], a.shape, b.shape)
+        if b.size == 0:
+            out[r["name"]] = 0.0
+            continue
+        floor = 1e-3 * fmax if r["quantity"] in ("e", "h") else 1e-3
+        if b.ndim == 2:   # whole-domain record: one trace per cell
+            den = np.maximum(np.max(np.abs(b), axis=0), floor)
+            out[r["name"]] = float(np.max(np.max(np.abs(a - b), axis=0) / den))
+        else:
+            out[r["name"]] = float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), floor))
+    return out
+
+
+def gpu_run(prob, precision=None, variant="auto", block=0, depth=0, chunks=None):
+    s = mb.Solver(prob, precision=precision, variant=variant, block=block, depth=depth)
+    if chunks:
+        for c in chunks:
+            s.run(c)
+    s.run()
+    rec = s.records()
+    s.close()
+    return rec
+
+
+def assert_same(a, b):
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+SMALL = [
+    dict(seed=11, N=2, nx=37, n_steps=70, refl=(0.0, 1.0)),
+    dict(seed=12, N=3, nx=150, n_steps=90, refl=(1.0, 0.0), soft=True),
+    dict(seed=13, N=4, nx=61, n_steps=50, refl=(0.0, 0.0), e_noise=1e7),
+    dict(seed=14, N=5, nx=45, n_steps=40, refl=(1.0, 1.0)),
+    dict(seed=15, N=6, nx=33, n_steps=30, refl=(0.0, 1.0)),
+    dict(seed=16, N=3, nx=1, n_steps=200, refl=(0.0, 0.0)),
+    dict(seed=17, N=0, nx=80, n_steps=120, refl=(0.0, 1.0)),
+    dict(seed=18, N=2, nx=3, n_steps=25, refl=(0.0, 0.0)),
+]
+
+
+def _small(case):
+    kw = dict(case)
+    return W.random_small(kw.pop("seed"), **kw)
+
+
+@pytest.mark.parametrize("case", SMALL, ids=lambda c: f"N{c['N']}-nx{c['nx']}-s{c['seed']}")
+def test_small_random_fp64_plain_and_blocked_vs_oracle(case):
+    prob = _small(case)
+    _say(f"case {prob['name']}")
+    ref = O.run(prob)
+    plain = gpu_run(prob, precision=64, variant="plain")
+    errs = rel_errors(prob, plain, ref)
+    assert max(errs.values()) <= TOL[64], errs
+    for block, depth in ((64, 1), (64, 7), (128, 31), (256, 32)):
+        blk = gpu_run(prob, precision=64, variant="blocked", block=block, depth=depth)
+        assert_same(blk, plain)
+
+
+@pytest.mark.parametrize("case", SMALL[:5], ids=lambda c: f"N{c['N']}-nx{c['nx']}-s{c['seed']}")
+def test_small_random_fp32_vs_oracle(case):
+    prob = _small(case)
+    _say(f"case {prob['name']} fp32")
+    ref = O.run(prob)
+    got = gpu_run(prob, precision=32, variant="blocked", block=128, depth=16)
+    errs = rel_errors(prob, got, ref)
+    assert max(errs.values()) <= TOL[32], errs
+
+
+def test_blocked_chunking_is_invisible():
+    """Splitting a run into calls of arbitrary length changes nothing (bitwise)."""
+    prob = W.random_small(21, N=3, nx=300, n_steps=100, refl=(0.0, 0.0))
+    _say("chunking")
+    whole = gpu_run(prob, precision=64, variant="blocked", block=128, depth=12)
+    split = gpu_run(prob, precision=64, variant="blocked", block=128, depth=12, chunks=[1, 7, 13, 30])
+    assert_same(whole, split)
+
+
+def test_read_state_matches_oracle_density():
+    prob = W.random_small(22, N=3, nx=50, n_steps=40, refl=(1.0, 0.0), full_records=False)
+    _say("state")
+    orc = O.Oracle(prob)
+    orc.run()
+    s = mb.Solver(prob, precision=64)
+    s.run()
+    e, h, rho = s.state()
+    s.close()
+    assert np.max(np.abs(e - orc.e)) <= 1e-10 * np.max(np.abs(orc.e))
+    assert np.max(np.abs(h[:-1] - orc.h)) <= 1e-10 * np.max(np.abs(orc.h))
+    ref = orc.full_density()
+    qm_cells = np.nonzero(np.abs(np.trace(ref, axis1=1, axis2=2)) > 0.5)[0]
+    assert len(qm_cells) > 10
+    assert np.max(np.abs(rho[qm_cells] - ref[qm_cells])) < 1e-10
+
+
+def test_nonfinite_field_is_reported():
+    prob = W.random_small(23, N=2, nx=40, n_steps=10, full_records=False)
+    prob["records"] = [W.record("e", "e", 20, 1)]
+    prob["e_init"] = np.zeros(40)
+    prob["e_init"][20] = np.nan
+    s = mb.Solver(prob, precision=64)
+    s.run()
+    with pytest.raises(mb.MBError) as ex:
+        s.record(0)
+    assert ex.value.code == -7
+    s.close()
+
+
+# ---------------------------------------------------------------- benchmark configurations
+
+def test_sit_two_level_full_fp64_and_fp32():
+    """Two-level SIT, 1500 cells, 20000 steps: FP64 within 1e-10, FP32 within 1e-4."""
+    prob = W.sit_2lvl()
+    _say("sit oracle")
+    ref = O.run(prob)
+    _say("sit gpu fp64")
+    got = gpu_run(prob, precision=64)
+    errs = rel_errors(prob, got, ref)
+    _say(f"sit fp64 errors {errs}")
+    assert max(errs.values()) <= TOL[64], errs
+    got32 = gpu_run(prob, precision=32)
+    errs32 = rel_errors(prob, got32, ref)
+    _say(f"sit fp32 errors {errs32}")
+    assert max(errs32.values()) <= TOL[32], errs32
+
+
+def test_lambda3_full_grid_prefix_vs_oracle():
+    """Three-level Lambda medium at its full 32768-cell grid, first 600 steps."""
+    prob = W.lambda3(n_steps=600, rec_interval=10)
+    _say("lambda3 oracle prefix")
+    ref = O.run(prob)
+    got = gpu_run(prob, precision=64)
+    errs = rel_errors(prob, got, ref)
+    assert max(errs.values()) <= TOL[64], max(errs.values())
+    got32 = gpu_run(prob, precision=32)
+    errs32 = rel_errors(prob, got32, ref)
+    assert max(errs32.values()) <= TOL[32], max(errs32.values())
+
+
+def test_lambda3_full_length_blocked_equals_plain_and_invariants():
+    """Full 200000 steps: blocked FP64 == two-launch FP64 bit for bit; populations valid."""
+    prob = W.lambda3()
+    _say("lambda3 full plain")
+    plain = gpu_run(prob, precision=64, variant="plain")
+    _say("lambda3 full blocked")
+    blk = gpu_run(prob, precision=64, variant="blocked")
+    assert_same(blk, plain)
+    for k in range(64):
+        names = [r["name"] for r in prob["records"][3 * k: 3 * k + 3]]
+        pops = np.array([blk[n] for n in names])
+        assert np.max(np.abs(pops.sum(axis=0) - 1.0)) < 1e-12
+        assert pops.min() > -1e-12 and pops.max() < 1 + 1e-12
+
+
+# ---------------------------------------------------------------- batching and serving
+
+def _mixed_batch(n=6, n_steps=400, precision=32):
+    rng = np.random.default_rng(5)
+    probs = []
+    for k in range(n):
+        nx = int(rng.integers(50, 700))
+        probs.append(W.sweep_sim(k, rng, nx=nx, n_steps=n_steps + 37 * k, precision=precision,
+                                 rec_interval=5))
+    return probs
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_batch_equals_individual_runs(precision):
+    probs = _mixed_batch(precision=precision)
+    _say(f"batch {precision}")
+    b = mb.Batch(probs, precision=precision, block=128, depth=16)
+    b.run(use_graph=True)
+    for k, p in enumerate(probs):
+        alone = gpu_run(p, precision=precision, variant="blocked", block=256, depth=32)
+        assert_same(b.records(k), alone)
+    b.close()
+    if precision == 64:
+        for k in (0, 1):
+            ref = O.run(probs[k])
+            b2 = mb.Batch(probs, precision=64, block=128, depth=16)
+            b2.run(use_graph=False)
+            errs = rel_errors(probs[k], b2.records(k), ref)
+            b2.close()
+            assert max(errs.values()) <= TOL[64], errs
+
+
+def test_server_results_equal_alone():
+    """Requests admitted while others run give the same records as solo runs."""
+    probs = _mixed_batch(n=8, n_steps=300, precision=32)
+    _say("server")
+    srv = mb.Server(hbm_budget=256 << 20, max_slots=3, precision=32, chunk_steps=16)
+    tickets = [srv.submit(p, arrival_s=0.002 * k) for k, p in enumerate(probs)]
+    srv.start()
+    srv.drain(timeout_s=120)
+    for t, p in zip(tickets, probs):
+        st = srv.status(t)
+        assert st[0] == 2, st
+        alone = gpu_run(p, precision=32, variant="blocked", block=256, depth=32)
+        for k, r in enumerate(p["records"]):
+            assert np.array_equal(srv.record(t, k), alone[r["name"]]), r["name"]
+    cu, busy, chunks = srv.stats()
+    assert cu == sum(p["nx"] * p["n_steps"] for p in probs)
+    srv.close()
+
+
+def test_server_budget_and_cancel():
+    p = _mixed_batch(n=1, n_steps=100, precision=32)[0]
+    srv = mb.Server(hbm_budget=1 << 16, max_slots=2, precision=32, chunk_steps=16)
+    with pytest.raises(mb.MBError) as ex:
+        srv.submit(p)
+    assert ex.value.code == -5
+    srv.close()
+    srv = mb.Server(hbm_budget=64 << 20, max_slots=1, precision=32, chunk_steps=16)
+    t1 = srv.submit(p, 0.0)
+    big = dict(p)
+    big["n_steps"] = 200000
+    t2 = srv.submit(big, 0.0)
+    srv.cancel(t2)
+    srv.start()
+    srv.drain(timeout_s=60)
+    assert srv.status(t1)[0] == 2
+    assert srv.status(t2)[0] == 3
+    srv.close()

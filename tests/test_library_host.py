@@ -1,0 +1,182 @@
+"""Host-side checks of libmbhip.so that need no GPU.
+
+* the shared library loads and exports every function ``include/mb.h`` declares;
+* the library's own FP64 plan (Jacobi eigen-basis of mu, real trace-eliminated
+  Liouvillian, Taylor scaling-and-squaring exponentials, polarization and
+  record readouts) reproduces the oracle's single-point solve when its tables
+  are stepped in the kernels' formulation (rotation by E, p = at.y + p0,
+  sigma' = y + am y + bf);
+* invalid descriptions map to the documented status codes.
+"""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2005_05412_amd as mb
+import workloads as W
+from oracle import mb_oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+C = W.CODATA
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "mb.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mb_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = mb.load()
+    names = declared_functions()
+    assert len(names) >= 28
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(mb.EXPORTS) == names
+
+
+def test_no_gpu_means_no_device_here():
+    # the container has no GPU; the call must still return cleanly
+    assert mb.load().mb_device_count() >= 0
+
+
+# ---------------------------------------------------------------- plan tables vs oracle
+
+def _rho_to_x(rho_p, n):
+    x = [rho_p[k, k].real for k in range(n - 1)]
+    for j in range(1, n):
+        for i in range(j):
+            x += [rho_p[i, j].real, rho_p[i, j].imag]
+    return np.array(x)
+
+
+def _x_to_rho(x, n):
+    r = np.zeros((n, n), complex)
+    for k in range(n - 1):
+        r[k, k] = x[k]
+    r[n - 1, n - 1] = 1.0 - sum(x[: n - 1])
+    q = 0
+    for j in range(1, n):
+        for i in range(j):
+            z = x[n - 1 + 2 * q] + 1j * x[n + 2 * q]
+            r[i, j], r[j, i] = z, np.conj(z)
+            q += 1
+    return r
+
+
+def _rotate(y, e, kappa, n):
+    y = y.copy()
+    q = 0
+    for j in range(1, n):
+        for i in range(j):
+            th = e * sum(kappa[i:j])
+            z = (y[n - 1 + 2 * q] + 1j * y[n + 2 * q]) * np.exp(1j * th)
+            y[n - 1 + 2 * q], y[n + 2 * q] = z.real, z.imag
+            q += 1
+    return y
+
+
+@pytest.mark.parametrize("n,seed", [(2, 1), (3, 2), (4, 3), (5, 4), (6, 5)])
+def test_plan_tables_reproduce_oracle_single_point(n, seed):
+    rng = np.random.default_rng(seed)
+    qm = W.random_qm(rng, n, dipole=3e-29)
+    rd, ro = W.random_rho(rng, n)
+    src = W.source("sech", 0, 3e9, 2e14, 5.0, 1.0 / 15e-15, phase=0.4)
+    dt, nt = 2e-17, 600
+    prob = W.make_problem("pt", 0.0, [W.qm_material(qm)], [(0.0, 0.0, 0)], 1, dt, nt, rd, ro,
+                          sources=[src], records=[])
+    t = mb.plan_material(prob, 0)
+    orc = O.Oracle(prob)
+    V = t["vec"]
+    rho0 = O.unpack_hermitian(rd, ro)
+    sigma = t["ah"] @ _rho_to_x(V.conj().T @ rho0 @ V, n) + t["bh"]
+    # eigen-decomposition of mu is the library's own
+    mu = O.describe(qm, C)[1]
+    assert np.allclose(V @ np.diag(t["lam"]) @ V.conj().T, mu, rtol=0, atol=1e-12 * abs(mu).max())
+    errs = []
+    for step in range(nt):
+        e = orc.e[0]
+        y = _rotate(sigma, e, t["kappa"], n)
+        p = t["at"] @ y + t["p0"]
+        rho_half = V @ _x_to_rho(t["ah"] @ y + t["bh"], n) @ V.conj().T
+        sigma = y + t["am"] @ y + t["bf"]
+        orc.step()
+        ref = orc.full_density()[0]
+        errs.append(np.max(np.abs(rho_half - ref)))
+        assert abs(p - orc.p_cur[0]) <= 1e-9 * max(1.0, abs(orc.p_cur[0])) + 1e-12 * np.abs(orc.p_cur).max()
+    assert max(errs) < 1e-12
+
+
+def test_plan_readouts_match_oracle_quantities():
+    rng = np.random.default_rng(7)
+    n = 4
+    qm = W.random_qm(rng, n)
+    rd, ro = W.random_rho(rng, n)
+    recs = [W.record("p2", "pop", 0, 1, 2, 2), W.record("inv", "inv", 0, 1, 1, 3),
+            W.record("re", "rho_re", 0, 1, 0, 2), W.record("im", "rho_im", 0, 1, 1, 3)]
+    prob = W.make_problem("pt", 0.0, [W.qm_material(qm)], [(0.0, 0.0, 0)], 1, 2e-17, 5, rd, ro,
+                          e_init=np.array([2e9]), records=recs)
+    t = mb.plan_material(prob, 0)
+    orc = O.Oracle(prob)
+    V = t["vec"]
+    sigma = t["ah"] @ _rho_to_x(V.conj().T @ O.unpack_hermitian(rd, ro) @ V, n) + t["bh"]
+    y = _rotate(sigma, 2e9, t["kappa"], n)
+    r = orc.run(1)
+    for k, rec in enumerate(recs):
+        ro_vec = mb.plan_readout(prob, k, 0)
+        val = ro_vec[0] + ro_vec[1:] @ y
+        assert abs(val - r[rec["name"]][0]) < 1e-13
+
+
+def test_two_level_constructor_matches_oracle():
+    qm = W.two_level_params(1e24, 2 * math.pi * 2e14, 6.24e-11, 1e10, 3e10, -0.5)
+    prob = W.make_problem("pt", 0.0, [W.qm_material(qm)], [(0.0, 0.0, 0)], 1, 1e-17, 3, [1.0, 0.0],
+                          records=[])
+    t = mb.plan_material(prob, 0)
+    h0, mu, rates, deph, _ = O.describe(qm, C)
+    assert np.allclose(np.sort(t["lam"]), np.linalg.eigvalsh(mu), rtol=1e-14)
+
+
+# ---------------------------------------------------------------- status codes
+
+def _vac(nx=20, courant=0.5, refl=(0.0, 0.0), levels_qm=None):
+    L = 1e-5
+    mats = [W.vacuum()] if levels_qm is None else [W.qm_material(levels_qm)]
+    dt = W.courant_dt(L, nx, C["c0"], courant)
+    rho = [1.0] if levels_qm is None else [1.0] + [0.0] * (W.qm_levels(levels_qm) - 1)
+    return W.make_problem("v", L, mats, [(0.0, L, 0)], nx, dt, 10, rho, refl=refl)
+
+
+def test_status_codes():
+    assert mb.plan_status(_vac()) == 0
+    with pytest.raises(mb.MBError) as ex:
+        mb.plan_status(_vac(courant=1.01))
+    assert ex.value.code == -2
+    with pytest.raises(mb.MBError) as ex:
+        mb.plan_status(_vac(refl=(0.5, 0.0)))
+    assert ex.value.code == -3
+    rng = np.random.default_rng(1)
+    with pytest.raises(mb.MBError) as ex:
+        mb.plan_status(_vac(levels_qm=W.random_qm(rng, 7)))
+    assert ex.value.code == -3
+    bad = _vac()
+    bad["regions"] = [dict(x_start=0.0, x_end=0.5e-5, material=0)]
+    with pytest.raises(mb.MBError) as ex:
+        mb.plan_status(bad)
+    assert ex.value.code == -1
+    bad = _vac()
+    bad["sources"] = [W.source("sech", 99, 1.0, 1e14, 1.0, 1e14)]
+    with pytest.raises(mb.MBError):
+        mb.plan_status(bad)
+
+
+def test_non_completely_positive_dephasing_warns():
+    qm = W.general_qm(1e24, [0.0, 0.1 * C["e"], 0.2 * C["e"]], None, None,
+                      np.array([1e-29, 1e-29, 0.0]), np.zeros((3, 3)), [1e12, 1e12, 10e12])
+    assert mb.plan_status(_vac(levels_qm=qm)) == mb.MB_WARN_NOT_CP
+    ok = W.general_qm(1e24, [0.0, 0.1 * C["e"], 0.2 * C["e"]], None, None,
+                      np.array([1e-29, 1e-29, 0.0]), np.zeros((3, 3)), [1e12, 1e12, 1e12])
+    assert mb.plan_status(_vac(levels_qm=ok)) == 0
