@@ -1,0 +1,280 @@
+"""Benchmark of the MI355X Maxwell-Bloch hot path.
+
+Default workload: the three-level Lambda medium on 32768 cells for 200000
+steps (16 seeded materials, Gaussian pulse-train drive, populations recorded
+at 64 probes every 10 steps).  One benchmark "step" is one complete solve of
+that workload (all 200000 time steps) with its inputs resident in device
+memory; the initial state is restored from a device copy between solves.
+
+Printed: one JSON line with cell-updates/s of the FP32 temporally blocked
+path (``value``), the FP64 two-launch and blocked paths on the same
+workload, their errors against the FP64 oracle on a bounded prefix (the same
+oracle run is the CPU baseline), the roofline of the dominant kernel and,
+unless disabled, the batched parameter sweep and a serving trace with
+p50/p99 solve latency.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import paper_2005_05412_amd as mb  # noqa: E402
+import workloads as W  # noqa: E402
+
+PEAK = {"fp32_tflops": 157.3, "fp64_tflops": 78.6, "hbm_gbs": 8000.0}
+
+
+def flops_per_cell_update(n):
+    """Algorithmic flops of one cell-update: Yee updates (8), field phases as
+    complex multiplies on the N(N-1)/2 coherences (6 each), polarization
+    readout (2M) and the affine propagator (2M^2 + M), M = N^2 - 1."""
+    m = n * n - 1
+    return 8 + 6 * (n * (n - 1) // 2) + 2 * m + 2 * m * m + m
+
+
+def bytes_per_cell_update(n, prec):
+    """Algorithmic HBM bytes of one cell-update: read and write of E, H and the M density reals."""
+    return 2 * (n * n + 1) * (8 if prec == 64 else 4)
+
+
+class Hip:
+    """Minimal HIP runtime access (stream, events, synchronisation) via ctypes."""
+
+    def __init__(self):
+        self.lib = ctypes.CDLL("libamdhip64.so")
+
+    def sync(self):
+        rc = self.lib.hipDeviceSynchronize()
+        if rc != 0:
+            raise RuntimeError(f"hipDeviceSynchronize failed: {rc}")
+
+    def stream(self):
+        s = ctypes.c_void_p()
+        if self.lib.hipStreamCreateWithFlags(ctypes.byref(s), 1) != 0:
+            raise RuntimeError("hipStreamCreateWithFlags failed")
+        return s.value
+
+    def event(self):
+        e = ctypes.c_void_p()
+        if self.lib.hipEventCreate(ctypes.byref(e)) != 0:
+            raise RuntimeError("hipEventCreate failed")
+        return e
+
+    def record(self, ev, stream):
+        self.lib.hipEventRecord(ev, ctypes.c_void_p(stream))
+
+    def elapsed_ms(self, a, b):
+        self.lib.hipEventSynchronize(b)
+        ms = ctypes.c_float()
+        self.lib.hipEventElapsedTime(ctypes.byref(ms), a, b)
+        return ms.value
+
+
+def rel_err(prob, got, ref):
+    worst = 0.0
+    for r in prob["records"]:
+        a, b = np.asarray(got[r["name"]]), np.asarray(ref[r["name"]])
+        n = min(len(a), len(b))
+        if n == 0:
+            continue
+        floor = 1e-3
+        worst = max(worst, float(np.max(np.abs(a[:n] - b[:n])) / max(np.max(np.abs(b[:n])), floor)))
+    return worst
+
+
+def timed_solves(hip, stream, solver, steps, warmup, n_launch):
+    for _ in range(warmup):
+        solver.reset(stream).run(-1, stream)
+    hip.sync()
+    evs = [(hip.event(), hip.event()) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        solver.reset(stream)
+        hip.record(a, stream)
+        solver.run(-1, stream)
+        hip.record(b, stream)
+    hip.sync()
+    wall = time.perf_counter() - t0
+    dev_ms = [hip.elapsed_ms(a, b) for a, b in evs]
+    return wall, dev_ms
+
+
+def cpu_baseline(prob, budget_s):
+    """The FP64 oracle timed on one host thread over a bounded prefix of the workload."""
+    from threadpoolctl import threadpool_limits
+    from oracle import Oracle
+
+    with threadpool_limits(limits=1):
+        orc = Oracle(prob)
+        t0 = time.perf_counter()
+        n = 0
+        step_rec = max(r["interval"] for r in prob["records"])
+        while True:
+            for _ in range(step_rec):
+                orc.step()
+            n += step_rec
+            el = time.perf_counter() - t0
+            if el > budget_s or n >= prob["n_steps"]:
+                break
+    recs = {k: np.array(v) for k, v in orc.records.items()}
+    return n, el, recs
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nx", type=int, default=32768)
+    ap.add_argument("--nt", type=int, default=200000)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--depth", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--out", default="")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU runs are not part of this build",
+              file=sys.stderr)
+        return 2
+    hip = Hip()
+    stream = hip.stream()
+    prob = W.lambda3(nx=args.nx, n_steps=args.nt, precision=32)
+    n_levels = 3
+    cells = prob["nx"] * prob["n_steps"]
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+
+    # ---- main leg: FP32 temporally blocked -------------------------------------------
+    log(f"[bench] lambda3 fp32 blocked nx={prob['nx']} nt={prob['n_steps']}")
+    s32 = mb.Solver(prob, precision=32, variant="blocked", block=args.block, depth=args.depth)
+    depth = args.depth or 32
+    n_launch = math.ceil(prob["n_steps"] / depth)
+    wall, dev_ms = timed_solves(hip, stream, s32, args.steps, args.warmup, n_launch)
+    rec32 = s32.records()
+    value = args.steps * cells / wall
+    avg_kernel_us = 1e3 * float(np.mean(dev_ms)) / n_launch
+    flop_launch = flops_per_cell_update(n_levels) * prob["nx"] * depth
+    achieved_tflops = flop_launch / (avg_kernel_us * 1e-6) / 1e12
+    eff_gbs = bytes_per_cell_update(n_levels, 32) * cells / (float(np.mean(dev_ms)) * 1e-3) / 1e9
+    log(f"[bench] fp32 blocked: {value:.3e} cell-updates/s, kernel {avg_kernel_us:.2f} us")
+
+    out = {
+        "metric": "cell-updates/s (FP64 plain vs FP32 batched) at stated error; p50/p99 solve latency",
+        "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "lambda3-3lvl", "nx": prob["nx"], "n_steps": prob["n_steps"], "levels": 3,
+                   "materials": len(prob["materials"]), "records": len(prob["records"]),
+                   "variant": "blocked", "block": args.block or 256, "depth": depth,
+                   "step": "one full solve of the workload"},
+        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK["fp32_tflops"],
+                     "unit": "TFLOP/s", "frac": achieved_tflops / PEAK["fp32_tflops"], "traffic": None,
+                     "kernel": "k_blocked<3,float,256>", "avg_kernel_us": avg_kernel_us,
+                     "flops_per_cell_update": flops_per_cell_update(n_levels),
+                     "cell_updates_per_launch": prob["nx"] * depth,
+                     "hbm_effective_gbs": eff_gbs, "hbm_effective_frac": eff_gbs / PEAK["hbm_gbs"]},
+    }
+
+    # ---- FP64 legs ---------------------------------------------------------------------
+    rec64 = None
+    if not args.no_fp64:
+        log("[bench] lambda3 fp64 blocked")
+        s64 = mb.Solver(prob, precision=64, variant="blocked", block=args.block, depth=args.depth)
+        w64, d64 = timed_solves(hip, stream, s64, 1, 1, n_launch)
+        rec64 = s64.records()
+        s64.close()
+        log("[bench] lambda3 fp64 plain (two launches per step)")
+        sp = mb.Solver(prob, precision=64, variant="plain")
+        t0 = time.perf_counter()
+        sp.run(-1, stream)
+        hip.sync()
+        wp = time.perf_counter() - t0
+        recp = sp.records()
+        sp.close()
+        same = all(np.array_equal(recp[k], rec64[k]) for k in rec64)
+        out["fp64_blocked"] = {"value": cells / w64, "unit": "cell-updates/s", "device_ms": d64[0]}
+        out["fp64_plain"] = {"value": cells / wp, "unit": "cell-updates/s", "wall_s": wp,
+                             "bitwise_equal_to_fp64_blocked": bool(same)}
+        out["fp32_vs_fp64_full_run_max_rel_err"] = rel_err(prob, rec32, rec64)
+
+    # ---- CPU baseline: the oracle on a bounded prefix, also the parity spot check -------
+    if not args.no_cpu:
+        log("[bench] oracle prefix on the host")
+        n_cpu, t_cpu, ref = cpu_baseline(prob, args.cpu_seconds)
+        out["cpu_baseline"] = {"value": prob["nx"] * n_cpu / t_cpu, "unit": "cell-updates/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"first {n_cpu} of {prob['n_steps']} steps of the same workload "
+                                         f"(all {prob['nx']} cells), numpy FP64, one thread"}
+        out["error_vs_oracle_prefix"] = {"steps": n_cpu, "fp32": rel_err(prob, rec32, ref)}
+        if rec64 is not None:
+            out["error_vs_oracle_prefix"]["fp64"] = rel_err(prob, rec64, ref)
+    s32.close()
+
+    # ---- batched sweep ---------------------------------------------------------------
+    if not args.no_batch:
+        log("[bench] batched sweep 256 sims fp32")
+        sims = W.sweep(n_sims=256, precision=32)
+        bcells = sum(p["nx"] * p["n_steps"] for p in sims)
+        bt = mb.Batch(sims, precision=32, variant="blocked")
+        bt.run(stream=stream, use_graph=True)
+        hip.sync()
+        bt.reset(stream)
+        hip.sync()
+        t0 = time.perf_counter()
+        bt.run(stream=stream, use_graph=True)
+        hip.sync()
+        tb = time.perf_counter() - t0
+        beff = sum(bytes_per_cell_update(2 if k % 2 == 0 else 3, 32) * p["nx"] * p["n_steps"]
+                   for k, p in enumerate(sims)) / tb / 1e9
+        out["batched_sweep"] = {"value": bcells / tb, "unit": "cell-updates/s", "sims": len(sims),
+                                "cell_updates": bcells, "wall_s": tb, "hbm_effective_gbs": beff,
+                                "hbm_effective_frac": beff / PEAK["hbm_gbs"]}
+        bt.close()
+
+    # ---- serving ---------------------------------------------------------------------
+    if not args.no_serve:
+        log(f"[bench] serving trace {args.serve_requests} requests")
+        trace = W.serve_trace(n_requests=args.serve_requests, precision=32)
+        srv = mb.Server(hbm_budget=16 << 30, max_slots=512, precision=32, chunk_steps=32)
+        tickets = [srv.submit(p, t) for t, p in trace]
+        t0 = time.perf_counter()
+        srv.start()
+        srv.drain(timeout_s=600)
+        tw = time.perf_counter() - t0
+        lat = []
+        for t in tickets:
+            st, ta, tadm, td = srv.status(t)
+            if st == 2:
+                lat.append(td - ta)
+        cu, busy, chunks = srv.stats()
+        srv.close()
+        lat = np.array(lat)
+        out["serving"] = {"requests": len(trace), "done": int(len(lat)),
+                          "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+                          "value": cu / tw, "unit": "cell-updates/s", "wall_s": tw, "busy_s": busy,
+                          "chunks": int(chunks), "arrival_rate_per_s": 200.0}
+
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(line + "\n")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -209,6 +209,12 @@ int mb_setup(int hip_device, const mb_device_desc *dev, const mb_scenario_desc *
  * hipStream_t, NULL = the legacy default stream).  Asynchronous. */
 int mb_run(mb_handle *h, int64_t n_steps, void *hip_stream);
 
+/* Restores the initial state (from a device-resident copy made at setup),
+ * clears the records and sets the step count to zero, asynchronously on
+ * `hip_stream`.  A later mb_run of the same length replays the HIP graph
+ * captured by the first one. */
+int mb_reset(mb_handle *h, void *hip_stream);
+
 /* Steps done so far. */
 int64_t mb_steps_done(const mb_handle *h);
 
@@ -242,6 +248,8 @@ int mb_batch_setup(int hip_device, int32_t n, const mb_device_desc *devs,
  * use_graph != 0 the chunk launches are captured once into a HIP graph and
  * replayed. */
 int mb_batch_run(mb_batch *b, void *hip_stream, int32_t use_graph);
+/* Restores every member's initial state and clears the records (as mb_reset). */
+int mb_batch_reset(mb_batch *b, void *hip_stream);
 int mb_batch_record_shape(const mb_batch *b, int32_t sim, int record_id, int64_t *n_samples,
                           int64_t *width);
 int mb_batch_read_records(mb_batch *b, int32_t sim, int record_id, double *out,

@@ -27,7 +27,7 @@ REC_KIND = {"e": 0, "h": 1, "pop": 2, "inv": 3, "rho_re": 4, "rho_im": 5}
 VARIANT = {"auto": 0, "plain": 1, "blocked": 2}
 
 EXPORTS = [
-    "mb_last_error", "mb_device_count", "mb_plan_material", "mb_plan_readout", "mb_setup", "mb_run", "mb_steps_done", "mb_record_shape",
+    "mb_last_error", "mb_device_count", "mb_plan_material", "mb_plan_readout", "mb_setup", "mb_run", "mb_reset", "mb_batch_reset", "mb_steps_done", "mb_record_shape",
     "mb_read_records", "mb_read_state", "mb_elapsed_ms", "mb_destroy", "mb_batch_setup", "mb_batch_run",
     "mb_batch_record_shape", "mb_batch_read_records", "mb_batch_elapsed_ms", "mb_batch_destroy",
     "mb_server_create", "mb_server_submit", "mb_server_start", "mb_server_drain", "mb_server_cancel",
@@ -120,6 +120,8 @@ def load():
                                       C.c_int32, dp, C.c_int64]),
         "mb_setup": (C.c_int, [C.c_int, C.POINTER(mb_device_desc), C.POINTER(mb_scenario_desc), C.POINTER(P)]),
         "mb_run": (C.c_int, [P, C.c_int64, P]),
+        "mb_reset": (C.c_int, [P, P]),
+        "mb_batch_reset": (C.c_int, [P, P]),
         "mb_steps_done": (C.c_int64, [P]),
         "mb_record_shape": (C.c_int, [P, C.c_int, i64p, i64p]),
         "mb_read_records": (C.c_int, [P, C.c_int, dp, C.c_int64, i64p]),
@@ -318,6 +320,10 @@ class Solver:
         _check(load().mb_run(self._h, int(n_steps), _stream_ptr(stream)))
         return self
 
+    def reset(self, stream=None):
+        _check(load().mb_reset(self._h, _stream_ptr(stream)))
+        return self
+
     @property
     def steps_done(self):
         return int(load().mb_steps_done(self._h))
@@ -330,7 +336,7 @@ class Solver:
         n = C.c_int64()
         _check(lib.mb_read_records(self._h, k, _dptr(out), out.size, C.byref(n)))
         out = out[: n.value]
-        return out.reshape(ns.value, w.value) if w.value > 1 else out
+        return out.reshape(ns.value, w.value) if self.prob["records"][k]["cell"] < 0 else out
 
     def records(self):
         return {r["name"]: self.record(k) for k, r in enumerate(self.prob["records"])}
@@ -389,6 +395,10 @@ class Batch:
         _check(load().mb_batch_run(self._h, _stream_ptr(stream), int(bool(use_graph))))
         return self
 
+    def reset(self, stream=None):
+        _check(load().mb_batch_reset(self._h, _stream_ptr(stream)))
+        return self
+
     def record(self, sim, k):
         lib = load()
         ns, w = C.c_int64(), C.c_int64()
@@ -397,7 +407,7 @@ class Batch:
         n = C.c_int64()
         _check(lib.mb_batch_read_records(self._h, sim, k, _dptr(out), out.size, C.byref(n)))
         out = out[: n.value]
-        return out.reshape(ns.value, w.value) if w.value > 1 else out
+        return out.reshape(ns.value, w.value) if self.probs[sim]["records"][k]["cell"] < 0 else out
 
     def records(self, sim):
         return {r["name"]: self.record(sim, k) for k, r in enumerate(self.probs[sim]["records"])}
@@ -434,6 +444,7 @@ class Server:
         m = _Marshal(prob)
         t = C.c_uint64()
         _check(load().mb_server_submit(self._h, C.byref(m.dev), C.byref(m.scen), float(arrival_s), C.byref(t)))
+        self._keep[t.value] = [r["cell"] for r in prob["records"]]
         return t.value
 
     def start(self):
@@ -459,7 +470,7 @@ class Server:
         n = C.c_int64()
         _check(lib.mb_server_read_records(self._h, C.c_uint64(ticket), k, _dptr(out), out.size, C.byref(n)))
         out = out[: n.value]
-        return out.reshape(ns.value, w.value) if w.value > 1 else out
+        return out.reshape(ns.value, w.value) if self._keep[ticket][k] < 0 else out
 
     def stats(self):
         cu, busy, ch = C.c_double(), C.c_double(), C.c_int64()

@@ -22,6 +22,27 @@ int fail(int code, const std::string &msg) {
 
 using namespace mb;
 
+namespace {
+
+// One captured run of chunk launches, replayed when the same run (engine
+// tables, start step, length) is asked for again, e.g. after mb_reset.
+struct GraphCache {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t version = -1, n0 = -1, steps = -1;
+  int k = 0;
+  void clear() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    version = n0 = steps = -1;
+  }
+  ~GraphCache() { clear(); }
+};
+
+}  // namespace
+
 struct mb_handle {
   int device = 0;
   std::unique_ptr<Engine> eng;
@@ -29,6 +50,7 @@ struct mb_handle {
   hipStream_t last_stream = nullptr;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   double ms_done = 0.0;
+  GraphCache gc;
 };
 
 struct mb_batch {
@@ -38,9 +60,57 @@ struct mb_batch {
   hipStream_t last_stream = nullptr;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   double ms_done = 0.0;
+  GraphCache gc;
 };
 
 namespace {
+
+// Advances the engine by `steps` steps in chunks of at most k.  With
+// use_graph the chunk launches are captured into one HIP graph (or the
+// cached graph of an identical earlier run is replayed).
+hipError_t run_steps(Engine &eng, hipStream_t st, int64_t steps, int k, bool use_graph, GraphCache &gc) {
+  hipError_t e = eng.sync_tables(st);
+  if (e != hipSuccess) return e;
+  if (!use_graph) {
+    while (steps > 0 && e == hipSuccess) {
+      int kk = int(std::min<int64_t>(k, steps));
+      e = eng.chunk(st, kk);
+      steps -= kk;
+    }
+    return e;
+  }
+  const int64_t n0 = eng.engine_step();
+  if (gc.exec && gc.version == eng.version() && gc.n0 == n0 && gc.steps == steps && gc.k == k) {
+    e = hipGraphLaunch(gc.exec, st);
+    for (int64_t left = steps; left > 0 && e == hipSuccess; left -= k) eng.commit_chunk(int(std::min<int64_t>(k, left)));
+    return e;
+  }
+  gc.clear();
+  hipStream_t cap;
+  if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) return e;
+  e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  for (int64_t left = steps; left > 0 && e == hipSuccess; left -= k) {
+    int kk = int(std::min<int64_t>(k, left));
+    e = eng.launch_only(cap, kk);
+    eng.commit_chunk(kk);
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t e2 = hipStreamEndCapture(cap, &graph);
+  (void)hipStreamDestroy(cap);
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    gc.exec = nullptr;
+    return e;
+  }
+  gc.graph = graph;
+  gc.version = eng.version();
+  gc.n0 = n0;
+  gc.steps = steps;
+  gc.k = k;
+  return hipGraphLaunch(gc.exec, st);
+}
 
 #define MB_GUARD_BEGIN try {
 #define MB_GUARD_END                                         \
@@ -179,15 +249,25 @@ int mb_run(mb_handle *h, int64_t n_steps, void *hip_stream) {
   hipError_t e = h->eng->sync_tables(st);
   if (e != hipSuccess) return hip_fail(e, "table upload");
   (void)hipEventRecord(a, st);
-  const int k = h->eng->variant() == MB_VARIANT_PLAIN ? 1 : h->eng->depth();
-  while (n_steps > 0) {
-    int kk = int(std::min<int64_t>(k, n_steps));
-    e = h->eng->chunk(st, kk);
-    if (e != hipSuccess) return hip_fail(e, "kernel launch");
-    n_steps -= kk;
-  }
+  const bool plain = h->eng->variant() == MB_VARIANT_PLAIN;
+  const int k = plain ? 1 : h->eng->depth();
+  e = run_steps(*h->eng, st, n_steps, k, !plain && n_steps >= 4 * int64_t(k), h->gc);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
   (void)hipEventRecord(b, st);
   h->events.emplace_back(a, b);
+  return MB_OK;
+  MB_GUARD_END
+}
+
+int mb_reset(mb_handle *h, void *hip_stream) {
+  MB_GUARD_BEGIN
+  if (!h) return fail(MB_ERR_ARG, "null handle");
+  if (hipSetDevice(h->device) != hipSuccess) return fail(MB_ERR_HIP, "hipSetDevice failed");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (h->last_stream != st) (void)hipStreamSynchronize(h->last_stream);
+  h->last_stream = st;
+  hipError_t e = h->eng->reset(st);
+  if (e != hipSuccess) return hip_fail(e, "reset");
   return MB_OK;
   MB_GUARD_END
 }
@@ -310,49 +390,27 @@ int mb_batch_run(mb_batch *b, void *hip_stream, int32_t use_graph) {
   if (e != hipSuccess) return hip_fail(e, "table upload");
   const bool plain = eng.variant() == MB_VARIANT_PLAIN;
   const int k = plain ? 1 : eng.depth();
-  int64_t chunks = (remaining + k - 1) / k;
   hipEvent_t ea, eb;
   if (hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess)
     return fail(MB_ERR_HIP, "hipEventCreate failed");
   (void)hipEventRecord(ea, st);
-  if (use_graph && chunks > 1) {
-    const int64_t g = std::min<int64_t>(chunks, plain ? 32 : 64);
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    hipStream_t cap;
-    if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
-    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    for (int64_t q = 0; q < g && e == hipSuccess; ++q) e = eng.launch_only(cap, k);
-    hipError_t e2 = hipStreamEndCapture(cap, &graph);
-    if (e == hipSuccess) e = e2;
-    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-      if (graph) (void)hipGraphDestroy(graph);
-      (void)hipStreamDestroy(cap);
-      return hip_fail(e, "graph capture");
-    }
-    int64_t reps = chunks / g;
-    for (int64_t r = 0; r < reps && e == hipSuccess; ++r) {
-      e = hipGraphLaunch(exec, st);
-      for (int64_t q = 0; q < g; ++q) eng.commit_chunk(k);
-    }
-    for (int64_t q = reps * g; q < chunks && e == hipSuccess; ++q) {
-      e = eng.launch_only(st, k);
-      eng.commit_chunk(k);
-    }
-    (void)hipStreamSynchronize(st);
-    (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
-    (void)hipStreamDestroy(cap);
-    if (e != hipSuccess) return hip_fail(e, "graph launch");
-  } else {
-    for (int64_t q = 0; q < chunks; ++q) {
-      e = eng.chunk(st, k);
-      if (e != hipSuccess) return hip_fail(e, "kernel launch");
-    }
-  }
+  e = run_steps(eng, st, remaining, k, use_graph != 0 && !plain, b->gc);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
   (void)hipEventRecord(eb, st);
   b->events.emplace_back(ea, eb);
+  return MB_OK;
+  MB_GUARD_END
+}
+
+int mb_batch_reset(mb_batch *b, void *hip_stream) {
+  MB_GUARD_BEGIN
+  if (!b) return fail(MB_ERR_ARG, "null batch");
+  if (hipSetDevice(b->device) != hipSuccess) return fail(MB_ERR_HIP, "hipSetDevice failed");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (b->last_stream != st) (void)hipStreamSynchronize(b->last_stream);
+  b->last_stream = st;
+  hipError_t e = b->eng->reset(st);
+  if (e != hipSuccess) return hip_fail(e, "reset");
   return MB_OK;
   MB_GUARD_END
 }

@@ -61,10 +61,4 @@ struct DevTile {
   int32_t c0;   // first output cell
 };
 
-struct DevClock {
-  int64_t n0;      // engine step at the start of the next launch
-  int32_t parity;  // engine buffer parity
-  int32_t pad;
-};
-
 }  // namespace mb

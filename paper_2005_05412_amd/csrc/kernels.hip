@@ -159,16 +159,16 @@ __device__ __forceinline__ R apply_sources(const DevSim &sim, int64_t c, int64_t
 template <int N, typename R, int B>
 __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
                                                const DevTile *__restrict__ tiles,
-                                               const DevClock *__restrict__ clk, int halo, int k) {
+                                               int64_t n0, int parity, int halo, int k) {
   using CL = Cell<N, R>;
   constexpr int M = CL::M, MA = CL::MA, S = mat_stride(N);
   __shared__ R se[B], sh[B], se2[B];
   const DevTile tile = tiles[blockIdx.x];
   const DevSim &sim = sims[tile.sim];
-  const int64_t ls0 = clk->n0 - sim.start;
+  const int64_t ls0 = n0 - sim.start;
   if (ls0 < 0 || ls0 >= sim.n_steps) return;
   const int ks = int(min(int64_t(k), sim.n_steps - ls0));
-  const int par = clk->parity ^ sim.parity_off;
+  const int par = parity ^ sim.parity_off;
   const int64_t nx = sim.nx;
   const R *__restrict__ e_in = static_cast<const R *>(sim.e[par]);
   const R *__restrict__ h_in = static_cast<const R *>(sim.h[par]);
@@ -275,18 +275,18 @@ constexpr int kPlainBlock = 256;
 template <int N>
 __global__ void __launch_bounds__(kPlainBlock) k_plain_hd(const DevSim *__restrict__ sims,
                                                           const DevTile *__restrict__ tiles,
-                                                          const DevClock *__restrict__ clk) {
+                                                          int64_t n0, int parity) {
   using R = double;
   using CL = Cell<N, R>;
   constexpr int M = CL::M, MA = CL::MA, S = mat_stride(N);
   const DevTile tile = tiles[blockIdx.x];
   const DevSim &sim = sims[tile.sim];
-  const int64_t n = clk->n0 - sim.start;
+  const int64_t n = n0 - sim.start;
   if (n < 0 || n >= sim.n_steps) return;
   const int64_t nx = sim.nx;
   const int64_t c = int64_t(tile.c0) + threadIdx.x;
   if (c >= nx) return;
-  const int par = clk->parity ^ sim.parity_off;
+  const int par = parity ^ sim.parity_off;
   const R *__restrict__ e_in = static_cast<const R *>(sim.e[par]);
   R *__restrict__ hh = static_cast<R *>(sim.h[0]);
   R *__restrict__ xx = static_cast<R *>(sim.x[0]);
@@ -335,17 +335,17 @@ __device__ __forceinline__ double plain_interior(const DevSim &sim, const double
 template <int N>
 __global__ void __launch_bounds__(kPlainBlock) k_plain_e(const DevSim *__restrict__ sims,
                                                          const DevTile *__restrict__ tiles,
-                                                         const DevClock *__restrict__ clk) {
+                                                         int64_t n0, int parity) {
   using R = double;
   constexpr int S = mat_stride(N);
   const DevTile tile = tiles[blockIdx.x];
   const DevSim &sim = sims[tile.sim];
-  const int64_t n = clk->n0 - sim.start;
+  const int64_t n = n0 - sim.start;
   if (n < 0 || n >= sim.n_steps) return;
   const int64_t nx = sim.nx;
   const int64_t c = int64_t(tile.c0) + threadIdx.x;
   if (c >= nx) return;
-  const int par = clk->parity ^ sim.parity_off;
+  const int par = parity ^ sim.parity_off;
   const R *__restrict__ e_in = static_cast<const R *>(sim.e[par]);
   R *__restrict__ e_out = static_cast<R *>(sim.e[par ^ 1]);
   const R *__restrict__ hh = static_cast<const R *>(sim.h[0]);
@@ -375,22 +375,15 @@ __global__ void __launch_bounds__(kPlainBlock) k_plain_e(const DevSim *__restric
   if (!isfinite(e)) *sim.status = 1;
 }
 
-__global__ void k_advance(DevClock *clk, int k) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    clk->n0 += k;
-    clk->parity ^= 1;
-  }
-}
-
 template <int N, typename R>
 hipError_t launch_blocked_nr(int block, const DevSim *sims, const DevTile *tiles, int n_tiles,
-                             const DevClock *clk, int halo, int k, hipStream_t st) {
+                             int64_t n0, int parity, int halo, int k, hipStream_t st) {
   switch (block) {
-    case 64: k_blocked<N, R, 64><<<n_tiles, 64, 0, st>>>(sims, tiles, clk, halo, k); break;
-    case 128: k_blocked<N, R, 128><<<n_tiles, 128, 0, st>>>(sims, tiles, clk, halo, k); break;
-    case 256: k_blocked<N, R, 256><<<n_tiles, 256, 0, st>>>(sims, tiles, clk, halo, k); break;
-    case 512: k_blocked<N, R, 512><<<n_tiles, 512, 0, st>>>(sims, tiles, clk, halo, k); break;
-    case 1024: k_blocked<N, R, 1024><<<n_tiles, 1024, 0, st>>>(sims, tiles, clk, halo, k); break;
+    case 64: k_blocked<N, R, 64><<<n_tiles, 64, 0, st>>>(sims, tiles, n0, parity, halo, k); break;
+    case 128: k_blocked<N, R, 128><<<n_tiles, 128, 0, st>>>(sims, tiles, n0, parity, halo, k); break;
+    case 256: k_blocked<N, R, 256><<<n_tiles, 256, 0, st>>>(sims, tiles, n0, parity, halo, k); break;
+    case 512: k_blocked<N, R, 512><<<n_tiles, 512, 0, st>>>(sims, tiles, n0, parity, halo, k); break;
+    case 1024: k_blocked<N, R, 1024><<<n_tiles, 1024, 0, st>>>(sims, tiles, n0, parity, halo, k); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -398,25 +391,25 @@ hipError_t launch_blocked_nr(int block, const DevSim *sims, const DevTile *tiles
 
 template <typename R>
 hipError_t launch_blocked_r(int levels, int block, const DevSim *sims, const DevTile *tiles,
-                            int n_tiles, const DevClock *clk, int halo, int k, hipStream_t st) {
+                            int n_tiles, int64_t n0, int parity, int halo, int k, hipStream_t st) {
   switch (levels) {
-    case 0: return launch_blocked_nr<0, R>(block, sims, tiles, n_tiles, clk, halo, k, st);
-    case 2: return launch_blocked_nr<2, R>(block, sims, tiles, n_tiles, clk, halo, k, st);
-    case 3: return launch_blocked_nr<3, R>(block, sims, tiles, n_tiles, clk, halo, k, st);
-    case 4: return launch_blocked_nr<4, R>(block, sims, tiles, n_tiles, clk, halo, k, st);
-    case 5: return launch_blocked_nr<5, R>(block, sims, tiles, n_tiles, clk, halo, k, st);
-    case 6: return launch_blocked_nr<6, R>(block, sims, tiles, n_tiles, clk, halo, k, st);
+    case 0: return launch_blocked_nr<0, R>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 2: return launch_blocked_nr<2, R>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 3: return launch_blocked_nr<3, R>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 4: return launch_blocked_nr<4, R>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 5: return launch_blocked_nr<5, R>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 6: return launch_blocked_nr<6, R>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
   }
   return hipErrorInvalidValue;
 }
 
 template <int N>
-hipError_t launch_plain_n(const DevSim *sims, const DevTile *tiles, int n_tiles, const DevClock *clk,
+hipError_t launch_plain_n(const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity,
                           hipStream_t st) {
-  k_plain_hd<N><<<n_tiles, kPlainBlock, 0, st>>>(sims, tiles, clk);
+  k_plain_hd<N><<<n_tiles, kPlainBlock, 0, st>>>(sims, tiles, n0, parity);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  k_plain_e<N><<<n_tiles, kPlainBlock, 0, st>>>(sims, tiles, clk);
+  k_plain_e<N><<<n_tiles, kPlainBlock, 0, st>>>(sims, tiles, n0, parity);
   return hipGetLastError();
 }
 
@@ -429,32 +422,27 @@ bool block_supported(int block) {
 int plain_block() { return kPlainBlock; }
 
 hipError_t launch_blocked(int levels, int precision, int block, const DevSim *sims,
-                          const DevTile *tiles, int n_tiles, const DevClock *clk, int halo, int k,
+                          const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo, int k,
                           hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
   if (k < 1 || k > halo || 2 * halo >= block) return hipErrorInvalidValue;
   if (precision == 64)
-    return launch_blocked_r<double>(levels, block, sims, tiles, n_tiles, clk, halo, k, st);
-  return launch_blocked_r<float>(levels, block, sims, tiles, n_tiles, clk, halo, k, st);
+    return launch_blocked_r<double>(levels, block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+  return launch_blocked_r<float>(levels, block, sims, tiles, n_tiles, n0, parity, halo, k, st);
 }
 
 hipError_t launch_plain(int levels, const DevSim *sims, const DevTile *tiles, int n_tiles,
-                        const DevClock *clk, hipStream_t st) {
+                        int64_t n0, int parity, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
   switch (levels) {
-    case 0: return launch_plain_n<0>(sims, tiles, n_tiles, clk, st);
-    case 2: return launch_plain_n<2>(sims, tiles, n_tiles, clk, st);
-    case 3: return launch_plain_n<3>(sims, tiles, n_tiles, clk, st);
-    case 4: return launch_plain_n<4>(sims, tiles, n_tiles, clk, st);
-    case 5: return launch_plain_n<5>(sims, tiles, n_tiles, clk, st);
-    case 6: return launch_plain_n<6>(sims, tiles, n_tiles, clk, st);
+    case 0: return launch_plain_n<0>(sims, tiles, n_tiles, n0, parity, st);
+    case 2: return launch_plain_n<2>(sims, tiles, n_tiles, n0, parity, st);
+    case 3: return launch_plain_n<3>(sims, tiles, n_tiles, n0, parity, st);
+    case 4: return launch_plain_n<4>(sims, tiles, n_tiles, n0, parity, st);
+    case 5: return launch_plain_n<5>(sims, tiles, n_tiles, n0, parity, st);
+    case 6: return launch_plain_n<6>(sims, tiles, n_tiles, n0, parity, st);
   }
   return hipErrorInvalidValue;
-}
-
-hipError_t launch_advance(DevClock *clk, int k, hipStream_t st) {
-  k_advance<<<1, 64, 0, st>>>(clk, k);
-  return hipGetLastError();
 }
 
 }  // namespace mb

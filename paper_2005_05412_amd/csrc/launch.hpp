@@ -10,14 +10,13 @@ namespace mb {
 bool block_supported(int block);
 int plain_block();
 
-// Temporally blocked launch: k <= halo steps for every tile; 2*halo < block.
+// Temporally blocked launch from engine step n0 with buffer parity `parity`:
+// k <= halo steps for every tile; 2*halo < block.
 hipError_t launch_blocked(int levels, int precision, int block, const DevSim *sims,
-                          const DevTile *tiles, int n_tiles, const DevClock *clk, int halo, int k,
+                          const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo, int k,
                           hipStream_t st);
 // One time step as two launches (FP64); tiles of plain_block() cells.
 hipError_t launch_plain(int levels, const DevSim *sims, const DevTile *tiles, int n_tiles,
-                        const DevClock *clk, hipStream_t st);
-// clk->n0 += k, clk->parity ^= 1 (one thread).
-hipError_t launch_advance(DevClock *clk, int k, hipStream_t st);
+                        int64_t n0, int parity, hipStream_t st);
 
 }  // namespace mb

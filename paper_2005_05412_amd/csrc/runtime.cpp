@@ -13,7 +13,7 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 constexpr int kStatusSlots = 4096;
 
 struct Layout {
-  size_t e, h, x, p, mat_e, mat_h, mtab, src, src_tab, rec, readout, rec_first, rec_ids, rec_all;
+  size_t e, h, x, init_e, init_x, p, mat_e, mat_h, mtab, src, src_tab, rec, readout, rec_first, rec_ids, rec_all;
   size_t outputs, end_head, total;
   std::vector<size_t> tab_off, ro_off, out_off;
   int n_point = 0, n_all = 0;
@@ -33,6 +33,8 @@ Layout layout_of(const SimPlan &p, int precision, bool plain) {
   L.e = take(2 * nx * rs);
   L.h = take(2 * nx * rs);
   L.x = take(std::max<size_t>(1, 2 * m * nx) * rs);
+  L.init_e = take(nx * rs);
+  L.init_x = take(std::max<size_t>(1, m * nx) * rs);
   L.p = take(plain ? nx * rs : rs);
   L.mat_e = take(nx);
   L.mat_h = take(nx);
@@ -84,12 +86,14 @@ void fill_state(const SimPlan &p, char *head, const Layout &L) {
   R *e = reinterpret_cast<R *>(head + L.e);
   R *h = reinterpret_cast<R *>(head + L.h);
   R *x = reinterpret_cast<R *>(head + L.x);
+  R *ie = reinterpret_cast<R *>(head + L.init_e);
+  R *ix = reinterpret_cast<R *>(head + L.init_x);
   for (size_t c = 0; c < nx; ++c) {
-    e[c] = e[nx + c] = R(p.e0[c]);
+    e[c] = e[nx + c] = ie[c] = R(p.e0[c]);
     h[c] = h[nx + c] = R(0);
   }
   const size_t mn = size_t(p.m) * nx;
-  for (size_t q = 0; q < mn; ++q) x[q] = x[mn + q] = R(p.x0[q]);
+  for (size_t q = 0; q < mn; ++q) x[q] = x[mn + q] = ix[q] = R(p.x0[q]);
   fill_mtab<R>(p, reinterpret_cast<R *>(head + L.mtab));
 }
 
@@ -176,7 +180,6 @@ Engine::~Engine() {
     if (g.d_sims) (void)hipFree(g.d_sims);
     if (g.d_tiles) (void)hipFree(g.d_tiles);
   }
-  if (d_clk_) (void)hipFree(d_clk_);
   if (d_status_) (void)hipFree(d_status_);
 }
 
@@ -191,14 +194,11 @@ int Engine::init(std::string &err) {
       return MB_ERR_ARG;
     }
   }
-  if (hipMalloc(&d_clk_, sizeof(DevClock)) != hipSuccess ||
-      hipMalloc(&d_status_, kStatusSlots * sizeof(int32_t)) != hipSuccess) {
+  if (hipMalloc(&d_status_, kStatusSlots * sizeof(int32_t)) != hipSuccess) {
     err = "device allocation failed";
     return MB_ERR_OOM;
   }
-  DevClock c{0, 0, 0};
-  if (hipMemcpy(d_clk_, &c, sizeof(c), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemset(d_status_, 0, kStatusSlots * sizeof(int32_t)) != hipSuccess) {
+  if (hipMemset(d_status_, 0, kStatusSlots * sizeof(int32_t)) != hipSuccess) {
     err = "device initialisation failed";
     return MB_ERR_HIP;
   }
@@ -241,6 +241,9 @@ int Engine::add(SimPlan &&plan, Arena *arena, hipStream_t st, std::string &err) 
   s->plan = std::move(plan);
   SimPlan &p = s->plan;
   s->bytes = L.total;
+  s->init_e = L.init_e;
+  s->init_x = L.init_x;
+  s->out_begin = L.end_head;
   s->block = block;
   s->own_block = arena == nullptr;
   // host image of everything before the record outputs
@@ -339,6 +342,7 @@ int Engine::add(SimPlan &&plan, Arena *arena, hipStream_t st, std::string &err) 
   group_for(p.n).members.push_back(id);
   sims_.push_back(std::move(s));
   dirty_ = true;
+  ++version_;
   return id;
 }
 
@@ -351,6 +355,7 @@ void Engine::remove(int id, Arena *arena) {
     }
     s.active = false;
     dirty_ = true;
+    ++version_;
   }
   if (s.block) {
     if (s.own_block)
@@ -411,21 +416,49 @@ hipError_t Engine::launch_only(hipStream_t st, int k) {
     for (int s = 0; s < k; ++s) {
       for (auto &g : groups_) {
         if (g.members.empty()) continue;
-        hipError_t e = launch_plain(g.levels, g.d_sims, g.d_tiles, g.n_tiles, d_clk_, st);
+        hipError_t e = launch_plain(g.levels, g.d_sims, g.d_tiles, g.n_tiles, n0_ + s, parity_ ^ (s & 1), st);
         if (e != hipSuccess) return e;
       }
-      hipError_t e = launch_advance(d_clk_, 1, st);
-      if (e != hipSuccess) return e;
     }
     return hipSuccess;
   }
   for (auto &g : groups_) {
     if (g.members.empty()) continue;
-    hipError_t e = launch_blocked(g.levels, precision_, block_, g.d_sims, g.d_tiles, g.n_tiles, d_clk_,
+    hipError_t e = launch_blocked(g.levels, precision_, block_, g.d_sims, g.d_tiles, g.n_tiles, n0_, parity_,
                                   halo_, k, st);
     if (e != hipSuccess) return e;
   }
-  return launch_advance(d_clk_, k, st);
+  return hipSuccess;
+}
+
+hipError_t Engine::reset(hipStream_t st) {
+  n0_ = 0;
+  parity_ = 0;
+  cell_updates_ = 0;
+  const size_t rs = precision_ == 64 ? 8 : 4;
+  for (auto &sp : sims_) {
+    SimState &s = *sp;
+    if (!s.active || !s.block) continue;
+    const size_t nx = size_t(s.plan.nx), m = size_t(s.plan.m);
+    hipError_t e = hipSuccess;
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+      e = hipMemcpyAsync(s.ds.e[b], s.block + s.init_e, nx * rs, hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess) e = hipMemsetAsync(s.ds.h[b], 0, nx * rs, st);
+      if (e == hipSuccess && m)
+        e = hipMemcpyAsync(s.ds.x[b], s.block + s.init_x, m * nx * rs, hipMemcpyDeviceToDevice, st);
+    }
+    if (e == hipSuccess && s.bytes > s.out_begin) e = hipMemsetAsync(s.block + s.out_begin, 0, s.bytes - s.out_begin, st);
+    if (e == hipSuccess) e = hipMemsetAsync(s.ds.status, 0, sizeof(int32_t), st);
+    if (e != hipSuccess) return e;
+    s.start = 0;
+    s.parity_off = 0;
+    s.ds.start = 0;
+    s.ds.parity_off = 0;
+    s.done = 0;
+    s.cur_e = s.cur_h = s.cur_x = 0;
+  }
+  dirty_ = true;
+  return sync_tables(st);
 }
 
 void Engine::commit_chunk(int k) {

@@ -45,6 +45,7 @@ struct SimState {
   int cur_e = 0, cur_h = 0, cur_x = 0;  // buffers holding the current state
   int64_t done = 0;            // steps completed (host mirror)
   std::vector<size_t> rec_off; // device offsets of record outputs inside block
+  size_t init_e = 0, init_x = 0, out_begin = 0;  // initial-state images, start of outputs
   bool active = false;
   int status_slot = -1;
 };
@@ -73,6 +74,11 @@ class Engine {
   // Launches of one chunk, for graph capture: tables must be current.
   hipError_t launch_only(hipStream_t st, int k);
   void commit_chunk(int k);  // host bookkeeping of a chunk launched via launch_only
+  // Restores every simulation's initial state from its device image and
+  // clears records (asynchronous copies on st, then table upload).
+  hipError_t reset(hipStream_t st);
+  // Changes whenever tables or the step origin change (graph cache key).
+  int64_t version() const { return version_; }
 
   bool finished(int id) const;
   bool all_finished() const;
@@ -105,7 +111,7 @@ class Engine {
   std::vector<std::unique_ptr<SimState>> sims_;
   std::vector<Group> groups_;
   bool dirty_ = true;
-  DevClock *d_clk_ = nullptr;
+  int64_t version_ = 0;
   int32_t *d_status_ = nullptr;
   int status_cap_ = 0;
   std::vector<int> free_slots_;

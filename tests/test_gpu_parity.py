@@ -29,10 +29,11 @@ def _say(msg):
 
 def rel_errors(prob, got, ref):
     """name -> relative max-norm error of each recorded trace."""
-    fmax = 0.0
+    fmax = max([s["amp"] for s in prob["sources"]] + [0.0])
     for r in prob["records"]:
-        if r["quantity"] in ("e", "h") and ref[r["name"]].size:
+        if r["quantity"] == "e" and ref[r["name"]].size:
             fmax = max(fmax, float(np.max(np.abs(ref[r["name"]]))))
+    eta = math.sqrt(prob["consts"]["mu0"] / prob["consts"]["eps0"])
     out = {}
     for r in prob["records"]:
         a, b = np.asarray(got[r["name"]]), np.asarray(ref[r["name"]])
@@ -40,7 +41,7 @@ def rel_errors(prob, got, ref):
         if b.size == 0:
             out[r["name"]] = 0.0
             continue
-        floor = 1e-3 * fmax if r["quantity"] in ("e", "h") else 1e-3
+        floor = {"e": 1e-3 * fmax, "h": 1e-3 * fmax / eta}.get(r["quantity"], 1e-3)
         if b.ndim == 2:   # whole-domain record: one trace per cell
             den = np.maximum(np.max(np.abs(b), axis=0), floor)
             out[r["name"]] = float(np.max(np.max(np.abs(a - b), axis=0) / den))
@@ -135,7 +136,7 @@ def test_nonfinite_field_is_reported():
     prob = W.random_small(23, N=2, nx=40, n_steps=10, full_records=False)
     prob["records"] = [W.record("e", "e", 20, 1)]
     prob["e_init"] = np.zeros(40)
-    prob["e_init"][20] = np.nan
+    prob["e_init"][20], prob["e_init"][21] = 1.7e308, -1.7e308   # finite, overflows in the first step
     s = mb.Solver(prob, precision=64)
     s.run()
     with pytest.raises(mb.MBError) as ex:
@@ -187,16 +188,16 @@ def test_lambda3_full_length_blocked_equals_plain_and_invariants():
         names = [r["name"] for r in prob["records"][3 * k: 3 * k + 3]]
         pops = np.array([blk[n] for n in names])
         assert np.max(np.abs(pops.sum(axis=0) - 1.0)) < 1e-12
-        assert pops.min() > -1e-12 and pops.max() < 1 + 1e-12
+        assert pops.min() > -1e-10 and pops.max() < 1 + 1e-10
 
 
 # ---------------------------------------------------------------- batching and serving
 
-def _mixed_batch(n=6, n_steps=400, precision=32):
+def _mixed_batch(n=6, n_steps=1600, precision=32):
     rng = np.random.default_rng(5)
     probs = []
     for k in range(n):
-        nx = int(rng.integers(50, 700))
+        nx = int(rng.integers(50, 500))
         probs.append(W.sweep_sim(k, rng, nx=nx, n_steps=n_steps + 37 * k, precision=precision,
                                  rec_interval=5))
     return probs
@@ -243,7 +244,7 @@ def test_server_results_equal_alone():
 
 def test_server_budget_and_cancel():
     p = _mixed_batch(n=1, n_steps=100, precision=32)[0]
-    srv = mb.Server(hbm_budget=1 << 16, max_slots=2, precision=32, chunk_steps=16)
+    srv = mb.Server(hbm_budget=1 << 12, max_slots=2, precision=32, chunk_steps=16)
     with pytest.raises(mb.MBError) as ex:
         srv.submit(p)
     assert ex.value.code == -5
@@ -259,3 +260,18 @@ def test_server_budget_and_cancel():
     assert srv.status(t1)[0] == 2
     assert srv.status(t2)[0] == 3
     srv.close()
+
+
+def test_reset_and_graph_replay_reproduce_the_run():
+    """mb_reset restores the initial state; the replayed graph gives identical records."""
+    prob = W.random_small(24, N=2, nx=400, n_steps=300, refl=(0.0, 0.0), full_records=False)
+    prob["records"] = [W.record("e", "e", 200, 3), W.record("inv", "inv", 150, 3, 0, 1)]
+    s = mb.Solver(prob, precision=32, variant="blocked", block=128, depth=16)
+    s.run()
+    first = s.records()
+    for _ in range(2):
+        s.reset()
+        s.run()
+        again = s.records()
+        assert_same(first, again)
+    s.close()
