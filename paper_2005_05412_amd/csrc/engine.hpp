@@ -53,7 +53,7 @@ struct DevSim {
   const int32_t *rec_ids;
   const int32_t *rec_all;    // whole-domain record ids
   int32_t *status;           // bit 0: non-finite field seen
-  int32_t pad;
+  int32_t rec_every;         // gcd of the record intervals (1 when there are no records)
 };
 
 struct DevTile {

@@ -1,9 +1,11 @@
 // HIP kernels for gfx950: one time step of the 1D Maxwell-Bloch system per
 // cell and lane.  State is structure-of-arrays (E, H and the M = N*N - 1
-// density parameters as separate planes), coefficients are per material and
-// read with wave-uniform addresses, every step of a cell is the same
+// density parameters as separate planes); per-material coefficients are
+// read through the constant address space with wave-uniform addresses (so
+// they become scalar loads into SGPRs); every step of a cell is the same
 // arithmetic in the two-launch and in the blocked kernels (explicit fma, no
-// contraction), so both produce bit-identical results.
+// contraction), so both produce bit-identical results.  Indices are 32-bit
+// (the host rejects grids where M * nx or the step count reach 2^31).
 #include <hip/hip_runtime.h>
 
 #include "engine.hpp"
@@ -12,8 +14,61 @@
 namespace mb {
 namespace {
 
-__device__ __forceinline__ void sincos_r(double a, double *s, double *c) { sincos(a, s, c); }
-__device__ __forceinline__ void sincos_r(float a, float *s, float *c) { sincosf(a, s, c); }
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+
+template <typename T>
+__device__ __forceinline__ cptr<T> kconst(const void *p) {
+  return (cptr<T>)(p);
+}
+
+// (cos t - 1, sin t) of a field phase.  Small angles (the usual case: the
+// phase per step is E dt (lam_j - lam_k)/hbar, a few 1e-2 rad) use the
+// Taylor series truncated where the remainder drops below half an ulp;
+// larger ones use the library sincos of t/2 with cos t - 1 = -2 sin^2(t/2).
+__device__ __forceinline__ void phase(double t, double &cm, double &sn) {
+  if (fabs(t) <= 0.25) {
+    const double t2 = t * t;
+    double s = fma(t2, -1.0 / 6227020800.0, 1.0 / 39916800.0);
+    s = fma(t2, s, -1.0 / 362880.0);
+    s = fma(t2, s, 1.0 / 5040.0);
+    s = fma(t2, s, -1.0 / 120.0);
+    s = fma(t2, s, 1.0 / 6.0);
+    sn = fma(-t * t2, s, t);  // t - t^3 (1/3! - t^2/5! + ...)
+    double c = fma(t2, 1.0 / 87178291200.0, -1.0 / 479001600.0);
+    c = fma(t2, c, 1.0 / 3628800.0);
+    c = fma(t2, c, -1.0 / 40320.0);
+    c = fma(t2, c, 1.0 / 720.0);
+    c = fma(t2, c, -1.0 / 24.0);
+    c = fma(t2, c, 0.5);
+    cm = -t2 * c;             // -(t^2/2! - t^4/4! + ...)
+  } else {
+    double s, c;
+    sincos(0.5 * t, &s, &c);
+    sn = 2.0 * s * c;
+    cm = -2.0 * s * s;
+  }
+}
+
+__device__ __forceinline__ void phase(float t, float &cm, float &sn) {
+  if (fabsf(t) <= 0.5f) {
+    const float t2 = t * t;
+    float s = fmaf(t2, 1.0f / 362880.0f, -1.0f / 5040.0f);
+    s = fmaf(t2, s, 1.0f / 120.0f);
+    s = fmaf(t2, s, -1.0f / 6.0f);
+    sn = fmaf(t * t2, s, t);
+    float c = fmaf(t2, -1.0f / 3628800.0f, 1.0f / 40320.0f);
+    c = fmaf(t2, c, -1.0f / 720.0f);
+    c = fmaf(t2, c, 1.0f / 24.0f);
+    c = fmaf(t2, c, -0.5f);
+    cm = t2 * c;
+  } else {
+    float s, c;
+    sincosf(0.5f * t, &s, &c);
+    sn = 2.0f * s * c;
+    cm = -2.0f * s * s;
+  }
+}
 
 template <int N, typename R>
 struct Cell {
@@ -22,36 +77,29 @@ struct Cell {
 
   // y <- Phi_E(y): coherence (j, k), j < k, of the state in the dipole
   // eigen-basis gains the phase theta_jk = dt E (lam_j - lam_k)/hbar, the
-  // sum of consecutive angles E kappa_q.  Each phase is kept as
-  // (cos - 1, sin) from a half-angle sincos so that the rotation is applied
-  // as a small increment.
-  static __device__ __forceinline__ void rotate(R (&y)[MA], R e, const R *__restrict__ mt) {
+  // sum of the consecutive angles E kappa_q; each phase is carried as
+  // (cos - 1, sin) and applied as a small increment.
+  static __device__ __forceinline__ void rotate(R (&y)[MA], R e, cptr<R> mt) {
     if constexpr (N >= 2) {
       R cm[N - 1], sn[N - 1];
 #pragma unroll
-      for (int q = 0; q < N - 1; ++q) {
-        R half = e * mt[kCoefKap + q] * R(0.5);
-        R s, c;
-        sincos_r(half, &s, &c);
-        sn[q] = R(2) * s * c;
-        cm[q] = R(-2) * s * s;
-      }
+      for (int q = 0; q < N - 1; ++q) phase(e * mt[kCoefKap + q], cm[q], sn[q]);
 #pragma unroll
       for (int j = 0; j < N - 1; ++j) {
         R pc = cm[j], ps = sn[j];
 #pragma unroll
         for (int k = j + 1; k < N; ++k) {
           if (k > j + 1) {
-            // (1 + pc + i ps)(1 + cm + i sn) = 1 + (pc + cm + pc cm - ps sn) + i (ps + sn + ps cm + pc sn)
-            R c2 = cm[k - 1], s2 = sn[k - 1];
-            R nc = fma(pc, c2, fma(-ps, s2, pc + c2));
-            R ns = fma(ps, c2, fma(pc, s2, ps + s2));
+            // (1 + pc + i ps)(1 + c2 + i s2) - 1
+            const R c2 = cm[k - 1], s2 = sn[k - 1];
+            const R nc = fma(pc, c2, fma(-ps, s2, pc + c2));
+            const R ns = fma(ps, c2, fma(pc, s2, ps + s2));
             pc = nc;
             ps = ns;
           }
           const int p = k * (k - 1) / 2 + j;
           const int ir = N - 1 + 2 * p, ii = ir + 1;
-          R re = y[ir], im = y[ii];
+          const R re = y[ir], im = y[ii];
           y[ir] = re + fma(re, pc, -(im * ps));
           y[ii] = im + fma(re, ps, im * pc);
         }
@@ -60,7 +108,7 @@ struct Cell {
   }
 
   // polarization current n3D tr{mu L0(rho^{n+1/2})} = at . y + p0
-  static __device__ __forceinline__ R polar(const R (&y)[MA], const R *__restrict__ mt) {
+  static __device__ __forceinline__ R polar(const R (&y)[MA], cptr<R> mt) {
     R acc = mt[coef_p0(N)];
 #pragma unroll
     for (int j = 0; j < M; ++j) acc = fma(mt[coef_at(N) + j], y[j], acc);
@@ -68,7 +116,7 @@ struct Cell {
   }
 
   // sigma_{n+1} = e^{L0 dt} y = y + (bf + am y)
-  static __device__ __forceinline__ void propagate(R (&y)[MA], const R *__restrict__ mt) {
+  static __device__ __forceinline__ void propagate(R (&y)[MA], cptr<R> mt) {
     R out[MA];
 #pragma unroll
     for (int i = 0; i < M; ++i) {
@@ -89,36 +137,45 @@ struct Cell {
   }
 };
 
-__device__ __forceinline__ bool due(int64_t n1, int64_t interval) { return n1 % interval == 0; }
+__device__ __forceinline__ bool due(uint32_t n1, int64_t interval) { return n1 % uint32_t(interval) == 0u; }
 
-// density records of one cell at local step n (values of rho^{n+1/2})
+// density records of one cell after local step n1 - 1 (values of rho^{n+1/2})
 template <int N, typename R>
-__device__ __forceinline__ void record_density(const DevSim &sim, int64_t c, int64_t n1, int mat,
-                                               const R (&y)[Cell<N, R>::MA]) {
+__device__ __forceinline__ void record_density(const DevSim &sim, int c, uint32_t n1, int mat,
+                                            const R (&y)[Cell<N, R>::MA]) {
   constexpr int M = Cell<N, R>::M;
   if (sim.rec_first) {
     const int32_t b = sim.rec_first[c], e = sim.rec_first[c + 1];
     for (int32_t r = b; r < e; ++r) {
       const DevRecord &rc = sim.rec[sim.rec_ids[r]];
       if (rc.quantity < 2 || !due(n1, rc.interval)) continue;
-      rc.out[n1 / rc.interval - 1] = Cell<N, R>::readout(y, rc.readout + int64_t(mat) * (M + 1));
+      rc.out[n1 / uint32_t(rc.interval) - 1] = Cell<N, R>::readout(y, rc.readout + mat * (M + 1));
     }
   }
   for (int32_t r = 0; r < sim.n_rec_all; ++r) {
     const DevRecord &rc = sim.rec[sim.rec_all[r]];
     if (rc.quantity < 2 || !due(n1, rc.interval)) continue;
-    rc.out[(n1 / rc.interval - 1) * sim.nx + c] = Cell<N, R>::readout(y, rc.readout + int64_t(mat) * (M + 1));
+    rc.out[size_t(n1 / uint32_t(rc.interval) - 1) * size_t(sim.nx) + c] =
+        Cell<N, R>::readout(y, rc.readout + mat * (M + 1));
   }
 }
 
 // field records (E^{n+1}, H^{n+1/2}) and zero density values outside quantum cells
 template <typename R>
-__device__ __forceinline__ void record_fields(const DevSim &sim, int64_t c, int64_t n1, R e, R h,
-                                              bool qm) {
+__device__ __noinline__ void record_fields(const DevSim &sim, int c, uint32_t n1, R e, R h, bool qm) {
   auto val = [&](const DevRecord &rc, double &v) -> bool {
-    if (rc.quantity == 0) { v = double(e); return true; }
-    if (rc.quantity == 1) { v = double(h); return true; }
-    if (!qm) { v = 0.0; return true; }
+    if (rc.quantity == 0) {
+      v = double(e);
+      return true;
+    }
+    if (rc.quantity == 1) {
+      v = double(h);
+      return true;
+    }
+    if (!qm) {
+      v = 0.0;
+      return true;
+    }
     return false;
   };
   if (sim.rec_first) {
@@ -127,22 +184,26 @@ __device__ __forceinline__ void record_fields(const DevSim &sim, int64_t c, int6
       const DevRecord &rc = sim.rec[sim.rec_ids[r]];
       double v;
       if (!due(n1, rc.interval) || !val(rc, v)) continue;
-      rc.out[n1 / rc.interval - 1] = v;
+      rc.out[n1 / uint32_t(rc.interval) - 1] = v;
     }
   }
   for (int32_t r = 0; r < sim.n_rec_all; ++r) {
     const DevRecord &rc = sim.rec[sim.rec_all[r]];
     double v;
     if (!due(n1, rc.interval) || !val(rc, v)) continue;
-    rc.out[(n1 / rc.interval - 1) * sim.nx + c] = v;
+    rc.out[size_t(n1 / uint32_t(rc.interval) - 1) * size_t(sim.nx) + c] = v;
   }
 }
 
+__device__ __forceinline__ bool has_records(const DevSim &sim, int c) {
+  return sim.n_rec_all > 0 || (sim.rec_first && sim.rec_first[c + 1] > sim.rec_first[c]);
+}
+
 template <typename R>
-__device__ __forceinline__ R apply_sources(const DevSim &sim, int64_t c, int64_t n1, R e) {
+__device__ __forceinline__ R apply_sources(const DevSim &sim, int c, uint32_t n1, R e) {
   for (int32_t j = 0; j < sim.n_src; ++j) {
     const DevSource &s = sim.src[j];
-    if (s.cell != c) continue;
+    if (int(s.cell) != c) continue;
     const R v = R(s.table[n1]);
     e = s.hard ? v : e + v;
   }
@@ -153,30 +214,32 @@ __device__ __forceinline__ R apply_sources(const DevSim &sim, int64_t c, int64_t
 // Temporally blocked kernel: one workgroup owns T = B - 2*halo consecutive
 // cells of one simulation, loads them with `halo` extra cells on both sides,
 // advances up to k <= halo steps with neighbour values exchanged through LDS
-// (the valid region shrinks by one cell per side and step), and writes the
-// owned cells to the other state buffer.
+// (the valid region shrinks by one cell per side and step, as the redundant
+// computation of overlapped tiles), and writes the owned cells to the other
+// state buffer.
 // ---------------------------------------------------------------------------
 template <int N, typename R, int B>
 __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
-                                               const DevTile *__restrict__ tiles,
-                                               int64_t n0, int parity, int halo, int k) {
+                                               const DevTile *__restrict__ tiles, int64_t n0, int parity,
+                                               int halo, int k) {
   using CL = Cell<N, R>;
   constexpr int M = CL::M, MA = CL::MA, S = mat_stride(N);
   __shared__ R se[B], sh[B], se2[B];
   const DevTile tile = tiles[blockIdx.x];
   const DevSim &sim = sims[tile.sim];
-  const int64_t ls0 = n0 - sim.start;
-  if (ls0 < 0 || ls0 >= sim.n_steps) return;
-  const int ks = int(min(int64_t(k), sim.n_steps - ls0));
+  const int64_t ls64 = n0 - sim.start;
+  if (ls64 < 0 || ls64 >= sim.n_steps) return;
+  const int ls0 = int(ls64);
+  const int ks = int(min(int64_t(k), sim.n_steps - ls64));
   const int par = parity ^ sim.parity_off;
-  const int64_t nx = sim.nx;
+  const int nx = int(sim.nx);
   const R *__restrict__ e_in = static_cast<const R *>(sim.e[par]);
   const R *__restrict__ h_in = static_cast<const R *>(sim.h[par]);
   const R *__restrict__ x_in = static_cast<const R *>(sim.x[par]);
-  const R *__restrict__ mtab = static_cast<const R *>(sim.mtab);
+  const cptr<R> mtab = kconst<R>(sim.mtab);
   const int l = threadIdx.x;
-  const int64_t lo = int64_t(tile.c0) - halo;
-  const int64_t c = lo + l;
+  const int lo = tile.c0 - halo;
+  const int c = lo + l;
   const bool in = c >= 0 && c < nx;
   const bool own = in && l >= halo && l < B - halo;
   int me = 0;
@@ -207,11 +270,13 @@ __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
   const bool left = in && nx > 1 && c == 0, right = in && nx > 1 && c == nx - 1;
   const bool mur_tile = nx > 1 && ((sim.edge_l == 1 && lo <= 0 && 0 < lo + B) ||
                                    (sim.edge_r == 1 && lo <= nx - 1 && nx - 1 < lo + B));
-  const bool rec_any = sim.n_rec > 0;
+  const bool rec_here = sim.n_rec > 0 && own && has_records(sim, c);
+  const uint32_t rec_every = uint32_t(sim.rec_every);
   const R kap_l = R(sim.kap_l), kap_r = R(sim.kap_r);
 
   for (int s = 0; s < ks; ++s) {
-    const int64_t n1 = ls0 + s + 1;
+    const uint32_t n1 = uint32_t(ls0 + s + 1);
+    const bool rec_now = rec_here && n1 % rec_every == 0u;
     se[l] = e;
     __syncthreads();
     const R er = l + 1 < B ? se[l + 1] : R(0);
@@ -225,10 +290,10 @@ __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
         const int mm = __builtin_amdgcn_readlane(me, lead);
         const bool mine = qm && me == mm;
         if (mine) {
-          const R *__restrict__ mt = mtab + mm * S;
+          const cptr<R> mt = mtab + __builtin_amdgcn_readfirstlane(mm * S);  // uniform: scalar loads
           CL::rotate(x, e, mt);
           p = CL::polar(x, mt);
-          if (rec_any && own) record_density<N, R>(sim, c, n1, mm, x);
+          if (rec_now) record_density<N, R>(sim, c, n1, mm, x);
           CL::propagate(x, mt);
         }
         todo &= ~__ballot(mine);
@@ -247,7 +312,7 @@ __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
     }
     if ((left && sim.edge_l == 0) || (right && sim.edge_r == 0)) e = 0;
     if (in) e = apply_sources(sim, c, n1, e);
-    if (rec_any && own) record_fields(sim, c, n1, e, hcell ? h : R(0), qm);
+    if (rec_now) record_fields(sim, c, n1, e, hcell ? h : R(0), qm);
   }
   if (own) {
     R *__restrict__ e_out = static_cast<R *>(sim.e[par ^ 1]);
@@ -274,43 +339,45 @@ constexpr int kPlainBlock = 256;
 
 template <int N>
 __global__ void __launch_bounds__(kPlainBlock) k_plain_hd(const DevSim *__restrict__ sims,
-                                                          const DevTile *__restrict__ tiles,
-                                                          int64_t n0, int parity) {
+                                                          const DevTile *__restrict__ tiles, int64_t n0,
+                                                          int parity) {
   using R = double;
   using CL = Cell<N, R>;
   constexpr int M = CL::M, MA = CL::MA, S = mat_stride(N);
   const DevTile tile = tiles[blockIdx.x];
   const DevSim &sim = sims[tile.sim];
-  const int64_t n = n0 - sim.start;
-  if (n < 0 || n >= sim.n_steps) return;
-  const int64_t nx = sim.nx;
-  const int64_t c = int64_t(tile.c0) + threadIdx.x;
+  const int64_t n64 = n0 - sim.start;
+  if (n64 < 0 || n64 >= sim.n_steps) return;
+  const uint32_t n1 = uint32_t(n64 + 1);
+  const int nx = int(sim.nx);
+  const int c = tile.c0 + int(threadIdx.x);
   if (c >= nx) return;
   const int par = parity ^ sim.parity_off;
   const R *__restrict__ e_in = static_cast<const R *>(sim.e[par]);
   R *__restrict__ hh = static_cast<R *>(sim.h[0]);
   R *__restrict__ xx = static_cast<R *>(sim.x[0]);
   R *__restrict__ pp = static_cast<R *>(sim.p);
-  const R *__restrict__ mtab = static_cast<const R *>(sim.mtab);
+  const cptr<R> mtab = kconst<R>(sim.mtab);
   const R e = e_in[c];
   if (c <= nx - 2) hh[c] = fma(mtab[sim.mat_h[c] * S + kCoefH], e_in[c + 1] - e, hh[c]);
   R p = 0;
   if constexpr (N > 0) {
     const int me = sim.mat_e[c];
     const bool qm = mtab[me * S + kCoefQM] != R(0);
+    const bool rec_now = sim.n_rec > 0 && n1 % uint32_t(sim.rec_every) == 0u && has_records(sim, c);
     uint64_t todo = __ballot(qm);
     while (todo) {
       const int lead = __ffsll(static_cast<unsigned long long>(todo)) - 1;
       const int mm = __builtin_amdgcn_readlane(me, lead);
       const bool mine = qm && me == mm;
       if (mine) {
-        const R *__restrict__ mt = mtab + mm * S;
+        const cptr<R> mt = mtab + __builtin_amdgcn_readfirstlane(mm * S);  // uniform: scalar loads
         R x[MA];
 #pragma unroll
         for (int a = 0; a < M; ++a) x[a] = xx[a * nx + c];
         CL::rotate(x, e, mt);
         p = CL::polar(x, mt);
-        if (sim.n_rec > 0) record_density<N, R>(sim, c, n + 1, mm, x);
+        if (rec_now) record_density<N, R>(sim, c, n1, mm, x);
         CL::propagate(x, mt);
 #pragma unroll
         for (int a = 0; a < M; ++a) xx[a * nx + c] = x[a];
@@ -322,10 +389,8 @@ __global__ void __launch_bounds__(kPlainBlock) k_plain_hd(const DevSim *__restri
 }
 
 __device__ __forceinline__ double plain_interior(const DevSim &sim, const double *__restrict__ e_in,
-                                                 const double *__restrict__ hh,
-                                                 const double *__restrict__ pp,
-                                                 const double *__restrict__ mtab, int stride,
-                                                 int64_t c) {
+                                                 const double *__restrict__ hh, const double *__restrict__ pp,
+                                                 cptr<double> mtab, int stride, int c) {
   const int me = sim.mat_e[c];
   const double ca = mtab[me * stride + kCoefA], cbg = mtab[me * stride + kCoefBG],
                cbd = mtab[me * stride + kCoefBD];
@@ -334,40 +399,39 @@ __device__ __forceinline__ double plain_interior(const DevSim &sim, const double
 
 template <int N>
 __global__ void __launch_bounds__(kPlainBlock) k_plain_e(const DevSim *__restrict__ sims,
-                                                         const DevTile *__restrict__ tiles,
-                                                         int64_t n0, int parity) {
+                                                         const DevTile *__restrict__ tiles, int64_t n0,
+                                                         int parity) {
   using R = double;
   constexpr int S = mat_stride(N);
   const DevTile tile = tiles[blockIdx.x];
   const DevSim &sim = sims[tile.sim];
-  const int64_t n = n0 - sim.start;
-  if (n < 0 || n >= sim.n_steps) return;
-  const int64_t nx = sim.nx;
-  const int64_t c = int64_t(tile.c0) + threadIdx.x;
+  const int64_t n64 = n0 - sim.start;
+  if (n64 < 0 || n64 >= sim.n_steps) return;
+  const uint32_t n1 = uint32_t(n64 + 1);
+  const int nx = int(sim.nx);
+  const int c = tile.c0 + int(threadIdx.x);
   if (c >= nx) return;
   const int par = parity ^ sim.parity_off;
   const R *__restrict__ e_in = static_cast<const R *>(sim.e[par]);
   R *__restrict__ e_out = static_cast<R *>(sim.e[par ^ 1]);
   const R *__restrict__ hh = static_cast<const R *>(sim.h[0]);
   const R *__restrict__ pp = static_cast<const R *>(sim.p);
-  const R *__restrict__ mtab = static_cast<const R *>(sim.mtab);
+  const cptr<R> mtab = kconst<R>(sim.mtab);
   R e = e_in[c];
   if (nx > 1) {
     if (c >= 1 && c <= nx - 2) {
       e = plain_interior(sim, e_in, hh, pp, mtab, S, c);
     } else if (c == 0) {
-      e = sim.edge_l == 0 ? 0.0
-                          : fma(sim.kap_l, plain_interior(sim, e_in, hh, pp, mtab, S, 1) - e_in[0], e_in[1]);
+      e = sim.edge_l == 0 ? 0.0 : fma(sim.kap_l, plain_interior(sim, e_in, hh, pp, mtab, S, 1) - e_in[0], e_in[1]);
     } else {
       e = sim.edge_r == 0
               ? 0.0
               : fma(sim.kap_r, plain_interior(sim, e_in, hh, pp, mtab, S, nx - 2) - e_in[nx - 1], e_in[nx - 2]);
     }
   }
-  const int64_t n1 = n + 1;
   e = apply_sources(sim, c, n1, e);
   e_out[c] = e;
-  if (sim.n_rec > 0) {
+  if (sim.n_rec > 0 && n1 % uint32_t(sim.rec_every) == 0u && has_records(sim, c)) {
     bool qm = false;
     if constexpr (N > 0) qm = mtab[sim.mat_e[c] * S + kCoefQM] != 0.0;
     record_fields(sim, c, n1, e, c <= nx - 2 ? hh[c] : 0.0, qm);
@@ -376,8 +440,8 @@ __global__ void __launch_bounds__(kPlainBlock) k_plain_e(const DevSim *__restric
 }
 
 template <int N, typename R>
-hipError_t launch_blocked_nr(int block, const DevSim *sims, const DevTile *tiles, int n_tiles,
-                             int64_t n0, int parity, int halo, int k, hipStream_t st) {
+hipError_t launch_blocked_nr(int block, const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0,
+                             int parity, int halo, int k, hipStream_t st) {
   switch (block) {
     case 64: k_blocked<N, R, 64><<<n_tiles, 64, 0, st>>>(sims, tiles, n0, parity, halo, k); break;
     case 128: k_blocked<N, R, 128><<<n_tiles, 128, 0, st>>>(sims, tiles, n0, parity, halo, k); break;
@@ -390,8 +454,8 @@ hipError_t launch_blocked_nr(int block, const DevSim *sims, const DevTile *tiles
 }
 
 template <typename R>
-hipError_t launch_blocked_r(int levels, int block, const DevSim *sims, const DevTile *tiles,
-                            int n_tiles, int64_t n0, int parity, int halo, int k, hipStream_t st) {
+hipError_t launch_blocked_r(int levels, int block, const DevSim *sims, const DevTile *tiles, int n_tiles,
+                            int64_t n0, int parity, int halo, int k, hipStream_t st) {
   switch (levels) {
     case 0: return launch_blocked_nr<0, R>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
     case 2: return launch_blocked_nr<2, R>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
@@ -421,18 +485,16 @@ bool block_supported(int block) {
 
 int plain_block() { return kPlainBlock; }
 
-hipError_t launch_blocked(int levels, int precision, int block, const DevSim *sims,
-                          const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo, int k,
-                          hipStream_t st) {
+hipError_t launch_blocked(int levels, int precision, int block, const DevSim *sims, const DevTile *tiles,
+                          int n_tiles, int64_t n0, int parity, int halo, int k, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
   if (k < 1 || k > halo || 2 * halo >= block) return hipErrorInvalidValue;
-  if (precision == 64)
-    return launch_blocked_r<double>(levels, block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+  if (precision == 64) return launch_blocked_r<double>(levels, block, sims, tiles, n_tiles, n0, parity, halo, k, st);
   return launch_blocked_r<float>(levels, block, sims, tiles, n_tiles, n0, parity, halo, k, st);
 }
 
-hipError_t launch_plain(int levels, const DevSim *sims, const DevTile *tiles, int n_tiles,
-                        int64_t n0, int parity, hipStream_t st) {
+hipError_t launch_plain(int levels, const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity,
+                        hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
   switch (levels) {
     case 0: return launch_plain_n<0>(sims, tiles, n_tiles, n0, parity, st);

@@ -513,8 +513,8 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
     err = "nx must be 1 (single point) or at least 3 (two edge nodes and an interior)";
     return MB_ERR_ARG;
   }
-  if (scen->nx > (int64_t(1) << 31)) {
-    err = "nx too large";
+  if (scen->nx >= (int64_t(1) << 26) || scen->n_steps >= (int64_t(1) << 31) - 1) {
+    err = "grid or step count too large for 32-bit indexing";
     return MB_ERR_ARG;
   }
   if (scen->precision != 64 && scen->precision != 32) {

@@ -2,6 +2,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <numeric>
 
 #include "launch.hpp"
 
@@ -325,6 +326,9 @@ int Engine::add(SimPlan &&plan, Arena *arena, hipStream_t st, std::string &err) 
   d.rec = reinterpret_cast<const DevRecord *>(dev + L.rec);
   d.n_rec = int32_t(p.records.size());
   d.n_rec_all = int32_t(all_ids.size());
+  int64_t g = 0;
+  for (auto &rp : p.records) g = std::gcd(g, rp.interval);
+  d.rec_every = int32_t(g > 0 ? g : 1);
   d.rec_first = L.n_point ? reinterpret_cast<const int32_t *>(dev + L.rec_first) : nullptr;
   d.rec_ids = reinterpret_cast<const int32_t *>(dev + L.rec_ids);
   d.rec_all = reinterpret_cast<const int32_t *>(dev + L.rec_all);
