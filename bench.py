@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 import paper_2005_05412_amd as mb  # noqa: E402
 import workloads as W  # noqa: E402
+from workloads.errors import max_error  # noqa: E402
 
 PEAK = {"fp32_tflops": 157.3, "fp64_tflops": 78.6, "hbm_gbs": 8000.0}
 
@@ -81,15 +82,9 @@ class Hip:
 
 
 def rel_err(prob, got, ref):
-    worst = 0.0
-    for r in prob["records"]:
-        a, b = np.asarray(got[r["name"]]), np.asarray(ref[r["name"]])
-        n = min(len(a), len(b))
-        if n == 0:
-            continue
-        floor = 1e-3
-        worst = max(worst, float(np.max(np.abs(a[:n] - b[:n])) / max(np.max(np.abs(b[:n])), floor)))
-    return worst
+    """Relative max-norm error over the recorded traces (compared on the common prefix)."""
+    n = min(min(len(got[r["name"]]), len(ref[r["name"]])) for r in prob["records"])
+    return max_error(prob, got, ref, n_samples=n)
 
 
 def timed_solves(hip, stream, solver, steps, warmup, n_launch):
@@ -160,8 +155,12 @@ def main(argv=None):
 
     # ---- main leg: FP32 temporally blocked -------------------------------------------
     log(f"[bench] lambda3 fp32 blocked nx={prob['nx']} nt={prob['n_steps']}")
-    s32 = mb.Solver(prob, precision=32, variant="blocked", block=args.block, depth=args.depth)
-    depth = args.depth or 32
+    variant = "blocked" if (args.block or args.depth) else "auto"
+    t_setup = time.perf_counter()
+    s32 = mb.Solver(prob, precision=32, variant=variant, block=args.block, depth=args.depth)
+    t_setup = time.perf_counter() - t_setup
+    block, depth = s32.shape()
+    log(f"[bench] tile shape block={block} depth={depth} (setup incl. tuning {t_setup:.2f} s)")
     n_launch = math.ceil(prob["n_steps"] / depth)
     wall, dev_ms = timed_solves(hip, stream, s32, args.steps, args.warmup, n_launch)
     rec32 = s32.records()
@@ -179,11 +178,11 @@ def main(argv=None):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "lambda3-3lvl", "nx": prob["nx"], "n_steps": prob["n_steps"], "levels": 3,
                    "materials": len(prob["materials"]), "records": len(prob["records"]),
-                   "variant": "blocked", "block": args.block or 256, "depth": depth,
+                   "variant": "blocked", "block": block, "depth": depth, "setup_s": t_setup,
                    "step": "one full solve of the workload"},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK["fp32_tflops"],
                      "unit": "TFLOP/s", "frac": achieved_tflops / PEAK["fp32_tflops"], "traffic": None,
-                     "kernel": "k_blocked<3,float,256>", "avg_kernel_us": avg_kernel_us,
+                     "kernel": f"k_blocked<3,float,{block}>", "avg_kernel_us": avg_kernel_us,
                      "flops_per_cell_update": flops_per_cell_update(n_levels),
                      "cell_updates_per_launch": prob["nx"] * depth,
                      "hbm_effective_gbs": eff_gbs, "hbm_effective_frac": eff_gbs / PEAK["hbm_gbs"]},
@@ -193,8 +192,9 @@ def main(argv=None):
     rec64 = None
     if not args.no_fp64:
         log("[bench] lambda3 fp64 blocked")
-        s64 = mb.Solver(prob, precision=64, variant="blocked", block=args.block, depth=args.depth)
-        w64, d64 = timed_solves(hip, stream, s64, 1, 1, n_launch)
+        s64 = mb.Solver(prob, precision=64, variant=variant, block=args.block, depth=args.depth)
+        b64, k64 = s64.shape()
+        w64, d64 = timed_solves(hip, stream, s64, 1, 1, math.ceil(prob["n_steps"] / k64))
         rec64 = s64.records()
         s64.close()
         log("[bench] lambda3 fp64 plain (two launches per step)")
@@ -206,7 +206,8 @@ def main(argv=None):
         recp = sp.records()
         sp.close()
         same = all(np.array_equal(recp[k], rec64[k]) for k in rec64)
-        out["fp64_blocked"] = {"value": cells / w64, "unit": "cell-updates/s", "device_ms": d64[0]}
+        out["fp64_blocked"] = {"value": cells / w64, "unit": "cell-updates/s", "device_ms": d64[0],
+                               "block": b64, "depth": k64}
         out["fp64_plain"] = {"value": cells / wp, "unit": "cell-updates/s", "wall_s": wp,
                              "bitwise_equal_to_fp64_blocked": bool(same)}
         out["fp32_vs_fp64_full_run_max_rel_err"] = rel_err(prob, rec32, rec64)
@@ -229,7 +230,8 @@ def main(argv=None):
         log("[bench] batched sweep 256 sims fp32")
         sims = W.sweep(n_sims=256, precision=32)
         bcells = sum(p["nx"] * p["n_steps"] for p in sims)
-        bt = mb.Batch(sims, precision=32, variant="blocked")
+        bt = mb.Batch(sims, precision=32, variant="auto")
+        bblock, bdepth = bt.shape()
         bt.run(stream=stream, use_graph=True)
         hip.sync()
         bt.reset(stream)
@@ -242,7 +244,7 @@ def main(argv=None):
                    for k, p in enumerate(sims)) / tb / 1e9
         out["batched_sweep"] = {"value": bcells / tb, "unit": "cell-updates/s", "sims": len(sims),
                                 "cell_updates": bcells, "wall_s": tb, "hbm_effective_gbs": beff,
-                                "hbm_effective_frac": beff / PEAK["hbm_gbs"]}
+                                "hbm_effective_frac": beff / PEAK["hbm_gbs"], "block": bblock, "depth": bdepth}
         bt.close()
 
     # ---- serving ---------------------------------------------------------------------

@@ -27,7 +27,7 @@ REC_KIND = {"e": 0, "h": 1, "pop": 2, "inv": 3, "rho_re": 4, "rho_im": 5}
 VARIANT = {"auto": 0, "plain": 1, "blocked": 2}
 
 EXPORTS = [
-    "mb_last_error", "mb_device_count", "mb_plan_material", "mb_plan_readout", "mb_setup", "mb_run", "mb_reset", "mb_batch_reset", "mb_steps_done", "mb_record_shape",
+    "mb_last_error", "mb_device_count", "mb_plan_material", "mb_plan_readout", "mb_setup", "mb_run", "mb_reset", "mb_batch_reset", "mb_shape", "mb_batch_shape", "mb_steps_done", "mb_record_shape",
     "mb_read_records", "mb_read_state", "mb_elapsed_ms", "mb_destroy", "mb_batch_setup", "mb_batch_run",
     "mb_batch_record_shape", "mb_batch_read_records", "mb_batch_elapsed_ms", "mb_batch_destroy",
     "mb_server_create", "mb_server_submit", "mb_server_start", "mb_server_drain", "mb_server_cancel",
@@ -122,6 +122,8 @@ def load():
         "mb_run": (C.c_int, [P, C.c_int64, P]),
         "mb_reset": (C.c_int, [P, P]),
         "mb_batch_reset": (C.c_int, [P, P]),
+        "mb_shape": (C.c_int, [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+        "mb_batch_shape": (C.c_int, [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "mb_steps_done": (C.c_int64, [P]),
         "mb_record_shape": (C.c_int, [P, C.c_int, i64p, i64p]),
         "mb_read_records": (C.c_int, [P, C.c_int, dp, C.c_int64, i64p]),
@@ -324,6 +326,11 @@ class Solver:
         _check(load().mb_reset(self._h, _stream_ptr(stream)))
         return self
 
+    def shape(self):
+        b, d = C.c_int32(), C.c_int32()
+        _check(load().mb_shape(self._h, C.byref(b), C.byref(d)))
+        return b.value, d.value
+
     @property
     def steps_done(self):
         return int(load().mb_steps_done(self._h))
@@ -398,6 +405,11 @@ class Batch:
     def reset(self, stream=None):
         _check(load().mb_batch_reset(self._h, _stream_ptr(stream)))
         return self
+
+    def shape(self):
+        b, d = C.c_int32(), C.c_int32()
+        _check(load().mb_batch_shape(self._h, C.byref(b), C.byref(d)))
+        return b.value, d.value
 
     def record(self, sim, k):
         lib = load()

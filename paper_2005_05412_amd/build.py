@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libmbhip.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "plan.cpp", "runtime.cpp", "abi.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "plan.cpp", "runtime.cpp", "tune.cpp", "abi.cpp", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("MB_OFFLOAD_ARCH", "gfx950")
 

@@ -10,6 +10,7 @@
 #include "mb.h"
 #include "launch.hpp"
 #include "runtime.hpp"
+#include "tune.hpp"
 
 namespace mb {
 thread_local std::string g_last_error;
@@ -218,6 +219,13 @@ int mb_setup(int hip_device, const mb_device_desc *dev, const mb_scenario_desc *
   int warn = rc;
   int block = 0, halo = 0;
   if ((rc = shape_for(plan, block, halo)) < 0) return rc;
+  if (plan.variant == MB_VARIANT_AUTO && plan.block == 0 && plan.depth == 0) {
+    if (hipSetDevice(hip_device) != hipSuccess) return fail(MB_ERR_HIP, "hipSetDevice failed");
+    Shape sh;
+    if ((rc = tune_shape(hip_device, {&plan}, plan.precision, sh, err)) < 0) return fail(rc, err);
+    block = sh.block;
+    halo = sh.halo;
+  }
   auto h = std::make_unique<mb_handle>();
   h->device = hip_device;
   int variant = plan.variant == MB_VARIANT_PLAIN ? MB_VARIANT_PLAIN : MB_VARIANT_BLOCKED;
@@ -250,7 +258,7 @@ int mb_run(mb_handle *h, int64_t n_steps, void *hip_stream) {
   if (e != hipSuccess) return hip_fail(e, "table upload");
   (void)hipEventRecord(a, st);
   const bool plain = h->eng->variant() == MB_VARIANT_PLAIN;
-  const int k = plain ? 1 : h->eng->depth();
+  const int k = plain ? 1 : h->eng->chunk_steps();
   e = run_steps(*h->eng, st, n_steps, k, !plain && n_steps >= 4 * int64_t(k), h->gc);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   (void)hipEventRecord(b, st);
@@ -273,6 +281,22 @@ int mb_reset(mb_handle *h, void *hip_stream) {
 }
 
 int64_t mb_steps_done(const mb_handle *h) { return h ? h->eng->sim(h->id).done : -1; }
+
+int mb_shape(const mb_handle *h, int32_t *block, int32_t *depth) {
+  if (!h) return fail(MB_ERR_ARG, "null handle");
+  const bool plain = h->eng->variant() == MB_VARIANT_PLAIN;
+  if (block) *block = plain ? plain_block() : h->eng->block();
+  if (depth) *depth = plain ? 1 : h->eng->chunk_steps();
+  return MB_OK;
+}
+
+int mb_batch_shape(const mb_batch *b, int32_t *block, int32_t *depth) {
+  if (!b) return fail(MB_ERR_ARG, "null batch");
+  const bool plain = b->eng->variant() == MB_VARIANT_PLAIN;
+  if (block) *block = plain ? plain_block() : b->eng->block();
+  if (depth) *depth = plain ? 1 : b->eng->chunk_steps();
+  return MB_OK;
+}
 
 int mb_record_shape(const mb_handle *h, int record_id, int64_t *n_samples, int64_t *width) {
   if (!h) return fail(MB_ERR_ARG, "null handle");
@@ -358,6 +382,15 @@ int mb_batch_setup(int hip_device, int32_t n, const mb_device_desc *devs, const 
   probe.block = plans[0].block;
   probe.depth = plans[0].depth;
   if ((rc = shape_for(probe, block, halo)) < 0) return rc;
+  if (probe.variant == MB_VARIANT_AUTO && probe.block == 0 && probe.depth == 0) {
+    if (hipSetDevice(hip_device) != hipSuccess) return fail(MB_ERR_HIP, "hipSetDevice failed");
+    std::vector<const SimPlan *> ptrs;
+    for (auto &p : plans) ptrs.push_back(&p);
+    Shape sh;
+    if ((rc = tune_shape(hip_device, ptrs, probe.precision, sh, err)) < 0) return fail(rc, err);
+    block = sh.block;
+    halo = sh.halo;
+  }
   auto b = std::make_unique<mb_batch>();
   b->device = hip_device;
   int variant = plans[0].variant == MB_VARIANT_PLAIN ? MB_VARIANT_PLAIN : MB_VARIANT_BLOCKED;
@@ -389,7 +422,7 @@ int mb_batch_run(mb_batch *b, void *hip_stream, int32_t use_graph) {
   hipError_t e = eng.sync_tables(st);
   if (e != hipSuccess) return hip_fail(e, "table upload");
   const bool plain = eng.variant() == MB_VARIANT_PLAIN;
-  const int k = plain ? 1 : eng.depth();
+  const int k = plain ? 1 : eng.chunk_steps();
   hipEvent_t ea, eb;
   if (hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess)
     return fail(MB_ERR_HIP, "hipEventCreate failed");

@@ -14,6 +14,9 @@
 namespace mb {
 namespace {
 
+constexpr int kTileSources = 4;  // sources per tile staged in LDS
+constexpr int kMaxChunk = 256;   // steps per blocked launch
+
 template <typename T>
 using cptr = const __attribute__((address_space(4))) T *;
 
@@ -162,7 +165,7 @@ __device__ __forceinline__ void record_density(const DevSim &sim, int c, uint32_
 
 // field records (E^{n+1}, H^{n+1/2}) and zero density values outside quantum cells
 template <typename R>
-__device__ __noinline__ void record_fields(const DevSim &sim, int c, uint32_t n1, R e, R h, bool qm) {
+__device__ __forceinline__ void record_fields(const DevSim &sim, int c, uint32_t n1, R e, R h, bool qm) {
   auto val = [&](const DevRecord &rc, double &v) -> bool {
     if (rc.quantity == 0) {
       v = double(e);
@@ -225,7 +228,10 @@ __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
   using CL = Cell<N, R>;
   constexpr int M = CL::M, MA = CL::MA, S = mat_stride(N);
   __shared__ R se[B], sh[B], se2[B];
+  __shared__ R s_src[kTileSources][kMaxChunk];
   const DevTile tile = tiles[blockIdx.x];
+  // fields used inside the step loop are copied to locals below, so stores to
+  // records cannot force them to be reloaded
   const DevSim &sim = sims[tile.sim];
   const int64_t ls64 = n0 - sim.start;
   if (ls64 < 0 || ls64 >= sim.n_steps) return;
@@ -265,11 +271,41 @@ __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
       }
     }
   }
+  // sources inside this tile: their values for the whole chunk are staged in
+  // LDS (ordered before the first read by the first barrier of the loop)
+  int src_cell[kTileSources];
+  bool src_hard[kTileSources];
+#pragma unroll
+  for (int t = 0; t < kTileSources; ++t) {
+    src_cell[t] = -1;
+    src_hard[t] = false;
+  }
+  int n_ts = 0;
+  bool src_direct = false;
+  for (int j = 0; j < sim.n_src; ++j) {
+    const DevSource sj = sim.src[j];
+    const int cell = int(sj.cell);
+    if (cell < lo || cell >= lo + B) continue;
+    if (n_ts == kTileSources) {
+      src_direct = true;
+      break;
+    }
+    for (int q = l; q < ks; q += B) s_src[n_ts][q] = R(sj.table[ls0 + q + 1]);
+#pragma unroll
+    for (int t = 0; t < kTileSources; ++t)
+      if (t == n_ts) {
+        src_cell[t] = cell;
+        src_hard[t] = sj.hard != 0;
+      }
+    ++n_ts;
+  }
   const bool hcell = in && c <= nx - 2;
   const bool ecell = in && c >= 1 && c <= nx - 2;
   const bool left = in && nx > 1 && c == 0, right = in && nx > 1 && c == nx - 1;
   const bool mur_tile = nx > 1 && ((sim.edge_l == 1 && lo <= 0 && 0 < lo + B) ||
                                    (sim.edge_r == 1 && lo <= nx - 1 && nx - 1 < lo + B));
+  const bool mur_l = left && sim.edge_l == 1, mur_r = right && sim.edge_r == 1;
+  const bool pec = (left && sim.edge_l == 0) || (right && sim.edge_r == 0);
   const bool rec_here = sim.n_rec > 0 && own && has_records(sim, c);
   const uint32_t rec_every = uint32_t(sim.rec_every);
   const R kap_l = R(sim.kap_l), kap_r = R(sim.kap_r);
@@ -307,11 +343,21 @@ __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
     if (mur_tile) {
       se2[l] = e;
       __syncthreads();
-      if (left && sim.edge_l == 1) e = fma(kap_l, se2[l + 1] - eo, er);
-      if (right && sim.edge_r == 1) e = fma(kap_r, se2[l - 1] - eo, el);
+      if (mur_l) e = fma(kap_l, se2[l + 1] - eo, er);
+      if (mur_r) e = fma(kap_r, se2[l - 1] - eo, el);
     }
-    if ((left && sim.edge_l == 0) || (right && sim.edge_r == 0)) e = 0;
-    if (in) e = apply_sources(sim, c, n1, e);
+    if (pec) e = 0;
+    if (src_direct) {
+      if (in) e = apply_sources(sim, c, n1, e);
+    } else {
+#pragma unroll
+      for (int t = 0; t < kTileSources; ++t) {
+        if (t < n_ts && c == src_cell[t]) {
+          const R v = s_src[t][s];
+          e = src_hard[t] ? v : e + v;
+        }
+      }
+    }
     if (rec_now) record_fields(sim, c, n1, e, hcell ? h : R(0), qm);
   }
   if (own) {
@@ -488,7 +534,7 @@ int plain_block() { return kPlainBlock; }
 hipError_t launch_blocked(int levels, int precision, int block, const DevSim *sims, const DevTile *tiles,
                           int n_tiles, int64_t n0, int parity, int halo, int k, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
-  if (k < 1 || k > halo || 2 * halo >= block) return hipErrorInvalidValue;
+  if (k < 1 || k > halo || k > kMaxChunk || 2 * halo >= block) return hipErrorInvalidValue;
   if (precision == 64) return launch_blocked_r<double>(levels, block, sims, tiles, n_tiles, n0, parity, halo, k, st);
   return launch_blocked_r<float>(levels, block, sims, tiles, n_tiles, n0, parity, halo, k, st);
 }

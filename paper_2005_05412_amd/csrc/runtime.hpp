@@ -84,6 +84,8 @@ class Engine {
   bool all_finished() const;
   int64_t engine_step() const { return n0_; }
   int depth() const { return halo_; }
+  // steps per blocked launch: the halo width, at most 256
+  int chunk_steps() const { return halo_ < 256 ? halo_ : 256; }
   int block() const { return block_; }
   int variant() const { return variant_; }
   int precision() const { return precision_; }

@@ -133,8 +133,8 @@ void mb_server::loop() {
     lk.unlock();
     auto tb = clk::now();
     hipError_t he = hipSuccess;
-    int k = e.variant() == MB_VARIANT_PLAIN ? chunk_steps : std::min(chunk_steps, e.depth());
-    int sub = e.variant() == MB_VARIANT_PLAIN ? 1 : std::max(1, chunk_steps / e.depth());
+    int k = e.variant() == MB_VARIANT_PLAIN ? chunk_steps : std::min(chunk_steps, e.chunk_steps());
+    int sub = e.variant() == MB_VARIANT_PLAIN ? 1 : std::max(1, chunk_steps / e.chunk_steps());
     for (int q = 0; q < sub && he == hipSuccess; ++q) he = e.chunk(stream, k);
     if (he == hipSuccess) he = hipStreamSynchronize(stream);
     std::vector<int32_t> status;

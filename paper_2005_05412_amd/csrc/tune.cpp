@@ -1,0 +1,160 @@
+// Tile-shape autotuner for the blocked kernel.  For a set of planned
+// simulations it times every candidate (threads per tile, halo depth) on a
+// scratch engine holding copies of the plans and keeps the fastest; results
+// are cached per (device architecture, level count, precision, total cells
+// rounded up to a power of two, simulation count rounded up to a power of
+// two), in memory and in a small text file.
+#include "tune.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+
+#include "launch.hpp"
+
+namespace mb {
+namespace {
+
+std::mutex g_mu;
+std::map<std::string, Shape> g_cache;
+bool g_loaded = false;
+
+std::string cache_path() {
+  if (const char *p = std::getenv("MB_TUNE_CACHE")) return p;
+  if (const char *h = std::getenv("HOME")) return std::string(h) + "/.cache/mbhip_tune.txt";
+  return "";
+}
+
+void load_cache() {
+  if (g_loaded) return;
+  g_loaded = true;
+  std::string path = cache_path();
+  if (path.empty()) return;
+  std::ifstream f(path);
+  std::string key;
+  Shape s;
+  while (f >> key >> s.block >> s.halo)
+    if (block_supported(s.block) && s.halo >= 1 && 2 * s.halo < s.block) g_cache[key] = s;
+}
+
+void store_cache(const std::string &key, const Shape &s) {
+  g_cache[key] = s;
+  std::string path = cache_path();
+  if (path.empty()) return;
+  std::ofstream f(path, std::ios::app);
+  if (f) f << key << " " << s.block << " " << s.halo << "\n";
+}
+
+uint64_t pow2_ceil(uint64_t v) {
+  uint64_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+}  // namespace
+
+std::vector<Shape> candidate_shapes(int levels) {
+  std::vector<Shape> all = {{64, 16},  {128, 16}, {128, 32},  {256, 32},  {256, 64},
+                            {512, 64}, {512, 128}, {512, 192}, {1024, 128}, {1024, 256}};
+  std::vector<Shape> out;
+  for (const Shape &s : all) {
+    if (levels >= 5 && s.block > 512) continue;  // register pressure of the large matvec
+    out.push_back(s);
+  }
+  return out;
+}
+
+std::string tune_key(int device, const std::vector<const SimPlan *> &plans, int precision) {
+  hipDeviceProp_t prop;
+  std::string arch = "gpu";
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) arch = prop.gcnArchName;
+  for (char &ch : arch)
+    if (ch == ':' || ch == ' ') ch = '_';
+  int levels = 0;
+  uint64_t cells = 0;
+  for (auto *p : plans) {
+    levels = std::max(levels, p->n);
+    cells += uint64_t(p->nx);
+  }
+  std::ostringstream os;
+  os << arch << "/N" << levels << "/p" << precision << "/cells" << pow2_ceil(cells) << "/sims"
+     << pow2_ceil(plans.size());
+  return os.str();
+}
+
+int tune_shape(int device, const std::vector<const SimPlan *> &plans, int precision, Shape &best,
+               std::string &err) {
+  const std::string key = tune_key(device, plans, precision);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_cache();
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+      best = it->second;
+      return MB_OK;
+    }
+  }
+  int levels = 0;
+  int64_t min_steps = INT64_MAX;
+  for (auto *p : plans) {
+    levels = std::max(levels, p->n);
+    min_steps = std::min(min_steps, p->n_steps);
+  }
+  hipStream_t st;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+    err = "stream creation failed";
+    return MB_ERR_HIP;
+  }
+  hipEvent_t a, b;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&b);
+  double best_us = 1e300;
+  best = Shape{256, 32};
+  for (const Shape &cand : candidate_shapes(levels)) {
+    Engine eng(device, precision, MB_VARIANT_BLOCKED, cand.block, cand.halo);
+    if (eng.init(err) < 0) continue;
+    bool ok = true;
+    for (auto *p : plans) {
+      SimPlan copy = *p;
+      std::string e2;
+      if (eng.add(std::move(copy), nullptr, st, e2) < 0) {
+        ok = false;
+        break;
+      }
+    }
+    if (!ok) continue;
+    const int k = eng.chunk_steps();
+    // time whole chunks: two for warm-up, then enough for ~2k steps
+    int64_t avail = min_steps / k;
+    if (avail < 3) continue;
+    int64_t timed = std::min<int64_t>(avail - 2, std::max<int64_t>(4, 2048 / k));
+    hipError_t he = hipSuccess;
+    for (int q = 0; q < 2 && he == hipSuccess; ++q) he = eng.chunk(st, k);
+    (void)hipEventRecord(a, st);
+    for (int64_t q = 0; q < timed && he == hipSuccess; ++q) he = eng.chunk(st, k);
+    (void)hipEventRecord(b, st);
+    if (he != hipSuccess || hipEventSynchronize(b) != hipSuccess) continue;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    double us = 1e3 * double(ms) / double(timed * k);
+    if (us < best_us) {
+      best_us = us;
+      best = cand;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  (void)hipStreamDestroy(st);
+  if (best_us >= 1e299) return MB_OK;  // too short to time: keep the default
+  std::lock_guard<std::mutex> lk(g_mu);
+  store_cache(key, best);
+  return MB_OK;
+}
+
+}  // namespace mb

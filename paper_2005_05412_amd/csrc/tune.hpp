@@ -1,0 +1,22 @@
+// Tile-shape autotuner of the blocked kernel.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "runtime.hpp"
+
+namespace mb {
+
+struct Shape {
+  int block = 256;  // threads (cells) per tile
+  int halo = 32;    // halo width = steps per launch (capped at 256)
+};
+
+std::vector<Shape> candidate_shapes(int levels);
+std::string tune_key(int device, const std::vector<const SimPlan *> &plans, int precision);
+// Picks the fastest candidate shape for these simulations (cached).
+int tune_shape(int device, const std::vector<const SimPlan *> &plans, int precision, Shape &best,
+               std::string &err);
+
+}  // namespace mb
