@@ -80,6 +80,20 @@ class Hip:
         self.lib.hipEventElapsedTime(ctypes.byref(ms), a, b)
         return ms.value
 
+    def copy_calibration(self, nbytes):
+        """One device-to-device copy of nbytes (a plain copy kernel of known traffic)."""
+        src, dst = ctypes.c_void_p(), ctypes.c_void_p()
+        if self.lib.hipMalloc(ctypes.byref(src), ctypes.c_size_t(nbytes)) != 0 or \
+                self.lib.hipMalloc(ctypes.byref(dst), ctypes.c_size_t(nbytes)) != 0:
+            raise RuntimeError("hipMalloc failed")
+        self.lib.hipMemset(src, 1, ctypes.c_size_t(nbytes))
+        self.sync()
+        if self.lib.hipMemcpy(dst, src, ctypes.c_size_t(nbytes), 3) != 0:   # device to device
+            raise RuntimeError("hipMemcpy failed")
+        self.sync()
+        self.lib.hipFree(src)
+        self.lib.hipFree(dst)
+
 
 def rel_err(prob, got, ref):
     """Relative max-norm error over the recorded traces (compared on the common prefix)."""
@@ -140,6 +154,8 @@ def main(argv=None):
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="also run one device-to-device copy of this size (counter calibration)")
     ap.add_argument("--out", default="")
     args = ap.parse_args(argv)
     if args.gpus != 1:
@@ -148,6 +164,8 @@ def main(argv=None):
         return 2
     hip = Hip()
     stream = hip.stream()
+    if args.copy_bytes > 0:
+        hip.copy_calibration(args.copy_bytes)
     prob = W.lambda3(nx=args.nx, n_steps=args.nt, precision=32)
     n_levels = 3
     cells = prob["nx"] * prob["n_steps"]
