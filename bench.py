@@ -177,8 +177,8 @@ def main(argv=None):
     t_setup = time.perf_counter()
     s32 = mb.Solver(prob, precision=32, variant=variant, block=args.block, depth=args.depth)
     t_setup = time.perf_counter() - t_setup
-    block, depth = s32.shape()
-    log(f"[bench] tile shape block={block} depth={depth} (setup incl. tuning {t_setup:.2f} s)")
+    block, depth, regs = s32.shape()
+    log(f"[bench] tile shape block={block} depth={depth} regs={regs} (setup incl. tuning {t_setup:.2f} s)")
     n_launch = math.ceil(prob["n_steps"] / depth)
     wall, dev_ms = timed_solves(hip, stream, s32, args.steps, args.warmup, n_launch)
     rec32 = s32.records()
@@ -196,11 +196,11 @@ def main(argv=None):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "lambda3-3lvl", "nx": prob["nx"], "n_steps": prob["n_steps"], "levels": 3,
                    "materials": len(prob["materials"]), "records": len(prob["records"]),
-                   "variant": "blocked", "block": block, "depth": depth, "setup_s": t_setup,
+                   "variant": "blocked", "block": block, "depth": depth, "regs": regs, "setup_s": t_setup,
                    "step": "one full solve of the workload"},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK["fp32_tflops"],
                      "unit": "TFLOP/s", "frac": achieved_tflops / PEAK["fp32_tflops"], "traffic": None,
-                     "kernel": f"k_blocked<3,float,{block}>", "avg_kernel_us": avg_kernel_us,
+                     "kernel": f"k_blocked<3,float,{block},{str(regs).lower()}>", "avg_kernel_us": avg_kernel_us,
                      "flops_per_cell_update": flops_per_cell_update(n_levels),
                      "cell_updates_per_launch": prob["nx"] * depth,
                      "hbm_effective_gbs": eff_gbs, "hbm_effective_frac": eff_gbs / PEAK["hbm_gbs"]},
@@ -211,7 +211,7 @@ def main(argv=None):
     if not args.no_fp64:
         log("[bench] lambda3 fp64 blocked")
         s64 = mb.Solver(prob, precision=64, variant=variant, block=args.block, depth=args.depth)
-        b64, k64 = s64.shape()
+        b64, k64, r64 = s64.shape()
         w64, d64 = timed_solves(hip, stream, s64, 1, 1, math.ceil(prob["n_steps"] / k64))
         rec64 = s64.records()
         s64.close()
@@ -225,7 +225,7 @@ def main(argv=None):
         sp.close()
         same = all(np.array_equal(recp[k], rec64[k]) for k in rec64)
         out["fp64_blocked"] = {"value": cells / w64, "unit": "cell-updates/s", "device_ms": d64[0],
-                               "block": b64, "depth": k64}
+                               "block": b64, "depth": k64, "regs": r64}
         out["fp64_plain"] = {"value": cells / wp, "unit": "cell-updates/s", "wall_s": wp,
                              "bitwise_equal_to_fp64_blocked": bool(same)}
         out["fp32_vs_fp64_full_run_max_rel_err"] = rel_err(prob, rec32, rec64)
@@ -249,7 +249,7 @@ def main(argv=None):
         sims = W.sweep(n_sims=256, precision=32)
         bcells = sum(p["nx"] * p["n_steps"] for p in sims)
         bt = mb.Batch(sims, precision=32, variant="auto")
-        bblock, bdepth = bt.shape()
+        bblock, bdepth, bregs = bt.shape()
         bt.run(stream=stream, use_graph=True)
         hip.sync()
         bt.reset(stream)
@@ -262,7 +262,7 @@ def main(argv=None):
                    for k, p in enumerate(sims)) / tb / 1e9
         out["batched_sweep"] = {"value": bcells / tb, "unit": "cell-updates/s", "sims": len(sims),
                                 "cell_updates": bcells, "wall_s": tb, "hbm_effective_gbs": beff,
-                                "hbm_effective_frac": beff / PEAK["hbm_gbs"], "block": bblock, "depth": bdepth}
+                                "hbm_effective_frac": beff / PEAK["hbm_gbs"], "block": bblock, "depth": bdepth, "regs": bregs}
         bt.close()
 
     # ---- serving ---------------------------------------------------------------------

@@ -85,6 +85,8 @@ extern "C" {
 #define MB_VARIANT_AUTO 0     /* blocked kernel, tile shape from the tuner / defaults */
 #define MB_VARIANT_PLAIN 1    /* two launches per step (Alg. 1 as written), FP64 only */
 #define MB_VARIANT_BLOCKED 2  /* temporally blocked overlapped tiles, FP64 or FP32 */
+#define MB_VARIANT_BLOCKED_REGS 3  /* blocked; coefficients of single-material waves held in
+                                    * registers (2 and 3 levels; same results as BLOCKED) */
 
 /* ---- description ------------------------------------------------------- */
 typedef struct mb_qm {
@@ -218,12 +220,13 @@ int mb_reset(mb_handle *h, void *hip_stream);
 /* Steps done so far. */
 int64_t mb_steps_done(const mb_handle *h);
 
-/* Tile shape in use: threads per tile and steps per launch (1 for the
- * two-launch variant).  With MB_VARIANT_AUTO and block = depth = 0 the shape
- * is chosen at setup by timing candidate shapes on this simulation (cached
- * per device architecture, level count, precision and size class; the cache
- * file is $MB_TUNE_CACHE or ~/.cache/mbhip_tune.txt). */
-int mb_shape(const mb_handle *h, int32_t *block, int32_t *depth);
+/* Tile shape in use: threads per tile, steps per launch (1 for the two-launch
+ * variant) and whether coefficients are held in registers.  With
+ * MB_VARIANT_AUTO and block = depth = 0 the shape is chosen at setup by timing
+ * candidate shapes on this simulation (cached per device architecture, level
+ * count, precision and size class; the cache file is $MB_TUNE_CACHE or
+ * ~/.cache/mbhip_tune.txt).  Any pointer may be NULL. */
+int mb_shape(const mb_handle *h, int32_t *block, int32_t *depth, int32_t *regs);
 
 /* Samples recorded so far for record `record_id` (per-sample width 1 or nx). */
 int mb_record_shape(const mb_handle *h, int record_id, int64_t *n_samples, int64_t *width);
@@ -258,7 +261,7 @@ int mb_batch_run(mb_batch *b, void *hip_stream, int32_t use_graph);
 /* Restores every member's initial state and clears the records (as mb_reset). */
 int mb_batch_reset(mb_batch *b, void *hip_stream);
 /* Tile shape in use (as mb_shape; tuned over the whole batch). */
-int mb_batch_shape(const mb_batch *b, int32_t *block, int32_t *depth);
+int mb_batch_shape(const mb_batch *b, int32_t *block, int32_t *depth, int32_t *regs);
 int mb_batch_record_shape(const mb_batch *b, int32_t sim, int record_id, int64_t *n_samples,
                           int64_t *width);
 int mb_batch_read_records(mb_batch *b, int32_t sim, int record_id, double *out,

@@ -24,7 +24,7 @@ ERRORS = {-1: "MB_ERR_ARG", -2: "MB_ERR_CFL", -3: "MB_ERR_UNSUPPORTED", -4: "MB_
           -5: "MB_ERR_BUDGET", -6: "MB_ERR_HIP", -7: "MB_ERR_NONFINITE", -8: "MB_ERR_STATE"}
 SRC_KIND = {"sech": 0, "gauss": 1}
 REC_KIND = {"e": 0, "h": 1, "pop": 2, "inv": 3, "rho_re": 4, "rho_im": 5}
-VARIANT = {"auto": 0, "plain": 1, "blocked": 2}
+VARIANT = {"auto": 0, "plain": 1, "blocked": 2, "blocked_regs": 3}
 
 EXPORTS = [
     "mb_last_error", "mb_device_count", "mb_plan_material", "mb_plan_readout", "mb_setup", "mb_run", "mb_reset", "mb_batch_reset", "mb_shape", "mb_batch_shape", "mb_steps_done", "mb_record_shape",
@@ -122,8 +122,8 @@ def load():
         "mb_run": (C.c_int, [P, C.c_int64, P]),
         "mb_reset": (C.c_int, [P, P]),
         "mb_batch_reset": (C.c_int, [P, P]),
-        "mb_shape": (C.c_int, [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
-        "mb_batch_shape": (C.c_int, [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+        "mb_shape": (C.c_int, [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+        "mb_batch_shape": (C.c_int, [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "mb_steps_done": (C.c_int64, [P]),
         "mb_record_shape": (C.c_int, [P, C.c_int, i64p, i64p]),
         "mb_read_records": (C.c_int, [P, C.c_int, dp, C.c_int64, i64p]),
@@ -327,9 +327,10 @@ class Solver:
         return self
 
     def shape(self):
-        b, d = C.c_int32(), C.c_int32()
-        _check(load().mb_shape(self._h, C.byref(b), C.byref(d)))
-        return b.value, d.value
+        """(threads per tile, steps per launch, coefficients in registers)."""
+        b, d, r = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(load().mb_shape(self._h, C.byref(b), C.byref(d), C.byref(r)))
+        return b.value, d.value, bool(r.value)
 
     @property
     def steps_done(self):
@@ -407,9 +408,10 @@ class Batch:
         return self
 
     def shape(self):
-        b, d = C.c_int32(), C.c_int32()
-        _check(load().mb_batch_shape(self._h, C.byref(b), C.byref(d)))
-        return b.value, d.value
+        """(threads per tile, steps per launch, coefficients in registers)."""
+        b, d, r = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(load().mb_batch_shape(self._h, C.byref(b), C.byref(d), C.byref(r)))
+        return b.value, d.value, bool(r.value)
 
     def record(self, sim, k):
         lib = load()

@@ -218,6 +218,7 @@ int mb_setup(int hip_device, const mb_device_desc *dev, const mb_scenario_desc *
   if (rc < 0) return fail(rc, err);
   int warn = rc;
   int block = 0, halo = 0;
+  bool vc = plan.variant == MB_VARIANT_BLOCKED_REGS;
   if ((rc = shape_for(plan, block, halo)) < 0) return rc;
   if (plan.variant == MB_VARIANT_AUTO && plan.block == 0 && plan.depth == 0) {
     if (hipSetDevice(hip_device) != hipSuccess) return fail(MB_ERR_HIP, "hipSetDevice failed");
@@ -225,11 +226,12 @@ int mb_setup(int hip_device, const mb_device_desc *dev, const mb_scenario_desc *
     if ((rc = tune_shape(hip_device, {&plan}, plan.precision, sh, err)) < 0) return fail(rc, err);
     block = sh.block;
     halo = sh.halo;
+    vc = sh.vc;
   }
   auto h = std::make_unique<mb_handle>();
   h->device = hip_device;
   int variant = plan.variant == MB_VARIANT_PLAIN ? MB_VARIANT_PLAIN : MB_VARIANT_BLOCKED;
-  h->eng = std::make_unique<Engine>(hip_device, plan.precision, variant, block, halo);
+  h->eng = std::make_unique<Engine>(hip_device, plan.precision, variant, block, halo, vc);
   if ((rc = h->eng->init(err)) < 0) return fail(rc, err);
   hipStream_t st = nullptr;
   int id = h->eng->add(std::move(plan), nullptr, st, err);
@@ -282,19 +284,21 @@ int mb_reset(mb_handle *h, void *hip_stream) {
 
 int64_t mb_steps_done(const mb_handle *h) { return h ? h->eng->sim(h->id).done : -1; }
 
-int mb_shape(const mb_handle *h, int32_t *block, int32_t *depth) {
+int mb_shape(const mb_handle *h, int32_t *block, int32_t *depth, int32_t *regs) {
   if (!h) return fail(MB_ERR_ARG, "null handle");
   const bool plain = h->eng->variant() == MB_VARIANT_PLAIN;
   if (block) *block = plain ? plain_block() : h->eng->block();
   if (depth) *depth = plain ? 1 : h->eng->chunk_steps();
+  if (regs) *regs = h->eng->vc() ? 1 : 0;
   return MB_OK;
 }
 
-int mb_batch_shape(const mb_batch *b, int32_t *block, int32_t *depth) {
+int mb_batch_shape(const mb_batch *b, int32_t *block, int32_t *depth, int32_t *regs) {
   if (!b) return fail(MB_ERR_ARG, "null batch");
   const bool plain = b->eng->variant() == MB_VARIANT_PLAIN;
   if (block) *block = plain ? plain_block() : b->eng->block();
   if (depth) *depth = plain ? 1 : b->eng->chunk_steps();
+  if (regs) *regs = b->eng->vc() ? 1 : 0;
   return MB_OK;
 }
 
@@ -373,6 +377,7 @@ int mb_batch_setup(int hip_device, int32_t n, const mb_device_desc *devs, const 
       return fail(MB_ERR_ARG, "batch members must share precision and variant");
   }
   int block = 0, halo = 0, rc;
+  bool vc = plans[0].variant == MB_VARIANT_BLOCKED_REGS;
   int nmax = 0;
   for (auto &p : plans) nmax = std::max(nmax, p.n);
   SimPlan probe;
@@ -390,11 +395,12 @@ int mb_batch_setup(int hip_device, int32_t n, const mb_device_desc *devs, const 
     if ((rc = tune_shape(hip_device, ptrs, probe.precision, sh, err)) < 0) return fail(rc, err);
     block = sh.block;
     halo = sh.halo;
+    vc = sh.vc;
   }
   auto b = std::make_unique<mb_batch>();
   b->device = hip_device;
   int variant = plans[0].variant == MB_VARIANT_PLAIN ? MB_VARIANT_PLAIN : MB_VARIANT_BLOCKED;
-  b->eng = std::make_unique<Engine>(hip_device, plans[0].precision, variant, block, halo);
+  b->eng = std::make_unique<Engine>(hip_device, plans[0].precision, variant, block, halo, vc);
   if ((rc = b->eng->init(err)) < 0) return fail(rc, err);
   for (int i = 0; i < n; ++i) {
     int id = b->eng->add(std::move(plans[i]), nullptr, nullptr, err);

@@ -16,6 +16,28 @@ namespace {
 
 constexpr int kTileSources = 4;  // sources per tile staged in LDS
 constexpr int kMaxChunk = 256;   // steps per blocked launch
+constexpr int kLaneRecs = 4;     // records per cell kept in registers during a launch
+
+// Neighbour values within one wave by DPP wavefront shifts (lane l receives
+// lane l+1, respectively l-1; the lane at the end of the wave receives 0).
+__device__ __forceinline__ int dpp_from_right(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_from_left(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ float lane_from_right(float v) { return __int_as_float(dpp_from_right(__float_as_int(v))); }
+__device__ __forceinline__ float lane_from_left(float v) { return __int_as_float(dpp_from_left(__float_as_int(v))); }
+__device__ __forceinline__ double lane_from_right(double v) {
+  return __hiloint2double(dpp_from_right(__double2hiint(v)), dpp_from_right(__double2loint(v)));
+}
+__device__ __forceinline__ double lane_from_left(double v) {
+  return __hiloint2double(dpp_from_left(__double2hiint(v)), dpp_from_left(__double2loint(v)));
+}
+
+// Register copy of the quantum coefficients of one material, indexed like
+// the table (offset kCoefKap).
+template <typename R, int SQ>
+struct RegCoef {
+  const R (&a)[SQ];
+  __device__ __forceinline__ R operator[](int i) const { return a[i - kCoefKap]; }
+};
 
 template <typename T>
 using cptr = const __attribute__((address_space(4))) T *;
@@ -82,7 +104,8 @@ struct Cell {
   // eigen-basis gains the phase theta_jk = dt E (lam_j - lam_k)/hbar, the
   // sum of the consecutive angles E kappa_q; each phase is carried as
   // (cos - 1, sin) and applied as a small increment.
-  static __device__ __forceinline__ void rotate(R (&y)[MA], R e, cptr<R> mt) {
+  template <typename C>
+  static __device__ __forceinline__ void rotate(R (&y)[MA], R e, const C &mt) {
     if constexpr (N >= 2) {
       R cm[N - 1], sn[N - 1];
 #pragma unroll
@@ -110,16 +133,23 @@ struct Cell {
     }
   }
 
-  // polarization current n3D tr{mu L0(rho^{n+1/2})} = at . y + p0
-  static __device__ __forceinline__ R polar(const R (&y)[MA], cptr<R> mt) {
-    R acc = mt[coef_p0(N)];
+  // polarization current n3D tr{mu L0(rho^{n+1/2})} = at . y + p0 (two
+  // interleaved partial sums for instruction-level parallelism)
+  template <typename C>
+  static __device__ __forceinline__ R polar(const R (&y)[MA], const C &mt) {
+    R acc0 = mt[coef_p0(N)], acc1 = R(0);
 #pragma unroll
-    for (int j = 0; j < M; ++j) acc = fma(mt[coef_at(N) + j], y[j], acc);
-    return acc;
+    for (int j = 0; j + 1 < M; j += 2) {
+      acc0 = fma(mt[coef_at(N) + j], y[j], acc0);
+      acc1 = fma(mt[coef_at(N) + j + 1], y[j + 1], acc1);
+    }
+    if constexpr (M % 2 == 1) acc0 = fma(mt[coef_at(N) + M - 1], y[M - 1], acc0);
+    return acc0 + acc1;
   }
 
   // sigma_{n+1} = e^{L0 dt} y = y + (bf + am y)
-  static __device__ __forceinline__ void propagate(R (&y)[MA], cptr<R> mt) {
+  template <typename C>
+  static __device__ __forceinline__ void propagate(R (&y)[MA], const C &mt) {
     R out[MA];
 #pragma unroll
     for (int i = 0; i < M; ++i) {
@@ -221,13 +251,16 @@ __device__ __forceinline__ R apply_sources(const DevSim &sim, int c, uint32_t n1
 // computation of overlapped tiles), and writes the owned cells to the other
 // state buffer.
 // ---------------------------------------------------------------------------
-template <int N, typename R, int B>
+template <int N, typename R, int B, bool VC>
 __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
                                                const DevTile *__restrict__ tiles, int64_t n0, int parity,
                                                int halo, int k) {
   using CL = Cell<N, R>;
   constexpr int M = CL::M, MA = CL::MA, S = mat_stride(N);
-  __shared__ R se[B], sh[B], se2[B];
+  constexpr bool WAVE = B == 64;           // one wave per tile: neighbours by DPP, no barriers
+  constexpr int LB = WAVE ? 1 : B;
+  constexpr int SQ = S - kCoefKap;         // quantum part of a material's coefficients
+  __shared__ R se[LB], sh[LB], se2[LB];
   __shared__ R s_src[kTileSources][kMaxChunk];
   const DevTile tile = tiles[blockIdx.x];
   // fields used inside the step loop are copied to locals below, so stores to
@@ -310,41 +343,130 @@ __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
   const uint32_t rec_every = uint32_t(sim.rec_every);
   const R kap_l = R(sim.kap_l), kap_r = R(sim.kap_r);
 
+  // per-lane record descriptors, fetched once per launch (at most kLaneRecs
+  // per cell; cells with more use the generic path)
+  int nrec = 0;
+  bool rec_slow = false;
+  int rq[kLaneRecs];
+  uint32_t rint[kLaneRecs], rstr[kLaneRecs];
+  double *rout[kLaneRecs];
+  const double *rro[kLaneRecs];
+#pragma unroll
+  for (int t = 0; t < kLaneRecs; ++t) {
+    rq[t] = 0;
+    rint[t] = 1;
+    rstr[t] = 1;
+    rout[t] = nullptr;
+    rro[t] = nullptr;
+  }
+  if (rec_here) {
+    auto add = [&](int id, bool whole) {
+      if (nrec == kLaneRecs) {
+        rec_slow = true;
+        return;
+      }
+      const DevRecord &rc = sim.rec[id];
+#pragma unroll
+      for (int t = 0; t < kLaneRecs; ++t)
+        if (t == nrec) {
+          rq[t] = rc.quantity;
+          rint[t] = uint32_t(rc.interval);
+          rstr[t] = whole ? uint32_t(nx) : 1u;
+          rout[t] = whole ? rc.out + c : rc.out;
+          rro[t] = rc.readout ? rc.readout + me * (M + 1) : nullptr;
+        }
+      ++nrec;
+    };
+    if (sim.rec_first)
+      for (int32_t r = sim.rec_first[c]; r < sim.rec_first[c + 1]; ++r) add(sim.rec_ids[r], false);
+    for (int32_t r = 0; r < sim.n_rec_all; ++r) add(sim.rec_all[r], true);
+  }
+
+  // coefficients of a single-material wave held in registers for the launch
+  R cf[VC ? SQ : 1];
+  bool wave_uni = false;
+  int mm0 = 0;
+  if constexpr (VC && N > 0) {
+    const uint64_t qmask = __ballot(qm);
+    if (qmask) {
+      mm0 = __builtin_amdgcn_readlane(me, __ffsll(static_cast<unsigned long long>(qmask)) - 1);
+      wave_uni = __ballot(qm && me != mm0) == 0;
+      if (wave_uni) {
+        const cptr<R> mt0 = mtab + __builtin_amdgcn_readfirstlane(mm0 * S);
+#pragma unroll
+        for (int i = 0; i < SQ; ++i) cf[i] = mt0[kCoefKap + i];
+      }
+    }
+  }
+  if constexpr (WAVE) __syncthreads();  // staged source values visible
+
   for (int s = 0; s < ks; ++s) {
     const uint32_t n1 = uint32_t(ls0 + s + 1);
     const bool rec_now = rec_here && n1 % rec_every == 0u;
-    se[l] = e;
-    __syncthreads();
-    const R er = l + 1 < B ? se[l + 1] : R(0);
-    const R el = l > 0 ? se[l - 1] : R(0);
+    R er, el;
+    if constexpr (WAVE) {
+      er = lane_from_right(e);
+      el = lane_from_left(e);
+    } else {
+      se[l] = e;
+      __syncthreads();
+      er = l + 1 < B ? se[l + 1] : R(0);
+      el = l > 0 ? se[l - 1] : R(0);
+    }
     if (hcell) h = fma(ch, er - e, h);
     R p = 0;
     if constexpr (N > 0) {
-      uint64_t todo = __ballot(qm);
-      while (todo) {
-        const int lead = __ffsll(static_cast<unsigned long long>(todo)) - 1;
-        const int mm = __builtin_amdgcn_readlane(me, lead);
-        const bool mine = qm && me == mm;
-        if (mine) {
-          const cptr<R> mt = mtab + __builtin_amdgcn_readfirstlane(mm * S);  // uniform: scalar loads
-          CL::rotate(x, e, mt);
-          p = CL::polar(x, mt);
-          if (rec_now) record_density<N, R>(sim, c, n1, mm, x);
-          CL::propagate(x, mt);
+      auto density = [&](const auto &mt, int mm) {
+        CL::rotate(x, e, mt);
+        p = CL::polar(x, mt);
+        if (rec_now) {
+          if (rec_slow) {
+            record_density<N, R>(sim, c, n1, mm, x);
+          } else {
+#pragma unroll
+            for (int t = 0; t < kLaneRecs; ++t)
+              if (t < nrec && rq[t] >= 2 && n1 % rint[t] == 0u)
+                rout[t][size_t(n1 / rint[t] - 1) * rstr[t]] = CL::readout(x, rro[t]);
+          }
         }
-        todo &= ~__ballot(mine);
+        CL::propagate(x, mt);
+      };
+      if (VC && wave_uni) {
+        if (qm) density(RegCoef<R, VC ? SQ : 1>{cf}, mm0);
+      } else {
+        uint64_t todo = __ballot(qm);
+        while (todo) {
+          const int lead = __ffsll(static_cast<unsigned long long>(todo)) - 1;
+          const int mm = __builtin_amdgcn_readlane(me, lead);
+          const bool mine = qm && me == mm;
+          if (mine) density(mtab + __builtin_amdgcn_readfirstlane(mm * S), mm);  // uniform: scalar loads
+          todo &= ~__ballot(mine);
+        }
       }
     }
-    sh[l] = h;
-    __syncthreads();
-    const R hl = l > 0 ? sh[l - 1] : R(0);
+    R hl;
+    if constexpr (WAVE) {
+      hl = lane_from_left(h);
+    } else {
+      sh[l] = h;
+      __syncthreads();
+      hl = l > 0 ? sh[l - 1] : R(0);
+    }
     const R eo = e;
     if (ecell) e = fma(cbd, h - hl, fma(ca, eo, -(cbg * p)));
     if (mur_tile) {
-      se2[l] = e;
-      __syncthreads();
-      if (mur_l) e = fma(kap_l, se2[l + 1] - eo, er);
-      if (mur_r) e = fma(kap_r, se2[l - 1] - eo, el);
+      R enr, enl;
+      if constexpr (WAVE) {
+        enr = lane_from_right(e);
+        enl = lane_from_left(e);
+      } else {
+        se2[l] = e;
+        __syncthreads();
+        enr = l + 1 < B ? se2[l + 1] : R(0);
+        enl = l > 0 ? se2[l - 1] : R(0);
+      }
+      if (mur_l) e = fma(kap_l, enr - eo, er);
+      if (mur_r) e = fma(kap_r, enl - eo, el);
     }
     if (pec) e = 0;
     if (src_direct) {
@@ -358,7 +480,26 @@ __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
         }
       }
     }
-    if (rec_now) record_fields(sim, c, n1, e, hcell ? h : R(0), qm);
+    if (rec_now) {
+      if (rec_slow) {
+        record_fields(sim, c, n1, e, hcell ? h : R(0), qm);
+      } else {
+#pragma unroll
+        for (int t = 0; t < kLaneRecs; ++t) {
+          if (t >= nrec || n1 % rint[t] != 0u) continue;
+          double v;
+          if (rq[t] == 0)
+            v = double(e);
+          else if (rq[t] == 1)
+            v = double(hcell ? h : R(0));
+          else if (!qm)
+            v = 0.0;
+          else
+            continue;
+          rout[t][size_t(n1 / rint[t] - 1) * rstr[t]] = v;
+        }
+      }
+    }
   }
   if (own) {
     R *__restrict__ e_out = static_cast<R *>(sim.e[par ^ 1]);
@@ -485,30 +626,40 @@ __global__ void __launch_bounds__(kPlainBlock) k_plain_e(const DevSim *__restric
   if (!isfinite(e)) *sim.status = 1;
 }
 
-template <int N, typename R>
-hipError_t launch_blocked_nr(int block, const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0,
-                             int parity, int halo, int k, hipStream_t st) {
+template <int N, typename R, bool VC>
+hipError_t launch_blocked_nrv(int block, const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0,
+                              int parity, int halo, int k, hipStream_t st) {
   switch (block) {
-    case 64: k_blocked<N, R, 64><<<n_tiles, 64, 0, st>>>(sims, tiles, n0, parity, halo, k); break;
-    case 128: k_blocked<N, R, 128><<<n_tiles, 128, 0, st>>>(sims, tiles, n0, parity, halo, k); break;
-    case 256: k_blocked<N, R, 256><<<n_tiles, 256, 0, st>>>(sims, tiles, n0, parity, halo, k); break;
-    case 512: k_blocked<N, R, 512><<<n_tiles, 512, 0, st>>>(sims, tiles, n0, parity, halo, k); break;
-    case 1024: k_blocked<N, R, 1024><<<n_tiles, 1024, 0, st>>>(sims, tiles, n0, parity, halo, k); break;
+    case 64: k_blocked<N, R, 64, VC><<<n_tiles, 64, 0, st>>>(sims, tiles, n0, parity, halo, k); break;
+    case 128: k_blocked<N, R, 128, VC><<<n_tiles, 128, 0, st>>>(sims, tiles, n0, parity, halo, k); break;
+    case 256: k_blocked<N, R, 256, VC><<<n_tiles, 256, 0, st>>>(sims, tiles, n0, parity, halo, k); break;
+    case 512: k_blocked<N, R, 512, VC><<<n_tiles, 512, 0, st>>>(sims, tiles, n0, parity, halo, k); break;
+    case 1024: k_blocked<N, R, 1024, VC><<<n_tiles, 1024, 0, st>>>(sims, tiles, n0, parity, halo, k); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+// register-resident coefficients are instantiated for the small level counts only
+template <int N, typename R>
+hipError_t launch_blocked_nr(int block, bool vc, const DevSim *sims, const DevTile *tiles, int n_tiles,
+                             int64_t n0, int parity, int halo, int k, hipStream_t st) {
+  if constexpr (N == 2 || N == 3) {
+    if (vc) return launch_blocked_nrv<N, R, true>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+  }
+  return launch_blocked_nrv<N, R, false>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+}
+
 template <typename R>
-hipError_t launch_blocked_r(int levels, int block, const DevSim *sims, const DevTile *tiles, int n_tiles,
-                            int64_t n0, int parity, int halo, int k, hipStream_t st) {
+hipError_t launch_blocked_r(int levels, int block, bool vc, const DevSim *sims, const DevTile *tiles,
+                            int n_tiles, int64_t n0, int parity, int halo, int k, hipStream_t st) {
   switch (levels) {
-    case 0: return launch_blocked_nr<0, R>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 2: return launch_blocked_nr<2, R>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 3: return launch_blocked_nr<3, R>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 4: return launch_blocked_nr<4, R>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 5: return launch_blocked_nr<5, R>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 6: return launch_blocked_nr<6, R>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 0: return launch_blocked_nr<0, R>(block, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 2: return launch_blocked_nr<2, R>(block, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 3: return launch_blocked_nr<3, R>(block, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 4: return launch_blocked_nr<4, R>(block, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 5: return launch_blocked_nr<5, R>(block, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 6: return launch_blocked_nr<6, R>(block, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
   }
   return hipErrorInvalidValue;
 }
@@ -531,12 +682,13 @@ bool block_supported(int block) {
 
 int plain_block() { return kPlainBlock; }
 
-hipError_t launch_blocked(int levels, int precision, int block, const DevSim *sims, const DevTile *tiles,
+hipError_t launch_blocked(int levels, int precision, int block, bool vc, const DevSim *sims, const DevTile *tiles,
                           int n_tiles, int64_t n0, int parity, int halo, int k, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
   if (k < 1 || k > halo || k > kMaxChunk || 2 * halo >= block) return hipErrorInvalidValue;
-  if (precision == 64) return launch_blocked_r<double>(levels, block, sims, tiles, n_tiles, n0, parity, halo, k, st);
-  return launch_blocked_r<float>(levels, block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+  if (precision == 64)
+    return launch_blocked_r<double>(levels, block, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
+  return launch_blocked_r<float>(levels, block, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
 }
 
 hipError_t launch_plain(int levels, const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity,

@@ -12,7 +12,9 @@ int plain_block();
 
 // Temporally blocked launch from engine step n0 with buffer parity `parity`:
 // k <= halo steps for every tile; 2*halo < block.
-hipError_t launch_blocked(int levels, int precision, int block, const DevSim *sims,
+// vc: quantum coefficients of single-material waves held in registers
+// (used for 2 and 3 levels, ignored otherwise).
+hipError_t launch_blocked(int levels, int precision, int block, bool vc, const DevSim *sims,
                           const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo, int k,
                           hipStream_t st);
 // One time step as two launches (FP64); tiles of plain_block() cells.

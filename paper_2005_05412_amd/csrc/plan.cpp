@@ -521,6 +521,10 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
     err = "precision must be 64 or 32";
     return MB_ERR_ARG;
   }
+  if (scen->variant < MB_VARIANT_AUTO || scen->variant > MB_VARIANT_BLOCKED_REGS) {
+    err = "unknown variant";
+    return MB_ERR_ARG;
+  }
   if (scen->variant == MB_VARIANT_PLAIN && scen->precision != 64) {
     err = "the plain variant runs in FP64 only";
     return MB_ERR_UNSUPPORTED;

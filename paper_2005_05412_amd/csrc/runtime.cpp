@@ -171,8 +171,8 @@ void Arena::release(void *p) {
 
 // ---------------------------------------------------------------- Engine
 
-Engine::Engine(int device, int precision, int variant, int block, int halo)
-    : device_(device), precision_(precision), variant_(variant), block_(block), halo_(halo) {}
+Engine::Engine(int device, int precision, int variant, int block, int halo, bool vc)
+    : device_(device), precision_(precision), variant_(variant), block_(block), halo_(halo), vc_(vc) {}
 
 Engine::~Engine() {
   for (auto &s : sims_)
@@ -428,7 +428,7 @@ hipError_t Engine::launch_only(hipStream_t st, int k) {
   }
   for (auto &g : groups_) {
     if (g.members.empty()) continue;
-    hipError_t e = launch_blocked(g.levels, precision_, block_, g.d_sims, g.d_tiles, g.n_tiles, n0_, parity_,
+    hipError_t e = launch_blocked(g.levels, precision_, block_, vc_, g.d_sims, g.d_tiles, g.n_tiles, n0_, parity_,
                                   halo_, k, st);
     if (e != hipSuccess) return e;
   }

@@ -55,7 +55,8 @@ size_t sim_bytes(const SimPlan &p, int precision, bool plain);
 
 class Engine {
  public:
-  Engine(int device, int precision, int variant, int block, int halo);
+  // vc: keep the quantum coefficients of single-material waves in registers
+  Engine(int device, int precision, int variant, int block, int halo, bool vc = false);
   ~Engine();
   int init(std::string &err);
 
@@ -87,6 +88,7 @@ class Engine {
   // steps per blocked launch: the halo width, at most 256
   int chunk_steps() const { return halo_ < 256 ? halo_ : 256; }
   int block() const { return block_; }
+  bool vc() const { return vc_; }
   int variant() const { return variant_; }
   int precision() const { return precision_; }
   SimState &sim(int id) { return *sims_[id]; }
@@ -110,6 +112,7 @@ class Engine {
   hipError_t upload_group(Group &g, hipStream_t st);
 
   int device_, precision_, variant_, block_, halo_;
+  bool vc_ = false;
   std::vector<std::unique_ptr<SimState>> sims_;
   std::vector<Group> groups_;
   bool dirty_ = true;

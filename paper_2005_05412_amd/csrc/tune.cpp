@@ -39,8 +39,11 @@ void load_cache() {
   std::ifstream f(path);
   std::string key;
   Shape s;
-  while (f >> key >> s.block >> s.halo)
+  int vc = 0;
+  while (f >> key >> s.block >> s.halo >> vc) {
+    s.vc = vc != 0;
     if (block_supported(s.block) && s.halo >= 1 && 2 * s.halo < s.block) g_cache[key] = s;
+  }
 }
 
 void store_cache(const std::string &key, const Shape &s) {
@@ -48,7 +51,7 @@ void store_cache(const std::string &key, const Shape &s) {
   std::string path = cache_path();
   if (path.empty()) return;
   std::ofstream f(path, std::ios::app);
-  if (f) f << key << " " << s.block << " " << s.halo << "\n";
+  if (f) f << key << " " << s.block << " " << s.halo << " " << (s.vc ? 1 : 0) << "\n";
 }
 
 uint64_t pow2_ceil(uint64_t v) {
@@ -60,12 +63,16 @@ uint64_t pow2_ceil(uint64_t v) {
 }  // namespace
 
 std::vector<Shape> candidate_shapes(int levels) {
-  std::vector<Shape> all = {{64, 16},  {128, 16}, {128, 32},  {256, 32},  {256, 64},
-                            {512, 64}, {512, 128}, {512, 192}, {1024, 128}, {1024, 256}};
+  // 64-thread tiles exchange neighbours inside one wave (no barriers); larger
+  // tiles go through LDS with a barrier per exchange
+  const std::vector<std::pair<int, int>> all = {{64, 8},   {64, 12},  {64, 16},   {64, 20},   {128, 16},
+                                                {128, 32}, {256, 32}, {256, 64},  {512, 64},  {512, 128},
+                                                {512, 192}, {1024, 128}, {1024, 256}};
   std::vector<Shape> out;
-  for (const Shape &s : all) {
-    if (levels >= 5 && s.block > 512) continue;  // register pressure of the large matvec
-    out.push_back(s);
+  for (auto [b, h] : all) {
+    if (levels >= 5 && b > 512) continue;  // register pressure of the large matvec
+    out.push_back(Shape{b, h, false});
+    if (levels == 2 || levels == 3) out.push_back(Shape{b, h, true});
   }
   return out;
 }
@@ -83,7 +90,7 @@ std::string tune_key(int device, const std::vector<const SimPlan *> &plans, int 
     cells += uint64_t(p->nx);
   }
   std::ostringstream os;
-  os << arch << "/N" << levels << "/p" << precision << "/cells" << pow2_ceil(cells) << "/sims"
+  os << arch << "/v2/N" << levels << "/p" << precision << "/cells" << pow2_ceil(cells) << "/sims"
      << pow2_ceil(plans.size());
   return os.str();
 }
@@ -117,7 +124,7 @@ int tune_shape(int device, const std::vector<const SimPlan *> &plans, int precis
   double best_us = 1e300;
   best = Shape{256, 32};
   for (const Shape &cand : candidate_shapes(levels)) {
-    Engine eng(device, precision, MB_VARIANT_BLOCKED, cand.block, cand.halo);
+    Engine eng(device, precision, MB_VARIANT_BLOCKED, cand.block, cand.halo, cand.vc);
     if (eng.init(err) < 0) continue;
     bool ok = true;
     for (auto *p : plans) {

@@ -11,6 +11,7 @@ namespace mb {
 struct Shape {
   int block = 256;  // threads (cells) per tile
   int halo = 32;    // halo width = steps per launch (capped at 256)
+  bool vc = false;  // quantum coefficients in registers (2 and 3 levels)
 };
 
 std::vector<Shape> candidate_shapes(int levels);

@@ -73,9 +73,10 @@ def test_small_random_fp64_plain_and_blocked_vs_oracle(case):
     plain = gpu_run(prob, precision=64, variant="plain")
     errs = rel_errors(prob, plain, ref)
     assert max(errs.values()) <= TOL[64], errs
-    for block, depth in ((64, 1), (64, 7), (128, 31), (256, 32)):
-        blk = gpu_run(prob, precision=64, variant="blocked", block=block, depth=depth)
-        assert_same(blk, plain)
+    for block, depth in ((64, 1), (64, 7), (64, 20), (128, 31), (256, 32), (512, 100)):
+        for variant in ("blocked", "blocked_regs"):
+            blk = gpu_run(prob, precision=64, variant=variant, block=block, depth=depth)
+            assert_same(blk, plain)
 
 
 @pytest.mark.parametrize("case", SMALL[:5], ids=lambda c: f"N{c['N']}-nx{c['nx']}-s{c['seed']}")
@@ -86,6 +87,9 @@ def test_small_random_fp32_vs_oracle(case):
     got = gpu_run(prob, precision=32, variant="blocked", block=128, depth=16)
     errs = rel_errors(prob, got, ref)
     assert max(errs.values()) <= TOL[32], errs
+    # every tile shape and coefficient placement runs the same per-cell arithmetic
+    for variant, block, depth in (("blocked", 64, 12), ("blocked_regs", 64, 16), ("blocked_regs", 256, 64)):
+        assert_same(gpu_run(prob, precision=32, variant=variant, block=block, depth=depth), got)
 
 
 def test_blocked_chunking_is_invisible():
