@@ -49,8 +49,8 @@ struct DevSim {
   const DevSource *src;
   const DevRecord *rec;
   int32_t n_rec, n_rec_all;
-  const int32_t *rec_first;  // nx+1 offsets into rec_ids (records at one cell), or null
-  const int32_t *rec_ids;
+  const int32_t *rec_first;  // nx+1 offsets into rec_cell (records at one cell), or null
+  const DevRecord *rec_cell; // copies of the single-cell records, grouped by cell
   const int32_t *rec_all;    // whole-domain record ids
   int32_t *status;           // bit 0: non-finite field seen
   int32_t rec_every;         // gcd of the record intervals (1 when there are no records)

@@ -16,7 +16,6 @@ namespace {
 
 constexpr int kTileSources = 4;  // sources per tile staged in LDS
 constexpr int kMaxChunk = 256;   // steps per blocked launch
-constexpr int kLaneRecs = 4;     // records per cell kept in registers during a launch
 
 // Neighbour values within one wave by DPP wavefront shifts (lane l receives
 // lane l+1, respectively l-1; the lane at the end of the wave receives 0).
@@ -172,18 +171,16 @@ struct Cell {
 
 __device__ __forceinline__ bool due(uint32_t n1, int64_t interval) { return n1 % uint32_t(interval) == 0u; }
 
-// density records of one cell after local step n1 - 1 (values of rho^{n+1/2})
+// density records of one cell after local step n1 - 1 (values of rho^{n+1/2});
+// [rb, re) are the cell's entries of the per-cell record table
 template <int N, typename R>
 __device__ __forceinline__ void record_density(const DevSim &sim, int c, uint32_t n1, int mat,
-                                            const R (&y)[Cell<N, R>::MA]) {
+                                            const R (&y)[Cell<N, R>::MA], int rb, int re) {
   constexpr int M = Cell<N, R>::M;
-  if (sim.rec_first) {
-    const int32_t b = sim.rec_first[c], e = sim.rec_first[c + 1];
-    for (int32_t r = b; r < e; ++r) {
-      const DevRecord &rc = sim.rec[sim.rec_ids[r]];
-      if (rc.quantity < 2 || !due(n1, rc.interval)) continue;
-      rc.out[n1 / uint32_t(rc.interval) - 1] = Cell<N, R>::readout(y, rc.readout + mat * (M + 1));
-    }
+  for (int32_t r = rb; r < re; ++r) {
+    const DevRecord &rc = sim.rec_cell[r];
+    if (rc.quantity < 2 || !due(n1, rc.interval)) continue;
+    rc.out[n1 / uint32_t(rc.interval) - 1] = Cell<N, R>::readout(y, rc.readout + mat * (M + 1));
   }
   for (int32_t r = 0; r < sim.n_rec_all; ++r) {
     const DevRecord &rc = sim.rec[sim.rec_all[r]];
@@ -195,7 +192,8 @@ __device__ __forceinline__ void record_density(const DevSim &sim, int c, uint32_
 
 // field records (E^{n+1}, H^{n+1/2}) and zero density values outside quantum cells
 template <typename R>
-__device__ __forceinline__ void record_fields(const DevSim &sim, int c, uint32_t n1, R e, R h, bool qm) {
+__device__ __forceinline__ void record_fields(const DevSim &sim, int c, uint32_t n1, R e, R h, bool qm, int rb,
+                                              int re) {
   auto val = [&](const DevRecord &rc, double &v) -> bool {
     if (rc.quantity == 0) {
       v = double(e);
@@ -211,14 +209,11 @@ __device__ __forceinline__ void record_fields(const DevSim &sim, int c, uint32_t
     }
     return false;
   };
-  if (sim.rec_first) {
-    const int32_t b = sim.rec_first[c], en = sim.rec_first[c + 1];
-    for (int32_t r = b; r < en; ++r) {
-      const DevRecord &rc = sim.rec[sim.rec_ids[r]];
-      double v;
-      if (!due(n1, rc.interval) || !val(rc, v)) continue;
-      rc.out[n1 / uint32_t(rc.interval) - 1] = v;
-    }
+  for (int32_t r = rb; r < re; ++r) {
+    const DevRecord &rc = sim.rec_cell[r];
+    double v;
+    if (!due(n1, rc.interval) || !val(rc, v)) continue;
+    rc.out[n1 / uint32_t(rc.interval) - 1] = v;
   }
   for (int32_t r = 0; r < sim.n_rec_all; ++r) {
     const DevRecord &rc = sim.rec[sim.rec_all[r]];
@@ -228,8 +223,13 @@ __device__ __forceinline__ void record_fields(const DevSim &sim, int c, uint32_t
   }
 }
 
-__device__ __forceinline__ bool has_records(const DevSim &sim, int c) {
-  return sim.n_rec_all > 0 || (sim.rec_first && sim.rec_first[c + 1] > sim.rec_first[c]);
+// the cell's entries [rb, re) in the per-cell record table
+__device__ __forceinline__ void record_range(const DevSim &sim, int c, int &rb, int &re) {
+  rb = re = 0;
+  if (sim.rec_first) {
+    rb = sim.rec_first[c];
+    re = sim.rec_first[c + 1];
+  }
 }
 
 template <typename R>
@@ -339,48 +339,12 @@ __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
                                    (sim.edge_r == 1 && lo <= nx - 1 && nx - 1 < lo + B));
   const bool mur_l = left && sim.edge_l == 1, mur_r = right && sim.edge_r == 1;
   const bool pec = (left && sim.edge_l == 0) || (right && sim.edge_r == 0);
-  const bool rec_here = sim.n_rec > 0 && own && has_records(sim, c);
+  // the cell's entries in the per-cell record table, fetched once per launch
+  int rb = 0, re = 0;
+  if (own && sim.n_rec > 0) record_range(sim, c, rb, re);
+  const bool rec_here = own && (re > rb || sim.n_rec_all > 0);
   const uint32_t rec_every = uint32_t(sim.rec_every);
   const R kap_l = R(sim.kap_l), kap_r = R(sim.kap_r);
-
-  // per-lane record descriptors, fetched once per launch (at most kLaneRecs
-  // per cell; cells with more use the generic path)
-  int nrec = 0;
-  bool rec_slow = false;
-  int rq[kLaneRecs];
-  uint32_t rint[kLaneRecs], rstr[kLaneRecs];
-  double *rout[kLaneRecs];
-  const double *rro[kLaneRecs];
-#pragma unroll
-  for (int t = 0; t < kLaneRecs; ++t) {
-    rq[t] = 0;
-    rint[t] = 1;
-    rstr[t] = 1;
-    rout[t] = nullptr;
-    rro[t] = nullptr;
-  }
-  if (rec_here) {
-    auto add = [&](int id, bool whole) {
-      if (nrec == kLaneRecs) {
-        rec_slow = true;
-        return;
-      }
-      const DevRecord &rc = sim.rec[id];
-#pragma unroll
-      for (int t = 0; t < kLaneRecs; ++t)
-        if (t == nrec) {
-          rq[t] = rc.quantity;
-          rint[t] = uint32_t(rc.interval);
-          rstr[t] = whole ? uint32_t(nx) : 1u;
-          rout[t] = whole ? rc.out + c : rc.out;
-          rro[t] = rc.readout ? rc.readout + me * (M + 1) : nullptr;
-        }
-      ++nrec;
-    };
-    if (sim.rec_first)
-      for (int32_t r = sim.rec_first[c]; r < sim.rec_first[c + 1]; ++r) add(sim.rec_ids[r], false);
-    for (int32_t r = 0; r < sim.n_rec_all; ++r) add(sim.rec_all[r], true);
-  }
 
   // coefficients of a single-material wave held in registers for the launch
   R cf[VC ? SQ : 1];
@@ -419,16 +383,7 @@ __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
       auto density = [&](const auto &mt, int mm) {
         CL::rotate(x, e, mt);
         p = CL::polar(x, mt);
-        if (rec_now) {
-          if (rec_slow) {
-            record_density<N, R>(sim, c, n1, mm, x);
-          } else {
-#pragma unroll
-            for (int t = 0; t < kLaneRecs; ++t)
-              if (t < nrec && rq[t] >= 2 && n1 % rint[t] == 0u)
-                rout[t][size_t(n1 / rint[t] - 1) * rstr[t]] = CL::readout(x, rro[t]);
-          }
-        }
+        if (rec_now) record_density<N, R>(sim, c, n1, mm, x, rb, re);
         CL::propagate(x, mt);
       };
       if (VC && wave_uni) {
@@ -481,24 +436,7 @@ __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
       }
     }
     if (rec_now) {
-      if (rec_slow) {
-        record_fields(sim, c, n1, e, hcell ? h : R(0), qm);
-      } else {
-#pragma unroll
-        for (int t = 0; t < kLaneRecs; ++t) {
-          if (t >= nrec || n1 % rint[t] != 0u) continue;
-          double v;
-          if (rq[t] == 0)
-            v = double(e);
-          else if (rq[t] == 1)
-            v = double(hcell ? h : R(0));
-          else if (!qm)
-            v = 0.0;
-          else
-            continue;
-          rout[t][size_t(n1 / rint[t] - 1) * rstr[t]] = v;
-        }
-      }
+      record_fields(sim, c, n1, e, hcell ? h : R(0), qm, rb, re);
     }
   }
   if (own) {
@@ -551,7 +489,9 @@ __global__ void __launch_bounds__(kPlainBlock) k_plain_hd(const DevSim *__restri
   if constexpr (N > 0) {
     const int me = sim.mat_e[c];
     const bool qm = mtab[me * S + kCoefQM] != R(0);
-    const bool rec_now = sim.n_rec > 0 && n1 % uint32_t(sim.rec_every) == 0u && has_records(sim, c);
+    int rb = 0, re = 0;
+    const bool rec_now = sim.n_rec > 0 && n1 % uint32_t(sim.rec_every) == 0u;
+    if (rec_now) record_range(sim, c, rb, re);
     uint64_t todo = __ballot(qm);
     while (todo) {
       const int lead = __ffsll(static_cast<unsigned long long>(todo)) - 1;
@@ -564,7 +504,7 @@ __global__ void __launch_bounds__(kPlainBlock) k_plain_hd(const DevSim *__restri
         for (int a = 0; a < M; ++a) x[a] = xx[a * nx + c];
         CL::rotate(x, e, mt);
         p = CL::polar(x, mt);
-        if (rec_now) record_density<N, R>(sim, c, n1, mm, x);
+        if (rec_now) record_density<N, R>(sim, c, n1, mm, x, rb, re);
         CL::propagate(x, mt);
 #pragma unroll
         for (int a = 0; a < M; ++a) xx[a * nx + c] = x[a];
@@ -618,10 +558,12 @@ __global__ void __launch_bounds__(kPlainBlock) k_plain_e(const DevSim *__restric
   }
   e = apply_sources(sim, c, n1, e);
   e_out[c] = e;
-  if (sim.n_rec > 0 && n1 % uint32_t(sim.rec_every) == 0u && has_records(sim, c)) {
+  if (sim.n_rec > 0 && n1 % uint32_t(sim.rec_every) == 0u) {
     bool qm = false;
     if constexpr (N > 0) qm = mtab[sim.mat_e[c] * S + kCoefQM] != 0.0;
-    record_fields(sim, c, n1, e, c <= nx - 2 ? hh[c] : 0.0, qm);
+    int rb, re;
+    record_range(sim, c, rb, re);
+    record_fields(sim, c, n1, e, c <= nx - 2 ? hh[c] : 0.0, qm, rb, re);
   }
   if (!isfinite(e)) *sim.status = 1;
 }

@@ -51,7 +51,7 @@ Layout layout_of(const SimPlan &p, int precision, bool plain) {
       ++L.n_all;
   }
   L.rec_first = L.n_point ? take((nx + 1) * sizeof(int32_t)) : 0;
-  L.rec_ids = take(std::max(1, L.n_point) * sizeof(int32_t));
+  L.rec_ids = take(std::max(1, L.n_point) * sizeof(DevRecord));
   L.rec_all = take(std::max(1, L.n_all) * sizeof(int32_t));
   L.end_head = off;
   for (auto &r : p.records) L.out_off.push_back(take(size_t(r.n_samples) * size_t(r.width) * sizeof(double)));
@@ -283,11 +283,11 @@ int Engine::add(SimPlan &&plan, Arena *arena, hipStream_t st, std::string &err) 
   }
   if (L.n_point) {
     int32_t *first = reinterpret_cast<int32_t *>(head.data() + L.rec_first);
-    int32_t *ids = reinterpret_cast<int32_t *>(head.data() + L.rec_ids);
+    DevRecord *cell_recs = reinterpret_cast<DevRecord *>(head.data() + L.rec_ids);
     int32_t k = 0;
     for (int64_t c = 0; c < p.nx; ++c) {
       first[c] = k;
-      for (int32_t id : per_cell[c]) ids[k++] = id;
+      for (int32_t id : per_cell[c]) cell_recs[k++] = recs[id];
     }
     first[p.nx] = k;
   }
@@ -330,7 +330,7 @@ int Engine::add(SimPlan &&plan, Arena *arena, hipStream_t st, std::string &err) 
   for (auto &rp : p.records) g = std::gcd(g, rp.interval);
   d.rec_every = int32_t(g > 0 ? g : 1);
   d.rec_first = L.n_point ? reinterpret_cast<const int32_t *>(dev + L.rec_first) : nullptr;
-  d.rec_ids = reinterpret_cast<const int32_t *>(dev + L.rec_ids);
+  d.rec_cell = reinterpret_cast<const DevRecord *>(dev + L.rec_ids);
   d.rec_all = reinterpret_cast<const int32_t *>(dev + L.rec_all);
   s->status_slot = free_slots_.back();
   free_slots_.pop_back();

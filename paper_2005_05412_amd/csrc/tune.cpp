@@ -141,12 +141,34 @@ int tune_shape(int device, const std::vector<const SimPlan *> &plans, int precis
     int64_t avail = min_steps / k;
     if (avail < 3) continue;
     int64_t timed = std::min<int64_t>(avail - 2, std::max<int64_t>(4, 2048 / k));
-    hipError_t he = hipSuccess;
+    hipError_t he = eng.sync_tables(st);
     for (int q = 0; q < 2 && he == hipSuccess; ++q) he = eng.chunk(st, k);
-    (void)hipEventRecord(a, st);
-    for (int64_t q = 0; q < timed && he == hipSuccess; ++q) he = eng.chunk(st, k);
-    (void)hipEventRecord(b, st);
-    if (he != hipSuccess || hipEventSynchronize(b) != hipSuccess) continue;
+    // the timed chunks run as one captured graph, as production runs do
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;
+    if (he == hipSuccess) he = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (he == hipSuccess) {
+      for (int64_t q = 0; q < timed && he == hipSuccess; ++q) {
+        he = eng.launch_only(cap, k);
+        eng.commit_chunk(k);
+      }
+      hipError_t e2 = hipStreamEndCapture(cap, &graph);
+      if (he == hipSuccess) he = e2;
+    }
+    if (he == hipSuccess) he = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he == hipSuccess) {
+      (void)hipEventRecord(a, st);
+      he = hipGraphLaunch(exec, st);
+      (void)hipEventRecord(b, st);
+    }
+    if (he == hipSuccess) he = hipEventSynchronize(b);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (he != hipSuccess) continue;
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, a, b);
     double us = 1e3 * double(ms) / double(timed * k);
