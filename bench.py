@@ -139,6 +139,90 @@ def cpu_baseline(prob, budget_s):
     return n, el, recs
 
 
+def run_serving(n_requests, rate, log):
+    """Poisson trace through the continuous-batching server; latency = arrival to records on the host."""
+    log(f"[bench] serving {n_requests} requests at {rate:g}/s")
+    trace = W.serve_trace(n_requests=n_requests, rate=rate, precision=32)
+    srv = mb.Server(hbm_budget=16 << 30, max_slots=512, precision=32, chunk_steps=32)
+    tickets = [srv.submit(p, t) for t, p in trace]
+    offered = sum(p["nx"] * p["n_steps"] for _, p in trace) / max(trace[-1][0], 1e-9)
+    t0 = time.perf_counter()
+    srv.start()
+    srv.drain(timeout_s=600)
+    tw = time.perf_counter() - t0
+    lat = []
+    for t in tickets:
+        st, ta, tadm, td = srv.status(t)
+        if st == 2:
+            lat.append(td - ta)
+    cu, busy, chunks = srv.stats()
+    srv.close()
+    lat = np.array(lat)
+    return {"requests": len(trace), "done": int(len(lat)), "arrival_rate_per_s": rate,
+            "offered_cell_updates_per_s": offered,
+            "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+            "value": cu / tw, "unit": "cell-updates/s", "wall_s": tw, "busy_s": busy, "chunks": int(chunks)}
+
+
+def solve_once(hip, stream, prob, precision, variant="auto"):
+    """Setup, one untimed graph-capturing run, then one timed run from the restored initial state."""
+    s = mb.Solver(prob, precision=precision, variant=variant)
+    s.run(-1, stream)
+    hip.sync()
+    s.reset(stream)
+    a, b = hip.event(), hip.event()
+    hip.record(a, stream)
+    s.run(-1, stream)
+    hip.record(b, stream)
+    hip.sync()
+    ms = hip.elapsed_ms(a, b)
+    rec = s.records()
+    shape = s.shape()
+    s.close()
+    return ms, rec, shape
+
+
+def other_configs(hip, stream, log):
+    """Throughput and FP32 error of the other scenario shapes."""
+    res = {}
+    log("[bench] sit 2-level fp64/fp32")
+    p = W.sit_2lvl()
+    ms64, r64, sh64 = solve_once(hip, stream, p, 64)
+    ms32, r32, sh32 = solve_once(hip, stream, p, 32)
+    cells = p["nx"] * p["n_steps"]
+    res["sit_2lvl"] = {"nx": p["nx"], "n_steps": p["n_steps"], "fp64": cells / (ms64 * 1e-3),
+                       "fp32": cells / (ms32 * 1e-3), "unit": "cell-updates/s",
+                       "fp32_vs_fp64_max_rel_err": max_error(p, r32, r64), "shape_fp32": list(sh32)}
+    log("[bench] qcl-like 6-level fp32/fp64, 1e6 steps")
+    p = W.qcl6()
+    ms32, r32, sh32 = solve_once(hip, stream, p, 32)
+    ms64, r64, sh64 = solve_once(hip, stream, p, 64)
+    cells = p["nx"] * p["n_steps"]
+    res["qcl_6lvl"] = {"nx": p["nx"], "n_steps": p["n_steps"], "fp32": cells / (ms32 * 1e-3),
+                       "fp64": cells / (ms64 * 1e-3), "unit": "cell-updates/s",
+                       "fp32_vs_fp64_max_rel_err": max_error(p, r32, r64), "shape_fp32": list(sh32)}
+    log("[bench] sweep x8: 2048 sims fp32 (state beyond the 256 MB last-level cache)")
+    sims = W.sweep(n_sims=2048, precision=32, seed=W.SEED_BASE + 13)
+    bcells = sum(q["nx"] * q["n_steps"] for q in sims)
+    bt = mb.Batch(sims, precision=32, variant="auto")
+    bt.run(stream=stream, use_graph=True)
+    hip.sync()
+    bt.reset(stream)
+    hip.sync()
+    t0 = time.perf_counter()
+    bt.run(stream=stream, use_graph=True)
+    hip.sync()
+    tb = time.perf_counter() - t0
+    beff = sum(bytes_per_cell_update(2 if k % 2 == 0 else 3, 32) * q["nx"] * q["n_steps"]
+               for k, q in enumerate(sims)) / tb / 1e9
+    state_bytes = sum(q["nx"] * (2 + (4 if k % 2 == 0 else 9)) * 4 for k, q in enumerate(sims))
+    res["sweep_x8"] = {"sims": len(sims), "cell_updates": bcells, "value": bcells / tb, "unit": "cell-updates/s",
+                       "wall_s": tb, "state_bytes_one_buffer": state_bytes, "hbm_effective_gbs": beff,
+                       "hbm_effective_frac": beff / PEAK["hbm_gbs"], "shape": list(bt.shape())}
+    bt.close()
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +237,7 @@ def main(argv=None):
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one device-to-device copy of this size (counter calibration)")
@@ -265,28 +350,14 @@ def main(argv=None):
                                 "hbm_effective_frac": beff / PEAK["hbm_gbs"], "block": bblock, "depth": bdepth, "regs": bregs}
         bt.close()
 
+    # ---- other configurations --------------------------------------------------------
+    if not args.no_configs:
+        out["configs"] = other_configs(hip, stream, log)
+
     # ---- serving ---------------------------------------------------------------------
     if not args.no_serve:
-        log(f"[bench] serving trace {args.serve_requests} requests")
-        trace = W.serve_trace(n_requests=args.serve_requests, precision=32)
-        srv = mb.Server(hbm_budget=16 << 30, max_slots=512, precision=32, chunk_steps=32)
-        tickets = [srv.submit(p, t) for t, p in trace]
-        t0 = time.perf_counter()
-        srv.start()
-        srv.drain(timeout_s=600)
-        tw = time.perf_counter() - t0
-        lat = []
-        for t in tickets:
-            st, ta, tadm, td = srv.status(t)
-            if st == 2:
-                lat.append(td - ta)
-        cu, busy, chunks = srv.stats()
-        srv.close()
-        lat = np.array(lat)
-        out["serving"] = {"requests": len(trace), "done": int(len(lat)),
-                          "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
-                          "value": cu / tw, "unit": "cell-updates/s", "wall_s": tw, "busy_s": busy,
-                          "chunks": int(chunks), "arrival_rate_per_s": 200.0}
+        out["serving"] = run_serving(args.serve_requests, 200.0, log)
+        out["serving_low_load"] = [run_serving(n, rate, log) for rate, n in ((25.0, 50), (50.0, 100), (100.0, 150))]
 
     line = json.dumps(out)
     print(line, flush=True)

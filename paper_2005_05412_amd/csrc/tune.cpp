@@ -113,6 +113,12 @@ int tune_shape(int device, const std::vector<const SimPlan *> &plans, int precis
     levels = std::max(levels, p->n);
     min_steps = std::min(min_steps, p->n_steps);
   }
+  // large batches are timed on an evenly spaced subset (enough tiles to fill the GPU)
+  std::vector<const SimPlan *> subset;
+  const size_t kMaxTuneSims = 64;
+  for (size_t i = 0; i < plans.size(); ++i)
+    if (plans.size() <= kMaxTuneSims || (i * kMaxTuneSims) / plans.size() != ((i + 1) * kMaxTuneSims) / plans.size())
+      subset.push_back(plans[i]);
   hipStream_t st;
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
     err = "stream creation failed";
@@ -127,7 +133,7 @@ int tune_shape(int device, const std::vector<const SimPlan *> &plans, int precis
     Engine eng(device, precision, MB_VARIANT_BLOCKED, cand.block, cand.halo, cand.vc);
     if (eng.init(err) < 0) continue;
     bool ok = true;
-    for (auto *p : plans) {
+    for (auto *p : subset) {
       SimPlan copy = *p;
       std::string e2;
       if (eng.add(std::move(copy), nullptr, st, e2) < 0) {

@@ -261,3 +261,34 @@ def test_reset_and_graph_replay_reproduce_the_run():
         again = s.records()
         assert_same(first, again)
     s.close()
+
+
+def test_qcl6_full_grid_prefix_vs_oracle():
+    """Six-level QCL-like cavity (8192 cells, PEC ends, noise start): first 600 steps."""
+    prob = W.qcl6(n_steps=600)
+    _say("qcl6 oracle prefix")
+    ref = O.run(prob)
+    got = gpu_run(prob, precision=64)
+    assert max(rel_errors(prob, got, ref).values()) <= TOL[64]
+    got32 = gpu_run(prob, precision=32)
+    assert max(rel_errors(prob, got32, ref).values()) <= TOL[32]
+
+
+def test_sweep_batch_spot_checks_vs_oracle():
+    """The 256-simulation FP32 sweep in one batch; 8 seeded members checked against the oracle
+    on their first 600 steps (12 record samples)."""
+    sims = W.sweep(n_sims=256, precision=32)
+    _say("sweep batch")
+    b = mb.Batch(sims, precision=32)
+    b.run(use_graph=True)
+    picks = np.random.default_rng(W.SEED_BASE + 3).choice(256, 8, replace=False)
+    for k in picks:
+        p = dict(sims[int(k)])
+        p["n_steps"] = 600
+        _say(f"sweep member {k} nx={p['nx']}")
+        ref = O.run(p)
+        got = b.records(int(k))
+        errs = trace_errors(p, got, ref, n_samples=600 // 50)
+        assert max(errs.values()) <= TOL[32], (k, errs)
+        assert len(got[p["records"][0]["name"]]) == 50000 // 50
+    b.close()
