@@ -143,7 +143,7 @@ def run_serving(n_requests, rate, log):
     """Poisson trace through the continuous-batching server; latency = arrival to records on the host."""
     log(f"[bench] serving {n_requests} requests at {rate:g}/s")
     trace = W.serve_trace(n_requests=n_requests, rate=rate, precision=32)
-    srv = mb.Server(hbm_budget=16 << 30, max_slots=512, precision=32, chunk_steps=32)
+    srv = mb.Server(hbm_budget=16 << 30, max_slots=512, precision=32, chunk_steps=256)
     tickets = [srv.submit(p, t) for t, p in trace]
     offered = sum(p["nx"] * p["n_steps"] for _, p in trace) / max(trace[-1][0], 1e-9)
     t0 = time.perf_counter()

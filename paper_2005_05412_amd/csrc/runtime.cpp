@@ -334,6 +334,7 @@ int Engine::add(SimPlan &&plan, Arena *arena, hipStream_t st, std::string &err) 
   d.rec_all = reinterpret_cast<const int32_t *>(dev + L.rec_all);
   s->status_slot = free_slots_.back();
   free_slots_.pop_back();
+  hi_slot_ = std::max(hi_slot_, s->status_slot + 1);
   d.status = d_status_ + s->status_slot;
   int32_t zero = 0;
   (void)hipMemcpy(d.status, &zero, sizeof(zero), hipMemcpyHostToDevice);
@@ -515,7 +516,8 @@ bool Engine::all_finished() const {
 
 hipError_t Engine::read_status(std::vector<int32_t> &out) {
   out.assign(status_cap_, 0);
-  return hipMemcpy(out.data(), d_status_, size_t(status_cap_) * sizeof(int32_t), hipMemcpyDeviceToHost);
+  if (hi_slot_ == 0) return hipSuccess;
+  return hipMemcpy(out.data(), d_status_, size_t(hi_slot_) * sizeof(int32_t), hipMemcpyDeviceToHost);
 }
 
 hipError_t Engine::read_records(int id, int rec, std::vector<double> &out) {

@@ -119,6 +119,7 @@ class Engine {
   int64_t version_ = 0;
   int32_t *d_status_ = nullptr;
   int status_cap_ = 0;
+  int hi_slot_ = 0;  // status slots in use lie below this index
   std::vector<int> free_slots_;
   int64_t n0_ = 0;
   int parity_ = 0;
