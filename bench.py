@@ -238,11 +238,18 @@ def main(argv=None):
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
+    ap.add_argument("--only", default="",
+                    help="comma list of optional legs to run (fp64,cpu,batch,configs,serve); others are skipped")
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one device-to-device copy of this size (counter calibration)")
     ap.add_argument("--out", default="")
     args = ap.parse_args(argv)
+    if args.only:
+        keep = set(args.only.split(","))
+        for leg in ("fp64", "cpu", "batch", "configs", "serve"):
+            if leg not in keep:
+                setattr(args, "no_" + leg, True)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU runs are not part of this build",
               file=sys.stderr)
