@@ -90,10 +90,15 @@ hipError_t run_steps(Engine &eng, hipStream_t st, int64_t steps, int k, bool use
   hipStream_t cap;
   if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) return e;
   e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-  for (int64_t left = steps; left > 0 && e == hipSuccess; left -= k) {
-    int kk = int(std::min<int64_t>(k, left));
-    e = eng.launch_only(cap, kk);
-    eng.commit_chunk(kk);
+  // full chunks in one fork/join, then the shorter tail chunk
+  const int64_t full = steps / k, tail = steps % k;
+  if (e == hipSuccess && full > 0) {
+    e = eng.launch_only(cap, k, int(full));
+    for (int64_t q = 0; q < full; ++q) eng.commit_chunk(k);
+  }
+  if (e == hipSuccess && tail > 0) {
+    e = eng.launch_only(cap, int(tail));
+    eng.commit_chunk(int(tail));
   }
   hipGraph_t graph = nullptr;
   hipError_t e2 = hipStreamEndCapture(cap, &graph);

@@ -182,6 +182,9 @@ Engine::~Engine() {
     if (g.d_tiles) (void)hipFree(g.d_tiles);
   }
   if (d_status_) (void)hipFree(d_status_);
+  for (hipStream_t q : side_) (void)hipStreamDestroy(q);
+  for (hipEvent_t ev : side_done_) (void)hipEventDestroy(ev);
+  if (fork_) (void)hipEventDestroy(fork_);
 }
 
 int Engine::init(std::string &err) {
@@ -416,24 +419,54 @@ hipError_t Engine::sync_tables(hipStream_t st) {
   return hipSuccess;
 }
 
-hipError_t Engine::launch_only(hipStream_t st, int k) {
-  if (variant_ == MB_VARIANT_PLAIN) {
-    for (int s = 0; s < k; ++s) {
-      for (auto &g : groups_) {
-        if (g.members.empty()) continue;
-        hipError_t e = launch_plain(g.levels, g.d_sims, g.d_tiles, g.n_tiles, n0_ + s, parity_ ^ (s & 1), st);
-        if (e != hipSuccess) return e;
+hipError_t Engine::launch_group(Group &g, hipStream_t st, int k, int reps) {
+  for (int r = 0; r < reps; ++r) {
+    hipError_t e;
+    if (variant_ == MB_VARIANT_PLAIN) {
+      for (int s = 0; s < k; ++s) {
+        const int64_t step = n0_ + int64_t(r) * k + s;
+        if ((e = launch_plain(g.levels, g.d_sims, g.d_tiles, g.n_tiles, step, int((parity_ + r * k + s) & 1), st)) !=
+            hipSuccess)
+          return e;
       }
+    } else if ((e = launch_blocked(g.levels, precision_, block_, vc_, g.d_sims, g.d_tiles, g.n_tiles,
+                                   n0_ + int64_t(r) * k, parity_ ^ (r & 1), halo_, k, st)) != hipSuccess) {
+      return e;
     }
-    return hipSuccess;
-  }
-  for (auto &g : groups_) {
-    if (g.members.empty()) continue;
-    hipError_t e = launch_blocked(g.levels, precision_, block_, vc_, g.d_sims, g.d_tiles, g.n_tiles, n0_, parity_,
-                                  halo_, k, st);
-    if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t Engine::launch_only(hipStream_t st, int k, int reps) {
+  std::vector<Group *> live;
+  for (auto &g : groups_)
+    if (!g.members.empty()) live.push_back(&g);
+  if (live.empty()) return hipSuccess;
+  if (live.size() == 1) return launch_group(*live[0], st, k, reps);
+  hipError_t e = hipSuccess;
+  if (!fork_) e = hipEventCreateWithFlags(&fork_, hipEventDisableTiming);
+  while (e == hipSuccess && side_.size() + 1 < live.size()) {
+    hipStream_t q;
+    hipEvent_t ev;
+    if ((e = hipStreamCreateWithFlags(&q, hipStreamNonBlocking)) != hipSuccess) break;
+    side_.push_back(q);
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) break;
+    side_done_.push_back(ev);
+  }
+  if (e != hipSuccess) return e;
+  if ((e = hipEventRecord(fork_, st)) != hipSuccess) return e;
+  for (size_t i = 1; i < live.size() && e == hipSuccess; ++i) {
+    e = hipStreamWaitEvent(side_[i - 1], fork_, 0);
+    if (e == hipSuccess) e = launch_group(*live[i], side_[i - 1], k, reps);
+    if (e == hipSuccess) e = hipEventRecord(side_done_[i - 1], side_[i - 1]);
+  }
+  if (e == hipSuccess) e = launch_group(*live[0], st, k, reps);
+  // join every side stream that was forked, also after a failed launch
+  for (size_t i = 1; i < live.size(); ++i) {
+    hipError_t e2 = hipStreamWaitEvent(st, side_done_[i - 1], 0);
+    if (e == hipSuccess) e = e2;
+  }
+  return e;
 }
 
 hipError_t Engine::reset(hipStream_t st) {
@@ -493,13 +526,14 @@ void Engine::commit_chunk(int k) {
   }
 }
 
-hipError_t Engine::chunk(hipStream_t st, int k) {
+hipError_t Engine::chunk(hipStream_t st, int k, int reps) {
   if (variant_ != MB_VARIANT_PLAIN && (k < 1 || k > halo_)) return hipErrorInvalidValue;
+  if (reps < 1) return hipErrorInvalidValue;
   hipError_t e = sync_tables(st);
   if (e != hipSuccess) return e;
-  e = launch_only(st, k);
+  e = launch_only(st, k, reps);
   if (e != hipSuccess) return e;
-  commit_chunk(k);
+  for (int r = 0; r < reps; ++r) commit_chunk(k);
   return hipSuccess;
 }
 

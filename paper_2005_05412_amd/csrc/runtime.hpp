@@ -66,14 +66,17 @@ class Engine {
   // Frees the simulation's device memory (after its last chunk completed).
   void remove(int id, Arena *arena);
 
-  // Advances every active simulation by up to k steps (k <= depth for the
-  // blocked variant, any k for the two-launch variant).  Asynchronous.
-  hipError_t chunk(hipStream_t st, int k);
+  // Advances every active simulation by reps chunks of up to k steps each
+  // (k <= depth for the blocked variant, any k for the two-launch variant).
+  // Asynchronous.
+  hipError_t chunk(hipStream_t st, int k, int reps = 1);
   // Uploads group tables if membership changed (synchronous copy).
   hipError_t sync_tables(hipStream_t st);
 
-  // Launches of one chunk, for graph capture: tables must be current.
-  hipError_t launch_only(hipStream_t st, int k);
+  // Launches of reps chunks of k steps, for graph capture: tables must be
+  // current.  Groups of different level counts run on their own streams,
+  // forked from and joined back into st, so their kernels overlap.
+  hipError_t launch_only(hipStream_t st, int k, int reps = 1);
   void commit_chunk(int k);  // host bookkeeping of a chunk launched via launch_only
   // Restores every simulation's initial state from its device image and
   // clears records (asynchronous copies on st, then table upload).
@@ -110,11 +113,16 @@ class Engine {
   };
   Group &group_for(int levels);
   hipError_t upload_group(Group &g, hipStream_t st);
+  hipError_t launch_group(Group &g, hipStream_t st, int k, int reps);
 
   int device_, precision_, variant_, block_, halo_;
   bool vc_ = false;
   std::vector<std::unique_ptr<SimState>> sims_;
   std::vector<Group> groups_;
+  // one stream and completion event per group beyond the first, plus the fork event
+  std::vector<hipStream_t> side_;
+  std::vector<hipEvent_t> side_done_;
+  hipEvent_t fork_ = nullptr;
   bool dirty_ = true;
   int64_t version_ = 0;
   int32_t *d_status_ = nullptr;

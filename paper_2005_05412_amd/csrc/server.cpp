@@ -135,7 +135,7 @@ void mb_server::loop() {
     hipError_t he = hipSuccess;
     int k = e.variant() == MB_VARIANT_PLAIN ? chunk_steps : std::min(chunk_steps, e.chunk_steps());
     int sub = e.variant() == MB_VARIANT_PLAIN ? 1 : std::max(1, chunk_steps / e.chunk_steps());
-    for (int q = 0; q < sub && he == hipSuccess; ++q) he = e.chunk(stream, k);
+    he = e.chunk(stream, k, sub);
     if (he == hipSuccess) he = hipStreamSynchronize(stream);
     std::vector<int32_t> status;
     if (he == hipSuccess) he = e.read_status(status);
