@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -69,8 +70,19 @@ namespace {
 // Advances the engine by `steps` steps in chunks of at most k.  With
 // use_graph the chunk launches are captured into one HIP graph (or the
 // cached graph of an identical earlier run is replayed).
+// Setting MB_GRAPHS=0 in the environment turns capture off (direct launches),
+// for tools that do not follow graph launches.
+bool graphs_enabled() {
+  static const bool on = [] {
+    const char *v = std::getenv("MB_GRAPHS");
+    return !(v && v[0] == '0');
+  }();
+  return on;
+}
+
 hipError_t run_steps(Engine &eng, hipStream_t st, int64_t steps, int k, bool use_graph, GraphCache &gc) {
   hipError_t e = eng.sync_tables(st);
+  use_graph = use_graph && graphs_enabled();
   if (e != hipSuccess) return e;
   if (!use_graph) {
     while (steps > 0 && e == hipSuccess) {
