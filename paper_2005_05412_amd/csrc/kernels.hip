@@ -171,8 +171,20 @@ struct Cell {
 
 __device__ __forceinline__ bool due(uint32_t n1, int64_t interval) { return n1 % uint32_t(interval) == 0u; }
 
-// density records of one cell after local step n1 - 1 (values of rho^{n+1/2});
-// [rb, re) are the cell's entries of the per-cell record table
+template <int N, typename R>
+__device__ __forceinline__ void record_density_all(const DevSim &sim, int c, uint32_t n1, int mat,
+                                                const R (&y)[Cell<N, R>::MA]) {
+  constexpr int M = Cell<N, R>::M;
+  for (int32_t r = 0; r < sim.n_rec_all; ++r) {
+    const DevRecord &rc = sim.rec[sim.rec_all[r]];
+    if (rc.quantity < 2 || !due(n1, rc.interval)) continue;
+    rc.out[size_t(n1 / uint32_t(rc.interval) - 1) * size_t(sim.nx) + c] =
+        Cell<N, R>::readout(y, rc.readout + mat * (M + 1));
+  }
+}
+
+// density records of one cell after local step n1 - 1 (values of rho^{n+1/2}):
+// entries [rb, re) of the per-cell record table, then the whole-domain records
 template <int N, typename R>
 __device__ __forceinline__ void record_density(const DevSim &sim, int c, uint32_t n1, int mat,
                                             const R (&y)[Cell<N, R>::MA], int rb, int re) {
@@ -182,46 +194,98 @@ __device__ __forceinline__ void record_density(const DevSim &sim, int c, uint32_
     if (rc.quantity < 2 || !due(n1, rc.interval)) continue;
     rc.out[n1 / uint32_t(rc.interval) - 1] = Cell<N, R>::readout(y, rc.readout + mat * (M + 1));
   }
-  for (int32_t r = 0; r < sim.n_rec_all; ++r) {
-    const DevRecord &rc = sim.rec[sim.rec_all[r]];
-    if (rc.quantity < 2 || !due(n1, rc.interval)) continue;
-    rc.out[size_t(n1 / uint32_t(rc.interval) - 1) * size_t(sim.nx) + c] =
-        Cell<N, R>::readout(y, rc.readout + mat * (M + 1));
-  }
+  record_density_all<N, R>(sim, c, n1, mat, y);
 }
 
-// field records (E^{n+1}, H^{n+1/2}) and zero density values outside quantum cells
+// value of a field record (E^{n+1}, H^{n+1/2}; density quantities read zero
+// outside quantum cells); false for density quantities of quantum cells
 template <typename R>
-__device__ __forceinline__ void record_fields(const DevSim &sim, int c, uint32_t n1, R e, R h, bool qm, int rb,
-                                              int re) {
-  auto val = [&](const DevRecord &rc, double &v) -> bool {
-    if (rc.quantity == 0) {
-      v = double(e);
-      return true;
-    }
-    if (rc.quantity == 1) {
-      v = double(h);
-      return true;
-    }
-    if (!qm) {
-      v = 0.0;
-      return true;
-    }
-    return false;
-  };
-  for (int32_t r = rb; r < re; ++r) {
-    const DevRecord &rc = sim.rec_cell[r];
-    double v;
-    if (!due(n1, rc.interval) || !val(rc, v)) continue;
-    rc.out[n1 / uint32_t(rc.interval) - 1] = v;
+__device__ __forceinline__ bool field_value(int quantity, R e, R h, bool qm, double &v) {
+  if (quantity == 0) {
+    v = double(e);
+    return true;
   }
+  if (quantity == 1) {
+    v = double(h);
+    return true;
+  }
+  if (!qm) {
+    v = 0.0;
+    return true;
+  }
+  return false;
+}
+
+template <typename R>
+__device__ __forceinline__ void record_fields_all(const DevSim &sim, int c, uint32_t n1, R e, R h, bool qm) {
   for (int32_t r = 0; r < sim.n_rec_all; ++r) {
     const DevRecord &rc = sim.rec[sim.rec_all[r]];
     double v;
-    if (!due(n1, rc.interval) || !val(rc, v)) continue;
+    if (!due(n1, rc.interval) || !field_value(rc.quantity, e, h, qm, v)) continue;
     rc.out[size_t(n1 / uint32_t(rc.interval) - 1) * size_t(sim.nx) + c] = v;
   }
 }
+
+template <typename R>
+__device__ __forceinline__ void record_fields(const DevSim &sim, int c, uint32_t n1, R e, R h, bool qm, int rb,
+                                              int re) {
+  for (int32_t r = rb; r < re; ++r) {
+    const DevRecord &rc = sim.rec_cell[r];
+    double v;
+    if (!due(n1, rc.interval) || !field_value(rc.quantity, e, h, qm, v)) continue;
+    rc.out[n1 / uint32_t(rc.interval) - 1] = v;
+  }
+  record_fields_all(sim, c, n1, e, h, qm);
+}
+
+// Single-cell records of one tile's owned cells, copied to LDS at the start
+// of a launch together with the readout row of each record's cell, so that a
+// recording step reads no record descriptors from global memory.
+constexpr int kTileRecs = 16;
+
+template <int N>
+struct TileRecs {
+  static constexpr int RO = mat_m(N) + 1;
+  double *out[kTileRecs];
+  uint32_t interval[kTileRecs];
+  int32_t quantity[kTileRecs];
+  double ro[kTileRecs][RO];
+
+  // entry i <- record table entry r (one thread per entry)
+  __device__ __forceinline__ void stage(const DevSim &sim, int i, int r) {
+    const DevRecord &rc = sim.rec_cell[r];
+    out[i] = rc.out;
+    interval[i] = uint32_t(rc.interval);
+    quantity[i] = rc.quantity;
+    if (rc.quantity >= 2 && rc.readout) {
+      const double *row = rc.readout + int(sim.mat_e[rc.cell]) * RO;
+      for (int a = 0; a < RO; ++a) ro[i][a] = row[a];
+    }
+  }
+
+  // same arithmetic as Cell::readout
+  template <typename R, int MA>
+  __device__ __forceinline__ void density(uint32_t n1, const R (&y)[MA], int rb, int re) const {
+    for (int r = rb; r < re; ++r) {
+      const uint32_t iv = interval[r];
+      if (quantity[r] < 2 || n1 % iv != 0u) continue;
+      double acc = ro[r][0];
+#pragma unroll
+      for (int j = 0; j < RO - 1; ++j) acc = fma(ro[r][1 + j], double(y[j]), acc);
+      out[r][n1 / iv - 1] = acc;
+    }
+  }
+
+  template <typename R>
+  __device__ __forceinline__ void fields(uint32_t n1, R e, R h, bool qm, int rb, int re) const {
+    for (int r = rb; r < re; ++r) {
+      const uint32_t iv = interval[r];
+      double v;
+      if (n1 % iv != 0u || !field_value(quantity[r], e, h, qm, v)) continue;
+      out[r][n1 / iv - 1] = v;
+    }
+  }
+};
 
 // the cell's entries [rb, re) in the per-cell record table
 __device__ __forceinline__ void record_range(const DevSim &sim, int c, int &rb, int &re) {
@@ -339,9 +403,25 @@ __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
                                    (sim.edge_r == 1 && lo <= nx - 1 && nx - 1 < lo + B));
   const bool mur_l = left && sim.edge_l == 1, mur_r = right && sim.edge_r == 1;
   const bool pec = (left && sim.edge_l == 0) || (right && sim.edge_r == 0);
-  // the cell's entries in the per-cell record table, fetched once per launch
+  // the cell's entries in the per-cell record table, fetched once per launch;
+  // when the tile's owned cells hold at most kTileRecs entries they are
+  // staged in LDS (visible after the first barrier) and [rb, re) index there
+  __shared__ TileRecs<N> trec;
   int rb = 0, re = 0;
-  if (own && sim.n_rec > 0) record_range(sim, c, rb, re);
+  bool rec_lds = false;
+  if (sim.rec_first) {
+    const int o0 = tile.c0, o1 = min(tile.c0 + B - 2 * halo, nx);
+    const int rbase = sim.rec_first[o0], n_tr = sim.rec_first[o1] - rbase;
+    rec_lds = n_tr <= kTileRecs;
+    if (rec_lds && l < n_tr) trec.stage(sim, l, rbase + l);
+    if (own) {
+      record_range(sim, c, rb, re);
+      if (rec_lds) {
+        rb -= rbase;
+        re -= rbase;
+      }
+    }
+  }
   const bool rec_here = own && (re > rb || sim.n_rec_all > 0);
   const uint32_t rec_every = uint32_t(sim.rec_every);
   const R kap_l = R(sim.kap_l), kap_r = R(sim.kap_r);
@@ -359,6 +439,10 @@ __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
         const cptr<R> mt0 = mtab + __builtin_amdgcn_readfirstlane(mm0 * S);
 #pragma unroll
         for (int i = 0; i < SQ; ++i) cf[i] = mt0[kCoefKap + i];
+        // opaque register copies: keeps the compiler from re-loading the
+        // coefficients from constant memory inside the step loop
+#pragma unroll
+        for (int i = 0; i < SQ; ++i) asm volatile("" : "+v"(cf[i]));
       }
     }
   }
@@ -383,7 +467,14 @@ __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
       auto density = [&](const auto &mt, int mm) {
         CL::rotate(x, e, mt);
         p = CL::polar(x, mt);
-        if (rec_now) record_density<N, R>(sim, c, n1, mm, x, rb, re);
+        if (rec_now) {
+          if (rec_lds) {
+            trec.density(n1, x, rb, re);
+            record_density_all<N, R>(sim, c, n1, mm, x);
+          } else {
+            record_density<N, R>(sim, c, n1, mm, x, rb, re);
+          }
+        }
         CL::propagate(x, mt);
       };
       if (VC && wave_uni) {
@@ -436,7 +527,12 @@ __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
       }
     }
     if (rec_now) {
-      record_fields(sim, c, n1, e, hcell ? h : R(0), qm, rb, re);
+      if (rec_lds) {
+        trec.fields(n1, e, hcell ? h : R(0), qm, rb, re);
+        record_fields_all(sim, c, n1, e, hcell ? h : R(0), qm);
+      } else {
+        record_fields(sim, c, n1, e, hcell ? h : R(0), qm, rb, re);
+      }
     }
   }
   if (own) {
