@@ -271,6 +271,7 @@ def main(argv=None):
     ap.add_argument("--nt", type=int, default=200000)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--depth", type=int, default=0)
+    ap.add_argument("--lanes", type=int, default=0, help="waves per 64 cells (1, 2, 4; 0 = tuned)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -304,12 +305,13 @@ def main(argv=None):
 
     # ---- main leg: FP32 temporally blocked -------------------------------------------
     log(f"[bench] lambda3 fp32 blocked nx={prob['nx']} nt={prob['n_steps']}")
-    variant = "blocked" if (args.block or args.depth) else "auto"
+    variant = "blocked" if (args.block or args.depth or args.lanes) else "auto"
     t_setup = time.perf_counter()
-    s32 = mb.Solver(prob, precision=32, variant=variant, block=args.block, depth=args.depth)
+    s32 = mb.Solver(prob, precision=32, variant=variant, block=args.block, depth=args.depth, lanes=args.lanes)
     t_setup = time.perf_counter() - t_setup
-    block, depth, regs = s32.shape()
-    log(f"[bench] tile shape block={block} depth={depth} regs={regs} (setup incl. tuning {t_setup:.2f} s)")
+    block, depth, regs, lanes = s32.shape()
+    log(f"[bench] tile shape block={block} depth={depth} regs={regs} lanes={lanes} "
+        f"(setup incl. tuning {t_setup:.2f} s)")
     n_launch = math.ceil(prob["n_steps"] / depth)
     wall, dev_ms = timed_solves(hip, stream, s32, args.steps, args.warmup, n_launch)
     rec32 = s32.records()
@@ -320,7 +322,7 @@ def main(argv=None):
     eff_gbs = bytes_per_cell_update(n_levels, 32) * cells / (float(np.mean(dev_ms)) * 1e-3) / 1e9
     log(f"[bench] fp32 blocked: {value:.3e} cell-updates/s, kernel {avg_kernel_us:.2f} us")
 
-    kname = f"k_blocked<3,float,{block},{str(regs).lower()}>"
+    kname = f"k_blocked<3,float,{block},{lanes},{str(regs).lower()}>"
     traffic = measured_traffic(kname, f"lambda3-3lvl/nx{prob['nx']}", depth)
     out = {
         "metric": "cell-updates/s (FP64 plain vs FP32 batched) at stated error; p50/p99 solve latency",
@@ -329,7 +331,7 @@ def main(argv=None):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "lambda3-3lvl", "nx": prob["nx"], "n_steps": prob["n_steps"], "levels": 3,
                    "materials": len(prob["materials"]), "records": len(prob["records"]),
-                   "variant": "blocked", "block": block, "depth": depth, "regs": regs, "setup_s": t_setup,
+                   "variant": "blocked", "block": block, "depth": depth, "regs": regs, "lanes": lanes, "setup_s": t_setup,
                    "step": "one full solve of the workload"},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK["fp32_tflops"],
                      "unit": "TFLOP/s", "frac": achieved_tflops / PEAK["fp32_tflops"], "traffic": traffic,
@@ -344,8 +346,9 @@ def main(argv=None):
     rec64 = None
     if not args.no_fp64:
         log("[bench] lambda3 fp64 blocked")
-        s64 = mb.Solver(prob, precision=64, variant=variant, block=args.block, depth=args.depth)
-        b64, k64, r64 = s64.shape()
+        s64 = mb.Solver(prob, precision=64, variant=variant, block=args.block, depth=args.depth,
+                        lanes=args.lanes)
+        b64, k64, r64, l64 = s64.shape()
         w64, d64 = timed_solves(hip, stream, s64, 1, 1, math.ceil(prob["n_steps"] / k64))
         rec64 = s64.records()
         s64.close()
@@ -359,7 +362,7 @@ def main(argv=None):
         sp.close()
         same = all(np.array_equal(recp[k], rec64[k]) for k in rec64)
         out["fp64_blocked"] = {"value": cells / w64, "unit": "cell-updates/s", "device_ms": d64[0],
-                               "block": b64, "depth": k64, "regs": r64}
+                               "block": b64, "depth": k64, "regs": r64, "lanes": l64}
         out["fp64_plain"] = {"value": cells / wp, "unit": "cell-updates/s", "wall_s": wp,
                              "bitwise_equal_to_fp64_blocked": bool(same)}
         out["fp32_vs_fp64_full_run_max_rel_err"] = rel_err(prob, rec32, rec64)
@@ -383,7 +386,7 @@ def main(argv=None):
         sims = W.sweep(n_sims=256, precision=32)
         bcells = sum(p["nx"] * p["n_steps"] for p in sims)
         bt = mb.Batch(sims, precision=32, variant="auto")
-        bblock, bdepth, bregs = bt.shape()
+        bblock, bdepth, bregs, blanes = bt.shape()
         bt.run(stream=stream, use_graph=True)
         hip.sync()
         bt.reset(stream)
@@ -396,7 +399,8 @@ def main(argv=None):
                    for k, p in enumerate(sims)) / tb / 1e9
         out["batched_sweep"] = {"value": bcells / tb, "unit": "cell-updates/s", "sims": len(sims),
                                 "cell_updates": bcells, "wall_s": tb, "hbm_effective_gbs": beff,
-                                "hbm_effective_frac": beff / PEAK["hbm_gbs"], "block": bblock, "depth": bdepth, "regs": bregs}
+                                "hbm_effective_frac": beff / PEAK["hbm_gbs"], "block": bblock, "depth": bdepth, "regs": bregs,
+                                "lanes": blanes}
         bt.close()
 
     # ---- other configurations --------------------------------------------------------

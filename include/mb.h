@@ -152,8 +152,11 @@ typedef struct mb_scenario_desc {
   int64_t n_steps;
   int32_t precision;         /* 64 or 32: arithmetic of the bulk field and density updates */
   int32_t variant;           /* MB_VARIANT_* */
-  int32_t block;             /* blocked variant: threads per tile (0 = default) */
+  int32_t block;             /* blocked variant: cells per tile (0 = default) */
   int32_t depth;             /* blocked variant: steps per launch = halo width (0 = default) */
+  int32_t lanes;             /* blocked variant: waves per 64 cells that share each cell's
+                                density update, 1, 2 or 4 (0 = default); results do not
+                                depend on it */
   const double *rho_diag;    /* N reals: initial density matrix (ic_density_const) */
   const double *rho_off;     /* N(N-1)/2 complex (re, im) */
   const double *e_init;      /* nx initial E values, or NULL for zero */
@@ -220,13 +223,14 @@ int mb_reset(mb_handle *h, void *hip_stream);
 /* Steps done so far. */
 int64_t mb_steps_done(const mb_handle *h);
 
-/* Tile shape in use: threads per tile, steps per launch (1 for the two-launch
- * variant) and whether coefficients are held in registers.  With
- * MB_VARIANT_AUTO and block = depth = 0 the shape is chosen at setup by timing
+/* Tile shape in use: cells per tile, steps per launch (1 for the two-launch
+ * variant), whether coefficients are held in registers and the waves per 64
+ * cells (a level count whose kernel is not built for that many uses fewer).  With
+ * MB_VARIANT_AUTO and block = depth = lanes = 0 the shape is chosen at setup by timing
  * candidate shapes on this simulation (cached per device architecture, level
  * count, precision and size class; the cache file is $MB_TUNE_CACHE or
  * ~/.cache/mbhip_tune.txt).  Any pointer may be NULL. */
-int mb_shape(const mb_handle *h, int32_t *block, int32_t *depth, int32_t *regs);
+int mb_shape(const mb_handle *h, int32_t *block, int32_t *depth, int32_t *regs, int32_t *lanes);
 
 /* Samples recorded so far for record `record_id` (per-sample width 1 or nx). */
 int mb_record_shape(const mb_handle *h, int record_id, int64_t *n_samples, int64_t *width);
@@ -261,7 +265,7 @@ int mb_batch_run(mb_batch *b, void *hip_stream, int32_t use_graph);
 /* Restores every member's initial state and clears the records (as mb_reset). */
 int mb_batch_reset(mb_batch *b, void *hip_stream);
 /* Tile shape in use (as mb_shape; tuned over the whole batch). */
-int mb_batch_shape(const mb_batch *b, int32_t *block, int32_t *depth, int32_t *regs);
+int mb_batch_shape(const mb_batch *b, int32_t *block, int32_t *depth, int32_t *regs, int32_t *lanes);
 int mb_batch_record_shape(const mb_batch *b, int32_t sim, int record_id, int64_t *n_samples,
                           int64_t *width);
 int mb_batch_read_records(mb_batch *b, int32_t sim, int record_id, double *out,

@@ -91,7 +91,7 @@ class mb_consts(C.Structure):
 class mb_scenario_desc(C.Structure):
     _fields_ = [("nx", C.c_int64), ("dt", C.c_double), ("n_steps", C.c_int64),
                 ("precision", C.c_int32), ("variant", C.c_int32), ("block", C.c_int32),
-                ("depth", C.c_int32), ("rho_diag", C.POINTER(C.c_double)),
+                ("depth", C.c_int32), ("lanes", C.c_int32), ("rho_diag", C.POINTER(C.c_double)),
                 ("rho_off", C.POINTER(C.c_double)), ("e_init", C.POINTER(C.c_double)),
                 ("n_sources", C.c_int32), ("sources", C.POINTER(mb_source)),
                 ("n_records", C.c_int32), ("records", C.POINTER(mb_record)), ("consts", mb_consts)]
@@ -122,8 +122,8 @@ def load():
         "mb_run": (C.c_int, [P, C.c_int64, P]),
         "mb_reset": (C.c_int, [P, P]),
         "mb_batch_reset": (C.c_int, [P, P]),
-        "mb_shape": (C.c_int, [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
-        "mb_batch_shape": (C.c_int, [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+        "mb_shape": (C.c_int, [P] + [C.POINTER(C.c_int32)] * 4),
+        "mb_batch_shape": (C.c_int, [P] + [C.POINTER(C.c_int32)] * 4),
         "mb_steps_done": (C.c_int64, [P]),
         "mb_record_shape": (C.c_int, [P, C.c_int, i64p, i64p]),
         "mb_read_records": (C.c_int, [P, C.c_int, dp, C.c_int64, i64p]),
@@ -179,7 +179,7 @@ def _complex_pairs(v):
 class _Marshal:
     """Keeps the ctypes structs of one problem and the arrays they point to alive."""
 
-    def __init__(self, prob, precision=None, variant="auto", block=0, depth=0):
+    def __init__(self, prob, precision=None, variant="auto", block=0, depth=0, lanes=0):
         keep = []
         self.keep = keep
 
@@ -238,7 +238,7 @@ class _Marshal:
         sc.nx, sc.dt, sc.n_steps = prob["nx"], prob["dt"], prob["n_steps"]
         sc.precision = prob["precision"] if precision is None else precision
         sc.variant = VARIANT[variant]
-        sc.block, sc.depth = block, depth
+        sc.block, sc.depth, sc.lanes = block, depth, lanes
         sc.rho_diag = arr(prob["rho_diag"])
         sc.rho_off = arr(_complex_pairs(prob["rho_off"])) if len(prob["rho_off"]) else arr(np.zeros(1))
         sc.e_init = None if prob["e_init"] is None else arr(prob["e_init"])
@@ -310,10 +310,10 @@ def plan_status(prob):
 class Solver:
     """One simulation resident on the GPU (mb_setup / mb_run / mb_read_records)."""
 
-    def __init__(self, prob, device=0, precision=None, variant="auto", block=0, depth=0):
+    def __init__(self, prob, device=0, precision=None, variant="auto", block=0, depth=0, lanes=0):
         lib = load()
         self.prob = prob
-        self._m = _Marshal(prob, precision, variant, block, depth)
+        self._m = _Marshal(prob, precision, variant, block, depth, lanes)
         h = C.c_void_p()
         self.warning = _check(lib.mb_setup(device, C.byref(self._m.dev), C.byref(self._m.scen), C.byref(h)))
         self._h = h
@@ -327,10 +327,10 @@ class Solver:
         return self
 
     def shape(self):
-        """(threads per tile, steps per launch, coefficients in registers)."""
-        b, d, r = C.c_int32(), C.c_int32(), C.c_int32()
-        _check(load().mb_shape(self._h, C.byref(b), C.byref(d), C.byref(r)))
-        return b.value, d.value, bool(r.value)
+        """(cells per tile, steps per launch, coefficients in registers, waves per 64 cells)."""
+        b, d, r, n = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(load().mb_shape(self._h, C.byref(b), C.byref(d), C.byref(r), C.byref(n)))
+        return b.value, d.value, bool(r.value), n.value
 
     @property
     def steps_done(self):
@@ -387,10 +387,10 @@ def _levels(prob):
 class Batch:
     """Many independent simulations advanced together (mb_batch_*)."""
 
-    def __init__(self, probs, device=0, precision=None, variant="auto", block=0, depth=0):
+    def __init__(self, probs, device=0, precision=None, variant="auto", block=0, depth=0, lanes=0):
         lib = load()
         self.probs = list(probs)
-        self._ms = [_Marshal(p, precision, variant, block, depth) for p in self.probs]
+        self._ms = [_Marshal(p, precision, variant, block, depth, lanes) for p in self.probs]
         n = len(self.probs)
         devs = (mb_device_desc * n)(*[m.dev for m in self._ms])
         scens = (mb_scenario_desc * n)(*[m.scen for m in self._ms])
@@ -408,10 +408,10 @@ class Batch:
         return self
 
     def shape(self):
-        """(threads per tile, steps per launch, coefficients in registers)."""
-        b, d, r = C.c_int32(), C.c_int32(), C.c_int32()
-        _check(load().mb_batch_shape(self._h, C.byref(b), C.byref(d), C.byref(r)))
-        return b.value, d.value, bool(r.value)
+        """(cells per tile, steps per launch, coefficients in registers, waves per 64 cells)."""
+        b, d, r, n = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(load().mb_batch_shape(self._h, C.byref(b), C.byref(d), C.byref(r), C.byref(n)))
+        return b.value, d.value, bool(r.value), n.value
 
     def record(self, sim, k):
         lib = load()

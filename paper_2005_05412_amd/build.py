@@ -12,7 +12,9 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libmbhip.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "plan.cpp", "runtime.cpp", "tune.cpp", "abi.cpp", "server.cpp"]
+# (source, extra flags, object name): the kernels are compiled in two parts
+SOURCES = [("kernels.hip", ["-DMB_PART=1"], "kernels_f32"), ("kernels.hip", ["-DMB_PART=2"], "kernels_f64")] + [
+    (f, [], f) for f in ("plan.cpp", "runtime.cpp", "tune.cpp", "abi.cpp", "server.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("MB_OFFLOAD_ARCH", "gfx950")
 
@@ -21,11 +23,13 @@ COMMON = ["-std=c++17", "-O3", "-fPIC", "-ffp-contract=off", f"-I{INCLUDE}", f"-
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OBJ, src + ".o")
-    cmd = [HIPCC] + COMMON + DEVICE + ["-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(item) -> str:
+    src, extra, name = item
+    obj = os.path.join(OBJ, name + ".o")
+    cmd = [HIPCC] + COMMON + DEVICE + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
     if not src.endswith(".hip"):
-        cmd = [HIPCC] + COMMON + ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC] + COMMON + extra + ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-c",
+                                          os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)

@@ -144,10 +144,12 @@ int hip_fail(hipError_t e, const char *what) {
   return fail(MB_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-int shape_for(const SimPlan &p, int &block, int &halo) {
+int shape_for(const SimPlan &p, int &block, int &halo, int &lanes) {
   default_shape(p.n, p.precision, block, halo);
+  lanes = 1;
   if (p.block > 0) block = p.block;
   if (p.depth > 0) halo = p.depth;
+  if (p.lanes > 0) lanes = p.lanes;
   if (p.variant == MB_VARIANT_PLAIN) return MB_OK;
   if (!block_supported(block) || halo < 1 || 2 * halo >= block)
     return fail(MB_ERR_ARG, "blocked variant needs block in {64,...,1024} and 1 <= depth < block/2");
@@ -234,21 +236,22 @@ int mb_setup(int hip_device, const mb_device_desc *dev, const mb_scenario_desc *
   int rc = build_plan(dev, scen, plan, err);
   if (rc < 0) return fail(rc, err);
   int warn = rc;
-  int block = 0, halo = 0;
+  int block = 0, halo = 0, lanes = 1;
   bool vc = plan.variant == MB_VARIANT_BLOCKED_REGS;
-  if ((rc = shape_for(plan, block, halo)) < 0) return rc;
-  if (plan.variant == MB_VARIANT_AUTO && plan.block == 0 && plan.depth == 0) {
+  if ((rc = shape_for(plan, block, halo, lanes)) < 0) return rc;
+  if (plan.variant == MB_VARIANT_AUTO && plan.block == 0 && plan.depth == 0 && plan.lanes == 0) {
     if (hipSetDevice(hip_device) != hipSuccess) return fail(MB_ERR_HIP, "hipSetDevice failed");
     Shape sh;
     if ((rc = tune_shape(hip_device, {&plan}, plan.precision, sh, err)) < 0) return fail(rc, err);
     block = sh.block;
     halo = sh.halo;
     vc = sh.vc;
+    lanes = sh.lanes;
   }
   auto h = std::make_unique<mb_handle>();
   h->device = hip_device;
   int variant = plan.variant == MB_VARIANT_PLAIN ? MB_VARIANT_PLAIN : MB_VARIANT_BLOCKED;
-  h->eng = std::make_unique<Engine>(hip_device, plan.precision, variant, block, halo, vc);
+  h->eng = std::make_unique<Engine>(hip_device, plan.precision, variant, block, halo, vc, lanes);
   if ((rc = h->eng->init(err)) < 0) return fail(rc, err);
   hipStream_t st = nullptr;
   int id = h->eng->add(std::move(plan), nullptr, st, err);
@@ -301,21 +304,23 @@ int mb_reset(mb_handle *h, void *hip_stream) {
 
 int64_t mb_steps_done(const mb_handle *h) { return h ? h->eng->sim(h->id).done : -1; }
 
-int mb_shape(const mb_handle *h, int32_t *block, int32_t *depth, int32_t *regs) {
+int mb_shape(const mb_handle *h, int32_t *block, int32_t *depth, int32_t *regs, int32_t *lanes) {
   if (!h) return fail(MB_ERR_ARG, "null handle");
   const bool plain = h->eng->variant() == MB_VARIANT_PLAIN;
   if (block) *block = plain ? plain_block() : h->eng->block();
   if (depth) *depth = plain ? 1 : h->eng->chunk_steps();
   if (regs) *regs = h->eng->vc() ? 1 : 0;
+  if (lanes) *lanes = plain ? 1 : h->eng->lanes();
   return MB_OK;
 }
 
-int mb_batch_shape(const mb_batch *b, int32_t *block, int32_t *depth, int32_t *regs) {
+int mb_batch_shape(const mb_batch *b, int32_t *block, int32_t *depth, int32_t *regs, int32_t *lanes) {
   if (!b) return fail(MB_ERR_ARG, "null batch");
   const bool plain = b->eng->variant() == MB_VARIANT_PLAIN;
   if (block) *block = plain ? plain_block() : b->eng->block();
   if (depth) *depth = plain ? 1 : b->eng->chunk_steps();
   if (regs) *regs = b->eng->vc() ? 1 : 0;
+  if (lanes) *lanes = plain ? 1 : b->eng->lanes();
   return MB_OK;
 }
 
@@ -393,7 +398,7 @@ int mb_batch_setup(int hip_device, int32_t n, const mb_device_desc *devs, const 
     if (plans[i].precision != plans[0].precision || (plans[i].variant == MB_VARIANT_PLAIN) != (plans[0].variant == MB_VARIANT_PLAIN))
       return fail(MB_ERR_ARG, "batch members must share precision and variant");
   }
-  int block = 0, halo = 0, rc;
+  int block = 0, halo = 0, lanes = 1, rc;
   bool vc = plans[0].variant == MB_VARIANT_BLOCKED_REGS;
   int nmax = 0;
   for (auto &p : plans) nmax = std::max(nmax, p.n);
@@ -403,8 +408,9 @@ int mb_batch_setup(int hip_device, int32_t n, const mb_device_desc *devs, const 
   probe.variant = plans[0].variant;
   probe.block = plans[0].block;
   probe.depth = plans[0].depth;
-  if ((rc = shape_for(probe, block, halo)) < 0) return rc;
-  if (probe.variant == MB_VARIANT_AUTO && probe.block == 0 && probe.depth == 0) {
+  probe.lanes = plans[0].lanes;
+  if ((rc = shape_for(probe, block, halo, lanes)) < 0) return rc;
+  if (probe.variant == MB_VARIANT_AUTO && probe.block == 0 && probe.depth == 0 && probe.lanes == 0) {
     if (hipSetDevice(hip_device) != hipSuccess) return fail(MB_ERR_HIP, "hipSetDevice failed");
     std::vector<const SimPlan *> ptrs;
     for (auto &p : plans) ptrs.push_back(&p);
@@ -413,11 +419,12 @@ int mb_batch_setup(int hip_device, int32_t n, const mb_device_desc *devs, const 
     block = sh.block;
     halo = sh.halo;
     vc = sh.vc;
+    lanes = sh.lanes;
   }
   auto b = std::make_unique<mb_batch>();
   b->device = hip_device;
   int variant = plans[0].variant == MB_VARIANT_PLAIN ? MB_VARIANT_PLAIN : MB_VARIANT_BLOCKED;
-  b->eng = std::make_unique<Engine>(hip_device, plans[0].precision, variant, block, halo, vc);
+  b->eng = std::make_unique<Engine>(hip_device, plans[0].precision, variant, block, halo, vc, lanes);
   if ((rc = b->eng->init(err)) < 0) return fail(rc, err);
   for (int i = 0; i < n; ++i) {
     int id = b->eng->add(std::move(plans[i]), nullptr, nullptr, err);

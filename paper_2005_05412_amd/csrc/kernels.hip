@@ -8,6 +8,8 @@
 // (the host rejects grids where M * nx or the step count reach 2^31).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "engine.hpp"
 #include "launch.hpp"
 
@@ -94,6 +96,31 @@ __device__ __forceinline__ void phase(float t, float &cm, float &sn) {
   }
 }
 
+// Split of one cell's density update over L waves (wave group s of L owns
+// a subset of the M state rows): coherence pairs (two rows each) are dealt
+// round-robin, then populations go one by one to the least-loaded group.
+template <int N, int L>
+struct Split {
+  static constexpr int M = mat_m(N);
+  static constexpr int P = N > 0 ? N * (N - 1) / 2 : 0;
+  static constexpr int owner(int a) {
+    if (L == 1) return 0;
+    if (a >= N - 1) return ((a - (N - 1)) / 2) % L;
+    int load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int q = 0; q < P; ++q) load[q % L] += 2;
+    int who = 0;
+    for (int u = 0; u <= a; ++u) {
+      int best = 0;
+      for (int g = 1; g < L; ++g)
+        if (load[g] < load[best]) best = g;
+      load[best] += 1;
+      who = best;
+    }
+    return who;
+  }
+  static constexpr bool owns(int sub, int a) { return L == 1 || owner(a) == sub; }
+};
+
 template <int N, typename R>
 struct Cell {
   static constexpr int M = mat_m(N);
@@ -103,7 +130,9 @@ struct Cell {
   // eigen-basis gains the phase theta_jk = dt E (lam_j - lam_k)/hbar, the
   // sum of the consecutive angles E kappa_q; each phase is carried as
   // (cos - 1, sin) and applied as a small increment.
-  template <typename C>
+  // (with L > 1 only the coherences of rows owned by group SUB are rotated;
+  // the composed phases are the same for every split)
+  template <int L = 1, int SUB = 0, typename C>
   static __device__ __forceinline__ void rotate(R (&y)[MA], R e, const C &mt) {
     if constexpr (N >= 2) {
       R cm[N - 1], sn[N - 1];
@@ -124,9 +153,11 @@ struct Cell {
           }
           const int p = k * (k - 1) / 2 + j;
           const int ir = N - 1 + 2 * p, ii = ir + 1;
-          const R re = y[ir], im = y[ii];
-          y[ir] = re + fma(re, pc, -(im * ps));
-          y[ii] = im + fma(re, ps, im * pc);
+          if (Split<N, L>::owns(SUB, ir)) {
+            const R re = y[ir], im = y[ii];
+            y[ir] = re + fma(re, pc, -(im * ps));
+            y[ii] = im + fma(re, ps, im * pc);
+          }
         }
       }
     }
@@ -146,19 +177,22 @@ struct Cell {
     return acc0 + acc1;
   }
 
-  // sigma_{n+1} = e^{L0 dt} y = y + (bf + am y)
-  template <typename C>
+  // sigma_{n+1} = e^{L0 dt} y = y + (bf + am y); with L > 1 the rows owned
+  // by group SUB (the others are left as they are)
+  template <int L = 1, int SUB = 0, typename C>
   static __device__ __forceinline__ void propagate(R (&y)[MA], const C &mt) {
     R out[MA];
 #pragma unroll
     for (int i = 0; i < M; ++i) {
+      if (!Split<N, L>::owns(SUB, i)) continue;
       R acc = mt[coef_bf(N) + i];
 #pragma unroll
       for (int j = 0; j < M; ++j) acc = fma(mt[coef_am(N) + i * M + j], y[j], acc);
       out[i] = y[i] + acc;
     }
 #pragma unroll
-    for (int i = 0; i < M; ++i) y[i] = out[i];
+    for (int i = 0; i < M; ++i)
+      if (Split<N, L>::owns(SUB, i)) y[i] = out[i];
   }
 
   static __device__ __forceinline__ double readout(const R (&y)[MA], const double *__restrict__ ro) {
@@ -313,19 +347,38 @@ __device__ __forceinline__ R apply_sources(const DevSim &sim, int c, uint32_t n1
 // advances up to k <= halo steps with neighbour values exchanged through LDS
 // (the valid region shrinks by one cell per side and step, as the redundant
 // computation of overlapped tiles), and writes the owned cells to the other
-// state buffer.
+// state buffer.  With L > 1 the workgroup holds L waves per 64 cells: every
+// wave group keeps E and H of all B cells (the field updates are repeated)
+// and advances only its own rows of the density state; the rotated rows are
+// exchanged through LDS once per step, so each group sees the whole state for
+// the polarization, the records and its rows of the propagator.  The
+// arithmetic per cell is the same for every B, L and coefficient placement.
 // ---------------------------------------------------------------------------
-template <int N, typename R, int B, bool VC>
-__global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
-                                               const DevTile *__restrict__ tiles, int64_t n0, int parity,
-                                               int halo, int k) {
+template <int N, typename R, int B, int L>
+struct TileShared {
+  static constexpr int GM = L > 1 ? mat_m(N) : 1;
+  static constexpr int GB = L > 1 ? B : 1;
+  R se[B], sh[B], se2[B];
+  R src[kTileSources][kMaxChunk];
+  TileRecs<N> trec;
+  R sy[GM][GB];  // rotated density rows of every cell (L > 1)
+};
+
+// split tiles stay at <= 512 threads: a 1024-thread workgroup caps a wave at
+// 128 registers, below what the density update needs
+template <int N, typename R, int B, int L>
+constexpr bool shape_fits() {
+  return (L == 1 || (N >= 2 && B * L <= 512)) && sizeof(TileShared<N, R, B, L>) <= 65536;
+}
+
+template <int N, typename R, int B, int L, bool VC, int SUB>
+__device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, const DevTile *__restrict__ tiles,
+                                           int64_t n0, int parity, int halo, int k, TileShared<N, R, B, L> &sm) {
   using CL = Cell<N, R>;
+  using SP = Split<N, L>;
   constexpr int M = CL::M, MA = CL::MA, S = mat_stride(N);
-  constexpr bool WAVE = B == 64;           // one wave per tile: neighbours by DPP, no barriers
-  constexpr int LB = WAVE ? 1 : B;
-  constexpr int SQ = S - kCoefKap;         // quantum part of a material's coefficients
-  __shared__ R se[LB], sh[LB], se2[LB];
-  __shared__ R s_src[kTileSources][kMaxChunk];
+  constexpr bool WAVE = B == 64 && L == 1;  // one wave per tile: neighbours by DPP, no barriers
+  constexpr int SQ = S - kCoefKap;          // quantum part of a material's coefficients
   const DevTile tile = tiles[blockIdx.x];
   // fields used inside the step loop are copied to locals below, so stores to
   // records cannot force them to be reloaded
@@ -340,7 +393,7 @@ __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
   const R *__restrict__ h_in = static_cast<const R *>(sim.h[par]);
   const R *__restrict__ x_in = static_cast<const R *>(sim.x[par]);
   const cptr<R> mtab = kconst<R>(sim.mtab);
-  const int l = threadIdx.x;
+  const int l = int(threadIdx.x) - SUB * B;  // cell lane
   const int lo = tile.c0 - halo;
   const int c = lo + l;
   const bool in = c >= 0 && c < nx;
@@ -364,7 +417,8 @@ __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
       qm = mtab[me * S + kCoefQM] != R(0);
       if (qm) {
 #pragma unroll
-        for (int a = 0; a < M; ++a) x[a] = x_in[a * nx + c];
+        for (int a = 0; a < M; ++a)
+          if (SP::owns(SUB, a)) x[a] = x_in[a * nx + c];
       }
     }
   }
@@ -387,7 +441,7 @@ __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
       src_direct = true;
       break;
     }
-    for (int q = l; q < ks; q += B) s_src[n_ts][q] = R(sj.table[ls0 + q + 1]);
+    for (int q = int(threadIdx.x); q < ks; q += B * L) sm.src[n_ts][q] = R(sj.table[ls0 + q + 1]);
 #pragma unroll
     for (int t = 0; t < kTileSources; ++t)
       if (t == n_ts) {
@@ -405,16 +459,16 @@ __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
   const bool pec = (left && sim.edge_l == 0) || (right && sim.edge_r == 0);
   // the cell's entries in the per-cell record table, fetched once per launch;
   // when the tile's owned cells hold at most kTileRecs entries they are
-  // staged in LDS (visible after the first barrier) and [rb, re) index there
-  __shared__ TileRecs<N> trec;
+  // staged in LDS (visible after the first barrier) and [rb, re) index there.
+  // Records are written by the first wave group only.
   int rb = 0, re = 0;
   bool rec_lds = false;
   if (sim.rec_first) {
     const int o0 = tile.c0, o1 = min(tile.c0 + B - 2 * halo, nx);
     const int rbase = sim.rec_first[o0], n_tr = sim.rec_first[o1] - rbase;
     rec_lds = n_tr <= kTileRecs;
-    if (rec_lds && l < n_tr) trec.stage(sim, l, rbase + l);
-    if (own) {
+    if (rec_lds && int(threadIdx.x) < n_tr) sm.trec.stage(sim, int(threadIdx.x), rbase + int(threadIdx.x));
+    if (own && SUB == 0) {
       record_range(sim, c, rb, re);
       if (rec_lds) {
         rb -= rbase;
@@ -422,11 +476,18 @@ __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
       }
     }
   }
-  const bool rec_here = own && (re > rb || sim.n_rec_all > 0);
+  const bool rec_here = SUB == 0 && own && (re > rb || sim.n_rec_all > 0);
   const uint32_t rec_every = uint32_t(sim.rec_every);
   const R kap_l = R(sim.kap_l), kap_r = R(sim.kap_r);
 
   // coefficients of a single-material wave held in registers for the launch
+  // (those this wave group reads: phases, polarization, its propagator rows)
+  auto coef_used = [](int i) {
+    const int t = i + kCoefKap;
+    if (t < coef_bf(N)) return true;
+    if (t < coef_am(N)) return SP::owns(SUB, t - coef_bf(N));
+    return SP::owns(SUB, (t - coef_am(N)) / (M > 0 ? M : 1));
+  };
   R cf[VC ? SQ : 1];
   bool wave_uni = false;
   int mm0 = 0;
@@ -438,15 +499,34 @@ __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
       if (wave_uni) {
         const cptr<R> mt0 = mtab + __builtin_amdgcn_readfirstlane(mm0 * S);
 #pragma unroll
-        for (int i = 0; i < SQ; ++i) cf[i] = mt0[kCoefKap + i];
+        for (int i = 0; i < SQ; ++i)
+          if (coef_used(i)) cf[i] = mt0[kCoefKap + i];
         // opaque register copies: keeps the compiler from re-loading the
         // coefficients from constant memory inside the step loop
 #pragma unroll
-        for (int i = 0; i < SQ; ++i) asm volatile("" : "+v"(cf[i]));
+        for (int i = 0; i < SQ; ++i)
+          if (coef_used(i)) asm volatile("" : "+v"(cf[i]));
       }
     }
   }
-  if constexpr (WAVE) __syncthreads();  // staged source values visible
+  if constexpr (WAVE) __syncthreads();  // staged source values and records visible
+
+  // runs f(coefficients, material) once per material present among the
+  // wave's quantum cells, for the lanes of that material
+  auto per_material = [&](auto &&f) {
+    if (VC && wave_uni) {
+      if (qm) f(RegCoef<R, VC ? SQ : 1>{cf}, mm0);
+    } else {
+      uint64_t todo = __ballot(qm);
+      while (todo) {
+        const int lead = __ffsll(static_cast<unsigned long long>(todo)) - 1;
+        const int mm = __builtin_amdgcn_readlane(me, lead);
+        const bool mine = qm && me == mm;
+        if (mine) f(mtab + __builtin_amdgcn_readfirstlane(mm * S), mm);  // uniform: scalar loads
+        todo &= ~__ballot(mine);
+      }
+    }
+  };
 
   for (int s = 0; s < ks; ++s) {
     const uint32_t n1 = uint32_t(ls0 + s + 1);
@@ -456,47 +536,57 @@ __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
       er = lane_from_right(e);
       el = lane_from_left(e);
     } else {
-      se[l] = e;
+      if (SUB == 0) sm.se[l] = e;
       __syncthreads();
-      er = l + 1 < B ? se[l + 1] : R(0);
-      el = l > 0 ? se[l - 1] : R(0);
+      er = l + 1 < B ? sm.se[l + 1] : R(0);
+      el = l > 0 ? sm.se[l - 1] : R(0);
     }
     if (hcell) h = fma(ch, er - e, h);
     R p = 0;
     if constexpr (N > 0) {
-      auto density = [&](const auto &mt, int mm) {
-        CL::rotate(x, e, mt);
+      auto finish = [&](const auto &mt, int mm) {
         p = CL::polar(x, mt);
         if (rec_now) {
           if (rec_lds) {
-            trec.density(n1, x, rb, re);
+            sm.trec.density(n1, x, rb, re);
             record_density_all<N, R>(sim, c, n1, mm, x);
           } else {
             record_density<N, R>(sim, c, n1, mm, x, rb, re);
           }
         }
-        CL::propagate(x, mt);
+        CL::template propagate<L, SUB>(x, mt);
       };
-      if (VC && wave_uni) {
-        if (qm) density(RegCoef<R, VC ? SQ : 1>{cf}, mm0);
+      if constexpr (L == 1) {
+        per_material([&](const auto &mt, int mm) {
+          CL::rotate(x, e, mt);
+          finish(mt, mm);
+        });
       } else {
-        uint64_t todo = __ballot(qm);
-        while (todo) {
-          const int lead = __ffsll(static_cast<unsigned long long>(todo)) - 1;
-          const int mm = __builtin_amdgcn_readlane(me, lead);
-          const bool mine = qm && me == mm;
-          if (mine) density(mtab + __builtin_amdgcn_readfirstlane(mm * S), mm);  // uniform: scalar loads
-          todo &= ~__ballot(mine);
+        per_material([&](const auto &mt, int) {
+          CL::template rotate<L, SUB>(x, e, mt);
+#pragma unroll
+          for (int a = 0; a < M; ++a)
+            if (SP::owns(SUB, a)) sm.sy[a][l] = x[a];
+        });
+        if (SUB == 0) sm.sh[l] = h;
+        __syncthreads();
+        if (qm) {
+#pragma unroll
+          for (int a = 0; a < M; ++a)
+            if (!SP::owns(SUB, a)) x[a] = sm.sy[a][l];
         }
+        per_material(finish);
       }
     }
     R hl;
     if constexpr (WAVE) {
       hl = lane_from_left(h);
     } else {
-      sh[l] = h;
-      __syncthreads();
-      hl = l > 0 ? sh[l - 1] : R(0);
+      if constexpr (L == 1 || N == 0) {
+        sm.sh[l] = h;
+        __syncthreads();
+      }
+      hl = l > 0 ? sm.sh[l - 1] : R(0);
     }
     const R eo = e;
     if (ecell) e = fma(cbd, h - hl, fma(ca, eo, -(cbg * p)));
@@ -506,10 +596,10 @@ __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
         enr = lane_from_right(e);
         enl = lane_from_left(e);
       } else {
-        se2[l] = e;
+        if (SUB == 0) sm.se2[l] = e;
         __syncthreads();
-        enr = l + 1 < B ? se2[l + 1] : R(0);
-        enl = l > 0 ? se2[l - 1] : R(0);
+        enr = l + 1 < B ? sm.se2[l + 1] : R(0);
+        enl = l > 0 ? sm.se2[l - 1] : R(0);
       }
       if (mur_l) e = fma(kap_l, enr - eo, er);
       if (mur_r) e = fma(kap_r, enl - eo, el);
@@ -521,14 +611,14 @@ __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
 #pragma unroll
       for (int t = 0; t < kTileSources; ++t) {
         if (t < n_ts && c == src_cell[t]) {
-          const R v = s_src[t][s];
+          const R v = sm.src[t][s];
           e = src_hard[t] ? v : e + v;
         }
       }
     }
     if (rec_now) {
       if (rec_lds) {
-        trec.fields(n1, e, hcell ? h : R(0), qm, rb, re);
+        sm.trec.fields(n1, e, hcell ? h : R(0), qm, rb, re);
         record_fields_all(sim, c, n1, e, hcell ? h : R(0), qm);
       } else {
         record_fields(sim, c, n1, e, hcell ? h : R(0), qm, rb, re);
@@ -539,15 +629,42 @@ __global__ void __launch_bounds__(B) k_blocked(const DevSim *__restrict__ sims,
     R *__restrict__ e_out = static_cast<R *>(sim.e[par ^ 1]);
     R *__restrict__ h_out = static_cast<R *>(sim.h[par ^ 1]);
     R *__restrict__ x_out = static_cast<R *>(sim.x[par ^ 1]);
-    e_out[c] = e;
-    h_out[c] = h;
+    if (SUB == 0) {
+      e_out[c] = e;
+      h_out[c] = h;
+    }
     if constexpr (N > 0) {
       if (qm) {
 #pragma unroll
-        for (int a = 0; a < M; ++a) x_out[a * nx + c] = x[a];
+        for (int a = 0; a < M; ++a)
+          if (SP::owns(SUB, a)) x_out[a * nx + c] = x[a];
       }
     }
-    if (!isfinite(double(e)) || !isfinite(double(h))) *sim.status = 1;
+    if (SUB == 0 && (!isfinite(double(e)) || !isfinite(double(h)))) *sim.status = 1;
+  }
+}
+
+template <int N, typename R, int B, int L, bool VC>
+__global__ void __launch_bounds__(B * L) k_blocked(const DevSim *__restrict__ sims,
+                                                   const DevTile *__restrict__ tiles, int64_t n0, int parity,
+                                                   int halo, int k) {
+  __shared__ TileShared<N, R, B, L> sm;
+  if constexpr (L == 1) {
+    tile_steps<N, R, B, 1, VC, 0>(sims, tiles, n0, parity, halo, k, sm);
+  } else {
+    // wave-uniform group index: each group runs its own specialisation, all
+    // with the same sequence of barriers
+    const int sub = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / B);
+    if (sub == 0) {
+      tile_steps<N, R, B, L, VC, 0>(sims, tiles, n0, parity, halo, k, sm);
+    } else if (sub == 1) {
+      tile_steps<N, R, B, L, VC, 1>(sims, tiles, n0, parity, halo, k, sm);
+    } else if constexpr (L == 4) {
+      if (sub == 2)
+        tile_steps<N, R, B, L, VC, 2>(sims, tiles, n0, parity, halo, k, sm);
+      else
+        tile_steps<N, R, B, L, VC, 3>(sims, tiles, n0, parity, halo, k, sm);
+    }
   }
 }
 
@@ -664,42 +781,104 @@ __global__ void __launch_bounds__(kPlainBlock) k_plain_e(const DevSim *__restric
   if (!isfinite(e)) *sim.status = 1;
 }
 
-template <int N, typename R, bool VC>
-hipError_t launch_blocked_nrv(int block, const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0,
-                              int parity, int halo, int k, hipStream_t st) {
-  switch (block) {
-    case 64: k_blocked<N, R, 64, VC><<<n_tiles, 64, 0, st>>>(sims, tiles, n0, parity, halo, k); break;
-    case 128: k_blocked<N, R, 128, VC><<<n_tiles, 128, 0, st>>>(sims, tiles, n0, parity, halo, k); break;
-    case 256: k_blocked<N, R, 256, VC><<<n_tiles, 256, 0, st>>>(sims, tiles, n0, parity, halo, k); break;
-    case 512: k_blocked<N, R, 512, VC><<<n_tiles, 512, 0, st>>>(sims, tiles, n0, parity, halo, k); break;
-    case 1024: k_blocked<N, R, 1024, VC><<<n_tiles, 1024, 0, st>>>(sims, tiles, n0, parity, halo, k); break;
-    default: return hipErrorInvalidValue;
+template <int N, typename R, int B, int L, bool VC>
+hipError_t launch_shape(const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo,
+                        int k, hipStream_t st) {
+  if constexpr (shape_fits<N, R, B, L>()) {
+    k_blocked<N, R, B, L, VC><<<n_tiles, B * L, 0, st>>>(sims, tiles, n0, parity, halo, k);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
-// register-resident coefficients are instantiated for the small level counts only
-template <int N, typename R>
-hipError_t launch_blocked_nr(int block, bool vc, const DevSim *sims, const DevTile *tiles, int n_tiles,
-                             int64_t n0, int parity, int halo, int k, hipStream_t st) {
-  if constexpr (N == 2 || N == 3) {
-    if (vc) return launch_blocked_nrv<N, R, true>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+template <int N, typename R, int L, bool VC>
+hipError_t launch_blocked_b(int block, const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0,
+                            int parity, int halo, int k, hipStream_t st) {
+  switch (block) {
+    case 64: return launch_shape<N, R, 64, L, VC>(sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 128: return launch_shape<N, R, 128, L, VC>(sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 256: return launch_shape<N, R, 256, L, VC>(sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 512: return launch_shape<N, R, 512, L, VC>(sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 1024: return launch_shape<N, R, 1024, L, VC>(sims, tiles, n_tiles, n0, parity, halo, k, st);
   }
-  return launch_blocked_nrv<N, R, false>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+  return hipErrorInvalidValue;
+}
+
+// register-resident coefficients are instantiated for the small level counts
+// only, split waves for the quantum level counts
+template <int N, typename R>
+hipError_t launch_blocked_nr(int block, int lanes, bool vc, const DevSim *sims, const DevTile *tiles, int n_tiles,
+                             int64_t n0, int parity, int halo, int k, hipStream_t st) {
+  constexpr bool kVC = N == 2 || N == 3;
+  switch (lanes) {
+    case 1:
+      if constexpr (kVC)
+        if (vc) return launch_blocked_b<N, R, 1, kVC>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+      return launch_blocked_b<N, R, 1, false>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 2:
+    case 4:
+      if constexpr (N >= 2) {
+        if (lanes == 2) {
+          if constexpr (kVC)
+            if (vc) return launch_blocked_b<N, R, 2, kVC>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+          return launch_blocked_b<N, R, 2, false>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+        }
+        if constexpr (kVC)
+          if (vc) return launch_blocked_b<N, R, 4, kVC>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+        return launch_blocked_b<N, R, 4, false>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+      }
+      break;
+  }
+  return hipErrorInvalidValue;
 }
 
 template <typename R>
-hipError_t launch_blocked_r(int levels, int block, bool vc, const DevSim *sims, const DevTile *tiles,
+hipError_t launch_blocked_r(int levels, int block, int lanes, bool vc, const DevSim *sims, const DevTile *tiles,
                             int n_tiles, int64_t n0, int parity, int halo, int k, hipStream_t st) {
   switch (levels) {
-    case 0: return launch_blocked_nr<0, R>(block, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 2: return launch_blocked_nr<2, R>(block, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 3: return launch_blocked_nr<3, R>(block, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 4: return launch_blocked_nr<4, R>(block, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 5: return launch_blocked_nr<5, R>(block, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 6: return launch_blocked_nr<6, R>(block, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 0: return launch_blocked_nr<0, R>(block, lanes, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 2: return launch_blocked_nr<2, R>(block, lanes, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 3: return launch_blocked_nr<3, R>(block, lanes, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 4: return launch_blocked_nr<4, R>(block, lanes, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 5: return launch_blocked_nr<5, R>(block, lanes, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 6: return launch_blocked_nr<6, R>(block, lanes, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
   }
   return hipErrorInvalidValue;
+}
+
+template <int N, typename R>
+bool fits_n(int block, int lanes) {
+  auto f = [&](auto lc) {
+    constexpr int Lc = decltype(lc)::value;
+    switch (block) {
+      case 64: return shape_fits<N, R, 64, Lc>();
+      case 128: return shape_fits<N, R, 128, Lc>();
+      case 256: return shape_fits<N, R, 256, Lc>();
+      case 512: return shape_fits<N, R, 512, Lc>();
+      case 1024: return shape_fits<N, R, 1024, Lc>();
+    }
+    return false;
+  };
+  switch (lanes) {
+    case 1: return f(std::integral_constant<int, 1>());
+    case 2: return f(std::integral_constant<int, 2>());
+    case 4: return f(std::integral_constant<int, 4>());
+  }
+  return false;
+}
+
+template <typename R>
+bool fits_r(int levels, int block, int lanes) {
+  switch (levels) {
+    case 0: return fits_n<0, R>(block, lanes);
+    case 2: return fits_n<2, R>(block, lanes);
+    case 3: return fits_n<3, R>(block, lanes);
+    case 4: return fits_n<4, R>(block, lanes);
+    case 5: return fits_n<5, R>(block, lanes);
+    case 6: return fits_n<6, R>(block, lanes);
+  }
+  return false;
 }
 
 template <int N>
@@ -714,19 +893,45 @@ hipError_t launch_plain_n(const DevSim *sims, const DevTile *tiles, int n_tiles,
 
 }  // namespace
 
+// The kernels are built in two parts so that the library compiles them in
+// parallel: MB_PART 1 holds the FP32 tiles, MB_PART 2 the FP64 tiles, the
+// two-launch kernels and the dispatch; without MB_PART both are built here.
+#ifndef MB_PART
+#define MB_PART 0
+#endif
+
+hipError_t launch_blocked_f32(int levels, int block, int lanes, bool vc, const DevSim *sims, const DevTile *tiles,
+                              int n_tiles, int64_t n0, int parity, int halo, int k, hipStream_t st);
+bool fits_f32(int levels, int block, int lanes);
+
+#if MB_PART != 2
+hipError_t launch_blocked_f32(int levels, int block, int lanes, bool vc, const DevSim *sims, const DevTile *tiles,
+                              int n_tiles, int64_t n0, int parity, int halo, int k, hipStream_t st) {
+  return launch_blocked_r<float>(levels, block, lanes, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
+}
+
+bool fits_f32(int levels, int block, int lanes) { return fits_r<float>(levels, block, lanes); }
+#endif
+
+#if MB_PART != 1
 bool block_supported(int block) {
   return block == 64 || block == 128 || block == 256 || block == 512 || block == 1024;
 }
 
+bool shape_supported(int levels, int precision, int block, int lanes) {
+  if (!block_supported(block)) return false;
+  return precision == 64 ? fits_r<double>(levels, block, lanes) : fits_f32(levels, block, lanes);
+}
+
 int plain_block() { return kPlainBlock; }
 
-hipError_t launch_blocked(int levels, int precision, int block, bool vc, const DevSim *sims, const DevTile *tiles,
-                          int n_tiles, int64_t n0, int parity, int halo, int k, hipStream_t st) {
+hipError_t launch_blocked(int levels, int precision, int block, int lanes, bool vc, const DevSim *sims,
+                          const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo, int k, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
   if (k < 1 || k > halo || k > kMaxChunk || 2 * halo >= block) return hipErrorInvalidValue;
   if (precision == 64)
-    return launch_blocked_r<double>(levels, block, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
-  return launch_blocked_r<float>(levels, block, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    return launch_blocked_r<double>(levels, block, lanes, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
+  return launch_blocked_f32(levels, block, lanes, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
 }
 
 hipError_t launch_plain(int levels, const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity,
@@ -742,5 +947,6 @@ hipError_t launch_plain(int levels, const DevSim *sims, const DevTile *tiles, in
   }
   return hipErrorInvalidValue;
 }
+#endif
 
 }  // namespace mb

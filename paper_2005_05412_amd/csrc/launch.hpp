@@ -8,13 +8,17 @@
 namespace mb {
 
 bool block_supported(int block);
+// whether the blocked kernel is built for this tile (block cells, lanes wave
+// groups per 64 cells: 1, 2 or 4) at this level count and precision
+bool shape_supported(int levels, int precision, int block, int lanes);
 int plain_block();
 
 // Temporally blocked launch from engine step n0 with buffer parity `parity`:
-// k <= halo steps for every tile; 2*halo < block.
+// k <= halo steps for every tile; 2*halo < block.  Tiles of `block` cells,
+// block*lanes threads.
 // vc: quantum coefficients of single-material waves held in registers
 // (used for 2 and 3 levels, ignored otherwise).
-hipError_t launch_blocked(int levels, int precision, int block, bool vc, const DevSim *sims,
+hipError_t launch_blocked(int levels, int precision, int block, int lanes, bool vc, const DevSim *sims,
                           const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo, int k,
                           hipStream_t st);
 // One time step as two launches (FP64); tiles of plain_block() cells.

@@ -525,6 +525,10 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
     err = "unknown variant";
     return MB_ERR_ARG;
   }
+  if (scen->lanes != 0 && scen->lanes != 1 && scen->lanes != 2 && scen->lanes != 4) {
+    err = "lanes must be 0, 1, 2 or 4";
+    return MB_ERR_ARG;
+  }
   if (scen->variant == MB_VARIANT_PLAIN && scen->precision != 64) {
     err = "the plain variant runs in FP64 only";
     return MB_ERR_UNSUPPORTED;
@@ -552,6 +556,7 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
   plan.variant = scen->variant;
   plan.block = scen->block;
   plan.depth = scen->depth;
+  plan.lanes = scen->lanes;
   plan.dx = scen->nx > 1 ? dev->length / double(scen->nx - 1) : 0.0;
   if (scen->nx > 1 && !(plan.dx > 0)) {
     err = "device length must be positive";

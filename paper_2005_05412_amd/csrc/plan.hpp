@@ -61,7 +61,7 @@ struct SimPlan {
   int n = 0, m = 0;               // levels (0: no quantum cells) and state dimension
   int precision = 64;
   int variant = MB_VARIANT_AUTO;
-  int block = 0, depth = 0;
+  int block = 0, depth = 0, lanes = 0;
   std::vector<uint8_t> mat_e, mat_h;
   std::vector<MaterialPlan> mats;
   int edge_l = 0, edge_r = 0;     // 0: PEC, 1: Mur

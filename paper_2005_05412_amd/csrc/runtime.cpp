@@ -171,8 +171,8 @@ void Arena::release(void *p) {
 
 // ---------------------------------------------------------------- Engine
 
-Engine::Engine(int device, int precision, int variant, int block, int halo, bool vc)
-    : device_(device), precision_(precision), variant_(variant), block_(block), halo_(halo), vc_(vc) {}
+Engine::Engine(int device, int precision, int variant, int block, int halo, bool vc, int lanes)
+    : device_(device), precision_(precision), variant_(variant), block_(block), halo_(halo), vc_(vc), lanes_(lanes) {}
 
 Engine::~Engine() {
   for (auto &s : sims_)
@@ -197,7 +197,14 @@ int Engine::init(std::string &err) {
       err = "blocked variant needs block in {64,128,256,512,1024} and 1 <= depth < block/2";
       return MB_ERR_ARG;
     }
+    if (lanes_ != 0 && lanes_ != 1 && lanes_ != 2 && lanes_ != 4) {
+      err = "lanes must be 0, 1, 2 or 4";
+      return MB_ERR_ARG;
+    }
   }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device_) == hipSuccess && prop.multiProcessorCount > 0)
+    n_cu_ = prop.multiProcessorCount;
   if (hipMalloc(&d_status_, kStatusSlots * sizeof(int32_t)) != hipSuccess) {
     err = "device allocation failed";
     return MB_ERR_OOM;
@@ -419,7 +426,21 @@ hipError_t Engine::sync_tables(hipStream_t st) {
   return hipSuccess;
 }
 
+int Engine::group_lanes(const Group &g) const {
+  int want = lanes_;
+  if (want == 0) {
+    // enough waves for about two per SIMD (4 SIMDs per compute unit)
+    const int64_t waves1 = int64_t(g.n_tiles) * (block_ / 64);
+    const int64_t target = 8 * int64_t(n_cu_);
+    want = waves1 * 4 <= target ? 4 : waves1 * 2 <= target ? 2 : 1;
+  }
+  for (int l = want; l > 1; l /= 2)
+    if (shape_supported(g.levels, precision_, block_, l)) return l;
+  return 1;
+}
+
 hipError_t Engine::launch_group(Group &g, hipStream_t st, int k, int reps) {
+  const int lanes = variant_ == MB_VARIANT_PLAIN ? 1 : group_lanes(g);
   for (int r = 0; r < reps; ++r) {
     hipError_t e;
     if (variant_ == MB_VARIANT_PLAIN) {
@@ -429,7 +450,7 @@ hipError_t Engine::launch_group(Group &g, hipStream_t st, int k, int reps) {
             hipSuccess)
           return e;
       }
-    } else if ((e = launch_blocked(g.levels, precision_, block_, vc_, g.d_sims, g.d_tiles, g.n_tiles,
+    } else if ((e = launch_blocked(g.levels, precision_, block_, lanes, vc_, g.d_sims, g.d_tiles, g.n_tiles,
                                    n0_ + int64_t(r) * k, parity_ ^ (r & 1), halo_, k, st)) != hipSuccess) {
       return e;
     }

@@ -55,8 +55,12 @@ size_t sim_bytes(const SimPlan &p, int precision, bool plain);
 
 class Engine {
  public:
-  // vc: keep the quantum coefficients of single-material waves in registers
-  Engine(int device, int precision, int variant, int block, int halo, bool vc = false);
+  // vc: keep the quantum coefficients of single-material waves in registers;
+  // lanes: waves per 64 cells sharing each cell's density update (1, 2, 4;
+  // a level count without a kernel for that many uses the next smaller), or
+  // 0 to choose per launch from the group's size (more waves per cell while
+  // the group has too few tiles to fill the GPU)
+  Engine(int device, int precision, int variant, int block, int halo, bool vc = false, int lanes = 1);
   ~Engine();
   int init(std::string &err);
 
@@ -91,6 +95,7 @@ class Engine {
   // steps per blocked launch: the halo width, at most 256
   int chunk_steps() const { return halo_ < 256 ? halo_ : 256; }
   int block() const { return block_; }
+  int lanes() const { return lanes_; }
   bool vc() const { return vc_; }
   int variant() const { return variant_; }
   int precision() const { return precision_; }
@@ -114,9 +119,12 @@ class Engine {
   Group &group_for(int levels);
   hipError_t upload_group(Group &g, hipStream_t st);
   hipError_t launch_group(Group &g, hipStream_t st, int k, int reps);
+  int group_lanes(const Group &g) const;
 
   int device_, precision_, variant_, block_, halo_;
   bool vc_ = false;
+  int lanes_ = 1;
+  int n_cu_ = 256;
   std::vector<std::unique_ptr<SimState>> sims_;
   std::vector<Group> groups_;
   // one stream and completion event per group beyond the first, plus the fork event

@@ -183,7 +183,9 @@ int mb_server_create(int hip_device, size_t hbm_budget, int32_t max_slots, int32
   int block = 256, halo = 32;
   default_shape(3, precision, block, halo);
   halo = std::min(halo, chunk_steps);
-  s->eng = std::make_unique<Engine>(hip_device, precision, MB_VARIANT_BLOCKED, block, halo);
+  // waves per cell chosen per launch from the load: a lightly loaded server
+  // spreads each cell's density update over more waves
+  s->eng = std::make_unique<Engine>(hip_device, precision, MB_VARIANT_BLOCKED, block, halo, false, 0);
   int rc = s->eng->init(err);
   if (rc < 0) return fail(rc, err);
   if ((rc = s->arena.init(hbm_budget, err)) < 0) return fail(rc, err);

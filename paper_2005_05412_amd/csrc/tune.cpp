@@ -40,9 +40,11 @@ void load_cache() {
   std::string key;
   Shape s;
   int vc = 0;
-  while (f >> key >> s.block >> s.halo >> vc) {
+  while (f >> key >> s.block >> s.halo >> vc >> s.lanes) {
     s.vc = vc != 0;
-    if (block_supported(s.block) && s.halo >= 1 && 2 * s.halo < s.block) g_cache[key] = s;
+    if (block_supported(s.block) && s.halo >= 1 && 2 * s.halo < s.block &&
+        (s.lanes == 1 || s.lanes == 2 || s.lanes == 4))
+      g_cache[key] = s;
   }
 }
 
@@ -51,7 +53,7 @@ void store_cache(const std::string &key, const Shape &s) {
   std::string path = cache_path();
   if (path.empty()) return;
   std::ofstream f(path, std::ios::app);
-  if (f) f << key << " " << s.block << " " << s.halo << " " << (s.vc ? 1 : 0) << "\n";
+  if (f) f << key << " " << s.block << " " << s.halo << " " << (s.vc ? 1 : 0) << " " << s.lanes << "\n";
 }
 
 uint64_t pow2_ceil(uint64_t v) {
@@ -62,18 +64,27 @@ uint64_t pow2_ceil(uint64_t v) {
 
 }  // namespace
 
-std::vector<Shape> candidate_shapes(int levels) {
-  // 64-thread tiles exchange neighbours inside one wave (no barriers); larger
-  // tiles go through LDS with a barrier per exchange
+std::vector<Shape> candidate_shapes(int levels, int precision) {
+  // 64-cell one-wave tiles exchange neighbours inside the wave (no barriers);
+  // larger tiles, and tiles with 2 or 4 waves per 64 cells, go through LDS
+  // with a barrier per exchange
   const std::vector<std::pair<int, int>> all = {{64, 8},   {64, 12},  {64, 16},   {64, 20},   {128, 16},
                                                 {128, 32}, {256, 32}, {256, 64},  {512, 64},  {512, 128},
                                                 {512, 192}, {1024, 128}, {1024, 256}};
+  const std::vector<std::pair<int, int>> split = {{64, 16}, {128, 32}, {256, 32}, {256, 64}};
   std::vector<Shape> out;
+  const bool regs = levels == 2 || levels == 3;
   for (auto [b, h] : all) {
     if (levels >= 5 && b > 512) continue;  // register pressure of the large matvec
-    out.push_back(Shape{b, h, false});
-    if (levels == 2 || levels == 3) out.push_back(Shape{b, h, true});
+    out.push_back(Shape{b, h, false, 1});
+    if (regs) out.push_back(Shape{b, h, true, 1});
   }
+  for (int lanes : {2, 4})
+    for (auto [b, h] : split) {
+      if (!shape_supported(levels, precision, b, lanes)) continue;
+      out.push_back(Shape{b, h, false, lanes});
+      if (regs) out.push_back(Shape{b, h, true, lanes});
+    }
   return out;
 }
 
@@ -90,7 +101,7 @@ std::string tune_key(int device, const std::vector<const SimPlan *> &plans, int 
     cells += uint64_t(p->nx);
   }
   std::ostringstream os;
-  os << arch << "/v2/N" << levels << "/p" << precision << "/cells" << pow2_ceil(cells) << "/sims"
+  os << arch << "/v3/N" << levels << "/p" << precision << "/cells" << pow2_ceil(cells) << "/sims"
      << pow2_ceil(plans.size());
   return os.str();
 }
@@ -128,9 +139,9 @@ int tune_shape(int device, const std::vector<const SimPlan *> &plans, int precis
   (void)hipEventCreate(&a);
   (void)hipEventCreate(&b);
   double best_us = 1e300;
-  best = Shape{256, 32};
-  for (const Shape &cand : candidate_shapes(levels)) {
-    Engine eng(device, precision, MB_VARIANT_BLOCKED, cand.block, cand.halo, cand.vc);
+  best = Shape{256, 32, false, 1};
+  for (const Shape &cand : candidate_shapes(levels, precision)) {
+    Engine eng(device, precision, MB_VARIANT_BLOCKED, cand.block, cand.halo, cand.vc, cand.lanes);
     if (eng.init(err) < 0) continue;
     bool ok = true;
     for (auto *p : subset) {

@@ -9,12 +9,13 @@
 namespace mb {
 
 struct Shape {
-  int block = 256;  // threads (cells) per tile
+  int block = 256;  // cells per tile
   int halo = 32;    // halo width = steps per launch (capped at 256)
   bool vc = false;  // quantum coefficients in registers (2 and 3 levels)
+  int lanes = 1;    // waves per 64 cells sharing each cell's density update
 };
 
-std::vector<Shape> candidate_shapes(int levels);
+std::vector<Shape> candidate_shapes(int levels, int precision);
 std::string tune_key(int device, const std::vector<const SimPlan *> &plans, int precision);
 // Picks the fastest candidate shape for these simulations (cached).
 int tune_shape(int device, const std::vector<const SimPlan *> &plans, int precision, Shape &best,

@@ -32,8 +32,8 @@ def rel_errors(prob, got, ref):
     return trace_errors(prob, got, ref)
 
 
-def gpu_run(prob, precision=None, variant="auto", block=0, depth=0, chunks=None):
-    s = mb.Solver(prob, precision=precision, variant=variant, block=block, depth=depth)
+def gpu_run(prob, precision=None, variant="auto", block=0, depth=0, chunks=None, lanes=0):
+    s = mb.Solver(prob, precision=precision, variant=variant, block=block, depth=depth, lanes=lanes)
     if chunks:
         for c in chunks:
             s.run(c)
@@ -73,9 +73,13 @@ def test_small_random_fp64_plain_and_blocked_vs_oracle(case):
     plain = gpu_run(prob, precision=64, variant="plain")
     errs = rel_errors(prob, plain, ref)
     assert max(errs.values()) <= TOL[64], errs
-    for block, depth in ((64, 1), (64, 7), (64, 20), (128, 31), (256, 32), (512, 100)):
+    # every tile shape, coefficient placement and split of the density update
+    # over 1, 2 or 4 waves per 64 cells runs the same per-cell arithmetic
+    shapes = [(64, 1, 1), (64, 7, 1), (64, 20, 1), (128, 31, 1), (256, 32, 1), (512, 100, 1),
+              (64, 7, 2), (128, 31, 2), (256, 64, 2), (64, 20, 4), (128, 16, 4), (256, 32, 4)]
+    for block, depth, lanes in shapes:
         for variant in ("blocked", "blocked_regs"):
-            blk = gpu_run(prob, precision=64, variant=variant, block=block, depth=depth)
+            blk = gpu_run(prob, precision=64, variant=variant, block=block, depth=depth, lanes=lanes)
             assert_same(blk, plain)
 
 
@@ -88,8 +92,10 @@ def test_small_random_fp32_vs_oracle(case):
     errs = rel_errors(prob, got, ref)
     assert max(errs.values()) <= TOL[32], errs
     # every tile shape and coefficient placement runs the same per-cell arithmetic
-    for variant, block, depth in (("blocked", 64, 12), ("blocked_regs", 64, 16), ("blocked_regs", 256, 64)):
-        assert_same(gpu_run(prob, precision=32, variant=variant, block=block, depth=depth), got)
+    for variant, block, depth, lanes in (("blocked", 64, 12, 1), ("blocked_regs", 64, 16, 1),
+                                         ("blocked_regs", 256, 64, 1), ("blocked", 128, 16, 2),
+                                         ("blocked_regs", 64, 16, 4), ("blocked", 256, 64, 4)):
+        assert_same(gpu_run(prob, precision=32, variant=variant, block=block, depth=depth, lanes=lanes), got)
 
 
 def test_blocked_chunking_is_invisible():
@@ -160,6 +166,12 @@ def test_lambda3_full_grid_prefix_vs_oracle():
     got32 = gpu_run(prob, precision=32)
     errs32 = rel_errors(prob, got32, ref)
     assert max(errs32.values()) <= TOL[32], max(errs32.values())
+    # the density update split over 2 or 4 waves per 64 cells gives the same bits
+    base = gpu_run(prob, precision=32, variant="blocked", block=256, depth=64, lanes=1)
+    for block, depth, lanes in ((256, 64, 2), (128, 32, 4)):
+        for variant in ("blocked", "blocked_regs"):
+            _say(f"lambda3 prefix {variant} {block}/{depth} lanes {lanes}")
+            assert_same(gpu_run(prob, precision=32, variant=variant, block=block, depth=depth, lanes=lanes), base)
 
 
 def test_lambda3_full_length_blocked_equals_plain_and_invariants():
@@ -193,7 +205,7 @@ def _mixed_batch(n=6, n_steps=1600, precision=32):
 def test_batch_equals_individual_runs(precision):
     probs = _mixed_batch(precision=precision)
     _say(f"batch {precision}")
-    b = mb.Batch(probs, precision=precision, block=128, depth=16)
+    b = mb.Batch(probs, precision=precision, block=128, depth=16, lanes=2)
     b.run(use_graph=True)
     for k, p in enumerate(probs):
         alone = gpu_run(p, precision=precision, variant="blocked", block=256, depth=32)
@@ -281,6 +293,10 @@ def test_qcl6_full_grid_prefix_vs_oracle():
     assert max(rel_errors(prob, got, ref).values()) <= TOL[64]
     got32 = gpu_run(prob, precision=32)
     assert max(rel_errors(prob, got32, ref).values()) <= QCL_FP32_TOL
+    base = gpu_run(prob, precision=32, variant="blocked", block=256, depth=64, lanes=1)
+    for block, depth, lanes in ((256, 64, 2), (128, 32, 4), (64, 16, 4)):
+        _say(f"qcl6 prefix {block}/{depth} lanes {lanes}")
+        assert_same(gpu_run(prob, precision=32, variant="blocked", block=block, depth=depth, lanes=lanes), base)
 
 
 def test_sweep_batch_spot_checks_vs_oracle():
