@@ -11,7 +11,7 @@ namespace mb {
 namespace {
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-constexpr int kStatusSlots = 4096;
+constexpr int kStatusSlots = Engine::kMaxStatusSlots;
 
 struct Layout {
   size_t e, h, x, init_e, init_x, p, mat_e, mat_h, mtab, src, src_tab, rec, readout, rec_first, rec_ids, rec_all;
@@ -567,6 +567,33 @@ bool Engine::all_finished() const {
   for (auto &s : sims_)
     if (s->active && s->done < s->plan.n_steps) return false;
   return true;
+}
+
+hipError_t Engine::enqueue_status(hipStream_t st, int32_t *host) {
+  if (hi_slot_ == 0) return hipSuccess;
+  return hipMemcpyAsync(host, d_status_, size_t(hi_slot_) * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+}
+
+int Engine::reshape(int block, int halo, int lanes, std::string &err) {
+  if (variant_ == MB_VARIANT_PLAIN) return MB_OK;
+  if (!block_supported(block) || halo < 1 || 2 * halo >= block || (lanes != 0 && lanes != 1 && lanes != 2 && lanes != 4)) {
+    err = "bad tile shape";
+    return MB_ERR_ARG;
+  }
+  if (block == block_ && halo == halo_ && lanes == lanes_) return MB_OK;
+  block_ = block;
+  halo_ = halo;
+  lanes_ = lanes;
+  dirty_ = true;
+  ++version_;
+  return MB_OK;
+}
+
+int64_t Engine::total_cells() const {
+  int64_t c = 0;
+  for (auto &s : sims_)
+    if (s->active) c += s->plan.nx;
+  return c;
 }
 
 hipError_t Engine::read_status(std::vector<int32_t> &out) {

@@ -104,6 +104,14 @@ class Engine {
   int n_sims() const { return int(sims_.size()); }
   // copies the status flags of all simulations to the host (synchronous)
   hipError_t read_status(std::vector<int32_t> &out);
+  // enqueues the copy of the status flags in use into `host` (pinned, at
+  // least kMaxStatusSlots entries) on st
+  hipError_t enqueue_status(hipStream_t st, int32_t *host);
+  static constexpr int kMaxStatusSlots = 4096;
+  // new tile shape for the following launches (tables are rebuilt at the next
+  // chunk); only between chunks
+  int reshape(int block, int halo, int lanes, std::string &err);
+  int64_t total_cells() const;
   hipError_t read_records(int id, int rec, std::vector<double> &out);
   hipError_t read_state(int id, double *e, double *h, double *rho);
   double cell_updates() const { return cell_updates_; }

@@ -41,14 +41,28 @@ struct Request {
 
 }  // namespace
 
+// Requests of one level count run in their own engine, on their own stream,
+// with their own chunk cadence: a slow six-level solve does not hold back the
+// two-level solves next to it.
+struct Lane {
+  int levels = 0;
+  std::unique_ptr<Engine> eng;
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  int32_t *status = nullptr;  // pinned copy of the status flags, written after each chunk
+  bool in_flight = false;
+  bool changed = false;       // membership changed since the last chunk
+  std::vector<Request *> running;
+};
+
 struct mb_server {
   int device = 0;
   int precision = 32;
   int max_slots = 1;
   int chunk_steps = 32;
-  std::unique_ptr<Engine> eng;
+  std::map<int, Lane> lanes;  // by level count
   Arena arena;
-  hipStream_t stream = nullptr, side = nullptr;
+  hipStream_t side = nullptr;
   std::mutex mu;
   std::condition_variable cv;
   std::thread worker;
@@ -57,19 +71,64 @@ struct mb_server {
   uint64_t next_ticket = 1;
   std::map<uint64_t, std::unique_ptr<Request>> reqs;
   std::deque<Request *> queue;      // ordered by arrival
-  std::vector<Request *> running;
+  int n_running = 0;
   size_t outstanding = 0;
   double busy_s = 0;
   int64_t chunks = 0;
+  double cell_updates_retired = 0;
   std::string worker_error;
 
   double now() const { return std::chrono::duration<double>(clk::now() - t0).count(); }
   void loop();
-  void retire(Request *r, int32_t state);
+  void retire(Lane &ln, Request *r, int32_t state);
+  int lane_for(int levels, std::string &err);
+  hipError_t launch(Lane &ln);
+  void finish(Lane &ln, hipError_t he);
 };
 
-void mb_server::retire(Request *r, int32_t state) {
-  Engine &e = *eng;
+// Tile shape of one lane for the cells it holds.  Few cells: latency
+// shapes (deep halos, large density updates on 128-cell tiles split over up
+// to 4 waves per 64 cells); many cells: 256-cell tiles with shallow halos,
+// which redo fewer halo cells.  The split itself follows the tile count.
+static void server_shape(int levels, int64_t cells, int chunk_steps, int &block, int &halo) {
+  const bool busy = cells > (levels >= 4 ? 65536 : 196608);
+  if (busy) {
+    block = 256;
+    halo = 32;
+  } else if (levels >= 4) {
+    block = 128;
+    halo = 32;
+  } else {
+    block = 256;
+    halo = 64;
+  }
+  halo = std::min(halo, chunk_steps);
+}
+
+int mb_server::lane_for(int levels, std::string &err) {
+  auto it = lanes.find(levels);
+  if (it != lanes.end()) return MB_OK;
+  Lane ln;
+  ln.levels = levels;
+  int block = 256, halo = 32;
+  server_shape(levels, 0, chunk_steps, block, halo);
+  ln.eng = std::make_unique<Engine>(device, precision, MB_VARIANT_BLOCKED, block, halo, false, 0);
+  int rc = ln.eng->init(err);
+  if (rc < 0) return rc;
+  if (hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&ln.done, hipEventDisableTiming) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void **>(&ln.status), Engine::kMaxStatusSlots * sizeof(int32_t),
+                    hipHostMallocDefault) != hipSuccess) {
+    err = "stream or pinned buffer creation failed";
+    return MB_ERR_HIP;
+  }
+  std::memset(ln.status, 0, Engine::kMaxStatusSlots * sizeof(int32_t));
+  lanes.emplace(levels, std::move(ln));
+  return MB_OK;
+}
+
+void mb_server::retire(Lane &ln, Request *r, int32_t state) {
+  Engine &e = *ln.eng;
   if (r->engine_id >= 0) {
     const SimState &s = e.sim(r->engine_id);
     r->records.resize(s.plan.records.size());
@@ -78,38 +137,102 @@ void mb_server::retire(Request *r, int32_t state) {
       (void)e.read_records(r->engine_id, int(q), r->records[q]);
       r->widths[q] = s.plan.records[q].width;
     }
+    cell_updates_retired += double(s.done) * double(s.plan.nx);
     e.remove(r->engine_id, &arena);
+    ln.changed = true;
   }
   r->state = state;
   r->t_done = now();
+  --n_running;
   if (outstanding) --outstanding;
+}
+
+// enqueues one chunk (chunk_steps steps) of every simulation of the lane
+hipError_t mb_server::launch(Lane &ln) {
+  Engine &e = *ln.eng;
+  if (ln.changed) {
+    int block = 256, halo = 32;
+    server_shape(ln.levels, e.total_cells(), chunk_steps, block, halo);
+    std::string err;
+    (void)e.reshape(block, halo, 0, err);
+    ln.changed = false;
+  }
+  const int k = std::min(chunk_steps, e.chunk_steps());
+  const int sub = std::max(1, chunk_steps / e.chunk_steps());
+  hipError_t he = e.chunk(ln.stream, k, sub);
+  if (he == hipSuccess) he = e.enqueue_status(ln.stream, ln.status);
+  if (he == hipSuccess) he = hipEventRecord(ln.done, ln.stream);
+  if (he == hipSuccess) {
+    ln.in_flight = true;
+    ++chunks;
+  }
+  return he;
+}
+
+// after the lane's chunk completed (or failed): status, retirements
+void mb_server::finish(Lane &ln, hipError_t he) {
+  ln.in_flight = false;
+  const int32_t *status = ln.status;
+  if (he != hipSuccess) {
+    worker_error = hipGetErrorString(he);
+    for (Request *r : ln.running) retire(ln, r, MB_ERR_HIP);
+    ln.running.clear();
+    return;
+  }
+  for (size_t i = 0; i < ln.running.size();) {
+    Request *r = ln.running[i];
+    const SimState &s = ln.eng->sim(r->engine_id);
+    int32_t st = 0;
+    if (status[s.status_slot]) st = MB_ERR_NONFINITE;
+    else if (r->cancel) st = 3;
+    else if (ln.eng->finished(r->engine_id)) st = 2;
+    if (st) {
+      retire(ln, r, st);
+      ln.running.erase(ln.running.begin() + long(i));
+    } else {
+      ++i;
+    }
+  }
 }
 
 void mb_server::loop() {
   (void)hipSetDevice(device);
-  Engine &e = *eng;
   std::unique_lock<std::mutex> lk(mu);
+  clk::time_point busy_since{};
+  bool busy = false;
   while (!stop) {
-    // admission: arrived requests in arrival order, while slots and memory allow
+    // admission: arrived requests in arrival order, while slots and memory
+    // allow, into lanes that have no chunk in flight
     double t = now();
-    while (!queue.empty()) {
-      Request *r = queue.front();
+    for (auto it = queue.begin(); it != queue.end();) {
+      Request *r = *it;
       if (r->cancel) {
-        queue.pop_front();
+        it = queue.erase(it);
         r->state = 3;
         r->t_done = t;
         if (outstanding) --outstanding;
         continue;
       }
-      if (r->arrival > t || int(running.size()) >= max_slots) break;
+      if (r->arrival > t || n_running >= max_slots) break;
       if (arena.capacity() - arena.used() < r->bytes) break;
+      const int levels = r->plan.n;
       std::string err;
-      int id = e.add(std::move(r->plan), &arena, side, err);
-      queue.pop_front();
-      if (id == MB_ERR_BUDGET) {  // fragmentation: retry after the next retirement
-        queue.push_front(r);
-        break;
+      int rc = lane_for(levels, err);
+      if (rc < 0) {
+        it = queue.erase(it);
+        r->state = rc;
+        r->t_done = t;
+        if (outstanding) --outstanding;
+        continue;
       }
+      Lane &ln = lanes[levels];
+      if (ln.in_flight) {
+        ++it;
+        continue;
+      }
+      int id = ln.eng->add(std::move(r->plan), &arena, side, err);
+      if (id == MB_ERR_BUDGET) break;  // fragmentation: retry after the next retirement
+      it = queue.erase(it);
       if (id < 0) {
         r->state = id;
         r->t_done = t;
@@ -119,9 +242,28 @@ void mb_server::loop() {
       r->engine_id = id;
       r->state = 1;
       r->t_admit = now();
-      running.push_back(r);
+      ln.running.push_back(r);
+      ln.changed = true;
+      ++n_running;
     }
-    if (running.empty()) {
+    // launch a chunk in every idle lane with work
+    for (auto &[lv, ln] : lanes) {
+      if (ln.in_flight || ln.running.empty()) continue;
+      hipError_t he = launch(ln);
+      if (he != hipSuccess) finish(ln, he);
+    }
+    bool any = false;
+    for (auto &[lv, ln] : lanes) any = any || ln.in_flight;
+    if (any && !busy) {
+      busy = true;
+      busy_since = clk::now();
+    }
+    if (!any) {
+      if (busy) {
+        busy = false;
+        busy_s += std::chrono::duration<double>(clk::now() - busy_since).count();
+      }
+      cv.notify_all();
       if (queue.empty())
         cv.wait(lk);
       else {
@@ -130,40 +272,28 @@ void mb_server::loop() {
       }
       continue;
     }
+    // wait for the first lane to complete its chunk (or for a new arrival)
     lk.unlock();
-    auto tb = clk::now();
-    hipError_t he = hipSuccess;
-    int k = e.variant() == MB_VARIANT_PLAIN ? chunk_steps : std::min(chunk_steps, e.chunk_steps());
-    int sub = e.variant() == MB_VARIANT_PLAIN ? 1 : std::max(1, chunk_steps / e.chunk_steps());
-    he = e.chunk(stream, k, sub);
-    if (he == hipSuccess) he = hipStreamSynchronize(stream);
-    std::vector<int32_t> status;
-    if (he == hipSuccess) he = e.read_status(status);
-    busy_s += std::chrono::duration<double>(clk::now() - tb).count();
-    lk.lock();
-    ++chunks;
-    if (he != hipSuccess) {
-      worker_error = hipGetErrorString(he);
-      for (Request *r : running) retire(r, MB_ERR_HIP);
-      running.clear();
-      continue;
+    // poll the lanes' completion events: spinning for the first ~0.5 ms, then
+    // in 20 us sleeps
+    bool done_any = false;
+    const auto w0 = clk::now();
+    while (!done_any) {
+      for (auto &[lv, ln] : lanes)
+        if (ln.in_flight && hipEventQuery(ln.done) != hipErrorNotReady) done_any = true;
+      if (!done_any && clk::now() - w0 > std::chrono::microseconds(500))
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
-    for (size_t i = 0; i < running.size();) {
-      Request *r = running[i];
-      const SimState &s = e.sim(r->engine_id);
-      int32_t st = 0;
-      if (status[s.status_slot]) st = MB_ERR_NONFINITE;
-      else if (r->cancel) st = 3;
-      else if (e.finished(r->engine_id)) st = 2;
-      if (st) {
-        retire(r, st);
-        running.erase(running.begin() + long(i));
-      } else {
-        ++i;
-      }
+    lk.lock();
+    for (auto &[lv, ln] : lanes) {
+      if (!ln.in_flight) continue;
+      hipError_t q = hipEventQuery(ln.done);
+      if (q == hipErrorNotReady) continue;
+      finish(ln, q);
     }
     cv.notify_all();
   }
+  if (busy) busy_s += std::chrono::duration<double>(clk::now() - busy_since).count();
 }
 
 extern "C" {
@@ -180,17 +310,9 @@ int mb_server_create(int hip_device, size_t hbm_budget, int32_t max_slots, int32
   s->chunk_steps = chunk_steps;
   std::string err;
   if (hipSetDevice(hip_device) != hipSuccess) return fail(MB_ERR_HIP, "hipSetDevice failed");
-  int block = 256, halo = 32;
-  default_shape(3, precision, block, halo);
-  halo = std::min(halo, chunk_steps);
-  // waves per cell chosen per launch from the load: a lightly loaded server
-  // spreads each cell's density update over more waves
-  s->eng = std::make_unique<Engine>(hip_device, precision, MB_VARIANT_BLOCKED, block, halo, false, 0);
-  int rc = s->eng->init(err);
-  if (rc < 0) return fail(rc, err);
+  int rc;
   if ((rc = s->arena.init(hbm_budget, err)) < 0) return fail(rc, err);
-  if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking) != hipSuccess)
+  if (hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking) != hipSuccess)
     return fail(MB_ERR_HIP, "stream creation failed");
   s->t0 = clk::now();
   *out = s.release();
@@ -306,7 +428,13 @@ int mb_server_read_records(mb_server *s, uint64_t ticket, int record_id, double 
 int mb_server_stats(mb_server *s, double *cell_updates, double *busy_s, int64_t *chunks) {
   if (!s) return fail(MB_ERR_ARG, "null server");
   std::lock_guard<std::mutex> lk(s->mu);
-  if (cell_updates) *cell_updates = s->eng->cell_updates();
+  if (cell_updates) {
+    // retired solves plus the progress of the running ones
+    double cu = s->cell_updates_retired;
+    for (auto &[lv, ln] : s->lanes)
+      for (Request *r : ln.running) cu += double(ln.eng->sim(r->engine_id).done) * double(ln.eng->sim(r->engine_id).plan.nx);
+    *cell_updates = cu;
+  }
   if (busy_s) *busy_s = s->busy_s;
   if (chunks) *chunks = s->chunks;
   return MB_OK;
@@ -321,9 +449,13 @@ int mb_server_destroy(mb_server *s) {
   }
   if (s->worker.joinable()) s->worker.join();
   (void)hipSetDevice(s->device);
-  if (s->stream) (void)hipStreamSynchronize(s->stream);
-  s->eng.reset();
-  if (s->stream) (void)hipStreamDestroy(s->stream);
+  for (auto &[lv, ln] : s->lanes) {
+    if (ln.stream) (void)hipStreamSynchronize(ln.stream);
+    ln.eng.reset();
+    if (ln.status) (void)hipHostFree(ln.status);
+    if (ln.done) (void)hipEventDestroy(ln.done);
+    if (ln.stream) (void)hipStreamDestroy(ln.stream);
+  }
   if (s->side) (void)hipStreamDestroy(s->side);
   delete s;
   return MB_OK;
