@@ -27,6 +27,9 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# the serving leg runs one stream per level count; give HIP enough hardware
+# queues (read at HIP start-up) that they do not share one
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
 
 import paper_2005_05412_amd as mb  # noqa: E402
 import workloads as W  # noqa: E402
@@ -178,6 +181,15 @@ def cpu_baseline(prob, budget_s):
     return n, el, recs
 
 
+def levels_of(prob):
+    """Level count of a problem's quantum material (0 for vacuum)."""
+    for m in prob["materials"]:
+        q = m["qm"]
+        if q is not None:
+            return 2 if q["kind"] == "2lvl" else len(q["h0_diag"])
+    return 0
+
+
 def run_serving(n_requests, rate, log):
     """Poisson trace through the continuous-batching server; latency = arrival to records on the host."""
     log(f"[bench] serving {n_requests} requests at {rate:g}/s")
@@ -190,16 +202,19 @@ def run_serving(n_requests, rate, log):
     srv.drain(timeout_s=600)
     tw = time.perf_counter() - t0
     lat = []
-    for t in tickets:
+    by_levels = {}
+    for t, (_, p) in zip(tickets, trace):
         st, ta, tadm, td = srv.status(t)
         if st == 2:
             lat.append(td - ta)
+            by_levels.setdefault(levels_of(p), []).append(td - ta)
     cu, busy, chunks = srv.stats()
     srv.close()
     lat = np.array(lat)
     return {"requests": len(trace), "done": int(len(lat)), "arrival_rate_per_s": rate,
             "offered_cell_updates_per_s": offered,
             "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+            "p50_latency_s_by_levels": {str(k): float(np.percentile(v, 50)) for k, v in sorted(by_levels.items())},
             "value": cu / tw, "unit": "cell-updates/s", "wall_s": tw, "busy_s": busy, "chunks": int(chunks)}
 
 

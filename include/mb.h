@@ -276,11 +276,18 @@ int mb_batch_destroy(mb_batch *b);
 /* ---- serving: continuous batching of solve requests --------------------- */
 
 /* A server owns `hbm_budget` bytes of device memory and runs up to
- * `max_slots` solves at a time in FP32 (precision 32) or FP64 (64).  Each
- * chunk advances every admitted solve by `chunk_steps` steps (or to its end);
- * between chunks finished solves are retired (records copied to the host,
- * memory freed) and queued requests whose arrival time has passed are
- * admitted while slots and memory allow. */
+ * `max_slots` solves at a time in FP32 (precision 32) or FP64 (64).  Solves
+ * of one level count share an engine ("lane") with its own stream; each
+ * chunk of a lane advances its solves by `chunk_steps` steps (or to their
+ * end), and lanes advance independently.  Between a lane's chunks finished
+ * solves are retired (records copied to the host, memory freed) and queued
+ * requests whose arrival time has passed are admitted while slots and memory
+ * allow.  The lanes use four streams created with the server; they overlap
+ * on the GPU only when the process has enough hardware queues (HIP's
+ * GPU_MAX_HW_QUEUES, read at HIP start-up: at least 8 is advised, with 4
+ * some lanes can end up queued behind each other).  With the environment
+ * variable MB_SERVER_TRACE=<file> each server appends one line per chunk
+ * (times, lane, solves, cells, tile shape) to <file> when destroyed. */
 int mb_server_create(int hip_device, size_t hbm_budget, int32_t max_slots, int32_t precision,
                      int32_t chunk_steps, mb_server **out);
 /* Queues a request; `arrival_s` is its arrival time in seconds after the

@@ -358,10 +358,10 @@ template <int N, typename R, int B, int L>
 struct TileShared {
   static constexpr int GM = L > 1 ? mat_m(N) : 1;
   static constexpr int GB = L > 1 ? B : 1;
-  R se[B], sh[B], se2[B];
+  R se[2][B], se2[B];  // E exchange (double-buffered by step parity), Mur exchange
   R src[kTileSources][kMaxChunk];
   TileRecs<N> trec;
-  R sy[GM][GB];  // rotated density rows of every cell (L > 1)
+  R sy[2][GM][GB];  // rotated density rows of every cell (L > 1), by step parity
 };
 
 // split tiles stay at <= 512 threads: a 1024-thread workgroup caps a wave at
@@ -452,6 +452,14 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
   }
   const bool hcell = in && c <= nx - 2;
   const bool ecell = in && c >= 1 && c <= nx - 2;
+  // H at the left node (cell c-1) is advanced here too, with the arithmetic
+  // of the lane that owns it, so no exchange of H is needed
+  const bool hleft = in && c >= 1;
+  R hl = 0, chl = 0;
+  if (hleft) {
+    hl = h_in[c - 1];
+    chl = mtab[int(sim.mat_h[c - 1]) * S + kCoefH];
+  }
   const bool left = in && nx > 1 && c == 0, right = in && nx > 1 && c == nx - 1;
   const bool mur_tile = nx > 1 && ((sim.edge_l == 1 && lo <= 0 && 0 < lo + B) ||
                                    (sim.edge_r == 1 && lo <= nx - 1 && nx - 1 < lo + B));
@@ -528,20 +536,44 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
     }
   };
 
+  // density rows of this wave group rotated by the field phases of E and
+  // published for the other groups (L > 1); the rotation of step s + 1 runs
+  // at the end of step s, so one barrier per step covers E and the rows
+  auto rotate_publish = [&](int buf) {
+    if constexpr (L > 1 && N > 0) {
+      per_material([&](const auto &mt, int) {
+        CL::template rotate<L, SUB>(x, e, mt);
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+          if (SP::owns(SUB, a)) sm.sy[buf][a][l] = x[a];
+      });
+    }
+  };
+  rotate_publish(0);
+
   for (int s = 0; s < ks; ++s) {
     const uint32_t n1 = uint32_t(ls0 + s + 1);
     const bool rec_now = rec_here && n1 % rec_every == 0u;
+    const int buf = s & 1;
     R er, el;
     if constexpr (WAVE) {
       er = lane_from_right(e);
       el = lane_from_left(e);
     } else {
-      if (SUB == 0) sm.se[l] = e;
+      if (SUB == 0) sm.se[buf][l] = e;
       __syncthreads();
-      er = l + 1 < B ? sm.se[l + 1] : R(0);
-      el = l > 0 ? sm.se[l - 1] : R(0);
+      er = l + 1 < B ? sm.se[buf][l + 1] : R(0);
+      el = l > 0 ? sm.se[buf][l - 1] : R(0);
+    }
+    if constexpr (L > 1 && N > 0) {
+      if (qm) {
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+          if (!SP::owns(SUB, a)) x[a] = sm.sy[buf][a][l];
+      }
     }
     if (hcell) h = fma(ch, er - e, h);
+    if (hleft) hl = fma(chl, e - el, hl);
     R p = 0;
     if constexpr (N > 0) {
       auto finish = [&](const auto &mt, int mm) {
@@ -562,31 +594,8 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
           finish(mt, mm);
         });
       } else {
-        per_material([&](const auto &mt, int) {
-          CL::template rotate<L, SUB>(x, e, mt);
-#pragma unroll
-          for (int a = 0; a < M; ++a)
-            if (SP::owns(SUB, a)) sm.sy[a][l] = x[a];
-        });
-        if (SUB == 0) sm.sh[l] = h;
-        __syncthreads();
-        if (qm) {
-#pragma unroll
-          for (int a = 0; a < M; ++a)
-            if (!SP::owns(SUB, a)) x[a] = sm.sy[a][l];
-        }
         per_material(finish);
       }
-    }
-    R hl;
-    if constexpr (WAVE) {
-      hl = lane_from_left(h);
-    } else {
-      if constexpr (L == 1 || N == 0) {
-        sm.sh[l] = h;
-        __syncthreads();
-      }
-      hl = l > 0 ? sm.sh[l - 1] : R(0);
     }
     const R eo = e;
     if (ecell) e = fma(cbd, h - hl, fma(ca, eo, -(cbg * p)));
@@ -624,6 +633,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
         record_fields(sim, c, n1, e, hcell ? h : R(0), qm, rb, re);
       }
     }
+    if (s + 1 < ks) rotate_publish(buf ^ 1);
   }
   if (own) {
     R *__restrict__ e_out = static_cast<R *>(sim.e[par ^ 1]);

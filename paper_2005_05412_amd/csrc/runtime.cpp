@@ -426,6 +426,12 @@ hipError_t Engine::sync_tables(hipStream_t st) {
   return hipSuccess;
 }
 
+int Engine::effective_lanes(int levels) const {
+  for (auto &g : groups_)
+    if (g.levels == levels) return group_lanes(g);
+  return 1;
+}
+
 int Engine::group_lanes(const Group &g) const {
   int want = lanes_;
   if (want == 0) {

@@ -96,6 +96,8 @@ class Engine {
   int chunk_steps() const { return halo_ < 256 ? halo_ : 256; }
   int block() const { return block_; }
   int lanes() const { return lanes_; }
+  // waves per 64 cells the next launch of the group of this level count uses
+  int effective_lanes(int levels) const;
   bool vc() const { return vc_; }
   int variant() const { return variant_; }
   int precision() const { return precision_; }

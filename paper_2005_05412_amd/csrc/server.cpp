@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -53,6 +55,14 @@ struct Lane {
   bool in_flight = false;
   bool changed = false;       // membership changed since the last chunk
   std::vector<Request *> running;
+  double t_launch = 0;        // host time of the chunk in flight
+};
+
+// one line of the optional chunk trace (MB_SERVER_TRACE=<file>)
+struct ChunkTrace {
+  double t_launch, t_done;
+  int levels, sims, block, halo, lanes;
+  int64_t cells;
 };
 
 struct mb_server {
@@ -62,7 +72,10 @@ struct mb_server {
   int chunk_steps = 32;
   std::map<int, Lane> lanes;  // by level count
   Arena arena;
-  hipStream_t side = nullptr;
+  // streams created together at start-up (so that they land on different
+  // hardware queues), handed to the lanes in order of creation
+  static constexpr int kStreams = 4;
+  hipStream_t pool[kStreams] = {};
   std::mutex mu;
   std::condition_variable cv;
   std::thread worker;
@@ -77,6 +90,8 @@ struct mb_server {
   int64_t chunks = 0;
   double cell_updates_retired = 0;
   std::string worker_error;
+  bool tracing = false;
+  std::vector<ChunkTrace> trace;
 
   double now() const { return std::chrono::duration<double>(clk::now() - t0).count(); }
   void loop();
@@ -115,8 +130,8 @@ int mb_server::lane_for(int levels, std::string &err) {
   ln.eng = std::make_unique<Engine>(device, precision, MB_VARIANT_BLOCKED, block, halo, false, 0);
   int rc = ln.eng->init(err);
   if (rc < 0) return rc;
-  if (hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&ln.done, hipEventDisableTiming) != hipSuccess ||
+  ln.stream = pool[lanes.size() % kStreams];
+  if (hipEventCreateWithFlags(&ln.done, hipEventDisableTiming) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void **>(&ln.status), Engine::kMaxStatusSlots * sizeof(int32_t),
                     hipHostMallocDefault) != hipSuccess) {
     err = "stream or pinned buffer creation failed";
@@ -164,6 +179,7 @@ hipError_t mb_server::launch(Lane &ln) {
   if (he == hipSuccess) he = hipEventRecord(ln.done, ln.stream);
   if (he == hipSuccess) {
     ln.in_flight = true;
+    ln.t_launch = now();
     ++chunks;
   }
   return he;
@@ -172,6 +188,9 @@ hipError_t mb_server::launch(Lane &ln) {
 // after the lane's chunk completed (or failed): status, retirements
 void mb_server::finish(Lane &ln, hipError_t he) {
   ln.in_flight = false;
+  if (tracing)
+    trace.push_back(ChunkTrace{ln.t_launch, now(), ln.levels, int(ln.running.size()), ln.eng->block(),
+                               ln.eng->depth(), ln.eng->effective_lanes(ln.levels), ln.eng->total_cells()});
   const int32_t *status = ln.status;
   if (he != hipSuccess) {
     worker_error = hipGetErrorString(he);
@@ -230,7 +249,7 @@ void mb_server::loop() {
         ++it;
         continue;
       }
-      int id = ln.eng->add(std::move(r->plan), &arena, side, err);
+      int id = ln.eng->add(std::move(r->plan), &arena, ln.stream, err);
       if (id == MB_ERR_BUDGET) break;  // fragmentation: retry after the next retirement
       it = queue.erase(it);
       if (id < 0) {
@@ -312,9 +331,10 @@ int mb_server_create(int hip_device, size_t hbm_budget, int32_t max_slots, int32
   if (hipSetDevice(hip_device) != hipSuccess) return fail(MB_ERR_HIP, "hipSetDevice failed");
   int rc;
   if ((rc = s->arena.init(hbm_budget, err)) < 0) return fail(rc, err);
-  if (hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking) != hipSuccess)
-    return fail(MB_ERR_HIP, "stream creation failed");
+  for (auto &q : s->pool)
+    if (hipStreamCreateWithFlags(&q, hipStreamNonBlocking) != hipSuccess) return fail(MB_ERR_HIP, "stream creation failed");
   s->t0 = clk::now();
+  s->tracing = std::getenv("MB_SERVER_TRACE") != nullptr;
   *out = s.release();
   return MB_OK;
 }
@@ -448,15 +468,24 @@ int mb_server_destroy(mb_server *s) {
     s->cv.notify_all();
   }
   if (s->worker.joinable()) s->worker.join();
+  if (s->tracing) {
+    if (FILE *f = std::fopen(std::getenv("MB_SERVER_TRACE"), "a")) {
+      std::fprintf(f, "# server: t_launch t_done levels sims cells block halo lanes\n");
+      for (const ChunkTrace &c : s->trace)
+        std::fprintf(f, "%.6f %.6f %d %d %lld %d %d %d\n", c.t_launch, c.t_done, c.levels, c.sims,
+                     static_cast<long long>(c.cells), c.block, c.halo, c.lanes);
+      std::fclose(f);
+    }
+  }
   (void)hipSetDevice(s->device);
   for (auto &[lv, ln] : s->lanes) {
     if (ln.stream) (void)hipStreamSynchronize(ln.stream);
     ln.eng.reset();
     if (ln.status) (void)hipHostFree(ln.status);
     if (ln.done) (void)hipEventDestroy(ln.done);
-    if (ln.stream) (void)hipStreamDestroy(ln.stream);
   }
-  if (s->side) (void)hipStreamDestroy(s->side);
+  for (auto &q : s->pool)
+    if (q) (void)hipStreamDestroy(q);
   delete s;
   return MB_OK;
 }
