@@ -155,8 +155,8 @@ typedef struct mb_scenario_desc {
   int32_t block;             /* blocked variant: cells per tile (0 = default) */
   int32_t depth;             /* blocked variant: steps per launch = halo width (0 = default) */
   int32_t lanes;             /* blocked variant: waves per 64 cells that share each cell's
-                                density update, 1, 2 or 4 (0 = default); results do not
-                                depend on it */
+                                density update, 1, 2, 4 or 8 (8: 4 to 6 levels, 64-cell
+                                tiles; 0 = default); results do not depend on it */
   const double *rho_diag;    /* N reals: initial density matrix (ic_density_const) */
   const double *rho_off;     /* N(N-1)/2 complex (re, im) */
   const double *e_init;      /* nx initial E values, or NULL for zero */

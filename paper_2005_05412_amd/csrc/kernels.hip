@@ -368,7 +368,7 @@ struct TileShared {
 // 128 registers, below what the density update needs
 template <int N, typename R, int B, int L>
 constexpr bool shape_fits() {
-  return (L == 1 || (N >= 2 && B * L <= 512)) && sizeof(TileShared<N, R, B, L>) <= 65536;
+  return (L == 1 || (N >= 2 && B * L <= 512 && (L < 8 || N >= 4))) && sizeof(TileShared<N, R, B, L>) <= 65536;
 }
 
 template <int N, typename R, int B, int L, bool VC, int SUB>
@@ -654,6 +654,21 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
   }
 }
 
+// runs the specialisation of wave group `sub` (wave-uniform); every group
+// executes the same sequence of barriers
+template <int N, typename R, int B, int L, bool VC, int S = 0>
+__device__ __forceinline__ void run_group(int sub, const DevSim *__restrict__ sims, const DevTile *__restrict__ tiles,
+                                          int64_t n0, int parity, int halo, int k, TileShared<N, R, B, L> &sm) {
+  if constexpr (S + 1 < L) {
+    if (sub == S)
+      tile_steps<N, R, B, L, VC, S>(sims, tiles, n0, parity, halo, k, sm);
+    else
+      run_group<N, R, B, L, VC, S + 1>(sub, sims, tiles, n0, parity, halo, k, sm);
+  } else {
+    tile_steps<N, R, B, L, VC, S>(sims, tiles, n0, parity, halo, k, sm);
+  }
+}
+
 template <int N, typename R, int B, int L, bool VC>
 __global__ void __launch_bounds__(B * L) k_blocked(const DevSim *__restrict__ sims,
                                                    const DevTile *__restrict__ tiles, int64_t n0, int parity,
@@ -662,19 +677,8 @@ __global__ void __launch_bounds__(B * L) k_blocked(const DevSim *__restrict__ si
   if constexpr (L == 1) {
     tile_steps<N, R, B, 1, VC, 0>(sims, tiles, n0, parity, halo, k, sm);
   } else {
-    // wave-uniform group index: each group runs its own specialisation, all
-    // with the same sequence of barriers
-    const int sub = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / B);
-    if (sub == 0) {
-      tile_steps<N, R, B, L, VC, 0>(sims, tiles, n0, parity, halo, k, sm);
-    } else if (sub == 1) {
-      tile_steps<N, R, B, L, VC, 1>(sims, tiles, n0, parity, halo, k, sm);
-    } else if constexpr (L == 4) {
-      if (sub == 2)
-        tile_steps<N, R, B, L, VC, 2>(sims, tiles, n0, parity, halo, k, sm);
-      else
-        tile_steps<N, R, B, L, VC, 3>(sims, tiles, n0, parity, halo, k, sm);
-    }
+    run_group<N, R, B, L, VC>(__builtin_amdgcn_readfirstlane(int(threadIdx.x) / B), sims, tiles, n0, parity, halo,
+                              k, sm);
   }
 }
 
@@ -839,6 +843,9 @@ hipError_t launch_blocked_nr(int block, int lanes, bool vc, const DevSim *sims, 
         return launch_blocked_b<N, R, 4, false>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
       }
       break;
+    case 8:  // 64-cell tiles of the large density updates only
+      if constexpr (N >= 4) return launch_blocked_b<N, R, 8, false>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+      break;
   }
   return hipErrorInvalidValue;
 }
@@ -874,6 +881,7 @@ bool fits_n(int block, int lanes) {
     case 1: return f(std::integral_constant<int, 1>());
     case 2: return f(std::integral_constant<int, 2>());
     case 4: return f(std::integral_constant<int, 4>());
+    case 8: return N >= 4 && f(std::integral_constant<int, 8>());
   }
   return false;
 }

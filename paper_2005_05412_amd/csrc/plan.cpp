@@ -525,8 +525,8 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
     err = "unknown variant";
     return MB_ERR_ARG;
   }
-  if (scen->lanes != 0 && scen->lanes != 1 && scen->lanes != 2 && scen->lanes != 4) {
-    err = "lanes must be 0, 1, 2 or 4";
+  if (scen->lanes != 0 && scen->lanes != 1 && scen->lanes != 2 && scen->lanes != 4 && scen->lanes != 8) {
+    err = "lanes must be 0, 1, 2, 4 or 8";
     return MB_ERR_ARG;
   }
   if (scen->variant == MB_VARIANT_PLAIN && scen->precision != 64) {

@@ -197,8 +197,8 @@ int Engine::init(std::string &err) {
       err = "blocked variant needs block in {64,128,256,512,1024} and 1 <= depth < block/2";
       return MB_ERR_ARG;
     }
-    if (lanes_ != 0 && lanes_ != 1 && lanes_ != 2 && lanes_ != 4) {
-      err = "lanes must be 0, 1, 2 or 4";
+    if (lanes_ != 0 && lanes_ != 1 && lanes_ != 2 && lanes_ != 4 && lanes_ != 8) {
+      err = "lanes must be 0, 1, 2, 4 or 8";
       return MB_ERR_ARG;
     }
   }
@@ -438,7 +438,7 @@ int Engine::group_lanes(const Group &g) const {
     // enough waves for about two per SIMD (4 SIMDs per compute unit)
     const int64_t waves1 = int64_t(g.n_tiles) * (block_ / 64);
     const int64_t target = 8 * int64_t(n_cu_);
-    want = waves1 * 4 <= target ? 4 : waves1 * 2 <= target ? 2 : 1;
+    want = waves1 * 8 <= target ? 8 : waves1 * 4 <= target ? 4 : waves1 * 2 <= target ? 2 : 1;
   }
   for (int l = want; l > 1; l /= 2)
     if (shape_supported(g.levels, precision_, block_, l)) return l;
@@ -582,7 +582,8 @@ hipError_t Engine::enqueue_status(hipStream_t st, int32_t *host) {
 
 int Engine::reshape(int block, int halo, int lanes, std::string &err) {
   if (variant_ == MB_VARIANT_PLAIN) return MB_OK;
-  if (!block_supported(block) || halo < 1 || 2 * halo >= block || (lanes != 0 && lanes != 1 && lanes != 2 && lanes != 4)) {
+  if (!block_supported(block) || halo < 1 || 2 * halo >= block ||
+      (lanes != 0 && lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8)) {
     err = "bad tile shape";
     return MB_ERR_ARG;
   }

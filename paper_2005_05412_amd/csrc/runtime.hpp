@@ -56,7 +56,7 @@ size_t sim_bytes(const SimPlan &p, int precision, bool plain);
 class Engine {
  public:
   // vc: keep the quantum coefficients of single-material waves in registers;
-  // lanes: waves per 64 cells sharing each cell's density update (1, 2, 4;
+  // lanes: waves per 64 cells sharing each cell's density update (1, 2, 4, 8;
   // a level count without a kernel for that many uses the next smaller), or
   // 0 to choose per launch from the group's size (more waves per cell while
   // the group has too few tiles to fill the GPU)

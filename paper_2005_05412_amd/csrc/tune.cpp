@@ -43,7 +43,7 @@ void load_cache() {
   while (f >> key >> s.block >> s.halo >> vc >> s.lanes) {
     s.vc = vc != 0;
     if (block_supported(s.block) && s.halo >= 1 && 2 * s.halo < s.block &&
-        (s.lanes == 1 || s.lanes == 2 || s.lanes == 4))
+        (s.lanes == 1 || s.lanes == 2 || s.lanes == 4 || s.lanes == 8))
       g_cache[key] = s;
   }
 }
@@ -79,7 +79,7 @@ std::vector<Shape> candidate_shapes(int levels, int precision) {
     out.push_back(Shape{b, h, false, 1});
     if (regs) out.push_back(Shape{b, h, true, 1});
   }
-  for (int lanes : {2, 4})
+  for (int lanes : {2, 4, 8})
     for (auto [b, h] : split) {
       if (!shape_supported(levels, precision, b, lanes)) continue;
       out.push_back(Shape{b, h, false, lanes});

@@ -76,7 +76,7 @@ def test_small_random_fp64_plain_and_blocked_vs_oracle(case):
     # every tile shape, coefficient placement and split of the density update
     # over 1, 2 or 4 waves per 64 cells runs the same per-cell arithmetic
     shapes = [(64, 1, 1), (64, 7, 1), (64, 20, 1), (128, 31, 1), (256, 32, 1), (512, 100, 1),
-              (64, 7, 2), (128, 31, 2), (256, 64, 2), (64, 20, 4), (128, 16, 4), (256, 32, 4)]
+              (64, 7, 2), (128, 31, 2), (256, 64, 2), (64, 20, 4), (128, 16, 4), (256, 32, 4), (64, 20, 8)]
     for block, depth, lanes in shapes:
         for variant in ("blocked", "blocked_regs"):
             blk = gpu_run(prob, precision=64, variant=variant, block=block, depth=depth, lanes=lanes)
@@ -294,7 +294,7 @@ def test_qcl6_full_grid_prefix_vs_oracle():
     got32 = gpu_run(prob, precision=32)
     assert max(rel_errors(prob, got32, ref).values()) <= QCL_FP32_TOL
     base = gpu_run(prob, precision=32, variant="blocked", block=256, depth=64, lanes=1)
-    for block, depth, lanes in ((256, 64, 2), (128, 32, 4), (64, 16, 4)):
+    for block, depth, lanes in ((256, 64, 2), (128, 32, 4), (64, 16, 4), (64, 16, 8)):
         _say(f"qcl6 prefix {block}/{depth} lanes {lanes}")
         assert_same(gpu_run(prob, precision=32, variant="blocked", block=block, depth=depth, lanes=lanes), base)
 
