@@ -29,7 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 # the serving leg runs one stream per level count; give HIP enough hardware
 # queues (read at HIP start-up) that they do not share one
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or 4) < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
 import paper_2005_05412_amd as mb  # noqa: E402
 import workloads as W  # noqa: E402

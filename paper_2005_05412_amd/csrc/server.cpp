@@ -73,9 +73,13 @@ struct mb_server {
   std::map<int, Lane> lanes;  // by level count
   Arena arena;
   // streams created together at start-up (so that they land on different
-  // hardware queues), handed to the lanes in order of creation
+  // hardware queues).  With at least 8 hardware queues per process every lane
+  // gets its own stream (up to 4); with fewer, the lanes of 2 and 3 levels
+  // share one stream and those of 4 to 6 levels another, so that a slow lane
+  // never queues a fast one behind its chunks.
   static constexpr int kStreams = 4;
   hipStream_t pool[kStreams] = {};
+  int n_pool = kStreams;
   std::mutex mu;
   std::condition_variable cv;
   std::thread worker;
@@ -130,7 +134,10 @@ int mb_server::lane_for(int levels, std::string &err) {
   ln.eng = std::make_unique<Engine>(device, precision, MB_VARIANT_BLOCKED, block, halo, false, 0);
   int rc = ln.eng->init(err);
   if (rc < 0) return rc;
-  ln.stream = pool[lanes.size() % kStreams];
+  if (n_pool == kStreams)
+    ln.stream = pool[lanes.size() % kStreams];
+  else
+    ln.stream = pool[levels >= 4 ? 1 : 0];
   if (hipEventCreateWithFlags(&ln.done, hipEventDisableTiming) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void **>(&ln.status), Engine::kMaxStatusSlots * sizeof(int32_t),
                     hipHostMallocDefault) != hipSuccess) {
@@ -331,8 +338,14 @@ int mb_server_create(int hip_device, size_t hbm_budget, int32_t max_slots, int32
   if (hipSetDevice(hip_device) != hipSuccess) return fail(MB_ERR_HIP, "hipSetDevice failed");
   int rc;
   if ((rc = s->arena.init(hbm_budget, err)) < 0) return fail(rc, err);
-  for (auto &q : s->pool)
-    if (hipStreamCreateWithFlags(&q, hipStreamNonBlocking) != hipSuccess) return fail(MB_ERR_HIP, "stream creation failed");
+  {
+    const char *hq = std::getenv("GPU_MAX_HW_QUEUES");
+    const int queues = hq ? std::atoi(hq) : 4;
+    s->n_pool = queues >= 8 ? mb_server::kStreams : 2;
+  }
+  for (int i = 0; i < s->n_pool; ++i)
+    if (hipStreamCreateWithFlags(&s->pool[i], hipStreamNonBlocking) != hipSuccess)
+      return fail(MB_ERR_HIP, "stream creation failed");
   s->t0 = clk::now();
   s->tracing = std::getenv("MB_SERVER_TRACE") != nullptr;
   *out = s.release();
