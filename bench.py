@@ -296,7 +296,8 @@ def main(argv=None):
     ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--only", default="",
                     help="comma list of optional legs to run (fp64,cpu,batch,configs,serve); others are skipped")
-    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests of the 200/s Poisson trace (2000 = the full 10 s trace)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one device-to-device copy of this size (counter calibration)")
     ap.add_argument("--out", default="")
