@@ -287,7 +287,8 @@ def main(argv=None):
     ap.add_argument("--nt", type=int, default=200000)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--depth", type=int, default=0)
-    ap.add_argument("--lanes", type=int, default=0, help="waves per 64 cells (1, 2, 4; 0 = tuned)")
+    ap.add_argument("--lanes", type=int, default=0, help="waves per 64 cells (1, 2, 4, 8; 0 = tuned)")
+    ap.add_argument("--regs", action="store_true", help="with --block/--depth/--lanes: coefficients in registers")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -322,7 +323,7 @@ def main(argv=None):
 
     # ---- main leg: FP32 temporally blocked -------------------------------------------
     log(f"[bench] lambda3 fp32 blocked nx={prob['nx']} nt={prob['n_steps']}")
-    variant = "blocked" if (args.block or args.depth or args.lanes) else "auto"
+    variant = ("blocked_regs" if args.regs else "blocked") if (args.block or args.depth or args.lanes) else "auto"
     t_setup = time.perf_counter()
     s32 = mb.Solver(prob, precision=32, variant=variant, block=args.block, depth=args.depth, lanes=args.lanes)
     t_setup = time.perf_counter() - t_setup
