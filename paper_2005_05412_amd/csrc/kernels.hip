@@ -52,22 +52,39 @@ __device__ __forceinline__ cptr<T> kconst(const void *p) {
 // phase per step is E dt (lam_j - lam_k)/hbar, a few 1e-2 rad) use the
 // Taylor series truncated where the remainder drops below half an ulp;
 // larger ones use the library sincos of t/2 with cos t - 1 = -2 sin^2(t/2).
-__device__ __forceinline__ void phase(double t, double &cm, double &sn) {
+__device__ __forceinline__ void phase_taylor(double t, double &cm, double &sn) {
+  const double t2 = t * t;
+  double s = fma(t2, -1.0 / 6227020800.0, 1.0 / 39916800.0);
+  s = fma(t2, s, -1.0 / 362880.0);
+  s = fma(t2, s, 1.0 / 5040.0);
+  s = fma(t2, s, -1.0 / 120.0);
+  s = fma(t2, s, 1.0 / 6.0);
+  sn = fma(-t * t2, s, t);  // t - t^3 (1/3! - t^2/5! + ...)
+  double c = fma(t2, 1.0 / 87178291200.0, -1.0 / 479001600.0);
+  c = fma(t2, c, 1.0 / 3628800.0);
+  c = fma(t2, c, -1.0 / 40320.0);
+  c = fma(t2, c, 1.0 / 720.0);
+  c = fma(t2, c, -1.0 / 24.0);
+  c = fma(t2, c, 0.5);
+  cm = -t2 * c;             // -(t^2/2! - t^4/4! + ...)
+}
+
+__device__ __forceinline__ void phase_taylor(float t, float &cm, float &sn) {
+  const float t2 = t * t;
+  float s = fmaf(t2, 1.0f / 362880.0f, -1.0f / 5040.0f);
+  s = fmaf(t2, s, 1.0f / 120.0f);
+  s = fmaf(t2, s, -1.0f / 6.0f);
+  sn = fmaf(t * t2, s, t);
+  float c = fmaf(t2, -1.0f / 3628800.0f, 1.0f / 40320.0f);
+  c = fmaf(t2, c, -1.0f / 720.0f);
+  c = fmaf(t2, c, 1.0f / 24.0f);
+  c = fmaf(t2, c, -0.5f);
+  cm = t2 * c;
+}
+
+__device__ __forceinline__ void phase_general(double t, double &cm, double &sn) {
   if (fabs(t) <= 0.25) {
-    const double t2 = t * t;
-    double s = fma(t2, -1.0 / 6227020800.0, 1.0 / 39916800.0);
-    s = fma(t2, s, -1.0 / 362880.0);
-    s = fma(t2, s, 1.0 / 5040.0);
-    s = fma(t2, s, -1.0 / 120.0);
-    s = fma(t2, s, 1.0 / 6.0);
-    sn = fma(-t * t2, s, t);  // t - t^3 (1/3! - t^2/5! + ...)
-    double c = fma(t2, 1.0 / 87178291200.0, -1.0 / 479001600.0);
-    c = fma(t2, c, 1.0 / 3628800.0);
-    c = fma(t2, c, -1.0 / 40320.0);
-    c = fma(t2, c, 1.0 / 720.0);
-    c = fma(t2, c, -1.0 / 24.0);
-    c = fma(t2, c, 0.5);
-    cm = -t2 * c;             // -(t^2/2! - t^4/4! + ...)
+    phase_taylor(t, cm, sn);
   } else {
     double s, c;
     sincos(0.5 * t, &s, &c);
@@ -76,18 +93,9 @@ __device__ __forceinline__ void phase(double t, double &cm, double &sn) {
   }
 }
 
-__device__ __forceinline__ void phase(float t, float &cm, float &sn) {
+__device__ __forceinline__ void phase_general(float t, float &cm, float &sn) {
   if (fabsf(t) <= 0.5f) {
-    const float t2 = t * t;
-    float s = fmaf(t2, 1.0f / 362880.0f, -1.0f / 5040.0f);
-    s = fmaf(t2, s, 1.0f / 120.0f);
-    s = fmaf(t2, s, -1.0f / 6.0f);
-    sn = fmaf(t * t2, s, t);
-    float c = fmaf(t2, -1.0f / 3628800.0f, 1.0f / 40320.0f);
-    c = fmaf(t2, c, -1.0f / 720.0f);
-    c = fmaf(t2, c, 1.0f / 24.0f);
-    c = fmaf(t2, c, -0.5f);
-    cm = t2 * c;
+    phase_taylor(t, cm, sn);
   } else {
     float s, c;
     sincosf(0.5f * t, &s, &c);
@@ -96,9 +104,17 @@ __device__ __forceinline__ void phase(float t, float &cm, float &sn) {
   }
 }
 
-// Split of one cell's density update over L waves (wave group s of L owns
-// a subset of the M state rows): coherence pairs (two rows each) are dealt
-// round-robin, then populations go one by one to the least-loaded group.
+// the whole wave takes the polynomial without a divergent branch when every
+// active lane's angle is small (the usual case); per-lane choice otherwise
+template <typename R>
+__device__ __forceinline__ void phase(R t, R &cm, R &sn) {
+  const R lim = sizeof(R) == 8 ? R(0.25) : R(0.5);
+  if (__builtin_amdgcn_ballot_w64(!(fabs(t) <= lim)) == 0)
+    phase_taylor(t, cm, sn);
+  else
+    phase_general(t, cm, sn);
+}
+
 template <int N, int L>
 struct Split {
   static constexpr int M = mat_m(N);
@@ -423,31 +439,33 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
     }
   }
   // sources inside this tile: their values for the whole chunk are staged in
-  // LDS (ordered before the first read by the first barrier of the loop)
-  int src_cell[kTileSources];
-  bool src_hard[kTileSources];
-#pragma unroll
-  for (int t = 0; t < kTileSources; ++t) {
-    src_cell[t] = -1;
-    src_hard[t] = false;
-  }
+  // LDS (ordered before the first read by the first barrier of the loop); a
+  // lane knows the one staged source at its cell.  Tiles with more than
+  // kTileSources sources, or two at one cell, read the source tables directly.
+  int my_src = -1;
+  bool my_hard = false;
+  int staged_cell[kTileSources];
   int n_ts = 0;
   bool src_direct = false;
   for (int j = 0; j < sim.n_src; ++j) {
     const DevSource sj = sim.src[j];
     const int cell = int(sj.cell);
     if (cell < lo || cell >= lo + B) continue;
-    if (n_ts == kTileSources) {
+    bool dup = false;
+#pragma unroll
+    for (int t = 0; t < kTileSources; ++t) dup = dup || (t < n_ts && staged_cell[t] == cell);
+    if (n_ts == kTileSources || dup) {
       src_direct = true;
       break;
     }
     for (int q = int(threadIdx.x); q < ks; q += B * L) sm.src[n_ts][q] = R(sj.table[ls0 + q + 1]);
 #pragma unroll
     for (int t = 0; t < kTileSources; ++t)
-      if (t == n_ts) {
-        src_cell[t] = cell;
-        src_hard[t] = sj.hard != 0;
-      }
+      if (t == n_ts) staged_cell[t] = cell;
+    if (cell == c) {
+      my_src = n_ts;
+      my_hard = sj.hard != 0;
+    }
     ++n_ts;
   }
   const bool hcell = in && c <= nx - 2;
@@ -485,6 +503,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
     }
   }
   const bool rec_here = SUB == 0 && own && (re > rb || sim.n_rec_all > 0);
+  const bool rec_tile = sim.rec_first != nullptr || sim.n_rec_all > 0;  // uniform
   const uint32_t rec_every = uint32_t(sim.rec_every);
   const R kap_l = R(sim.kap_l), kap_r = R(sim.kap_r);
 
@@ -553,7 +572,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
 
   for (int s = 0; s < ks; ++s) {
     const uint32_t n1 = uint32_t(ls0 + s + 1);
-    const bool rec_now = rec_here && n1 % rec_every == 0u;
+    const bool rec_step = rec_tile && n1 % rec_every == 0u;  // uniform: a recording step
     const int buf = s & 1;
     R er, el;
     if constexpr (WAVE) {
@@ -572,18 +591,20 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
           if (!SP::owns(SUB, a)) x[a] = sm.sy[buf][a][l];
       }
     }
-    if (hcell) h = fma(ch, er - e, h);
-    if (hleft) hl = fma(chl, e - el, hl);
+    h = hcell ? fma(ch, er - e, h) : h;
+    hl = hleft ? fma(chl, e - el, hl) : hl;
     R p = 0;
     if constexpr (N > 0) {
       auto finish = [&](const auto &mt, int mm) {
         p = CL::polar(x, mt);
-        if (rec_now) {
-          if (rec_lds) {
-            sm.trec.density(n1, x, rb, re);
-            record_density_all<N, R>(sim, c, n1, mm, x);
-          } else {
-            record_density<N, R>(sim, c, n1, mm, x, rb, re);
+        if (rec_step) {
+          if (rec_here) {
+            if (rec_lds) {
+              sm.trec.density(n1, x, rb, re);
+              record_density_all<N, R>(sim, c, n1, mm, x);
+            } else {
+              record_density<N, R>(sim, c, n1, mm, x, rb, re);
+            }
           }
         }
         CL::template propagate<L, SUB>(x, mt);
@@ -598,7 +619,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
       }
     }
     const R eo = e;
-    if (ecell) e = fma(cbd, h - hl, fma(ca, eo, -(cbg * p)));
+    e = ecell ? fma(cbd, h - hl, fma(ca, eo, -(cbg * p))) : e;
     if (mur_tile) {
       R enr, enl;
       if constexpr (WAVE) {
@@ -610,27 +631,24 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
         enr = l + 1 < B ? sm.se2[l + 1] : R(0);
         enl = l > 0 ? sm.se2[l - 1] : R(0);
       }
-      if (mur_l) e = fma(kap_l, enr - eo, er);
-      if (mur_r) e = fma(kap_r, enl - eo, el);
+      e = mur_l ? fma(kap_l, enr - eo, er) : e;
+      e = mur_r ? fma(kap_r, enl - eo, el) : e;
     }
-    if (pec) e = 0;
+    e = pec ? R(0) : e;
     if (src_direct) {
       if (in) e = apply_sources(sim, c, n1, e);
-    } else {
-#pragma unroll
-      for (int t = 0; t < kTileSources; ++t) {
-        if (t < n_ts && c == src_cell[t]) {
-          const R v = sm.src[t][s];
-          e = src_hard[t] ? v : e + v;
-        }
-      }
+    } else if (my_src >= 0) {
+      const R v = sm.src[my_src][s];
+      e = my_hard ? v : e + v;
     }
-    if (rec_now) {
-      if (rec_lds) {
-        sm.trec.fields(n1, e, hcell ? h : R(0), qm, rb, re);
-        record_fields_all(sim, c, n1, e, hcell ? h : R(0), qm);
-      } else {
-        record_fields(sim, c, n1, e, hcell ? h : R(0), qm, rb, re);
+    if (rec_step) {
+      if (rec_here) {
+        if (rec_lds) {
+          sm.trec.fields(n1, e, hcell ? h : R(0), qm, rb, re);
+          record_fields_all(sim, c, n1, e, hcell ? h : R(0), qm);
+        } else {
+          record_fields(sim, c, n1, e, hcell ? h : R(0), qm, rb, re);
+        }
       }
     }
     if (s + 1 < ks) rotate_publish(buf ^ 1);
