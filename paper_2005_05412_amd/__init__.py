@@ -294,10 +294,10 @@ def plan_readout(prob, record_id, material):
     return out
 
 
-def plan_status(prob):
+def plan_status(prob, precision=None, variant="auto", block=0, depth=0, lanes=0):
     """Status of planning a problem on the host: 0, a positive warning, or raises MBError."""
     lib = load()
-    m = _Marshal(prob)
+    m = _Marshal(prob, precision, variant, block, depth, lanes)
     out = np.zeros(4 * 36 * 36 + 64)
     n = C.c_int64()
     for k, mat in enumerate(prob["materials"]):

@@ -171,6 +171,16 @@ def test_status_codes():
     bad["sources"] = [W.source("sech", 99, 1.0, 1e14, 1.0, 1e14)]
     with pytest.raises(mb.MBError):
         mb.plan_status(bad)
+    # waves per 64 cells: 0 (default), 1, 2, 4 or 8
+    for lanes in (0, 1, 2, 4, 8):
+        assert mb.plan_status(_vac(), lanes=lanes) == 0
+    for lanes in (3, 16, -1):
+        with pytest.raises(mb.MBError) as ex:
+            mb.plan_status(_vac(), lanes=lanes)
+        assert ex.value.code == -1
+    with pytest.raises(mb.MBError) as ex:
+        mb.plan_status(_vac(), precision=32, variant="plain")
+    assert ex.value.code == -3
 
 
 def test_non_completely_positive_dephasing_warns():
