@@ -28,7 +28,12 @@ What it computes (paper sections cited per function):
 
 Readings of points the paper leaves open (also listed in the design notes):
 edges with R = 1 are a perfect electric conductor (E = 0), edges with R = 0
-are a first-order Mur absorbing boundary; sources are evaluated at t_{n+1};
+are a first-order Mur absorbing boundary, and edges with 0 < R < 1 (the
+semi-transparent mirrors of Sec. 2.1, whose mechanism the paper does not
+give) are a resistive termination: the edge node's half cell is loaded by an
+impedance Z_L = eta (1 - sqrt R)/(1 + sqrt R), eta the wave impedance of the
+edge material, whose normal-incidence amplitude reflection (Z_L - eta)/
+(Z_L + eta) = -sqrt(R); sources are evaluated at t_{n+1};
 a hard source sets E, a soft source adds to it; sech source
 s(t) = A sech(w t - shift) sin(2 pi f t + phi) and the Gaussian source
 s(t) = A exp(-(w t - shift)^2) sin(2 pi f t + phi); records are taken after
@@ -306,6 +311,23 @@ class Oracle:
         cl = light_speed(self.p["materials"][self.mat_e[cell]], self.c)
         return (cl * self.dt - self.dx) / (cl * self.dt + self.dx)
 
+    def _load_coeff(self, cell, refl):
+        """Half-cell update of an edge node terminated by Z_L (semi-transparent mirror).
+
+        Ampere's law over the half cell [edge, edge +- dx/2] with the load current
+        E/Z_L taken at t_{n+1/2} as the mean of E^n and E^{n+1}:
+            eps dx/2 (E^{n+1} - E^n)/dt = +-H_inner^{n+1/2} - (E^{n+1} + E^n)/(2 Z_L),
+        so E^{n+1} = g E^n +- d H_inner with a = dt/(eps dx Z_L), g = (1 - a)/(1 + a),
+        d = 2 dt/(eps dx)/(1 + a) (+ on the left edge, - on the right)."""
+        m = self.p["materials"][self.mat_e[cell]]
+        eps = self.c["eps0"] * m["eps_r"]
+        mu = self.c["mu0"] * m["mu_r"]
+        eta = math.sqrt(mu / eps)
+        sr = math.sqrt(refl)
+        zl = eta * (1.0 - sr) / (1.0 + sr)
+        a = self.dt / (eps * self.dx * zl)
+        return (1.0 - a) / (1.0 + a), 2.0 * self.dt / (eps * self.dx) / (1.0 + a)
+
     def _apply_edges_init(self):
         if self.nx < 2:
             return
@@ -355,13 +377,18 @@ class Oracle:
             self.e[m] = (self.ca[m] * e_old[m] - self.cb[m] * self.gam[m] * self.p_cur[m]
                          + self.cb[m] / self.dx * (self.h[1:] - self.h[:-1]))
             for side, cell, nb in ((0, 0, 1), (1, nx - 1, nx - 2)):
-                if self.p["refl"][side] == 1.0:
+                r = self.p["refl"][side]
+                if r == 1.0:
                     self.e[cell] = 0.0
-                elif self.p["refl"][side] == 0.0:
+                elif r == 0.0:
                     kap = self._mur_coeff(cell)
                     self.e[cell] = e_old[nb] + kap * (self.e[nb] - e_old[cell])
+                elif 0.0 < r < 1.0:
+                    g, d = self._load_coeff(cell, r)
+                    h_in = self.h[0] if side == 0 else -self.h[-1]
+                    self.e[cell] = g * e_old[cell] + d * h_in
                 else:
-                    raise ValueError("only reflectivities 0 and 1 are defined")
+                    raise ValueError("reflectivity outside [0, 1]")
         self._apply_sources((n + 1) * self.dt)
         self.step_index = n + 1
         self._record(n)

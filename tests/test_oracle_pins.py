@@ -317,6 +317,43 @@ def test_absorbing_and_reflecting_ends():
             assert e[-1][199] < -0.8 * 1e6
 
 
+@pytest.mark.parametrize("refl", [0.25, 0.64, 0.9])
+def test_semi_transparent_end_reflects_r_equal_minus_sqrt_R(refl):
+    """0 < R < 1 (semi-transparent mirror, Sec. 2.1): the reflected power fraction of a pulse
+    at normal incidence is R and the amplitude changes sign (impedance below the medium's),
+    from transmission-line theory, r = (Z_L - eta)/(Z_L + eta), independent of the scheme.
+    Measured in a dielectric (eps_r 12.96) so that the edge material enters."""
+    nx, mid = 1200, 600
+    x = np.arange(nx)
+    e0 = np.exp(-((x - mid) / 20.0) ** 2) * 1e6
+    mats = [W.vacuum(eps_r=12.96)]
+    prob = _vacuum_problem(nx, 0.5, 2800, refl=(refl, 0.0), e_init=e0, mats=mats,
+                           records=[W.record("e", "e", -1, 1)])
+    e = O.Oracle(prob).run()["e"]
+    # step 400: the two halves of the split pulse are apart, the left one still inside
+    left = np.sum(e[399][:mid] ** 2)
+    # step 2800: the left half came back from the left end, the right half left the grid
+    back = np.sum(e[2799] ** 2)
+    assert abs(back / left - refl) < 0.01 * refl
+    peak = e[2799][np.argmax(np.abs(e[2799]))]
+    assert peak < 0
+    assert abs(abs(peak) / (0.5e6 * math.sqrt(refl)) - 1.0) < 0.02
+
+
+def test_semi_transparent_end_limits():
+    """R -> 1 approaches the perfect conductor, R -> 0 a nearly matched end."""
+    nx = 600
+    x = np.arange(nx)
+    e0 = np.exp(-((x - 300) / 15.0) ** 2) * 1e6
+    out = {}
+    for refl in (1.0, 1.0 - 1e-8, 1e-8):
+        prob = _vacuum_problem(nx, 0.5, 900, refl=(refl, refl), e_init=e0,
+                               records=[W.record("e", "e", -1, 1)])
+        out[refl] = O.Oracle(prob).run()["e"][-1]
+    assert np.max(np.abs(out[1.0 - 1e-8] - out[1.0])) < 1e-3 * 1e6
+    assert np.sum(out[1e-8] ** 2) < 1e-3 * np.sum(e0 ** 2)
+
+
 # ---------------------------------------------------------------- energy exchange with the medium
 
 def _energy_drift(nx, steps):
