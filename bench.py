@@ -256,6 +256,15 @@ def other_configs(hip, stream, log):
     res["qcl_6lvl"] = {"nx": p["nx"], "n_steps": p["n_steps"], "fp32": cells / (ms32 * 1e-3),
                        "fp64": cells / (ms64 * 1e-3), "unit": "cell-updates/s",
                        "fp32_vs_fp64_max_rel_err": max_error(p, r32, r64), "shape_fp32": list(sh32)}
+    log("[bench] paper's 5-level QCL comb (R = 0.8 mirrors) fp32/fp64, 200000 steps")
+    p = W.qcl5_comb()
+    ms32, r32, sh32 = solve_once(hip, stream, p, 32)
+    ms64, r64, sh64 = solve_once(hip, stream, p, 64)
+    cells = p["nx"] * p["n_steps"]
+    res["qcl_5lvl_comb"] = {"nx": p["nx"], "n_steps": p["n_steps"], "fp32": cells / (ms32 * 1e-3),
+                            "fp64": cells / (ms64 * 1e-3), "unit": "cell-updates/s",
+                            "fp32_vs_fp64_max_rel_err": max_error(p, r32, r64), "shape_fp32": list(sh32),
+                            "shape_fp64": list(sh64)}
     log("[bench] sweep x8: 2048 sims fp32 (state beyond the 256 MB last-level cache)")
     sims = W.sweep(n_sims=2048, precision=32, seed=W.SEED_BASE + 13)
     bcells = sum(q["nx"] * q["n_steps"] for q in sims)
@@ -270,7 +279,7 @@ def other_configs(hip, stream, log):
     tb = time.perf_counter() - t0
     beff = sum(bytes_per_cell_update(2 if k % 2 == 0 else 3, 32) * q["nx"] * q["n_steps"]
                for k, q in enumerate(sims)) / tb / 1e9
-    state_bytes = sum(q["nx"] * (2 + (4 if k % 2 == 0 else 9)) * 4 for k, q in enumerate(sims))
+    state_bytes = sum(q["nx"] * (2 + (3 if k % 2 == 0 else 8)) * 4 for k, q in enumerate(sims))
     res["sweep_x8"] = {"sims": len(sims), "cell_updates": bcells, "value": bcells / tb, "unit": "cell-updates/s",
                        "wall_s": tb, "state_bytes_one_buffer": state_bytes, "hbm_effective_gbs": beff,
                        "hbm_effective_frac": beff / PEAK["hbm_gbs"], "shape": list(bt.shape())}

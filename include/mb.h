@@ -30,9 +30,12 @@
  *    x_{m+1/2}, m = 0..nx-2.  The material of a node is the first region
  *    with x_start <= x < x_end, else the first with x_start <= x <= x_end,
  *    else the right-most region if x exceeds the device by under dx/2.
- *  - Edges: reflectivity 1 is a perfect electric conductor (E = 0),
- *    reflectivity 0 a first-order Mur absorbing boundary.  Other values are
- *    rejected with MB_ERR_UNSUPPORTED.
+ *  - Edges (Sec. 2.1): reflectivity 1 is a perfect electric conductor
+ *    (E = 0), reflectivity 0 a first-order Mur absorbing boundary, and
+ *    0 < R < 1 (a semi-transparent mirror) a resistive load
+ *    Z_L = eta (1 - sqrt R)/(1 + sqrt R) on the edge node's half cell (eta:
+ *    wave impedance of the edge material), whose amplitude reflection at
+ *    normal incidence is -sqrt R.  Values outside [0, 1] are MB_ERR_ARG.
  *  - Sources act after each step at t_{n+1} = (n+1) dt: a hard source sets E
  *    at its cell, a soft source adds to it.  A hard source also sets E^0.
  *  - Records are sampled after step n when (n+1) is a multiple of their
@@ -63,7 +66,7 @@ extern "C" {
 #define MB_WARN_NOT_CP 1        /* pure dephasing admits no positive semi-definite C (Sec. 3.1.1) */
 #define MB_ERR_ARG -1           /* invalid argument or inconsistent description */
 #define MB_ERR_CFL -2           /* c_max * dt > dx: time step beyond the Courant limit (Sec. 3.2) */
-#define MB_ERR_UNSUPPORTED -3   /* level count outside 2..6, reflectivity outside {0, 1}, ... */
+#define MB_ERR_UNSUPPORTED -3   /* level count outside 2..6, plain variant in FP32, ... */
 #define MB_ERR_OOM -4           /* device allocation failed */
 #define MB_ERR_BUDGET -5        /* a request does not fit the server's device-memory budget */
 #define MB_ERR_HIP -6           /* a HIP runtime call failed */
@@ -120,7 +123,7 @@ typedef struct mb_region {
 
 typedef struct mb_device_desc {
   double length;             /* [m] */
-  double refl_left, refl_right;  /* 0 or 1 */
+  double refl_left, refl_right;  /* field reflectivity of each end, in [0, 1] */
   int32_t n_materials;       /* at most 255 */
   const mb_material *materials;
   int32_t n_regions;

@@ -40,8 +40,9 @@ struct DevSim {
   int64_t start;        // engine step at which this simulation's step 0 runs
   int32_t parity_off;   // buffer parity of the engine when the simulation joined
   int32_t n_src;
-  int32_t edge_l, edge_r;  // 0: perfect conductor, 1: first-order Mur
-  double kap_l, kap_r;
+  int32_t edge_l, edge_r;  // 0: perfect conductor, 1: first-order Mur, 2: impedance load
+  double kap_l, kap_r;      // Mur coefficients
+  double load_g_l, load_d_l, load_g_r, load_d_r;  // load edges: E' = g E + d H_{1/2} (left), g E - d H_{nx-3/2} (right)
   void *e[2], *h[2], *x[2];  // state buffers of element type R; x: M planes of nx
   void *p;                   // polarization scratch of the two-launch path
   const uint8_t *mat_e, *mat_h;

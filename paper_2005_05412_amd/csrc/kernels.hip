@@ -483,6 +483,8 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
                                    (sim.edge_r == 1 && lo <= nx - 1 && nx - 1 < lo + B));
   const bool mur_l = left && sim.edge_l == 1, mur_r = right && sim.edge_r == 1;
   const bool pec = (left && sim.edge_l == 0) || (right && sim.edge_r == 0);
+  const bool load_l = left && sim.edge_l == 2, load_r = right && sim.edge_r == 2;
+  const R lg_l = R(sim.load_g_l), ld_l = R(sim.load_d_l), lg_r = R(sim.load_g_r), ld_r = R(sim.load_d_r);
   // the cell's entries in the per-cell record table, fetched once per launch;
   // when the tile's owned cells hold at most kTileRecs entries they are
   // staged in LDS (visible after the first barrier) and [rb, re) index there.
@@ -635,6 +637,8 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
       e = mur_r ? fma(kap_r, enl - eo, el) : e;
     }
     e = pec ? R(0) : e;
+    e = load_l ? fma(lg_l, eo, ld_l * h) : e;        // H_{1/2} is this lane's own
+    e = load_r ? fma(lg_r, eo, -(ld_r * hl)) : e;    // H_{nx-3/2} is the tracked left node
     if (src_direct) {
       if (in) e = apply_sources(sim, c, n1, e);
     } else if (my_src >= 0) {
@@ -794,11 +798,14 @@ __global__ void __launch_bounds__(kPlainBlock) k_plain_e(const DevSim *__restric
     if (c >= 1 && c <= nx - 2) {
       e = plain_interior(sim, e_in, hh, pp, mtab, S, c);
     } else if (c == 0) {
-      e = sim.edge_l == 0 ? 0.0 : fma(sim.kap_l, plain_interior(sim, e_in, hh, pp, mtab, S, 1) - e_in[0], e_in[1]);
+      e = sim.edge_l == 0   ? 0.0
+          : sim.edge_l == 1 ? fma(sim.kap_l, plain_interior(sim, e_in, hh, pp, mtab, S, 1) - e_in[0], e_in[1])
+                            : fma(sim.load_g_l, e_in[0], sim.load_d_l * hh[0]);
     } else {
-      e = sim.edge_r == 0
-              ? 0.0
-              : fma(sim.kap_r, plain_interior(sim, e_in, hh, pp, mtab, S, nx - 2) - e_in[nx - 1], e_in[nx - 2]);
+      e = sim.edge_r == 0 ? 0.0
+          : sim.edge_r == 1
+              ? fma(sim.kap_r, plain_interior(sim, e_in, hh, pp, mtab, S, nx - 2) - e_in[nx - 1], e_in[nx - 2])
+              : fma(sim.load_g_r, e_in[nx - 1], -(sim.load_d_r * hh[nx - 2]));
     }
   }
   e = apply_sources(sim, c, n1, e);

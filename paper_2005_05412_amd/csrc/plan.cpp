@@ -539,9 +539,9 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
     return MB_ERR_ARG;
   }
   for (double r : {dev->refl_left, dev->refl_right})
-    if (r != 0.0 && r != 1.0) {
-      err = "only reflectivities 0 (absorbing) and 1 (mirror) are supported";
-      return MB_ERR_UNSUPPORTED;
+    if (!(r >= 0.0 && r <= 1.0)) {
+      err = "reflectivities must lie in [0, 1]";
+      return MB_ERR_ARG;
     }
   for (int r = 0; r < dev->n_regions; ++r)
     if (dev->regions[r].material < 0 || dev->regions[r].material >= dev->n_materials) {
@@ -622,13 +622,27 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
       build_quantum(plan.mats[i], qms[i], plan.dt, k);
       if (plan.mats[i].min_gram_eig < -1e-9) plan.warn = MB_WARN_NOT_CP;
     }
-  // edges
-  plan.edge_l = dev->refl_left == 1.0 ? 0 : 1;
-  plan.edge_r = dev->refl_right == 1.0 ? 0 : 1;
+  // edges (Sec. 2.1): R = 1 perfect conductor, R = 0 first-order Mur, 0 < R < 1 a
+  // resistive load Z_L = eta (1 - sqrt R)/(1 + sqrt R) on the edge node's half cell,
+  // amplitude reflection -sqrt R; Ampere's law over the half cell with the load
+  // current at t_{n+1/2} gives E' = g E +- d H_inner, a = dt/(eps dx Z_L),
+  // g = (1 - a)/(1 + a), d = 2 dt/(eps dx)/(1 + a)
+  auto edge_kind = [](double r) { return r == 1.0 ? 0 : r == 0.0 ? 1 : 2; };
+  plan.edge_l = edge_kind(dev->refl_left);
+  plan.edge_r = edge_kind(dev->refl_right);
   if (nx > 1) {
     double cl = plan.mats[plan.mat_e[0]].c_light, cr = plan.mats[plan.mat_e[nx - 1]].c_light;
     plan.kap_l = (cl * plan.dt - plan.dx) / (cl * plan.dt + plan.dx);
     plan.kap_r = (cr * plan.dt - plan.dx) / (cr * plan.dt + plan.dx);
+    auto load = [&](const MaterialPlan &mp, double r, double &g, double &d) {
+      const double eps = k.eps0 * mp.eps_r, mu = k.mu0 * mp.mu_r;
+      const double sr = std::sqrt(r), zl = std::sqrt(mu / eps) * (1.0 - sr) / (1.0 + sr);
+      const double a = plan.dt / (eps * plan.dx * zl);
+      g = (1.0 - a) / (1.0 + a);
+      d = 2.0 * plan.dt / (eps * plan.dx) / (1.0 + a);
+    };
+    if (plan.edge_l == 2) load(plan.mats[plan.mat_e[0]], dev->refl_left, plan.load_g_l, plan.load_d_l);
+    if (plan.edge_r == 2) load(plan.mats[plan.mat_e[nx - 1]], dev->refl_right, plan.load_g_r, plan.load_d_r);
   }
   // sources: FP64 tables s(n dt), n = 0..n_steps
   if (scen->n_sources < 0 || (scen->n_sources > 0 && !scen->sources)) {

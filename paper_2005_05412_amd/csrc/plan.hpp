@@ -64,8 +64,9 @@ struct SimPlan {
   int block = 0, depth = 0, lanes = 0;
   std::vector<uint8_t> mat_e, mat_h;
   std::vector<MaterialPlan> mats;
-  int edge_l = 0, edge_r = 0;     // 0: PEC, 1: Mur
-  double kap_l = 0, kap_r = 0;
+  int edge_l = 0, edge_r = 0;     // 0: PEC, 1: Mur, 2: impedance load (0 < R < 1)
+  double kap_l = 0, kap_r = 0;    // Mur coefficients
+  double load_g_l = 0, load_d_l = 0, load_g_r = 0, load_d_r = 0;  // E' = g E +- d H_inner
   std::vector<SourcePlan> sources;
   std::vector<RecordPlan> records;
   std::vector<double> e0;         // nx

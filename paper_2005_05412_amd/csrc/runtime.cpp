@@ -322,6 +322,10 @@ int Engine::add(SimPlan &&plan, Arena *arena, hipStream_t st, std::string &err) 
   d.edge_r = p.edge_r;
   d.kap_l = p.kap_l;
   d.kap_r = p.kap_r;
+  d.load_g_l = p.load_g_l;
+  d.load_d_l = p.load_d_l;
+  d.load_g_r = p.load_g_r;
+  d.load_d_r = p.load_d_r;
   d.e[0] = dev + L.e;
   d.e[1] = dev + L.e + nx * rs;
   d.h[0] = dev + L.h;

@@ -57,6 +57,8 @@ SMALL = [
     dict(seed=16, N=3, nx=1, n_steps=200, refl=(0.0, 0.0)),
     dict(seed=17, N=0, nx=80, n_steps=120, refl=(0.0, 1.0)),
     dict(seed=18, N=2, nx=3, n_steps=25, refl=(0.0, 0.0)),
+    dict(seed=25, N=3, nx=120, n_steps=80, refl=(0.64, 0.3)),       # semi-transparent ends
+    dict(seed=26, N=5, nx=70, n_steps=40, refl=(0.8, 0.8), e_noise=1e6),
 ]
 
 
@@ -296,6 +298,26 @@ def test_qcl6_full_grid_prefix_vs_oracle():
     base = gpu_run(prob, precision=32, variant="blocked", block=256, depth=64, lanes=1)
     for block, depth, lanes in ((256, 64, 2), (128, 32, 4), (64, 16, 4), (64, 16, 8)):
         _say(f"qcl6 prefix {block}/{depth} lanes {lanes}")
+        assert_same(gpu_run(prob, precision=32, variant="blocked", block=block, depth=depth, lanes=lanes), base)
+
+
+def test_qcl5_comb_prefix_vs_oracle():
+    """The paper's five-level QCL comb example (8192 cells, R = 0.8 mirrors, noise start):
+    first 600 steps against the oracle; FP32 under the QCL bound; the density update
+    split over 4 and 8 waves gives the same bits."""
+    prob = W.qcl5_comb(n_steps=600)
+    _say("qcl5 oracle prefix")
+    ref = O.run(prob)
+    got = gpu_run(prob, precision=64)
+    errs = rel_errors(prob, got, ref)
+    _say(f"qcl5 fp64 {errs}")
+    assert max(errs.values()) <= TOL[64], errs
+    got32 = gpu_run(prob, precision=32)
+    errs32 = rel_errors(prob, got32, ref)
+    _say(f"qcl5 fp32 {errs32}")
+    assert max(errs32.values()) <= QCL_FP32_TOL, errs32
+    base = gpu_run(prob, precision=32, variant="blocked", block=256, depth=64, lanes=1)
+    for block, depth, lanes in ((128, 32, 4), (64, 16, 8)):
         assert_same(gpu_run(prob, precision=32, variant="blocked", block=block, depth=depth, lanes=lanes), base)
 
 

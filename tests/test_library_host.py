@@ -155,9 +155,11 @@ def test_status_codes():
     with pytest.raises(mb.MBError) as ex:
         mb.plan_status(_vac(courant=1.01))
     assert ex.value.code == -2
-    with pytest.raises(mb.MBError) as ex:
-        mb.plan_status(_vac(refl=(0.5, 0.0)))
-    assert ex.value.code == -3
+    assert mb.plan_status(_vac(refl=(0.5, 0.8))) == 0      # semi-transparent ends
+    for bad_r in ((1.5, 0.0), (0.0, -0.1)):
+        with pytest.raises(mb.MBError) as ex:
+            mb.plan_status(_vac(refl=bad_r))
+        assert ex.value.code == -1
     rng = np.random.default_rng(1)
     with pytest.raises(mb.MBError) as ex:
         mb.plan_status(_vac(levels_qm=W.random_qm(rng, 7)))

@@ -10,7 +10,7 @@ A *problem* is a dict:
 
 ``consts``     SI constants (CODATA 2018): hbar, e, c0, mu0, eps0.
 ``length``     device length L [m] (the grid spacing is L/(nx-1)).
-``refl``       (R_left, R_right) field reflectivity of the two ends, each 0 or 1.
+``refl``       (R_left, R_right) field reflectivity of the two ends, each in [0, 1].
 ``materials``  list of dicts: eps_r, mu_r, alpha0 [1/m], overlap (Gamma) and
                ``qm`` = None (no quantum system) or a dict with n3d [m^-3],
                h0_diag (N,) [J], h0_off (N(N-1)/2,) complex [J], mu_diag,
@@ -280,6 +280,49 @@ def qcl6(nx=8192, n_steps=1_000_000, precision=32, seed=None, rec_interval=1):
     rho[N - 1] = 1.0
     return make_problem("qcl-6lvl", L, mats, [(0.0, L, 0)], nx, dt, n_steps, rho,
                         refl=(1.0, 1.0), e_init=e_init, records=recs, precision=precision)
+
+
+def qcl5_comb(nx=8192, n_steps=200_000, precision=32, rec_interval=1, noise=1.0):
+    """The paper's quantum cascade laser frequency-comb example (Sec. 4.4, its C++ listing).
+
+    Five-level active region with the printed Hamiltonian (diagonal energies and the two
+    tunnelling couplings (1,3), (2,3), in eV), the single dipole element on the (3,4)
+    upper/lower laser transition (-e * 4 nm), the printed 5 x 5 scattering-rate matrix
+    (entry [i][j] read as the rate from level j into level i, the index order of the
+    population equation of Sec. 3.1.1), pure dephasing 1/(0.6 ps) on the injector pairs
+    (1,3), (2,3) and 1/(1 ps) elsewhere, n3d = 5.6e21 m^-3, background eps_r 12.96,
+    overlap 0.9, alpha0 1100 1/m, a 5 mm cavity with semi-transparent mirrors R = 0.8 at
+    both ends, all population in level 3, and the field at the left facet recorded.
+    The listing leaves the grid, the end time and the noise of the random initial field
+    open: nx cells at Courant 1/2, n_steps steps, uniform noise of amplitude `noise` V/m
+    from SplitMix64.
+    """
+    c = CODATA
+    ev = c["e"]
+    N = 5
+    en = np.array([0.10103, 0.09677, 0.09720, 0.08129, 0.07633]) * ev
+    h0_off = np.zeros(n_off(N), complex)
+    h0_off[1] = 1.2329e-3 * ev                   # (1,3)
+    h0_off[2] = -1.3447e-3 * ev                  # (2,3)
+    mu_off = np.zeros(n_off(N), complex)
+    mu_off[5] = -ev * 4e-9                       # (3,4)
+    rates = np.array([[0.0000000, 0.4947e12, 0.0974e12, 0.8116e12, 1.0410e12],
+                      [0.8245e12, 0.0000000, 0.1358e12, 0.6621e12, 1.1240e12],
+                      [0.0229e12, 0.0469e12, 0.0000000, 0.0794e12, 0.0357e12],
+                      [0.0047e12, 0.0029e12, 0.1252e12, 0.0000000, 0.2810e12],
+                      [0.0049e12, 0.0049e12, 0.1101e12, 0.4949e12, 0.0000000]])
+    inj, other = 1.0 / 0.6e-12, 1.0 / 1.0e-12
+    deph = np.array([0.0, inj, inj] + [other] * 7)
+    qm = general_qm(5.6e21, en, h0_off, None, mu_off, rates, deph)
+    L = 5e-3
+    mats = [qm_material(qm, eps_r=12.96, overlap=0.9, alpha0=1100.0)]
+    dt = courant_dt(L, nx, c["c0"] / math.sqrt(12.96))
+    e_init = noise * (2.0 * splitmix64_uniform(SEED_BASE + 5, nx) - 1.0)
+    recs = [record("e@facet", "e", 0, rec_interval)]
+    rho = np.zeros(N)
+    rho[2] = 1.0
+    return make_problem("qcl-5lvl-comb", L, mats, [(0.0, L, 0)], nx, dt, n_steps, rho,
+                        refl=(0.8, 0.8), e_init=e_init, records=recs, precision=precision)
 
 
 def sweep_sim(k, rng, nx=None, n_steps=50000, precision=32, rec_interval=50):
