@@ -5,11 +5,13 @@ The relative max-norm over recorded traces: for every record r,
     err_r = max |got_r - ref_r|  /  scale(class of r),
 
 where the scale of a class is the max-norm of the reference over all
-records of that class in the problem: the electric field (together with the
-source amplitudes), the magnetic field (source amplitudes divided by the
-vacuum impedance), or density-matrix quantities (populations, inversions and
-coherences).  A trace that stays near zero (an empty level, a field before the
-pulse arrives) is thus measured on the scale of its class, not on its own.
+records of that class in the problem: the electric field (together with what
+drives it: the source amplitudes and the max-norm of the initial field, e.g.
+the random field that starts a laser), the magnetic field (the same divided by
+the vacuum impedance), or density-matrix quantities (populations, inversions
+and coherences).  A trace that stays near zero (an empty level, a field before
+the pulse arrives, the field at a partly transparent facet) is thus measured
+on the scale of its class, not on its own.
 """
 from __future__ import annotations
 
@@ -23,6 +25,8 @@ _CLASS = {"e": "e", "h": "h", "pop": "rho", "inv": "rho", "rho_re": "rho", "rho_
 def class_scales(prob, ref):
     eta = math.sqrt(prob["consts"]["mu0"] / prob["consts"]["eps0"])
     amp = max([s["amp"] for s in prob["sources"]] + [0.0])
+    if prob.get("e_init") is not None:
+        amp = max(amp, float(np.max(np.abs(prob["e_init"]))))
     scale = {"e": amp, "h": amp / eta, "rho": 0.0}
     for r in prob["records"]:
         b = np.asarray(ref[r["name"]])
