@@ -380,11 +380,14 @@ struct TileShared {
   R sy[2][GM][GB];  // rotated density rows of every cell (L > 1), by step parity
 };
 
-// split tiles stay at <= 512 threads: a 1024-thread workgroup caps a wave at
-// 128 registers, below what the density update needs
+// split tiles stay at <= 512 threads (a 1024-thread workgroup caps a wave at
+// 128 registers, below what most density updates need), except FP32 with up
+// to 3 levels, whose waves fit in 128
 template <int N, typename R, int B, int L>
 constexpr bool shape_fits() {
-  return (L == 1 || (N >= 2 && B * L <= 512 && (L < 8 || N >= 4))) && sizeof(TileShared<N, R, B, L>) <= 65536;
+  constexpr int max_threads = (N <= 3 && sizeof(R) == 4) ? 1024 : 512;
+  return (L == 1 || (N >= 2 && B * L <= max_threads && (L < 8 || N >= 4))) &&
+         sizeof(TileShared<N, R, B, L>) <= 65536;
 }
 
 template <int N, typename R, int B, int L, bool VC, int SUB>

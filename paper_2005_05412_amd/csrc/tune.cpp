@@ -71,7 +71,7 @@ std::vector<Shape> candidate_shapes(int levels, int precision) {
   const std::vector<std::pair<int, int>> all = {{64, 8},   {64, 12},  {64, 16},   {64, 20},   {128, 16},
                                                 {128, 32}, {256, 32}, {256, 64},  {512, 64},  {512, 128},
                                                 {512, 192}, {1024, 128}, {1024, 256}};
-  const std::vector<std::pair<int, int>> split = {{64, 16}, {128, 32}, {256, 32}, {256, 64}};
+  const std::vector<std::pair<int, int>> split = {{64, 16}, {128, 32}, {256, 32}, {256, 64}, {512, 64}, {512, 128}};
   std::vector<Shape> out;
   const bool regs = levels == 2 || levels == 3;
   for (auto [b, h] : all) {

@@ -170,7 +170,7 @@ def test_lambda3_full_grid_prefix_vs_oracle():
     assert max(errs32.values()) <= TOL[32], max(errs32.values())
     # the density update split over 2 or 4 waves per 64 cells gives the same bits
     base = gpu_run(prob, precision=32, variant="blocked", block=256, depth=64, lanes=1)
-    for block, depth, lanes in ((256, 64, 2), (128, 32, 4)):
+    for block, depth, lanes in ((256, 64, 2), (128, 32, 4), (256, 64, 4), (512, 128, 2)):
         for variant in ("blocked", "blocked_regs"):
             _say(f"lambda3 prefix {variant} {block}/{depth} lanes {lanes}")
             assert_same(gpu_run(prob, precision=32, variant=variant, block=block, depth=depth, lanes=lanes), base)
