@@ -101,7 +101,7 @@ std::string tune_key(int device, const std::vector<const SimPlan *> &plans, int 
     cells += uint64_t(p->nx);
   }
   std::ostringstream os;
-  os << arch << "/v3/N" << levels << "/p" << precision << "/cells" << pow2_ceil(cells) << "/sims"
+  os << arch << "/v4/N" << levels << "/p" << precision << "/cells" << pow2_ceil(cells) << "/sims"
      << pow2_ceil(plans.size());
   return os.str();
 }
