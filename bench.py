@@ -265,6 +265,17 @@ def other_configs(hip, stream, log):
                             "fp64": cells / (ms64 * 1e-3), "unit": "cell-updates/s",
                             "fp32_vs_fp64_max_rel_err": max_error(p, r32, r64), "shape_fp32": list(sh32),
                             "shape_fp64": list(sh64)}
+    log("[bench] anharmonic ladder N = 2..6, 8192 cells, 20000 steps, fp32/fp64")
+    scal = {}
+    for n in range(2, 7):
+        p = W.ladder(n)
+        ms32, r32, sh32 = solve_once(hip, stream, p, 32)
+        ms64, r64, sh64 = solve_once(hip, stream, p, 64)
+        cells = p["nx"] * p["n_steps"]
+        scal[str(n)] = {"fp32": cells / (ms32 * 1e-3), "fp64": cells / (ms64 * 1e-3),
+                        "fp32_vs_fp64_max_rel_err": max_error(p, r32, r64),
+                        "flop_per_cell_update": flops_per_cell_update(n), "shape_fp32": list(sh32)}
+    res["ladder_n_scaling"] = {"nx": 8192, "n_steps": 20000, "unit": "cell-updates/s", "by_levels": scal}
     log("[bench] sweep x8: 2048 sims fp32 (state beyond the 256 MB last-level cache)")
     sims = W.sweep(n_sims=2048, precision=32, seed=W.SEED_BASE + 13)
     bcells = sum(q["nx"] * q["n_steps"] for q in sims)

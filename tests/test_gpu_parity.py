@@ -342,6 +342,22 @@ def test_qcl5_comb_prefix_vs_oracle():
         assert_same(gpu_run(prob, precision=32, variant="blocked", block=block, depth=depth, lanes=lanes), base)
 
 
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6])
+def test_anharmonic_ladder_vs_oracle(n):
+    """The level-count benchmark system of Sec. 4.3 (anharmonic ladder), 300 cells x 400
+    steps: FP64 within 1e-10, FP32 within 1e-4, every split of the density update the same."""
+    prob = W.ladder(n, nx=300, n_steps=400, rec_interval=4)
+    _say(f"ladder {n}")
+    ref = O.run(prob)
+    got = gpu_run(prob, precision=64)
+    assert max(rel_errors(prob, got, ref).values()) <= TOL[64]
+    got32 = gpu_run(prob, precision=32, variant="blocked", block=128, depth=16, lanes=1)
+    errs32 = rel_errors(prob, got32, ref)
+    assert max(errs32.values()) <= TOL[32], errs32
+    for block, depth, lanes in ((128, 16, 2), (64, 8, 4), (64, 8, 8)):
+        assert_same(gpu_run(prob, precision=32, variant="blocked", block=block, depth=depth, lanes=lanes), got32)
+
+
 def test_sweep_batch_spot_checks_vs_oracle():
     """The 256-simulation FP32 sweep in one batch; 8 seeded members checked against the oracle
     on their first 600 steps (12 record samples)."""

@@ -325,6 +325,46 @@ def qcl5_comb(nx=8192, n_steps=200_000, precision=32, rec_interval=1, noise=1.0)
                         refl=(0.8, 0.8), e_init=e_init, records=recs, precision=precision)
 
 
+def ladder(N, nx=8192, n_steps=20000, precision=32, rec_interval=100, length=2e-3):
+    """Anharmonic N-level ladder (Sec. 4.3): E_1 = 0, E_{n+1} = E_n + hbar w0 (1 - 0.1 (n - 3)),
+    w0 = 2 pi 1e13 1/s, any N >= 2 (the paper's level-count benchmark).
+
+    The paper prints only the level energies and the default grid (8192 points, 2 ns);
+    the rest is this generator's choice: dipoles on adjacent transitions
+    mu_{n,n+1} = 1e-29 sqrt(n) C m (oscillator-like), decay n -> n-1 at 1e10 n 1/s,
+    pure dephasing 1e11 1/s on every pair, n3d = 1e24 m^-3, ground state, the medium in the
+    middle half of a `length` vacuum domain, a hard Gaussian pulse at w0 (tau 100 fs,
+    1e8 V/m) at cell 0, absorbing ends; all populations at the centre and E at 3/4 length
+    recorded every `rec_interval` steps.
+    """
+    c = CODATA
+    w0 = 2 * math.pi * 1e13
+    en = [0.0]
+    for n in range(1, N):
+        en.append(en[-1] + c["hbar"] * w0 * (1.0 - 0.1 * (n - 3)))
+    mu_off = np.zeros(n_off(N), complex)
+    for n in range(1, N):                        # 1-based pair (n, n+1): packed index of (n-1, n)
+        i, j = n - 1, n
+        mu_off[j * (j - 1) // 2 + i] = 1e-29 * math.sqrt(n)
+    rates = np.zeros((N, N))
+    for n in range(1, N):
+        rates[n - 1, n] = 1e10 * n               # from level n+1 (0-based n) into level n
+    deph = np.full(n_off(N), 1e11)
+    qm = general_qm(1e24, en, None, None, mu_off, rates, deph)
+    mats = [vacuum(), qm_material(qm)]
+    regions = [(0.0, 0.25 * length, 0), (0.25 * length, 0.75 * length, 1), (0.75 * length, length, 0)]
+    dt = courant_dt(length, nx, c["c0"])
+    tau = 100e-15
+    src = source("gauss", 0, 1e8, w0 / (2 * math.pi), 5.0, 1.0 / tau)
+    mid = nx // 2
+    recs = [record(f"pop{k}", "pop", mid, rec_interval, i=k, j=k) for k in range(N)]
+    recs.append(record("e@3/4", "e", (3 * nx) // 4, rec_interval))
+    rho = np.zeros(N)
+    rho[0] = 1.0
+    return make_problem(f"ladder-{N}lvl", length, mats, regions, nx, dt, n_steps, rho,
+                        refl=(0.0, 0.0), sources=[src], records=recs, precision=precision)
+
+
 def sweep_sim(k, rng, nx=None, n_steps=50000, precision=32, rec_interval=50):
     """One member of the batched parameter sweep (even index: 2 levels, odd: 3)."""
     c = CODATA
