@@ -25,6 +25,14 @@ What it computes (paper sections cited per function):
   t_{n+1/2} from rho^{n+1/2} with L0 only, because tr{mu [mu, rho]} = 0.
 * Loop order of Alg. 1: H and rho (and p) first, then E, then edges,
   sources and records.
+* Strong coupling (Sec. 2.2 names it beside the weak coupling above, without a
+  formula): rho lives at the times of E.  Reading used here: rho^{n+1} is the
+  same Strang step driven by the midpoint field (E^n + E^{n+1})/2, and the
+  polarization current of eq:ediscrete is the centred difference
+  n3D tr{mu (rho^{n+1} - rho^n)}/dt.  The E update of a quantum cell then
+  depends on E^{n+1} through rho^{n+1}; it is solved by fixed-point iteration
+  to convergence.  Edges and sources follow as in the weak scheme, and every
+  quantum cell's rho^{n+1} is finally taken with its final E^{n+1}.
 
 Readings of points the paper leaves open (also listed in the design notes):
 edges with R = 1 are a perfect electric conductor (E = 0), edges with R = 0
@@ -345,6 +353,20 @@ class Oracle:
                 self.e[s["cell"]] += v
 
     # -- density step ---------------------------------------------------------
+    def _strang(self, g, rho, e_cells):
+        """e^{L0 dt/2} [ W (e^{L0 dt/2} rho) W^+ ] for each cell, W = exp(+i dt E mu / hbar)."""
+        k, n = rho.shape[0], g["n"]
+        r = (rho.reshape(k, n * n) @ g["p_half"].T).reshape(k, n, n)
+        vec, lam = g["vec"], g["lam"]
+        ph = np.exp(1j * self.dt / self.c["hbar"] * e_cells[:, None] * lam[None, :])
+        w = np.einsum("ij,kj,lj->kil", vec, ph, vec.conj())
+        r = w @ r @ np.conj(np.transpose(w, (0, 2, 1)))
+        return (r.reshape(k, n * n) @ g["p_half"].T).reshape(k, n, n)
+
+    @staticmethod
+    def _tr_mu(g, rho):
+        return np.real(np.einsum("ij,kji->k", g["mu"], rho))
+
     def _density_step(self, g, e_cells):
         """Strang splitting: half free step, field conjugation, half free step."""
         k, n = len(g["cells"]), g["n"]
@@ -365,6 +387,9 @@ class Oracle:
 
     def step(self):
         """One time step n -> n+1 in the order of Alg. 1."""
+        if self.p.get("coupling", "weak") == "strong":
+            self._step_strong()
+            return
         nx, n = self.nx, self.step_index
         e_old = self.e.copy()
         if nx > 1:
@@ -376,20 +401,65 @@ class Oracle:
             m = slice(1, nx - 1)
             self.e[m] = (self.ca[m] * e_old[m] - self.cb[m] * self.gam[m] * self.p_cur[m]
                          + self.cb[m] / self.dx * (self.h[1:] - self.h[:-1]))
-            for side, cell, nb in ((0, 0, 1), (1, nx - 1, nx - 2)):
-                r = self.p["refl"][side]
-                if r == 1.0:
-                    self.e[cell] = 0.0
-                elif r == 0.0:
-                    kap = self._mur_coeff(cell)
-                    self.e[cell] = e_old[nb] + kap * (self.e[nb] - e_old[cell])
-                elif 0.0 < r < 1.0:
-                    g, d = self._load_coeff(cell, r)
-                    h_in = self.h[0] if side == 0 else -self.h[-1]
-                    self.e[cell] = g * e_old[cell] + d * h_in
-                else:
-                    raise ValueError("reflectivity outside [0, 1]")
+            self._edges(e_old)
         self._apply_sources((n + 1) * self.dt)
+        self.step_index = n + 1
+        self._record(n)
+
+    def _edges(self, e_old):
+        nx = self.nx
+        for side, cell, nb in ((0, 0, 1), (1, nx - 1, nx - 2)):
+            r = self.p["refl"][side]
+            if r == 1.0:
+                self.e[cell] = 0.0
+            elif r == 0.0:
+                kap = self._mur_coeff(cell)
+                self.e[cell] = e_old[nb] + kap * (self.e[nb] - e_old[cell])
+            elif 0.0 < r < 1.0:
+                g, d = self._load_coeff(cell, r)
+                h_in = self.h[0] if side == 0 else -self.h[-1]
+                self.e[cell] = g * e_old[cell] + d * h_in
+            else:
+                raise ValueError("reflectivity outside [0, 1]")
+
+    def _step_strong(self):
+        """Strong coupling: rho^n, E^n -> rho^{n+1}, E^{n+1} (rho at the times of E)."""
+        nx, n = self.nx, self.step_index
+        e_old = self.e.copy()
+        if nx > 1:
+            self.h += self.ch * (e_old[1:] - e_old[:-1])
+            m = slice(1, nx - 1)
+            e_free = e_old.copy()
+            e_free[m] = self.ca[m] * e_old[m] + self.cb[m] / self.dx * (self.h[1:] - self.h[:-1])
+            self.e = e_free.copy()
+            for g in self.groups:
+                cells = g["cells"][(g["cells"] >= 1) & (g["cells"] <= nx - 2)]
+                if len(cells) == 0:
+                    continue
+                sel = np.isin(g["cells"], cells)
+                rho_n = g["rho"][sel]
+                q_n = self._tr_mu(g, rho_n)
+                e_star = e_free[cells].copy()
+                for _ in range(100):
+                    rho_new = self._strang(g, rho_n, 0.5 * (e_old[cells] + e_star))
+                    pol = g["n3d"] * (self._tr_mu(g, rho_new) - q_n) / self.dt
+                    e_new = e_free[cells] - self.cb[cells] * self.gam[cells] * pol
+                    done = np.max(np.abs(e_new - e_star)) <= 1e-15 * max(1.0, np.max(np.abs(e_new)))
+                    e_star = e_new
+                    if done:
+                        break
+                else:
+                    raise RuntimeError("strong-coupling field iteration did not converge")
+                self.e[cells] = e_star
+            self._edges(e_old)
+        else:
+            self.e = e_old.copy()
+        self._apply_sources((n + 1) * self.dt)
+        self.p_cur[:] = 0.0
+        for g in self.groups:
+            rho_n = g["rho"]
+            g["rho"] = self._strang(g, rho_n, 0.5 * (e_old[g["cells"]] + self.e[g["cells"]]))
+            self.p_cur[g["cells"]] = g["n3d"] * (self._tr_mu(g, g["rho"]) - self._tr_mu(g, rho_n)) / self.dt
         self.step_index = n + 1
         self._record(n)
 

@@ -356,7 +356,7 @@ def test_semi_transparent_end_limits():
 
 # ---------------------------------------------------------------- energy exchange with the medium
 
-def _energy_drift(nx, steps):
+def _energy_drift(nx, steps, coupling="weak"):
     L = 60e-6
     qm = two_level(2 * math.pi * 2e14, 1e-29 / C["e"], 0.0, 0.0, -1.0, n3d=2e24)
     gam = 0.7
@@ -368,7 +368,8 @@ def _energy_drift(nx, steps):
     e0 = 2e9 * np.exp(-((x - 15e-6) / (C["c0"] * tau)) ** 2) * np.sin(2 * math.pi * 2e14 * x / C["c0"])
     e0[0] = e0[-1] = 0.0
     dt = W.courant_dt(L, nx, C["c0"], 0.5)
-    prob = W.make_problem("pt", L, mats, regions, nx, dt, 1, [1.0, 0.0], refl=(1.0, 1.0), e_init=e0)
+    prob = W.make_problem("pt", L, mats, regions, nx, dt, 1, [1.0, 0.0], refl=(1.0, 1.0), e_init=e0,
+                          coupling=coupling)
     orc = O.Oracle(prob)
     eps, mu = C["eps0"], C["mu0"]
     h0 = O.describe(qm, C)[0]
@@ -382,7 +383,8 @@ def _energy_drift(nx, steps):
     es, hs, us = np.array(es), np.array(hs), np.array(us)
     # W^{n+1} = eps/2 sum (E^{n+1})^2 dx + mu/2 sum H^{n+3/2} H^{n+1/2} dx ; U^{n+1} ~ mean of halves
     field = 0.5 * eps * dx * np.sum(es[:-1] ** 2, axis=1) + 0.5 * mu * dx * np.sum(hs[1:] * hs[:-1], axis=1)
-    atoms = 0.5 * (us[1:] + us[:-1])
+    # weak coupling: rho^{n+1/2} after step n, averaged to integer times; strong: rho^{n+1}
+    atoms = 0.5 * (us[1:] + us[:-1]) if coupling == "weak" else us[:-1]
     total = field + atoms
     return np.max(np.abs(total - total[0])), np.max(np.abs(atoms - atoms[0])), field[0]
 
@@ -397,6 +399,47 @@ def test_poynting_energy_balance_with_two_level_medium():
     assert ex1 > 0.05 * f1 and abs(ex2 / ex1 - 1) < 0.05
     assert 3.5 < d1 / d2 < 4.5, (d1, d2)
     assert d2 < 2e-3 * ex2
+
+
+def test_strong_coupling_energy_balance():
+    """Strong coupling (Sec. 2.2: rho at the times of E): the same energy exchange between
+    field and systems holds to second order."""
+    d1, ex1, f1 = _energy_drift(600, 3000, "strong")
+    d2, ex2, _ = _energy_drift(1199, 6000, "strong")
+    assert ex1 > 0.05 * f1 and abs(ex2 / ex1 - 1) < 0.05
+    assert 3.5 < d1 / d2 < 4.5, (d1, d2)
+    assert d2 < 2e-3 * ex2
+
+
+def _coupling_pair(nx, steps):
+    """E at 3/4 of a two-level slab driven by a hard Gaussian pulse at the left end, weak and
+    strong coupling."""
+    L = 40e-6
+    qm = two_level(2 * math.pi * 2e14, 2e-29 / C["e"], 1e11, 2e11, -1.0, n3d=3e24)
+    mats = [W.vacuum(), W.qm_material(qm)]
+    regions = [(0.0, 15e-6, 0), (15e-6, 30e-6, 1), (30e-6, L, 0)]
+    dt = W.courant_dt(L, nx, C["c0"], 0.5)
+    src = W.source("gauss", 0, 5e9, 2e14, 4.0, 1.0 / 15e-15)
+    out = {}
+    for cpl in ("weak", "strong"):
+        prob = W.make_problem("cpl", L, mats, regions, nx, dt, steps, [1.0, 0.0], refl=(0.0, 0.0),
+                              sources=[src], records=[W.record("e", "e", 3 * (nx - 1) // 4, 1)],
+                              coupling=cpl)
+        out[cpl] = O.run(prob)["e"]
+    return out
+
+
+def test_strong_and_weak_coupling_agree_to_second_order():
+    """Both couplings discretise the same equations to second order, so their difference
+    falls by 4 when dx and dt are halved (a first-order slip, such as driving rho with E^n
+    instead of the midpoint field, would give 2)."""
+    a = _coupling_pair(401, 3200)
+    b = _coupling_pair(801, 6400)
+    d1 = np.max(np.abs(a["strong"] - a["weak"]))
+    d2 = np.max(np.abs(b["strong"][1::2] - b["weak"][1::2]))
+    scale = np.max(np.abs(a["weak"]))
+    assert d1 > 1e-4 * scale            # the schemes really differ
+    assert 3.5 < d1 / d2 < 4.6, (d1, d2)
 
 
 # ---------------------------------------------------------------- P9 self-induced transparency

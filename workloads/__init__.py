@@ -11,6 +11,8 @@ A *problem* is a dict:
 ``consts``     SI constants (CODATA 2018): hbar, e, c0, mu0, eps0.
 ``length``     device length L [m] (the grid spacing is L/(nx-1)).
 ``refl``       (R_left, R_right) field reflectivity of the two ends, each in [0, 1].
+``coupling``   "weak" (density matrix half a step after E, the default) or "strong"
+               (density matrix at the same times as E).
 ``materials``  list of dicts: eps_r, mu_r, alpha0 [1/m], overlap (Gamma) and
                ``qm`` = None (no quantum system) or a dict with n3d [m^-3],
                h0_diag (N,) [J], h0_off (N(N-1)/2,) complex [J], mu_diag,
@@ -121,9 +123,10 @@ def record(name, quantity, cell, interval, i=0, j=0):
 
 def make_problem(name, length, materials, regions, nx, dt, n_steps, rho_diag,
                  rho_off=None, refl=(0.0, 0.0), e_init=None, sources=(), records=(),
-                 precision=64, consts=CODATA):
+                 precision=64, consts=CODATA, coupling="weak"):
     n = len(rho_diag)
-    return {"name": name, "consts": dict(consts), "length": float(length),
+    assert coupling in ("weak", "strong")
+    return {"name": name, "consts": dict(consts), "length": float(length), "coupling": coupling,
             "refl": (float(refl[0]), float(refl[1])), "materials": list(materials),
             "regions": [dict(x_start=float(a), x_end=float(b), material=int(m)) for a, b, m in regions],
             "nx": int(nx), "dt": float(dt), "n_steps": int(n_steps), "precision": int(precision),
