@@ -85,6 +85,16 @@ extern "C" {
 #define MB_REC_RHO_RE 4  /* Re rho_ij                        */
 #define MB_REC_RHO_IM 5  /* Im rho_ij                        */
 
+/* time discretisation of the density matrix (Sec. 2.2): weak coupling keeps
+ * rho at t_{n+1/2} (the default), strong coupling at t_n with E; there the
+ * step is driven by the midpoint field (E^n + E^{n+1})/2 and the
+ * polarization current is n3D tr{mu (rho^{n+1} - rho^n)}/dt, the E update of
+ * a quantum cell being solved by fixed-point iteration (3 iterations on the
+ * GPU).  Strong coupling runs on the blocked variant only, with one wave per
+ * 64 cells. */
+#define MB_COUPLING_WEAK 0
+#define MB_COUPLING_STRONG 1
+
 #define MB_VARIANT_AUTO 0     /* blocked kernel, tile shape from the tuner / defaults */
 #define MB_VARIANT_PLAIN 1    /* two launches per step (Alg. 1 as written), FP64 only */
 #define MB_VARIANT_BLOCKED 2  /* temporally blocked overlapped tiles, FP64 or FP32 */
@@ -157,6 +167,8 @@ typedef struct mb_scenario_desc {
   int32_t variant;           /* MB_VARIANT_* */
   int32_t block;             /* blocked variant: cells per tile (0 = default) */
   int32_t depth;             /* blocked variant: steps per launch = halo width (0 = default) */
+  int32_t coupling;          /* MB_COUPLING_WEAK (rho half a step after E, Fig. 1) or
+                                MB_COUPLING_STRONG (rho at the times of E; Sec. 2.2) */
   int32_t lanes;             /* blocked variant: waves per 64 cells that share each cell's
                                 density update, 1, 2, 4 or 8 (8: 4 to 6 levels, 64-cell
                                 tiles; 0 = default); results do not depend on it */

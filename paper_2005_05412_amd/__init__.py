@@ -91,7 +91,8 @@ class mb_consts(C.Structure):
 class mb_scenario_desc(C.Structure):
     _fields_ = [("nx", C.c_int64), ("dt", C.c_double), ("n_steps", C.c_int64),
                 ("precision", C.c_int32), ("variant", C.c_int32), ("block", C.c_int32),
-                ("depth", C.c_int32), ("lanes", C.c_int32), ("rho_diag", C.POINTER(C.c_double)),
+                ("depth", C.c_int32), ("coupling", C.c_int32), ("lanes", C.c_int32),
+                ("rho_diag", C.POINTER(C.c_double)),
                 ("rho_off", C.POINTER(C.c_double)), ("e_init", C.POINTER(C.c_double)),
                 ("n_sources", C.c_int32), ("sources", C.POINTER(mb_source)),
                 ("n_records", C.c_int32), ("records", C.POINTER(mb_record)), ("consts", mb_consts)]
@@ -239,6 +240,7 @@ class _Marshal:
         sc.precision = prob["precision"] if precision is None else precision
         sc.variant = VARIANT[variant]
         sc.block, sc.depth, sc.lanes = block, depth, lanes
+        sc.coupling = 1 if prob.get("coupling", "weak") == "strong" else 0
         sc.rho_diag = arr(prob["rho_diag"])
         sc.rho_off = arr(_complex_pairs(prob["rho_off"])) if len(prob["rho_off"]) else arr(np.zeros(1))
         sc.e_init = None if prob["e_init"] is None else arr(prob["e_init"])

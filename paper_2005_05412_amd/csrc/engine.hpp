@@ -55,6 +55,10 @@ struct DevSim {
   const int32_t *rec_all;    // whole-domain record ids
   int32_t *status;           // bit 0: non-finite field seen
   int32_t rec_every;         // gcd of the record intervals (1 when there are no records)
+  // strong coupling: (n3D/dt) tr{mu rho^n} per cell (FP64 ping-pong like x) and per
+  // material its readout (qc, aq[M]) from the rotated state
+  double *qs[2];
+  const double *qtab;
 };
 
 struct DevTile {

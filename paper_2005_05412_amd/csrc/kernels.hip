@@ -18,6 +18,7 @@ namespace {
 
 constexpr int kTileSources = 4;  // sources per tile staged in LDS
 constexpr int kMaxChunk = 256;   // steps per blocked launch
+constexpr int kStrongIters = 3;  // fixed-point iterations of a strong-coupling E update
 
 // Neighbour values within one wave by DPP wavefront shifts (lane l receives
 // lane l+1, respectively l-1; the lane at the end of the wave receives 0).
@@ -390,7 +391,7 @@ constexpr bool shape_fits() {
          sizeof(TileShared<N, R, B, L>) <= 65536;
 }
 
-template <int N, typename R, int B, int L, bool VC, int SUB>
+template <int N, typename R, int B, int L, bool VC, int SUB, bool ST>
 __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, const DevTile *__restrict__ tiles,
                                            int64_t n0, int parity, int halo, int k, TileShared<N, R, B, L> &sm) {
   using CL = Cell<N, R>;
@@ -440,6 +441,11 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
           if (SP::owns(SUB, a)) x[a] = x_in[a * nx + c];
       }
     }
+  }
+  // strong coupling: (n3D/dt) tr{mu rho^n} of the cell, carried in FP64
+  double qn = 0.0;
+  if constexpr (ST) {
+    if (qm) qn = sim.qs[par][c];
   }
   // sources inside this tile: their values for the whole chunk are staged in
   // LDS (ordered before the first read by the first barrier of the loop); a
@@ -599,7 +605,27 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
     h = hcell ? fma(ch, er - e, h) : h;
     hl = hleft ? fma(chl, e - el, hl) : hl;
     R p = 0;
-    if constexpr (N > 0) {
+    if constexpr (ST && N > 0) {
+      // strong coupling: the E update of an interior quantum cell depends on
+      // rho^{n+1}, driven by (E^n + E^{n+1})/2; fixed-point iteration from the
+      // field without polarization
+      per_material([&](const auto &mt, int mm) {
+        const cptr<double> qt = kconst<double>(sim.qtab) + __builtin_amdgcn_readfirstlane(mm * (M + 1));
+        R pi = 0;
+        for (int it = 0; it < kStrongIters; ++it) {
+          const R es = fma(cbd, h - hl, fma(ca, e, -(cbg * pi)));
+          R yv[MA];
+#pragma unroll
+          for (int a = 0; a < MA; ++a) yv[a] = x[a];
+          CL::rotate(yv, R(0.5) * (e + es), mt);
+          double q = qt[0];
+#pragma unroll
+          for (int j = 0; j < M; ++j) q = fma(qt[1 + j], double(yv[j]), q);
+          pi = R(q - qn);
+        }
+        p = pi;
+      });
+    } else if constexpr (N > 0) {
       auto finish = [&](const auto &mt, int mm) {
         p = CL::polar(x, mt);
         if (rec_step) {
@@ -648,6 +674,29 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
       const R v = sm.src[my_src][s];
       e = my_hard ? v : e + v;
     }
+    if constexpr (ST && N > 0) {
+      // rho^{n+1} with the final E^{n+1}: rotation by the midpoint field, the
+      // new tr{mu rho}, records of rho^{n+1}, propagation of the running state
+      per_material([&](const auto &mt, int mm) {
+        const cptr<double> qt = kconst<double>(sim.qtab) + __builtin_amdgcn_readfirstlane(mm * (M + 1));
+        CL::rotate(x, R(0.5) * (eo + e), mt);
+        double q = qt[0];
+#pragma unroll
+        for (int j = 0; j < M; ++j) q = fma(qt[1 + j], double(x[j]), q);
+        qn = q;
+        if (rec_step) {
+          if (rec_here) {
+            if (rec_lds) {
+              sm.trec.density(n1, x, rb, re);
+              record_density_all<N, R>(sim, c, n1, mm, x);
+            } else {
+              record_density<N, R>(sim, c, n1, mm, x, rb, re);
+            }
+          }
+        }
+        CL::propagate(x, mt);
+      });
+    }
     if (rec_step) {
       if (rec_here) {
         if (rec_lds) {
@@ -673,6 +722,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
 #pragma unroll
         for (int a = 0; a < M; ++a)
           if (SP::owns(SUB, a)) x_out[a * nx + c] = x[a];
+        if constexpr (ST) sim.qs[par ^ 1][c] = qn;
       }
     }
     if (SUB == 0 && (!isfinite(double(e)) || !isfinite(double(h)))) *sim.status = 1;
@@ -686,21 +736,22 @@ __device__ __forceinline__ void run_group(int sub, const DevSim *__restrict__ si
                                           int64_t n0, int parity, int halo, int k, TileShared<N, R, B, L> &sm) {
   if constexpr (S + 1 < L) {
     if (sub == S)
-      tile_steps<N, R, B, L, VC, S>(sims, tiles, n0, parity, halo, k, sm);
+      tile_steps<N, R, B, L, VC, S, false>(sims, tiles, n0, parity, halo, k, sm);
     else
       run_group<N, R, B, L, VC, S + 1>(sub, sims, tiles, n0, parity, halo, k, sm);
   } else {
-    tile_steps<N, R, B, L, VC, S>(sims, tiles, n0, parity, halo, k, sm);
+    tile_steps<N, R, B, L, VC, S, false>(sims, tiles, n0, parity, halo, k, sm);
   }
 }
 
-template <int N, typename R, int B, int L, bool VC>
+// ST: strong coupling (one wave per 64 cells only)
+template <int N, typename R, int B, int L, bool VC, bool ST = false>
 __global__ void __launch_bounds__(B * L) k_blocked(const DevSim *__restrict__ sims,
                                                    const DevTile *__restrict__ tiles, int64_t n0, int parity,
                                                    int halo, int k) {
   __shared__ TileShared<N, R, B, L> sm;
   if constexpr (L == 1) {
-    tile_steps<N, R, B, 1, VC, 0>(sims, tiles, n0, parity, halo, k, sm);
+    tile_steps<N, R, B, 1, VC, 0, ST>(sims, tiles, n0, parity, halo, k, sm);
   } else {
     run_group<N, R, B, L, VC>(__builtin_amdgcn_readfirstlane(int(threadIdx.x) / B), sims, tiles, n0, parity, halo,
                               k, sm);
@@ -823,26 +874,26 @@ __global__ void __launch_bounds__(kPlainBlock) k_plain_e(const DevSim *__restric
   if (!isfinite(e)) *sim.status = 1;
 }
 
-template <int N, typename R, int B, int L, bool VC>
+template <int N, typename R, int B, int L, bool VC, bool ST = false>
 hipError_t launch_shape(const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo,
                         int k, hipStream_t st) {
-  if constexpr (shape_fits<N, R, B, L>()) {
-    k_blocked<N, R, B, L, VC><<<n_tiles, B * L, 0, st>>>(sims, tiles, n0, parity, halo, k);
+  if constexpr (shape_fits<N, R, B, L>() && (!ST || (L == 1 && !VC && N >= 2))) {
+    k_blocked<N, R, B, L, VC, ST><<<n_tiles, B * L, 0, st>>>(sims, tiles, n0, parity, halo, k);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
   }
 }
 
-template <int N, typename R, int L, bool VC>
+template <int N, typename R, int L, bool VC, bool ST = false>
 hipError_t launch_blocked_b(int block, const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0,
                             int parity, int halo, int k, hipStream_t st) {
   switch (block) {
-    case 64: return launch_shape<N, R, 64, L, VC>(sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 128: return launch_shape<N, R, 128, L, VC>(sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 256: return launch_shape<N, R, 256, L, VC>(sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 512: return launch_shape<N, R, 512, L, VC>(sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 1024: return launch_shape<N, R, 1024, L, VC>(sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 64: return launch_shape<N, R, 64, L, VC, ST>(sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 128: return launch_shape<N, R, 128, L, VC, ST>(sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 256: return launch_shape<N, R, 256, L, VC, ST>(sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 512: return launch_shape<N, R, 512, L, VC, ST>(sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 1024: return launch_shape<N, R, 1024, L, VC, ST>(sims, tiles, n_tiles, n0, parity, halo, k, st);
   }
   return hipErrorInvalidValue;
 }
@@ -850,9 +901,14 @@ hipError_t launch_blocked_b(int block, const DevSim *sims, const DevTile *tiles,
 // register-resident coefficients are instantiated for the small level counts
 // only, split waves for the quantum level counts
 template <int N, typename R>
-hipError_t launch_blocked_nr(int block, int lanes, bool vc, const DevSim *sims, const DevTile *tiles, int n_tiles,
-                             int64_t n0, int parity, int halo, int k, hipStream_t st) {
+hipError_t launch_blocked_nr(int block, int lanes, bool vc, bool strong, const DevSim *sims, const DevTile *tiles,
+                             int n_tiles, int64_t n0, int parity, int halo, int k, hipStream_t st) {
   constexpr bool kVC = N == 2 || N == 3;
+  if (strong) {
+    if constexpr (N >= 2)
+      return launch_blocked_b<N, R, 1, false, true>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    return hipErrorInvalidValue;
+  }
   switch (lanes) {
     case 1:
       if constexpr (kVC)
@@ -879,15 +935,16 @@ hipError_t launch_blocked_nr(int block, int lanes, bool vc, const DevSim *sims, 
 }
 
 template <typename R>
-hipError_t launch_blocked_r(int levels, int block, int lanes, bool vc, const DevSim *sims, const DevTile *tiles,
-                            int n_tiles, int64_t n0, int parity, int halo, int k, hipStream_t st) {
+hipError_t launch_blocked_r(int levels, int block, int lanes, bool vc, bool strong, const DevSim *sims,
+                            const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo, int k,
+                            hipStream_t st) {
   switch (levels) {
-    case 0: return launch_blocked_nr<0, R>(block, lanes, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 2: return launch_blocked_nr<2, R>(block, lanes, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 3: return launch_blocked_nr<3, R>(block, lanes, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 4: return launch_blocked_nr<4, R>(block, lanes, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 5: return launch_blocked_nr<5, R>(block, lanes, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 6: return launch_blocked_nr<6, R>(block, lanes, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 0: return launch_blocked_nr<0, R>(block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 2: return launch_blocked_nr<2, R>(block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 3: return launch_blocked_nr<3, R>(block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 4: return launch_blocked_nr<4, R>(block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 5: return launch_blocked_nr<5, R>(block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 6: return launch_blocked_nr<6, R>(block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, st);
   }
   return hipErrorInvalidValue;
 }
@@ -946,14 +1003,16 @@ hipError_t launch_plain_n(const DevSim *sims, const DevTile *tiles, int n_tiles,
 #define MB_PART 0
 #endif
 
-hipError_t launch_blocked_f32(int levels, int block, int lanes, bool vc, const DevSim *sims, const DevTile *tiles,
-                              int n_tiles, int64_t n0, int parity, int halo, int k, hipStream_t st);
+hipError_t launch_blocked_f32(int levels, int block, int lanes, bool vc, bool strong, const DevSim *sims,
+                              const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo, int k,
+                              hipStream_t st);
 bool fits_f32(int levels, int block, int lanes);
 
 #if MB_PART != 2
-hipError_t launch_blocked_f32(int levels, int block, int lanes, bool vc, const DevSim *sims, const DevTile *tiles,
-                              int n_tiles, int64_t n0, int parity, int halo, int k, hipStream_t st) {
-  return launch_blocked_r<float>(levels, block, lanes, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
+hipError_t launch_blocked_f32(int levels, int block, int lanes, bool vc, bool strong, const DevSim *sims,
+                              const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo, int k,
+                              hipStream_t st) {
+  return launch_blocked_r<float>(levels, block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, st);
 }
 
 bool fits_f32(int levels, int block, int lanes) { return fits_r<float>(levels, block, lanes); }
@@ -971,13 +1030,15 @@ bool shape_supported(int levels, int precision, int block, int lanes) {
 
 int plain_block() { return kPlainBlock; }
 
-hipError_t launch_blocked(int levels, int precision, int block, int lanes, bool vc, const DevSim *sims,
-                          const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo, int k, hipStream_t st) {
+hipError_t launch_blocked(int levels, int precision, int block, int lanes, bool vc, bool strong,
+                          const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo,
+                          int k, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
   if (k < 1 || k > halo || k > kMaxChunk || 2 * halo >= block) return hipErrorInvalidValue;
   if (precision == 64)
-    return launch_blocked_r<double>(levels, block, lanes, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
-  return launch_blocked_f32(levels, block, lanes, vc, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    return launch_blocked_r<double>(levels, block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k,
+                                    st);
+  return launch_blocked_f32(levels, block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, st);
 }
 
 hipError_t launch_plain(int levels, const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity,

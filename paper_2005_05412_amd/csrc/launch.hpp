@@ -18,9 +18,10 @@ int plain_block();
 // block*lanes threads.
 // vc: quantum coefficients of single-material waves held in registers
 // (used for 2 and 3 levels, ignored otherwise).
-hipError_t launch_blocked(int levels, int precision, int block, int lanes, bool vc, const DevSim *sims,
-                          const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo, int k,
-                          hipStream_t st);
+// strong: strong-coupling simulations (one wave per 64 cells, no register coefficients)
+hipError_t launch_blocked(int levels, int precision, int block, int lanes, bool vc, bool strong,
+                          const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity,
+                          int halo, int k, hipStream_t st);
 // One time step as two launches (FP64); tiles of plain_block() cells.
 hipError_t launch_plain(int levels, const DevSim *sims, const DevTile *tiles, int n_tiles,
                         int64_t n0, int parity, hipStream_t st);

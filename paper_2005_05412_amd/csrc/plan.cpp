@@ -376,6 +376,16 @@ void build_quantum(MaterialPlan &mp, const QmFull &q, double dt, const mb_consts
   double p0 = 0.0;
   for (int a = 0; a < m; ++a) p0 += cg[a] * mp.bh[a] + c[a] * mp.gen_off[a];
   mp.p0 = p0;
+  // strong coupling: (n3D/dt) tr{mu rho} with rho' = ah y + bh (trace eliminated):
+  // n3D/dt [lam_{N-1} + sum_{k<N-1} (lam_k - lam_{N-1}) (ah y + bh)_k]
+  mp.aq.assign(m, 0.0);
+  double qc = q.n3d * mp.lam[n - 1];
+  for (int kk = 0; kk < n - 1; ++kk) {
+    for (int b = 0; b < m; ++b) mp.aq[b] += c[kk] * mp.ah[size_t(kk) * m + b];
+    qc += c[kk] * mp.bh[kk];
+  }
+  for (double &v : mp.aq) v /= dt;
+  mp.qc = qc / dt;
   // complete positivity of the pure dephasing: Gram matrix -1/2 J D J, D_ij = 2 gamma_ij,p
   Mat d(size_t(n) * n, 0.0), jm(size_t(n) * n, 0.0);
   double dmax = 0.0;
@@ -529,6 +539,14 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
     err = "lanes must be 0, 1, 2, 4 or 8";
     return MB_ERR_ARG;
   }
+  if (scen->coupling != MB_COUPLING_WEAK && scen->coupling != MB_COUPLING_STRONG) {
+    err = "coupling must be MB_COUPLING_WEAK or MB_COUPLING_STRONG";
+    return MB_ERR_ARG;
+  }
+  if (scen->coupling == MB_COUPLING_STRONG && scen->variant == MB_VARIANT_PLAIN) {
+    err = "strong coupling runs on the blocked variant";
+    return MB_ERR_UNSUPPORTED;
+  }
   if (scen->variant == MB_VARIANT_PLAIN && scen->precision != 64) {
     err = "the plain variant runs in FP64 only";
     return MB_ERR_UNSUPPORTED;
@@ -557,6 +575,7 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
   plan.block = scen->block;
   plan.depth = scen->depth;
   plan.lanes = scen->lanes;
+  plan.coupling = scen->coupling;
   plan.dx = scen->nx > 1 ? dev->length / double(scen->nx - 1) : 0.0;
   if (scen->nx > 1 && !(plan.dx > 0)) {
     err = "device length must be positive";
@@ -717,6 +736,7 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
     int n = levels, m = plan.m;
     std::vector<cd> rho0 = unpack(n, scen->rho_diag, scen->rho_off);
     plan.x0.assign(size_t(m) * nx, 0.0);
+    plan.q0.assign(nx, 0.0);
     for (int i = 0; i < dev->n_materials; ++i) {
       const MaterialPlan &mp = plan.mats[i];
       if (!mp.qm) continue;
@@ -729,9 +749,15 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
         for (int b = 0; b < m; ++b) acc += mp.ah[size_t(a) * m + b] * x[b];
         sig[a] = acc;
       }
+      // (n3D/dt) tr{mu rho^0} in the eigen-basis of mu
+      double q = mp.lam[n - 1];
+      for (int kk = 0; kk < n - 1; ++kk) q += (mp.lam[kk] - mp.lam[n - 1]) * x[kk];
+      q *= mp.n3d / plan.dt;
       for (int64_t c = 0; c < nx; ++c)
-        if (plan.mat_e[c] == i)
+        if (plan.mat_e[c] == i) {
           for (int a = 0; a < m; ++a) plan.x0[size_t(a) * nx + c] = sig[a];
+          plan.q0[c] = q;
+        }
     }
   }
   for (double v : plan.e0)

@@ -39,6 +39,8 @@ struct MaterialPlan {
   std::vector<double> am, bf;     // e^{L0 dt} - I and its affine part
   std::vector<double> at;         // M: p = at . y + p0
   double p0 = 0;
+  std::vector<double> aq;         // M: strong coupling, (n3D/dt) tr{mu rho} = aq . y + qc
+  double qc = 0;
   double min_gram_eig = 0;        // complete-positivity check of the dephasing rates
 };
 
@@ -62,6 +64,7 @@ struct SimPlan {
   int precision = 64;
   int variant = MB_VARIANT_AUTO;
   int block = 0, depth = 0, lanes = 0;
+  int coupling = MB_COUPLING_WEAK;
   std::vector<uint8_t> mat_e, mat_h;
   std::vector<MaterialPlan> mats;
   int edge_l = 0, edge_r = 0;     // 0: PEC, 1: Mur, 2: impedance load (0 < R < 1)
@@ -71,6 +74,7 @@ struct SimPlan {
   std::vector<RecordPlan> records;
   std::vector<double> e0;         // nx
   std::vector<double> x0;         // m planes of nx: the running state sigma_0
+  std::vector<double> q0;         // strong coupling: (n3D/dt) tr{mu rho^0} per cell
   int warn = MB_OK;
 };
 

@@ -15,6 +15,7 @@ constexpr int kStatusSlots = Engine::kMaxStatusSlots;
 
 struct Layout {
   size_t e, h, x, init_e, init_x, p, mat_e, mat_h, mtab, src, src_tab, rec, readout, rec_first, rec_ids, rec_all;
+  size_t qs, init_q, qtab;  // strong coupling
   size_t outputs, end_head, total;
   std::vector<size_t> tab_off, ro_off, out_off;
   int n_point = 0, n_all = 0;
@@ -40,6 +41,10 @@ Layout layout_of(const SimPlan &p, int precision, bool plain) {
   L.mat_e = take(nx);
   L.mat_h = take(nx);
   L.mtab = take(p.mats.size() * size_t(mat_stride(p.n)) * rs);
+  const bool strong = p.coupling == MB_COUPLING_STRONG && p.n > 0;
+  L.qs = take(strong ? 2 * nx * sizeof(double) : sizeof(double));
+  L.init_q = take(strong ? nx * sizeof(double) : sizeof(double));
+  L.qtab = take(strong ? p.mats.size() * size_t(m + 1) * sizeof(double) : sizeof(double));
   L.src = take(std::max<size_t>(1, p.sources.size()) * sizeof(DevSource));
   for (auto &s : p.sources) L.tab_off.push_back(take(s.table.size() * sizeof(double)));
   L.rec = take(std::max<size_t>(1, p.records.size()) * sizeof(DevRecord));
@@ -96,6 +101,18 @@ void fill_state(const SimPlan &p, char *head, const Layout &L) {
   const size_t mn = size_t(p.m) * nx;
   for (size_t q = 0; q < mn; ++q) x[q] = x[mn + q] = ix[q] = R(p.x0[q]);
   fill_mtab<R>(p, reinterpret_cast<R *>(head + L.mtab));
+  if (p.coupling == MB_COUPLING_STRONG && p.n > 0) {
+    double *qs = reinterpret_cast<double *>(head + L.qs);
+    double *iq = reinterpret_cast<double *>(head + L.init_q);
+    for (size_t c = 0; c < nx; ++c) qs[c] = qs[nx + c] = iq[c] = p.q0[c];
+    double *qt = reinterpret_cast<double *>(head + L.qtab);
+    const size_t m1 = size_t(p.m) + 1;
+    for (size_t i = 0; i < p.mats.size(); ++i) {
+      const MaterialPlan &mp = p.mats[i];
+      qt[i * m1] = mp.qm ? mp.qc : 0.0;
+      for (int a = 0; a < p.m; ++a) qt[i * m1 + 1 + a] = mp.qm ? mp.aq[a] : 0.0;
+    }
+  }
 }
 
 }  // namespace
@@ -218,16 +235,21 @@ int Engine::init(std::string &err) {
   return MB_OK;
 }
 
-Engine::Group &Engine::group_for(int levels) {
+Engine::Group &Engine::group_for(int levels, bool strong) {
   for (auto &g : groups_)
-    if (g.levels == levels) return g;
+    if (g.levels == levels && g.strong == strong) return g;
   groups_.push_back(Group());
   groups_.back().levels = levels;
+  groups_.back().strong = strong;
   return groups_.back();
 }
 
 int Engine::add(SimPlan &&plan, Arena *arena, hipStream_t st, std::string &err) {
   const bool plain = variant_ == MB_VARIANT_PLAIN;
+  if (plain && plan.coupling == MB_COUPLING_STRONG) {
+    err = "strong coupling runs on the blocked variant";
+    return MB_ERR_UNSUPPORTED;
+  }
   if (plain && precision_ != 64) {
     err = "the two-launch variant runs in FP64 only";
     return MB_ERR_UNSUPPORTED;
@@ -254,6 +276,7 @@ int Engine::add(SimPlan &&plan, Arena *arena, hipStream_t st, std::string &err) 
   s->bytes = L.total;
   s->init_e = L.init_e;
   s->init_x = L.init_x;
+  s->init_q = L.init_q;
   s->out_begin = L.end_head;
   s->block = block;
   s->own_block = arena == nullptr;
@@ -332,6 +355,9 @@ int Engine::add(SimPlan &&plan, Arena *arena, hipStream_t st, std::string &err) 
   d.h[1] = dev + L.h + nx * rs;
   d.x[0] = dev + L.x;
   d.x[1] = dev + L.x + size_t(p.m) * nx * rs;
+  d.qs[0] = reinterpret_cast<double *>(dev + L.qs);
+  d.qs[1] = p.coupling == MB_COUPLING_STRONG && p.n > 0 ? d.qs[0] + nx : d.qs[0];
+  d.qtab = reinterpret_cast<const double *>(dev + L.qtab);
   d.p = dev + L.p;
   d.mat_e = reinterpret_cast<const uint8_t *>(dev + L.mat_e);
   d.mat_h = reinterpret_cast<const uint8_t *>(dev + L.mat_h);
@@ -358,7 +384,7 @@ int Engine::add(SimPlan &&plan, Arena *arena, hipStream_t st, std::string &err) 
   d.parity_off = s->parity_off;
   s->active = true;
   int id = int(sims_.size());
-  group_for(p.n).members.push_back(id);
+  group_for(p.n, p.coupling == MB_COUPLING_STRONG && p.n > 0).members.push_back(id);
   sims_.push_back(std::move(s));
   dirty_ = true;
   ++version_;
@@ -432,11 +458,12 @@ hipError_t Engine::sync_tables(hipStream_t st) {
 
 int Engine::effective_lanes(int levels) const {
   for (auto &g : groups_)
-    if (g.levels == levels) return group_lanes(g);
+    if (g.levels == levels && !g.strong) return group_lanes(g);
   return 1;
 }
 
 int Engine::group_lanes(const Group &g) const {
+  if (g.strong) return 1;  // the strong-coupling field iteration runs in one wave per cell
   int want = lanes_;
   if (want == 0) {
     // enough waves for about two per SIMD (4 SIMDs per compute unit)
@@ -460,7 +487,7 @@ hipError_t Engine::launch_group(Group &g, hipStream_t st, int k, int reps) {
             hipSuccess)
           return e;
       }
-    } else if ((e = launch_blocked(g.levels, precision_, block_, lanes, vc_, g.d_sims, g.d_tiles, g.n_tiles,
+    } else if ((e = launch_blocked(g.levels, precision_, block_, lanes, vc_, g.strong, g.d_sims, g.d_tiles, g.n_tiles,
                                    n0_ + int64_t(r) * k, parity_ ^ (r & 1), halo_, k, st)) != hipSuccess) {
       return e;
     }
@@ -515,6 +542,8 @@ hipError_t Engine::reset(hipStream_t st) {
       if (e == hipSuccess) e = hipMemsetAsync(s.ds.h[b], 0, nx * rs, st);
       if (e == hipSuccess && m)
         e = hipMemcpyAsync(s.ds.x[b], s.block + s.init_x, m * nx * rs, hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess && s.plan.coupling == MB_COUPLING_STRONG && m)
+        e = hipMemcpyAsync(s.ds.qs[b], s.block + s.init_q, nx * sizeof(double), hipMemcpyDeviceToDevice, st);
     }
     if (e == hipSuccess && s.bytes > s.out_begin) e = hipMemsetAsync(s.block + s.out_begin, 0, s.bytes - s.out_begin, st);
     if (e == hipSuccess) e = hipMemsetAsync(s.ds.status, 0, sizeof(int32_t), st);

@@ -45,7 +45,7 @@ struct SimState {
   int cur_e = 0, cur_h = 0, cur_x = 0;  // buffers holding the current state
   int64_t done = 0;            // steps completed (host mirror)
   std::vector<size_t> rec_off; // device offsets of record outputs inside block
-  size_t init_e = 0, init_x = 0, out_begin = 0;  // initial-state images, start of outputs
+  size_t init_e = 0, init_x = 0, init_q = 0, out_begin = 0;  // initial-state images, start of outputs
   bool active = false;
   int status_slot = -1;
 };
@@ -121,12 +121,13 @@ class Engine {
  private:
   struct Group {
     int levels = 0;
+    bool strong = false;  // strong-coupling simulations (their own kernel)
     std::vector<int> members;
     DevSim *d_sims = nullptr;
     DevTile *d_tiles = nullptr;
     int n_tiles = 0, cap_sims = 0, cap_tiles = 0;
   };
-  Group &group_for(int levels);
+  Group &group_for(int levels, bool strong);
   hipError_t upload_group(Group &g, hipStream_t st);
   hipError_t launch_group(Group &g, hipStream_t st, int k, int reps);
   int group_lanes(const Group &g) const;

@@ -358,6 +358,54 @@ def test_anharmonic_ladder_vs_oracle(n):
         assert_same(gpu_run(prob, precision=32, variant="blocked", block=block, depth=depth, lanes=lanes), got32)
 
 
+STRONG = [
+    dict(seed=41, N=2, nx=60, n_steps=80, refl=(0.0, 1.0)),
+    dict(seed=42, N=3, nx=150, n_steps=90, refl=(0.64, 0.0), soft=True),
+    dict(seed=43, N=5, nx=45, n_steps=40, refl=(1.0, 1.0), e_noise=1e7),
+    dict(seed=44, N=3, nx=1, n_steps=200, refl=(0.0, 0.0)),
+]
+
+
+@pytest.mark.parametrize("case", STRONG, ids=lambda c: f"N{c['N']}-nx{c['nx']}-s{c['seed']}")
+def test_strong_coupling_vs_oracle(case):
+    """Strong coupling (rho at the times of E, Sec. 2.2): FP64 within 1e-10 and FP32 within
+    1e-4 of the oracle, whose field iteration runs to convergence; every tile shape the same."""
+    kw = dict(case)
+    prob = W.random_small(kw.pop("seed"), **kw)
+    prob["coupling"] = "strong"
+    _say(f"strong {prob['name']}")
+    ref = O.run(prob)
+    got = gpu_run(prob, precision=64, variant="blocked", block=128, depth=16)
+    errs = rel_errors(prob, got, ref)
+    assert max(errs.values()) <= TOL[64], errs
+    for block, depth in ((64, 7), (256, 32), (512, 100)):
+        assert_same(gpu_run(prob, precision=64, variant="blocked", block=block, depth=depth), got)
+    got32 = gpu_run(prob, precision=32, variant="blocked", block=128, depth=16)
+    errs32 = rel_errors(prob, got32, ref)
+    assert max(errs32.values()) <= TOL[32], errs32
+
+
+def test_strong_coupling_sit_prefix_and_mixed_batch():
+    """Two-level SIT with strong coupling, first 4000 steps against the oracle; a batch that
+    mixes weakly and strongly coupled simulations gives each one's solo records."""
+    prob = W.sit_2lvl(n_steps=4000)
+    prob["coupling"] = "strong"
+    _say("strong sit")
+    ref = O.run(prob)
+    errs = rel_errors(prob, gpu_run(prob, precision=64), ref)
+    assert max(errs.values()) <= TOL[64], errs
+    errs32 = rel_errors(prob, gpu_run(prob, precision=32), ref)
+    assert max(errs32.values()) <= TOL[32], errs32
+    probs = _mixed_batch(n=4, n_steps=500, precision=64)
+    for k in (1, 2):
+        probs[k]["coupling"] = "strong"
+    b = mb.Batch(probs, precision=64, block=128, depth=16)
+    b.run(use_graph=True)
+    for k, p in enumerate(probs):
+        assert_same(b.records(k), gpu_run(p, precision=64, variant="blocked", block=256, depth=32))
+    b.close()
+
+
 def test_sweep_batch_spot_checks_vs_oracle():
     """The 256-simulation FP32 sweep in one batch; 8 seeded members checked against the oracle
     on their first 600 steps (12 record samples)."""

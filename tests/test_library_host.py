@@ -183,6 +183,12 @@ def test_status_codes():
     with pytest.raises(mb.MBError) as ex:
         mb.plan_status(_vac(), precision=32, variant="plain")
     assert ex.value.code == -3
+    strong = _vac()
+    strong["coupling"] = "strong"
+    assert mb.plan_status(strong) == 0
+    with pytest.raises(mb.MBError) as ex:        # strong coupling runs on the blocked variant
+        mb.plan_status(strong, variant="plain")
+    assert ex.value.code == -3
 
 
 def test_non_completely_positive_dephasing_warns():
