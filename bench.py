@@ -339,7 +339,7 @@ def main(argv=None):
             if leg not in keep:
                 setattr(args, "no_" + leg, True)
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU runs are not part of this build",
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library has no multi-GPU path",
               file=sys.stderr)
         return 2
     hip = Hip()

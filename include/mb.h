@@ -72,6 +72,8 @@ extern "C" {
 #define MB_ERR_HIP -6           /* a HIP runtime call failed */
 #define MB_ERR_NONFINITE -7     /* a simulation produced a non-finite field value */
 #define MB_ERR_STATE -8         /* call out of order (e.g. reading a request not yet done) */
+#define MB_ERR_DEVICE -9        /* a tile of a persistent launch gave up waiting (2 s) for a
+                                   neighbour tile; the run's results are not valid */
 
 /* ---- enumerations -------------------------------------------------------- */
 #define MB_SRC_SECH 0   /* s(t) = amp sech(width t' - shift) sin(2 pi freq t + phase) */
@@ -165,7 +167,8 @@ typedef struct mb_scenario_desc {
   int64_t n_steps;
   int32_t precision;         /* 64 or 32: arithmetic of the bulk field and density updates */
   int32_t variant;           /* MB_VARIANT_* */
-  int32_t block;             /* blocked variant: cells per tile (0 = default) */
+  int32_t block;             /* blocked variant: cells per tile, 64, 128, 192, 256, 512 or
+                                1024 (0 = default) */
   int32_t depth;             /* blocked variant: steps per launch = halo width (0 = default) */
   int32_t coupling;          /* MB_COUPLING_WEAK (rho half a step after E, Fig. 1) or
                                 MB_COUPLING_STRONG (rho at the times of E; Sec. 2.2) */
@@ -226,8 +229,18 @@ int mb_setup(int hip_device, const mb_device_desc *dev, const mb_scenario_desc *
              mb_handle **out);
 
 /* Enqueues n_steps time steps (-1: all remaining) on `hip_stream` (a
- * hipStream_t, NULL = the legacy default stream).  Asynchronous. */
+ * hipStream_t, NULL = the legacy default stream).  Asynchronous.  The blocked
+ * variant runs its full chunks as persistent launches when every tile fits on
+ * the device at once and 3 depth <= block (MB_PERSIST=0 in the environment at
+ * setup switches this off); otherwise, and for the tail, one launch per chunk,
+ * captured into a HIP graph.  Results are the same bits either way. */
 int mb_run(mb_handle *h, int64_t n_steps, void *hip_stream);
+
+/* 1 when mb_run(h, n_steps) would run its full chunks as persistent launches
+ * (one launch for up to 4096 chunks; tiles wait for their neighbours' flags
+ * between chunks), 0 when every chunk is its own launch, negative on error.
+ * Uploads pending simulation tables (synchronously). */
+int mb_run_mode(mb_handle *h, int64_t n_steps);
 
 /* Restores the initial state (from a device-resident copy made at setup),
  * clears the records and sets the step count to zero, asynchronously on

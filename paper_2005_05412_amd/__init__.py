@@ -21,13 +21,14 @@ LIB_PATH = os.path.join(_HERE, "libmbhip.so")
 MB_OK = 0
 MB_WARN_NOT_CP = 1
 ERRORS = {-1: "MB_ERR_ARG", -2: "MB_ERR_CFL", -3: "MB_ERR_UNSUPPORTED", -4: "MB_ERR_OOM",
-          -5: "MB_ERR_BUDGET", -6: "MB_ERR_HIP", -7: "MB_ERR_NONFINITE", -8: "MB_ERR_STATE"}
+          -5: "MB_ERR_BUDGET", -6: "MB_ERR_HIP", -7: "MB_ERR_NONFINITE", -8: "MB_ERR_STATE",
+          -9: "MB_ERR_DEVICE"}
 SRC_KIND = {"sech": 0, "gauss": 1}
 REC_KIND = {"e": 0, "h": 1, "pop": 2, "inv": 3, "rho_re": 4, "rho_im": 5}
 VARIANT = {"auto": 0, "plain": 1, "blocked": 2, "blocked_regs": 3}
 
 EXPORTS = [
-    "mb_last_error", "mb_device_count", "mb_plan_material", "mb_plan_readout", "mb_setup", "mb_run", "mb_reset", "mb_batch_reset", "mb_shape", "mb_batch_shape", "mb_steps_done", "mb_record_shape",
+    "mb_last_error", "mb_device_count", "mb_plan_material", "mb_plan_readout", "mb_setup", "mb_run", "mb_run_mode", "mb_reset", "mb_batch_reset", "mb_shape", "mb_batch_shape", "mb_steps_done", "mb_record_shape",
     "mb_read_records", "mb_read_state", "mb_elapsed_ms", "mb_destroy", "mb_batch_setup", "mb_batch_run",
     "mb_batch_record_shape", "mb_batch_read_records", "mb_batch_elapsed_ms", "mb_batch_destroy",
     "mb_server_create", "mb_server_submit", "mb_server_start", "mb_server_drain", "mb_server_cancel",
@@ -121,6 +122,7 @@ def load():
                                       C.c_int32, dp, C.c_int64]),
         "mb_setup": (C.c_int, [C.c_int, C.POINTER(mb_device_desc), C.POINTER(mb_scenario_desc), C.POINTER(P)]),
         "mb_run": (C.c_int, [P, C.c_int64, P]),
+        "mb_run_mode": (C.c_int, [P, C.c_int64]),
         "mb_reset": (C.c_int, [P, P]),
         "mb_batch_reset": (C.c_int, [P, P]),
         "mb_shape": (C.c_int, [P] + [C.POINTER(C.c_int32)] * 4),
@@ -333,6 +335,13 @@ class Solver:
         b, d, r, n = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
         _check(load().mb_shape(self._h, C.byref(b), C.byref(d), C.byref(r), C.byref(n)))
         return b.value, d.value, bool(r.value), n.value
+
+    def persistent(self, n_steps=None):
+        """Whether run(n_steps) (default: all steps) runs its full chunks as persistent launches."""
+        n = self.prob["n_steps"] if n_steps is None else int(n_steps)
+        r = load().mb_run_mode(self._h, n)
+        _check(min(r, 0))
+        return r == 1
 
     @property
     def steps_done(self):

@@ -84,6 +84,13 @@ hipError_t run_steps(Engine &eng, hipStream_t st, int64_t steps, int k, bool use
   hipError_t e = eng.sync_tables(st);
   use_graph = use_graph && graphs_enabled();
   if (e != hipSuccess) return e;
+  // full chunks as persistent launches when every tile fits on the device at
+  // once (no graph: one launch covers thousands of chunks), then the tail
+  if (eng.persist_ok(k, steps / k)) {
+    e = eng.run_persistent(st, k, steps / k);
+    if (e == hipSuccess && steps % k) e = eng.chunk(st, int(steps % k));
+    return e;
+  }
   if (!use_graph) {
     while (steps > 0 && e == hipSuccess) {
       int kk = int(std::min<int64_t>(k, steps));
@@ -289,6 +296,18 @@ int mb_run(mb_handle *h, int64_t n_steps, void *hip_stream) {
   MB_GUARD_END
 }
 
+int mb_run_mode(mb_handle *h, int64_t n_steps) {
+  MB_GUARD_BEGIN
+  if (!h) return fail(MB_ERR_ARG, "null handle");
+  if (hipSetDevice(h->device) != hipSuccess) return fail(MB_ERR_HIP, "hipSetDevice failed");
+  if (h->eng->variant() == MB_VARIANT_PLAIN) return 0;
+  hipError_t e = h->eng->sync_tables(h->last_stream);
+  if (e != hipSuccess) return hip_fail(e, "table upload");
+  const int k = h->eng->chunk_steps();
+  return h->eng->persist_ok(k, n_steps / k) ? 1 : 0;
+  MB_GUARD_END
+}
+
 int mb_reset(mb_handle *h, void *hip_stream) {
   MB_GUARD_BEGIN
   if (!h) return fail(MB_ERR_ARG, "null handle");
@@ -349,7 +368,9 @@ int mb_read_records(mb_handle *h, int record_id, double *out, int64_t capacity, 
   if (!buf.empty()) std::memcpy(out, buf.data(), buf.size() * sizeof(double));
   if (n_out) *n_out = int64_t(buf.size());
   std::vector<int32_t> st;
-  if (h->eng->read_status(st) == hipSuccess && st[s.status_slot])
+  if (h->eng->read_status(st) == hipSuccess && (st[s.status_slot] & kStatusWaitTimeout))
+    return fail(MB_ERR_DEVICE, "a tile gave up waiting for its neighbours in a persistent launch");
+  if (st[s.status_slot] & kStatusNonFinite)
     return fail(MB_ERR_NONFINITE, "the simulation produced a non-finite field value");
   return MB_OK;
   MB_GUARD_END
@@ -503,7 +524,9 @@ int mb_batch_read_records(mb_batch *b, int32_t sim, int record_id, double *out, 
   if (!buf.empty()) std::memcpy(out, buf.data(), buf.size() * sizeof(double));
   if (n_out) *n_out = int64_t(buf.size());
   std::vector<int32_t> st;
-  if (b->eng->read_status(st) == hipSuccess && st[s.status_slot])
+  if (b->eng->read_status(st) == hipSuccess && (st[s.status_slot] & kStatusWaitTimeout))
+    return fail(MB_ERR_DEVICE, "a tile gave up waiting for its neighbours in a persistent launch");
+  if (st[s.status_slot] & kStatusNonFinite)
     return fail(MB_ERR_NONFINITE, "the simulation produced a non-finite field value");
   return MB_OK;
   MB_GUARD_END

@@ -53,7 +53,7 @@ struct DevSim {
   const int32_t *rec_first;  // nx+1 offsets into rec_cell (records at one cell), or null
   const DevRecord *rec_cell; // copies of the single-cell records, grouped by cell
   const int32_t *rec_all;    // whole-domain record ids
-  int32_t *status;           // bit 0: non-finite field seen
+  int32_t *status;           // kStatus* bits
   int32_t rec_every;         // gcd of the record intervals (1 when there are no records)
   // strong coupling: (n3D/dt) tr{mu rho^n} per cell (FP64 ping-pong like x) and per
   // material its readout (qc, aq[M]) from the rotated state
@@ -62,8 +62,24 @@ struct DevSim {
 };
 
 struct DevTile {
-  int32_t sim;  // index in the group's simulation table
-  int32_t c0;   // first output cell
+  int32_t sim;          // index in the group's simulation table
+  int32_t c0;           // first output cell
+  int32_t left, right;  // tiles owning the cells next to this tile's (same simulation), or -1
 };
+
+// Several chunks in one launch (a persistent launch): after each chunk a tile
+// writes its owned cells, raises its flag to the chunk's epoch and waits until
+// both neighbour tiles have raised theirs, so that it reloads its halo from
+// finished chunks.  All tiles of the launch must be resident at once.
+struct ChunkSync {
+  uint32_t *flags;     // one per tile: epoch of the last chunk the tile finished (null: one chunk)
+  uint32_t epoch;      // epoch of the launch's first chunk; chunk j ends at epoch + j + 1
+  int32_t n_chunks;    // chunks of k steps in this launch
+  int64_t spin_ticks;  // device wall-clock ticks a tile waits for a neighbour before giving up
+};
+
+// bits of DevSim::status
+constexpr int32_t kStatusNonFinite = 1;    // a non-finite field value was seen
+constexpr int32_t kStatusWaitTimeout = 2;  // a tile gave up waiting for a neighbour tile
 
 }  // namespace mb

@@ -291,14 +291,18 @@ __device__ __forceinline__ void record_fields(const DevSim &sim, int c, uint32_t
 
 // Single-cell records of one tile's owned cells, copied to LDS at the start
 // of a launch together with the readout row of each record's cell, so that a
-// recording step reads no record descriptors from global memory.
+// recording step reads no record descriptors from global memory.  A record's
+// interval is a multiple `mult` of the simulation's record period (the gcd of
+// all intervals); at the q-th multiple of the period (n1 = q * period) a
+// record is due when q % mult == 0 and takes sample q / mult - 1.
 constexpr int kTileRecs = 16;
 
 template <int N>
 struct TileRecs {
   static constexpr int RO = mat_m(N) + 1;
   double *out[kTileRecs];
-  uint32_t interval[kTileRecs];
+  int64_t n_out[kTileRecs];  // samples the output holds
+  uint32_t mult[kTileRecs];
   int32_t quantity[kTileRecs];
   double ro[kTileRecs][RO];
 
@@ -306,7 +310,8 @@ struct TileRecs {
   __device__ __forceinline__ void stage(const DevSim &sim, int i, int r) {
     const DevRecord &rc = sim.rec_cell[r];
     out[i] = rc.out;
-    interval[i] = uint32_t(rc.interval);
+    n_out[i] = sim.n_steps / rc.interval;
+    mult[i] = uint32_t(rc.interval / sim.rec_every);
     quantity[i] = rc.quantity;
     if (rc.quantity >= 2 && rc.readout) {
       const double *row = rc.readout + int(sim.mat_e[rc.cell]) * RO;
@@ -314,26 +319,37 @@ struct TileRecs {
     }
   }
 
+  // sample index of entry r at the q-th record period, or -1 when not due
+  // (or, defensively, outside the output)
+  __device__ __forceinline__ int64_t sample(int r, uint32_t q) const {
+    const uint32_t m = mult[r];
+    const int64_t at = m == 1u ? int64_t(q) - 1 : q % m == 0u ? int64_t(q / m) - 1 : -1;
+    return at < n_out[r] ? at : -1;
+  }
+
   // same arithmetic as Cell::readout
   template <typename R, int MA>
-  __device__ __forceinline__ void density(uint32_t n1, const R (&y)[MA], int rb, int re) const {
+  __device__ __forceinline__ void density(uint32_t q, const R (&y)[MA], int rb, int re) const {
     for (int r = rb; r < re; ++r) {
-      const uint32_t iv = interval[r];
-      if (quantity[r] < 2 || n1 % iv != 0u) continue;
+      if (quantity[r] < 2) continue;
+      const int64_t at = sample(r, q);
+      if (at < 0) continue;
       double acc = ro[r][0];
 #pragma unroll
       for (int j = 0; j < RO - 1; ++j) acc = fma(ro[r][1 + j], double(y[j]), acc);
-      out[r][n1 / iv - 1] = acc;
+      out[r][at] = acc;
     }
   }
 
   template <typename R>
-  __device__ __forceinline__ void fields(uint32_t n1, R e, R h, bool qm, int rb, int re) const {
+  __device__ __forceinline__ void fields(uint32_t q, R e, R h, bool qm, int rb, int re) const {
     for (int r = rb; r < re; ++r) {
-      const uint32_t iv = interval[r];
+      const int qty = quantity[r];
+      if (qty >= 2 && qm) continue;  // density record of a quantum cell: written by density()
+      const int64_t at = sample(r, q);
       double v;
-      if (n1 % iv != 0u || !field_value(quantity[r], e, h, qm, v)) continue;
-      out[r][n1 / iv - 1] = v;
+      if (at < 0 || !field_value(qty, e, h, qm, v)) continue;
+      out[r][at] = v;
     }
   }
 };
@@ -379,7 +395,25 @@ struct TileShared {
   R src[kTileSources][kMaxChunk];
   TileRecs<N> trec;
   R sy[2][GM][GB];  // rotated density rows of every cell (L > 1), by step parity
+  int stop;         // a neighbour wait gave up: the tile ends the launch
 };
+
+// true once both neighbour tiles have finished the chunk of epoch `target`;
+// false after cs.spin_ticks of the device wall clock (the launch is then
+// abandoned and the simulation's status reports it)
+__device__ __forceinline__ bool neighbours_reached(const ChunkSync &cs, const DevTile &tile, uint32_t target) {
+  const int64_t t0 = wall_clock64();
+  for (;;) {
+    bool ok = true;
+    if (tile.left >= 0)
+      ok = int32_t(__hip_atomic_load(cs.flags + tile.left, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) >= 0;
+    if (ok && tile.right >= 0)
+      ok = int32_t(__hip_atomic_load(cs.flags + tile.right, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) >= 0;
+    if (ok) return true;
+    if (wall_clock64() - t0 > cs.spin_ticks) return false;
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
 
 // split tiles stay at <= 512 threads (a 1024-thread workgroup caps a wave at
 // 128 registers, below what most density updates need), except FP32 with up
@@ -393,7 +427,8 @@ constexpr bool shape_fits() {
 
 template <int N, typename R, int B, int L, bool VC, int SUB, bool ST>
 __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, const DevTile *__restrict__ tiles,
-                                           int64_t n0, int parity, int halo, int k, TileShared<N, R, B, L> &sm) {
+                                           int64_t n0, int parity, int halo, int k, const ChunkSync &cs,
+                                           TileShared<N, R, B, L> &sm) {
   using CL = Cell<N, R>;
   using SP = Split<N, L>;
   constexpr int M = CL::M, MA = CL::MA, S = mat_stride(N);
@@ -403,15 +438,12 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
   // fields used inside the step loop are copied to locals below, so stores to
   // records cannot force them to be reloaded
   const DevSim &sim = sims[tile.sim];
-  const int64_t ls64 = n0 - sim.start;
-  if (ls64 < 0 || ls64 >= sim.n_steps) return;
-  const int ls0 = int(ls64);
-  const int ks = int(min(int64_t(k), sim.n_steps - ls64));
-  const int par = parity ^ sim.parity_off;
+  {
+    // nothing to do in any chunk of this launch (the range is uniform over the tile)
+    const int64_t first = n0 - sim.start, last = first + int64_t(cs.n_chunks) * k;
+    if (last <= 0 || first >= sim.n_steps) return;
+  }
   const int nx = int(sim.nx);
-  const R *__restrict__ e_in = static_cast<const R *>(sim.e[par]);
-  const R *__restrict__ h_in = static_cast<const R *>(sim.h[par]);
-  const R *__restrict__ x_in = static_cast<const R *>(sim.x[par]);
   const cptr<R> mtab = kconst<R>(sim.mtab);
   const int l = int(threadIdx.x) - SUB * B;  // cell lane
   const int lo = tile.c0 - halo;
@@ -419,41 +451,25 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
   const bool in = c >= 0 && c < nx;
   const bool own = in && l >= halo && l < B - halo;
   int me = 0;
-  R e = 0, h = 0, ca = 1, cbg = 0, cbd = 0, ch = 0;
-  R x[MA];
-#pragma unroll
-  for (int a = 0; a < MA; ++a) x[a] = 0;
+  R ca = 1, cbg = 0, cbd = 0, ch = 0;
   bool qm = false;
   if (in) {
     me = sim.mat_e[c];
     const int mh = sim.mat_h[c];
-    e = e_in[c];
-    h = h_in[c];
     ca = mtab[me * S + kCoefA];
     cbg = mtab[me * S + kCoefBG];
     cbd = mtab[me * S + kCoefBD];
     ch = mtab[mh * S + kCoefH];
-    if constexpr (N > 0) {
-      qm = mtab[me * S + kCoefQM] != R(0);
-      if (qm) {
-#pragma unroll
-        for (int a = 0; a < M; ++a)
-          if (SP::owns(SUB, a)) x[a] = x_in[a * nx + c];
-      }
-    }
+    if constexpr (N > 0) qm = mtab[me * S + kCoefQM] != R(0);
   }
-  // strong coupling: (n3D/dt) tr{mu rho^n} of the cell, carried in FP64
-  double qn = 0.0;
-  if constexpr (ST) {
-    if (qm) qn = sim.qs[par][c];
-  }
-  // sources inside this tile: their values for the whole chunk are staged in
-  // LDS (ordered before the first read by the first barrier of the loop); a
+  // sources inside this tile: their values for each chunk are staged in LDS
+  // (ordered before the first read by the first barrier of the step loop); a
   // lane knows the one staged source at its cell.  Tiles with more than
   // kTileSources sources, or two at one cell, read the source tables directly.
   int my_src = -1;
   bool my_hard = false;
   int staged_cell[kTileSources];
+  const double *staged_tab[kTileSources];
   int n_ts = 0;
   bool src_direct = false;
   for (int j = 0; j < sim.n_src; ++j) {
@@ -467,10 +483,12 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
       src_direct = true;
       break;
     }
-    for (int q = int(threadIdx.x); q < ks; q += B * L) sm.src[n_ts][q] = R(sj.table[ls0 + q + 1]);
 #pragma unroll
     for (int t = 0; t < kTileSources; ++t)
-      if (t == n_ts) staged_cell[t] = cell;
+      if (t == n_ts) {
+        staged_cell[t] = cell;
+        staged_tab[t] = sj.table;
+      }
     if (cell == c) {
       my_src = n_ts;
       my_hard = sj.hard != 0;
@@ -482,11 +500,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
   // H at the left node (cell c-1) is advanced here too, with the arithmetic
   // of the lane that owns it, so no exchange of H is needed
   const bool hleft = in && c >= 1;
-  R hl = 0, chl = 0;
-  if (hleft) {
-    hl = h_in[c - 1];
-    chl = mtab[int(sim.mat_h[c - 1]) * S + kCoefH];
-  }
+  const R chl = hleft ? mtab[int(sim.mat_h[c - 1]) * S + kCoefH] : R(0);
   const bool left = in && nx > 1 && c == 0, right = in && nx > 1 && c == nx - 1;
   const bool mur_tile = nx > 1 && ((sim.edge_l == 1 && lo <= 0 && 0 < lo + B) ||
                                    (sim.edge_r == 1 && lo <= nx - 1 && nx - 1 < lo + B));
@@ -526,34 +540,26 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
     if (t < coef_am(N)) return SP::owns(SUB, t - coef_bf(N));
     return SP::owns(SUB, (t - coef_am(N)) / (M > 0 ? M : 1));
   };
+  // (each lane holds its own cell's material, so waves across a material
+  // boundary cost the same as single-material ones)
   R cf[VC ? SQ : 1];
-  bool wave_uni = false;
-  int mm0 = 0;
   if constexpr (VC && N > 0) {
-    const uint64_t qmask = __ballot(qm);
-    if (qmask) {
-      mm0 = __builtin_amdgcn_readlane(me, __ffsll(static_cast<unsigned long long>(qmask)) - 1);
-      wave_uni = __ballot(qm && me != mm0) == 0;
-      if (wave_uni) {
-        const cptr<R> mt0 = mtab + __builtin_amdgcn_readfirstlane(mm0 * S);
 #pragma unroll
-        for (int i = 0; i < SQ; ++i)
-          if (coef_used(i)) cf[i] = mt0[kCoefKap + i];
-        // opaque register copies: keeps the compiler from re-loading the
-        // coefficients from constant memory inside the step loop
+    for (int i = 0; i < SQ; ++i)
+      if (coef_used(i)) cf[i] = qm ? mtab[me * S + kCoefKap + i] : R(0);
+    // opaque register copies: keeps the compiler from re-loading the
+    // coefficients from memory inside the step loop
 #pragma unroll
-        for (int i = 0; i < SQ; ++i)
-          if (coef_used(i)) asm volatile("" : "+v"(cf[i]));
-      }
-    }
+    for (int i = 0; i < SQ; ++i)
+      if (coef_used(i)) asm volatile("" : "+v"(cf[i]));
   }
-  if constexpr (WAVE) __syncthreads();  // staged source values and records visible
 
-  // runs f(coefficients, material) once per material present among the
-  // wave's quantum cells, for the lanes of that material
+  // runs f(coefficients, material) for the wave's quantum cells: once with
+  // the lanes' register coefficients, or once per material present (scalar
+  // loads of that material's coefficients) for the lanes of that material
   auto per_material = [&](auto &&f) {
-    if (VC && wave_uni) {
-      if (qm) f(RegCoef<R, VC ? SQ : 1>{cf}, mm0);
+    if constexpr (VC) {
+      if (qm) f(RegCoef<R, VC ? SQ : 1>{cf}, me);
     } else {
       uint64_t todo = __ballot(qm);
       while (todo) {
@@ -565,6 +571,10 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
       }
     }
   };
+
+  R e = 0, h = 0, hl = 0;
+  R x[MA];
+  double qn = 0.0;  // strong coupling: (n3D/dt) tr{mu rho^n} of the cell, carried in FP64
 
   // density rows of this wave group rotated by the field phases of E and
   // published for the other groups (L > 1); the rotation of step s + 1 runs
@@ -579,153 +589,209 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
       });
     }
   };
-  rotate_publish(0);
 
-  for (int s = 0; s < ks; ++s) {
-    const uint32_t n1 = uint32_t(ls0 + s + 1);
-    const bool rec_step = rec_tile && n1 % rec_every == 0u;  // uniform: a recording step
-    const int buf = s & 1;
-    R er, el;
-    if constexpr (WAVE) {
-      er = lane_from_right(e);
-      el = lane_from_left(e);
-    } else {
-      if (SUB == 0) sm.se[buf][l] = e;
-      __syncthreads();
-      er = l + 1 < B ? sm.se[buf][l + 1] : R(0);
-      el = l > 0 ? sm.se[buf][l - 1] : R(0);
-    }
-    if constexpr (L > 1 && N > 0) {
-      if (qm) {
+  for (int chunk = 0; chunk < cs.n_chunks; ++chunk) {
+    const int64_t ls64 = n0 + int64_t(chunk) * k - sim.start;
+    if (ls64 >= sim.n_steps) break;  // the simulation has finished (uniform over its tiles)
+    if (ls64 < 0) continue;          // not started yet (uniform over its tiles)
+    const int ls0 = int(ls64);
+    const int ks = int(min(int64_t(k), sim.n_steps - ls64));
+    const int par = parity ^ (chunk & 1) ^ sim.parity_off;
+    const R *__restrict__ e_in = static_cast<const R *>(sim.e[par]);
+    const R *__restrict__ h_in = static_cast<const R *>(sim.h[par]);
+    const R *__restrict__ x_in = static_cast<const R *>(sim.x[par]);
+    e = h = hl = 0;
 #pragma unroll
-        for (int a = 0; a < M; ++a)
-          if (!SP::owns(SUB, a)) x[a] = sm.sy[buf][a][l];
+    for (int a = 0; a < MA; ++a) x[a] = 0;
+    if (in) {
+      e = e_in[c];
+      h = h_in[c];
+      if constexpr (N > 0) {
+        if (qm) {
+#pragma unroll
+          for (int a = 0; a < M; ++a)
+            if (SP::owns(SUB, a)) x[a] = x_in[a * nx + c];
+        }
       }
     }
-    h = hcell ? fma(ch, er - e, h) : h;
-    hl = hleft ? fma(chl, e - el, hl) : hl;
-    R p = 0;
-    if constexpr (ST && N > 0) {
-      // strong coupling: the E update of an interior quantum cell depends on
-      // rho^{n+1}, driven by (E^n + E^{n+1})/2; fixed-point iteration from the
-      // field without polarization
-      per_material([&](const auto &mt, int mm) {
-        const cptr<double> qt = kconst<double>(sim.qtab) + __builtin_amdgcn_readfirstlane(mm * (M + 1));
-        R pi = 0;
-        for (int it = 0; it < kStrongIters; ++it) {
-          const R es = fma(cbd, h - hl, fma(ca, e, -(cbg * pi)));
-          R yv[MA];
-#pragma unroll
-          for (int a = 0; a < MA; ++a) yv[a] = x[a];
-          CL::rotate(yv, R(0.5) * (e + es), mt);
-          double q = qt[0];
-#pragma unroll
-          for (int j = 0; j < M; ++j) q = fma(qt[1 + j], double(yv[j]), q);
-          pi = R(q - qn);
-        }
-        p = pi;
-      });
-    } else if constexpr (N > 0) {
-      auto finish = [&](const auto &mt, int mm) {
-        p = CL::polar(x, mt);
-        if (rec_step) {
-          if (rec_here) {
-            if (rec_lds) {
-              sm.trec.density(n1, x, rb, re);
-              record_density_all<N, R>(sim, c, n1, mm, x);
-            } else {
-              record_density<N, R>(sim, c, n1, mm, x, rb, re);
-            }
-          }
-        }
-        CL::template propagate<L, SUB>(x, mt);
-      };
-      if constexpr (L == 1) {
-        per_material([&](const auto &mt, int mm) {
-          CL::rotate(x, e, mt);
-          finish(mt, mm);
-        });
-      } else {
-        per_material(finish);
-      }
+    if constexpr (ST) {
+      if (qm) qn = sim.qs[par][c];
     }
-    const R eo = e;
-    e = ecell ? fma(cbd, h - hl, fma(ca, eo, -(cbg * p))) : e;
-    if (mur_tile) {
-      R enr, enl;
+    if (hleft) hl = h_in[c - 1];
+    for (int t = 0; t < n_ts; ++t)
+      for (int q = int(threadIdx.x); q < ks; q += B * L) sm.src[t][q] = R(staged_tab[t][ls0 + q + 1]);
+    // record periods: steps left before the next one, and its index
+    uint32_t rec_in = rec_every - 1u - uint32_t(ls0) % rec_every;
+    uint32_t rec_q = uint32_t(ls0) / rec_every + 1u;
+    if constexpr (WAVE) __syncthreads();  // staged source values and records visible
+
+    rotate_publish(0);
+
+    for (int s = 0; s < ks; ++s) {
+      const uint32_t n1 = uint32_t(ls0 + s + 1);
+      const bool rec_step = rec_tile && rec_in == 0u;  // uniform: n1 is a multiple of the record period
+      const uint32_t rq = rec_q;  // n1 / record period on a recording step
+      rec_in = rec_in == 0u ? rec_every - 1u : rec_in - 1u;
+      rec_q += rec_in == rec_every - 1u ? 1u : 0u;
+      const int buf = s & 1;
+      R er, el;
       if constexpr (WAVE) {
-        enr = lane_from_right(e);
-        enl = lane_from_left(e);
+        er = lane_from_right(e);
+        el = lane_from_left(e);
       } else {
-        if (SUB == 0) sm.se2[l] = e;
+        if (SUB == 0) sm.se[buf][l] = e;
         __syncthreads();
-        enr = l + 1 < B ? sm.se2[l + 1] : R(0);
-        enl = l > 0 ? sm.se2[l - 1] : R(0);
+        er = l + 1 < B ? sm.se[buf][l + 1] : R(0);
+        el = l > 0 ? sm.se[buf][l - 1] : R(0);
       }
-      e = mur_l ? fma(kap_l, enr - eo, er) : e;
-      e = mur_r ? fma(kap_r, enl - eo, el) : e;
-    }
-    e = pec ? R(0) : e;
-    e = load_l ? fma(lg_l, eo, ld_l * h) : e;        // H_{1/2} is this lane's own
-    e = load_r ? fma(lg_r, eo, -(ld_r * hl)) : e;    // H_{nx-3/2} is the tracked left node
-    if (src_direct) {
-      if (in) e = apply_sources(sim, c, n1, e);
-    } else if (my_src >= 0) {
-      const R v = sm.src[my_src][s];
-      e = my_hard ? v : e + v;
-    }
-    if constexpr (ST && N > 0) {
-      // rho^{n+1} with the final E^{n+1}: rotation by the midpoint field, the
-      // new tr{mu rho}, records of rho^{n+1}, propagation of the running state
-      per_material([&](const auto &mt, int mm) {
-        const cptr<double> qt = kconst<double>(sim.qtab) + __builtin_amdgcn_readfirstlane(mm * (M + 1));
-        CL::rotate(x, R(0.5) * (eo + e), mt);
-        double q = qt[0];
+      if constexpr (L > 1 && N > 0) {
+        if (qm) {
 #pragma unroll
-        for (int j = 0; j < M; ++j) q = fma(qt[1 + j], double(x[j]), q);
-        qn = q;
-        if (rec_step) {
-          if (rec_here) {
-            if (rec_lds) {
-              sm.trec.density(n1, x, rb, re);
-              record_density_all<N, R>(sim, c, n1, mm, x);
-            } else {
-              record_density<N, R>(sim, c, n1, mm, x, rb, re);
+          for (int a = 0; a < M; ++a)
+            if (!SP::owns(SUB, a)) x[a] = sm.sy[buf][a][l];
+        }
+      }
+      h = hcell ? fma(ch, er - e, h) : h;
+      hl = hleft ? fma(chl, e - el, hl) : hl;
+      R p = 0;
+      if constexpr (ST && N > 0) {
+        // strong coupling: the E update of an interior quantum cell depends on
+        // rho^{n+1}, driven by (E^n + E^{n+1})/2; fixed-point iteration from the
+        // field without polarization
+        per_material([&](const auto &mt, int mm) {
+          const cptr<double> qt = kconst<double>(sim.qtab) + __builtin_amdgcn_readfirstlane(mm * (M + 1));
+          R pi = 0;
+          for (int it = 0; it < kStrongIters; ++it) {
+            const R es = fma(cbd, h - hl, fma(ca, e, -(cbg * pi)));
+            R yv[MA];
+#pragma unroll
+            for (int a = 0; a < MA; ++a) yv[a] = x[a];
+            CL::rotate(yv, R(0.5) * (e + es), mt);
+            double tq = qt[0];
+#pragma unroll
+            for (int j = 0; j < M; ++j) tq = fma(qt[1 + j], double(yv[j]), tq);
+            pi = R(tq - qn);
+          }
+          p = pi;
+        });
+      } else if constexpr (N > 0) {
+        auto finish = [&](const auto &mt, int mm) {
+          p = CL::polar(x, mt);
+          if (rec_step) {
+            if (rec_here) {
+              if (rec_lds) {
+                sm.trec.density(rq, x, rb, re);
+                record_density_all<N, R>(sim, c, n1, mm, x);
+              } else {
+                record_density<N, R>(sim, c, n1, mm, x, rb, re);
+              }
             }
           }
-        }
-        CL::propagate(x, mt);
-      });
-    }
-    if (rec_step) {
-      if (rec_here) {
-        if (rec_lds) {
-          sm.trec.fields(n1, e, hcell ? h : R(0), qm, rb, re);
-          record_fields_all(sim, c, n1, e, hcell ? h : R(0), qm);
+          CL::template propagate<L, SUB>(x, mt);
+        };
+        if constexpr (L == 1) {
+          per_material([&](const auto &mt, int mm) {
+            CL::rotate(x, e, mt);
+            finish(mt, mm);
+          });
         } else {
-          record_fields(sim, c, n1, e, hcell ? h : R(0), qm, rb, re);
+          per_material(finish);
         }
       }
-    }
-    if (s + 1 < ks) rotate_publish(buf ^ 1);
-  }
-  if (own) {
-    R *__restrict__ e_out = static_cast<R *>(sim.e[par ^ 1]);
-    R *__restrict__ h_out = static_cast<R *>(sim.h[par ^ 1]);
-    R *__restrict__ x_out = static_cast<R *>(sim.x[par ^ 1]);
-    if (SUB == 0) {
-      e_out[c] = e;
-      h_out[c] = h;
-    }
-    if constexpr (N > 0) {
-      if (qm) {
-#pragma unroll
-        for (int a = 0; a < M; ++a)
-          if (SP::owns(SUB, a)) x_out[a * nx + c] = x[a];
-        if constexpr (ST) sim.qs[par ^ 1][c] = qn;
+      const R eo = e;
+      e = ecell ? fma(cbd, h - hl, fma(ca, eo, -(cbg * p))) : e;
+      if (mur_tile) {
+        R enr, enl;
+        if constexpr (WAVE) {
+          enr = lane_from_right(e);
+          enl = lane_from_left(e);
+        } else {
+          if (SUB == 0) sm.se2[l] = e;
+          __syncthreads();
+          enr = l + 1 < B ? sm.se2[l + 1] : R(0);
+          enl = l > 0 ? sm.se2[l - 1] : R(0);
+        }
+        e = mur_l ? fma(kap_l, enr - eo, er) : e;
+        e = mur_r ? fma(kap_r, enl - eo, el) : e;
       }
+      e = pec ? R(0) : e;
+      e = load_l ? fma(lg_l, eo, ld_l * h) : e;        // H_{1/2} is this lane's own
+      e = load_r ? fma(lg_r, eo, -(ld_r * hl)) : e;    // H_{nx-3/2} is the tracked left node
+      if (src_direct) {
+        if (in) e = apply_sources(sim, c, n1, e);
+      } else if (my_src >= 0) {
+        const R v = sm.src[my_src][s];
+        e = my_hard ? v : e + v;
+      }
+      if constexpr (ST && N > 0) {
+        // rho^{n+1} with the final E^{n+1}: rotation by the midpoint field, the
+        // new tr{mu rho}, records of rho^{n+1}, propagation of the running state
+        per_material([&](const auto &mt, int mm) {
+          const cptr<double> qt = kconst<double>(sim.qtab) + __builtin_amdgcn_readfirstlane(mm * (M + 1));
+          CL::rotate(x, R(0.5) * (eo + e), mt);
+          double tq = qt[0];
+#pragma unroll
+          for (int j = 0; j < M; ++j) tq = fma(qt[1 + j], double(x[j]), tq);
+          qn = tq;
+          if (rec_step) {
+            if (rec_here) {
+              if (rec_lds) {
+                sm.trec.density(rq, x, rb, re);
+                record_density_all<N, R>(sim, c, n1, mm, x);
+              } else {
+                record_density<N, R>(sim, c, n1, mm, x, rb, re);
+              }
+            }
+          }
+          CL::propagate(x, mt);
+        });
+      }
+      if (rec_step) {
+        if (rec_here) {
+          if (rec_lds) {
+            sm.trec.fields(rq, e, hcell ? h : R(0), qm, rb, re);
+            record_fields_all(sim, c, n1, e, hcell ? h : R(0), qm);
+          } else {
+            record_fields(sim, c, n1, e, hcell ? h : R(0), qm, rb, re);
+          }
+        }
+      }
+      if (s + 1 < ks) rotate_publish(buf ^ 1);
     }
-    if (SUB == 0 && (!isfinite(double(e)) || !isfinite(double(h)))) *sim.status = 1;
+    if (own) {
+      R *__restrict__ e_out = static_cast<R *>(sim.e[par ^ 1]);
+      R *__restrict__ h_out = static_cast<R *>(sim.h[par ^ 1]);
+      R *__restrict__ x_out = static_cast<R *>(sim.x[par ^ 1]);
+      if (SUB == 0) {
+        e_out[c] = e;
+        h_out[c] = h;
+      }
+      if constexpr (N > 0) {
+        if (qm) {
+#pragma unroll
+          for (int a = 0; a < M; ++a)
+            if (SP::owns(SUB, a)) x_out[a * nx + c] = x[a];
+          if constexpr (ST) sim.qs[par ^ 1][c] = qn;
+        }
+      }
+      if (SUB == 0 && (!isfinite(double(e)) || !isfinite(double(h)))) atomicOr(sim.status, kStatusNonFinite);
+    }
+    if (cs.flags && chunk + 1 < cs.n_chunks) {
+      // the owned cells of every wave are written before the tile's flag is
+      // raised; the halo of the next chunk is read after both neighbours' flags
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const uint32_t target = cs.epoch + uint32_t(chunk) + 1u;
+        __hip_atomic_store(cs.flags + blockIdx.x, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        bool ok = neighbours_reached(cs, tile, target);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        sm.stop = !ok;
+        if (!ok) atomicOr(sim.status, kStatusWaitTimeout);
+      }
+      __syncthreads();
+      if (sm.stop) return;
+    }
   }
 }
 
@@ -733,14 +799,15 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
 // executes the same sequence of barriers
 template <int N, typename R, int B, int L, bool VC, int S = 0>
 __device__ __forceinline__ void run_group(int sub, const DevSim *__restrict__ sims, const DevTile *__restrict__ tiles,
-                                          int64_t n0, int parity, int halo, int k, TileShared<N, R, B, L> &sm) {
+                                          int64_t n0, int parity, int halo, int k, const ChunkSync &cs,
+                                          TileShared<N, R, B, L> &sm) {
   if constexpr (S + 1 < L) {
     if (sub == S)
-      tile_steps<N, R, B, L, VC, S, false>(sims, tiles, n0, parity, halo, k, sm);
+      tile_steps<N, R, B, L, VC, S, false>(sims, tiles, n0, parity, halo, k, cs, sm);
     else
-      run_group<N, R, B, L, VC, S + 1>(sub, sims, tiles, n0, parity, halo, k, sm);
+      run_group<N, R, B, L, VC, S + 1>(sub, sims, tiles, n0, parity, halo, k, cs, sm);
   } else {
-    tile_steps<N, R, B, L, VC, S, false>(sims, tiles, n0, parity, halo, k, sm);
+    tile_steps<N, R, B, L, VC, S, false>(sims, tiles, n0, parity, halo, k, cs, sm);
   }
 }
 
@@ -748,13 +815,13 @@ __device__ __forceinline__ void run_group(int sub, const DevSim *__restrict__ si
 template <int N, typename R, int B, int L, bool VC, bool ST = false>
 __global__ void __launch_bounds__(B * L) k_blocked(const DevSim *__restrict__ sims,
                                                    const DevTile *__restrict__ tiles, int64_t n0, int parity,
-                                                   int halo, int k) {
+                                                   int halo, int k, ChunkSync cs) {
   __shared__ TileShared<N, R, B, L> sm;
   if constexpr (L == 1) {
-    tile_steps<N, R, B, 1, VC, 0, ST>(sims, tiles, n0, parity, halo, k, sm);
+    tile_steps<N, R, B, 1, VC, 0, ST>(sims, tiles, n0, parity, halo, k, cs, sm);
   } else {
     run_group<N, R, B, L, VC>(__builtin_amdgcn_readfirstlane(int(threadIdx.x) / B), sims, tiles, n0, parity, halo,
-                              k, sm);
+                              k, cs, sm);
   }
 }
 
@@ -871,14 +938,25 @@ __global__ void __launch_bounds__(kPlainBlock) k_plain_e(const DevSim *__restric
     record_range(sim, c, rb, re);
     record_fields(sim, c, n1, e, c <= nx - 2 ? hh[c] : 0.0, qm, rb, re);
   }
-  if (!isfinite(e)) *sim.status = 1;
+  if (!isfinite(e)) atomicOr(sim.status, kStatusNonFinite);
 }
 
+// Launch (per_cu null) or occupancy query (resident tiles per compute unit
+// into *per_cu) of one tile shape.  A launch of several chunks is cooperative:
+// every tile must be resident for the neighbour flags to make progress.
 template <int N, typename R, int B, int L, bool VC, bool ST = false>
 hipError_t launch_shape(const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo,
-                        int k, hipStream_t st) {
+                        int k, const ChunkSync &cs, int *per_cu, hipStream_t st) {
   if constexpr (shape_fits<N, R, B, L>() && (!ST || (L == 1 && !VC && N >= 2))) {
-    k_blocked<N, R, B, L, VC, ST><<<n_tiles, B * L, 0, st>>>(sims, tiles, n0, parity, halo, k);
+    auto kern = k_blocked<N, R, B, L, VC, ST>;
+    if (per_cu) return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kern, B * L, 0);
+    if (cs.n_chunks > 1) {
+      ChunkSync c = cs;
+      void *args[] = {&sims, &tiles, &n0, &parity, &halo, &k, &c};
+      return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(n_tiles), dim3(B * L), args, 0,
+                                        st);
+    }
+    kern<<<n_tiles, B * L, 0, st>>>(sims, tiles, n0, parity, halo, k, cs);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -887,13 +965,14 @@ hipError_t launch_shape(const DevSim *sims, const DevTile *tiles, int n_tiles, i
 
 template <int N, typename R, int L, bool VC, bool ST = false>
 hipError_t launch_blocked_b(int block, const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0,
-                            int parity, int halo, int k, hipStream_t st) {
+                            int parity, int halo, int k, const ChunkSync &cs, int *per_cu, hipStream_t st) {
   switch (block) {
-    case 64: return launch_shape<N, R, 64, L, VC, ST>(sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 128: return launch_shape<N, R, 128, L, VC, ST>(sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 256: return launch_shape<N, R, 256, L, VC, ST>(sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 512: return launch_shape<N, R, 512, L, VC, ST>(sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 1024: return launch_shape<N, R, 1024, L, VC, ST>(sims, tiles, n_tiles, n0, parity, halo, k, st);
+    case 64: return launch_shape<N, R, 64, L, VC, ST>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+    case 128: return launch_shape<N, R, 128, L, VC, ST>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+    case 192: return launch_shape<N, R, 192, L, VC, ST>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+    case 256: return launch_shape<N, R, 256, L, VC, ST>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+    case 512: return launch_shape<N, R, 512, L, VC, ST>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+    case 1024: return launch_shape<N, R, 1024, L, VC, ST>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
   }
   return hipErrorInvalidValue;
 }
@@ -902,33 +981,36 @@ hipError_t launch_blocked_b(int block, const DevSim *sims, const DevTile *tiles,
 // only, split waves for the quantum level counts
 template <int N, typename R>
 hipError_t launch_blocked_nr(int block, int lanes, bool vc, bool strong, const DevSim *sims, const DevTile *tiles,
-                             int n_tiles, int64_t n0, int parity, int halo, int k, hipStream_t st) {
+                             int n_tiles, int64_t n0, int parity, int halo, int k, const ChunkSync &cs, int *per_cu,
+                             hipStream_t st) {
   constexpr bool kVC = N == 2 || N == 3;
   if (strong) {
     if constexpr (N >= 2)
-      return launch_blocked_b<N, R, 1, false, true>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+      return launch_blocked_b<N, R, 1, false, true>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
     return hipErrorInvalidValue;
   }
   switch (lanes) {
     case 1:
       if constexpr (kVC)
-        if (vc) return launch_blocked_b<N, R, 1, kVC>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
-      return launch_blocked_b<N, R, 1, false>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+        if (vc) return launch_blocked_b<N, R, 1, kVC>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+      return launch_blocked_b<N, R, 1, false>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
     case 2:
     case 4:
       if constexpr (N >= 2) {
         if (lanes == 2) {
           if constexpr (kVC)
-            if (vc) return launch_blocked_b<N, R, 2, kVC>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
-          return launch_blocked_b<N, R, 2, false>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+            if (vc)
+              return launch_blocked_b<N, R, 2, kVC>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+          return launch_blocked_b<N, R, 2, false>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
         }
         if constexpr (kVC)
-          if (vc) return launch_blocked_b<N, R, 4, kVC>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
-        return launch_blocked_b<N, R, 4, false>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+          if (vc) return launch_blocked_b<N, R, 4, kVC>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+        return launch_blocked_b<N, R, 4, false>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
       }
       break;
     case 8:  // 64-cell tiles of the large density updates only
-      if constexpr (N >= 4) return launch_blocked_b<N, R, 8, false>(block, sims, tiles, n_tiles, n0, parity, halo, k, st);
+      if constexpr (N >= 4)
+        return launch_blocked_b<N, R, 8, false>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
       break;
   }
   return hipErrorInvalidValue;
@@ -937,14 +1019,19 @@ hipError_t launch_blocked_nr(int block, int lanes, bool vc, bool strong, const D
 template <typename R>
 hipError_t launch_blocked_r(int levels, int block, int lanes, bool vc, bool strong, const DevSim *sims,
                             const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo, int k,
-                            hipStream_t st) {
+                            const ChunkSync &cs, int *per_cu, hipStream_t st) {
   switch (levels) {
-    case 0: return launch_blocked_nr<0, R>(block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 2: return launch_blocked_nr<2, R>(block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 3: return launch_blocked_nr<3, R>(block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 4: return launch_blocked_nr<4, R>(block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 5: return launch_blocked_nr<5, R>(block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, st);
-    case 6: return launch_blocked_nr<6, R>(block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, st);
+#define MB_LEVELS_CASE(n)                                                                                       \
+  case n:                                                                                                         \
+    return launch_blocked_nr<n, R>(block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, \
+                                   st);
+    MB_LEVELS_CASE(0)
+    MB_LEVELS_CASE(2)
+    MB_LEVELS_CASE(3)
+    MB_LEVELS_CASE(4)
+    MB_LEVELS_CASE(5)
+    MB_LEVELS_CASE(6)
+#undef MB_LEVELS_CASE
   }
   return hipErrorInvalidValue;
 }
@@ -956,6 +1043,7 @@ bool fits_n(int block, int lanes) {
     switch (block) {
       case 64: return shape_fits<N, R, 64, Lc>();
       case 128: return shape_fits<N, R, 128, Lc>();
+      case 192: return shape_fits<N, R, 192, Lc>();
       case 256: return shape_fits<N, R, 256, Lc>();
       case 512: return shape_fits<N, R, 512, Lc>();
       case 1024: return shape_fits<N, R, 1024, Lc>();
@@ -1005,14 +1093,15 @@ hipError_t launch_plain_n(const DevSim *sims, const DevTile *tiles, int n_tiles,
 
 hipError_t launch_blocked_f32(int levels, int block, int lanes, bool vc, bool strong, const DevSim *sims,
                               const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo, int k,
-                              hipStream_t st);
+                              const ChunkSync &cs, int *per_cu, hipStream_t st);
 bool fits_f32(int levels, int block, int lanes);
 
 #if MB_PART != 2
 hipError_t launch_blocked_f32(int levels, int block, int lanes, bool vc, bool strong, const DevSim *sims,
                               const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo, int k,
-                              hipStream_t st) {
-  return launch_blocked_r<float>(levels, block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, st);
+                              const ChunkSync &cs, int *per_cu, hipStream_t st) {
+  return launch_blocked_r<float>(levels, block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, cs,
+                                 per_cu, st);
 }
 
 bool fits_f32(int levels, int block, int lanes) { return fits_r<float>(levels, block, lanes); }
@@ -1020,7 +1109,7 @@ bool fits_f32(int levels, int block, int lanes) { return fits_r<float>(levels, b
 
 #if MB_PART != 1
 bool block_supported(int block) {
-  return block == 64 || block == 128 || block == 256 || block == 512 || block == 1024;
+  return block == 64 || block == 128 || block == 192 || block == 256 || block == 512 || block == 1024;
 }
 
 bool shape_supported(int levels, int precision, int block, int lanes) {
@@ -1032,13 +1121,25 @@ int plain_block() { return kPlainBlock; }
 
 hipError_t launch_blocked(int levels, int precision, int block, int lanes, bool vc, bool strong,
                           const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo,
-                          int k, hipStream_t st) {
+                          int k, const ChunkSync &cs, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
-  if (k < 1 || k > halo || k > kMaxChunk || 2 * halo >= block) return hipErrorInvalidValue;
+  if (k < 1 || k > halo || k > kMaxChunk || 2 * halo >= block || cs.n_chunks < 1) return hipErrorInvalidValue;
+  if (cs.n_chunks > 1 && (!cs.flags || k != halo || 3 * halo > block)) return hipErrorInvalidValue;
   if (precision == 64)
-    return launch_blocked_r<double>(levels, block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k,
-                                    st);
-  return launch_blocked_f32(levels, block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, st);
+    return launch_blocked_r<double>(levels, block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, cs,
+                                    nullptr, st);
+  return launch_blocked_f32(levels, block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, cs, nullptr,
+                            st);
+}
+
+int blocked_tiles_per_cu(int levels, int precision, int block, int lanes, bool vc, bool strong) {
+  int per_cu = 0;
+  const ChunkSync none{nullptr, 0u, 1, 0};
+  hipError_t e = precision == 64 ? launch_blocked_r<double>(levels, block, lanes, vc, strong, nullptr, nullptr, 0, 0,
+                                                            0, 1, 1, none, &per_cu, nullptr)
+                                 : launch_blocked_f32(levels, block, lanes, vc, strong, nullptr, nullptr, 0, 0, 0, 1, 1,
+                                                      none, &per_cu, nullptr);
+  return e == hipSuccess ? per_cu : 0;
 }
 
 hipError_t launch_plain(int levels, const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity,

@@ -1,6 +1,7 @@
 #include "runtime.hpp"
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 
@@ -197,6 +198,7 @@ Engine::~Engine() {
   for (auto &g : groups_) {
     if (g.d_sims) (void)hipFree(g.d_sims);
     if (g.d_tiles) (void)hipFree(g.d_tiles);
+    if (g.d_flags) (void)hipFree(g.d_flags);
   }
   if (d_status_) (void)hipFree(d_status_);
   for (hipStream_t q : side_) (void)hipStreamDestroy(q);
@@ -211,7 +213,7 @@ int Engine::init(std::string &err) {
   }
   if (variant_ != MB_VARIANT_PLAIN) {
     if (!block_supported(block_) || halo_ < 1 || 2 * halo_ >= block_) {
-      err = "blocked variant needs block in {64,128,256,512,1024} and 1 <= depth < block/2";
+      err = "blocked variant needs block in {64,128,192,256,512,1024} and 1 <= depth < block/2";
       return MB_ERR_ARG;
     }
     if (lanes_ != 0 && lanes_ != 1 && lanes_ != 2 && lanes_ != 4 && lanes_ != 8) {
@@ -222,6 +224,13 @@ int Engine::init(std::string &err) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device_) == hipSuccess && prop.multiProcessorCount > 0)
     n_cu_ = prop.multiProcessorCount;
+  if (const char *v = std::getenv("MB_PERSIST")) persist_ = std::string(v) != "0";
+  int coop = 0, clock_khz = 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device_) != hipSuccess || !coop)
+    persist_ = false;
+  if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, device_) != hipSuccess || clock_khz <= 0)
+    persist_ = false;
+  spin_ticks_ = int64_t(clock_khz) * 1000 * 2;  // two seconds
   if (hipMalloc(&d_status_, kStatusSlots * sizeof(int32_t)) != hipSuccess) {
     err = "device allocation failed";
     return MB_ERR_OOM;
@@ -425,7 +434,12 @@ hipError_t Engine::upload_group(Group &g, hipStream_t st) {
     const SimState &s = *sims_[id];
     int32_t local = int32_t(hs.size());
     hs.push_back(s.ds);
-    for (int64_t c0 = 0; c0 < s.plan.nx; c0 += span) ht.push_back(DevTile{local, int32_t(c0)});
+    const int32_t first = int32_t(ht.size());
+    for (int64_t c0 = 0; c0 < s.plan.nx; c0 += span) {
+      const int32_t idx = int32_t(ht.size());
+      ht.push_back(DevTile{local, int32_t(c0), idx > first ? idx - 1 : -1, -1});
+      if (idx > first) ht[idx - 1].right = idx;
+    }
   }
   if (int(hs.size()) > g.cap_sims) {
     if (g.d_sims) (void)hipFree(g.d_sims);
@@ -434,13 +448,20 @@ hipError_t Engine::upload_group(Group &g, hipStream_t st) {
   }
   if (int(ht.size()) > g.cap_tiles) {
     if (g.d_tiles) (void)hipFree(g.d_tiles);
+    if (g.d_flags) (void)hipFree(g.d_flags);
+    g.d_flags = nullptr;
     g.cap_tiles = std::max<int>(int(ht.size()), 2 * g.cap_tiles);
     if (hipMalloc(&g.d_tiles, size_t(g.cap_tiles) * sizeof(DevTile)) != hipSuccess) return hipErrorOutOfMemory;
+    if (hipMalloc(&g.d_flags, size_t(g.cap_tiles) * sizeof(uint32_t)) != hipSuccess) return hipErrorOutOfMemory;
   }
   hipError_t e = hipSuccess;
   if (!hs.empty()) e = hipMemcpyAsync(g.d_sims, hs.data(), hs.size() * sizeof(DevSim), hipMemcpyHostToDevice, st);
   if (e == hipSuccess && !ht.empty())
     e = hipMemcpyAsync(g.d_tiles, ht.data(), ht.size() * sizeof(DevTile), hipMemcpyHostToDevice, st);
+  // every tile's flag at the epoch of the next persistent launch (earlier epochs count as finished)
+  std::vector<uint32_t> hf(ht.size(), epoch_);
+  if (e == hipSuccess && !hf.empty())
+    e = hipMemcpyAsync(g.d_flags, hf.data(), hf.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   g.n_tiles = int(ht.size());
   return e;
@@ -488,9 +509,50 @@ hipError_t Engine::launch_group(Group &g, hipStream_t st, int k, int reps) {
           return e;
       }
     } else if ((e = launch_blocked(g.levels, precision_, block_, lanes, vc_, g.strong, g.d_sims, g.d_tiles, g.n_tiles,
-                                   n0_ + int64_t(r) * k, parity_ ^ (r & 1), halo_, k, st)) != hipSuccess) {
+                                   n0_ + int64_t(r) * k, parity_ ^ (r & 1), halo_, k, ChunkSync{nullptr, 0u, 1, 0},
+                                   st)) != hipSuccess) {
       return e;
     }
+  }
+  return hipSuccess;
+}
+
+bool Engine::persist_ok(int k, int64_t reps) {
+  if (!persist_ || variant_ == MB_VARIANT_PLAIN || reps < 2 || k != halo_ || 3 * halo_ > block_ || dirty_)
+    return false;
+  Group *live = nullptr;
+  for (auto &g : groups_) {
+    if (g.members.empty()) continue;
+    if (live) return false;  // groups of different kernels overlap on side streams
+    live = &g;
+  }
+  if (!live || live->n_tiles < 1 || !live->d_flags) return false;
+  const int lanes = group_lanes(*live);
+  if (live->occ_block != block_ || live->occ_lanes != lanes) {
+    live->occ_block = block_;
+    live->occ_lanes = lanes;
+    live->occ_per_cu = blocked_tiles_per_cu(live->levels, precision_, block_, lanes, vc_, live->strong);
+  }
+  return int64_t(live->n_tiles) <= int64_t(live->occ_per_cu) * n_cu_;
+}
+
+hipError_t Engine::run_persistent(hipStream_t st, int k, int64_t reps) {
+  hipError_t e = sync_tables(st);
+  if (e != hipSuccess) return e;
+  if (!persist_ok(k, reps)) return hipErrorInvalidValue;
+  Group *g = nullptr;
+  for (auto &q : groups_)
+    if (!q.members.empty()) g = &q;
+  const int lanes = group_lanes(*g);
+  while (reps > 0) {
+    const int n = int(std::min<int64_t>(reps, kMaxPersistChunks));
+    const ChunkSync cs{g->d_flags, epoch_, n, spin_ticks_};
+    e = launch_blocked(g->levels, precision_, block_, lanes, vc_, g->strong, g->d_sims, g->d_tiles, g->n_tiles, n0_,
+                       parity_, halo_, k, cs, st);
+    if (e != hipSuccess) return e;
+    epoch_ += uint32_t(n);
+    for (int r = 0; r < n; ++r) commit_chunk(k);
+    reps -= n;
   }
   return hipSuccess;
 }

@@ -77,6 +77,15 @@ class Engine {
   // Uploads group tables if membership changed (synchronous copy).
   hipError_t sync_tables(hipStream_t st);
 
+  // Whether reps chunks of k steps can run as persistent launches: one group
+  // of simulations, k equal to the halo, every tile resident at once, not
+  // switched off (MB_PERSIST=0).  Tables must be current.
+  bool persist_ok(int k, int64_t reps);
+  // reps chunks of k steps as persistent launches (at most kMaxPersistChunks
+  // chunks each); asynchronous, not capturable into graphs
+  hipError_t run_persistent(hipStream_t st, int k, int64_t reps);
+  static constexpr int kMaxPersistChunks = 4096;
+
   // Launches of reps chunks of k steps, for graph capture: tables must be
   // current.  Groups of different level counts run on their own streams,
   // forked from and joined back into st, so their kernels overlap.
@@ -125,7 +134,9 @@ class Engine {
     std::vector<int> members;
     DevSim *d_sims = nullptr;
     DevTile *d_tiles = nullptr;
+    uint32_t *d_flags = nullptr;  // per tile: epoch of the last finished chunk (persistent launches)
     int n_tiles = 0, cap_sims = 0, cap_tiles = 0;
+    int occ_block = 0, occ_lanes = 0, occ_per_cu = 0;  // cached occupancy of the group's kernel
   };
   Group &group_for(int levels, bool strong);
   hipError_t upload_group(Group &g, hipStream_t st);
@@ -150,6 +161,9 @@ class Engine {
   std::vector<int> free_slots_;
   int64_t n0_ = 0;
   int parity_ = 0;
+  bool persist_ = true;        // persistent launches allowed
+  uint32_t epoch_ = 0;         // chunk epoch of the next persistent launch
+  int64_t spin_ticks_ = 0;     // device wall-clock ticks of a neighbour wait before giving up
   double cell_updates_ = 0;
 };
 

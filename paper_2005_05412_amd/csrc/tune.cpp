@@ -68,10 +68,11 @@ std::vector<Shape> candidate_shapes(int levels, int precision) {
   // 64-cell one-wave tiles exchange neighbours inside the wave (no barriers);
   // larger tiles, and tiles with 2 or 4 waves per 64 cells, go through LDS
   // with a barrier per exchange
-  const std::vector<std::pair<int, int>> all = {{64, 8},   {64, 12},  {64, 16},   {64, 20},   {128, 16},
-                                                {128, 32}, {256, 32}, {256, 64},  {512, 64},  {512, 128},
-                                                {512, 192}, {1024, 128}, {1024, 256}};
-  const std::vector<std::pair<int, int>> split = {{64, 16}, {128, 32}, {256, 32}, {256, 64}, {512, 64}, {512, 128}};
+  const std::vector<std::pair<int, int>> all = {{64, 8},    {64, 12},   {64, 16},   {64, 20},    {128, 16},
+                                                {128, 32},  {192, 32},  {192, 64},  {256, 32},   {256, 64},
+                                                {512, 64},  {512, 128}, {512, 192}, {1024, 128}, {1024, 256}};
+  const std::vector<std::pair<int, int>> split = {{64, 16},  {128, 16}, {128, 32}, {192, 16}, {192, 32},
+                                                  {192, 48}, {256, 32}, {256, 64}, {512, 64}, {512, 128}};
   std::vector<Shape> out;
   const bool regs = levels == 2 || levels == 3;
   for (auto [b, h] : all) {
@@ -101,7 +102,7 @@ std::string tune_key(int device, const std::vector<const SimPlan *> &plans, int 
     cells += uint64_t(p->nx);
   }
   std::ostringstream os;
-  os << arch << "/v4/N" << levels << "/p" << precision << "/cells" << pow2_ceil(cells) << "/sims"
+  os << arch << "/v6/N" << levels << "/p" << precision << "/cells" << pow2_ceil(cells) << "/sims"
      << pow2_ceil(plans.size());
   return os.str();
 }
@@ -160,13 +161,28 @@ int tune_shape(int device, const std::vector<const SimPlan *> &plans, int precis
     int64_t timed = std::min<int64_t>(avail - 2, std::max<int64_t>(4, 2048 / k));
     hipError_t he = eng.sync_tables(st);
     for (int q = 0; q < 2 && he == hipSuccess; ++q) he = eng.chunk(st, k);
-    // the timed chunks run as one captured graph, as production runs do
+    // the timed chunks run as production runs do: one persistent launch when
+    // the tiles fit on the device at once, else one captured graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;
-    if (he == hipSuccess) he = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-    if (he == hipSuccess) he = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (he == hipSuccess) {
+    const bool persist = he == hipSuccess && eng.persist_ok(k, timed);
+    if (persist) {
+      he = hipStreamSynchronize(st);
+      if (he == hipSuccess) {
+        (void)hipEventRecord(a, st);
+        he = eng.run_persistent(st, k, timed);
+        (void)hipEventRecord(b, st);
+      }
+      if (he == hipSuccess) he = hipEventSynchronize(b);
+      std::vector<int32_t> status;
+      if (he == hipSuccess && eng.read_status(status) == hipSuccess)
+        for (int32_t v : status)
+          if (v & kStatusWaitTimeout) he = hipErrorLaunchFailure;
+    }
+    if (!persist && he == hipSuccess) he = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (!persist && he == hipSuccess) he = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (!persist && he == hipSuccess) {
       for (int64_t q = 0; q < timed && he == hipSuccess; ++q) {
         he = eng.launch_only(cap, k);
         eng.commit_chunk(k);
@@ -174,14 +190,14 @@ int tune_shape(int device, const std::vector<const SimPlan *> &plans, int precis
       hipError_t e2 = hipStreamEndCapture(cap, &graph);
       if (he == hipSuccess) he = e2;
     }
-    if (he == hipSuccess) he = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (he == hipSuccess) he = hipStreamSynchronize(st);
-    if (he == hipSuccess) {
+    if (!persist && he == hipSuccess) he = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (!persist && he == hipSuccess) he = hipStreamSynchronize(st);
+    if (!persist && he == hipSuccess) {
       (void)hipEventRecord(a, st);
       he = hipGraphLaunch(exec, st);
       (void)hipEventRecord(b, st);
     }
-    if (he == hipSuccess) he = hipEventSynchronize(b);
+    if (!persist && he == hipSuccess) he = hipEventSynchronize(b);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cap) (void)hipStreamDestroy(cap);

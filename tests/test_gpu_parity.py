@@ -77,8 +77,9 @@ def test_small_random_fp64_plain_and_blocked_vs_oracle(case):
     assert max(errs.values()) <= TOL[64], errs
     # every tile shape, coefficient placement and split of the density update
     # over 1, 2 or 4 waves per 64 cells runs the same per-cell arithmetic
-    shapes = [(64, 1, 1), (64, 7, 1), (64, 20, 1), (128, 31, 1), (256, 32, 1), (512, 100, 1),
-              (64, 7, 2), (128, 31, 2), (256, 64, 2), (64, 20, 4), (128, 16, 4), (256, 32, 4), (64, 20, 8)]
+    shapes = [(64, 1, 1), (64, 7, 1), (64, 20, 1), (128, 31, 1), (192, 48, 1), (256, 32, 1), (512, 100, 1),
+              (64, 7, 2), (128, 31, 2), (192, 64, 2), (256, 64, 2), (64, 20, 4), (128, 16, 4), (192, 32, 4),
+              (256, 32, 4), (64, 20, 8)]
     for block, depth, lanes in shapes:
         for variant in ("blocked", "blocked_regs"):
             blk = gpu_run(prob, precision=64, variant=variant, block=block, depth=depth, lanes=lanes)
@@ -96,7 +97,8 @@ def test_small_random_fp32_vs_oracle(case):
     # every tile shape and coefficient placement runs the same per-cell arithmetic
     for variant, block, depth, lanes in (("blocked", 64, 12, 1), ("blocked_regs", 64, 16, 1),
                                          ("blocked_regs", 256, 64, 1), ("blocked", 128, 16, 2),
-                                         ("blocked_regs", 64, 16, 4), ("blocked", 256, 64, 4)):
+                                         ("blocked_regs", 64, 16, 4), ("blocked_regs", 192, 32, 4),
+                                         ("blocked", 256, 64, 4)):
         assert_same(gpu_run(prob, precision=32, variant=variant, block=block, depth=depth, lanes=lanes), got)
 
 
@@ -170,7 +172,7 @@ def test_lambda3_full_grid_prefix_vs_oracle():
     assert max(errs32.values()) <= TOL[32], max(errs32.values())
     # the density update split over 2 or 4 waves per 64 cells gives the same bits
     base = gpu_run(prob, precision=32, variant="blocked", block=256, depth=64, lanes=1)
-    for block, depth, lanes in ((256, 64, 2), (128, 32, 4), (256, 64, 4), (512, 128, 2)):
+    for block, depth, lanes in ((256, 64, 2), (128, 32, 4), (192, 32, 4), (256, 64, 4), (512, 128, 2)):
         for variant in ("blocked", "blocked_regs"):
             _say(f"lambda3 prefix {variant} {block}/{depth} lanes {lanes}")
             assert_same(gpu_run(prob, precision=32, variant=variant, block=block, depth=depth, lanes=lanes), base)
@@ -221,6 +223,54 @@ def test_batch_equals_individual_runs(precision):
             errs = rel_errors(probs[k], b2.records(k), ref)
             b2.close()
             assert max(errs.values()) <= TOL[64], errs
+
+
+class _persist:
+    """Engines created inside the block run every chunk as its own launch (MB_PERSIST=0) or not."""
+
+    def __init__(self, on):
+        self.on = on
+
+    def __enter__(self):
+        import os
+        self.old = os.environ.get("MB_PERSIST")
+        os.environ["MB_PERSIST"] = "1" if self.on else "0"
+
+    def __exit__(self, *exc):
+        import os
+        if self.old is None:
+            os.environ.pop("MB_PERSIST", None)
+        else:
+            os.environ["MB_PERSIST"] = self.old
+
+
+def test_persistent_launch_equals_relaunches():
+    """Chunks chained in one launch by neighbour flags give the bits of one launch per chunk."""
+    prob = _small(SMALL[1])                      # 3 levels, 150 cells, soft source
+    prob["n_steps"] = 400
+    for precision, variant, block, depth, lanes in ((64, "blocked", 64, 16, 1), (64, "blocked_regs", 128, 16, 2),
+                                                    (32, "blocked_regs", 192, 32, 4), (32, "blocked", 64, 8, 4),
+                                                    (64, "blocked", 256, 64, 2)):
+        _say(f"persistent {precision} {variant} {block}/{depth}/{lanes}")
+        with _persist(False):
+            ref = gpu_run(prob, precision=precision, variant=variant, block=block, depth=depth, lanes=lanes)
+        with _persist(True):
+            got = gpu_run(prob, precision=precision, variant=variant, block=block, depth=depth, lanes=lanes,
+                          chunks=[5, 100])
+        assert_same(got, ref)
+    # one level count, uneven lengths and step counts: simulations finish in different chunks
+    rng = np.random.default_rng(9)
+    probs = [W.sweep_sim(k, rng, nx=int(rng.integers(100, 900)), n_steps=700 + 61 * k, precision=32,
+                         rec_interval=5) for k in range(0, 12, 2)]    # even members: two levels
+    _say(f"persistent batch of {len(probs)}")
+    with _persist(True):
+        b = mb.Batch(probs, precision=32, block=128, depth=32, lanes=2)
+        b.run(use_graph=False)
+        got = [b.records(k) for k in range(len(probs))]
+        b.close()
+    with _persist(False):
+        for k, p in enumerate(probs):
+            assert_same(got[k], gpu_run(p, precision=32, variant="blocked", block=128, depth=32, lanes=2))
 
 
 def test_server_results_equal_alone():
