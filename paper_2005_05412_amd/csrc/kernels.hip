@@ -70,7 +70,19 @@ __device__ __forceinline__ void phase_taylor(double t, double &cm, double &sn) {
   cm = -t2 * c;             // -(t^2/2! - t^4/4! + ...)
 }
 
-__device__ __forceinline__ void phase_taylor(float t, float &cm, float &sn) {
+// |t| <= 1/16: the series to t^5 and t^6 leave relative remainders of at
+// most 1.2e-11 and 3e-12 (the terms t^7/7! and t^8/8!), far below FP32's ulp
+constexpr float kPhaseShort = 0.0625f;
+__device__ __forceinline__ void phase_short(float t, float &cm, float &sn) {
+  const float t2 = t * t;
+  const float s = fmaf(t2, 1.0f / 120.0f, -1.0f / 6.0f);
+  sn = fmaf(t * t2, s, t);
+  float c = fmaf(t2, -1.0f / 720.0f, 1.0f / 24.0f);
+  c = fmaf(t2, c, -0.5f);
+  cm = t2 * c;
+}
+
+__device__ __forceinline__ void phase_long(float t, float &cm, float &sn) {
   const float t2 = t * t;
   float s = fmaf(t2, 1.0f / 362880.0f, -1.0f / 5040.0f);
   s = fmaf(t2, s, 1.0f / 120.0f);
@@ -94,6 +106,15 @@ __device__ __forceinline__ void phase_general(double t, double &cm, double &sn) 
   }
 }
 
+// per lane: the short series, the long one, or sincos (the result depends on
+// t alone, not on which lanes share the wave)
+__device__ __forceinline__ void phase_taylor(float t, float &cm, float &sn) {
+  if (fabsf(t) <= kPhaseShort)
+    phase_short(t, cm, sn);
+  else
+    phase_long(t, cm, sn);
+}
+
 __device__ __forceinline__ void phase_general(float t, float &cm, float &sn) {
   if (fabsf(t) <= 0.5f) {
     phase_taylor(t, cm, sn);
@@ -109,6 +130,12 @@ __device__ __forceinline__ void phase_general(float t, float &cm, float &sn) {
 // active lane's angle is small (the usual case); per-lane choice otherwise
 template <typename R>
 __device__ __forceinline__ void phase(R t, R &cm, R &sn) {
+  if constexpr (sizeof(R) == 4) {
+    if (__builtin_amdgcn_ballot_w64(!(fabsf(t) <= kPhaseShort)) == 0) {
+      phase_short(t, cm, sn);
+      return;
+    }
+  }
   const R lim = sizeof(R) == 8 ? R(0.25) : R(0.5);
   if (__builtin_amdgcn_ballot_w64(!(fabs(t) <= lim)) == 0)
     phase_taylor(t, cm, sn);
@@ -398,6 +425,18 @@ struct TileShared {
   int stop;         // a neighbour wait gave up: the tile ends the launch
 };
 
+// Device-coherent (agent-scope) accesses: they bypass the per-XCD caches, so
+// tiles on different XCDs exchange cells without cache write-back or
+// invalidation.  Used for the state a persistent launch hands between chunks.
+template <typename T>
+__device__ __forceinline__ T load_coherent(const T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void store_coherent(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // true once both neighbour tiles have finished the chunk of epoch `target`;
 // false after cs.spin_ticks of the device wall clock (the launch is then
 // abandoned and the simulation's status reports it)
@@ -600,24 +639,28 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
     const R *__restrict__ e_in = static_cast<const R *>(sim.e[par]);
     const R *__restrict__ h_in = static_cast<const R *>(sim.h[par]);
     const R *__restrict__ x_in = static_cast<const R *>(sim.x[par]);
+    // after the first chunk of a persistent launch the cells come from
+    // neighbour tiles' stores of this launch: device-coherent loads
+    const bool fresh = cs.flags != nullptr && chunk > 0;
+    auto ld = [fresh](const auto *ptr) { return fresh ? load_coherent(ptr) : *ptr; };
     e = h = hl = 0;
 #pragma unroll
     for (int a = 0; a < MA; ++a) x[a] = 0;
     if (in) {
-      e = e_in[c];
-      h = h_in[c];
+      e = ld(e_in + c);
+      h = ld(h_in + c);
       if constexpr (N > 0) {
         if (qm) {
 #pragma unroll
           for (int a = 0; a < M; ++a)
-            if (SP::owns(SUB, a)) x[a] = x_in[a * nx + c];
+            if (SP::owns(SUB, a)) x[a] = ld(x_in + a * nx + c);
         }
       }
     }
     if constexpr (ST) {
-      if (qm) qn = sim.qs[par][c];
+      if (qm) qn = ld(sim.qs[par] + c);
     }
-    if (hleft) hl = h_in[c - 1];
+    if (hleft) hl = ld(h_in + c - 1);
     for (int t = 0; t < n_ts; ++t)
       for (int q = int(threadIdx.x); q < ks; q += B * L) sm.src[t][q] = R(staged_tab[t][ls0 + q + 1]);
     // record periods: steps left before the next one, and its index
@@ -719,9 +762,11 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
       e = load_r ? fma(lg_r, eo, -(ld_r * hl)) : e;    // H_{nx-3/2} is the tracked left node
       if (src_direct) {
         if (in) e = apply_sources(sim, c, n1, e);
-      } else if (my_src >= 0) {
-        const R v = sm.src[my_src][s];
-        e = my_hard ? v : e + v;
+      } else if (n_ts > 0) {
+        if (my_src >= 0) {
+          const R v = sm.src[my_src][s];
+          e = my_hard ? v : e + v;
+        }
       }
       if constexpr (ST && N > 0) {
         // rho^{n+1} with the final E^{n+1}: rotation by the midpoint field, the
@@ -762,30 +807,39 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
       R *__restrict__ e_out = static_cast<R *>(sim.e[par ^ 1]);
       R *__restrict__ h_out = static_cast<R *>(sim.h[par ^ 1]);
       R *__restrict__ x_out = static_cast<R *>(sim.x[par ^ 1]);
+      // persistent launches: device-coherent stores, read by the neighbours
+      const bool share = cs.flags != nullptr;
+      auto st = [share](auto *ptr, auto v) {
+        if (share)
+          store_coherent(ptr, v);
+        else
+          *ptr = v;
+      };
       if (SUB == 0) {
-        e_out[c] = e;
-        h_out[c] = h;
+        st(e_out + c, e);
+        st(h_out + c, h);
       }
       if constexpr (N > 0) {
         if (qm) {
 #pragma unroll
           for (int a = 0; a < M; ++a)
-            if (SP::owns(SUB, a)) x_out[a * nx + c] = x[a];
-          if constexpr (ST) sim.qs[par ^ 1][c] = qn;
+            if (SP::owns(SUB, a)) st(x_out + a * nx + c, x[a]);
+          if constexpr (ST) st(sim.qs[par ^ 1] + c, qn);
         }
       }
       if (SUB == 0 && (!isfinite(double(e)) || !isfinite(double(h)))) atomicOr(sim.status, kStatusNonFinite);
     }
     if (cs.flags && chunk + 1 < cs.n_chunks) {
-      // the owned cells of every wave are written before the tile's flag is
-      // raised; the halo of the next chunk is read after both neighbours' flags
+      // every wave's coherent stores of its owned cells are complete before
+      // the tile's flag is raised; the next chunk's cells are read (coherent
+      // loads) after both neighbours have raised theirs
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // keeps the stores above the wait
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
       if (threadIdx.x == 0) {
         const uint32_t target = cs.epoch + uint32_t(chunk) + 1u;
-        __hip_atomic_store(cs.flags + blockIdx.x, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        bool ok = neighbours_reached(cs, tile, target);
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        store_coherent(cs.flags + blockIdx.x, target);
+        const bool ok = neighbours_reached(cs, tile, target);
         sm.stop = !ok;
         if (!ok) atomicOr(sim.status, kStatusWaitTimeout);
       }
