@@ -65,14 +65,18 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload, depth):
+PERSIST_CHUNKS = 4096  # chunks one persistent launch of mb_run covers at most
+
+
+def measured_traffic(kernel, workload, depth, steps):
     """HBM bytes per launch of `kernel` from a committed counter summary.
 
     The summaries under profiles/ carry lines of the form
-    ``traffic-record: kernel=K workload=W depth=D source=S bytes_per_launch=B``
-    where B is FETCH_SIZE + WRITE_SIZE per dispatch, each scaled by what the
-    counter reads for a device copy of known size.  The figure is used only
-    while the device sources still hash to S; otherwise None.
+    ``traffic-record: kernel=K workload=W depth=D steps=T source=S bytes_per_launch=B``
+    (T: time steps one launch advances) where B is FETCH_SIZE + WRITE_SIZE per
+    dispatch, each scaled by what the counter reads for a device copy of known
+    size.  The figure is used only while the device sources still hash to S;
+    otherwise None.
     """
     src = kernel_source_hash()
     pdir = os.path.join(ROOT, "profiles")
@@ -86,7 +90,8 @@ def measured_traffic(kernel, workload, depth):
                     continue
                 kv = dict(t.split("=", 1) for t in line.split()[1:] if "=" in t)
                 if (kv.get("kernel") == kernel and kv.get("workload") == workload
-                        and kv.get("depth") == str(depth) and kv.get("source") == src):
+                        and kv.get("depth") == str(depth) and kv.get("steps") == str(steps)
+                        and kv.get("source") == src):
                     return float(kv["bytes_per_launch"])
     return None
 
@@ -360,18 +365,27 @@ def main(argv=None):
     block, depth, regs, lanes = s32.shape()
     log(f"[bench] tile shape block={block} depth={depth} regs={regs} lanes={lanes} "
         f"(setup incl. tuning {t_setup:.2f} s)")
-    n_launch = math.ceil(prob["n_steps"] / depth)
+    # full chunks of `depth` steps run as persistent launches (up to
+    # PERSIST_CHUNKS chunks each) when the tiles fit on the device at once,
+    # else one launch per chunk; the tail chunk is a launch of its own
+    persistent = s32.persistent()
+    n_chunks = math.ceil(prob["n_steps"] / depth)
+    full, tail = divmod(prob["n_steps"], depth)
+    n_launch = (math.ceil(full / PERSIST_CHUNKS) + (1 if tail else 0)) if persistent else n_chunks
+    steps_per_launch = prob["n_steps"] // n_launch
     wall, dev_ms = timed_solves(hip, stream, s32, args.steps, args.warmup, n_launch)
     rec32 = s32.records()
     value = args.steps * cells / wall
     avg_kernel_us = 1e3 * float(np.mean(dev_ms)) / n_launch
-    flop_launch = flops_per_cell_update(n_levels) * prob["nx"] * depth
+    chunk_us = 1e3 * float(np.mean(dev_ms)) / n_chunks
+    flop_launch = flops_per_cell_update(n_levels) * prob["nx"] * steps_per_launch
     achieved_tflops = flop_launch / (avg_kernel_us * 1e-6) / 1e12
     eff_gbs = bytes_per_cell_update(n_levels, 32) * cells / (float(np.mean(dev_ms)) * 1e-3) / 1e9
-    log(f"[bench] fp32 blocked: {value:.3e} cell-updates/s, kernel {avg_kernel_us:.2f} us")
+    log(f"[bench] fp32 blocked: {value:.3e} cell-updates/s, {n_launch} launch(es) of {steps_per_launch} steps "
+        f"(persistent={persistent}), {avg_kernel_us:.2f} us per launch, {chunk_us:.2f} us per {depth}-step chunk")
 
     kname = f"k_blocked<3,float,{block},{lanes},{str(regs).lower()}>"
-    traffic = measured_traffic(kname, f"lambda3-3lvl/nx{prob['nx']}", depth)
+    traffic = measured_traffic(kname, f"lambda3-3lvl/nx{prob['nx']}", depth, steps_per_launch)
     out = {
         "metric": "cell-updates/s (FP64 plain vs FP32 batched) at stated error; p50/p99 solve latency",
         "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -384,9 +398,11 @@ def main(argv=None):
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK["fp32_tflops"],
                      "unit": "TFLOP/s", "frac": achieved_tflops / PEAK["fp32_tflops"], "traffic": traffic,
                      "traffic_unit": "bytes per launch (HBM, counter-measured)",
-                     "kernel": kname, "avg_kernel_us": avg_kernel_us,
+                     "kernel": kname, "avg_kernel_us": avg_kernel_us, "persistent": persistent,
+                     "launches_per_solve": n_launch, "steps_per_launch": steps_per_launch,
+                     "chunk_us": chunk_us,
                      "flops_per_cell_update": flops_per_cell_update(n_levels),
-                     "cell_updates_per_launch": prob["nx"] * depth,
+                     "cell_updates_per_launch": prob["nx"] * steps_per_launch,
                      "hbm_effective_gbs": eff_gbs, "hbm_effective_frac": eff_gbs / PEAK["hbm_gbs"]},
     }
 

@@ -996,20 +996,16 @@ __global__ void __launch_bounds__(kPlainBlock) k_plain_e(const DevSim *__restric
 }
 
 // Launch (per_cu null) or occupancy query (resident tiles per compute unit
-// into *per_cu) of one tile shape.  A launch of several chunks is cooperative:
-// every tile must be resident for the neighbour flags to make progress.
+// into *per_cu) of one tile shape.  A launch of several chunks needs every
+// tile resident at once for the neighbour flags to make progress: the caller
+// checks the tile count against the occupancy (and a tile that waits too long
+// gives up, so a launch that does not fit ends with an error, not a hang).
 template <int N, typename R, int B, int L, bool VC, bool ST = false>
 hipError_t launch_shape(const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo,
                         int k, const ChunkSync &cs, int *per_cu, hipStream_t st) {
   if constexpr (shape_fits<N, R, B, L>() && (!ST || (L == 1 && !VC && N >= 2))) {
     auto kern = k_blocked<N, R, B, L, VC, ST>;
     if (per_cu) return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kern, B * L, 0);
-    if (cs.n_chunks > 1) {
-      ChunkSync c = cs;
-      void *args[] = {&sims, &tiles, &n0, &parity, &halo, &k, &c};
-      return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(n_tiles), dim3(B * L), args, 0,
-                                        st);
-    }
     kern<<<n_tiles, B * L, 0, st>>>(sims, tiles, n0, parity, halo, k, cs);
     return hipGetLastError();
   } else {

@@ -225,9 +225,7 @@ int Engine::init(std::string &err) {
   if (hipGetDeviceProperties(&prop, device_) == hipSuccess && prop.multiProcessorCount > 0)
     n_cu_ = prop.multiProcessorCount;
   if (const char *v = std::getenv("MB_PERSIST")) persist_ = std::string(v) != "0";
-  int coop = 0, clock_khz = 0;
-  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device_) != hipSuccess || !coop)
-    persist_ = false;
+  int clock_khz = 0;
   if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, device_) != hipSuccess || clock_khz <= 0)
     persist_ = false;
   spin_ticks_ = int64_t(clock_khz) * 1000 * 2;  // two seconds

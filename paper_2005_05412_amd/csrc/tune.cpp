@@ -155,10 +155,10 @@ int tune_shape(int device, const std::vector<const SimPlan *> &plans, int precis
     }
     if (!ok) continue;
     const int k = eng.chunk_steps();
-    // time whole chunks: two for warm-up, then enough for ~2k steps
+    // time whole chunks: two for warm-up, then enough for ~8k steps
     int64_t avail = min_steps / k;
     if (avail < 3) continue;
-    int64_t timed = std::min<int64_t>(avail - 2, std::max<int64_t>(4, 2048 / k));
+    int64_t timed = std::min<int64_t>(avail - 2, std::max<int64_t>(4, 8192 / k));
     hipError_t he = eng.sync_tables(st);
     for (int q = 0; q < 2 && he == hipSuccess; ++q) he = eng.chunk(st, k);
     // the timed chunks run as production runs do: one persistent launch when
