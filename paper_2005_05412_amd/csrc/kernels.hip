@@ -464,7 +464,9 @@ constexpr bool shape_fits() {
          sizeof(TileShared<N, R, B, L>) <= 65536;
 }
 
-template <int N, typename R, int B, int L, bool VC, int SUB, bool ST>
+// P: a persistent launch (several chunks, neighbour flags, device-coherent
+// exchange of the owned cells); without it one chunk, and none of that code
+template <int N, typename R, int B, int L, bool VC, int SUB, bool ST, bool P>
 __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, const DevTile *__restrict__ tiles,
                                            int64_t n0, int parity, int halo, int k, const ChunkSync &cs,
                                            TileShared<N, R, B, L> &sm) {
@@ -479,7 +481,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
   const DevSim &sim = sims[tile.sim];
   {
     // nothing to do in any chunk of this launch (the range is uniform over the tile)
-    const int64_t first = n0 - sim.start, last = first + int64_t(cs.n_chunks) * k;
+    const int64_t first = n0 - sim.start, last = first + int64_t(P ? cs.n_chunks : 1) * k;
     if (last <= 0 || first >= sim.n_steps) return;
   }
   const int nx = int(sim.nx);
@@ -629,7 +631,8 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
     }
   };
 
-  for (int chunk = 0; chunk < cs.n_chunks; ++chunk) {
+  const int n_chunks = P ? cs.n_chunks : 1;
+  for (int chunk = 0; chunk < n_chunks; ++chunk) {
     const int64_t ls64 = n0 + int64_t(chunk) * k - sim.start;
     if (ls64 >= sim.n_steps) break;  // the simulation has finished (uniform over its tiles)
     if (ls64 < 0) continue;          // not started yet (uniform over its tiles)
@@ -641,7 +644,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
     const R *__restrict__ x_in = static_cast<const R *>(sim.x[par]);
     // after the first chunk of a persistent launch the cells come from
     // neighbour tiles' stores of this launch: device-coherent loads
-    const bool fresh = cs.flags != nullptr && chunk > 0;
+    const bool fresh = P && chunk > 0;
     auto ld = [fresh](const auto *ptr) { return fresh ? load_coherent(ptr) : *ptr; };
     e = h = hl = 0;
 #pragma unroll
@@ -808,7 +811,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
       R *__restrict__ h_out = static_cast<R *>(sim.h[par ^ 1]);
       R *__restrict__ x_out = static_cast<R *>(sim.x[par ^ 1]);
       // persistent launches: device-coherent stores, read by the neighbours
-      const bool share = cs.flags != nullptr;
+      constexpr bool share = P;
       auto st = [share](auto *ptr, auto v) {
         if (share)
           store_coherent(ptr, v);
@@ -829,7 +832,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
       }
       if (SUB == 0 && (!isfinite(double(e)) || !isfinite(double(h)))) atomicOr(sim.status, kStatusNonFinite);
     }
-    if (cs.flags && chunk + 1 < cs.n_chunks) {
+    if (P && chunk + 1 < n_chunks) {
       // every wave's coherent stores of its owned cells are complete before
       // the tile's flag is raised; the next chunk's cells are read (coherent
       // loads) after both neighbours have raised theirs
@@ -851,30 +854,30 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
 
 // runs the specialisation of wave group `sub` (wave-uniform); every group
 // executes the same sequence of barriers
-template <int N, typename R, int B, int L, bool VC, int S = 0>
+template <int N, typename R, int B, int L, bool VC, bool P, int S = 0>
 __device__ __forceinline__ void run_group(int sub, const DevSim *__restrict__ sims, const DevTile *__restrict__ tiles,
                                           int64_t n0, int parity, int halo, int k, const ChunkSync &cs,
                                           TileShared<N, R, B, L> &sm) {
   if constexpr (S + 1 < L) {
     if (sub == S)
-      tile_steps<N, R, B, L, VC, S, false>(sims, tiles, n0, parity, halo, k, cs, sm);
+      tile_steps<N, R, B, L, VC, S, false, P>(sims, tiles, n0, parity, halo, k, cs, sm);
     else
-      run_group<N, R, B, L, VC, S + 1>(sub, sims, tiles, n0, parity, halo, k, cs, sm);
+      run_group<N, R, B, L, VC, P, S + 1>(sub, sims, tiles, n0, parity, halo, k, cs, sm);
   } else {
-    tile_steps<N, R, B, L, VC, S, false>(sims, tiles, n0, parity, halo, k, cs, sm);
+    tile_steps<N, R, B, L, VC, S, false, P>(sims, tiles, n0, parity, halo, k, cs, sm);
   }
 }
 
 // ST: strong coupling (one wave per 64 cells only)
-template <int N, typename R, int B, int L, bool VC, bool ST = false>
+template <int N, typename R, int B, int L, bool VC, bool ST, bool P>
 __global__ void __launch_bounds__(B * L) k_blocked(const DevSim *__restrict__ sims,
                                                    const DevTile *__restrict__ tiles, int64_t n0, int parity,
                                                    int halo, int k, ChunkSync cs) {
   __shared__ TileShared<N, R, B, L> sm;
   if constexpr (L == 1) {
-    tile_steps<N, R, B, 1, VC, 0, ST>(sims, tiles, n0, parity, halo, k, cs, sm);
+    tile_steps<N, R, B, 1, VC, 0, ST, P>(sims, tiles, n0, parity, halo, k, cs, sm);
   } else {
-    run_group<N, R, B, L, VC>(__builtin_amdgcn_readfirstlane(int(threadIdx.x) / B), sims, tiles, n0, parity, halo,
+    run_group<N, R, B, L, VC, P>(__builtin_amdgcn_readfirstlane(int(threadIdx.x) / B), sims, tiles, n0, parity, halo,
                               k, cs, sm);
   }
 }
@@ -1000,11 +1003,11 @@ __global__ void __launch_bounds__(kPlainBlock) k_plain_e(const DevSim *__restric
 // tile resident at once for the neighbour flags to make progress: the caller
 // checks the tile count against the occupancy (and a tile that waits too long
 // gives up, so a launch that does not fit ends with an error, not a hang).
-template <int N, typename R, int B, int L, bool VC, bool ST = false>
+template <int N, typename R, int B, int L, bool VC, bool ST, bool P>
 hipError_t launch_shape(const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo,
                         int k, const ChunkSync &cs, int *per_cu, hipStream_t st) {
   if constexpr (shape_fits<N, R, B, L>() && (!ST || (L == 1 && !VC && N >= 2))) {
-    auto kern = k_blocked<N, R, B, L, VC, ST>;
+    auto kern = k_blocked<N, R, B, L, VC, ST, P>;
     if (per_cu) return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kern, B * L, 0);
     kern<<<n_tiles, B * L, 0, st>>>(sims, tiles, n0, parity, halo, k, cs);
     return hipGetLastError();
@@ -1013,67 +1016,67 @@ hipError_t launch_shape(const DevSim *sims, const DevTile *tiles, int n_tiles, i
   }
 }
 
-template <int N, typename R, int L, bool VC, bool ST = false>
+template <int N, typename R, int L, bool VC, bool ST, bool P>
 hipError_t launch_blocked_b(int block, const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0,
                             int parity, int halo, int k, const ChunkSync &cs, int *per_cu, hipStream_t st) {
   switch (block) {
-    case 64: return launch_shape<N, R, 64, L, VC, ST>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
-    case 128: return launch_shape<N, R, 128, L, VC, ST>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
-    case 192: return launch_shape<N, R, 192, L, VC, ST>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
-    case 256: return launch_shape<N, R, 256, L, VC, ST>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
-    case 512: return launch_shape<N, R, 512, L, VC, ST>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
-    case 1024: return launch_shape<N, R, 1024, L, VC, ST>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+    case 64: return launch_shape<N, R, 64, L, VC, ST, P>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+    case 128: return launch_shape<N, R, 128, L, VC, ST, P>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+    case 192: return launch_shape<N, R, 192, L, VC, ST, P>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+    case 256: return launch_shape<N, R, 256, L, VC, ST, P>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+    case 512: return launch_shape<N, R, 512, L, VC, ST, P>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+    case 1024: return launch_shape<N, R, 1024, L, VC, ST, P>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
   }
   return hipErrorInvalidValue;
 }
 
 // register-resident coefficients are instantiated for the small level counts
 // only, split waves for the quantum level counts
-template <int N, typename R>
+template <int N, typename R, bool P>
 hipError_t launch_blocked_nr(int block, int lanes, bool vc, bool strong, const DevSim *sims, const DevTile *tiles,
                              int n_tiles, int64_t n0, int parity, int halo, int k, const ChunkSync &cs, int *per_cu,
                              hipStream_t st) {
   constexpr bool kVC = N == 2 || N == 3;
   if (strong) {
     if constexpr (N >= 2)
-      return launch_blocked_b<N, R, 1, false, true>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+      return launch_blocked_b<N, R, 1, false, true, P>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
     return hipErrorInvalidValue;
   }
   switch (lanes) {
     case 1:
       if constexpr (kVC)
-        if (vc) return launch_blocked_b<N, R, 1, kVC>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
-      return launch_blocked_b<N, R, 1, false>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+        if (vc) return launch_blocked_b<N, R, 1, kVC, false, P>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+      return launch_blocked_b<N, R, 1, false, false, P>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
     case 2:
     case 4:
       if constexpr (N >= 2) {
         if (lanes == 2) {
           if constexpr (kVC)
             if (vc)
-              return launch_blocked_b<N, R, 2, kVC>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
-          return launch_blocked_b<N, R, 2, false>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+              return launch_blocked_b<N, R, 2, kVC, false, P>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+          return launch_blocked_b<N, R, 2, false, false, P>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
         }
         if constexpr (kVC)
-          if (vc) return launch_blocked_b<N, R, 4, kVC>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
-        return launch_blocked_b<N, R, 4, false>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+          if (vc) return launch_blocked_b<N, R, 4, kVC, false, P>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+        return launch_blocked_b<N, R, 4, false, false, P>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
       }
       break;
     case 8:  // 64-cell tiles of the large density updates only
       if constexpr (N >= 4)
-        return launch_blocked_b<N, R, 8, false>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+        return launch_blocked_b<N, R, 8, false, false, P>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
       break;
   }
   return hipErrorInvalidValue;
 }
 
-template <typename R>
+template <typename R, bool P>
 hipError_t launch_blocked_r(int levels, int block, int lanes, bool vc, bool strong, const DevSim *sims,
                             const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo, int k,
                             const ChunkSync &cs, int *per_cu, hipStream_t st) {
   switch (levels) {
 #define MB_LEVELS_CASE(n)                                                                                       \
   case n:                                                                                                         \
-    return launch_blocked_nr<n, R>(block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, \
+    return launch_blocked_nr<n, R, P>(block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, \
                                    st);
     MB_LEVELS_CASE(0)
     MB_LEVELS_CASE(2)
@@ -1134,30 +1137,36 @@ hipError_t launch_plain_n(const DevSim *sims, const DevTile *tiles, int n_tiles,
 
 }  // namespace
 
-// The kernels are built in two parts so that the library compiles them in
-// parallel: MB_PART 1 holds the FP32 tiles, MB_PART 2 the FP64 tiles, the
-// two-launch kernels and the dispatch; without MB_PART both are built here.
+// The kernels are built in four parts so that the library compiles them in
+// parallel: MB_PART 1 holds the FP32 one-chunk tiles, 3 the FP32 persistent
+// tiles, 4 the FP64 persistent tiles, 2 the FP64 one-chunk tiles, the
+// two-launch kernels and the dispatch; without MB_PART all are built here.
 #ifndef MB_PART
 #define MB_PART 0
 #endif
 
-hipError_t launch_blocked_f32(int levels, int block, int lanes, bool vc, bool strong, const DevSim *sims,
-                              const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo, int k,
-                              const ChunkSync &cs, int *per_cu, hipStream_t st);
+#define MB_LAUNCH_ARGS                                                                                           \
+  int levels, int block, int lanes, bool vc, bool strong, const DevSim *sims, const DevTile *tiles, int n_tiles, \
+      int64_t n0, int parity, int halo, int k, const ChunkSync &cs, int *per_cu, hipStream_t st
+#define MB_LAUNCH_PASS levels, block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st
+
+hipError_t launch_blocked_f32(MB_LAUNCH_ARGS);
+hipError_t launch_blocked_f32p(MB_LAUNCH_ARGS);
+hipError_t launch_blocked_f64p(MB_LAUNCH_ARGS);
 bool fits_f32(int levels, int block, int lanes);
 
-#if MB_PART != 2
-hipError_t launch_blocked_f32(int levels, int block, int lanes, bool vc, bool strong, const DevSim *sims,
-                              const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo, int k,
-                              const ChunkSync &cs, int *per_cu, hipStream_t st) {
-  return launch_blocked_r<float>(levels, block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, cs,
-                                 per_cu, st);
-}
-
+#if MB_PART == 0 || MB_PART == 1
+hipError_t launch_blocked_f32(MB_LAUNCH_ARGS) { return launch_blocked_r<float, false>(MB_LAUNCH_PASS); }
 bool fits_f32(int levels, int block, int lanes) { return fits_r<float>(levels, block, lanes); }
 #endif
+#if MB_PART == 0 || MB_PART == 3
+hipError_t launch_blocked_f32p(MB_LAUNCH_ARGS) { return launch_blocked_r<float, true>(MB_LAUNCH_PASS); }
+#endif
+#if MB_PART == 0 || MB_PART == 4
+hipError_t launch_blocked_f64p(MB_LAUNCH_ARGS) { return launch_blocked_r<double, true>(MB_LAUNCH_PASS); }
+#endif
 
-#if MB_PART != 1
+#if MB_PART == 0 || MB_PART == 2
 bool block_supported(int block) {
   return block == 64 || block == 128 || block == 192 || block == 256 || block == 512 || block == 1024;
 }
@@ -1175,21 +1184,25 @@ hipError_t launch_blocked(int levels, int precision, int block, int lanes, bool 
   if (n_tiles <= 0) return hipSuccess;
   if (k < 1 || k > halo || k > kMaxChunk || 2 * halo >= block || cs.n_chunks < 1) return hipErrorInvalidValue;
   if (cs.n_chunks > 1 && (!cs.flags || k != halo || 3 * halo > block)) return hipErrorInvalidValue;
-  if (precision == 64)
-    return launch_blocked_r<double>(levels, block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, cs,
-                                    nullptr, st);
-  return launch_blocked_f32(levels, block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, cs, nullptr,
-                            st);
+  int *per_cu = nullptr;
+  if (cs.n_chunks > 1)
+    return precision == 64 ? launch_blocked_f64p(MB_LAUNCH_PASS) : launch_blocked_f32p(MB_LAUNCH_PASS);
+  return precision == 64 ? launch_blocked_r<double, false>(MB_LAUNCH_PASS) : launch_blocked_f32(MB_LAUNCH_PASS);
 }
 
+// occupancy of the persistent form (the only one that needs every tile resident)
 int blocked_tiles_per_cu(int levels, int precision, int block, int lanes, bool vc, bool strong) {
-  int per_cu = 0;
-  const ChunkSync none{nullptr, 0u, 1, 0};
-  hipError_t e = precision == 64 ? launch_blocked_r<double>(levels, block, lanes, vc, strong, nullptr, nullptr, 0, 0,
-                                                            0, 1, 1, none, &per_cu, nullptr)
-                                 : launch_blocked_f32(levels, block, lanes, vc, strong, nullptr, nullptr, 0, 0, 0, 1, 1,
-                                                      none, &per_cu, nullptr);
-  return e == hipSuccess ? per_cu : 0;
+  int per_cu_v = 0;
+  int *per_cu = &per_cu_v;
+  const ChunkSync cs{nullptr, 0u, 2, 0};
+  const DevSim *sims = nullptr;
+  const DevTile *tiles = nullptr;
+  const int n_tiles = 0, parity = 0, halo = 1, k = 1;
+  const int64_t n0 = 0;
+  hipStream_t st = nullptr;
+  const hipError_t e =
+      precision == 64 ? launch_blocked_f64p(MB_LAUNCH_PASS) : launch_blocked_f32p(MB_LAUNCH_PASS);
+  return e == hipSuccess ? per_cu_v : 0;
 }
 
 hipError_t launch_plain(int levels, const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity,
