@@ -356,8 +356,9 @@ struct TileRecs {
 
   // same arithmetic as Cell::readout
   template <typename R, int MA>
-  __device__ __forceinline__ void density(uint32_t q, const R (&y)[MA], int rb, int re) const {
-    for (int r = rb; r < re; ++r) {
+  // entries rb, rb + step, ... below re
+  __device__ __forceinline__ void density(uint32_t q, const R (&y)[MA], int rb, int re, int step) const {
+    for (int r = rb; r < re; r += step) {
       if (quantity[r] < 2) continue;
       const int64_t at = sample(r, q);
       if (at < 0) continue;
@@ -369,8 +370,8 @@ struct TileRecs {
   }
 
   template <typename R>
-  __device__ __forceinline__ void fields(uint32_t q, R e, R h, bool qm, int rb, int re) const {
-    for (int r = rb; r < re; ++r) {
+  __device__ __forceinline__ void fields(uint32_t q, R e, R h, bool qm, int rb, int re, int step) const {
+    for (int r = rb; r < re; r += step) {
       const int qty = quantity[r];
       if (qty >= 2 && qm) continue;  // density record of a quantum cell: written by density()
       const int64_t at = sample(r, q);
@@ -546,13 +547,19 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
   const bool mur_tile = nx > 1 && ((sim.edge_l == 1 && lo <= 0 && 0 < lo + B) ||
                                    (sim.edge_r == 1 && lo <= nx - 1 && nx - 1 < lo + B));
   const bool mur_l = left && sim.edge_l == 1, mur_r = right && sim.edge_r == 1;
+  // the inner neighbour of a Mur edge cell is the next lane of the same wave
+  // unless the edge cell is the last (left edge) or first (right edge) lane of
+  // its wave: then the new E of the neighbour goes through LDS and a barrier
+  const bool mur_dpp = (!(sim.edge_l == 1 && lo <= 0 && 0 < lo + B) || ((-lo) & 63) != 63) &&
+                       (!(sim.edge_r == 1 && lo <= nx - 1 && nx - 1 < lo + B) || ((nx - 1 - lo) & 63) != 0);
   const bool pec = (left && sim.edge_l == 0) || (right && sim.edge_r == 0);
   const bool load_l = left && sim.edge_l == 2, load_r = right && sim.edge_r == 2;
   const R lg_l = R(sim.load_g_l), ld_l = R(sim.load_d_l), lg_r = R(sim.load_g_r), ld_r = R(sim.load_d_r);
   // the cell's entries in the per-cell record table, fetched once per launch;
   // when the tile's owned cells hold at most kTileRecs entries they are
   // staged in LDS (visible after the first barrier) and [rb, re) index there.
-  // Records are written by the first wave group only.
+  // Staged records are shared out over the wave groups (entry rb + SUB, then
+  // every L-th), the rest is written by the first wave group.
   int rb = 0, re = 0;
   bool rec_lds = false;
   if (sim.rec_first) {
@@ -560,7 +567,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
     const int rbase = sim.rec_first[o0], n_tr = sim.rec_first[o1] - rbase;
     rec_lds = n_tr <= kTileRecs;
     if (rec_lds && int(threadIdx.x) < n_tr) sm.trec.stage(sim, int(threadIdx.x), rbase + int(threadIdx.x));
-    if (own && SUB == 0) {
+    if (own && (rec_lds || SUB == 0)) {
       record_range(sim, c, rb, re);
       if (rec_lds) {
         rb -= rbase;
@@ -568,7 +575,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
       }
     }
   }
-  const bool rec_here = SUB == 0 && own && (re > rb || sim.n_rec_all > 0);
+  const bool rec_here = own && (re > rb || (SUB == 0 && sim.n_rec_all > 0));
   const bool rec_tile = sim.rec_first != nullptr || sim.n_rec_all > 0;  // uniform
   const uint32_t rec_every = uint32_t(sim.rec_every);
   const R kap_l = R(sim.kap_l), kap_r = R(sim.kap_r);
@@ -726,8 +733,8 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
           if (rec_step) {
             if (rec_here) {
               if (rec_lds) {
-                sm.trec.density(rq, x, rb, re);
-                record_density_all<N, R>(sim, c, n1, mm, x);
+                sm.trec.density(rq, x, rb + SUB, re, L);
+                if (SUB == 0) record_density_all<N, R>(sim, c, n1, mm, x);
               } else {
                 record_density<N, R>(sim, c, n1, mm, x, rb, re);
               }
@@ -748,7 +755,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
       e = ecell ? fma(cbd, h - hl, fma(ca, eo, -(cbg * p))) : e;
       if (mur_tile) {
         R enr, enl;
-        if constexpr (WAVE) {
+        if (WAVE || mur_dpp) {
           enr = lane_from_right(e);
           enl = lane_from_left(e);
         } else {
@@ -784,8 +791,8 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
           if (rec_step) {
             if (rec_here) {
               if (rec_lds) {
-                sm.trec.density(rq, x, rb, re);
-                record_density_all<N, R>(sim, c, n1, mm, x);
+                sm.trec.density(rq, x, rb + SUB, re, L);
+                if (SUB == 0) record_density_all<N, R>(sim, c, n1, mm, x);
               } else {
                 record_density<N, R>(sim, c, n1, mm, x, rb, re);
               }
@@ -797,8 +804,8 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
       if (rec_step) {
         if (rec_here) {
           if (rec_lds) {
-            sm.trec.fields(rq, e, hcell ? h : R(0), qm, rb, re);
-            record_fields_all(sim, c, n1, e, hcell ? h : R(0), qm);
+            sm.trec.fields(rq, e, hcell ? h : R(0), qm, rb + SUB, re, L);
+            if (SUB == 0) record_fields_all(sim, c, n1, e, hcell ? h : R(0), qm);
           } else {
             record_fields(sim, c, n1, e, hcell ? h : R(0), qm, rb, re);
           }
