@@ -562,6 +562,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
   // every L-th), the rest is written by the first wave group.
   int rb = 0, re = 0;
   bool rec_lds = false;
+  bool rec_fld = false;  // this lane's entries hold one that the field records write
   if (sim.rec_first) {
     const int o0 = tile.c0, o1 = min(tile.c0 + B - 2 * halo, nx);
     const int rbase = sim.rec_first[o0], n_tr = sim.rec_first[o1] - rbase;
@@ -569,6 +570,10 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
     if (rec_lds && int(threadIdx.x) < n_tr) sm.trec.stage(sim, int(threadIdx.x), rbase + int(threadIdx.x));
     if (own && (rec_lds || SUB == 0)) {
       record_range(sim, c, rb, re);
+      for (int r = rb + (rec_lds ? SUB : 0); r < re; r += rec_lds ? L : 1) {
+        const int qty = sim.rec_cell[r].quantity;
+        rec_fld = rec_fld || qty < 2 || !qm;  // E or H, or a density quantity outside the medium
+      }
       if (rec_lds) {
         rb -= rbase;
         re -= rbase;
@@ -576,6 +581,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
     }
   }
   const bool rec_here = own && (re > rb || (SUB == 0 && sim.n_rec_all > 0));
+  const bool rec_fields_here = rec_here && (rec_fld || (SUB == 0 && sim.n_rec_all > 0));
   const bool rec_tile = sim.rec_first != nullptr || sim.n_rec_all > 0;  // uniform
   const uint32_t rec_every = uint32_t(sim.rec_every);
   const R kap_l = R(sim.kap_l), kap_r = R(sim.kap_r);
@@ -802,7 +808,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
         });
       }
       if (rec_step) {
-        if (rec_here) {
+        if (rec_fields_here) {
           if (rec_lds) {
             sm.trec.fields(rq, e, hcell ? h : R(0), qm, rb + SUB, re, L);
             if (SUB == 0) record_fields_all(sim, c, n1, e, hcell ? h : R(0), qm);
