@@ -244,7 +244,7 @@ int mb_setup(int hip_device, const mb_device_desc *dev, const mb_scenario_desc *
   if (rc < 0) return fail(rc, err);
   int warn = rc;
   int block = 0, halo = 0, lanes = 1;
-  bool vc = plan.variant == MB_VARIANT_BLOCKED_REGS;
+  bool vc = plan.variant == MB_VARIANT_BLOCKED_REGS, persist = true;
   if ((rc = shape_for(plan, block, halo, lanes)) < 0) return rc;
   if (plan.variant == MB_VARIANT_AUTO && plan.block == 0 && plan.depth == 0 && plan.lanes == 0) {
     if (hipSetDevice(hip_device) != hipSuccess) return fail(MB_ERR_HIP, "hipSetDevice failed");
@@ -254,12 +254,14 @@ int mb_setup(int hip_device, const mb_device_desc *dev, const mb_scenario_desc *
     halo = sh.halo;
     vc = sh.vc;
     lanes = sh.lanes;
+    persist = sh.persist;
   }
   auto h = std::make_unique<mb_handle>();
   h->device = hip_device;
   int variant = plan.variant == MB_VARIANT_PLAIN ? MB_VARIANT_PLAIN : MB_VARIANT_BLOCKED;
   h->eng = std::make_unique<Engine>(hip_device, plan.precision, variant, block, halo, vc, lanes);
   if ((rc = h->eng->init(err)) < 0) return fail(rc, err);
+  h->eng->set_persist(persist);
   hipStream_t st = nullptr;
   int id = h->eng->add(std::move(plan), nullptr, st, err);
   if (id < 0) return fail(id, err);
@@ -420,7 +422,7 @@ int mb_batch_setup(int hip_device, int32_t n, const mb_device_desc *devs, const 
       return fail(MB_ERR_ARG, "batch members must share precision and variant");
   }
   int block = 0, halo = 0, lanes = 1, rc;
-  bool vc = plans[0].variant == MB_VARIANT_BLOCKED_REGS;
+  bool vc = plans[0].variant == MB_VARIANT_BLOCKED_REGS, persist = true;
   int nmax = 0;
   for (auto &p : plans) nmax = std::max(nmax, p.n);
   SimPlan probe;
@@ -441,12 +443,14 @@ int mb_batch_setup(int hip_device, int32_t n, const mb_device_desc *devs, const 
     halo = sh.halo;
     vc = sh.vc;
     lanes = sh.lanes;
+    persist = sh.persist;
   }
   auto b = std::make_unique<mb_batch>();
   b->device = hip_device;
   int variant = plans[0].variant == MB_VARIANT_PLAIN ? MB_VARIANT_PLAIN : MB_VARIANT_BLOCKED;
   b->eng = std::make_unique<Engine>(hip_device, plans[0].precision, variant, block, halo, vc, lanes);
   if ((rc = b->eng->init(err)) < 0) return fail(rc, err);
+  b->eng->set_persist(persist);
   for (int i = 0; i < n; ++i) {
     int id = b->eng->add(std::move(plans[i]), nullptr, nullptr, err);
     if (id < 0) return fail(id, "simulation " + std::to_string(i) + ": " + err);

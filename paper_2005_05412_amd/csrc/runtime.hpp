@@ -84,6 +84,8 @@ class Engine {
   // reps chunks of k steps as persistent launches (at most kMaxPersistChunks
   // chunks each); asynchronous, not capturable into graphs
   hipError_t run_persistent(hipStream_t st, int k, int64_t reps);
+  // allows (on) or forbids persistent launches (MB_PERSIST=0 forbids them regardless)
+  void set_persist(bool on) { persist_ = persist_ && on; }
   static constexpr int kMaxPersistChunks = 4096;
 
   // Launches of reps chunks of k steps, for graph capture: tables must be

@@ -39,9 +39,10 @@ void load_cache() {
   std::ifstream f(path);
   std::string key;
   Shape s;
-  int vc = 0;
-  while (f >> key >> s.block >> s.halo >> vc >> s.lanes) {
+  int vc = 0, persist = 0;
+  while (f >> key >> s.block >> s.halo >> vc >> s.lanes >> persist) {
     s.vc = vc != 0;
+    s.persist = persist != 0;
     if (block_supported(s.block) && s.halo >= 1 && 2 * s.halo < s.block &&
         (s.lanes == 1 || s.lanes == 2 || s.lanes == 4 || s.lanes == 8))
       g_cache[key] = s;
@@ -53,7 +54,9 @@ void store_cache(const std::string &key, const Shape &s) {
   std::string path = cache_path();
   if (path.empty()) return;
   std::ofstream f(path, std::ios::app);
-  if (f) f << key << " " << s.block << " " << s.halo << " " << (s.vc ? 1 : 0) << " " << s.lanes << "\n";
+  if (f)
+    f << key << " " << s.block << " " << s.halo << " " << (s.vc ? 1 : 0) << " " << s.lanes << " " << (s.persist ? 1 : 0)
+      << "\n";
 }
 
 uint64_t pow2_ceil(uint64_t v) {
@@ -97,13 +100,15 @@ std::string tune_key(int device, const std::vector<const SimPlan *> &plans, int 
     if (ch == ':' || ch == ' ') ch = '_';
   int levels = 0;
   uint64_t cells = 0;
+  bool strong = false;
   for (auto *p : plans) {
     levels = std::max(levels, p->n);
     cells += uint64_t(p->nx);
+    strong = strong || p->coupling == MB_COUPLING_STRONG;
   }
   std::ostringstream os;
-  os << arch << "/v6/N" << levels << "/p" << precision << "/cells" << pow2_ceil(cells) << "/sims"
-     << pow2_ceil(plans.size());
+  os << arch << "/v7/N" << levels << "/p" << precision << (strong ? "/strong" : "") << "/cells" << pow2_ceil(cells)
+     << "/sims" << pow2_ceil(plans.size());
   return os.str();
 }
 
@@ -155,34 +160,20 @@ int tune_shape(int device, const std::vector<const SimPlan *> &plans, int precis
     }
     if (!ok) continue;
     const int k = eng.chunk_steps();
-    // time whole chunks: two for warm-up, then enough for ~8k steps
+    // whole chunks: two for warm-up, then ~8k steps through a captured graph
+    // (one launch per chunk) and, when the tiles fit on the device at once,
+    // as many through a persistent launch; the faster form is kept with the shape
     int64_t avail = min_steps / k;
     if (avail < 3) continue;
     int64_t timed = std::min<int64_t>(avail - 2, std::max<int64_t>(4, 8192 / k));
     hipError_t he = eng.sync_tables(st);
     for (int q = 0; q < 2 && he == hipSuccess; ++q) he = eng.chunk(st, k);
-    // the timed chunks run as production runs do: one persistent launch when
-    // the tiles fit on the device at once, else one captured graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;
-    const bool persist = he == hipSuccess && eng.persist_ok(k, timed);
-    if (persist) {
-      he = hipStreamSynchronize(st);
-      if (he == hipSuccess) {
-        (void)hipEventRecord(a, st);
-        he = eng.run_persistent(st, k, timed);
-        (void)hipEventRecord(b, st);
-      }
-      if (he == hipSuccess) he = hipEventSynchronize(b);
-      std::vector<int32_t> status;
-      if (he == hipSuccess && eng.read_status(status) == hipSuccess)
-        for (int32_t v : status)
-          if (v & kStatusWaitTimeout) he = hipErrorLaunchFailure;
-    }
-    if (!persist && he == hipSuccess) he = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-    if (!persist && he == hipSuccess) he = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (!persist && he == hipSuccess) {
+    if (he == hipSuccess) he = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (he == hipSuccess) {
       for (int64_t q = 0; q < timed && he == hipSuccess; ++q) {
         he = eng.launch_only(cap, k);
         eng.commit_chunk(k);
@@ -190,14 +181,14 @@ int tune_shape(int device, const std::vector<const SimPlan *> &plans, int precis
       hipError_t e2 = hipStreamEndCapture(cap, &graph);
       if (he == hipSuccess) he = e2;
     }
-    if (!persist && he == hipSuccess) he = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (!persist && he == hipSuccess) he = hipStreamSynchronize(st);
-    if (!persist && he == hipSuccess) {
+    if (he == hipSuccess) he = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he == hipSuccess) {
       (void)hipEventRecord(a, st);
       he = hipGraphLaunch(exec, st);
       (void)hipEventRecord(b, st);
     }
-    if (!persist && he == hipSuccess) he = hipEventSynchronize(b);
+    if (he == hipSuccess) he = hipEventSynchronize(b);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cap) (void)hipStreamDestroy(cap);
@@ -205,11 +196,33 @@ int tune_shape(int device, const std::vector<const SimPlan *> &plans, int precis
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, a, b);
     double us = 1e3 * double(ms) / double(timed * k);
+    Shape got = cand;
+    got.persist = false;
+    const int64_t timed_p = std::min<int64_t>(timed, avail - 2 - timed);
+    if (timed_p >= 4 && eng.persist_ok(k, timed_p)) {
+      (void)hipEventRecord(a, st);
+      he = eng.run_persistent(st, k, timed_p);
+      (void)hipEventRecord(b, st);
+      if (he == hipSuccess) he = hipEventSynchronize(b);
+      std::vector<int32_t> status;
+      bool gave_up = false;
+      if (he == hipSuccess && eng.read_status(status) == hipSuccess)
+        for (int32_t v : status) gave_up = gave_up || (v & kStatusWaitTimeout);
+      float ms_p = 0.f;
+      if (he == hipSuccess && !gave_up && hipEventElapsedTime(&ms_p, a, b) == hipSuccess) {
+        const double us_p = 1e3 * double(ms_p) / double(timed_p * k);
+        if (us_p < us) {
+          us = us_p;
+          got.persist = true;
+        }
+      }
+      (void)hipGetLastError();
+    }
     // a later candidate has to be 2 % faster: near-ties (timing noise) keep the
     // earlier shape, so repeated tunings of one workload agree
     if (us < 0.98 * best_us) {
       best_us = us;
-      best = cand;
+      best = got;
     }
   }
   (void)hipEventDestroy(a);

@@ -13,6 +13,7 @@ struct Shape {
   int halo = 32;    // halo width = steps per launch (capped at 256)
   bool vc = false;  // quantum coefficients in registers (2 and 3 levels)
   int lanes = 1;    // waves per 64 cells sharing each cell's density update
+  bool persist = true;  // full chunks as persistent launches (when the tiles fit on the device)
 };
 
 std::vector<Shape> candidate_shapes(int levels, int precision);
