@@ -558,8 +558,12 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
   // the cell's entries in the per-cell record table, fetched once per launch;
   // when the tile's owned cells hold at most kTileRecs entries they are
   // staged in LDS (visible after the first barrier) and [rb, re) index there.
-  // Staged records are shared out over the wave groups (entry rb + SUB, then
-  // every L-th), the rest is written by the first wave group.
+  // Staged records are shared out over the first RS wave groups (entry
+  // rb + SUB, then every RS-th), the rest is written by the first wave group.
+  // (Each group is its own copy of the step loop: with more than four groups,
+  // or the long loops of 5 and 6 levels, copies with record code outgrow the
+  // instruction cache, and there the records are a small part of a step.)
+  constexpr int RS = N >= 5 ? 1 : L < 4 ? L : 4;
   int rb = 0, re = 0;
   bool rec_lds = false;
   bool rec_fld = false;  // this lane's entries hold one that the field records write
@@ -568,9 +572,9 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
     const int rbase = sim.rec_first[o0], n_tr = sim.rec_first[o1] - rbase;
     rec_lds = n_tr <= kTileRecs;
     if (rec_lds && int(threadIdx.x) < n_tr) sm.trec.stage(sim, int(threadIdx.x), rbase + int(threadIdx.x));
-    if (own && (rec_lds || SUB == 0)) {
+    if (own && (rec_lds ? SUB < RS : SUB == 0)) {
       record_range(sim, c, rb, re);
-      for (int r = rb + (rec_lds ? SUB : 0); r < re; r += rec_lds ? L : 1) {
+      for (int r = rb + (rec_lds ? SUB : 0); r < re; r += rec_lds ? RS : 1) {
         const int qty = sim.rec_cell[r].quantity;
         rec_fld = rec_fld || qty < 2 || !qm;  // E or H, or a density quantity outside the medium
       }
@@ -580,7 +584,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
       }
     }
   }
-  const bool rec_here = own && (re > rb || (SUB == 0 && sim.n_rec_all > 0));
+  const bool rec_here = SUB < RS && own && (re > rb || (SUB == 0 && sim.n_rec_all > 0));
   const bool rec_fields_here = rec_here && (rec_fld || (SUB == 0 && sim.n_rec_all > 0));
   const bool rec_tile = sim.rec_first != nullptr || sim.n_rec_all > 0;  // uniform
   const uint32_t rec_every = uint32_t(sim.rec_every);
@@ -739,7 +743,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
           if (rec_step) {
             if (rec_here) {
               if (rec_lds) {
-                sm.trec.density(rq, x, rb + SUB, re, L);
+                sm.trec.density(rq, x, rb + SUB, re, RS);
                 if (SUB == 0) record_density_all<N, R>(sim, c, n1, mm, x);
               } else {
                 record_density<N, R>(sim, c, n1, mm, x, rb, re);
@@ -797,7 +801,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
           if (rec_step) {
             if (rec_here) {
               if (rec_lds) {
-                sm.trec.density(rq, x, rb + SUB, re, L);
+                sm.trec.density(rq, x, rb + SUB, re, RS);
                 if (SUB == 0) record_density_all<N, R>(sim, c, n1, mm, x);
               } else {
                 record_density<N, R>(sim, c, n1, mm, x, rb, re);
@@ -810,7 +814,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
       if (rec_step) {
         if (rec_fields_here) {
           if (rec_lds) {
-            sm.trec.fields(rq, e, hcell ? h : R(0), qm, rb + SUB, re, L);
+            sm.trec.fields(rq, e, hcell ? h : R(0), qm, rb + SUB, re, RS);
             if (SUB == 0) record_fields_all(sim, c, n1, e, hcell ? h : R(0), qm);
           } else {
             record_fields(sim, c, n1, e, hcell ? h : R(0), qm, rb, re);
