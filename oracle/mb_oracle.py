@@ -33,6 +33,11 @@ What it computes (paper sections cited per function):
   depends on E^{n+1} through rho^{n+1}; it is solved by fixed-point iteration
   to convergence.  Edges and sources follow as in the weak scheme, and every
   quantum cell's rho^{n+1} is finally taken with its final E^{n+1}.
+* Field part by a Cayley approximant (the class name lindblad_reg_cayley of
+  Sec. 3.2 names the Cayley form; the paper prints no formula): problems with
+  field_step == "cayley" replace W = exp(A), A = i dt E mu / hbar, by the
+  Cayley transform W_C = (I - A/2)^{-1} (I + A/2), which is unitary for the
+  anti-Hermitian A and agrees with exp(A) to second order.
 
 Readings of points the paper leaves open (also listed in the design notes):
 edges with R = 1 are a perfect electric conductor (E = 0), edges with R = 0
@@ -353,13 +358,24 @@ class Oracle:
                 self.e[s["cell"]] += v
 
     # -- density step ---------------------------------------------------------
-    def _strang(self, g, rho, e_cells):
-        """e^{L0 dt/2} [ W (e^{L0 dt/2} rho) W^+ ] for each cell, W = exp(+i dt E mu / hbar)."""
-        k, n = rho.shape[0], g["n"]
-        r = (rho.reshape(k, n * n) @ g["p_half"].T).reshape(k, n, n)
+    def _field_op(self, g, e_cells):
+        """Field part of the step for each cell: W = exp(A) with A = i dt E mu / hbar
+        (through the eigen-decomposition of mu), or its Cayley approximant
+        (I - A/2)^{-1} (I + A/2) when the problem asks for field_step "cayley"."""
+        n = g["n"]
+        if self.p.get("field_step", "exact") == "cayley":
+            a = 1j * self.dt / self.c["hbar"] * e_cells[:, None, None] * g["mu"][None, :, :]
+            eye = np.eye(n)[None, :, :]
+            return np.linalg.solve(eye - 0.5 * a, eye + 0.5 * a)
         vec, lam = g["vec"], g["lam"]
         ph = np.exp(1j * self.dt / self.c["hbar"] * e_cells[:, None] * lam[None, :])
-        w = np.einsum("ij,kj,lj->kil", vec, ph, vec.conj())
+        return np.einsum("ij,kj,lj->kil", vec, ph, vec.conj())
+
+    def _strang(self, g, rho, e_cells):
+        """e^{L0 dt/2} [ W (e^{L0 dt/2} rho) W^+ ] for each cell (W from _field_op)."""
+        k, n = rho.shape[0], g["n"]
+        r = (rho.reshape(k, n * n) @ g["p_half"].T).reshape(k, n, n)
+        w = self._field_op(g, e_cells)
         r = w @ r @ np.conj(np.transpose(w, (0, 2, 1)))
         return (r.reshape(k, n * n) @ g["p_half"].T).reshape(k, n, n)
 
@@ -373,10 +389,8 @@ class Oracle:
         rho = g["rho"]
         v = rho.reshape(k, n * n) @ g["p_half"].T
         rho = v.reshape(k, n, n)
-        # W = V diag(exp(i dt E lam / hbar)) V^+ ;  rho <- W rho W^+
-        vec, lam = g["vec"], g["lam"]
-        ph = np.exp(1j * self.dt / self.c["hbar"] * e_cells[:, None] * lam[None, :])
-        w = np.einsum("ij,kj,lj->kil", vec, ph, vec.conj())
+        # rho <- W rho W^+ (W = exp(i dt E mu / hbar) or its Cayley approximant)
+        w = self._field_op(g, e_cells)
         rho = w @ rho @ np.conj(np.transpose(w, (0, 2, 1)))
         v = rho.reshape(k, n * n) @ g["p_half"].T
         g["rho"] = v.reshape(k, n, n)

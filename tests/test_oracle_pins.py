@@ -442,6 +442,68 @@ def test_strong_and_weak_coupling_agree_to_second_order():
     assert 3.5 < d1 / d2 < 4.6, (d1, d2)
 
 
+# ---------------------------------------------------------------- Cayley field step
+
+def _cayley(prob):
+    prob["field_step"] = "cayley"
+    return prob
+
+
+def test_cayley_field_step_rabi_closed_form():
+    """H0 = 0, no relaxation, constant E, mu = mu12 sigma_x: the Cayley transform of
+    A = i dt E mu / hbar is diag((1 + i x_j)/(1 - i x_j)) in mu's eigenbasis, x_j = dt E
+    lam_j / (2 hbar), i.e. a rotation by 2 atan(x) per step where exp(A) rotates by 2x, so
+    rho_22 after n steps is sin^2(2 n atan(mu12 E dt / (2 hbar)))."""
+    z21 = 1e-10
+    qm = two_level(0.0, z21, 0.0, 0.0, -1.0)
+    mu12 = C["e"] * z21
+    dt, nt = 5e-16, 400
+    e_c = 0.6 * HB / (mu12 * dt)                      # x = 0.3 per level
+    recs = O.Oracle(_cayley(single_point(qm, nt, dt, [1.0, 0.0], e_const=e_c))).run()
+    n = np.arange(nt) + 1
+    x = mu12 * e_c * dt / (2 * HB)
+    cay = np.sin(2 * n * math.atan(x)) ** 2
+    exact = np.sin(2 * n * x) ** 2
+    assert np.max(np.abs(recs["p1"] - cay)) < 1e-12
+    assert np.max(np.abs(recs["p1"] - exact)) > 0.1    # the two field steps really differ
+
+
+@pytest.mark.parametrize("n", [3, 4])
+def test_cayley_field_step_keeps_density_matrices_valid(n):
+    """The Cayley transform of an anti-Hermitian matrix is unitary: trace one, Hermitian,
+    positive semi-definite density matrices in every quantum cell (Sec. 2.2)."""
+    prob = _cayley(W.random_small(40 + n, N=n, nx=30, n_steps=60, full_records=False))
+    prob["e_init"] = np.full(30, 3e9)                # strong field: large Cayley angles
+    orc = O.Oracle(prob)
+    for _ in range(60):
+        orc.step()
+        for g in orc.groups:
+            rho = g["rho"]
+            assert np.max(np.abs(np.trace(rho, axis1=1, axis2=2) - 1.0)) < 1e-12
+            assert np.max(np.abs(rho - np.conj(np.transpose(rho, (0, 2, 1))))) < 1e-14
+            assert np.linalg.eigvalsh(rho).min() > -1e-12
+
+
+def test_cayley_and_exact_field_steps_agree_to_second_order():
+    """Detuned Rabi problem: the Cayley and exact field steps differ by O(dt^2), so the
+    difference of their trajectories at fixed times falls by 4 when dt halves."""
+    om, z21 = 2 * math.pi * 1e14, 1e-29 / C["e"]
+    e_c = 0.25 * HB * om / 1e-29
+    qm = two_level(om, z21, 0.0, 0.0, -1.0)
+
+    def diff(dt):
+        nt = int(round(1e-13 / dt))
+        a = O.Oracle(single_point(qm, nt, dt, [1.0, 0.0], e_const=e_c)).run()["p1"]
+        b = O.Oracle(_cayley(single_point(qm, nt, dt, [1.0, 0.0], e_const=e_c))).run()["p1"]
+        return a - b
+
+    d1 = diff(2e-16)
+    d2 = diff(1e-16)[1::2]
+    r = np.max(np.abs(d1)) / np.max(np.abs(d2))
+    assert np.max(np.abs(d1)) > 1e-6
+    assert 3.6 < r < 4.4, r
+
+
 # ---------------------------------------------------------------- P9 self-induced transparency
 
 @pytest.mark.slow

@@ -123,10 +123,12 @@ def record(name, quantity, cell, interval, i=0, j=0):
 
 def make_problem(name, length, materials, regions, nx, dt, n_steps, rho_diag,
                  rho_off=None, refl=(0.0, 0.0), e_init=None, sources=(), records=(),
-                 precision=64, consts=CODATA, coupling="weak"):
+                 precision=64, consts=CODATA, coupling="weak", field_step="exact"):
     n = len(rho_diag)
     assert coupling in ("weak", "strong")
+    assert field_step in ("exact", "cayley")
     return {"name": name, "consts": dict(consts), "length": float(length), "coupling": coupling,
+            "field_step": field_step,
             "refl": (float(refl[0]), float(refl[1])), "materials": list(materials),
             "regions": [dict(x_start=float(a), x_end=float(b), material=int(m)) for a, b, m in regions],
             "nx": int(nx), "dt": float(dt), "n_steps": int(n_steps), "precision": int(precision),
