@@ -280,6 +280,16 @@ def other_configs(hip, stream, log):
                                       "fp64": cells / (ms64 * 1e-3), "unit": "cell-updates/s",
                                       "fp32_vs_fp64_max_rel_err": max_error(p, r32, r64),
                                       "shape_fp32": list(sh32)}
+    log("[bench] lambda3 with the Cayley field step fp32/fp64")
+    p = W.lambda3()
+    p["field_step"] = "cayley"
+    ms32, r32, sh32 = solve_once(hip, stream, p, 32)
+    ms64, r64, sh64 = solve_once(hip, stream, p, 64)
+    cells = p["nx"] * p["n_steps"]
+    res["lambda3_cayley_field_step"] = {"nx": p["nx"], "n_steps": p["n_steps"], "fp32": cells / (ms32 * 1e-3),
+                                        "fp64": cells / (ms64 * 1e-3), "unit": "cell-updates/s",
+                                        "fp32_vs_fp64_max_rel_err": max_error(p, r32, r64),
+                                        "shape_fp32": list(sh32), "shape_fp64": list(sh64)}
     log("[bench] anharmonic ladder N = 2..6, 8192 cells, 20000 steps, fp32/fp64")
     scal = {}
     for n in range(2, 7):

@@ -76,6 +76,15 @@ extern "C" {
                                    neighbour tile; the run's results are not valid */
 
 /* ---- enumerations -------------------------------------------------------- */
+/* Field part of the density step, W rho W^+ with A = i dt E mu / hbar:
+ * MB_FIELD_EXACT takes W = exp(A) (through the eigen-decomposition of mu);
+ * MB_FIELD_CAYLEY its Cayley approximant W = (I - A/2)^{-1} (I + A/2), unitary and
+ * second-order accurate (the lindblad_reg_cayley class of Sec. 3.2 names the
+ * form).  The Cayley form runs without register coefficients and one chunk per
+ * launch, never persistent (MB_VARIANT_BLOCKED_REGS with it is MB_ERR_UNSUPPORTED). */
+#define MB_FIELD_EXACT 0
+#define MB_FIELD_CAYLEY 1
+
 #define MB_SRC_SECH 0   /* s(t) = amp sech(width t' - shift) sin(2 pi freq t + phase) */
 #define MB_SRC_GAUSS 1  /* s(t) = amp exp(-(width t' - shift)^2) sin(2 pi freq t + phase) */
                         /* t' = t - q period, summed over q = 0..count-1 */
@@ -175,6 +184,8 @@ typedef struct mb_scenario_desc {
   int32_t lanes;             /* blocked variant: waves per 64 cells that share each cell's
                                 density update, 1, 2, 4 or 8 (8: 4 to 6 levels, 64-cell
                                 tiles; 0 = default); results do not depend on it */
+  int32_t field_step;        /* MB_FIELD_EXACT or MB_FIELD_CAYLEY: the field part of the
+                                density step (see below) */
   const double *rho_diag;    /* N reals: initial density matrix (ic_density_const) */
   const double *rho_off;     /* N(N-1)/2 complex (re, im) */
   const double *e_init;      /* nx initial E values, or NULL for zero */

@@ -26,6 +26,7 @@ ERRORS = {-1: "MB_ERR_ARG", -2: "MB_ERR_CFL", -3: "MB_ERR_UNSUPPORTED", -4: "MB_
 SRC_KIND = {"sech": 0, "gauss": 1}
 REC_KIND = {"e": 0, "h": 1, "pop": 2, "inv": 3, "rho_re": 4, "rho_im": 5}
 VARIANT = {"auto": 0, "plain": 1, "blocked": 2, "blocked_regs": 3}
+FIELD_STEP = {"exact": 0, "cayley": 1}    # MB_FIELD_EXACT, MB_FIELD_CAYLEY
 
 EXPORTS = [
     "mb_last_error", "mb_device_count", "mb_plan_material", "mb_plan_readout", "mb_setup", "mb_run", "mb_run_mode", "mb_reset", "mb_batch_reset", "mb_shape", "mb_batch_shape", "mb_steps_done", "mb_record_shape",
@@ -93,6 +94,7 @@ class mb_scenario_desc(C.Structure):
     _fields_ = [("nx", C.c_int64), ("dt", C.c_double), ("n_steps", C.c_int64),
                 ("precision", C.c_int32), ("variant", C.c_int32), ("block", C.c_int32),
                 ("depth", C.c_int32), ("coupling", C.c_int32), ("lanes", C.c_int32),
+                ("field_step", C.c_int32),
                 ("rho_diag", C.POINTER(C.c_double)),
                 ("rho_off", C.POINTER(C.c_double)), ("e_init", C.POINTER(C.c_double)),
                 ("n_sources", C.c_int32), ("sources", C.POINTER(mb_source)),
@@ -243,6 +245,10 @@ class _Marshal:
         sc.variant = VARIANT[variant]
         sc.block, sc.depth, sc.lanes = block, depth, lanes
         sc.coupling = 1 if prob.get("coupling", "weak") == "strong" else 0
+        fs = prob.get("field_step", "exact")
+        if fs not in FIELD_STEP:
+            raise ValueError(f"field_step must be one of {sorted(FIELD_STEP)}, not {fs!r}")
+        sc.field_step = FIELD_STEP[fs]
         sc.rho_diag = arr(prob["rho_diag"])
         sc.rho_off = arr(_complex_pairs(prob["rho_off"])) if len(prob["rho_off"]) else arr(np.zeros(1))
         sc.e_init = None if prob["e_init"] is None else arr(prob["e_init"])

@@ -8,16 +8,16 @@ namespace mb {
 // Per-material coefficient block, element type R (float or double), stride
 // mat_stride(N):  [0] a'  [1] b' Gamma  [2] b'/dx  [3] c' (for H nodes)
 // [4] 1 if the material has quantum systems, then kappa[N-1], p0, at[M],
-// bf[M], am[M*M] (row-major, e^{L0 dt} - I).
+// bf[M], am[M*M] (row-major, e^{L0 dt} - I), sigma[N] (dt lam_j / hbar, the
+// dipole eigenvalues; Cayley field step).  kappa[q] = sigma[q] - sigma[q+1].
 constexpr int kCoefA = 0, kCoefBG = 1, kCoefBD = 2, kCoefH = 3, kCoefQM = 4, kCoefKap = 5;
 __host__ __device__ constexpr int mat_m(int n) { return n > 0 ? n * n - 1 : 0; }
 __host__ __device__ constexpr int coef_p0(int n) { return kCoefKap + (n > 0 ? n - 1 : 0); }
 __host__ __device__ constexpr int coef_at(int n) { return coef_p0(n) + 1; }
 __host__ __device__ constexpr int coef_bf(int n) { return coef_at(n) + mat_m(n); }
 __host__ __device__ constexpr int coef_am(int n) { return coef_bf(n) + mat_m(n); }
-__host__ __device__ constexpr int mat_stride(int n) {
-  return n > 0 ? coef_am(n) + mat_m(n) * mat_m(n) : kCoefKap;
-}
+__host__ __device__ constexpr int coef_sg(int n) { return coef_am(n) + mat_m(n) * mat_m(n); }
+__host__ __device__ constexpr int mat_stride(int n) { return n > 0 ? coef_sg(n) + n : kCoefKap; }
 
 struct DevSource {
   int64_t cell;
@@ -55,6 +55,7 @@ struct DevSim {
   const int32_t *rec_all;    // whole-domain record ids
   int32_t *status;           // kStatus* bits
   int32_t rec_every;         // gcd of the record intervals (1 when there are no records)
+  int32_t cayley;            // field part by the Cayley approximant (MB_FIELD_CAYLEY)
   // strong coupling: (n3D/dt) tr{mu rho^n} per cell (FP64 ping-pong like x) and per
   // material its readout (qc, aq[M]) from the rotated state
   double *qs[2];

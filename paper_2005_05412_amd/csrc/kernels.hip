@@ -176,12 +176,28 @@ struct Cell {
   // (cos - 1, sin) and applied as a small increment.
   // (with L > 1 only the coherences of rows owned by group SUB are rotated;
   // the composed phases are the same for every split)
+  // cay: the Cayley approximant of the field exponential instead: level j's
+  // factor (1 + i x_j)/(1 - i x_j), x_j = E sigma_j / 2, so the consecutive
+  // pair (q, q+1) turns by u/conj(u), u = 1 + x_q x_{q+1} + i (x_q - x_{q+1}):
+  // cos - 1 = -2 d^2/|u|^2 and sin = 2 s d/|u|^2 with d = x_q - x_{q+1} and
+  // s = 1 + x_q x_{q+1} (no cancellation for small angles).
   template <int L = 1, int SUB = 0, typename C>
-  static __device__ __forceinline__ void rotate(R (&y)[MA], R e, const C &mt) {
+  static __device__ __forceinline__ void rotate(R (&y)[MA], R e, const C &mt, bool cay = false) {
     if constexpr (N >= 2) {
       R cm[N - 1], sn[N - 1];
+      if (cay) {
 #pragma unroll
-      for (int q = 0; q < N - 1; ++q) phase(e * mt[kCoefKap + q], cm[q], sn[q]);
+        for (int q = 0; q < N - 1; ++q) {
+          const R a = R(0.5) * e * mt[coef_sg(N) + q], b = R(0.5) * e * mt[coef_sg(N) + q + 1];
+          const R d = a - b, s = fma(a, b, R(1));
+          const R inv = R(1) / fma(s, s, d * d);
+          cm[q] = R(-2) * (d * d) * inv;
+          sn[q] = R(2) * (s * d) * inv;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < N - 1; ++q) phase(e * mt[kCoefKap + q], cm[q], sn[q]);
+      }
 #pragma unroll
       for (int j = 0; j < N - 1; ++j) {
         R pc = cm[j], ps = sn[j];
@@ -467,7 +483,7 @@ constexpr bool shape_fits() {
 
 // P: a persistent launch (several chunks, neighbour flags, device-coherent
 // exchange of the owned cells); without it one chunk, and none of that code
-template <int N, typename R, int B, int L, bool VC, int SUB, bool ST, bool P>
+template <int N, typename R, int B, int L, bool VC, int SUB, bool ST, bool P, bool CY>
 __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, const DevTile *__restrict__ tiles,
                                            int64_t n0, int parity, int halo, int k, const ChunkSync &cs,
                                            TileShared<N, R, B, L> &sm) {
@@ -589,11 +605,15 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
   const bool rec_tile = sim.rec_first != nullptr || sim.n_rec_all > 0;  // uniform
   const uint32_t rec_every = uint32_t(sim.rec_every);
   const R kap_l = R(sim.kap_l), kap_r = R(sim.kap_r);
+  // field part by the Cayley approximant (kernels of their own: the extra
+  // phase code costs the other kernels instruction-cache space)
+  constexpr bool cay = CY;
 
   // coefficients of a single-material wave held in registers for the launch
   // (those this wave group reads: phases, polarization, its propagator rows)
   auto coef_used = [](int i) {
     const int t = i + kCoefKap;
+    if (t >= coef_sg(N)) return false;  // Cayley coefficients: never with register coefficients
     if (t < coef_bf(N)) return true;
     if (t < coef_am(N)) return SP::owns(SUB, t - coef_bf(N));
     return SP::owns(SUB, (t - coef_am(N)) / (M > 0 ? M : 1));
@@ -640,7 +660,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
   auto rotate_publish = [&](int buf) {
     if constexpr (L > 1 && N > 0) {
       per_material([&](const auto &mt, int) {
-        CL::template rotate<L, SUB>(x, e, mt);
+        CL::template rotate<L, SUB>(x, e, mt, cay);
 #pragma unroll
         for (int a = 0; a < M; ++a)
           if (SP::owns(SUB, a)) sm.sy[buf][a][l] = x[a];
@@ -729,7 +749,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
             R yv[MA];
 #pragma unroll
             for (int a = 0; a < MA; ++a) yv[a] = x[a];
-            CL::rotate(yv, R(0.5) * (e + es), mt);
+            CL::rotate(yv, R(0.5) * (e + es), mt, cay);
             double tq = qt[0];
 #pragma unroll
             for (int j = 0; j < M; ++j) tq = fma(qt[1 + j], double(yv[j]), tq);
@@ -754,7 +774,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
         };
         if constexpr (L == 1) {
           per_material([&](const auto &mt, int mm) {
-            CL::rotate(x, e, mt);
+            CL::rotate(x, e, mt, cay);
             finish(mt, mm);
           });
         } else {
@@ -793,7 +813,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
         // new tr{mu rho}, records of rho^{n+1}, propagation of the running state
         per_material([&](const auto &mt, int mm) {
           const cptr<double> qt = kconst<double>(sim.qtab) + __builtin_amdgcn_readfirstlane(mm * (M + 1));
-          CL::rotate(x, R(0.5) * (eo + e), mt);
+          CL::rotate(x, R(0.5) * (eo + e), mt, cay);
           double tq = qt[0];
 #pragma unroll
           for (int j = 0; j < M; ++j) tq = fma(qt[1 + j], double(x[j]), tq);
@@ -871,30 +891,30 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
 
 // runs the specialisation of wave group `sub` (wave-uniform); every group
 // executes the same sequence of barriers
-template <int N, typename R, int B, int L, bool VC, bool P, int S = 0>
+template <int N, typename R, int B, int L, bool VC, bool P, bool CY, int S = 0>
 __device__ __forceinline__ void run_group(int sub, const DevSim *__restrict__ sims, const DevTile *__restrict__ tiles,
                                           int64_t n0, int parity, int halo, int k, const ChunkSync &cs,
                                           TileShared<N, R, B, L> &sm) {
   if constexpr (S + 1 < L) {
     if (sub == S)
-      tile_steps<N, R, B, L, VC, S, false, P>(sims, tiles, n0, parity, halo, k, cs, sm);
+      tile_steps<N, R, B, L, VC, S, false, P, CY>(sims, tiles, n0, parity, halo, k, cs, sm);
     else
-      run_group<N, R, B, L, VC, P, S + 1>(sub, sims, tiles, n0, parity, halo, k, cs, sm);
+      run_group<N, R, B, L, VC, P, CY, S + 1>(sub, sims, tiles, n0, parity, halo, k, cs, sm);
   } else {
-    tile_steps<N, R, B, L, VC, S, false, P>(sims, tiles, n0, parity, halo, k, cs, sm);
+    tile_steps<N, R, B, L, VC, S, false, P, CY>(sims, tiles, n0, parity, halo, k, cs, sm);
   }
 }
 
-// ST: strong coupling (one wave per 64 cells only)
-template <int N, typename R, int B, int L, bool VC, bool ST, bool P>
+// ST: strong coupling (one wave per 64 cells only); CY: Cayley field step
+template <int N, typename R, int B, int L, bool VC, bool ST, bool P, bool CY>
 __global__ void __launch_bounds__(B * L) k_blocked(const DevSim *__restrict__ sims,
                                                    const DevTile *__restrict__ tiles, int64_t n0, int parity,
                                                    int halo, int k, ChunkSync cs) {
   __shared__ TileShared<N, R, B, L> sm;
   if constexpr (L == 1) {
-    tile_steps<N, R, B, 1, VC, 0, ST, P>(sims, tiles, n0, parity, halo, k, cs, sm);
+    tile_steps<N, R, B, 1, VC, 0, ST, P, CY>(sims, tiles, n0, parity, halo, k, cs, sm);
   } else {
-    run_group<N, R, B, L, VC, P>(__builtin_amdgcn_readfirstlane(int(threadIdx.x) / B), sims, tiles, n0, parity, halo,
+    run_group<N, R, B, L, VC, P, CY>(__builtin_amdgcn_readfirstlane(int(threadIdx.x) / B), sims, tiles, n0, parity, halo,
                               k, cs, sm);
   }
 }
@@ -946,7 +966,7 @@ __global__ void __launch_bounds__(kPlainBlock) k_plain_hd(const DevSim *__restri
         R x[MA];
 #pragma unroll
         for (int a = 0; a < M; ++a) x[a] = xx[a * nx + c];
-        CL::rotate(x, e, mt);
+        CL::rotate(x, e, mt, sim.cayley != 0);
         p = CL::polar(x, mt);
         if (rec_now) record_density<N, R>(sim, c, n1, mm, x, rb, re);
         CL::propagate(x, mt);
@@ -1020,11 +1040,11 @@ __global__ void __launch_bounds__(kPlainBlock) k_plain_e(const DevSim *__restric
 // tile resident at once for the neighbour flags to make progress: the caller
 // checks the tile count against the occupancy (and a tile that waits too long
 // gives up, so a launch that does not fit ends with an error, not a hang).
-template <int N, typename R, int B, int L, bool VC, bool ST, bool P>
+template <int N, typename R, int B, int L, bool VC, bool ST, bool P, bool CY>
 hipError_t launch_shape(const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo,
                         int k, const ChunkSync &cs, int *per_cu, hipStream_t st) {
-  if constexpr (shape_fits<N, R, B, L>() && (!ST || (L == 1 && !VC && N >= 2))) {
-    auto kern = k_blocked<N, R, B, L, VC, ST, P>;
+  if constexpr (shape_fits<N, R, B, L>() && (!ST || (L == 1 && !VC && N >= 2)) && (!CY || (!VC && N >= 2))) {
+    auto kern = k_blocked<N, R, B, L, VC, ST, P, CY>;
     if (per_cu) return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kern, B * L, 0);
     kern<<<n_tiles, B * L, 0, st>>>(sims, tiles, n0, parity, halo, k, cs);
     return hipGetLastError();
@@ -1033,67 +1053,67 @@ hipError_t launch_shape(const DevSim *sims, const DevTile *tiles, int n_tiles, i
   }
 }
 
-template <int N, typename R, int L, bool VC, bool ST, bool P>
+template <int N, typename R, int L, bool VC, bool ST, bool P, bool CY>
 hipError_t launch_blocked_b(int block, const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0,
                             int parity, int halo, int k, const ChunkSync &cs, int *per_cu, hipStream_t st) {
   switch (block) {
-    case 64: return launch_shape<N, R, 64, L, VC, ST, P>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
-    case 128: return launch_shape<N, R, 128, L, VC, ST, P>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
-    case 192: return launch_shape<N, R, 192, L, VC, ST, P>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
-    case 256: return launch_shape<N, R, 256, L, VC, ST, P>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
-    case 512: return launch_shape<N, R, 512, L, VC, ST, P>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
-    case 1024: return launch_shape<N, R, 1024, L, VC, ST, P>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+    case 64: return launch_shape<N, R, 64, L, VC, ST, P, CY>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+    case 128: return launch_shape<N, R, 128, L, VC, ST, P, CY>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+    case 192: return launch_shape<N, R, 192, L, VC, ST, P, CY>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+    case 256: return launch_shape<N, R, 256, L, VC, ST, P, CY>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+    case 512: return launch_shape<N, R, 512, L, VC, ST, P, CY>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+    case 1024: return launch_shape<N, R, 1024, L, VC, ST, P, CY>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
   }
   return hipErrorInvalidValue;
 }
 
 // register-resident coefficients are instantiated for the small level counts
 // only, split waves for the quantum level counts
-template <int N, typename R, bool P>
+template <int N, typename R, bool P, bool CY>
 hipError_t launch_blocked_nr(int block, int lanes, bool vc, bool strong, const DevSim *sims, const DevTile *tiles,
                              int n_tiles, int64_t n0, int parity, int halo, int k, const ChunkSync &cs, int *per_cu,
                              hipStream_t st) {
-  constexpr bool kVC = N == 2 || N == 3;
+  constexpr bool kVC = (N == 2 || N == 3) && !CY;
   if (strong) {
     if constexpr (N >= 2)
-      return launch_blocked_b<N, R, 1, false, true, P>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+      return launch_blocked_b<N, R, 1, false, true, P, CY>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
     return hipErrorInvalidValue;
   }
   switch (lanes) {
     case 1:
       if constexpr (kVC)
-        if (vc) return launch_blocked_b<N, R, 1, kVC, false, P>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
-      return launch_blocked_b<N, R, 1, false, false, P>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+        if (vc) return launch_blocked_b<N, R, 1, kVC, false, P, CY>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+      return launch_blocked_b<N, R, 1, false, false, P, CY>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
     case 2:
     case 4:
       if constexpr (N >= 2) {
         if (lanes == 2) {
           if constexpr (kVC)
             if (vc)
-              return launch_blocked_b<N, R, 2, kVC, false, P>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
-          return launch_blocked_b<N, R, 2, false, false, P>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+              return launch_blocked_b<N, R, 2, kVC, false, P, CY>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+          return launch_blocked_b<N, R, 2, false, false, P, CY>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
         }
         if constexpr (kVC)
-          if (vc) return launch_blocked_b<N, R, 4, kVC, false, P>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
-        return launch_blocked_b<N, R, 4, false, false, P>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+          if (vc) return launch_blocked_b<N, R, 4, kVC, false, P, CY>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+        return launch_blocked_b<N, R, 4, false, false, P, CY>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
       }
       break;
     case 8:  // 64-cell tiles of the large density updates only
       if constexpr (N >= 4)
-        return launch_blocked_b<N, R, 8, false, false, P>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+        return launch_blocked_b<N, R, 8, false, false, P, CY>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
       break;
   }
   return hipErrorInvalidValue;
 }
 
-template <typename R, bool P>
+template <typename R, bool P, bool CY>
 hipError_t launch_blocked_r(int levels, int block, int lanes, bool vc, bool strong, const DevSim *sims,
                             const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo, int k,
                             const ChunkSync &cs, int *per_cu, hipStream_t st) {
   switch (levels) {
 #define MB_LEVELS_CASE(n)                                                                                       \
   case n:                                                                                                         \
-    return launch_blocked_nr<n, R, P>(block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, \
+    return launch_blocked_nr<n, R, P, CY>(block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, \
                                    st);
     MB_LEVELS_CASE(0)
     MB_LEVELS_CASE(2)
@@ -1154,10 +1174,11 @@ hipError_t launch_plain_n(const DevSim *sims, const DevTile *tiles, int n_tiles,
 
 }  // namespace
 
-// The kernels are built in four parts so that the library compiles them in
+// The kernels are built in six parts so that the library compiles them in
 // parallel: MB_PART 1 holds the FP32 one-chunk tiles, 3 the FP32 persistent
-// tiles, 4 the FP64 persistent tiles, 2 the FP64 one-chunk tiles, the
-// two-launch kernels and the dispatch; without MB_PART all are built here.
+// tiles, 4 the FP64 persistent tiles, 5 and 6 the FP32 and FP64 Cayley tiles,
+// 2 the FP64 one-chunk tiles, the two-launch kernels and the dispatch;
+// without MB_PART all are built here.
 #ifndef MB_PART
 #define MB_PART 0
 #endif
@@ -1170,17 +1191,26 @@ hipError_t launch_plain_n(const DevSim *sims, const DevTile *tiles, int n_tiles,
 hipError_t launch_blocked_f32(MB_LAUNCH_ARGS);
 hipError_t launch_blocked_f32p(MB_LAUNCH_ARGS);
 hipError_t launch_blocked_f64p(MB_LAUNCH_ARGS);
+hipError_t launch_blocked_f32c(MB_LAUNCH_ARGS);
+hipError_t launch_blocked_f64c(MB_LAUNCH_ARGS);
 bool fits_f32(int levels, int block, int lanes);
 
 #if MB_PART == 0 || MB_PART == 1
-hipError_t launch_blocked_f32(MB_LAUNCH_ARGS) { return launch_blocked_r<float, false>(MB_LAUNCH_PASS); }
+hipError_t launch_blocked_f32(MB_LAUNCH_ARGS) { return launch_blocked_r<float, false, false>(MB_LAUNCH_PASS); }
 bool fits_f32(int levels, int block, int lanes) { return fits_r<float>(levels, block, lanes); }
 #endif
 #if MB_PART == 0 || MB_PART == 3
-hipError_t launch_blocked_f32p(MB_LAUNCH_ARGS) { return launch_blocked_r<float, true>(MB_LAUNCH_PASS); }
+hipError_t launch_blocked_f32p(MB_LAUNCH_ARGS) { return launch_blocked_r<float, true, false>(MB_LAUNCH_PASS); }
 #endif
 #if MB_PART == 0 || MB_PART == 4
-hipError_t launch_blocked_f64p(MB_LAUNCH_ARGS) { return launch_blocked_r<double, true>(MB_LAUNCH_PASS); }
+hipError_t launch_blocked_f64p(MB_LAUNCH_ARGS) { return launch_blocked_r<double, true, false>(MB_LAUNCH_PASS); }
+#endif
+// Cayley field step: one-chunk tiles only, without register coefficients
+#if MB_PART == 0 || MB_PART == 5
+hipError_t launch_blocked_f32c(MB_LAUNCH_ARGS) { return launch_blocked_r<float, false, true>(MB_LAUNCH_PASS); }
+#endif
+#if MB_PART == 0 || MB_PART == 6
+hipError_t launch_blocked_f64c(MB_LAUNCH_ARGS) { return launch_blocked_r<double, false, true>(MB_LAUNCH_PASS); }
 #endif
 
 #if MB_PART == 0 || MB_PART == 2
@@ -1195,16 +1225,20 @@ bool shape_supported(int levels, int precision, int block, int lanes) {
 
 int plain_block() { return kPlainBlock; }
 
-hipError_t launch_blocked(int levels, int precision, int block, int lanes, bool vc, bool strong,
+hipError_t launch_blocked(int levels, int precision, int block, int lanes, bool vc, bool strong, bool cayley,
                           const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo,
                           int k, const ChunkSync &cs, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
   if (k < 1 || k > halo || k > kMaxChunk || 2 * halo >= block || cs.n_chunks < 1) return hipErrorInvalidValue;
   if (cs.n_chunks > 1 && (!cs.flags || k != halo || 3 * halo > block)) return hipErrorInvalidValue;
   int *per_cu = nullptr;
+  if (cayley) {
+    if (cs.n_chunks > 1 || vc) return hipErrorInvalidValue;
+    return precision == 64 ? launch_blocked_f64c(MB_LAUNCH_PASS) : launch_blocked_f32c(MB_LAUNCH_PASS);
+  }
   if (cs.n_chunks > 1)
     return precision == 64 ? launch_blocked_f64p(MB_LAUNCH_PASS) : launch_blocked_f32p(MB_LAUNCH_PASS);
-  return precision == 64 ? launch_blocked_r<double, false>(MB_LAUNCH_PASS) : launch_blocked_f32(MB_LAUNCH_PASS);
+  return precision == 64 ? launch_blocked_r<double, false, false>(MB_LAUNCH_PASS) : launch_blocked_f32(MB_LAUNCH_PASS);
 }
 
 // occupancy of the persistent form (the only one that needs every tile resident)

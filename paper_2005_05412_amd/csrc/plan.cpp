@@ -318,6 +318,8 @@ void build_quantum(MaterialPlan &mp, const QmFull &q, double dt, const mb_consts
   hermitian_eig(n, q.mu, mp.lam, mp.vec);
   mp.kappa.resize(n - 1);
   for (int i = 0; i + 1 < n; ++i) mp.kappa[i] = dt * (mp.lam[i] - mp.lam[i + 1]) / k.hbar;
+  mp.sigma.resize(n);
+  for (int i = 0; i < n; ++i) mp.sigma[i] = dt * mp.lam[i] / k.hbar;
   // full real generator in the eigen-basis: column a = L0' applied to basis a
   Mat gfull(size_t(nn) * nn, 0.0);
   std::vector<cd> out;
@@ -543,6 +545,14 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
     err = "coupling must be MB_COUPLING_WEAK or MB_COUPLING_STRONG";
     return MB_ERR_ARG;
   }
+  if (scen->field_step != MB_FIELD_EXACT && scen->field_step != MB_FIELD_CAYLEY) {
+    err = "field_step must be MB_FIELD_EXACT or MB_FIELD_CAYLEY";
+    return MB_ERR_ARG;
+  }
+  if (scen->field_step == MB_FIELD_CAYLEY && scen->variant == MB_VARIANT_BLOCKED_REGS) {
+    err = "the Cayley field step runs without register coefficients";
+    return MB_ERR_UNSUPPORTED;
+  }
   if (scen->coupling == MB_COUPLING_STRONG && scen->variant == MB_VARIANT_PLAIN) {
     err = "strong coupling runs on the blocked variant";
     return MB_ERR_UNSUPPORTED;
@@ -576,6 +586,7 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
   plan.depth = scen->depth;
   plan.lanes = scen->lanes;
   plan.coupling = scen->coupling;
+  plan.field_step = scen->field_step;
   plan.dx = scen->nx > 1 ? dev->length / double(scen->nx - 1) : 0.0;
   if (scen->nx > 1 && !(plan.dx > 0)) {
     err = "device length must be positive";

@@ -33,6 +33,7 @@ struct MaterialPlan {
   std::vector<double> lam;        // N sorted eigenvalues of mu
   std::vector<cd> vec;            // N x N eigenvectors (columns), row-major
   std::vector<double> kappa;      // N-1: dt (lam_q - lam_{q+1}) / hbar
+  std::vector<double> sigma;      // N: dt lam_j / hbar (Cayley field step)
   std::vector<double> gen;        // M x M generator of L0 (x' = G x + g)
   std::vector<double> gen_off;    // M
   std::vector<double> ah, bh;     // e^{L0 dt/2}: x -> ah x + bh
@@ -65,6 +66,7 @@ struct SimPlan {
   int variant = MB_VARIANT_AUTO;
   int block = 0, depth = 0, lanes = 0;
   int coupling = MB_COUPLING_WEAK;
+  int field_step = MB_FIELD_EXACT;
   std::vector<uint8_t> mat_e, mat_h;
   std::vector<MaterialPlan> mats;
   int edge_l = 0, edge_r = 0;     // 0: PEC, 1: Mur, 2: impedance load (0 < R < 1)

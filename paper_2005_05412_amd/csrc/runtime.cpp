@@ -84,6 +84,7 @@ void fill_mtab(const SimPlan &p, R *out) {
       t[coef_bf(n) + a] = mp.qm ? R(mp.bf[a]) : R(0);
       for (int b = 0; b < m; ++b) t[coef_am(n) + a * m + b] = mp.qm ? R(mp.am[size_t(a) * m + b]) : R(0);
     }
+    for (int j = 0; j < n; ++j) t[coef_sg(n) + j] = mp.qm ? R(mp.sigma[j]) : R(0);
   }
 }
 
@@ -242,12 +243,13 @@ int Engine::init(std::string &err) {
   return MB_OK;
 }
 
-Engine::Group &Engine::group_for(int levels, bool strong) {
+Engine::Group &Engine::group_for(int levels, bool strong, bool cayley) {
   for (auto &g : groups_)
-    if (g.levels == levels && g.strong == strong) return g;
+    if (g.levels == levels && g.strong == strong && g.cayley == cayley) return g;
   groups_.push_back(Group());
   groups_.back().levels = levels;
   groups_.back().strong = strong;
+  groups_.back().cayley = cayley;
   return groups_.back();
 }
 
@@ -255,6 +257,10 @@ int Engine::add(SimPlan &&plan, Arena *arena, hipStream_t st, std::string &err) 
   const bool plain = variant_ == MB_VARIANT_PLAIN;
   if (plain && plan.coupling == MB_COUPLING_STRONG) {
     err = "strong coupling runs on the blocked variant";
+    return MB_ERR_UNSUPPORTED;
+  }
+  if (vc_ && !plain && plan.field_step == MB_FIELD_CAYLEY) {
+    err = "the Cayley field step runs without register coefficients";
     return MB_ERR_UNSUPPORTED;
   }
   if (plain && precision_ != 64) {
@@ -376,6 +382,7 @@ int Engine::add(SimPlan &&plan, Arena *arena, hipStream_t st, std::string &err) 
   int64_t g = 0;
   for (auto &rp : p.records) g = std::gcd(g, rp.interval);
   d.rec_every = int32_t(g > 0 ? g : 1);
+  d.cayley = p.field_step == MB_FIELD_CAYLEY ? 1 : 0;
   d.rec_first = L.n_point ? reinterpret_cast<const int32_t *>(dev + L.rec_first) : nullptr;
   d.rec_cell = reinterpret_cast<const DevRecord *>(dev + L.rec_ids);
   d.rec_all = reinterpret_cast<const int32_t *>(dev + L.rec_all);
@@ -391,7 +398,8 @@ int Engine::add(SimPlan &&plan, Arena *arena, hipStream_t st, std::string &err) 
   d.parity_off = s->parity_off;
   s->active = true;
   int id = int(sims_.size());
-  group_for(p.n, p.coupling == MB_COUPLING_STRONG && p.n > 0).members.push_back(id);
+  group_for(p.n, p.coupling == MB_COUPLING_STRONG && p.n > 0, p.field_step == MB_FIELD_CAYLEY && p.n > 0)
+      .members.push_back(id);
   sims_.push_back(std::move(s));
   dirty_ = true;
   ++version_;
@@ -506,7 +514,7 @@ hipError_t Engine::launch_group(Group &g, hipStream_t st, int k, int reps) {
             hipSuccess)
           return e;
       }
-    } else if ((e = launch_blocked(g.levels, precision_, block_, lanes, vc_, g.strong, g.d_sims, g.d_tiles, g.n_tiles,
+    } else if ((e = launch_blocked(g.levels, precision_, block_, lanes, vc_, g.strong, g.cayley, g.d_sims, g.d_tiles, g.n_tiles,
                                    n0_ + int64_t(r) * k, parity_ ^ (r & 1), halo_, k, ChunkSync{nullptr, 0u, 1, 0},
                                    st)) != hipSuccess) {
       return e;
@@ -525,6 +533,7 @@ bool Engine::persist_ok(int k, int64_t reps) {
     live = &g;
   }
   if (!live || live->n_tiles < 1 || !live->d_flags) return false;
+  if (live->cayley) return false;  // the Cayley kernels run one chunk per launch
   const int lanes = group_lanes(*live);
   if (live->occ_block != block_ || live->occ_lanes != lanes) {
     live->occ_block = block_;
@@ -545,7 +554,7 @@ hipError_t Engine::run_persistent(hipStream_t st, int k, int64_t reps) {
   while (reps > 0) {
     const int n = int(std::min<int64_t>(reps, kMaxPersistChunks));
     const ChunkSync cs{g->d_flags, epoch_, n, spin_ticks_};
-    e = launch_blocked(g->levels, precision_, block_, lanes, vc_, g->strong, g->d_sims, g->d_tiles, g->n_tiles, n0_,
+    e = launch_blocked(g->levels, precision_, block_, lanes, vc_, g->strong, g->cayley, g->d_sims, g->d_tiles, g->n_tiles, n0_,
                        parity_, halo_, k, cs, st);
     if (e != hipSuccess) return e;
     epoch_ += uint32_t(n);

@@ -133,6 +133,7 @@ class Engine {
   struct Group {
     int levels = 0;
     bool strong = false;  // strong-coupling simulations (their own kernel)
+    bool cayley = false;  // Cayley field step (their own kernel)
     std::vector<int> members;
     DevSim *d_sims = nullptr;
     DevTile *d_tiles = nullptr;
@@ -140,7 +141,7 @@ class Engine {
     int n_tiles = 0, cap_sims = 0, cap_tiles = 0;
     int occ_block = 0, occ_lanes = 0, occ_per_cu = 0;  // cached occupancy of the group's kernel
   };
-  Group &group_for(int levels, bool strong);
+  Group &group_for(int levels, bool strong, bool cayley);
   hipError_t upload_group(Group &g, hipStream_t st);
   hipError_t launch_group(Group &g, hipStream_t st, int k, int reps);
   int group_lanes(const Group &g) const;

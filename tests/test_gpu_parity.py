@@ -456,6 +456,65 @@ def test_strong_coupling_sit_prefix_and_mixed_batch():
     b.close()
 
 
+CAYLEY = [
+    dict(seed=11, N=2, nx=37, n_steps=70, refl=(0.0, 1.0)),
+    dict(seed=12, N=3, nx=150, n_steps=90, refl=(1.0, 0.0), soft=True),
+    dict(seed=14, N=5, nx=45, n_steps=40, refl=(1.0, 1.0)),
+    dict(seed=15, N=6, nx=33, n_steps=30, refl=(0.0, 1.0)),
+    dict(seed=16, N=3, nx=1, n_steps=200, refl=(0.0, 0.0)),
+]
+
+
+@pytest.mark.parametrize("case", CAYLEY, ids=lambda c: f"N{c['N']}-nx{c['nx']}-s{c['seed']}")
+def test_cayley_field_step_vs_oracle(case):
+    """Field part by the Cayley approximant: FP64 within 1e-10 and FP32 within 1e-4 of the
+    oracle's Cayley run (which differs from the exact field step by 1e-7 and more on these
+    cases, so the tolerance tells the two apart); every tile shape the same bits; register
+    coefficients refused; with strong coupling too."""
+    prob = _small(case)
+    prob["field_step"] = "cayley"
+    _say(f"cayley {prob['name']}")
+    ref = O.run(prob)
+    plain = gpu_run(prob, precision=64, variant="plain")
+    errs = rel_errors(prob, plain, ref)
+    assert max(errs.values()) <= TOL[64], errs
+    for block, depth, lanes in ((64, 7, 1), (128, 31, 1), (192, 48, 2), (256, 32, 4), (64, 20, 8)):
+        assert_same(gpu_run(prob, precision=64, variant="blocked", block=block, depth=depth, lanes=lanes), plain)
+    got32 = gpu_run(prob, precision=32, variant="blocked", block=128, depth=16)
+    errs32 = rel_errors(prob, got32, ref)
+    assert max(errs32.values()) <= TOL[32], errs32
+    assert_same(gpu_run(prob, precision=32, variant="blocked", block=64, depth=16, lanes=4), got32)
+    with pytest.raises(mb.MBError) as ex:
+        mb.Solver(prob, precision=32, variant="blocked_regs")
+    assert ex.value.code == -3
+    prob["coupling"] = "strong"
+    ref = O.run(prob)
+    errs = rel_errors(prob, gpu_run(prob, precision=64, variant="blocked", block=128, depth=16), ref)
+    assert max(errs.values()) <= TOL[64], errs
+
+
+def test_cayley_sit_prefix_tuned_and_batched():
+    """Two-level SIT, first 4000 steps, with the Cayley field step through the tuned (auto)
+    shape in FP64 and FP32, and a batch that mixes exact and Cayley members."""
+    prob = W.sit_2lvl(n_steps=4000)
+    prob["field_step"] = "cayley"
+    _say("cayley sit")
+    ref = O.run(prob)
+    got = gpu_run(prob, precision=64)
+    errs = rel_errors(prob, got, ref)
+    assert max(errs.values()) <= TOL[64], errs
+    errs32 = rel_errors(prob, gpu_run(prob, precision=32), ref)
+    assert max(errs32.values()) <= TOL[32], errs32
+    probs = _mixed_batch(n=4, n_steps=500, precision=32)
+    for k in (0, 3):
+        probs[k]["field_step"] = "cayley"
+    b = mb.Batch(probs, precision=32)
+    b.run(use_graph=True)
+    for k, p in enumerate(probs):
+        assert_same(b.records(k), gpu_run(p, precision=32, variant="blocked", block=256, depth=32))
+    b.close()
+
+
 def test_sweep_batch_spot_checks_vs_oracle():
     """The 256-simulation FP32 sweep in one batch; 8 seeded members checked against the oracle
     on their first 600 steps (12 record samples)."""

@@ -189,6 +189,13 @@ def test_status_codes():
     with pytest.raises(mb.MBError) as ex:        # strong coupling runs on the blocked variant
         mb.plan_status(strong, variant="plain")
     assert ex.value.code == -3
+    cay = _vac()
+    cay["field_step"] = "cayley"
+    assert mb.plan_status(cay) == 0
+    assert mb.plan_status(cay, variant="plain") == 0
+    with pytest.raises(mb.MBError) as ex:        # the Cayley phases are not register coefficients
+        mb.plan_status(cay, variant="blocked_regs")
+    assert ex.value.code == -3
 
 
 def test_non_completely_positive_dephasing_warns():
