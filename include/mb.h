@@ -230,14 +230,27 @@ int mb_plan_readout(const mb_device_desc *dev, const mb_scenario_desc *scen, int
 
 /* ---- single simulation --------------------------------------------------- */
 
+/* Device bytes the simulation occupies (state planes E, H and rho twice, the
+ * initial state, material, source and record tables, record buffers): the
+ * size of a caller-provided mb_setup workspace.  Host-only (no GPU call);
+ * errors as mb_setup's validation. */
+int mb_workspace_bytes(const mb_device_desc *dev, const mb_scenario_desc *scen, size_t *bytes);
+
 /* Validates the description, computes every FP64 table on the host
  * (coefficients a', b', c' of Sec. 3.2, the Liouvillian and its
- * exponentials, the field eigen-basis, source values, record plan), allocates
- * device memory on HIP device `hip_device` and uploads the initial state.
+ * exponentials, the field eigen-basis, source values, record plan), places
+ * the simulation in device memory of HIP device `hip_device` and uploads the
+ * initial state.
+ * workspace: NULL = the library allocates (and frees in mb_destroy); else a
+ * caller-owned device pointer (e.g. a torch tensor's data_ptr) of ws_bytes >=
+ * mb_workspace_bytes, 256-byte aligned, which must stay allocated until
+ * mb_destroy (the library never frees it); too small or misaligned:
+ * MB_ERR_ARG.  The engine's launch tables (a few KB) and, with automatic
+ * shapes, the tuner's first timing runs are still allocated by the library.
  * Returns MB_WARN_NOT_CP (with a valid handle) when a material's dephasing
  * rates admit no completely positive dissipator. */
-int mb_setup(int hip_device, const mb_device_desc *dev, const mb_scenario_desc *scen,
-             mb_handle **out);
+int mb_setup(int hip_device, const mb_device_desc *dev, const mb_scenario_desc *scen, void *workspace,
+             size_t ws_bytes, mb_handle **out);
 
 /* Enqueues n_steps time steps (-1: all remaining) on `hip_stream` (a
  * hipStream_t, NULL = the legacy default stream).  Asynchronous.  The blocked
@@ -341,6 +354,11 @@ int mb_server_start(mb_server *s);
 int mb_server_drain(mb_server *s, double timeout_s);
 /* Cancels a queued or running request; it is retired at the next chunk boundary. */
 int mb_server_cancel(mb_server *s, uint64_t ticket);
+/* Tickets of requests that reached a final state (done, cancelled or failed;
+ * mb_server_status tells which) since the previous poll, oldest first: up to
+ * `capacity` of them into done[], their count in *n_done; the rest stay for
+ * the next poll.  Non-blocking. */
+int mb_server_poll(mb_server *s, uint64_t *done, int32_t capacity, int32_t *n_done);
 /* Status of a request: 0 queued, 1 running, 2 done, 3 cancelled, or a
  * negative error it ended with.  Times (seconds on the server clock) may be NULL. */
 int mb_server_status(mb_server *s, uint64_t ticket, int32_t *state, double *t_arrival,

@@ -29,10 +29,10 @@ VARIANT = {"auto": 0, "plain": 1, "blocked": 2, "blocked_regs": 3}
 FIELD_STEP = {"exact": 0, "cayley": 1}    # MB_FIELD_EXACT, MB_FIELD_CAYLEY
 
 EXPORTS = [
-    "mb_last_error", "mb_device_count", "mb_plan_material", "mb_plan_readout", "mb_setup", "mb_run", "mb_run_mode", "mb_reset", "mb_batch_reset", "mb_shape", "mb_batch_shape", "mb_steps_done", "mb_record_shape",
+    "mb_last_error", "mb_device_count", "mb_plan_material", "mb_plan_readout", "mb_workspace_bytes", "mb_setup", "mb_run", "mb_run_mode", "mb_reset", "mb_batch_reset", "mb_shape", "mb_batch_shape", "mb_steps_done", "mb_record_shape",
     "mb_read_records", "mb_read_state", "mb_elapsed_ms", "mb_destroy", "mb_batch_setup", "mb_batch_run",
     "mb_batch_record_shape", "mb_batch_read_records", "mb_batch_elapsed_ms", "mb_batch_destroy",
-    "mb_server_create", "mb_server_submit", "mb_server_start", "mb_server_drain", "mb_server_cancel",
+    "mb_server_create", "mb_server_submit", "mb_server_start", "mb_server_drain", "mb_server_cancel", "mb_server_poll",
     "mb_server_status", "mb_server_record_shape", "mb_server_read_records", "mb_server_stats",
     "mb_server_destroy",
 ]
@@ -122,7 +122,10 @@ def load():
                                        dp, C.c_int64, i64p]),
         "mb_plan_readout": (C.c_int, [C.POINTER(mb_device_desc), C.POINTER(mb_scenario_desc), C.c_int32,
                                       C.c_int32, dp, C.c_int64]),
-        "mb_setup": (C.c_int, [C.c_int, C.POINTER(mb_device_desc), C.POINTER(mb_scenario_desc), C.POINTER(P)]),
+        "mb_setup": (C.c_int, [C.c_int, C.POINTER(mb_device_desc), C.POINTER(mb_scenario_desc), P, C.c_size_t,
+                               C.POINTER(P)]),
+        "mb_workspace_bytes": (C.c_int, [C.POINTER(mb_device_desc), C.POINTER(mb_scenario_desc),
+                                         C.POINTER(C.c_size_t)]),
         "mb_run": (C.c_int, [P, C.c_int64, P]),
         "mb_run_mode": (C.c_int, [P, C.c_int64]),
         "mb_reset": (C.c_int, [P, P]),
@@ -148,6 +151,7 @@ def load():
         "mb_server_start": (C.c_int, [P]),
         "mb_server_drain": (C.c_int, [P, C.c_double]),
         "mb_server_cancel": (C.c_int, [P, C.c_uint64]),
+        "mb_server_poll": (C.c_int, [P, C.POINTER(C.c_uint64), C.c_int32, C.POINTER(C.c_int32)]),
         "mb_server_status": (C.c_int, [P, C.c_uint64, C.POINTER(C.c_int32), dp, dp, dp]),
         "mb_server_record_shape": (C.c_int, [P, C.c_uint64, C.c_int, i64p, i64p]),
         "mb_server_read_records": (C.c_int, [P, C.c_uint64, C.c_int, dp, C.c_int64, i64p]),
@@ -317,15 +321,38 @@ def plan_status(prob, precision=None, variant="auto", block=0, depth=0, lanes=0)
     return 0
 
 
+def workspace_bytes(prob, precision=None, variant="auto"):
+    """Device bytes of one simulation (mb_workspace_bytes): the size of a Solver workspace."""
+    m = _Marshal(prob, precision, variant, 0, 0, 0)
+    n = C.c_size_t()
+    _check(load().mb_workspace_bytes(C.byref(m.dev), C.byref(m.scen), C.byref(n)))
+    return n.value
+
+
+def _workspace_ptr(ws):
+    if ws is None:
+        return None, 0
+    if isinstance(ws, tuple):
+        return C.c_void_p(int(ws[0])), int(ws[1])
+    return C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size()
+
+
 class Solver:
     """One simulation resident on the GPU (mb_setup / mb_run / mb_read_records)."""
 
-    def __init__(self, prob, device=0, precision=None, variant="auto", block=0, depth=0, lanes=0):
+    def __init__(self, prob, device=0, precision=None, variant="auto", block=0, depth=0, lanes=0,
+                 workspace=None):
+        """workspace: None (the library allocates), or caller-owned device memory for the
+        simulation: a tensor (kept referenced by the solver) or (pointer, bytes), at least
+        workspace_bytes(...) bytes, 256-byte aligned."""
         lib = load()
         self.prob = prob
         self._m = _Marshal(prob, precision, variant, block, depth, lanes)
+        self._ws = workspace
+        ptr, nbytes = _workspace_ptr(workspace)
         h = C.c_void_p()
-        self.warning = _check(lib.mb_setup(device, C.byref(self._m.dev), C.byref(self._m.scen), C.byref(h)))
+        self.warning = _check(lib.mb_setup(device, C.byref(self._m.dev), C.byref(self._m.scen), ptr, nbytes,
+                                           C.byref(h)))
         self._h = h
 
     def run(self, n_steps=-1, stream=None):
@@ -486,6 +513,13 @@ class Server:
 
     def cancel(self, ticket):
         _check(load().mb_server_cancel(self._h, C.c_uint64(ticket)))
+
+    def poll(self, capacity=256):
+        """Tickets that reached a final state since the previous poll (non-blocking)."""
+        buf = (C.c_uint64 * max(1, capacity))()
+        n = C.c_int32()
+        _check(load().mb_server_poll(self._h, buf, int(capacity), C.byref(n)))
+        return [int(buf[i]) for i in range(n.value)]
 
     def status(self, ticket):
         st, ta, tb, tc = C.c_int32(), C.c_double(), C.c_double(), C.c_double()

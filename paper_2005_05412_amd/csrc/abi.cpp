@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <memory>
@@ -26,6 +27,10 @@ using namespace mb;
 
 namespace {
 
+// a simulation's device block, rounded to the sub-allocator's granule
+constexpr size_t kWorkspaceAlign = 256;
+size_t workspace_round(size_t v) { return (v + kWorkspaceAlign - 1) / kWorkspaceAlign * kWorkspaceAlign; }
+
 // One captured run of chunk launches, replayed when the same run (engine
 // tables, start step, length) is asked for again, e.g. after mb_reset.
 struct GraphCache {
@@ -47,6 +52,7 @@ struct GraphCache {
 
 struct mb_handle {
   int device = 0;
+  Arena ws;  // the caller's workspace, if any (declared before eng: outlives it)
   std::unique_ptr<Engine> eng;
   int id = -1;
   hipStream_t last_stream = nullptr;
@@ -234,7 +240,21 @@ int mb_plan_readout(const mb_device_desc *dev, const mb_scenario_desc *scen, int
   MB_GUARD_END
 }
 
-int mb_setup(int hip_device, const mb_device_desc *dev, const mb_scenario_desc *scen, mb_handle **out) {
+int mb_workspace_bytes(const mb_device_desc *dev, const mb_scenario_desc *scen, size_t *bytes) {
+  MB_GUARD_BEGIN
+  if (!bytes) return fail(MB_ERR_ARG, "null output");
+  *bytes = 0;
+  SimPlan plan;
+  std::string err;
+  int rc = build_plan(dev, scen, plan, err);
+  if (rc < 0) return fail(rc, err);
+  *bytes = workspace_round(sim_bytes(plan, plan.precision, plan.variant == MB_VARIANT_PLAIN));
+  return MB_OK;
+  MB_GUARD_END
+}
+
+int mb_setup(int hip_device, const mb_device_desc *dev, const mb_scenario_desc *scen, void *workspace,
+             size_t ws_bytes, mb_handle **out) {
   MB_GUARD_BEGIN
   if (!out) return fail(MB_ERR_ARG, "null output handle");
   *out = nullptr;
@@ -243,6 +263,13 @@ int mb_setup(int hip_device, const mb_device_desc *dev, const mb_scenario_desc *
   int rc = build_plan(dev, scen, plan, err);
   if (rc < 0) return fail(rc, err);
   int warn = rc;
+  const size_t need = workspace_round(sim_bytes(plan, plan.precision, plan.variant == MB_VARIANT_PLAIN));
+  if (workspace) {
+    if (reinterpret_cast<uintptr_t>(workspace) % kWorkspaceAlign != 0)
+      return fail(MB_ERR_ARG, "workspace must be 256-byte aligned");
+    if (ws_bytes < need)
+      return fail(MB_ERR_ARG, "workspace smaller than mb_workspace_bytes (" + std::to_string(need) + " bytes)");
+  }
   int block = 0, halo = 0, lanes = 1;
   bool vc = plan.variant == MB_VARIANT_BLOCKED_REGS, persist = true;
   if ((rc = shape_for(plan, block, halo, lanes)) < 0) return rc;
@@ -263,7 +290,8 @@ int mb_setup(int hip_device, const mb_device_desc *dev, const mb_scenario_desc *
   if ((rc = h->eng->init(err)) < 0) return fail(rc, err);
   h->eng->set_persist(persist);
   hipStream_t st = nullptr;
-  int id = h->eng->add(std::move(plan), nullptr, st, err);
+  if (workspace) h->ws.init_external(workspace, ws_bytes);
+  int id = h->eng->add(std::move(plan), workspace ? &h->ws : nullptr, st, err);
   if (id < 0) return fail(id, err);
   h->id = id;
   *out = h.release();

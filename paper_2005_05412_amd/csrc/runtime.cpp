@@ -135,7 +135,17 @@ void default_shape(int levels, int precision, int &block, int &halo) {
 // ---------------------------------------------------------------- Arena
 
 Arena::~Arena() {
-  if (base_) (void)hipFree(base_);
+  if (base_ && own_) (void)hipFree(base_);
+}
+
+void Arena::init_external(void *base, size_t bytes) {
+  base_ = static_cast<char *>(base);
+  own_ = false;
+  cap_ = bytes / kAlign * kAlign;
+  used_ = 0;
+  free_.clear();
+  live_.clear();
+  if (cap_) free_[0] = cap_;
 }
 
 int Arena::init(size_t bytes, std::string &err) {

@@ -22,6 +22,9 @@ class Arena {
   Arena() = default;
   ~Arena();
   int init(size_t bytes, std::string &err);
+  // sub-allocates from caller-owned device memory (never freed here); base
+  // must be 256-byte aligned
+  void init_external(void *base, size_t bytes);
   void *alloc(size_t bytes);
   void release(void *p);
   size_t capacity() const { return cap_; }
@@ -29,6 +32,7 @@ class Arena {
 
  private:
   char *base_ = nullptr;
+  bool own_ = true;
   size_t cap_ = 0, used_ = 0;
   std::map<size_t, size_t> free_;  // offset -> size
   std::map<size_t, size_t> live_;  // offset -> size

@@ -88,6 +88,7 @@ struct mb_server {
   uint64_t next_ticket = 1;
   std::map<uint64_t, std::unique_ptr<Request>> reqs;
   std::deque<Request *> queue;      // ordered by arrival
+  std::deque<uint64_t> finished;    // tickets that reached a final state, not yet polled
   int n_running = 0;
   size_t outstanding = 0;
   double busy_s = 0;
@@ -165,6 +166,7 @@ void mb_server::retire(Lane &ln, Request *r, int32_t state) {
   }
   r->state = state;
   r->t_done = now();
+  finished.push_back(r->ticket);
   --n_running;
   if (outstanding) --outstanding;
 }
@@ -236,6 +238,7 @@ void mb_server::loop() {
         it = queue.erase(it);
         r->state = 3;
         r->t_done = t;
+        finished.push_back(r->ticket);
         if (outstanding) --outstanding;
         continue;
       }
@@ -248,6 +251,7 @@ void mb_server::loop() {
         it = queue.erase(it);
         r->state = rc;
         r->t_done = t;
+        finished.push_back(r->ticket);
         if (outstanding) --outstanding;
         continue;
       }
@@ -262,6 +266,7 @@ void mb_server::loop() {
       if (id < 0) {
         r->state = id;
         r->t_done = t;
+        finished.push_back(r->ticket);
         if (outstanding) --outstanding;
         continue;
       }
@@ -425,6 +430,18 @@ int mb_server_status(mb_server *s, uint64_t ticket, int32_t *state, double *t_ar
   if (t_arrival) *t_arrival = r.arrival;
   if (t_admit) *t_admit = r.t_admit;
   if (t_done) *t_done = r.t_done;
+  return MB_OK;
+}
+
+int mb_server_poll(mb_server *s, uint64_t *done, int32_t capacity, int32_t *n_done) {
+  if (!s || !n_done || (capacity > 0 && !done) || capacity < 0) return fail(MB_ERR_ARG, "bad arguments");
+  std::lock_guard<std::mutex> lk(s->mu);
+  int32_t n = 0;
+  while (n < capacity && !s->finished.empty()) {
+    done[n++] = s->finished.front();
+    s->finished.pop_front();
+  }
+  *n_done = n;
   return MB_OK;
 }
 

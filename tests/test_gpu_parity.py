@@ -274,8 +274,11 @@ def test_persistent_launch_equals_relaunches():
 
 
 def test_server_results_equal_alone():
-    """Requests admitted while others run give the same records as solo runs."""
+    """Requests admitted while others run give the same records as solo runs (two of them
+    with the Cayley field step, which run as a kernel group of their own)."""
     probs = _mixed_batch(n=8, n_steps=300, precision=32)
+    for k in (2, 5):
+        probs[k]["field_step"] = "cayley"
     _say("server")
     srv = mb.Server(hbm_budget=256 << 20, max_slots=3, precision=32, chunk_steps=16)
     tickets = [srv.submit(p, arrival_s=0.002 * k) for k, p in enumerate(probs)]
@@ -289,6 +292,8 @@ def test_server_results_equal_alone():
             assert np.array_equal(srv.record(t, k), alone[r["name"]]), r["name"]
     cu, busy, chunks = srv.stats()
     assert cu == sum(p["nx"] * p["n_steps"] for p in probs)
+    polled = srv.poll(capacity=5) + srv.poll()
+    assert sorted(polled) == sorted(tickets) and srv.poll() == []
     srv.close()
 
 
@@ -310,6 +315,31 @@ def test_server_budget_and_cancel():
     assert srv.status(t1)[0] == 2
     assert srv.status(t2)[0] == 3
     srv.close()
+
+
+def test_caller_workspace():
+    """mb_setup into caller-owned device memory (a torch tensor) gives the same records as
+    library-allocated memory; a workspace that is too small or misaligned is refused."""
+    import torch
+    prob = W.random_small(12, N=3, nx=150, n_steps=90, refl=(1.0, 0.0), soft=True)
+    _say("workspace")
+    for precision, variant in ((64, "plain"), (32, "blocked")):
+        need = mb.workspace_bytes(prob, precision=precision, variant=variant)
+        shape = dict(block=128, depth=16) if variant == "blocked" else {}
+        ref = gpu_run(prob, precision=precision, variant=variant, **shape)
+        ws = torch.full((need + 512,), 255, dtype=torch.uint8, device="cuda")
+        assert ws.data_ptr() % 256 == 0
+        torch.cuda.synchronize()  # the fill is done before the library uploads the state
+        s = mb.Solver(prob, precision=precision, variant=variant, workspace=ws, **shape)
+        s.run()
+        assert_same(s.records(), ref)
+        s.close()
+        for bad in ((ws.data_ptr(), need - 256), (ws.data_ptr() + 64, need + 256)):
+            with pytest.raises(mb.MBError) as ex:
+                mb.Solver(prob, precision=precision, variant=variant, workspace=bad, **shape)
+            assert ex.value.code == -1
+        del ws
+        torch.cuda.synchronize()
 
 
 def test_reset_and_graph_replay_reproduce_the_run():

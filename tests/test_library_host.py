@@ -198,6 +198,23 @@ def test_status_codes():
     assert ex.value.code == -3
 
 
+def test_workspace_bytes():
+    """mb_workspace_bytes: host-only, 256-byte granules, at least the two state copies of
+    E, H and the M density planes, growing with the grid and the precision."""
+    p = W.random_small(12, N=3, nx=150, n_steps=90)
+    b64 = mb.workspace_bytes(p, precision=64)
+    b32 = mb.workspace_bytes(p, precision=32)
+    assert b64 % 256 == 0 and b32 % 256 == 0
+    m = 8
+    assert b64 >= 2 * (2 + m) * 150 * 8 and b32 >= 2 * (2 + m) * 150 * 4
+    assert b32 < b64
+    big = W.random_small(12, N=3, nx=1500, n_steps=90)
+    assert mb.workspace_bytes(big, precision=64) > b64
+    with pytest.raises(mb.MBError) as ex:
+        mb.workspace_bytes(_vac(courant=1.01))
+    assert ex.value.code == -2
+
+
 def test_non_completely_positive_dephasing_warns():
     qm = W.general_qm(1e24, [0.0, 0.1 * C["e"], 0.2 * C["e"]], None, None,
                       np.array([1e-29, 1e-29, 0.0]), np.zeros((3, 3)), [1e12, 1e12, 10e12])
