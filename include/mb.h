@@ -242,7 +242,7 @@ int mb_workspace_bytes(const mb_device_desc *dev, const mb_scenario_desc *scen, 
  * the simulation in device memory of HIP device `hip_device` and uploads the
  * initial state.
  * workspace: NULL = the library allocates (and frees in mb_destroy); else a
- * caller-owned device pointer (e.g. a torch tensor's data_ptr) of ws_bytes >=
+ * caller-owned device pointer (hipMalloc'ed on hip_device) of ws_bytes >=
  * mb_workspace_bytes, 256-byte aligned, which must stay allocated until
  * mb_destroy (the library never frees it); too small or misaligned:
  * MB_ERR_ARG.  The engine's launch tables (a few KB) and, with automatic

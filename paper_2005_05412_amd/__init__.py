@@ -343,8 +343,9 @@ class Solver:
     def __init__(self, prob, device=0, precision=None, variant="auto", block=0, depth=0, lanes=0,
                  workspace=None):
         """workspace: None (the library allocates), or caller-owned device memory for the
-        simulation: a tensor (kept referenced by the solver) or (pointer, bytes), at least
-        workspace_bytes(...) bytes, 256-byte aligned."""
+        simulation, allocated through the same HIP runtime as the library: (pointer, bytes)
+        or an object with data_ptr()/numel()/element_size() (kept referenced by the solver),
+        at least workspace_bytes(...) bytes, 256-byte aligned."""
         lib = load()
         self.prob = prob
         self._m = _Marshal(prob, precision, variant, block, depth, lanes)

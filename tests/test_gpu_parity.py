@@ -318,28 +318,34 @@ def test_server_budget_and_cancel():
 
 
 def test_caller_workspace():
-    """mb_setup into caller-owned device memory (a torch tensor) gives the same records as
-    library-allocated memory; a workspace that is too small or misaligned is refused."""
-    import torch
+    """mb_setup into caller-owned device memory (hipMalloc'ed here, filled with 0xFF) gives
+    the same records as library-allocated memory; a workspace that is too small or
+    misaligned is refused before any device work."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
     prob = W.random_small(12, N=3, nx=150, n_steps=90, refl=(1.0, 0.0), soft=True)
     _say("workspace")
     for precision, variant in ((64, "plain"), (32, "blocked")):
         need = mb.workspace_bytes(prob, precision=precision, variant=variant)
         shape = dict(block=128, depth=16) if variant == "blocked" else {}
         ref = gpu_run(prob, precision=precision, variant=variant, **shape)
-        ws = torch.full((need + 512,), 255, dtype=torch.uint8, device="cuda")
-        assert ws.data_ptr() % 256 == 0
-        torch.cuda.synchronize()  # the fill is done before the library uploads the state
-        s = mb.Solver(prob, precision=precision, variant=variant, workspace=ws, **shape)
-        s.run()
-        assert_same(s.records(), ref)
-        s.close()
-        for bad in ((ws.data_ptr(), need - 256), (ws.data_ptr() + 64, need + 256)):
-            with pytest.raises(mb.MBError) as ex:
-                mb.Solver(prob, precision=precision, variant=variant, workspace=bad, **shape)
-            assert ex.value.code == -1
-        del ws
-        torch.cuda.synchronize()
+        ptr = ctypes.c_void_p()
+        assert hip.hipMalloc(ctypes.byref(ptr), ctypes.c_size_t(need + 512)) == 0
+        try:
+            assert ptr.value % 256 == 0
+            assert hip.hipMemset(ptr, 0xFF, ctypes.c_size_t(need + 512)) == 0
+            assert hip.hipDeviceSynchronize() == 0
+            s = mb.Solver(prob, precision=precision, variant=variant, workspace=(ptr.value, need), **shape)
+            s.run()
+            assert_same(s.records(), ref)
+            s.close()
+            for bad in ((ptr.value, need - 256), (ptr.value + 64, need + 256)):
+                with pytest.raises(mb.MBError) as ex:
+                    mb.Solver(prob, precision=precision, variant=variant, workspace=bad, **shape)
+                assert ex.value.code == -1
+        finally:
+            assert hip.hipDeviceSynchronize() == 0
+            hip.hipFree(ptr)
 
 
 def test_reset_and_graph_replay_reproduce_the_run():
