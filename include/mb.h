@@ -80,8 +80,8 @@ extern "C" {
  * MB_FIELD_EXACT takes W = exp(A) (through the eigen-decomposition of mu);
  * MB_FIELD_CAYLEY its Cayley approximant W = (I - A/2)^{-1} (I + A/2), unitary and
  * second-order accurate (the lindblad_reg_cayley class of Sec. 3.2 names the
- * form).  The Cayley form runs without register coefficients and one chunk per
- * launch, never persistent (MB_VARIANT_BLOCKED_REGS with it is MB_ERR_UNSUPPORTED). */
+ * form).  Both forms run on every variant; persistent Cayley launches use one
+ * wave per 64 cells. */
 #define MB_FIELD_EXACT 0
 #define MB_FIELD_CAYLEY 1
 

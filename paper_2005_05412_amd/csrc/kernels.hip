@@ -606,14 +606,14 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
   const uint32_t rec_every = uint32_t(sim.rec_every);
   const R kap_l = R(sim.kap_l), kap_r = R(sim.kap_r);
   // field part by the Cayley approximant (kernels of their own: the extra
-  // phase code costs the other kernels instruction-cache space)
+  // phase code would cost the other kernels instruction-cache space)
   constexpr bool cay = CY;
 
   // coefficients of a single-material wave held in registers for the launch
   // (those this wave group reads: phases, polarization, its propagator rows)
   auto coef_used = [](int i) {
     const int t = i + kCoefKap;
-    if (t >= coef_sg(N)) return false;  // Cayley coefficients: never with register coefficients
+    if (t >= coef_sg(N)) return CY;  // Cayley coefficients (every wave group rotates)
     if (t < coef_bf(N)) return true;
     if (t < coef_am(N)) return SP::owns(SUB, t - coef_bf(N));
     return SP::owns(SUB, (t - coef_am(N)) / (M > 0 ? M : 1));
@@ -1043,7 +1043,7 @@ __global__ void __launch_bounds__(kPlainBlock) k_plain_e(const DevSim *__restric
 template <int N, typename R, int B, int L, bool VC, bool ST, bool P, bool CY>
 hipError_t launch_shape(const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo,
                         int k, const ChunkSync &cs, int *per_cu, hipStream_t st) {
-  if constexpr (shape_fits<N, R, B, L>() && (!ST || (L == 1 && !VC && N >= 2)) && (!CY || (!VC && N >= 2))) {
+  if constexpr (shape_fits<N, R, B, L>() && (!ST || (L == 1 && !VC && N >= 2)) && (!CY || N >= 2)) {
     auto kern = k_blocked<N, R, B, L, VC, ST, P, CY>;
     if (per_cu) return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kern, B * L, 0);
     kern<<<n_tiles, B * L, 0, st>>>(sims, tiles, n0, parity, halo, k, cs);
@@ -1073,7 +1073,11 @@ template <int N, typename R, bool P, bool CY>
 hipError_t launch_blocked_nr(int block, int lanes, bool vc, bool strong, const DevSim *sims, const DevTile *tiles,
                              int n_tiles, int64_t n0, int parity, int halo, int k, const ChunkSync &cs, int *per_cu,
                              hipStream_t st) {
-  constexpr bool kVC = (N == 2 || N == 3) && !CY;
+  constexpr bool kVC = N == 2 || N == 3;
+  // persistent Cayley tiles: one wave per 64 cells only (the other forms
+  // report no occupancy, so such runs take one launch per chunk)
+  if constexpr (P && CY)
+    if (lanes != 1 && !strong) return hipErrorInvalidValue;
   if (strong) {
     if constexpr (N >= 2)
       return launch_blocked_b<N, R, 1, false, true, P, CY>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
@@ -1174,11 +1178,11 @@ hipError_t launch_plain_n(const DevSim *sims, const DevTile *tiles, int n_tiles,
 
 }  // namespace
 
-// The kernels are built in six parts so that the library compiles them in
+// The kernels are built in eight parts so that the library compiles them in
 // parallel: MB_PART 1 holds the FP32 one-chunk tiles, 3 the FP32 persistent
-// tiles, 4 the FP64 persistent tiles, 5 and 6 the FP32 and FP64 Cayley tiles,
-// 2 the FP64 one-chunk tiles, the two-launch kernels and the dispatch;
-// without MB_PART all are built here.
+// tiles, 4 the FP64 persistent tiles, 5 and 6 the FP32 and FP64 one-chunk
+// Cayley tiles, 7 and 8 the persistent ones, 2 the FP64 one-chunk tiles, the
+// two-launch kernels and the dispatch; without MB_PART all are built here.
 #ifndef MB_PART
 #define MB_PART 0
 #endif
@@ -1193,6 +1197,8 @@ hipError_t launch_blocked_f32p(MB_LAUNCH_ARGS);
 hipError_t launch_blocked_f64p(MB_LAUNCH_ARGS);
 hipError_t launch_blocked_f32c(MB_LAUNCH_ARGS);
 hipError_t launch_blocked_f64c(MB_LAUNCH_ARGS);
+hipError_t launch_blocked_f32pc(MB_LAUNCH_ARGS);
+hipError_t launch_blocked_f64pc(MB_LAUNCH_ARGS);
 bool fits_f32(int levels, int block, int lanes);
 
 #if MB_PART == 0 || MB_PART == 1
@@ -1205,12 +1211,18 @@ hipError_t launch_blocked_f32p(MB_LAUNCH_ARGS) { return launch_blocked_r<float, 
 #if MB_PART == 0 || MB_PART == 4
 hipError_t launch_blocked_f64p(MB_LAUNCH_ARGS) { return launch_blocked_r<double, true, false>(MB_LAUNCH_PASS); }
 #endif
-// Cayley field step: one-chunk tiles only, without register coefficients
+// Cayley field step: one-chunk and persistent tiles
 #if MB_PART == 0 || MB_PART == 5
 hipError_t launch_blocked_f32c(MB_LAUNCH_ARGS) { return launch_blocked_r<float, false, true>(MB_LAUNCH_PASS); }
 #endif
 #if MB_PART == 0 || MB_PART == 6
 hipError_t launch_blocked_f64c(MB_LAUNCH_ARGS) { return launch_blocked_r<double, false, true>(MB_LAUNCH_PASS); }
+#endif
+#if MB_PART == 0 || MB_PART == 7
+hipError_t launch_blocked_f32pc(MB_LAUNCH_ARGS) { return launch_blocked_r<float, true, true>(MB_LAUNCH_PASS); }
+#endif
+#if MB_PART == 0 || MB_PART == 8
+hipError_t launch_blocked_f64pc(MB_LAUNCH_ARGS) { return launch_blocked_r<double, true, true>(MB_LAUNCH_PASS); }
 #endif
 
 #if MB_PART == 0 || MB_PART == 2
@@ -1233,7 +1245,8 @@ hipError_t launch_blocked(int levels, int precision, int block, int lanes, bool 
   if (cs.n_chunks > 1 && (!cs.flags || k != halo || 3 * halo > block)) return hipErrorInvalidValue;
   int *per_cu = nullptr;
   if (cayley) {
-    if (cs.n_chunks > 1 || vc) return hipErrorInvalidValue;
+    if (cs.n_chunks > 1)
+      return precision == 64 ? launch_blocked_f64pc(MB_LAUNCH_PASS) : launch_blocked_f32pc(MB_LAUNCH_PASS);
     return precision == 64 ? launch_blocked_f64c(MB_LAUNCH_PASS) : launch_blocked_f32c(MB_LAUNCH_PASS);
   }
   if (cs.n_chunks > 1)
@@ -1242,7 +1255,7 @@ hipError_t launch_blocked(int levels, int precision, int block, int lanes, bool 
 }
 
 // occupancy of the persistent form (the only one that needs every tile resident)
-int blocked_tiles_per_cu(int levels, int precision, int block, int lanes, bool vc, bool strong) {
+int blocked_tiles_per_cu(int levels, int precision, int block, int lanes, bool vc, bool strong, bool cayley) {
   int per_cu_v = 0;
   int *per_cu = &per_cu_v;
   const ChunkSync cs{nullptr, 0u, 2, 0};
@@ -1252,7 +1265,8 @@ int blocked_tiles_per_cu(int levels, int precision, int block, int lanes, bool v
   const int64_t n0 = 0;
   hipStream_t st = nullptr;
   const hipError_t e =
-      precision == 64 ? launch_blocked_f64p(MB_LAUNCH_PASS) : launch_blocked_f32p(MB_LAUNCH_PASS);
+      cayley ? (precision == 64 ? launch_blocked_f64pc(MB_LAUNCH_PASS) : launch_blocked_f32pc(MB_LAUNCH_PASS))
+             : (precision == 64 ? launch_blocked_f64p(MB_LAUNCH_PASS) : launch_blocked_f32p(MB_LAUNCH_PASS));
   return e == hipSuccess ? per_cu_v : 0;
 }
 

@@ -549,10 +549,6 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
     err = "field_step must be MB_FIELD_EXACT or MB_FIELD_CAYLEY";
     return MB_ERR_ARG;
   }
-  if (scen->field_step == MB_FIELD_CAYLEY && scen->variant == MB_VARIANT_BLOCKED_REGS) {
-    err = "the Cayley field step runs without register coefficients";
-    return MB_ERR_UNSUPPORTED;
-  }
   if (scen->coupling == MB_COUPLING_STRONG && scen->variant == MB_VARIANT_PLAIN) {
     err = "strong coupling runs on the blocked variant";
     return MB_ERR_UNSUPPORTED;

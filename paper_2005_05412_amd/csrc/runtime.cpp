@@ -269,10 +269,6 @@ int Engine::add(SimPlan &&plan, Arena *arena, hipStream_t st, std::string &err) 
     err = "strong coupling runs on the blocked variant";
     return MB_ERR_UNSUPPORTED;
   }
-  if (vc_ && !plain && plan.field_step == MB_FIELD_CAYLEY) {
-    err = "the Cayley field step runs without register coefficients";
-    return MB_ERR_UNSUPPORTED;
-  }
   if (plain && precision_ != 64) {
     err = "the two-launch variant runs in FP64 only";
     return MB_ERR_UNSUPPORTED;
@@ -543,12 +539,11 @@ bool Engine::persist_ok(int k, int64_t reps) {
     live = &g;
   }
   if (!live || live->n_tiles < 1 || !live->d_flags) return false;
-  if (live->cayley) return false;  // the Cayley kernels run one chunk per launch
   const int lanes = group_lanes(*live);
   if (live->occ_block != block_ || live->occ_lanes != lanes) {
     live->occ_block = block_;
     live->occ_lanes = lanes;
-    live->occ_per_cu = blocked_tiles_per_cu(live->levels, precision_, block_, lanes, vc_, live->strong);
+    live->occ_per_cu = blocked_tiles_per_cu(live->levels, precision_, block_, lanes, vc_, live->strong, live->cayley);
   }
   return int64_t(live->n_tiles) <= int64_t(live->occ_per_cu) * n_cu_;
 }

@@ -106,7 +106,7 @@ std::string tune_key(int device, const std::vector<const SimPlan *> &plans, int 
     levels = std::max(levels, p->n);
     cells += uint64_t(p->nx);
     strong = strong || p->coupling == MB_COUPLING_STRONG;
-    cayley = cayley || p->field_step == MB_FIELD_CAYLEY;  // no register-coefficient shapes
+    cayley = cayley || p->field_step == MB_FIELD_CAYLEY;  // kernels of their own
     steps = std::max<uint64_t>(steps, uint64_t(p->n_steps));
   }
   // the step count matters: a short run cannot time the persistent form

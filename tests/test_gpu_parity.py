@@ -317,6 +317,34 @@ def test_server_budget_and_cancel():
     srv.close()
 
 
+def test_degenerate_runs():
+    """No steps, a record period longer than the run, run(0), and such members in a batch:
+    empty records like the oracle's, and the other members unchanged."""
+    p0 = W.random_small(31, N=3, nx=40, n_steps=0)
+    p1 = W.random_small(32, N=2, nx=40, n_steps=5, rec_interval=10)
+    p2 = W.random_small(33, N=3, nx=90, n_steps=40)
+    _say("degenerate")
+    for p in (p0, p1):
+        ref = O.run(p)
+        for precision, variant in ((64, "plain"), (64, "blocked"), (32, "blocked")):
+            got = gpu_run(p, precision=precision, variant=variant)
+            for k in ref:
+                assert got[k].size == 0 and np.asarray(ref[k]).size == 0, k
+    s = mb.Solver(p2, precision=64, variant="blocked", block=128, depth=16)
+    s.run(0)
+    s.run(0)
+    assert s.steps_done == 0
+    s.run()
+    assert_same(s.records(), gpu_run(p2, precision=64, variant="blocked", block=128, depth=16))
+    s.close()
+    b = mb.Batch([p0, p2, p1], precision=32, block=128, depth=16)
+    b.run(use_graph=True)
+    assert_same(b.records(1), gpu_run(p2, precision=32, variant="blocked", block=128, depth=16))
+    for k in (0, 2):
+        assert all(v.size == 0 for v in b.records(k).values())
+    b.close()
+
+
 def test_caller_workspace():
     """mb_setup into caller-owned device memory (hipMalloc'ed here, filled with 0xFF) gives
     the same records as library-allocated memory; a workspace that is too small or
@@ -505,8 +533,8 @@ CAYLEY = [
 def test_cayley_field_step_vs_oracle(case):
     """Field part by the Cayley approximant: FP64 within 1e-10 and FP32 within 1e-4 of the
     oracle's Cayley run (which differs from the exact field step by 1e-7 and more on these
-    cases, so the tolerance tells the two apart); every tile shape the same bits; register
-    coefficients refused; with strong coupling too."""
+    cases, so the tolerance tells the two apart); every tile shape, coefficient placement and
+    launch form the same bits; with strong coupling too."""
     prob = _small(case)
     prob["field_step"] = "cayley"
     _say(f"cayley {prob['name']}")
@@ -520,9 +548,18 @@ def test_cayley_field_step_vs_oracle(case):
     errs32 = rel_errors(prob, got32, ref)
     assert max(errs32.values()) <= TOL[32], errs32
     assert_same(gpu_run(prob, precision=32, variant="blocked", block=64, depth=16, lanes=4), got32)
-    with pytest.raises(mb.MBError) as ex:
-        mb.Solver(prob, precision=32, variant="blocked_regs")
-    assert ex.value.code == -3
+    assert_same(gpu_run(prob, precision=32, variant="blocked_regs", block=128, depth=16), got32)
+    # register coefficients and persistent launches (one wave per 64 cells): the same bits
+    for variant in ("blocked", "blocked_regs"):
+        with _persist(False):
+            ref64 = gpu_run(prob, precision=64, variant=variant, block=64, depth=16)
+        assert_same(ref64, plain)
+        with _persist(True):
+            s = mb.Solver(prob, precision=64, variant=variant, block=64, depth=16, lanes=1)
+            assert s.persistent() == (prob["n_steps"] // 16 >= 2)
+            s.run()
+            assert_same(s.records(), plain)
+            s.close()
     prob["coupling"] = "strong"
     ref = O.run(prob)
     errs = rel_errors(prob, gpu_run(prob, precision=64, variant="blocked", block=128, depth=16), ref)

@@ -152,6 +152,9 @@ def _vac(nx=20, courant=0.5, refl=(0.0, 0.0), levels_qm=None):
 
 def test_status_codes():
     assert mb.plan_status(_vac()) == 0
+    with pytest.raises(mb.MBError) as ex:    # two nodes: edges only, no interior to update
+        mb.plan_status(_vac(nx=2))
+    assert ex.value.code == -1
     with pytest.raises(mb.MBError) as ex:
         mb.plan_status(_vac(courant=1.01))
     assert ex.value.code == -2
@@ -193,9 +196,10 @@ def test_status_codes():
     cay["field_step"] = "cayley"
     assert mb.plan_status(cay) == 0
     assert mb.plan_status(cay, variant="plain") == 0
-    with pytest.raises(mb.MBError) as ex:        # the Cayley phases are not register coefficients
-        mb.plan_status(cay, variant="blocked_regs")
-    assert ex.value.code == -3
+    assert mb.plan_status(cay, variant="blocked_regs") == 0
+    cay["field_step"] = "pade"
+    with pytest.raises(ValueError):
+        mb.plan_status(cay)
 
 
 def test_workspace_bytes():
