@@ -47,6 +47,11 @@ def flops_per_cell_update(n):
     return 8 + 6 * (n * (n - 1) // 2) + 2 * m + 2 * m * m + m
 
 
+def alu_tflops(n, cell_updates, ms):
+    """Algorithmic TFLOP/s of cell_updates N-level cell-updates in ms milliseconds."""
+    return flops_per_cell_update(n) * cell_updates / (ms * 1e-3) / 1e12
+
+
 def bytes_per_cell_update(n, prec):
     """Algorithmic HBM bytes of one cell-update: read and write of E, H and the M density reals."""
     return 2 * (n * n + 1) * (8 if prec == 64 else 4)
@@ -278,6 +283,8 @@ def other_configs(hip, stream, log):
     cells = p["nx"] * p["n_steps"]
     res["lambda3_strong_coupling"] = {"nx": p["nx"], "n_steps": p["n_steps"], "fp32": cells / (ms32 * 1e-3),
                                       "fp64": cells / (ms64 * 1e-3), "unit": "cell-updates/s",
+                                      "fp32_tflops_algorithmic": alu_tflops(3, cells, ms32),
+                                      "fp32_alu_frac": alu_tflops(3, cells, ms32) / PEAK["fp32_tflops"],
                                       "fp32_vs_fp64_max_rel_err": max_error(p, r32, r64),
                                       "shape_fp32": list(sh32)}
     log("[bench] lambda3 with the Cayley field step fp32/fp64")
@@ -288,6 +295,9 @@ def other_configs(hip, stream, log):
     cells = p["nx"] * p["n_steps"]
     res["lambda3_cayley_field_step"] = {"nx": p["nx"], "n_steps": p["n_steps"], "fp32": cells / (ms32 * 1e-3),
                                         "fp64": cells / (ms64 * 1e-3), "unit": "cell-updates/s",
+                                        "fp32_tflops_algorithmic": alu_tflops(3, cells, ms32),
+                                        "fp32_alu_frac": alu_tflops(3, cells, ms32) / PEAK["fp32_tflops"],
+                                        "fp64_alu_frac": alu_tflops(3, cells, ms64) / PEAK["fp64_tflops"],
                                         "fp32_vs_fp64_max_rel_err": max_error(p, r32, r64),
                                         "shape_fp32": list(sh32), "shape_fp64": list(sh64)}
     log("[bench] anharmonic ladder N = 2..6, 8192 cells, 20000 steps, fp32/fp64")
@@ -344,6 +354,8 @@ def main(argv=None):
                     help="comma list of optional legs to run (fp64,cpu,batch,configs,serve); others are skipped")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the 200/s Poisson trace (2000 = the full 10 s trace)")
+    ap.add_argument("--field-step", default="exact", choices=("exact", "cayley"),
+                    help="field part of the density step of the main workload (exact exponential or Cayley)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one device-to-device copy of this size (counter calibration)")
     ap.add_argument("--out", default="")
@@ -362,6 +374,8 @@ def main(argv=None):
     if args.copy_bytes > 0:
         hip.copy_calibration(args.copy_bytes)
     prob = W.lambda3(nx=args.nx, n_steps=args.nt, precision=32)
+    prob["field_step"] = args.field_step
+    wname = "lambda3-3lvl" + ("-cayley" if args.field_step == "cayley" else "")
     n_levels = 3
     cells = prob["nx"] * prob["n_steps"]
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
@@ -395,13 +409,13 @@ def main(argv=None):
         f"(persistent={persistent}), {avg_kernel_us:.2f} us per launch, {chunk_us:.2f} us per {depth}-step chunk")
 
     kname = f"k_blocked<3,float,{block},{lanes},{str(regs).lower()}>"
-    traffic = measured_traffic(kname, f"lambda3-3lvl/nx{prob['nx']}", depth, steps_per_launch)
+    traffic = measured_traffic(kname, f"{wname}/nx{prob['nx']}", depth, steps_per_launch)
     out = {
         "metric": "cell-updates/s (FP64 plain vs FP32 batched) at stated error; p50/p99 solve latency",
         "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "lambda3-3lvl", "nx": prob["nx"], "n_steps": prob["n_steps"], "levels": 3,
+        "config": {"workload": wname, "field_step": args.field_step, "nx": prob["nx"], "n_steps": prob["n_steps"], "levels": 3,
                    "materials": len(prob["materials"]), "records": len(prob["records"]),
                    "variant": "blocked", "block": block, "depth": depth, "regs": regs, "lanes": lanes, "setup_s": t_setup,
                    "step": "one full solve of the workload"},
