@@ -124,6 +124,13 @@ typedef struct mb_qm {
   const double *mu_off;      /* N(N-1)/2 complex (re, im) [C m] */
   const double *rates;       /* N*N, rates[i*N+j] = gamma_ij = rate j -> i [1/s] */
   const double *pure_deph;   /* N(N-1)/2 [1/s] */
+  /* explicit Lindblad operators (eq:lindbladdiss with C diagonalised):
+   * D(rho) = sum_k L_k rho L_k^+ - 1/2 {L_k^+ L_k, rho}.  n_lindblad > 0
+   * replaces rates and pure_deph (which may then be NULL); lindblad_ops holds
+   * n_lindblad matrices of N*N complex (re, im) entries, row-major, in
+   * sqrt(1/s).  At most 64 operators. */
+  int32_t n_lindblad;
+  const double *lindblad_ops;
   /* two-level form (Sec. 3.1.1, qm_desc_2lvl): H0 = hbar w21/2 diag(-1, 1),
    * mu = -e z21 sigma_x, gamma_12 = g1 (1-w0)/2, gamma_21 = g1 (1+w0)/2,
    * gamma_12,p = g2 - g1/2 */

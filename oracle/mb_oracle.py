@@ -15,7 +15,9 @@ What it computes (paper sections cited per function):
   relation alpha0 = sqrt(mu/eps) sigma / 2 (Sec. 3.1.1).
 * The master equation eq:master1D with H = H0 - mu E and the relaxation
   superoperator given by scattering rates and pure dephasing rates
-  (eq:relax_pop and the dephasing equation, Sec. 3.1.1).
+  (eq:relax_pop and the dephasing equation, Sec. 3.1.1), or by explicit
+  Lindblad operators (eq:lindbladdiss with the coefficient matrix
+  diagonalised) when a quantum description lists ``lindblad_ops``.
 * Weak coupling in time (Sec. 2.2, Fig. 1): rho lives at t_{n+1/2} at the
   E nodes.  The density step exp(L dt) is approximated by an operator
   splitting (Sec. 2.2, "exact step + operator splitting" family); the
@@ -140,9 +142,11 @@ def dissipator(rho, rates, deph):
     return out
 
 
-def free_generator(rho, h0, rates, deph, hbar):
-    """L0(rho) = -i/hbar [H0, rho] + D(rho)  (eq:master1D without the field)."""
-    return -1j / hbar * (h0 @ rho - rho @ h0) + dissipator(rho, rates, deph)
+def free_generator(rho, h0, rates, deph, hbar, ops=None):
+    """L0(rho) = -i/hbar [H0, rho] + D(rho)  (eq:master1D without the field); D in rate
+    form, or from explicit Lindblad operators when ops is given."""
+    d = dissipator(rho, rates, deph) if ops is None else lindblad_dissipator(rho, ops)
+    return -1j / hbar * (h0 @ rho - rho @ h0) + d
 
 
 def field_generator(rho, mu, e_field, hbar):
@@ -300,7 +304,9 @@ class Oracle:
             assert n_lv in (None, n)
             n_lv = n
             hbar = c["hbar"]
-            l0 = superoperator(lambda r: free_generator(r, h0, rates, deph, hbar), n)
+            ops = m["qm"].get("lindblad_ops")
+            ops = None if ops is None or len(ops) == 0 else [np.asarray(o, complex) for o in ops]
+            l0 = superoperator(lambda r: free_generator(r, h0, rates, deph, hbar, ops), n)
             p_half = sla.expm(l0 * (self.dt / 2.0))
             lam, vec = np.linalg.eigh(mu)
             self.groups.append(dict(cells=cells, n=n, h0=h0, mu=mu, rates=rates, deph=deph,

@@ -55,6 +55,7 @@ class mb_qm(C.Structure):
                 ("h0_diag", C.POINTER(C.c_double)), ("h0_off", C.POINTER(C.c_double)),
                 ("mu_diag", C.POINTER(C.c_double)), ("mu_off", C.POINTER(C.c_double)),
                 ("rates", C.POINTER(C.c_double)), ("pure_deph", C.POINTER(C.c_double)),
+                ("n_lindblad", C.c_int32), ("lindblad_ops", C.POINTER(C.c_double)),
                 ("omega21", C.c_double), ("z21", C.c_double), ("gamma1", C.c_double),
                 ("gamma2", C.c_double), ("w0", C.c_double)]
 
@@ -220,6 +221,11 @@ class _Marshal:
                 s.mu_off = arr(_complex_pairs(q["mu_off"]))
                 s.rates = arr(np.asarray(q["rates"], float).reshape(-1))
                 s.pure_deph = arr(q["pure_deph"])
+                ops = q.get("lindblad_ops")
+                if ops is not None and len(ops):
+                    flat = np.asarray(ops, complex).reshape(len(ops), -1)
+                    s.n_lindblad = len(ops)
+                    s.lindblad_ops = arr(_complex_pairs(flat.reshape(-1)))
             qms.append(s)
             mats[k].qm = C.pointer(s)
         keep.extend([mats, qms])

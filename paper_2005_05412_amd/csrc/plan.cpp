@@ -163,6 +163,7 @@ struct QmFull {
   std::vector<cd> h0, mu;     // N x N row-major
   std::vector<double> rates;  // N x N, rates[i*N+j] = gamma_ij (j -> i)
   std::vector<double> deph;   // packed pairs
+  std::vector<std::vector<cd>> ops;  // explicit Lindblad operators (replace rates, deph)
 };
 
 // packed index of the pair (i, j), i < j, in column order
@@ -190,8 +191,8 @@ int describe(const mb_qm &q, const mb_consts &k, QmFull &out, std::string &err) 
   out.n = n;
   out.n3d = q.n3d;
   if (q.two_level) {
-    if (n != 2) {
-      err = "two-level form needs levels == 2";
+    if (n != 2 || q.n_lindblad != 0) {
+      err = "two-level form needs levels == 2 and no Lindblad operators";
       return MB_ERR_ARG;
     }
     // Sec. 3.1.1: H0 = hbar w21/2 diag(-1, 1), mu = -e z21 sigma_x
@@ -203,12 +204,35 @@ int describe(const mb_qm &q, const mb_consts &k, QmFull &out, std::string &err) 
     out.deph = {q.gamma2 - q.gamma1 / 2.0};
     return MB_OK;
   }
-  if (!q.h0_diag || !q.rates || !q.pure_deph) {
-    err = "general quantum description needs h0_diag, rates and pure_deph";
+  if (q.n_lindblad < 0 || q.n_lindblad > kMaxLindbladOps || (q.n_lindblad > 0 && !q.lindblad_ops)) {
+    err = "n_lindblad must be 0..64, with lindblad_ops when positive";
+    return MB_ERR_ARG;
+  }
+  if (!q.h0_diag || (q.n_lindblad == 0 && (!q.rates || !q.pure_deph))) {
+    err = "general quantum description needs h0_diag, and rates and pure_deph or Lindblad operators";
     return MB_ERR_ARG;
   }
   out.h0 = unpack(n, q.h0_diag, q.h0_off);
   out.mu = unpack(n, q.mu_diag, q.mu_off);
+  if (q.n_lindblad > 0) {
+    // the operators replace the rate form: rates and dephasing stay zero
+    out.rates.assign(size_t(n) * n, 0.0);
+    out.deph.assign(pair_count(n), 0.0);
+    for (int k = 0; k < q.n_lindblad; ++k) {
+      std::vector<cd> op(size_t(n) * n);
+      for (int e = 0; e < n * n; ++e) {
+        const double re = q.lindblad_ops[2 * (size_t(k) * n * n + e)];
+        const double im = q.lindblad_ops[2 * (size_t(k) * n * n + e) + 1];
+        if (!std::isfinite(re) || !std::isfinite(im)) {
+          err = "Lindblad operators must be finite";
+          return MB_ERR_ARG;
+        }
+        op[e] = cd(re, im);
+      }
+      out.ops.push_back(std::move(op));
+    }
+    return MB_OK;
+  }
   out.rates.assign(q.rates, q.rates + n * n);
   for (int i = 0; i < n; ++i) out.rates[i * n + i] = 0.0;
   out.deph.assign(q.pure_deph, q.pure_deph + pair_count(n));
@@ -221,7 +245,8 @@ int describe(const mb_qm &q, const mb_consts &k, QmFull &out, std::string &err) 
 }
 
 // L0(rho) = -i/hbar [H0, rho] + D(rho), D in rate form (eq:relax_pop and the
-// dephasing law, Sec. 3.1.1).  All matrices N x N row-major, original basis.
+// dephasing law, Sec. 3.1.1) or from explicit Lindblad operators
+// (eq:lindbladdiss).  All matrices N x N row-major, original basis.
 void apply_free(const QmFull &q, double hbar, const std::vector<cd> &rho, std::vector<cd> &out) {
   int n = q.n;
   out.assign(size_t(n) * n, cd(0, 0));
@@ -233,6 +258,32 @@ void apply_free(const QmFull &q, double hbar, const std::vector<cd> &rho, std::v
         acc += q.h0[size_t(i) * n + k] * rho[size_t(k) * n + j] - rho[size_t(i) * n + k] * q.h0[size_t(k) * n + j];
       out[size_t(i) * n + j] = mi * acc;
     }
+  if (!q.ops.empty()) {
+    // L rho L^+ - 1/2 (L^+ L rho + rho L^+ L), one operator at a time
+    std::vector<cd> lr(size_t(n) * n), ll(size_t(n) * n);
+    for (const auto &op : q.ops) {
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+          cd a(0, 0), b(0, 0);
+          for (int k = 0; k < n; ++k) {
+            a += op[size_t(i) * n + k] * rho[size_t(k) * n + j];               // (L rho)_ij
+            b += std::conj(op[size_t(k) * n + i]) * op[size_t(k) * n + j];     // (L^+ L)_ij
+          }
+          lr[size_t(i) * n + j] = a;
+          ll[size_t(i) * n + j] = b;
+        }
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+          cd acc(0, 0);
+          for (int k = 0; k < n; ++k) {
+            acc += lr[size_t(i) * n + k] * std::conj(op[size_t(j) * n + k]);   // (L rho L^+)_ij
+            acc -= 0.5 * (ll[size_t(i) * n + k] * rho[size_t(k) * n + j] + rho[size_t(i) * n + k] * ll[size_t(k) * n + j]);
+          }
+          out[size_t(i) * n + j] += acc;
+        }
+    }
+    return;
+  }
   std::vector<double> out_rate(n, 0.0);  // 1/tau_j = sum_{i != j} gamma_ij
   for (int j = 0; j < n; ++j)
     for (int i = 0; i < n; ++i)

@@ -14,6 +14,7 @@ namespace mb {
 using cd = std::complex<double>;
 
 constexpr int kMaxLevels = 6;
+constexpr int kMaxLindbladOps = 64;
 
 // Real parametrisation of an N x N Hermitian density matrix written in the
 // eigen-basis of the dipole operator: populations 0..N-2 (the last one is

@@ -317,6 +317,26 @@ def test_server_budget_and_cancel():
     srv.close()
 
 
+@pytest.mark.parametrize("n,seed", [(2, 71), (3, 72), (5, 73)])
+def test_explicit_lindblad_ops_vs_oracle(n, seed):
+    """Materials described by explicit Lindblad operators (eq:lindbladdiss) instead of rates:
+    FP64 within 1e-10 and FP32 within 1e-4 of the oracle; blocked == two-launch bitwise."""
+    prob = W.random_small(seed, N=n, nx=70, n_steps=60, refl=(0.0, 1.0))
+    rng = np.random.default_rng(seed)
+    for m in prob["materials"]:
+        if m["qm"] is not None:
+            m["qm"] = dict(m["qm"], lindblad_ops=[(rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n)))
+                                                  * np.sqrt(1e12 / n) for _ in range(3)])
+    _say(f"lindblad ops {prob['name']}")
+    ref = O.run(prob)
+    plain = gpu_run(prob, precision=64, variant="plain")
+    errs = rel_errors(prob, plain, ref)
+    assert max(errs.values()) <= TOL[64], errs
+    assert_same(gpu_run(prob, precision=64, variant="blocked", block=128, depth=16), plain)
+    errs32 = rel_errors(prob, gpu_run(prob, precision=32, variant="blocked", block=64, depth=16), ref)
+    assert max(errs32.values()) <= TOL[32], errs32
+
+
 def test_degenerate_runs():
     """No steps, a record period longer than the run, run(0), and such members in a batch:
     empty records like the oracle's, and the other members unchanged."""

@@ -79,10 +79,18 @@ def _rotate(y, e, kappa, n):
     return y
 
 
-@pytest.mark.parametrize("n,seed", [(2, 1), (3, 2), (4, 3), (5, 4), (6, 5)])
-def test_plan_tables_reproduce_oracle_single_point(n, seed):
+def _random_ops(rng, n, k=3, rate=1e12):
+    """k random complex N x N Lindblad operators of size ~ sqrt(rate)."""
+    return [(rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))) * np.sqrt(rate / n) for _ in range(k)]
+
+
+@pytest.mark.parametrize("n,seed,ops", [(2, 1, False), (3, 2, False), (4, 3, False), (5, 4, False), (6, 5, False),
+                                        (3, 6, True), (5, 7, True)])
+def test_plan_tables_reproduce_oracle_single_point(n, seed, ops):
     rng = np.random.default_rng(seed)
     qm = W.random_qm(rng, n, dipole=3e-29)
+    if ops:                                  # explicit Lindblad operators replace the rates
+        qm["lindblad_ops"] = _random_ops(rng, n)
     rd, ro = W.random_rho(rng, n)
     src = W.source("sech", 0, 3e9, 2e14, 5.0, 1.0 / 15e-15, phase=0.4)
     dt, nt = 2e-17, 600

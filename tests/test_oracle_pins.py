@@ -591,3 +591,63 @@ def test_p11_sit_listing_pulse_area_is_two_pi():
     assert abs(area / (2 * math.pi) - 1.0) < 1e-3
     # the envelope peaks at t = shift / width = 50 fs, as in the Song listing (49 fs)
     assert abs(t[np.argmax(env)] - 50e-15) < 1e-17
+
+
+# ---------------------------------------------------------------- explicit Lindblad operators
+
+def test_explicit_lindblad_ops_closed_form():
+    """Decay L1 = sqrt(g)|0><1| and dephasing L2 = sqrt(k)|1><1| (eq:lindbladdiss) on a
+    single point without field: rho_11 = rho_11(0) e^{-g t} and
+    rho_01 = rho_01(0) e^{(i w - (g + k)/2) t} for H0 = diag(0, hbar w)."""
+    hbar = C["hbar"]
+    w, g, k = 2 * np.pi * 1e13, 1.0e12, 2.5e12
+    qm = W.general_qm(1e24, [0.0, hbar * w], None, None, np.array([1e-29]), np.zeros((2, 2)), [0.0])
+    l1 = np.zeros((2, 2), complex)
+    l1[0, 1] = np.sqrt(g)
+    l2 = np.zeros((2, 2), complex)
+    l2[1, 1] = np.sqrt(k)
+    qm["lindblad_ops"] = [l1, l2]
+    rho01 = 0.3 + 0.1j
+    dt, steps = 1e-15, 500
+    prob = W.make_problem("lops", 0.0, [W.qm_material(qm)], [(0.0, 0.0, 0)], 1, dt, steps,
+                          [0.4, 0.6], [rho01])
+    orc = O.Oracle(prob)
+    for n in range(1, steps + 1):
+        orc.step()
+        if n % 100:
+            continue
+        rho = orc.density_at(0)
+        t = n * dt
+        assert abs(rho[1, 1].real - 0.6 * np.exp(-g * t)) < 1e-12
+        assert abs(rho[0, 0].real - (1.0 - 0.6 * np.exp(-g * t))) < 1e-12
+        assert abs(rho[0, 1] - rho01 * np.exp((1j * w - 0.5 * (g + k)) * t)) < 1e-12
+    # and the rate form with the same physics: gamma_01 = g, no rate 0 -> 1, and the
+    # coherence decay (g + k)/2 = g/2 + gamma_p gives gamma_p = k/2
+    qr = W.general_qm(1e24, [0.0, hbar * w], None, None, np.array([1e-29]),
+                      np.array([[0.0, g], [0.0, 0.0]]), [k / 2])
+    pr = W.make_problem("rates", 0.0, [W.qm_material(qr)], [(0.0, 0.0, 0)], 1, dt, steps,
+                        [0.4, 0.6], [rho01])
+    o2 = O.Oracle(pr)
+    for _ in range(steps):
+        o2.step()
+    assert np.max(np.abs(o2.density_at(0) - orc.density_at(0))) < 1e-12
+
+
+@pytest.mark.parametrize("n,seed", [(3, 61), (4, 62)])
+def test_explicit_lindblad_ops_equal_rate_form(n, seed):
+    """The rate-form dissipator (eq:relax_pop and the dephasing law) and the operator form
+    (eq:lindbladdiss) with the equivalent jump and dephasing operators give the same run
+    of a driven device (fields, populations, coherences)."""
+    prob = W.random_small(seed, N=n, nx=30, n_steps=80, n_materials=1)
+    qm = prob["materials"][1]["qm"]
+    ops, lam_min = O.lindblad_from_rates(np.asarray(qm["rates"]), np.asarray(qm["pure_deph"]))
+    assert lam_min >= -1e-9 * np.abs(qm["pure_deph"]).max()     # completely positive case
+    ref = O.run(prob)
+    qm2 = dict(qm)
+    qm2["lindblad_ops"] = ops
+    prob2 = dict(prob)
+    prob2["materials"] = [prob["materials"][0], dict(prob["materials"][1], qm=qm2)]
+    got = O.run(prob2)
+    for key in ref:
+        scale = max(1e-30, np.abs(ref[key]).max())
+        assert np.max(np.abs(np.asarray(got[key]) - np.asarray(ref[key]))) <= 1e-10 * scale, key
