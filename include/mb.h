@@ -88,6 +88,7 @@ extern "C" {
 #define MB_SRC_SECH 0   /* s(t) = amp sech(width t' - shift) sin(2 pi freq t + phase) */
 #define MB_SRC_GAUSS 1  /* s(t) = amp exp(-(width t' - shift)^2) sin(2 pi freq t + phase) */
                         /* t' = t - q period, summed over q = 0..count-1 */
+#define MB_SRC_TABLE 2  /* s(t_n) = table[n] for n < table_len, 0 after (sampled waveform) */
 
 #define MB_REC_E 0       /* E at the cell                    */
 #define MB_REC_H 1       /* H at x_{cell+1/2} (0 at the last cell) */
@@ -164,6 +165,8 @@ typedef struct mb_source {
   int64_t cell;
   double amp, freq, shift, width, phase, period;
   int32_t count;             /* pulses in the train (>= 1) */
+  const double *table;       /* MB_SRC_TABLE: values at t_n = n dt, n = 0..table_len-1 */
+  int64_t table_len;         /* (copied at setup; ignored by the other kinds) */
 } mb_source;
 
 typedef struct mb_record {

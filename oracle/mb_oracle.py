@@ -230,8 +230,11 @@ def light_speed(mat, consts):
     return 1.0 / math.sqrt(consts["eps0"] * mat["eps_r"] * consts["mu0"] * mat["mu_r"])
 
 
-def source_value(src, t):
-    """Source waveform at time t (sech or Gaussian envelope times a carrier)."""
+def source_value(src, t, n=None):
+    """Source value at time t = n dt: sech or Gaussian envelope times a carrier, or the
+    n-th sample of a sampled waveform (zero after its end; needs n)."""
+    if src["kind"] == "table":
+        return float(src["table"][n]) if n < len(src["table"]) else 0.0
     env = 0.0
     for q in range(max(1, src["count"])):
         arg = src["width"] * (t - q * src["period"]) - src["shift"]
@@ -322,7 +325,7 @@ class Oracle:
             g["rho"] = np.repeat(rho0[None, :, :], len(g["cells"]), axis=0).copy()
         self.step_index = 0
         self._apply_edges_init()
-        self._apply_sources(0.0, init=True)
+        self._apply_sources(0, init=True)
         self.records = {r["name"]: [] for r in prob["records"]}
 
     # -- boundary handling --------------------------------------------------
@@ -355,9 +358,9 @@ class Oracle:
         if self.p["refl"][1] == 1.0:
             self.e[-1] = 0.0
 
-    def _apply_sources(self, t, init=False):
+    def _apply_sources(self, n, init=False):
         for s in self.p["sources"]:
-            v = source_value(s, t)
+            v = source_value(s, n * self.dt, n)
             if s["hard"]:
                 self.e[s["cell"]] = v
             elif not init:
@@ -422,7 +425,7 @@ class Oracle:
             self.e[m] = (self.ca[m] * e_old[m] - self.cb[m] * self.gam[m] * self.p_cur[m]
                          + self.cb[m] / self.dx * (self.h[1:] - self.h[:-1]))
             self._edges(e_old)
-        self._apply_sources((n + 1) * self.dt)
+        self._apply_sources(n + 1)
         self.step_index = n + 1
         self._record(n)
 
@@ -474,7 +477,7 @@ class Oracle:
             self._edges(e_old)
         else:
             self.e = e_old.copy()
-        self._apply_sources((n + 1) * self.dt)
+        self._apply_sources(n + 1)
         self.p_cur[:] = 0.0
         for g in self.groups:
             rho_n = g["rho"]

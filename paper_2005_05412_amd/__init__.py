@@ -23,7 +23,7 @@ MB_WARN_NOT_CP = 1
 ERRORS = {-1: "MB_ERR_ARG", -2: "MB_ERR_CFL", -3: "MB_ERR_UNSUPPORTED", -4: "MB_ERR_OOM",
           -5: "MB_ERR_BUDGET", -6: "MB_ERR_HIP", -7: "MB_ERR_NONFINITE", -8: "MB_ERR_STATE",
           -9: "MB_ERR_DEVICE"}
-SRC_KIND = {"sech": 0, "gauss": 1}
+SRC_KIND = {"sech": 0, "gauss": 1, "table": 2}
 REC_KIND = {"e": 0, "h": 1, "pop": 2, "inv": 3, "rho_re": 4, "rho_im": 5}
 VARIANT = {"auto": 0, "plain": 1, "blocked": 2, "blocked_regs": 3}
 FIELD_STEP = {"exact": 0, "cayley": 1}    # MB_FIELD_EXACT, MB_FIELD_CAYLEY
@@ -78,7 +78,8 @@ class mb_device_desc(C.Structure):
 class mb_source(C.Structure):
     _fields_ = [("kind", C.c_int32), ("hard", C.c_int32), ("cell", C.c_int64), ("amp", C.c_double),
                 ("freq", C.c_double), ("shift", C.c_double), ("width", C.c_double),
-                ("phase", C.c_double), ("period", C.c_double), ("count", C.c_int32)]
+                ("phase", C.c_double), ("period", C.c_double), ("count", C.c_int32),
+                ("table", C.POINTER(C.c_double)), ("table_len", C.c_int64)]
 
 
 class mb_record(C.Structure):
@@ -244,6 +245,9 @@ class _Marshal:
             srcs[k].amp, srcs[k].freq, srcs[k].shift = s["amp"], s["freq"], s["shift"]
             srcs[k].width, srcs[k].phase, srcs[k].period, srcs[k].count = (s["width"], s["phase"],
                                                                           s["period"], s["count"])
+            if s["kind"] == "table":
+                srcs[k].table = arr(np.asarray(s["table"], float))
+                srcs[k].table_len = len(s["table"])
         recs = (mb_record * max(1, len(prob["records"])))()
         for k, r in enumerate(prob["records"]):
             recs[k].quantity, recs[k].i, recs[k].j = REC_KIND[r["quantity"]], r["i"], r["j"]

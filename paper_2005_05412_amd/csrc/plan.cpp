@@ -728,15 +728,27 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
   }
   for (int s = 0; s < scen->n_sources; ++s) {
     const mb_source &src = scen->sources[s];
-    if (src.cell < 0 || src.cell >= nx || (src.kind != MB_SRC_SECH && src.kind != MB_SRC_GAUSS)) {
+    if (src.cell < 0 || src.cell >= nx ||
+        (src.kind != MB_SRC_SECH && src.kind != MB_SRC_GAUSS && src.kind != MB_SRC_TABLE)) {
       err = "source outside the grid or of unknown kind";
+      return MB_ERR_ARG;
+    }
+    if (src.kind == MB_SRC_TABLE && (src.table_len < 0 || (src.table_len > 0 && !src.table))) {
+      err = "table source needs table_len >= 0 values";
       return MB_ERR_ARG;
     }
     SourcePlan sp;
     sp.cell = src.cell;
     sp.hard = src.hard ? 1 : 0;
     sp.table.resize(plan.n_steps + 1);
-    for (int64_t t = 0; t <= plan.n_steps; ++t) sp.table[t] = source_value(src, double(t) * plan.dt);
+    for (int64_t t = 0; t <= plan.n_steps; ++t)
+      sp.table[t] = src.kind == MB_SRC_TABLE ? (t < src.table_len ? src.table[t] : 0.0)
+                                             : source_value(src, double(t) * plan.dt);
+    for (double v : sp.table)
+      if (!std::isfinite(v)) {
+        err = "source values must be finite";
+        return MB_ERR_ARG;
+      }
     plan.sources.push_back(std::move(sp));
   }
   // records

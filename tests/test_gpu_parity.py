@@ -337,6 +337,24 @@ def test_explicit_lindblad_ops_vs_oracle(n, seed):
     assert max(errs32.values()) <= TOL[32], errs32
 
 
+def test_table_sources_vs_oracle():
+    """Sampled-waveform sources (a hard one shorter than the run and a soft one) drive a
+    random three-level device: FP64 within 1e-10 and FP32 within 1e-4 of the oracle."""
+    prob = W.random_small(81, N=3, nx=90, n_steps=120, refl=(0.0, 1.0))
+    rng = np.random.default_rng(81)
+    amp = max(abs(s["amp"]) for s in prob["sources"]) if prob["sources"] else 1e9
+    prob["sources"] = [W.table_source(0, amp * np.sin(0.3 * np.arange(80)) * np.exp(-np.arange(80) / 40.0)),
+                       W.table_source(45, 0.1 * amp * rng.normal(size=121), hard=False)]
+    _say("table sources")
+    ref = O.run(prob)
+    plain = gpu_run(prob, precision=64, variant="plain")
+    errs = rel_errors(prob, plain, ref)
+    assert max(errs.values()) <= TOL[64], errs
+    assert_same(gpu_run(prob, precision=64, variant="blocked", block=128, depth=16), plain)
+    errs32 = rel_errors(prob, gpu_run(prob, precision=32, variant="blocked", block=128, depth=16), ref)
+    assert max(errs32.values()) <= TOL[32], errs32
+
+
 def test_degenerate_runs():
     """No steps, a record period longer than the run, run(0), and such members in a batch:
     empty records like the oracle's, and the other members unchanged."""

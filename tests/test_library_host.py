@@ -184,6 +184,14 @@ def test_status_codes():
     bad["sources"] = [W.source("sech", 99, 1.0, 1e14, 1.0, 1e14)]
     with pytest.raises(mb.MBError):
         mb.plan_status(bad)
+    bad = _vac()
+    bad["sources"] = [W.table_source(3, [0.0, np.nan, 1.0])]
+    with pytest.raises(mb.MBError) as ex:
+        mb.plan_status(bad)
+    assert ex.value.code == -1
+    ok = _vac()
+    ok["sources"] = [W.table_source(3, [0.0, 0.5, 1.0]), W.table_source(4, [], hard=False)]
+    assert mb.plan_status(ok) == 0
     # waves per 64 cells: 0 (default), 1, 2, 4 or 8
     for lanes in (0, 1, 2, 4, 8):
         assert mb.plan_status(_vac(), lanes=lanes) == 0

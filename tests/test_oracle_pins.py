@@ -270,6 +270,28 @@ def test_p7_magic_time_step_shifts_one_cell():
         assert np.max(np.abs(recs["e"][n - 1] - f(x - n))) < 1e-12
 
 
+def test_p7_table_source_is_translated_one_cell_per_step():
+    """A hard sampled-waveform source (table[n] at t_n = n dt) at cell 0 of a vacuum grid
+    at C = 1: the discrete wave equation is exact there, so E_m^n = table[n - m] (zero
+    outside the table)."""
+    rng = np.random.default_rng(3)
+    vals = rng.normal(size=40)
+    nx, steps = 120, 70
+    prob = _vacuum_problem(nx, 1.0, steps, refl=(0.0, 0.0), records=[W.record("e", "e", -1, 1)],
+                           sources=[W.table_source(0, vals)])
+    recs = O.run(prob)
+    for n in (1, 25, 39, 55, 70):
+        want = np.array([vals[n - m] if 0 <= n - m < len(vals) else 0.0 for m in range(nx)])
+        assert np.max(np.abs(recs["e"][n - 1] - want)) < 1e-12, n
+    # a table holding an analytic waveform's samples gives that waveform's run exactly
+    src = W.source("gauss", 0, 1.0, 3e13, 4.0, 1.0 / 20e-15)
+    p1 = _vacuum_problem(nx, 0.9, steps, refl=(0.0, 0.0), records=[W.record("e", "e", -1, 1)], sources=[src])
+    samples = [O.source_value(src, n * p1["dt"]) for n in range(steps + 1)]
+    p2 = _vacuum_problem(nx, 0.9, steps, refl=(0.0, 0.0), records=[W.record("e", "e", -1, 1)],
+                         sources=[W.table_source(0, samples)])
+    assert np.array_equal(O.run(p1)["e"], O.run(p2)["e"])
+
+
 # ---------------------------------------------------------------- P8 loss
 
 def test_p8_lossy_background_field_decay():

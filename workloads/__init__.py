@@ -115,6 +115,13 @@ def source(kind, cell, amp, freq, shift, width, phase=0.0, hard=True, period=0.0
             "phase": float(phase), "period": float(period), "count": int(count)}
 
 
+def table_source(cell, values, hard=True):
+    """Sampled waveform: values[n] at t_n = n dt, zero after the table."""
+    s = source("table", cell, 0.0, 0.0, 0.0, 0.0, hard=hard)
+    s["table"] = np.asarray(values, float)
+    return s
+
+
 def record(name, quantity, cell, interval, i=0, j=0):
     assert quantity in QUANTITIES
     return {"name": name, "quantity": quantity, "cell": int(cell),
