@@ -355,6 +355,26 @@ def test_table_sources_vs_oracle():
     assert max(errs32.values()) <= TOL[32], errs32
 
 
+@pytest.mark.parametrize("noise,precision", [(5e11, 64), (3e10, 32)])
+def test_large_field_phases_vs_oracle(noise, precision):
+    """Field phases far beyond the series range (up to ~12 rad per step in FP64, ~0.7 in
+    FP32, past both precisions' series limits) take the range-reduced path: FP64 within
+    1e-10, FP32 within 1e-4 of the oracle; FP64 blocked == two-launch bitwise."""
+    prob = W.random_small(91, N=3, nx=50, n_steps=40, e_noise=noise, refl=(1.0, 1.0))
+    kap = max(np.abs(mb.plan_material(prob, k)["kappa"]).max() for k in (1, 2))
+    angle = kap * np.abs(prob["e_init"]).max()
+    assert angle > (3.0 if precision == 64 else 0.5), angle
+    _say(f"large phases {precision}: {angle:.2f} rad")
+    ref = O.run(prob)
+    if precision == 64:
+        got = gpu_run(prob, precision=64, variant="plain")
+        assert_same(gpu_run(prob, precision=64, variant="blocked", block=64, depth=8), got)
+    else:
+        got = gpu_run(prob, precision=32, variant="blocked", block=64, depth=8)
+    errs = rel_errors(prob, got, ref)
+    assert max(errs.values()) <= TOL[precision], errs
+
+
 def test_degenerate_runs():
     """No steps, a record period longer than the run, run(0), and such members in a batch:
     empty records like the oracle's, and the other members unchanged."""
