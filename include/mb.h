@@ -198,12 +198,18 @@ typedef struct mb_scenario_desc {
                                 density step (see below) */
   const double *rho_diag;    /* N reals: initial density matrix (ic_density_const) */
   const double *rho_off;     /* N(N-1)/2 complex (re, im) */
-  const double *e_init;      /* nx initial E values, or NULL for zero */
+  const double *e_init;      /* nx initial E values, or NULL: e_const + e_noise (2 u_m - 1) */
   int32_t n_sources;
   const mb_source *sources;
   int32_t n_records;
   const mb_record *records;
   mb_consts consts;
+  /* initial field without e_init (ic_field_const / ic_field_random):
+   * E_m = e_const + e_noise (2 u_m - 1), u_m = the (m+1)-th output z of
+   * SplitMix64 seeded with e_seed, as (z >> 11) 2^-53 in [0, 1) (e_noise = 0:
+   * no draws).  Edge and hard-source cells are then set as with e_init. */
+  double e_const, e_noise;
+  uint64_t e_seed;
 } mb_scenario_desc;
 
 typedef struct mb_handle mb_handle;

@@ -100,7 +100,8 @@ class mb_scenario_desc(C.Structure):
                 ("rho_diag", C.POINTER(C.c_double)),
                 ("rho_off", C.POINTER(C.c_double)), ("e_init", C.POINTER(C.c_double)),
                 ("n_sources", C.c_int32), ("sources", C.POINTER(mb_source)),
-                ("n_records", C.c_int32), ("records", C.POINTER(mb_record)), ("consts", mb_consts)]
+                ("n_records", C.c_int32), ("records", C.POINTER(mb_record)), ("consts", mb_consts),
+                ("e_const", C.c_double), ("e_noise", C.c_double), ("e_seed", C.c_uint64)]
 
 
 _lib = None
@@ -266,6 +267,9 @@ class _Marshal:
         sc.rho_diag = arr(prob["rho_diag"])
         sc.rho_off = arr(_complex_pairs(prob["rho_off"])) if len(prob["rho_off"]) else arr(np.zeros(1))
         sc.e_init = None if prob["e_init"] is None else arr(prob["e_init"])
+        # without an array: constant plus seeded noise drawn by the library
+        ef = prob.get("e_field") or {}
+        sc.e_const, sc.e_noise, sc.e_seed = ef.get("const", 0.0), ef.get("noise", 0.0), ef.get("seed", 0)
         sc.n_sources, sc.sources = len(prob["sources"]), srcs
         sc.n_records, sc.records = len(prob["records"]), recs
         cs = prob["consts"]

@@ -790,8 +790,30 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
   }
   // initial state: E^0 (edges, hard sources at t = 0), sigma_0 = e^{L0 dt/2} rho_init
   plan.e0.assign(nx, 0.0);
-  if (scen->e_init)
+  if (!std::isfinite(scen->e_const) || !std::isfinite(scen->e_noise)) {
+    err = "e_const and e_noise must be finite";
+    return MB_ERR_ARG;
+  }
+  if (scen->e_init) {
     for (int64_t c = 0; c < nx; ++c) plan.e0[c] = scen->e_init[c];
+  } else {
+    // SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): a Weyl sequence with
+    // increment 0x9E3779B97F4A7C15 passed through a 64-bit finaliser
+    uint64_t state = scen->e_seed;
+    for (int64_t c = 0; c < nx; ++c) {
+      double v = scen->e_const;
+      if (scen->e_noise != 0.0) {
+        state += 0x9E3779B97F4A7C15ull;
+        uint64_t z = state;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        const double u = double(z >> 11) * 0x1.0p-53;
+        v += scen->e_noise * (2.0 * u - 1.0);
+      }
+      plan.e0[c] = v;
+    }
+  }
   if (nx > 1) {
     if (plan.edge_l == 0) plan.e0[0] = 0.0;
     if (plan.edge_r == 0) plan.e0[nx - 1] = 0.0;

@@ -375,6 +375,27 @@ def test_large_field_phases_vs_oracle(noise, precision):
     assert max(errs.values()) <= TOL[precision], errs
 
 
+def test_library_drawn_initial_field():
+    """Without an e_init array the library draws E_m = c + A (2 u_m - 1) from SplitMix64
+    itself: the same initial field and the same run, bit for bit, as the array drawn by the
+    input generator (an independent SplitMix64)."""
+    base = W.random_small(95, N=3, nx=80, n_steps=50, refl=(0.0, 1.0))
+    spec = {"const": 2e6, "noise": 3e8, "seed": 12345}
+    lib = dict(base, e_init=None, e_field=spec)
+    arr = dict(base, e_init=spec["const"] + spec["noise"] * (2.0 * W.splitmix64_uniform(spec["seed"], 80) - 1.0))
+    _say("library-drawn initial field")
+    for precision, variant in ((64, "plain"), (32, "blocked")):
+        shape = dict(block=64, depth=16) if variant == "blocked" else {}
+        a = mb.Solver(lib, precision=precision, variant=variant, **shape)
+        b = mb.Solver(arr, precision=precision, variant=variant, **shape)
+        assert np.array_equal(a.state(3)[0], b.state(3)[0])
+        a.run()
+        b.run()
+        assert_same(a.records(), b.records())
+        a.close()
+        b.close()
+
+
 def test_degenerate_runs():
     """No steps, a record period longer than the run, run(0), and such members in a batch:
     empty records like the oracle's, and the other members unchanged."""

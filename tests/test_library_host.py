@@ -242,3 +242,12 @@ def test_non_completely_positive_dephasing_warns():
     ok = W.general_qm(1e24, [0.0, 0.1 * C["e"], 0.2 * C["e"]], None, None,
                       np.array([1e-29, 1e-29, 0.0]), np.zeros((3, 3)), [1e12, 1e12, 1e12])
     assert mb.plan_status(_vac(levels_qm=ok)) == 0
+
+
+def test_splitmix64_published_outputs():
+    """The seeded generator the inputs are drawn from is SplitMix64: for seed 0 its first
+    outputs are 0xe220a8397b1dcdaf, 0x6e789e6aa1b965f4, 0x06c45d188009454f (the published
+    reference sequence), mapped to [0, 1) by their top 53 bits."""
+    want = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    got = W.splitmix64_uniform(0, 3)
+    assert list(got) == [(z >> 11) * 2.0 ** -53 for z in want]
