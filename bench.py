@@ -450,7 +450,9 @@ def main(argv=None):
         sp.close()
         same = all(np.array_equal(recp[k], rec64[k]) for k in rec64)
         out["fp64_blocked"] = {"value": cells / w64, "unit": "cell-updates/s", "device_ms": d64[0],
-                               "block": b64, "depth": k64, "regs": r64, "lanes": l64}
+                               "block": b64, "depth": k64, "regs": r64, "lanes": l64,
+                               "tflops_algorithmic": alu_tflops(n_levels, cells, d64[0]),
+                               "alu_frac": alu_tflops(n_levels, cells, d64[0]) / PEAK["fp64_tflops"]}
         out["fp64_plain"] = {"value": cells / wp, "unit": "cell-updates/s", "wall_s": wp,
                              "bitwise_equal_to_fp64_blocked": bool(same)}
         out["fp32_vs_fp64_full_run_max_rel_err"] = rel_err(prob, rec32, rec64)
@@ -485,7 +487,9 @@ def main(argv=None):
         tb = time.perf_counter() - t0
         beff = sum(bytes_per_cell_update(2 if k % 2 == 0 else 3, 32) * p["nx"] * p["n_steps"]
                    for k, p in enumerate(sims)) / tb / 1e9
-        out["batched_sweep"] = {"value": bcells / tb, "unit": "cell-updates/s", "sims": len(sims),
+        bflop = sum(flops_per_cell_update(2 if k % 2 == 0 else 3) * p["nx"] * p["n_steps"]
+                    for k, p in enumerate(sims)) / tb / 1e12
+        out["batched_sweep"] = {"tflops_algorithmic": bflop, "alu_frac": bflop / PEAK["fp32_tflops"],"value": bcells / tb, "unit": "cell-updates/s", "sims": len(sims),
                                 "cell_updates": bcells, "wall_s": tb, "hbm_effective_gbs": beff,
                                 "hbm_effective_frac": beff / PEAK["hbm_gbs"], "block": bblock, "depth": bdepth, "regs": bregs,
                                 "lanes": blanes}
