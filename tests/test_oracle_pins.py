@@ -584,36 +584,7 @@ def test_p10c_non_euclidean_dephasing_is_flagged():
 
 
 # ---------------------------------------------------------------- P11 the paper's printed numbers
-
-def test_p11_packing_from_qcl_listing():
-    """QCL listing (Sec. 4.4): the dipole sits in packed slot 6, the tunnelling couplings in
-    slots 2 and 3 and the injector-ULL dephasing in slots 2 and 3.  With column-wise packing
-    slot 6 is (3,4): it couples the initially populated level 3, and slots 2, 3 are (1,3),
-    (2,3), the injector pair coupled to level 3."""
-    e = C["e"]
-    h_off = [0.0, 1.2329e-3 * e, -1.3447e-3 * e, 0, 0, 0, 0, 0, 0, 0]
-    u_off = [0.0, 0, 0, 0, 0, -e * 4e-9, 0, 0, 0, 0]
-    h = O.unpack_hermitian([0.10103 * e, 0.09677 * e, 0.09720 * e, 0.08129 * e, 0.07633 * e], h_off)
-    u = O.unpack_hermitian([0.0] * 5, u_off)
-    nz = [(i, j) for i in range(5) for j in range(i + 1, 5) if u[i, j] != 0]
-    assert nz == [(2, 3)]
-    hz = [(i, j) for i in range(5) for j in range(i + 1, 5) if h[i, j] != 0]
-    assert hz == [(0, 2), (1, 2)]
-    assert O.pair_list(5)[1:3] == [(0, 2), (1, 2)]
-    assert np.allclose(h, h.conj().T)
-
-
-def test_p11_sit_listing_pulse_area_is_two_pi():
-    """SIT listing (Sec. 4.1): dipole e * 6.24e-11 m, sech(4.2186e9, 2e14 Hz, shift 10,
-    width 2e14): the envelope area mu/hbar * int A sech(w t - 10) dt = 2 pi."""
-    src = W.source("sech", 0, 4.2186e9, 0.0, 10.0, 2e14, phase=math.pi / 2)
-    t = np.linspace(-50e-15, 250e-15, 300001)
-    env = np.array([O.source_value(src, tt) for tt in t])
-    area = C["e"] * 6.24e-11 / HB * np.trapezoid(env, t)
-    assert abs(area / (2 * math.pi) - 1.0) < 1e-3
-    # the envelope peaks at t = shift / width = 50 fs, as in the Song listing (49 fs)
-    assert abs(t[np.argmax(env)] - 50e-15) < 1e-17
-
+# (read from tests/golden/, see the golden-fixture tests at the end of this file)
 
 # ---------------------------------------------------------------- explicit Lindblad operators
 
@@ -673,3 +644,80 @@ def test_explicit_lindblad_ops_equal_rate_form(n, seed):
     for key in ref:
         scale = max(1e-30, np.abs(ref[key]).max())
         assert np.max(np.abs(np.asarray(got[key]) - np.asarray(ref[key]))) <= 1e-10 * scale, key
+
+
+# ---------------------------------------------------------------- golden fixtures (printed examples)
+
+GOLDEN = __import__("pathlib").Path(__file__).parent / "golden"
+
+
+def _golden(name):
+    """key -> list of floats from a fixture of the paper's printed example values."""
+    out = {}
+    for line in (GOLDEN / name).read_text().splitlines():
+        line = line.split("#", 1)[0].strip()
+        if line:
+            key, val = line.split("=", 1)
+            out[key.strip()] = [float(v) for v in val.split()]
+    return out
+
+
+def test_golden_sit_listing():
+    """Sec. 4.1 listing: the transition frequency is 2 pi 2e14, the sech source carries a
+    2 pi pulse area for the dipole e z21, and the two-level constructor relaxes the
+    inversion towards w0 at the rate gamma1 (closed form, single point, no field)."""
+    g = _golden("sit_ziolkowski.txt")
+    assert g["omega21"][0] == 2 * math.pi * 2e14
+    amp, freq, shift, width = g["source"]
+    src = W.source("sech", 0, amp, 0.0, shift, width, phase=math.pi / 2)
+    t = np.linspace(-50e-15, 250e-15, 300001)
+    env = np.array([O.source_value(src, tt) for tt in t])
+    area = C["e"] * g["z21"][0] / HB * np.trapezoid(env, t)
+    assert abs(area / (2 * math.pi) - 1.0) < 1e-3
+    assert abs(t[np.argmax(env)] - shift / width) < 1e-17     # envelope peak at 50 fs
+    qm = W.two_level_params(g["n3d"][0], g["omega21"][0], g["z21"][0], g["gamma1"][0], g["gamma2"][0], g["w0"][0])
+    dt, steps = 2e-12, 50
+    prob = W.make_problem("sit-relax", 0.0, [W.qm_material(qm)], [(0.0, 0.0, 0)], 1, dt, steps, [0.0, 1.0])
+    orc = O.Oracle(prob)
+    for _ in range(steps):
+        orc.step()
+    rho = orc.density_at(0)
+    w = (rho[1, 1] - rho[0, 0]).real
+    w0, g1 = g["w0"][0], g["gamma1"][0]
+    assert abs(w - (w0 + (1.0 - w0) * math.exp(-g1 * steps * dt))) < 1e-12
+
+
+def test_golden_qcl_listing_is_the_workload():
+    """Sec. 4.4 listing: the five-level comb workload holds the printed Hamiltonian,
+    dipole, rate matrix, dephasing, density, material, mirrors and length; with column
+    packing the dipole couples (3,4) and the tunnelling (1,3), (2,3)."""
+    g = _golden("qcl_tzenov.txt")
+    e = C["e"]
+    prob = W.qcl5_comb(nx=64, n_steps=10)
+    qm = prob["materials"][0]["qm"]
+    assert np.array_equal(qm["h0_diag"], np.array(g["h0_diag_ev"]) * e)
+    assert np.array_equal(qm["h0_off"], np.array(g["h0_off_ev"]) * e)
+    assert np.array_equal(qm["mu_off"], np.array(g["mu_off_em"]) * e)
+    rates = np.array([g[f"rates_row{k}"] for k in range(1, 6)])
+    assert np.array_equal(qm["rates"], rates)
+    tau = np.array(g["dephasing_times"])
+    assert np.allclose(qm["pure_deph"], np.where(tau > 0, 1.0 / np.where(tau > 0, tau, 1.0), 0.0), rtol=1e-15)
+    assert qm["n3d"] == g["n3d"][0]
+    m = prob["materials"][0]
+    assert [m["eps_r"], m["overlap"], m["alpha0"]] == g["material"]
+    assert list(prob["refl"]) == g["reflectivity"] and prob["length"] == g["length"][0]
+    h = O.unpack_hermitian(qm["h0_diag"], qm["h0_off"])
+    u = O.unpack_hermitian([0.0] * 5, qm["mu_off"])
+    assert [(i, j) for i in range(5) for j in range(i + 1, 5) if u[i, j] != 0] == [(2, 3)]
+    assert [(i, j) for i in range(5) for j in range(i + 1, 5) if h[i, j] != 0] == [(0, 2), (1, 2)]
+
+
+def test_golden_ladder_levels():
+    """Sec. 4.3: the ladder workload's level spacings are the printed formula's, and w0 is
+    the E_3 -> E_4 transition frequency as the text states."""
+    g = _golden("ladder_marskar.txt")
+    n = int(g["levels"][0])
+    qm = W.ladder(n, nx=64, n_steps=10)["materials"][1]["qm"]
+    gaps = np.diff(np.asarray(qm["h0_diag"])) / (HB * g["omega0"][0])
+    assert np.allclose(gaps, g["spacings"], rtol=1e-12)
+    assert abs(gaps[2] - 1.0) < 1e-12
