@@ -314,6 +314,8 @@ def test_server_budget_and_cancel():
     srv.drain(timeout_s=60)
     assert srv.status(t1)[0] == 2
     assert srv.status(t2)[0] == 3
+    assert sorted(srv.poll()) == sorted([t1, t2])      # done and cancelled both reported once
+    assert srv.poll() == []
     srv.close()
 
 
