@@ -52,7 +52,8 @@ __device__ __forceinline__ cptr<T> kconst(const void *p) {
 // (cos t - 1, sin t) of a field phase.  Small angles (the usual case: the
 // phase per step is E dt (lam_j - lam_k)/hbar, a few 1e-2 rad) use the
 // Taylor series truncated where the remainder drops below half an ulp;
-// larger ones use the library sincos of t/2 with cos t - 1 = -2 sin^2(t/2).
+// larger ones use angle halving and doubling (FP64) or the library sincos of
+// t/2 with cos t - 1 = -2 sin^2(t/2) (FP32).
 __device__ __forceinline__ void phase_taylor(double t, double &cm, double &sn) {
   const double t2 = t * t;
   double s = fma(t2, -1.0 / 6227020800.0, 1.0 / 39916800.0);
@@ -95,15 +96,29 @@ __device__ __forceinline__ void phase_long(float t, float &cm, float &sn) {
   cm = t2 * c;
 }
 
+// |t| > 0.25 in FP64: the series at t / 2^k (below 0.25), then k double-angle
+// steps, cos 2x - 1 = 2 c (c + 2) and sin 2x = 2 s (c + 1) for c = cos x - 1,
+// s = sin x (no cancellation); each step doubles the absolute error, about
+// 2^k ulp in all.  A short loop in few registers: the library sincos needed
+// so many that the FP64 tiles spilled into accumulation registers.
+// (k = 0 for the lanes with |t| <= 0.25)
 __device__ __forceinline__ void phase_general(double t, double &cm, double &sn) {
-  if (fabs(t) <= 0.25) {
-    phase_taylor(t, cm, sn);
-  } else {
-    double s, c;
-    sincos(0.5 * t, &s, &c);
-    sn = 2.0 * s * c;
-    cm = -2.0 * s * s;
+  int k = 0;
+  double ts = t;
+  if (!(fabs(t) <= 0.25)) {
+    const int e = ilogb(t);  // |t| < 2^(e+1)
+    k = e > 61 ? 64 : (e < -2 ? 1 : e + 3);
+    ts = ldexp(t, -k);
   }
+  double c, s;
+  phase_taylor(ts, c, s);
+  for (int i = 0; i < k; ++i) {
+    const double c2 = 2.0 * c * (c + 2.0);
+    s = 2.0 * s * (c + 1.0);
+    c = c2;
+  }
+  cm = c;
+  sn = s;
 }
 
 // per lane: the short series, the long one, or sincos (the result depends on
