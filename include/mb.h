@@ -36,8 +36,9 @@
  *    Z_L = eta (1 - sqrt R)/(1 + sqrt R) on the edge node's half cell (eta:
  *    wave impedance of the edge material), whose amplitude reflection at
  *    normal incidence is -sqrt R.  Values outside [0, 1] are MB_ERR_ARG.
- *  - Sources act after each step at t_{n+1} = (n+1) dt: a hard source sets E
- *    at its cell, a soft source adds to it.  A hard source also sets E^0.
+ *  - Sources act after each step at t_{n+1} = (n+1) dt at the E node nearest
+ *    to their position (halves to the even node): a hard source sets E there, a
+ *    soft source adds to it.  A hard source also sets E^0.
  *  - Records are sampled after step n when (n+1) is a multiple of their
  *    interval; density quantities refer to rho^{n+1/2}, E to E^{n+1}, H to
  *    H^{n+1/2}.  Every record value is delivered in double precision.
@@ -162,7 +163,9 @@ typedef struct mb_device_desc {
 typedef struct mb_source {
   int32_t kind;              /* MB_SRC_* */
   int32_t hard;              /* 1 hard, 0 soft */
-  int64_t cell;
+  double x;                  /* position [m]; the source acts at E node round(x/dx), halves
+                                to the even node (Sec. 3.2 converts positions to grid
+                                indices); outside [0, nx-1] after rounding: MB_ERR_ARG */
   double amp, freq, shift, width, phase, period;
   int32_t count;             /* pulses in the train (>= 1) */
   const double *table;       /* MB_SRC_TABLE: values at t_n = n dt, n = 0..table_len-1 */
@@ -243,6 +246,13 @@ int mb_plan_material(const mb_device_desc *dev, const mb_scenario_desc *scen, in
  * post-rotation state y (M+1 doubles). */
 int mb_plan_readout(const mb_device_desc *dev, const mb_scenario_desc *scen, int32_t record_id,
                     int32_t material, double *out, int64_t capacity);
+
+/* Source `source_id` as planned: its E node (round(x/dx), halves to the even
+ * node) into *node and the first `capacity` values of its FP64 table s(n dt),
+ * n = 0..n_steps, into values (NULL: none), their count into *n_out.  Returns
+ * the plan status. */
+int mb_plan_source(const mb_device_desc *dev, const mb_scenario_desc *scen, int32_t source_id, int64_t *node,
+                   double *values, int64_t capacity, int64_t *n_out);
 
 /* ---- single simulation --------------------------------------------------- */
 

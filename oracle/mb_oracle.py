@@ -49,7 +49,8 @@ give) are a resistive termination: the edge node's half cell is loaded by an
 impedance Z_L = eta (1 - sqrt R)/(1 + sqrt R), eta the wave impedance of the
 edge material, whose normal-incidence amplitude reflection (Z_L - eta)/
 (Z_L + eta) = -sqrt(R); sources are evaluated at t_{n+1};
-a hard source sets E, a soft source adds to it; sech source
+a hard source sets E, a soft source adds to it, at the node nearest to its
+position (ties to the even node); sech source
 s(t) = A sech(w t - shift) sin(2 pi f t + phi) and the Gaussian source
 s(t) = A exp(-(w t - shift)^2) sin(2 pi f t + phi); records are taken after
 step n when (n+1) is a multiple of the interval.
@@ -247,6 +248,20 @@ def source_value(src, t, n=None):
     return src["amp"] * env * math.sin(2.0 * math.pi * src["freq"] * t + src["phase"])
 
 
+def source_cell(x, dx, nx):
+    """E node of a source at position x: round(x/dx) with ties to the even node (the
+    paper converts positions to integer grid indices at set-up, Sec. 3.2).  A single-point
+    device (nx = 1) has its one node at x = 0."""
+    if nx == 1:
+        if x != 0.0:
+            raise ValueError(f"source at x={x} on a single-point device")
+        return 0
+    cell = round(x / dx)            # Python rounds halves to even
+    if not 0 <= cell <= nx - 1:
+        raise ValueError(f"source at x={x} lies outside the grid")
+    return int(cell)
+
+
 def material_index(regions, x, dx):
     """Region lookup: [x_start, x_end) first, then closed intervals, then the right end."""
     for r in regions:
@@ -323,6 +338,7 @@ class Oracle:
         rho0 = unpack_hermitian(prob["rho_diag"], prob["rho_off"]) if n else None
         for g in self.groups:
             g["rho"] = np.repeat(rho0[None, :, :], len(g["cells"]), axis=0).copy()
+        self.src_cell = [source_cell(s["x"], self.dx, nx) for s in prob["sources"]]
         self.step_index = 0
         self._apply_edges_init()
         self._apply_sources(0, init=True)
@@ -359,12 +375,12 @@ class Oracle:
             self.e[-1] = 0.0
 
     def _apply_sources(self, n, init=False):
-        for s in self.p["sources"]:
+        for s, cell in zip(self.p["sources"], self.src_cell):
             v = source_value(s, n * self.dt, n)
             if s["hard"]:
-                self.e[s["cell"]] = v
+                self.e[cell] = v
             elif not init:
-                self.e[s["cell"]] += v
+                self.e[cell] += v
 
     # -- density step ---------------------------------------------------------
     def _field_op(self, g, e_cells):

@@ -29,7 +29,7 @@ VARIANT = {"auto": 0, "plain": 1, "blocked": 2, "blocked_regs": 3}
 FIELD_STEP = {"exact": 0, "cayley": 1}    # MB_FIELD_EXACT, MB_FIELD_CAYLEY
 
 EXPORTS = [
-    "mb_last_error", "mb_device_count", "mb_plan_material", "mb_plan_readout", "mb_workspace_bytes", "mb_setup", "mb_run", "mb_run_mode", "mb_reset", "mb_batch_reset", "mb_shape", "mb_batch_shape", "mb_steps_done", "mb_record_shape",
+    "mb_last_error", "mb_device_count", "mb_plan_material", "mb_plan_readout", "mb_plan_source", "mb_workspace_bytes", "mb_setup", "mb_run", "mb_run_mode", "mb_reset", "mb_batch_reset", "mb_shape", "mb_batch_shape", "mb_steps_done", "mb_record_shape",
     "mb_read_records", "mb_read_state", "mb_elapsed_ms", "mb_destroy", "mb_batch_setup", "mb_batch_run",
     "mb_batch_record_shape", "mb_batch_read_records", "mb_batch_elapsed_ms", "mb_batch_destroy",
     "mb_server_create", "mb_server_submit", "mb_server_start", "mb_server_drain", "mb_server_cancel", "mb_server_poll",
@@ -76,7 +76,7 @@ class mb_device_desc(C.Structure):
 
 
 class mb_source(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("hard", C.c_int32), ("cell", C.c_int64), ("amp", C.c_double),
+    _fields_ = [("kind", C.c_int32), ("hard", C.c_int32), ("x", C.c_double), ("amp", C.c_double),
                 ("freq", C.c_double), ("shift", C.c_double), ("width", C.c_double),
                 ("phase", C.c_double), ("period", C.c_double), ("count", C.c_int32),
                 ("table", C.POINTER(C.c_double)), ("table_len", C.c_int64)]
@@ -125,6 +125,8 @@ def load():
                                        dp, C.c_int64, i64p]),
         "mb_plan_readout": (C.c_int, [C.POINTER(mb_device_desc), C.POINTER(mb_scenario_desc), C.c_int32,
                                       C.c_int32, dp, C.c_int64]),
+        "mb_plan_source": (C.c_int, [C.POINTER(mb_device_desc), C.POINTER(mb_scenario_desc), C.c_int32,
+                                     i64p, dp, C.c_int64, i64p]),
         "mb_setup": (C.c_int, [C.c_int, C.POINTER(mb_device_desc), C.POINTER(mb_scenario_desc), P, C.c_size_t,
                                C.POINTER(P)]),
         "mb_workspace_bytes": (C.c_int, [C.POINTER(mb_device_desc), C.POINTER(mb_scenario_desc),
@@ -242,7 +244,7 @@ class _Marshal:
         dev.n_regions, dev.regions = len(prob["regions"]), regs
         srcs = (mb_source * max(1, len(prob["sources"])))()
         for k, s in enumerate(prob["sources"]):
-            srcs[k].kind, srcs[k].hard, srcs[k].cell = SRC_KIND[s["kind"]], int(s["hard"]), s["cell"]
+            srcs[k].kind, srcs[k].hard, srcs[k].x = SRC_KIND[s["kind"]], int(s["hard"]), s["x"]
             srcs[k].amp, srcs[k].freq, srcs[k].shift = s["amp"], s["freq"], s["shift"]
             srcs[k].width, srcs[k].phase, srcs[k].period, srcs[k].count = (s["width"], s["phase"],
                                                                           s["period"], s["count"])
@@ -320,6 +322,17 @@ def plan_readout(prob, record_id, material):
     out = np.zeros(lv * lv)
     _check(lib.mb_plan_readout(C.byref(m.dev), C.byref(m.scen), record_id, material, _dptr(out), out.size))
     return out
+
+
+def plan_source(prob, source_id, n_values=0):
+    """Host-only plan of one source (mb_plan_source): (E node, first n_values table values)."""
+    lib = load()
+    m = _Marshal(prob)
+    node, n = C.c_int64(), C.c_int64()
+    out = np.zeros(max(1, n_values))
+    _check(lib.mb_plan_source(C.byref(m.dev), C.byref(m.scen), source_id, C.byref(node),
+                              _dptr(out) if n_values > 0 else None, n_values, C.byref(n)))
+    return node.value, out[: n.value].copy()
 
 
 def plan_status(prob, precision=None, variant="auto", block=0, depth=0, lanes=0):

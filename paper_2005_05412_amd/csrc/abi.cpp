@@ -240,6 +240,23 @@ int mb_plan_readout(const mb_device_desc *dev, const mb_scenario_desc *scen, int
   MB_GUARD_END
 }
 
+int mb_plan_source(const mb_device_desc *dev, const mb_scenario_desc *scen, int32_t source_id, int64_t *node,
+                   double *values, int64_t capacity, int64_t *n_out) {
+  MB_GUARD_BEGIN
+  SimPlan plan;
+  std::string err;
+  int rc = build_plan(dev, scen, plan, err);
+  if (rc < 0) return fail(rc, err);
+  if (source_id < 0 || source_id >= int(plan.sources.size())) return fail(MB_ERR_ARG, "bad source id");
+  const SourcePlan &sp = plan.sources[source_id];
+  if (node) *node = sp.cell;
+  const int64_t n = std::min<int64_t>(capacity, int64_t(sp.table.size()));
+  if (values && n > 0) std::memcpy(values, sp.table.data(), size_t(n) * sizeof(double));
+  if (n_out) *n_out = values ? std::max<int64_t>(n, 0) : 0;
+  return rc;
+  MB_GUARD_END
+}
+
 int mb_workspace_bytes(const mb_device_desc *dev, const mb_scenario_desc *scen, size_t *bytes) {
   MB_GUARD_BEGIN
   if (!bytes) return fail(MB_ERR_ARG, "null output");

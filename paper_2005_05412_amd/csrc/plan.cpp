@@ -502,6 +502,20 @@ double source_value(const mb_source &s, double t) {
   return s.amp * env * std::sin(2.0 * M_PI * s.freq * t + s.phase);
 }
 
+// Node of a source at position x (Sec. 3.2 converts positions to integer grid
+// indices at set-up): round(x/dx) with halves to the even node; -1 outside the
+// grid.  A single-point device (nx = 1) has its one node at x = 0.
+int64_t source_node(double x, double dx, int64_t nx) {
+  if (!std::isfinite(x)) return -1;
+  if (nx == 1) return x == 0.0 ? 0 : -1;
+  const double q = x / dx;
+  if (!(q > -1.0 && q < double(nx))) return -1;
+  double r = std::floor(q);
+  const double f = q - r;
+  if (f > 0.5 || (f == 0.5 && std::fmod(r, 2.0) != 0.0)) r += 1.0;
+  return r >= 0.0 && r <= double(nx - 1) ? int64_t(r) : -1;
+}
+
 int region_material(const mb_device_desc *dev, double x, double dx, std::string &err) {
   for (int r = 0; r < dev->n_regions; ++r)
     if (dev->regions[r].x_start <= x && x < dev->regions[r].x_end) return dev->regions[r].material;
@@ -728,8 +742,8 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
   }
   for (int s = 0; s < scen->n_sources; ++s) {
     const mb_source &src = scen->sources[s];
-    if (src.cell < 0 || src.cell >= nx ||
-        (src.kind != MB_SRC_SECH && src.kind != MB_SRC_GAUSS && src.kind != MB_SRC_TABLE)) {
+    const int64_t cell = source_node(src.x, plan.dx, nx);
+    if (cell < 0 || (src.kind != MB_SRC_SECH && src.kind != MB_SRC_GAUSS && src.kind != MB_SRC_TABLE)) {
       err = "source outside the grid or of unknown kind";
       return MB_ERR_ARG;
     }
@@ -738,7 +752,7 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
       return MB_ERR_ARG;
     }
     SourcePlan sp;
-    sp.cell = src.cell;
+    sp.cell = cell;
     sp.hard = src.hard ? 1 : 0;
     sp.table.resize(plan.n_steps + 1);
     for (int64_t t = 0; t <= plan.n_steps; ++t)

@@ -1,8 +1,8 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle.
 
-Tolerances (relative max-norm over recorded traces, see workloads.errors:
-max |x - x_ref| of a trace over the max-norm of all reference traces of the
-same quantity class): FP64 1e-10, FP32 1e-4.  The two-launch FP64 kernels and the
+Tolerances (relative max-norm of each recorded trace, see workloads.errors:
+max |x - x_ref| / max |x_ref| per trace, the reference max-norm floored at 1e-3
+for density quantities and 1 V/m for E): FP64 1e-10, FP32 1e-4.  The two-launch FP64 kernels and the
 blocked FP64 kernel execute the same per-cell arithmetic, so they must agree
 bit for bit whatever the tile shape.
 """
@@ -28,7 +28,7 @@ def _say(msg):
 
 
 def rel_errors(prob, got, ref):
-    """name -> relative max-norm error of each recorded trace, on its quantity's scale."""
+    """name -> relative max-norm error of each recorded trace."""
     return trace_errors(prob, got, ref)
 
 
@@ -345,8 +345,10 @@ def test_table_sources_vs_oracle():
     prob = W.random_small(81, N=3, nx=90, n_steps=120, refl=(0.0, 1.0))
     rng = np.random.default_rng(81)
     amp = max(abs(s["amp"]) for s in prob["sources"]) if prob["sources"] else 1e9
-    prob["sources"] = [W.table_source(0, amp * np.sin(0.3 * np.arange(80)) * np.exp(-np.arange(80) / 40.0)),
-                       W.table_source(45, 0.1 * amp * rng.normal(size=121), hard=False)]
+    # the soft source sits half way between nodes 44 and 45: both sides take the even node
+    prob["sources"] = [W.table_source(0.0, amp * np.sin(0.3 * np.arange(80)) * np.exp(-np.arange(80) / 40.0)),
+                       W.table_source(W.node_x(prob["length"], 90, 44.5), 0.1 * amp * rng.normal(size=121),
+                                      hard=False)]
     _say("table sources")
     ref = O.run(prob)
     plain = gpu_run(prob, precision=64, variant="plain")
@@ -472,45 +474,21 @@ def test_reset_and_graph_replay_reproduce_the_run():
     s.close()
 
 
-def fp32_field_bound(prob, n_steps):
-    """Stated FP32 error bound of a noise-started cavity, relative to the field scale.
-
-    FP32 resolves a density-matrix element to 2^-24; the polarization current is
-    n3D tr{mu L0 rho}, at most n3D |mu|_max omega_max per unit of a coherence, and
-    enters the E update times b' Gamma = dt Gamma / eps.  Each step therefore adds
-    up to b' Gamma n3D |mu|_max omega_max 2^-24 V/m of rounding, which accumulates
-    like a random walk over n_steps.  The laser cavities start from a ~1 V/m noise
-    field, so this is far above the 1e-4 that sources of ~1e8 V/m allow."""
-    c = prob["consts"]
-    bound = 0.0
-    for m in prob["materials"]:
-        q = m["qm"]
-        if q is None or q["kind"] != "general":
-            continue
-        h0 = O.unpack_hermitian(q["h0_diag"], q["h0_off"])
-        ev = np.linalg.eigvalsh(h0)
-        omega = (ev[-1] - ev[0]) / c["hbar"]
-        mu = max(np.max(np.abs(q["mu_off"])), np.max(np.abs(q["mu_diag"])))
-        b = prob["dt"] * m["overlap"] / (c["eps0"] * m["eps_r"])
-        bound = max(bound, b * q["n3d"] * mu * omega * 2.0 ** -24 * math.sqrt(n_steps))
-    ref_scale = max(np.max(np.abs(prob["e_init"])), max([s["amp"] for s in prob["sources"]] + [0.0]))
-    return bound / ref_scale
-
-
 def test_qcl6_full_grid_prefix_vs_oracle():
     """Six-level QCL-like cavity (8192 cells, PEC ends, noise start): first 600 steps.
 
-    FP64 meets 1e-10.  FP32 is held to the stated bound of fp32_field_bound (1.3e-2
-    here; measured 3.8e-4)."""
+    FP64 within 1e-10 and FP32 within 1e-4 per trace."""
     prob = W.qcl6(n_steps=600)
     _say("qcl6 oracle prefix")
     ref = O.run(prob)
     got = gpu_run(prob, precision=64)
-    assert max(rel_errors(prob, got, ref).values()) <= TOL[64]
+    errs = rel_errors(prob, got, ref)
+    _say(f"qcl6 fp64 {errs}")
+    assert max(errs.values()) <= TOL[64], errs
     got32 = gpu_run(prob, precision=32)
-    err32 = max(rel_errors(prob, got32, ref).values())
-    _say(f"qcl6 fp32 {err32} bound {fp32_field_bound(prob, 600)}")
-    assert err32 <= fp32_field_bound(prob, 600)
+    errs32 = rel_errors(prob, got32, ref)
+    _say(f"qcl6 fp32 {errs32}")
+    assert max(errs32.values()) <= TOL[32], errs32
     base = gpu_run(prob, precision=32, variant="blocked", block=256, depth=64, lanes=1)
     for block, depth, lanes in ((256, 64, 2), (128, 32, 4), (64, 16, 4), (64, 16, 8)):
         _say(f"qcl6 prefix {block}/{depth} lanes {lanes}")
@@ -519,8 +497,8 @@ def test_qcl6_full_grid_prefix_vs_oracle():
 
 def test_qcl5_comb_prefix_vs_oracle():
     """The paper's five-level QCL comb example (8192 cells, R = 0.8 mirrors, noise start):
-    first 600 steps against the oracle; FP32 under fp32_field_bound (5.7e-3 here,
-    measured 1.5e-3); the density update split over 4 and 8 waves gives the same bits."""
+    first 600 steps against the oracle, FP64 within 1e-10 and FP32 within 1e-4 per trace;
+    the density update split over 4 and 8 waves gives the same bits."""
     prob = W.qcl5_comb(n_steps=600)
     _say("qcl5 oracle prefix")
     ref = O.run(prob)
@@ -531,7 +509,7 @@ def test_qcl5_comb_prefix_vs_oracle():
     got32 = gpu_run(prob, precision=32)
     errs32 = rel_errors(prob, got32, ref)
     _say(f"qcl5 fp32 {errs32}")
-    assert max(errs32.values()) <= fp32_field_bound(prob, 600), (errs32, fp32_field_bound(prob, 600))
+    assert max(errs32.values()) <= TOL[32], errs32
     base = gpu_run(prob, precision=32, variant="blocked", block=256, depth=64, lanes=1)
     for block, depth, lanes in ((128, 32, 4), (64, 16, 8)):
         assert_same(gpu_run(prob, precision=32, variant="blocked", block=block, depth=depth, lanes=lanes), base)

@@ -180,17 +180,20 @@ def test_status_codes():
     with pytest.raises(mb.MBError) as ex:
         mb.plan_status(bad)
     assert ex.value.code == -1
+    for x in (1e-5 * (1 + 0.6 / 19), -0.6e-5 / 19, float("nan")):     # beyond either end by > dx/2
+        bad = _vac()
+        bad["sources"] = [W.source("sech", x, 1.0, 1e14, 1.0, 1e14)]
+        with pytest.raises(mb.MBError) as ex:
+            mb.plan_status(bad)
+        assert ex.value.code == -1
     bad = _vac()
-    bad["sources"] = [W.source("sech", 99, 1.0, 1e14, 1.0, 1e14)]
-    with pytest.raises(mb.MBError):
-        mb.plan_status(bad)
-    bad = _vac()
-    bad["sources"] = [W.table_source(3, [0.0, np.nan, 1.0])]
+    bad["sources"] = [W.table_source(W.node_x(1e-5, 20, 3), [0.0, np.nan, 1.0])]
     with pytest.raises(mb.MBError) as ex:
         mb.plan_status(bad)
     assert ex.value.code == -1
     ok = _vac()
-    ok["sources"] = [W.table_source(3, [0.0, 0.5, 1.0]), W.table_source(4, [], hard=False)]
+    ok["sources"] = [W.table_source(W.node_x(1e-5, 20, 3), [0.0, 0.5, 1.0]),
+                     W.table_source(W.node_x(1e-5, 20, 4), [], hard=False)]
     assert mb.plan_status(ok) == 0
     # waves per 64 cells: 0 (default), 1, 2, 4 or 8
     for lanes in (0, 1, 2, 4, 8):
@@ -251,3 +254,21 @@ def test_splitmix64_published_outputs():
     want = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
     got = W.splitmix64_uniform(0, 3)
     assert list(got) == [(z >> 11) * 2.0 ** -53 for z in want]
+
+
+def test_source_positions_convert_like_the_oracle():
+    """The library puts a source at the node the oracle does: round(x/dx), halves to the
+    even node (Sec. 3.2 converts positions to grid indices), and its FP64 value table is
+    the oracle's source at t_n = n dt."""
+    prob = _vac(nx=21)
+    dx = prob["length"] / 20
+    xs = [0.0, 0.3 * dx, 0.5 * dx, 1.5 * dx, 2.5 * dx, 7.49 * dx, 7.5 * dx, 19.5 * dx, prob["length"],
+          prob["length"] + 0.4 * dx]
+    prob["sources"] = [W.source("gauss", x, 2e8, 1.9e14, 3.0, 1.0 / 5e-15, phase=0.3) for x in xs]
+    orc = O.Oracle(prob)
+    for k, x in enumerate(xs):
+        node, vals = mb.plan_source(prob, k, n_values=prob["n_steps"] + 1)
+        assert node == O.source_cell(x, dx, 21) == orc.src_cell[k], (k, x / dx)
+        want = [O.source_value(prob["sources"][k], n * prob["dt"]) for n in range(prob["n_steps"] + 1)]
+        assert np.max(np.abs(vals - want)) <= 1e-15 * 2e8
+    assert [orc.src_cell[k] for k in range(len(xs))] == [0, 0, 0, 2, 2, 7, 8, 20, 20, 20]

@@ -721,3 +721,102 @@ def test_golden_ladder_levels():
     gaps = np.diff(np.asarray(qm["h0_diag"])) / (HB * g["omega0"][0])
     assert np.allclose(gaps, g["spacings"], rtol=1e-12)
     assert abs(gaps[2] - 1.0) < 1e-12
+
+
+# ---------------------------------------------------------------- sources and regions
+
+def _envelope(kind, amp, shift, width, period=0.0, count=1):
+    """The oracle's source with its carrier set to 1 (frequency 0, phase pi/2): the envelope."""
+    return W.source(kind, 0.0, amp, 0.0, shift, width, phase=math.pi / 2, period=period, count=count)
+
+
+def test_gaussian_source_closed_forms():
+    """Gaussian source of Sec. 2.1/3.1 (the paper gives no formula; reading: amplitude
+    times exp(-(width t - shift)^2) times the carrier): the envelope integrates to
+    amp sqrt(pi)/width, peaks at t = shift/width with the value amp, falls to amp/e one
+    1/width either side of the peak, and the carrier is sin(2 pi f t + phase) of the
+    absolute time."""
+    amp, shift, width = 3.7e8, 5.0, 1.0 / 30e-15
+    src = _envelope("gauss", amp, shift, width)
+    t = np.linspace(0.0, 2 * shift / width, 400001)
+    env = np.array([O.source_value(src, tt) for tt in t])
+    area = np.trapezoid(env, t)
+    assert abs(area / (amp * math.sqrt(math.pi) / width) - 1.0) < 1e-9
+    tp = shift / width
+    assert abs(O.source_value(src, tp) - amp) < 1e-15 * amp
+    assert abs(t[np.argmax(env)] - tp) < 1e-18
+    for d in (-1.0, 1.0):
+        assert abs(O.source_value(src, tp + d / width) - amp / math.e) < 1e-14 * amp
+    # carrier: at the peak the value is amp sin(2 pi f tp + phase), whatever f and phase
+    f, ph = 1.9e14, 0.7
+    s2 = W.source("gauss", 0.0, amp, f, shift, width, phase=ph)
+    assert abs(O.source_value(s2, tp) - amp * math.sin(2 * math.pi * f * tp + ph)) < 1e-14 * amp
+
+
+def test_pulse_train_is_a_sum_of_shifted_pulses():
+    """A train of `count` pulses with period T: its envelope is the sum of the single
+    pulse's envelope shifted by 0, T, 2T, ... (peaks at shift/width + q T); the carrier
+    stays that of the absolute time."""
+    amp, shift, width, T = 2.0e8, 4.0, 1.0 / 20e-15, 1.5e-12
+    single = _envelope("gauss", amp, shift, width)
+    train = _envelope("gauss", amp, shift, width, period=T, count=3)
+    for t in np.linspace(-0.2e-12, 5e-12, 2001):
+        want = sum(O.source_value(single, t - q * T) for q in range(3))
+        assert abs(O.source_value(train, t) - want) <= 1e-15 * amp
+    for q in range(3):
+        assert abs(O.source_value(train, shift / width + q * T) - amp) < 1e-12 * amp
+    # beyond the last pulse the train is the single pulse's tail only
+    assert O.source_value(train, shift / width + 3 * T) < 1e-100
+    st = _envelope("sech", amp, shift, width, period=T, count=2)
+    ss = _envelope("sech", amp, shift, width)
+    for t in np.linspace(0.0, 3e-12, 301):
+        assert abs(O.source_value(st, t) - O.source_value(ss, t) - O.source_value(ss, t - T)) <= 1e-15 * amp
+
+
+def test_lambda_drive_is_a_pi_half_pulse_train():
+    """The three-level Lambda workload's drive: each Gaussian of the train carries the
+    pulse area pi/2 on a 1e-29 C m dipole (area = dipole/hbar times the envelope
+    integral), its first peak is at 100 fs and the period is 2 ps."""
+    prob = W.lambda3(nx=64, n_steps=10)
+    s = prob["sources"][0]
+    env = _envelope("gauss", s["amp"], s["shift"], s["width"])
+    t = np.linspace(-200e-15, 400e-15, 600001)      # +- 10 widths around the first peak
+    area = 1e-29 / HB * np.trapezoid([O.source_value(env, tt) for tt in t], t)
+    assert abs(area / (math.pi / 2) - 1.0) < 1e-6
+    assert abs(s["shift"] / s["width"] - 100e-15) < 1e-27
+    assert s["period"] == 2e-12 and s["kind"] == "gauss" and s["freq"] == 190e12
+
+
+def test_region_lookup_at_interfaces():
+    """Regions are half-open [x_start, x_end) (reading of Sec. 3.1, region): a node on an
+    interface belongs to the region that starts there, the node at the far end to the
+    last region, a node beyond the end by less than dx/2 to the right-most region, and a
+    node in no region is an error."""
+    dx = 0.25
+    regions = [dict(x_start=0.0, x_end=1.0, material=0), dict(x_start=1.0, x_end=2.0, material=1),
+               dict(x_start=2.0, x_end=3.0, material=2)]
+    got = [O.material_index(regions, m * dx, dx) for m in range(13)]
+    assert got == [0, 0, 0, 0, 1, 1, 1, 1, 2, 2, 2, 2, 2]
+    assert O.material_index(regions, 3.0 + 0.4 * dx, dx) == 2
+    with pytest.raises(ValueError):
+        O.material_index(regions, 3.0 + 0.6 * dx, dx)
+    gap = [dict(x_start=0.0, x_end=1.0, material=0), dict(x_start=1.5, x_end=3.0, material=1)]
+    with pytest.raises(ValueError):
+        O.material_index(gap, 1.25, dx)
+    # a solve sees the same split: E nodes on the interfaces carry the right-hand medium
+    p = W.lambda3(nx=65, n_steps=1, n_regions=4)
+    orc = O.Oracle(p)
+    assert list(orc.mat_e[[0, 15, 16, 17, 31, 32, 48, 64]]) == [0, 0, 1, 1, 1, 2, 3, 3]
+
+
+def test_source_position_rounds_to_the_nearest_node():
+    """Source positions are converted to grid nodes by round(x/dx), ties to the even node
+    (Sec. 3.2: positions are converted to integer grid indices)."""
+    nx, length = 11, 1e-6
+    dx = length / (nx - 1)
+    for x, cell in ((0.0, 0), (0.49 * dx, 0), (0.5 * dx, 0), (1.5 * dx, 2), (2.5 * dx, 2), (3.51 * dx, 4),
+                    (length, 10)):
+        assert O.source_cell(x, dx, nx) == cell, (x / dx, cell)
+    for bad in (-0.6 * dx, length + 0.6 * dx):
+        with pytest.raises(ValueError):
+            O.source_cell(bad, dx, nx)

@@ -25,7 +25,8 @@ A *problem* is a dict:
 ``nx``, ``dt`` [s], ``n_steps``, ``precision`` (64 or 32).
 ``rho_diag``, ``rho_off``  initial density matrix in the same packed form.
 ``e_init``     None (zero field) or an (nx,) array of initial E [V/m].
-``sources``    list of dicts: kind ('sech'|'gauss'), hard (bool), cell,
+``sources``    list of dicts: kind ('sech'|'gauss'|'table'), hard (bool), x
+               (position [m]; each consumer converts it to the nearest E node),
                amp [V/m], freq [Hz], shift, width [1/s], phase [rad],
                period [s], count (number of pulses in a train).
 ``records``    list of dicts: name, quantity ('e'|'h'|'pop'|'inv'|'rho_re'|
@@ -109,15 +110,21 @@ def problem_levels(p) -> int:
     return ns.pop() if ns else 0
 
 
-def source(kind, cell, amp, freq, shift, width, phase=0.0, hard=True, period=0.0, count=1):
-    return {"kind": kind, "hard": bool(hard), "cell": int(cell), "amp": float(amp),
+def node_x(length, nx, cell):
+    """Position [m] of E node `cell` of an nx-node grid over `length` (x_m = m dx)."""
+    return 0.0 if nx <= 1 else cell * (length / (nx - 1))
+
+
+def source(kind, x, amp, freq, shift, width, phase=0.0, hard=True, period=0.0, count=1):
+    """A source at position x [m] (hard: sets E there, soft: adds to it)."""
+    return {"kind": kind, "hard": bool(hard), "x": float(x), "amp": float(amp),
             "freq": float(freq), "shift": float(shift), "width": float(width),
             "phase": float(phase), "period": float(period), "count": int(count)}
 
 
-def table_source(cell, values, hard=True):
-    """Sampled waveform: values[n] at t_n = n dt, zero after the table."""
-    s = source("table", cell, 0.0, 0.0, 0.0, 0.0, hard=hard)
+def table_source(x, values, hard=True):
+    """Sampled waveform at position x [m]: values[n] at t_n = n dt, zero after the table."""
+    s = source("table", x, 0.0, 0.0, 0.0, 0.0, hard=hard)
     s["table"] = np.asarray(values, float)
     return s
 
@@ -188,7 +195,7 @@ def sit_2lvl(nx=1500, n_steps=20000, precision=64, area_pi=2.0, probes=(300, 750
     fwhm = 100e-15
     tau = fwhm / (2.0 * math.acosh(math.sqrt(2.0)))   # intensity FWHM of sech^2
     amp = area_pi * c["hbar"] / (dipole * tau)         # area = mu A pi tau / hbar
-    src = source("sech", 0, amp, 2e14, 10.0, 1.0 / tau)
+    src = source("sech", 0.0, amp, 2e14, 10.0, 1.0 / tau)
     recs = []
     for p in probes:
         recs.append(record(f"e@{p}", "e", p, rec_interval))
@@ -241,7 +248,7 @@ def lambda3(nx=32768, n_steps=200000, precision=64, n_regions=16, n_probes=64,
     dt = courant_dt(L, nx, c["c0"])
     tau = 30e-15
     amp = math.sqrt(math.pi) * c["hbar"] / (2 * 1e-29 * tau)
-    src = source("gauss", 0, amp, 190e12, 100e-15 / tau, 1.0 / tau, period=2e-12,
+    src = source("gauss", 0.0, amp, 190e12, 100e-15 / tau, 1.0 / tau, period=2e-12,
                  count=max(1, int(math.ceil(n_steps * dt / 2e-12)) + 1))
     recs = []
     for k in range(n_probes):
@@ -367,7 +374,7 @@ def ladder(N, nx=8192, n_steps=20000, precision=32, rec_interval=100, length=2e-
     regions = [(0.0, 0.25 * length, 0), (0.25 * length, 0.75 * length, 1), (0.75 * length, length, 0)]
     dt = courant_dt(length, nx, c["c0"])
     tau = 100e-15
-    src = source("gauss", 0, 1e8, w0 / (2 * math.pi), 5.0, 1.0 / tau)
+    src = source("gauss", 0.0, 1e8, w0 / (2 * math.pi), 5.0, 1.0 / tau)
     mid = nx // 2
     recs = [record(f"pop{k}", "pop", mid, rec_interval, i=k, j=k) for k in range(N)]
     recs.append(record("e@3/4", "e", (3 * nx) // 4, rec_interval))
@@ -391,14 +398,14 @@ def sweep_sim(k, rng, nx=None, n_steps=50000, precision=32, rec_interval=50):
         qm = two_level_params(n3d, 2 * math.pi * 2e14, dipole / c["e"], 1.0 / t12, 1.0 / t12, -1.0)
         rho = [1.0, 0.0]
         tau = 100e-15 / (2.0 * math.acosh(math.sqrt(2.0)))
-        src = source("sech", 0, 2.0 * c["hbar"] / (dipole * tau), 2e14, 10.0, 1.0 / tau)
+        src = source("sech", 0.0, 2.0 * c["hbar"] / (dipole * tau), 2e14, 10.0, 1.0 / tau)
     else:
         qm = _lambda3_material(rng, c)
         qm["n3d"] = n3d
         qm["mu_off"] = qm["mu_off"] * (dipole / 1e-29)
         rho = [0.5, 0.5, 0.0]
         tau = 30e-15
-        src = source("gauss", 0, math.sqrt(math.pi) * c["hbar"] / (2 * dipole * tau), 190e12,
+        src = source("gauss", 0.0, math.sqrt(math.pi) * c["hbar"] / (2 * dipole * tau), 190e12,
                      100e-15 / tau, 1.0 / tau)
     mats = [vacuum(), qm_material(qm)]
     regions = [(0.0, 0.1 * L, 0), (0.1 * L, 0.9 * L, 1), (0.9 * L, L, 0)]
@@ -449,7 +456,7 @@ def serve_trace(n_requests=2000, rate=200.0, seed=None, precision=32,
                      rec_interval=rec_interval)
             p["refl"] = (0.0, 0.0)
             p["e_init"] = None
-            p["sources"] = [source("gauss", 0, 1e6, 3e12, 5.0, 1.0 / 500e-15)]
+            p["sources"] = [source("gauss", 0.0, 1e6, 3e12, 5.0, 1.0 / 500e-15)]
         p["records"] = p["records"][:1]
         p["records"][0]["interval"] = rec_interval
         p["name"] = f"req-{k}"
@@ -531,11 +538,11 @@ def random_small(seed, N=3, nx=40, n_steps=60, n_materials=2, refl=(0.0, 1.0),
     else:
         rd, ro = np.array([1.0]), np.zeros(0, complex)
     width = 1.0 / (rng.uniform(2.0, 6.0) * dt)
-    src = source("sech", 0 if nx > 1 else 0, rng.uniform(3e9, 8e9), rng.uniform(1e14, 3e14),
+    src = source("sech", 0.0, rng.uniform(3e9, 8e9), rng.uniform(1e14, 3e14),
                  4.0, width, phase=rng.uniform(0, 2 * math.pi), hard=not soft)
     srcs = [src]
     if nx > 4:
-        srcs.append(source("gauss", nx // 2, rng.uniform(1e9, 3e9), rng.uniform(1e14, 3e14),
+        srcs.append(source("gauss", node_x(L, nx, nx // 2), rng.uniform(1e9, 3e9), rng.uniform(1e14, 3e14),
                            3.0, 1.0 / (rng.uniform(3.0, 8.0) * dt), hard=False))
     e_init = None
     if e_noise > 0.0:
