@@ -189,8 +189,8 @@ typedef struct mb_scenario_desc {
   int64_t n_steps;
   int32_t precision;         /* 64 or 32: arithmetic of the bulk field and density updates */
   int32_t variant;           /* MB_VARIANT_* */
-  int32_t block;             /* blocked variant: cells per tile, 64, 128, 192, 256, 512 or
-                                1024 (0 = default) */
+  int32_t block;             /* blocked variant: cells per tile, 64, 128, 192, 256 or 512
+                                (0 = default; 5 and 6 levels: block * lanes <= 256) */
   int32_t depth;             /* blocked variant: steps per launch = halo width (0 = default) */
   int32_t coupling;          /* MB_COUPLING_WEAK (rho half a step after E, Fig. 1) or
                                 MB_COUPLING_STRONG (rho at the times of E; Sec. 2.2) */
@@ -230,20 +230,27 @@ int mb_device_count(void);
 /* Builds the FP64 plan on the host and copies the tables of material
  * `material` in the order lam[N] (ascending eigenvalues of mu), vec[2*N*N]
  * (the eigenvectors as the columns of a row-major complex N x N matrix V,
- * (re, im) pairs), kappa[N-1]
- * (dt (lam_q - lam_{q+1}) / hbar), p0, at[M], ah[M*M], bh[M], am[M*M],
- * bf[M] with M = N*N - 1: the running state sigma (populations 0..N-2 and
- * (Re, Im) of the packed pairs, in the eigen-basis of mu) advances as
- * y = rotation of sigma by E (coherence (j,k) times e^{i E sum kappa}),
- * p = at . y + p0, sigma' = y + am y + bf, and rho^{n+1/2} = ah y + bh
- * (rho = V rho' V^+ in the original basis).
+ * (re, im) pairs), kappa[N-1] (dt (lam_q - lam_{q+1}) / hbar), p0, at[M],
+ * ah[M*M], bh[M], am[M*M], bf[M], t0[K], tm[K*M], sm[M*K], as[K], bm[M*K],
+ * lvl[N] with M = N*N - 1 and K = N*(N-1).  The tables use the operator
+ * basis with the levels reordered: the caller's level i is level lvl[i] (the
+ * most populated initial level is placed last, where the trace elimination
+ * drops it).  The running state sigma (populations 0..N-2 and (Re, Im) of the
+ * packed pairs) advances by the Strang step of Sec. 2.2 as
+ *   z = t0 + tm sigma        (Re, Im) of the coherences of V^+ rho V,
+ *   d = (e^{i theta} - 1) z  pair (j,k): theta = E sum_{q=j}^{k-1} kappa_q,
+ *   y = sigma + sm d         the field conjugation W rho W^+,
+ *   p = at . y + p0 = at . sigma + as . d + p0,
+ *   sigma' = y + am y + bf = sigma + am sigma + bm d + bf,
+ * and rho^{n+1/2} = ah y + bh.
  * Returns the plan status (MB_OK, MB_WARN_NOT_CP or an error). */
 int mb_plan_material(const mb_device_desc *dev, const mb_scenario_desc *scen, int32_t material,
                      double *out, int64_t capacity, int64_t *n_out);
 
 /* Readout of record `record_id` for cells of material `material`:
- * out[0] + sum_a out[1+a] y_a gives the recorded density quantity from the
- * post-rotation state y (M+1 doubles). */
+ * out[0] + sum_a out[1+a] sigma_a + sum_r out[1+M+r] d_r gives the recorded
+ * density quantity from the running state sigma and the field increments d
+ * of the step (M+1+K doubles, names as for mb_plan_material). */
 int mb_plan_readout(const mb_device_desc *dev, const mb_scenario_desc *scen, int32_t record_id,
                     int32_t material, double *out, int64_t capacity);
 
@@ -253,6 +260,14 @@ int mb_plan_readout(const mb_device_desc *dev, const mb_scenario_desc *scen, int
  * the plan status. */
 int mb_plan_source(const mb_device_desc *dev, const mb_scenario_desc *scen, int32_t source_id, int64_t *node,
                    double *values, int64_t capacity, int64_t *n_out);
+
+/* 1 when the blocked kernel is built for tiles of `block` cells with `lanes`
+ * waves per 64 cells (1, 2, 4 or 8) at this level count (0 = no quantum
+ * cells, else 2..6) and precision (64 or 32), else 0.  A run asking for more
+ * lanes than are built for its tile takes the largest built count below; a
+ * block that is not built even with one lane is MB_ERR_UNSUPPORTED at set-up.
+ * Host-only. */
+int mb_tile_supported(int32_t levels, int32_t precision, int32_t block, int32_t lanes);
 
 /* ---- single simulation --------------------------------------------------- */
 

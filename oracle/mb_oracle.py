@@ -384,24 +384,39 @@ class Oracle:
 
     # -- density step ---------------------------------------------------------
     def _field_op(self, g, e_cells):
-        """Field part of the step for each cell: W = exp(A) with A = i dt E mu / hbar
-        (through the eigen-decomposition of mu), or its Cayley approximant
-        (I - A/2)^{-1} (I + A/2) when the problem asks for field_step "cayley"."""
+        """Cayley field operator (I - A/2)^{-1} (I + A/2), A = i dt E mu / hbar, for
+        problems that ask for field_step "cayley" (the exact form is applied by
+        _conjugate without forming W)."""
         n = g["n"]
+        a = 1j * self.dt / self.c["hbar"] * e_cells[:, None, None] * g["mu"][None, :, :]
+        eye = np.eye(n)[None, :, :]
+        return np.linalg.solve(eye - 0.5 * a, eye + 0.5 * a)
+
+    def _conjugate(self, g, rho, e_cells):
+        """Field part of the step for each cell: W rho W^+ with W = exp(A), A = i dt E mu
+        / hbar (Sec. 2.2; the free part is handled by the splitting around it), or
+        with the Cayley approximant of W.
+
+        In the eigenbasis of mu (mu = V diag(lam) V^+) W is diagonal, so
+        V^+ (W rho W^+) V has entries e^{i dt E (lam_j - lam_k)/hbar} (V^+ rho V)_jk.
+        The conjugation is written as rho plus its change,
+            W rho W^+ = rho + V [ (e^{i dt E (lam_j - lam_k)/hbar} - 1) (V^+ rho V)_jk ] V^+,
+        so that a zero field (W = I) leaves rho exactly as it is, as the definition
+        does, instead of passing it through V V^+ = I up to rounding."""
         if self.p.get("field_step", "exact") == "cayley":
-            a = 1j * self.dt / self.c["hbar"] * e_cells[:, None, None] * g["mu"][None, :, :]
-            eye = np.eye(n)[None, :, :]
-            return np.linalg.solve(eye - 0.5 * a, eye + 0.5 * a)
+            w = self._field_op(g, e_cells)
+            return w @ rho @ np.conj(np.transpose(w, (0, 2, 1)))
         vec, lam = g["vec"], g["lam"]
-        ph = np.exp(1j * self.dt / self.c["hbar"] * e_cells[:, None] * lam[None, :])
-        return np.einsum("ij,kj,lj->kil", vec, ph, vec.conj())
+        vh = vec.conj().T
+        rp = vh[None, :, :] @ rho @ vec[None, :, :]
+        th = self.dt / self.c["hbar"] * e_cells[:, None, None] * (lam[None, :, None] - lam[None, None, :])
+        return rho + vec[None, :, :] @ (np.expm1(1j * th) * rp) @ vh[None, :, :]
 
     def _strang(self, g, rho, e_cells):
-        """e^{L0 dt/2} [ W (e^{L0 dt/2} rho) W^+ ] for each cell (W from _field_op)."""
+        """e^{L0 dt/2} [ W (e^{L0 dt/2} rho) W^+ ] for each cell (W rho W^+ from _conjugate)."""
         k, n = rho.shape[0], g["n"]
         r = (rho.reshape(k, n * n) @ g["p_half"].T).reshape(k, n, n)
-        w = self._field_op(g, e_cells)
-        r = w @ r @ np.conj(np.transpose(w, (0, 2, 1)))
+        r = self._conjugate(g, r, e_cells)
         return (r.reshape(k, n * n) @ g["p_half"].T).reshape(k, n, n)
 
     @staticmethod
@@ -415,8 +430,7 @@ class Oracle:
         v = rho.reshape(k, n * n) @ g["p_half"].T
         rho = v.reshape(k, n, n)
         # rho <- W rho W^+ (W = exp(i dt E mu / hbar) or its Cayley approximant)
-        w = self._field_op(g, e_cells)
-        rho = w @ rho @ np.conj(np.transpose(w, (0, 2, 1)))
+        rho = self._conjugate(g, rho, e_cells)
         v = rho.reshape(k, n * n) @ g["p_half"].T
         g["rho"] = v.reshape(k, n, n)
         # polarization current n3D tr{mu L0(rho)}

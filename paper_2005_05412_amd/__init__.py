@@ -29,7 +29,7 @@ VARIANT = {"auto": 0, "plain": 1, "blocked": 2, "blocked_regs": 3}
 FIELD_STEP = {"exact": 0, "cayley": 1}    # MB_FIELD_EXACT, MB_FIELD_CAYLEY
 
 EXPORTS = [
-    "mb_last_error", "mb_device_count", "mb_plan_material", "mb_plan_readout", "mb_plan_source", "mb_workspace_bytes", "mb_setup", "mb_run", "mb_run_mode", "mb_reset", "mb_batch_reset", "mb_shape", "mb_batch_shape", "mb_steps_done", "mb_record_shape",
+    "mb_last_error", "mb_device_count", "mb_plan_material", "mb_plan_readout", "mb_plan_source", "mb_tile_supported", "mb_workspace_bytes", "mb_setup", "mb_run", "mb_run_mode", "mb_reset", "mb_batch_reset", "mb_shape", "mb_batch_shape", "mb_steps_done", "mb_record_shape",
     "mb_read_records", "mb_read_state", "mb_elapsed_ms", "mb_destroy", "mb_batch_setup", "mb_batch_run",
     "mb_batch_record_shape", "mb_batch_read_records", "mb_batch_elapsed_ms", "mb_batch_destroy",
     "mb_server_create", "mb_server_submit", "mb_server_start", "mb_server_drain", "mb_server_cancel", "mb_server_poll",
@@ -127,6 +127,7 @@ def load():
                                       C.c_int32, dp, C.c_int64]),
         "mb_plan_source": (C.c_int, [C.POINTER(mb_device_desc), C.POINTER(mb_scenario_desc), C.c_int32,
                                      i64p, dp, C.c_int64, i64p]),
+        "mb_tile_supported": (C.c_int, [C.c_int32] * 4),
         "mb_setup": (C.c_int, [C.c_int, C.POINTER(mb_device_desc), C.POINTER(mb_scenario_desc), P, C.c_size_t,
                                C.POINTER(P)]),
         "mb_workspace_bytes": (C.c_int, [C.POINTER(mb_device_desc), C.POINTER(mb_scenario_desc),
@@ -287,22 +288,27 @@ def _stream_ptr(stream):
     return C.c_void_p(stream.cuda_stream)  # torch.cuda.Stream
 
 
+# doubles of the largest mb_plan_material output (six levels)
+_PLAN_CAP = 8 * 36 * 36 + 256
+
+
 def plan_material(prob, material, precision=None):
     """Host-only FP64 tables of one material (mb_plan_material), as a dict."""
     lib = load()
     m = _Marshal(prob, precision)
-    out = np.zeros(4 * 36 * 36 + 64)
+    out = np.zeros(_PLAN_CAP)
     n = C.c_int64()
     rc = _check(lib.mb_plan_material(C.byref(m.dev), C.byref(m.scen), material, _dptr(out), out.size,
                                      C.byref(n)))
     lv = _levels(prob)
-    M = lv * lv - 1
+    M, K = lv * lv - 1, lv * (lv - 1)
     v = out[: n.value]
     d = {"status": rc}
     if n.value == 0:
         return d
     sizes = [("lam", lv), ("vec", 2 * lv * lv), ("kappa", lv - 1), ("p0", 1), ("at", M), ("ah", M * M), ("bh", M),
-             ("am", M * M), ("bf", M)]
+             ("am", M * M), ("bf", M), ("t0", K), ("tm", K * M), ("sm", M * K), ("as", K), ("bm", M * K),
+             ("lvl", lv)]
     k = 0
     for name, sz in sizes:
         d[name] = v[k:k + sz].copy()
@@ -311,6 +317,10 @@ def plan_material(prob, material, precision=None):
     d["vec"] = (d["vec"][0::2] + 1j * d["vec"][1::2]).reshape(lv, lv)
     d["ah"] = d["ah"].reshape(M, M)
     d["am"] = d["am"].reshape(M, M)
+    d["tm"] = d["tm"].reshape(K, M)
+    d["sm"] = d["sm"].reshape(M, K)
+    d["bm"] = d["bm"].reshape(M, K)
+    d["lvl"] = d["lvl"].astype(int)
     return d
 
 
@@ -319,9 +329,14 @@ def plan_readout(prob, record_id, material):
     lib = load()
     m = _Marshal(prob)
     lv = _levels(prob)
-    out = np.zeros(lv * lv)
+    out = np.zeros(lv * lv + lv * (lv - 1))
     _check(lib.mb_plan_readout(C.byref(m.dev), C.byref(m.scen), record_id, material, _dptr(out), out.size))
     return out
+
+
+def tile_supported(levels, precision, block, lanes=1):
+    """Whether the blocked kernel is built for this tile (mb_tile_supported); host-only."""
+    return bool(load().mb_tile_supported(int(levels), int(precision), int(block), int(lanes)))
 
 
 def plan_source(prob, source_id, n_values=0):
@@ -339,7 +354,7 @@ def plan_status(prob, precision=None, variant="auto", block=0, depth=0, lanes=0)
     """Status of planning a problem on the host: 0, a positive warning, or raises MBError."""
     lib = load()
     m = _Marshal(prob, precision, variant, block, depth, lanes)
-    out = np.zeros(4 * 36 * 36 + 64)
+    out = np.zeros(_PLAN_CAP)
     n = C.c_int64()
     for k, mat in enumerate(prob["materials"]):
         rc = _check(lib.mb_plan_material(C.byref(m.dev), C.byref(m.scen), k, _dptr(out), out.size, C.byref(n)))

@@ -27,9 +27,21 @@ COMMON = ["-std=c++17", "-O3", "-fPIC", "-ffp-contract=off", f"-I{INCLUDE}", f"-
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def _compile(item) -> str:
+def _deps(src: str):
+    """Files an object depends on: the kernels on their own headers, the host
+    sources on every header (they share the plan and engine structures)."""
+    heads = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+    heads += [os.path.join(INCLUDE, f) for f in os.listdir(INCLUDE) if f.endswith(".h")]
+    if src.endswith(".hip"):
+        heads = [h for h in heads if os.path.basename(h) in ("engine.hpp", "launch.hpp")]
+    return [os.path.join(CSRC, src)] + heads
+
+
+def _compile(item, incremental=False) -> str:
     src, extra, name = item
     obj = os.path.join(OBJ, name + ".o")
+    if incremental and os.path.exists(obj) and os.path.getmtime(obj) > max(map(os.path.getmtime, _deps(src))):
+        return obj
     cmd = [HIPCC] + COMMON + DEVICE + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
     if not src.endswith(".hip"):
         cmd = [HIPCC] + COMMON + extra + ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-c",
@@ -41,10 +53,12 @@ def _compile(item) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compiles every source (incremental: only objects older than their
+    sources or headers) and links libmbhip.so."""
     os.makedirs(OBJ, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda it: _compile(it, incremental), SOURCES))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -58,4 +72,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)

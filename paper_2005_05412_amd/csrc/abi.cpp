@@ -165,7 +165,7 @@ int shape_for(const SimPlan &p, int &block, int &halo, int &lanes) {
   if (p.lanes > 0) lanes = p.lanes;
   if (p.variant == MB_VARIANT_PLAIN) return MB_OK;
   if (!block_supported(block) || halo < 1 || 2 * halo >= block)
-    return fail(MB_ERR_ARG, "blocked variant needs block in {64,...,1024} and 1 <= depth < block/2");
+    return fail(MB_ERR_ARG, "blocked variant needs block in {64,...,512} and 1 <= depth < block/2");
   return MB_OK;
 }
 
@@ -212,7 +212,9 @@ int mb_plan_material(const mb_device_desc *dev, const mb_scenario_desc *scen, in
     }
     v.insert(v.end(), mp.kappa.begin(), mp.kappa.end());
     v.push_back(mp.p0);
-    for (auto *t : {&mp.at, &mp.ah, &mp.bh, &mp.am, &mp.bf}) v.insert(v.end(), t->begin(), t->end());
+    for (auto *t : {&mp.at, &mp.ah, &mp.bh, &mp.am, &mp.bf, &mp.t0, &mp.tm, &mp.sm, &mp.as, &mp.bm})
+      v.insert(v.end(), t->begin(), t->end());
+    for (int l : mp.lvl) v.push_back(double(l));
   }
   if (int64_t(v.size()) > capacity) return fail(MB_ERR_ARG, "output buffer too small");
   if (!v.empty()) std::memcpy(out, v.data(), v.size() * sizeof(double));
@@ -232,12 +234,18 @@ int mb_plan_readout(const mb_device_desc *dev, const mb_scenario_desc *scen, int
   if (record_id < 0 || record_id >= int(plan.records.size())) return fail(MB_ERR_ARG, "bad record id");
   if (material < 0 || material >= int(plan.mats.size())) return fail(MB_ERR_ARG, "bad material index");
   const RecordPlan &rp = plan.records[record_id];
-  const int m1 = plan.m + 1;
+  const int m1 = ro_len(plan.n);
   if (rp.readout.empty() || !plan.mats[material].qm) return fail(MB_ERR_ARG, "no density readout for this pair");
   if (capacity < m1) return fail(MB_ERR_ARG, "output buffer too small");
   std::memcpy(out, rp.readout.data() + size_t(material) * m1, size_t(m1) * sizeof(double));
   return MB_OK;
   MB_GUARD_END
+}
+
+int mb_tile_supported(int32_t levels, int32_t precision, int32_t block, int32_t lanes) {
+  if ((levels != 0 && (levels < 2 || levels > 6)) || (precision != 32 && precision != 64)) return 0;
+  if (lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8) return 0;
+  return shape_supported(levels, precision, block, lanes) ? 1 : 0;
 }
 
 int mb_plan_source(const mb_device_desc *dev, const mb_scenario_desc *scen, int32_t source_id, int64_t *node,

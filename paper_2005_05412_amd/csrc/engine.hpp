@@ -6,18 +6,34 @@
 namespace mb {
 
 // Per-material coefficient block, element type R (float or double), stride
-// mat_stride(N):  [0] a'  [1] b' Gamma  [2] b'/dx  [3] c' (for H nodes)
-// [4] 1 if the material has quantum systems, then kappa[N-1], p0, at[M],
-// bf[M], am[M*M] (row-major, e^{L0 dt} - I), sigma[N] (dt lam_j / hbar, the
-// dipole eigenvalues; Cayley field step).  kappa[q] = sigma[q] - sigma[q+1].
+// mat_stride(N).  The density state x (M = N*N - 1 reals) is kept in the basis
+// the operators are given in; the field part is applied through the (Re, Im)
+// coordinates z (K = N*(N-1) reals) of the coherences in the dipole eigenbasis.
+//   [0] a'  [1] b' Gamma  [2] b'/dx  [3] c' (for H nodes)  [4] 1 if quantum
+//   kappa[N-1]          dt (lam_q - lam_{q+1}) / hbar, consecutive eigenvalue gaps
+//   p0, at[M], as[K]    polarization p = p0 + at . x + as . d
+//   bf[M]               affine part of e^{L0 dt}
+//   prop[M][M+K]        row i: (e^{L0 dt} - I)_i (M), then (e^{L0 dt} S)_i (K)
+//   t0[K], tm[K][M]     z = t0 + tm x
+//   sigma[N]            dt lam_j / hbar (Cayley field step)
+// where d = (e^{i theta} - 1) z pairwise and S maps d back to the state
+// coordinates; one step is x <- x + bf + (A - I) x + (A S) d.
 constexpr int kCoefA = 0, kCoefBG = 1, kCoefBD = 2, kCoefH = 3, kCoefQM = 4, kCoefKap = 5;
 __host__ __device__ constexpr int mat_m(int n) { return n > 0 ? n * n - 1 : 0; }
+__host__ __device__ constexpr int mat_k(int n) { return n > 0 ? n * (n - 1) : 0; }
 __host__ __device__ constexpr int coef_p0(int n) { return kCoefKap + (n > 0 ? n - 1 : 0); }
 __host__ __device__ constexpr int coef_at(int n) { return coef_p0(n) + 1; }
-__host__ __device__ constexpr int coef_bf(int n) { return coef_at(n) + mat_m(n); }
+__host__ __device__ constexpr int coef_as(int n) { return coef_at(n) + mat_m(n); }
+__host__ __device__ constexpr int coef_bf(int n) { return coef_as(n) + mat_k(n); }
 __host__ __device__ constexpr int coef_am(int n) { return coef_bf(n) + mat_m(n); }
-__host__ __device__ constexpr int coef_sg(int n) { return coef_am(n) + mat_m(n) * mat_m(n); }
+__host__ __device__ constexpr int prop_w(int n) { return mat_m(n) + mat_k(n); }
+__host__ __device__ constexpr int coef_t0(int n) { return coef_am(n) + mat_m(n) * prop_w(n); }
+__host__ __device__ constexpr int coef_tm(int n) { return coef_t0(n) + mat_k(n); }
+__host__ __device__ constexpr int coef_sg(int n) { return coef_tm(n) + mat_k(n) * mat_m(n); }
 __host__ __device__ constexpr int mat_stride(int n) { return n > 0 ? coef_sg(n) + n : kCoefKap; }
+// FP64 readout row of a density record (and the strong-coupling trace) per
+// material: value = r0 + r . x + rs . d, length ro_len(N)
+__host__ __device__ constexpr int ro_len(int n) { return mat_m(n) + 1 + mat_k(n); }
 
 struct DevSource {
   int64_t cell;
@@ -32,7 +48,7 @@ struct DevRecord {
   int64_t cell;
   int64_t interval;
   double *out;          // samples (x nx when whole)
-  const double *readout;  // density quantities: per material (M+1) doubles
+  const double *readout;  // density quantities: per material ro_len(N) doubles
 };
 
 struct DevSim {
@@ -57,7 +73,7 @@ struct DevSim {
   int32_t rec_every;         // gcd of the record intervals (1 when there are no records)
   int32_t cayley;            // field part by the Cayley approximant (MB_FIELD_CAYLEY)
   // strong coupling: (n3D/dt) tr{mu rho^n} per cell (FP64 ping-pong like x) and per
-  // material its readout (qc, aq[M]) from the rotated state
+  // material its readout (qc, aq[M], aqs[K]) from the state and the field increments
   double *qs[2];
   const double *qtab;
 };

@@ -158,56 +158,78 @@ __device__ __forceinline__ void phase(R t, R &cm, R &sn) {
     phase_general(t, cm, sn);
 }
 
+// Work of a cell's density update shared out over L wave groups: the
+// eigenbasis coherence pairs (two rows of z each, M multiply-adds per row) and
+// the rows of the state (M + K multiply-adds each), each given in turn to the
+// least loaded group.
 template <int N, int L>
 struct Split {
   static constexpr int M = mat_m(N);
   static constexpr int P = N > 0 ? N * (N - 1) / 2 : 0;
-  static constexpr int owner(int a) {
+  // item u < P: pair u; item P + a: state row a
+  static constexpr int owner(int item) {
     if (L == 1) return 0;
-    if (a >= N - 1) return ((a - (N - 1)) / 2) % L;
     int load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int q = 0; q < P; ++q) load[q % L] += 2;
     int who = 0;
-    for (int u = 0; u <= a; ++u) {
+    for (int u = 0; u <= item; ++u) {
+      const int cost = u < P ? 2 * M : M + 2 * P;
       int best = 0;
       for (int g = 1; g < L; ++g)
         if (load[g] < load[best]) best = g;
-      load[best] += 1;
+      load[best] += cost;
       who = best;
     }
     return who;
   }
-  static constexpr bool owns(int sub, int a) { return L == 1 || owner(a) == sub; }
+  static constexpr bool owns(int sub, int a) { return L == 1 || owner(P + a) == sub; }
+  static constexpr bool owns_z(int sub, int r) { return L == 1 || owner(r / 2) == sub; }
 };
 
 template <int N, typename R>
 struct Cell {
   static constexpr int M = mat_m(N);
   static constexpr int MA = M > 0 ? M : 1;
+  static constexpr int K = mat_k(N);
+  static constexpr int KA = K > 0 ? K : 1;
 
-  // y <- Phi_E(y): coherence (j, k), j < k, of the state in the dipole
-  // eigen-basis gains the phase theta_jk = dt E (lam_j - lam_k)/hbar, the
-  // sum of the consecutive angles E kappa_q; each phase is carried as
-  // (cos - 1, sin) and applied as a small increment.
-  // (with L > 1 only the coherences of rows owned by group SUB are rotated;
-  // the composed phases are the same for every split)
+  // entry t of the vector (x, d): the state, then the field increments
+  static __device__ __forceinline__ R xd(const R (&x)[MA], const R (&d)[KA], int t) { return t < M ? x[t] : d[t - M]; }
+
+  // z <- t0 + tm x: (Re, Im) of the coherences of the state in the dipole
+  // eigenbasis (with L > 1 the rows of the pairs owned by group SUB)
+  template <int L = 1, int SUB = 0, typename C>
+  static __device__ __forceinline__ void coherences(const R (&x)[MA], R (&z)[KA], const C &mt) {
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      if (!Split<N, L>::owns_z(SUB, r)) continue;
+      R acc = mt[coef_t0(N) + r];
+#pragma unroll
+      for (int j = 0; j < M; ++j) acc = fma(mt[coef_tm(N) + r * M + j], x[j], acc);
+      z[r] = acc;
+    }
+  }
+
+  // z <- d = (e^{i theta_jk} - 1) z_jk: the change of eigenbasis coherence
+  // (j, k), j < k, under the field conjugation, theta_jk = dt E (lam_j -
+  // lam_k)/hbar, the sum of the consecutive angles E kappa_q; each phase is
+  // carried as (cos - 1, sin), so the increment has no cancellation.
   // cay: the Cayley approximant of the field exponential instead: level j's
   // factor (1 + i x_j)/(1 - i x_j), x_j = E sigma_j / 2, so the consecutive
   // pair (q, q+1) turns by u/conj(u), u = 1 + x_q x_{q+1} + i (x_q - x_{q+1}):
   // cos - 1 = -2 d^2/|u|^2 and sin = 2 s d/|u|^2 with d = x_q - x_{q+1} and
   // s = 1 + x_q x_{q+1} (no cancellation for small angles).
-  template <int L = 1, int SUB = 0, typename C>
-  static __device__ __forceinline__ void rotate(R (&y)[MA], R e, const C &mt, bool cay = false) {
+  template <typename C>
+  static __device__ __forceinline__ void increments(R (&z)[KA], R e, const C &mt, bool cay = false) {
     if constexpr (N >= 2) {
       R cm[N - 1], sn[N - 1];
       if (cay) {
 #pragma unroll
         for (int q = 0; q < N - 1; ++q) {
           const R a = R(0.5) * e * mt[coef_sg(N) + q], b = R(0.5) * e * mt[coef_sg(N) + q + 1];
-          const R d = a - b, s = fma(a, b, R(1));
-          const R inv = R(1) / fma(s, s, d * d);
-          cm[q] = R(-2) * (d * d) * inv;
-          sn[q] = R(2) * (s * d) * inv;
+          const R dd = a - b, s = fma(a, b, R(1));
+          const R inv = R(1) / fma(s, s, dd * dd);
+          cm[q] = R(-2) * (dd * dd) * inv;
+          sn[q] = R(2) * (s * dd) * inv;
         }
       } else {
 #pragma unroll
@@ -226,54 +248,54 @@ struct Cell {
             pc = nc;
             ps = ns;
           }
-          const int p = k * (k - 1) / 2 + j;
-          const int ir = N - 1 + 2 * p, ii = ir + 1;
-          if (Split<N, L>::owns(SUB, ir)) {
-            const R re = y[ir], im = y[ii];
-            y[ir] = re + fma(re, pc, -(im * ps));
-            y[ii] = im + fma(re, ps, im * pc);
-          }
+          const int ir = 2 * (k * (k - 1) / 2 + j), ii = ir + 1;
+          const R re = z[ir], im = z[ii];
+          z[ir] = fma(re, pc, -(im * ps));
+          z[ii] = fma(re, ps, im * pc);
         }
       }
     }
   }
 
-  // polarization current n3D tr{mu L0(rho^{n+1/2})} = at . y + p0 (two
-  // interleaved partial sums for instruction-level parallelism)
+  // polarization current n3D tr{mu L0(rho^{n+1/2})} = p0 + at . x + as . d
+  // (two interleaved partial sums for instruction-level parallelism)
   template <typename C>
-  static __device__ __forceinline__ R polar(const R (&y)[MA], const C &mt) {
+  static __device__ __forceinline__ R polar(const R (&x)[MA], const R (&d)[KA], const C &mt) {
     R acc0 = mt[coef_p0(N)], acc1 = R(0);
 #pragma unroll
-    for (int j = 0; j + 1 < M; j += 2) {
-      acc0 = fma(mt[coef_at(N) + j], y[j], acc0);
-      acc1 = fma(mt[coef_at(N) + j + 1], y[j + 1], acc1);
+    for (int t = 0; t + 1 < M + K; t += 2) {
+      acc0 = fma(mt[coef_at(N) + t], xd(x, d, t), acc0);
+      acc1 = fma(mt[coef_at(N) + t + 1], xd(x, d, t + 1), acc1);
     }
-    if constexpr (M % 2 == 1) acc0 = fma(mt[coef_at(N) + M - 1], y[M - 1], acc0);
+    if constexpr ((M + K) % 2 == 1) acc0 = fma(mt[coef_at(N) + M + K - 1], xd(x, d, M + K - 1), acc0);
     return acc0 + acc1;
   }
 
-  // sigma_{n+1} = e^{L0 dt} y = y + (bf + am y); with L > 1 the rows owned
-  // by group SUB (the others are left as they are)
+  // sigma_{n+1} = e^{L0 dt} (x + S d): x_i <- x_i + (bf_i + (A - I)_i x +
+  // (A S)_i d); with L > 1 the rows owned by group SUB (the others are left
+  // as they are)
   template <int L = 1, int SUB = 0, typename C>
-  static __device__ __forceinline__ void propagate(R (&y)[MA], const C &mt) {
+  static __device__ __forceinline__ void propagate(R (&x)[MA], const R (&d)[KA], const C &mt) {
     R out[MA];
 #pragma unroll
     for (int i = 0; i < M; ++i) {
       if (!Split<N, L>::owns(SUB, i)) continue;
       R acc = mt[coef_bf(N) + i];
 #pragma unroll
-      for (int j = 0; j < M; ++j) acc = fma(mt[coef_am(N) + i * M + j], y[j], acc);
-      out[i] = y[i] + acc;
+      for (int t = 0; t < M + K; ++t) acc = fma(mt[coef_am(N) + i * (M + K) + t], xd(x, d, t), acc);
+      out[i] = x[i] + acc;
     }
 #pragma unroll
     for (int i = 0; i < M; ++i)
-      if (Split<N, L>::owns(SUB, i)) y[i] = out[i];
+      if (Split<N, L>::owns(SUB, i)) x[i] = out[i];
   }
 
-  static __device__ __forceinline__ double readout(const R (&y)[MA], const double *__restrict__ ro) {
+  // FP64 readout r0 + r . x + rs . d of a density quantity of rho^{n+1/2}
+  static __device__ __forceinline__ double readout(const R (&x)[MA], const R (&d)[KA],
+                                                   const double *__restrict__ ro) {
     double acc = ro[0];
 #pragma unroll
-    for (int j = 0; j < M; ++j) acc = fma(ro[1 + j], double(y[j]), acc);
+    for (int t = 0; t < M + K; ++t) acc = fma(ro[1 + t], double(xd(x, d, t)), acc);
     return acc;
   }
 };
@@ -282,13 +304,12 @@ __device__ __forceinline__ bool due(uint32_t n1, int64_t interval) { return n1 %
 
 template <int N, typename R>
 __device__ __forceinline__ void record_density_all(const DevSim &sim, int c, uint32_t n1, int mat,
-                                                const R (&y)[Cell<N, R>::MA]) {
-  constexpr int M = Cell<N, R>::M;
+                                                const R (&x)[Cell<N, R>::MA], const R (&d)[Cell<N, R>::KA]) {
   for (int32_t r = 0; r < sim.n_rec_all; ++r) {
     const DevRecord &rc = sim.rec[sim.rec_all[r]];
     if (rc.quantity < 2 || !due(n1, rc.interval)) continue;
     rc.out[size_t(n1 / uint32_t(rc.interval) - 1) * size_t(sim.nx) + c] =
-        Cell<N, R>::readout(y, rc.readout + mat * (M + 1));
+        Cell<N, R>::readout(x, d, rc.readout + mat * ro_len(N));
   }
 }
 
@@ -296,14 +317,14 @@ __device__ __forceinline__ void record_density_all(const DevSim &sim, int c, uin
 // entries [rb, re) of the per-cell record table, then the whole-domain records
 template <int N, typename R>
 __device__ __forceinline__ void record_density(const DevSim &sim, int c, uint32_t n1, int mat,
-                                            const R (&y)[Cell<N, R>::MA], int rb, int re) {
-  constexpr int M = Cell<N, R>::M;
+                                            const R (&x)[Cell<N, R>::MA], const R (&d)[Cell<N, R>::KA], int rb,
+                                            int re) {
   for (int32_t r = rb; r < re; ++r) {
     const DevRecord &rc = sim.rec_cell[r];
     if (rc.quantity < 2 || !due(n1, rc.interval)) continue;
-    rc.out[n1 / uint32_t(rc.interval) - 1] = Cell<N, R>::readout(y, rc.readout + mat * (M + 1));
+    rc.out[n1 / uint32_t(rc.interval) - 1] = Cell<N, R>::readout(x, d, rc.readout + mat * ro_len(N));
   }
-  record_density_all<N, R>(sim, c, n1, mat, y);
+  record_density_all<N, R>(sim, c, n1, mat, x, d);
 }
 
 // value of a field record (E^{n+1}, H^{n+1/2}; density quantities read zero
@@ -357,7 +378,7 @@ constexpr int kTileRecs = 16;
 
 template <int N>
 struct TileRecs {
-  static constexpr int RO = mat_m(N) + 1;
+  static constexpr int RO = ro_len(N);
   double *out[kTileRecs];
   int64_t n_out[kTileRecs];  // samples the output holds
   uint32_t mult[kTileRecs];
@@ -385,17 +406,18 @@ struct TileRecs {
     return at < n_out[r] ? at : -1;
   }
 
-  // same arithmetic as Cell::readout
-  template <typename R, int MA>
-  // entries rb, rb + step, ... below re
-  __device__ __forceinline__ void density(uint32_t q, const R (&y)[MA], int rb, int re, int step) const {
+  // same arithmetic as Cell::readout; entries rb, rb + step, ... below re
+  template <typename R, int MA, int KA>
+  __device__ __forceinline__ void density(uint32_t q, const R (&x)[MA], const R (&d)[KA], int rb, int re,
+                                          int step) const {
+    constexpr int M = mat_m(N);
     for (int r = rb; r < re; r += step) {
       if (quantity[r] < 2) continue;
       const int64_t at = sample(r, q);
       if (at < 0) continue;
       double acc = ro[r][0];
 #pragma unroll
-      for (int j = 0; j < RO - 1; ++j) acc = fma(ro[r][1 + j], double(y[j]), acc);
+      for (int t = 0; t < RO - 1; ++t) acc = fma(ro[r][1 + t], double(t < M ? x[t] : d[t - M]), acc);
       out[r][at] = acc;
     }
   }
@@ -441,19 +463,26 @@ __device__ __forceinline__ R apply_sources(const DevSim &sim, int c, uint32_t n1
 // computation of overlapped tiles), and writes the owned cells to the other
 // state buffer.  With L > 1 the workgroup holds L waves per 64 cells: every
 // wave group keeps E and H of all B cells (the field updates are repeated)
-// and advances only its own rows of the density state; the rotated rows are
-// exchanged through LDS once per step, so each group sees the whole state for
-// the polarization, the records and its rows of the propagator.  The
-// arithmetic per cell is the same for every B, L and coefficient placement.
+// and computes only its own eigenbasis coherences and rows of the density
+// state; both are exchanged through LDS every step (one barrier each), so
+// each group sees the whole state and all field increments for the
+// polarization, the records and its rows of the propagator.  The arithmetic
+// per cell is the same for every B, L and coefficient placement.
 // ---------------------------------------------------------------------------
 template <int N, typename R, int B, int L>
 struct TileShared {
   static constexpr int GM = L > 1 ? mat_m(N) : 1;
+  static constexpr int GK = L > 1 && N > 0 ? mat_k(N) : 1;
   static constexpr int GB = L > 1 ? B : 1;
   R se[2][B], se2[B];  // E exchange (double-buffered by step parity), Mur exchange
   R src[kTileSources][kMaxChunk];
   TileRecs<N> trec;
-  R sy[2][GM][GB];  // rotated density rows of every cell (L > 1), by step parity
+  // density rows and eigenbasis coherences of every cell (L > 1).  One buffer
+  // each suffices: the rows are read after a step's first barrier and
+  // rewritten after its second, the coherences written after the first and
+  // read after the second.
+  R sx[GM][GB];
+  R sz[GK][GB];
   int stop;         // a neighbour wait gave up: the tile ends the launch
 };
 
@@ -486,14 +515,22 @@ __device__ __forceinline__ bool neighbours_reached(const ChunkSync &cs, const De
   }
 }
 
-// split tiles stay at <= 512 threads (a 1024-thread workgroup caps a wave at
-// 128 registers, below what most density updates need), except FP32 with up
-// to 3 levels, whose waves fit in 128
+// tiles stay at <= 512 threads (a 1024-thread workgroup caps a wave at 128
+// registers, below what most density updates need), except split FP32 tiles
+// with up to 3 levels, whose waves fit in 128; five and six levels use at most
+// 256 threads (their waves need the full register file)
 template <int N, typename R, int B, int L>
 constexpr bool shape_fits() {
-  constexpr int max_threads = (N <= 3 && sizeof(R) == 4) ? 1024 : 512;
-  return (L == 1 || (N >= 2 && B * L <= max_threads && (L < 8 || N >= 4))) &&
+  constexpr int max_threads = N >= 5 ? 256 : (N <= 3 && sizeof(R) == 4 && L > 1) ? 1024 : 512;
+  return B * L <= max_threads && (L == 1 || (N >= 2 && (L < 8 || N >= 4))) &&
          sizeof(TileShared<N, R, B, L>) <= 65536;
+}
+
+// coefficients in registers: two levels, and three levels in FP32 with one
+// wave per 64 cells and at most 256 cells (beyond that the registers spill)
+template <int N, typename R, int B, int L>
+constexpr bool regs_fit() {
+  return N == 2 || (N == 3 && sizeof(R) == 4 && L == 1 && B <= 256);
 }
 
 // P: a persistent launch (several chunks, neighbour flags, device-coherent
@@ -629,9 +666,11 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
   auto coef_used = [](int i) {
     const int t = i + kCoefKap;
     if (t >= coef_sg(N)) return CY;  // Cayley coefficients (every wave group rotates)
-    if (t < coef_bf(N)) return true;
+    if (t < coef_bf(N)) return true;  // phases and polarization
     if (t < coef_am(N)) return SP::owns(SUB, t - coef_bf(N));
-    return SP::owns(SUB, (t - coef_am(N)) / (M > 0 ? M : 1));
+    if (t < coef_t0(N)) return SP::owns(SUB, (t - coef_am(N)) / prop_w(N));
+    if (t < coef_tm(N)) return SP::owns_z(SUB, t - coef_t0(N));
+    return SP::owns_z(SUB, (t - coef_tm(N)) / (M > 0 ? M : 1));
   };
   // (each lane holds its own cell's material, so waves across a material
   // boundary cost the same as single-material ones)
@@ -667,19 +706,16 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
 
   R e = 0, h = 0, hl = 0;
   R x[MA];
+  R z[CL::KA];      // eigenbasis coherences of x, then the field increments d
   double qn = 0.0;  // strong coupling: (n3D/dt) tr{mu rho^n} of the cell, carried in FP64
 
-  // density rows of this wave group rotated by the field phases of E and
-  // published for the other groups (L > 1); the rotation of step s + 1 runs
-  // at the end of step s, so one barrier per step covers E and the rows
-  auto rotate_publish = [&](int buf) {
+  // density rows of this wave group published for the other groups (L > 1);
+  // they are read after the next step's E exchange barrier
+  auto publish_x = [&]() {
     if constexpr (L > 1 && N > 0) {
-      per_material([&](const auto &mt, int) {
-        CL::template rotate<L, SUB>(x, e, mt, cay);
 #pragma unroll
-        for (int a = 0; a < M; ++a)
-          if (SP::owns(SUB, a)) sm.sy[buf][a][l] = x[a];
-      });
+      for (int a = 0; a < M; ++a)
+        if (SP::owns(SUB, a)) sm.sx[a][l] = x[a];
     }
   };
 
@@ -701,6 +737,8 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
     e = h = hl = 0;
 #pragma unroll
     for (int a = 0; a < MA; ++a) x[a] = 0;
+#pragma unroll
+    for (int a = 0; a < CL::KA; ++a) z[a] = 0;
     if (in) {
       e = ld(e_in + c);
       h = ld(h_in + c);
@@ -723,7 +761,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
     uint32_t rec_q = uint32_t(ls0) / rec_every + 1u;
     if constexpr (WAVE) __syncthreads();  // staged source values and records visible
 
-    rotate_publish(0);
+    publish_x();
 
     for (int s = 0; s < ks; ++s) {
       const uint32_t n1 = uint32_t(ls0 + s + 1);
@@ -746,7 +784,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
         if (qm) {
 #pragma unroll
           for (int a = 0; a < M; ++a)
-            if (!SP::owns(SUB, a)) x[a] = sm.sy[buf][a][l];
+            if (!SP::owns(SUB, a)) x[a] = sm.sx[a][l];
         }
       }
       h = hcell ? fma(ch, er - e, h) : h;
@@ -757,42 +795,55 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
         // rho^{n+1}, driven by (E^n + E^{n+1})/2; fixed-point iteration from the
         // field without polarization
         per_material([&](const auto &mt, int mm) {
-          const cptr<double> qt = kconst<double>(sim.qtab) + __builtin_amdgcn_readfirstlane(mm * (M + 1));
+          const cptr<double> qt = kconst<double>(sim.qtab) + __builtin_amdgcn_readfirstlane(mm * ro_len(N));
+          CL::coherences(x, z, mt);
           R pi = 0;
           for (int it = 0; it < kStrongIters; ++it) {
             const R es = fma(cbd, h - hl, fma(ca, e, -(cbg * pi)));
-            R yv[MA];
+            R dv[CL::KA];
 #pragma unroll
-            for (int a = 0; a < MA; ++a) yv[a] = x[a];
-            CL::rotate(yv, R(0.5) * (e + es), mt, cay);
+            for (int a = 0; a < CL::KA; ++a) dv[a] = z[a];
+            CL::increments(dv, R(0.5) * (e + es), mt, cay);
             double tq = qt[0];
 #pragma unroll
-            for (int j = 0; j < M; ++j) tq = fma(qt[1 + j], double(yv[j]), tq);
+            for (int t = 0; t < M + CL::K; ++t) tq = fma(qt[1 + t], double(CL::xd(x, dv, t)), tq);
             pi = R(tq - qn);
           }
           p = pi;
         });
       } else if constexpr (N > 0) {
         auto finish = [&](const auto &mt, int mm) {
-          p = CL::polar(x, mt);
+          CL::increments(z, e, mt, cay);
+          p = CL::polar(x, z, mt);
           if (rec_step) {
             if (rec_here) {
               if (rec_lds) {
-                sm.trec.density(rq, x, rb + SUB, re, RS);
-                if (SUB == 0) record_density_all<N, R>(sim, c, n1, mm, x);
+                sm.trec.density(rq, x, z, rb + SUB, re, RS);
+                if (SUB == 0) record_density_all<N, R>(sim, c, n1, mm, x, z);
               } else {
-                record_density<N, R>(sim, c, n1, mm, x, rb, re);
+                record_density<N, R>(sim, c, n1, mm, x, z, rb, re);
               }
             }
           }
-          CL::template propagate<L, SUB>(x, mt);
+          CL::template propagate<L, SUB>(x, z, mt);
         };
         if constexpr (L == 1) {
           per_material([&](const auto &mt, int mm) {
-            CL::rotate(x, e, mt, cay);
+            CL::coherences(x, z, mt);
             finish(mt, mm);
           });
         } else {
+          // this group's coherence rows, exchanged through LDS
+          per_material([&](const auto &mt, int) { CL::template coherences<L, SUB>(x, z, mt); });
+#pragma unroll
+          for (int r = 0; r < CL::K; ++r)
+            if (SP::owns_z(SUB, r)) sm.sz[r][l] = z[r];
+          __syncthreads();
+          if (qm) {
+#pragma unroll
+            for (int r = 0; r < CL::K; ++r)
+              if (!SP::owns_z(SUB, r)) z[r] = sm.sz[r][l];
+          }
           per_material(finish);
         }
       }
@@ -827,23 +878,23 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
         // rho^{n+1} with the final E^{n+1}: rotation by the midpoint field, the
         // new tr{mu rho}, records of rho^{n+1}, propagation of the running state
         per_material([&](const auto &mt, int mm) {
-          const cptr<double> qt = kconst<double>(sim.qtab) + __builtin_amdgcn_readfirstlane(mm * (M + 1));
-          CL::rotate(x, R(0.5) * (eo + e), mt, cay);
+          const cptr<double> qt = kconst<double>(sim.qtab) + __builtin_amdgcn_readfirstlane(mm * ro_len(N));
+          CL::increments(z, R(0.5) * (eo + e), mt, cay);
           double tq = qt[0];
 #pragma unroll
-          for (int j = 0; j < M; ++j) tq = fma(qt[1 + j], double(x[j]), tq);
+          for (int t = 0; t < M + CL::K; ++t) tq = fma(qt[1 + t], double(CL::xd(x, z, t)), tq);
           qn = tq;
           if (rec_step) {
             if (rec_here) {
               if (rec_lds) {
-                sm.trec.density(rq, x, rb + SUB, re, RS);
-                if (SUB == 0) record_density_all<N, R>(sim, c, n1, mm, x);
+                sm.trec.density(rq, x, z, rb + SUB, re, RS);
+                if (SUB == 0) record_density_all<N, R>(sim, c, n1, mm, x, z);
               } else {
-                record_density<N, R>(sim, c, n1, mm, x, rb, re);
+                record_density<N, R>(sim, c, n1, mm, x, z, rb, re);
               }
             }
           }
-          CL::propagate(x, mt);
+          CL::propagate(x, z, mt);
         });
       }
       if (rec_step) {
@@ -856,7 +907,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
           }
         }
       }
-      if (s + 1 < ks) rotate_publish(buf ^ 1);
+      if (s + 1 < ks) publish_x();
     }
     if (own) {
       R *__restrict__ e_out = static_cast<R *>(sim.e[par ^ 1]);
@@ -978,13 +1029,14 @@ __global__ void __launch_bounds__(kPlainBlock) k_plain_hd(const DevSim *__restri
       const bool mine = qm && me == mm;
       if (mine) {
         const cptr<R> mt = mtab + __builtin_amdgcn_readfirstlane(mm * S);  // uniform: scalar loads
-        R x[MA];
+        R x[MA], z[CL::KA];
 #pragma unroll
         for (int a = 0; a < M; ++a) x[a] = xx[a * nx + c];
-        CL::rotate(x, e, mt, sim.cayley != 0);
-        p = CL::polar(x, mt);
-        if (rec_now) record_density<N, R>(sim, c, n1, mm, x, rb, re);
-        CL::propagate(x, mt);
+        CL::coherences(x, z, mt);
+        CL::increments(z, e, mt, sim.cayley != 0);
+        p = CL::polar(x, z, mt);
+        if (rec_now) record_density<N, R>(sim, c, n1, mm, x, z, rb, re);
+        CL::propagate(x, z, mt);
 #pragma unroll
         for (int a = 0; a < M; ++a) xx[a * nx + c] = x[a];
       }
@@ -1058,7 +1110,11 @@ __global__ void __launch_bounds__(kPlainBlock) k_plain_e(const DevSim *__restric
 template <int N, typename R, int B, int L, bool VC, bool ST, bool P, bool CY>
 hipError_t launch_shape(const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo,
                         int k, const ChunkSync &cs, int *per_cu, hipStream_t st) {
-  if constexpr (shape_fits<N, R, B, L>() && (!ST || (L == 1 && !VC && N >= 2)) && (!CY || N >= 2)) {
+  if constexpr (VC && !regs_fit<N, R, B, L>()) {
+    // register coefficients are not built for this shape: the same arithmetic
+    // with scalar coefficient loads
+    return launch_shape<N, R, B, L, false, ST, P, CY>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+  } else if constexpr (shape_fits<N, R, B, L>() && (!ST || (L == 1 && !VC && N >= 2)) && (!CY || N >= 2)) {
     auto kern = k_blocked<N, R, B, L, VC, ST, P, CY>;
     if (per_cu) return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kern, B * L, 0);
     kern<<<n_tiles, B * L, 0, st>>>(sims, tiles, n0, parity, halo, k, cs);
@@ -1077,7 +1133,6 @@ hipError_t launch_blocked_b(int block, const DevSim *sims, const DevTile *tiles,
     case 192: return launch_shape<N, R, 192, L, VC, ST, P, CY>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
     case 256: return launch_shape<N, R, 256, L, VC, ST, P, CY>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
     case 512: return launch_shape<N, R, 512, L, VC, ST, P, CY>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
-    case 1024: return launch_shape<N, R, 1024, L, VC, ST, P, CY>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
   }
   return hipErrorInvalidValue;
 }
@@ -1155,7 +1210,6 @@ bool fits_n(int block, int lanes) {
       case 192: return shape_fits<N, R, 192, Lc>();
       case 256: return shape_fits<N, R, 256, Lc>();
       case 512: return shape_fits<N, R, 512, Lc>();
-      case 1024: return shape_fits<N, R, 1024, Lc>();
     }
     return false;
   };
@@ -1164,6 +1218,18 @@ bool fits_n(int block, int lanes) {
     case 2: return f(std::integral_constant<int, 2>());
     case 4: return f(std::integral_constant<int, 4>());
     case 8: return N >= 4 && f(std::integral_constant<int, 8>());
+  }
+  return false;
+}
+
+template <int N, typename R>
+bool regs_n(int block, int lanes) {
+  switch (block) {
+    case 64: return lanes == 1 ? regs_fit<N, R, 64, 1>() : regs_fit<N, R, 64, 2>();
+    case 128: return lanes == 1 ? regs_fit<N, R, 128, 1>() : regs_fit<N, R, 128, 2>();
+    case 192: return lanes == 1 ? regs_fit<N, R, 192, 1>() : regs_fit<N, R, 192, 2>();
+    case 256: return lanes == 1 ? regs_fit<N, R, 256, 1>() : regs_fit<N, R, 256, 2>();
+    case 512: return lanes == 1 ? regs_fit<N, R, 512, 1>() : regs_fit<N, R, 512, 2>();
   }
   return false;
 }
@@ -1241,9 +1307,7 @@ hipError_t launch_blocked_f64pc(MB_LAUNCH_ARGS) { return launch_blocked_r<double
 #endif
 
 #if MB_PART == 0 || MB_PART == 2
-bool block_supported(int block) {
-  return block == 64 || block == 128 || block == 192 || block == 256 || block == 512 || block == 1024;
-}
+bool block_supported(int block) { return block == 64 || block == 128 || block == 192 || block == 256 || block == 512; }
 
 bool shape_supported(int levels, int precision, int block, int lanes) {
   if (!block_supported(block)) return false;
@@ -1251,6 +1315,15 @@ bool shape_supported(int levels, int precision, int block, int lanes) {
 }
 
 int plain_block() { return kPlainBlock; }
+
+bool regs_supported(int levels, int precision, int block, int lanes) {
+  if (!shape_supported(levels, precision, block, lanes)) return false;
+  switch (levels) {
+    case 2: return precision == 64 ? regs_n<2, double>(block, lanes) : regs_n<2, float>(block, lanes);
+    case 3: return precision == 64 ? regs_n<3, double>(block, lanes) : regs_n<3, float>(block, lanes);
+  }
+  return false;
+}
 
 hipError_t launch_blocked(int levels, int precision, int block, int lanes, bool vc, bool strong, bool cayley,
                           const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo,

@@ -11,6 +11,9 @@ bool block_supported(int block);
 // whether the blocked kernel is built for this tile (block cells, lanes wave
 // groups per 64 cells: 1, 2 or 4) at this level count and precision
 bool shape_supported(int levels, int precision, int block, int lanes);
+// whether that tile is also built with register-resident coefficients (a run
+// that asks for them on another shape uses scalar coefficient loads)
+bool regs_supported(int levels, int precision, int block, int lanes);
 int plain_block();
 
 // Temporally blocked launch from engine step n0 with buffer parity `parity`:

@@ -36,11 +36,15 @@ double norm1(const Mat &a, int n) {
   return best;
 }
 
-// Matrix exponential by scaling and squaring of a truncated Taylor series
-// (Moler & Van Loan, "Nineteen dubious ways", methods 1 and 3): the scaled
-// matrix has 1-norm <= 1/4, where 30 Taylor terms leave a remainder far
-// below double rounding.
-Mat expm(const Mat &z, int n) {
+// e^Z - I by scaling and squaring of a truncated Taylor series (Moler & Van
+// Loan, "Nineteen dubious ways", methods 1 and 3), carried without the
+// identity: the scaled matrix has 1-norm <= 1/4, where 30 terms of
+// Z + Z^2/2! + ... leave a remainder far below double rounding, and each
+// squaring (I + E)^2 - I = 2E + E^2 keeps E to its own relative accuracy.
+// (Forming e^Z first and subtracting I would leave the small entries of a
+// propagator over one time step with an absolute error of an ulp of 1, which
+// over many steps drifts a stationary state.)
+Mat expm_minus_identity(const Mat &z, int n) {
   double nrm = norm1(z, n);
   int s = 0;
   while (nrm > 0.25) {
@@ -50,9 +54,8 @@ Mat expm(const Mat &z, int n) {
   double scale = std::ldexp(1.0, -s);
   Mat zs(z);
   for (double &v : zs) v *= scale;
-  Mat result(size_t(n) * n, 0.0), term(size_t(n) * n, 0.0);
-  for (int i = 0; i < n; ++i) result[size_t(i) * n + i] = term[size_t(i) * n + i] = 1.0;
-  for (int k = 1; k <= 30; ++k) {
+  Mat result(zs), term(zs);
+  for (int k = 2; k <= 30; ++k) {
     term = matmul(term, zs, n);
     double inv = 1.0 / k, tn = 0.0;
     for (double &v : term) {
@@ -62,7 +65,10 @@ Mat expm(const Mat &z, int n) {
     for (size_t q = 0; q < result.size(); ++q) result[q] += term[q];
     if (tn < 1e-300) break;
   }
-  for (int q = 0; q < s; ++q) result = matmul(result, result, n);
+  for (int q = 0; q < s; ++q) {
+    Mat sq = matmul(result, result, n);
+    for (size_t i = 0; i < result.size(); ++i) result[i] = 2.0 * result[i] + sq[i];
+  }
   return result;
 }
 
@@ -180,6 +186,30 @@ std::vector<cd> unpack(int n, const double *diag, const double *off) {
       a[size_t(j) * n + i] = std::conj(v);
     }
   return a;
+}
+
+// a[to[i]][to[j]] <- a[i][j]
+std::vector<cd> permute_matrix(int n, const std::vector<cd> &a, const std::vector<int> &to) {
+  std::vector<cd> b(a.size());
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) b[size_t(to[i]) * n + to[j]] = a[size_t(i) * n + j];
+  return b;
+}
+
+// the same quantum description with its levels relabelled (i -> to[i])
+void permute_levels(QmFull &q, const std::vector<int> &to) {
+  const int n = q.n;
+  q.h0 = permute_matrix(n, q.h0, to);
+  q.mu = permute_matrix(n, q.mu, to);
+  std::vector<double> rates(q.rates.size(), 0.0), deph(q.deph.size(), 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) rates[size_t(to[i]) * n + to[j]] = q.rates[size_t(i) * n + j];
+  for (int j = 1; j < n; ++j)
+    for (int i = 0; i < j; ++i)
+      deph[pair_index(std::min(to[i], to[j]), std::max(to[i], to[j]))] = q.deph[pair_index(i, j)];
+  q.rates = rates;
+  q.deph = deph;
+  for (auto &op : q.ops) op = permute_matrix(n, op, to);
 }
 
 int describe(const mb_qm &q, const mb_consts &k, QmFull &out, std::string &err) {
@@ -361,8 +391,33 @@ std::vector<double> x_to_full(int n, const double *x) {
   return v;
 }
 
+// Hermitian rho of the trace-eliminated state x (trace 1)
+std::vector<cd> rho_of_x(int n, const double *x) { return from_real(n, x_to_full(n, x)); }
+
+// state coordinates of a traceless Hermitian matrix (the last population is
+// minus the sum of the others, so it is dropped)
+std::vector<double> x_of_traceless(int n, const std::vector<cd> &a) {
+  const int m = state_dim(n);
+  std::vector<double> v = to_real(n, a), x(m);
+  for (int c = 0; c < m; ++c) x[c] = v[full_index(n, c)];
+  return x;
+}
+
+// (Re, Im) of the coherences of B = V^+ A V, pairs in packed order
+std::vector<double> eig_coherences(int n, const std::vector<cd> &vec, const std::vector<cd> &a) {
+  std::vector<cd> b = conj_by(n, vec, a, true);
+  std::vector<double> z(size_t(coh_dim(n)));
+  for (int kk = 1; kk < n; ++kk)
+    for (int j = 0; j < kk; ++j) {
+      const int p = pair_index(j, kk);
+      z[2 * p] = b[size_t(j) * n + kk].real();
+      z[2 * p + 1] = b[size_t(j) * n + kk].imag();
+    }
+  return z;
+}
+
 void build_quantum(MaterialPlan &mp, const QmFull &q, double dt, const mb_consts &k) {
-  int n = q.n, m = state_dim(n), nn = n * n;
+  int n = q.n, m = state_dim(n), nn = n * n, kd = coh_dim(n);
   mp.qm = true;
   mp.n = n;
   mp.n3d = q.n3d;
@@ -371,15 +426,14 @@ void build_quantum(MaterialPlan &mp, const QmFull &q, double dt, const mb_consts
   for (int i = 0; i + 1 < n; ++i) mp.kappa[i] = dt * (mp.lam[i] - mp.lam[i + 1]) / k.hbar;
   mp.sigma.resize(n);
   for (int i = 0; i < n; ++i) mp.sigma[i] = dt * mp.lam[i] / k.hbar;
-  // full real generator in the eigen-basis: column a = L0' applied to basis a
+  // full real generator in the operator basis: column a = L0 applied to basis a
   Mat gfull(size_t(nn) * nn, 0.0);
   std::vector<cd> out;
   for (int a = 0; a < nn; ++a) {
     std::vector<double> e(nn, 0.0);
     e[a] = 1.0;
-    std::vector<cd> rho = conj_by(n, mp.vec, from_real(n, e), false);  // to original basis
-    apply_free(q, k.hbar, rho, out);
-    std::vector<double> col = to_real(n, conj_by(n, mp.vec, out, true));
+    apply_free(q, k.hbar, from_real(n, e), out);
+    std::vector<double> col = to_real(n, out);
     for (int r = 0; r < nn; ++r) gfull[size_t(r) * nn + a] = col[r];
   }
   // trace elimination: rho_{N-1,N-1} = 1 - sum_{k<N-1} x_k
@@ -402,24 +456,70 @@ void build_quantum(MaterialPlan &mp, const QmFull &q, double dt, const mb_consts
     for (int b = 0; b < m; ++b) z[size_t(a) * ma + b] = mp.gen[size_t(a) * m + b] * (dt / 2);
     z[size_t(a) * ma + m] = mp.gen_off[a] * (dt / 2);
   }
-  Mat half = expm(z, ma);
+  // e^{Z} - I for the half step, then the full step (I + E)^2 - I = 2E + E^2;
+  // the affine parts are the last columns
+  Mat half = expm_minus_identity(z, ma);
   Mat full = matmul(half, half, ma);
+  for (size_t i = 0; i < full.size(); ++i) full[i] += 2.0 * half[i];
   mp.ah.assign(size_t(m) * m, 0.0);
   mp.bh.assign(m, 0.0);
   mp.am.assign(size_t(m) * m, 0.0);
   mp.bf.assign(m, 0.0);
   for (int a = 0; a < m; ++a) {
     for (int b = 0; b < m; ++b) {
-      mp.ah[size_t(a) * m + b] = half[size_t(a) * ma + b];
-      mp.am[size_t(a) * m + b] = full[size_t(a) * ma + b] - (a == b ? 1.0 : 0.0);
+      mp.ah[size_t(a) * m + b] = half[size_t(a) * ma + b] + (a == b ? 1.0 : 0.0);
+      mp.am[size_t(a) * m + b] = full[size_t(a) * ma + b];
     }
     mp.bh[a] = half[size_t(a) * ma + m];
     mp.bf[a] = full[size_t(a) * ma + m];
   }
-  // p = n3D tr{mu' L0'(rho')} = n3D sum_{k<N-1} (lam_k - lam_{N-1}) xdot_k,
-  // xdot = G (ah y + bh) + g
+  // field part: W rho W^+ with W = V diag(e^{i E sigma}) V^+ changes only the
+  // eigenbasis coherences z of rho, z_jk -> e^{i theta_jk} z_jk; the step adds
+  // the increment V Delta V^+ (Delta: the coherences d = (e^{i theta} - 1) z,
+  // zero diagonal), whose state coordinates are sm d.  z = t0 + tm x.
+  {
+    std::vector<double> zero(m, 0.0);
+    mp.t0 = eig_coherences(n, mp.vec, rho_of_x(n, zero.data()));
+    mp.tm.assign(size_t(kd) * m, 0.0);
+    for (int b = 0; b < m; ++b) {
+      std::vector<double> e(m, 0.0);
+      e[b] = 1.0;
+      std::vector<double> zb = eig_coherences(n, mp.vec, rho_of_x(n, e.data()));
+      for (int r = 0; r < kd; ++r) mp.tm[size_t(r) * m + b] = zb[r] - mp.t0[r];
+    }
+    mp.sm.assign(size_t(m) * kd, 0.0);
+    for (int kk = 1; kk < n; ++kk)
+      for (int j = 0; j < kk; ++j)
+        for (int part = 0; part < 2; ++part) {
+          const int r = 2 * pair_index(j, kk) + part;
+          const cd v = part == 0 ? cd(1, 0) : cd(0, 1);
+          std::vector<cd> delta(size_t(n) * n, cd(0, 0));
+          delta[size_t(j) * n + kk] = v;
+          delta[size_t(kk) * n + j] = std::conj(v);
+          std::vector<double> col = x_of_traceless(n, conj_by(n, mp.vec, delta, false));
+          for (int a = 0; a < m; ++a) mp.sm[size_t(a) * kd + r] = col[a];
+        }
+    mp.bm.assign(size_t(m) * kd, 0.0);
+    for (int a = 0; a < m; ++a)
+      for (int r = 0; r < kd; ++r) {
+        double acc = mp.sm[size_t(a) * kd + r];
+        for (int b = 0; b < m; ++b) acc += mp.am[size_t(a) * m + b] * mp.sm[size_t(b) * kd + r];
+        mp.bm[size_t(a) * kd + r] = acc;
+      }
+  }
+  // tr{mu X} for a Hermitian X with state coordinates x (trace eliminated):
+  // c0 + c . x, c_a = mu_aa - mu_{N-1,N-1}, c_(Re, Im of pair ij) = 2 (Re, Im) mu_ij
   std::vector<double> c(m, 0.0);
-  for (int kk = 0; kk < n - 1; ++kk) c[kk] = q.n3d * (mp.lam[kk] - mp.lam[n - 1]);
+  const double mu_last = q.mu[size_t(n - 1) * n + (n - 1)].real();
+  for (int a = 0; a < n - 1; ++a) c[a] = q.n3d * (q.mu[size_t(a) * n + a].real() - mu_last);
+  for (int j = 1; j < n; ++j)
+    for (int i = 0; i < j; ++i) {
+      const int p = pair_index(i, j);
+      c[n - 1 + 2 * p] = 2.0 * q.n3d * q.mu[size_t(i) * n + j].real();
+      c[n + 2 * p] = 2.0 * q.n3d * q.mu[size_t(i) * n + j].imag();
+    }
+  // p = n3D tr{mu L0(rho^{n+1/2})} = c . xdot, xdot = G (ah y + bh) + g (the
+  // derivative is traceless, so c0 drops)
   std::vector<double> cg(m, 0.0);  // c^T G
   for (int b = 0; b < m; ++b)
     for (int a = 0; a < m; ++a) cg[b] += c[a] * mp.gen[size_t(a) * m + b];
@@ -429,16 +529,24 @@ void build_quantum(MaterialPlan &mp, const QmFull &q, double dt, const mb_consts
   double p0 = 0.0;
   for (int a = 0; a < m; ++a) p0 += cg[a] * mp.bh[a] + c[a] * mp.gen_off[a];
   mp.p0 = p0;
-  // strong coupling: (n3D/dt) tr{mu rho} with rho' = ah y + bh (trace eliminated):
-  // n3D/dt [lam_{N-1} + sum_{k<N-1} (lam_k - lam_{N-1}) (ah y + bh)_k]
+  // strong coupling: (n3D/dt) tr{mu rho} with rho = ah y + bh
   mp.aq.assign(m, 0.0);
-  double qc = q.n3d * mp.lam[n - 1];
-  for (int kk = 0; kk < n - 1; ++kk) {
-    for (int b = 0; b < m; ++b) mp.aq[b] += c[kk] * mp.ah[size_t(kk) * m + b];
-    qc += c[kk] * mp.bh[kk];
+  double qc = q.n3d * mu_last;
+  for (int a = 0; a < m; ++a) {
+    for (int b = 0; b < m; ++b) mp.aq[b] += c[a] * mp.ah[size_t(a) * m + b];
+    qc += c[a] * mp.bh[a];
   }
   for (double &v : mp.aq) v /= dt;
   mp.qc = qc / dt;
+  // readouts of y = x + sm d folded: the d parts
+  auto fold = [&](const std::vector<double> &r) {
+    std::vector<double> rs(kd, 0.0);
+    for (int t = 0; t < kd; ++t)
+      for (int a = 0; a < m; ++a) rs[t] += r[a] * mp.sm[size_t(a) * kd + t];
+    return rs;
+  };
+  mp.as = fold(mp.at);
+  mp.aqs = fold(mp.aq);
   // complete positivity of the pure dephasing: Gram matrix -1/2 J D J, D_ij = 2 gamma_ij,p
   Mat d(size_t(n) * n, 0.0), jm(size_t(n) * n, 0.0);
   double dmax = 0.0;
@@ -454,10 +562,12 @@ void build_quantum(MaterialPlan &mp, const QmFull &q, double dt, const mb_consts
   mp.min_gram_eig = sym_min_eig(n, g) / std::max(dmax, 1e-300);
 }
 
-// value of a density quantity for a full real vector v in the eigen-basis
+// value of a density quantity for a full real vector v (operator basis)
 double quantity_of(const MaterialPlan &mp, int quantity, int i, int j, const std::vector<double> &v) {
   int n = mp.n;
-  std::vector<cd> rho = conj_by(n, mp.vec, from_real(n, v), false);
+  std::vector<cd> rho = from_real(n, v);
+  i = mp.lvl[i];
+  j = mp.lvl[j];
   switch (quantity) {
     case MB_REC_POP: return rho[size_t(i) * n + i].real();
     case MB_REC_INV: return (rho[size_t(j) * n + j] - rho[size_t(i) * n + i]).real();
@@ -467,10 +577,10 @@ double quantity_of(const MaterialPlan &mp, int quantity, int i, int j, const std
   return 0.0;
 }
 
-// Readout (r0, r) with value = r0 + r . y for the post-rotation state y:
-// rho^{n+1/2} = ah y + bh (affine in y).
+// Readout (r0, r, rs) with value = r0 + r . x + rs . d for the state x and the
+// field increments d of the step: rho^{n+1/2} = ah y + bh, y = x + sm d.
 void build_readout(const MaterialPlan &mp, int quantity, int i, int j, double *out) {
-  int n = mp.n, m = state_dim(n);
+  int n = mp.n, m = state_dim(n), kd = coh_dim(n);
   std::vector<double> zero(m, 0.0);
   double base = quantity_of(mp, quantity, i, j, x_to_full(n, zero.data()));
   std::vector<double> r(m, 0.0);
@@ -486,6 +596,11 @@ void build_readout(const MaterialPlan &mp, int quantity, int i, int j, double *o
     double acc = 0.0;
     for (int a = 0; a < m; ++a) acc += r[a] * mp.ah[size_t(a) * m + b];
     out[1 + b] = acc;
+  }
+  for (int t = 0; t < kd; ++t) {
+    double acc = 0.0;
+    for (int b = 0; b < m; ++b) acc += out[1 + b] * mp.sm[size_t(b) * kd + t];
+    out[1 + m + t] = acc;
   }
 }
 
@@ -567,8 +682,9 @@ void state_to_rho(const MaterialPlan &mp, const double *sigma, cd *rho) {
   std::vector<double> rhs(m);
   for (int a = 0; a < m; ++a) rhs[a] = sigma[a] - mp.bh[a];
   solve_linear(m, mp.ah, rhs);
-  std::vector<cd> r = conj_by(n, mp.vec, from_real(n, x_to_full(n, rhs.data())), false);
-  for (int q = 0; q < n * n; ++q) rho[q] = r[q];
+  std::vector<cd> r = rho_of_x(n, rhs.data());
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) rho[size_t(i) * n + j] = r[size_t(mp.lvl[i]) * n + mp.lvl[j]];
 }
 
 int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan &plan,
@@ -708,8 +824,22 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
   }
   plan.n = levels;
   plan.m = levels ? state_dim(levels) : 0;
+  std::vector<int> lvl;
+  if (levels) {
+    if (!scen->rho_diag) {
+      err = "initial density matrix missing";
+      return MB_ERR_ARG;
+    }
+    // the most populated initial level (the last of equals) goes last
+    int top = 0;
+    for (int i = 1; i < levels; ++i)
+      if (scen->rho_diag[i] >= scen->rho_diag[top]) top = i;
+    for (int i = 0, at = 0; i < levels; ++i) lvl.push_back(i == top ? levels - 1 : at++);
+  }
   for (int i = 0; i < dev->n_materials; ++i)
     if (dev->materials[i].qm) {
+      permute_levels(qms[i], lvl);
+      plan.mats[i].lvl = lvl;
       build_quantum(plan.mats[i], qms[i], plan.dt, k);
       if (plan.mats[i].min_gram_eig < -1e-9) plan.warn = MB_WARN_NOT_CP;
     }
@@ -795,10 +925,10 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
     rp.width = rc.cell < 0 ? nx : 1;
     rp.n_samples = plan.n_steps / rp.interval;
     if (dens) {
-      int m = plan.m;
-      rp.readout.assign(size_t(dev->n_materials) * (m + 1), 0.0);
+      const int rl = plan.m + 1 + coh_dim(levels);
+      rp.readout.assign(size_t(dev->n_materials) * rl, 0.0);
       for (int i = 0; i < dev->n_materials; ++i)
-        if (plan.mats[i].qm) build_readout(plan.mats[i], rc.quantity, rc.i, rc.j, &rp.readout[size_t(i) * (m + 1)]);
+        if (plan.mats[i].qm) build_readout(plan.mats[i], rc.quantity, rc.i, rc.j, &rp.readout[size_t(i) * rl]);
     }
     plan.records.push_back(std::move(rp));
   }
@@ -840,13 +970,13 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
       return MB_ERR_ARG;
     }
     int n = levels, m = plan.m;
-    std::vector<cd> rho0 = unpack(n, scen->rho_diag, scen->rho_off);
+    std::vector<cd> rho0 = permute_matrix(n, unpack(n, scen->rho_diag, scen->rho_off), lvl);
     plan.x0.assign(size_t(m) * nx, 0.0);
     plan.q0.assign(nx, 0.0);
     for (int i = 0; i < dev->n_materials; ++i) {
       const MaterialPlan &mp = plan.mats[i];
       if (!mp.qm) continue;
-      std::vector<double> v = to_real(n, conj_by(n, mp.vec, rho0, true));
+      std::vector<double> v = to_real(n, rho0);
       std::vector<double> x(m);
       for (int a = 0; a < m; ++a) x[a] = v[full_index(n, a)];
       std::vector<double> sig(m);
@@ -855,9 +985,11 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
         for (int b = 0; b < m; ++b) acc += mp.ah[size_t(a) * m + b] * x[b];
         sig[a] = acc;
       }
-      // (n3D/dt) tr{mu rho^0} in the eigen-basis of mu
-      double q = mp.lam[n - 1];
-      for (int kk = 0; kk < n - 1; ++kk) q += (mp.lam[kk] - mp.lam[n - 1]) * x[kk];
+      // (n3D/dt) tr{mu rho^0}
+      double q = 0.0;
+      for (int a = 0; a < n; ++a) q += (qms[i].mu[size_t(a) * n + a] * rho0[size_t(a) * n + a]).real();
+      for (int jj = 1; jj < n; ++jj)
+        for (int ii = 0; ii < jj; ++ii) q += 2.0 * (qms[i].mu[size_t(jj) * n + ii] * rho0[size_t(ii) * n + jj]).real();
       q *= mp.n3d / plan.dt;
       for (int64_t c = 0; c < nx; ++c)
         if (plan.mat_e[c] == i) {

@@ -16,12 +16,15 @@ using cd = std::complex<double>;
 constexpr int kMaxLevels = 6;
 constexpr int kMaxLindbladOps = 64;
 
-// Real parametrisation of an N x N Hermitian density matrix written in the
-// eigen-basis of the dipole operator: populations 0..N-2 (the last one is
-// 1 - sum, trace elimination), then (Re, Im) of each upper pair in packed
-// order (1,2),(1,3),(2,3),...  Dimension M = N*N - 1.
+// Real parametrisation of an N x N Hermitian density matrix in the basis the
+// operators are given in: populations 0..N-2 (the last one is 1 - sum, trace
+// elimination), then (Re, Im) of each upper pair in packed order
+// (1,2),(1,3),(2,3),...  Dimension M = N*N - 1.  The field part works on the
+// (Re, Im) coordinates of the coherences in the dipole eigenbasis (K = N*(N-1)
+// reals, same pair order).
 inline int state_dim(int n) { return n * n - 1; }
 inline int pair_count(int n) { return n * (n - 1) / 2; }
+inline int coh_dim(int n) { return n * (n - 1); }
 
 struct MaterialPlan {
   double eps_r = 1, mu_r = 1, alpha0 = 0, overlap = 1;
@@ -30,7 +33,12 @@ struct MaterialPlan {
   bool qm = false;
   int n = 0;
   double n3d = 0;
-  // quantum tables (FP64), in the dipole eigen-basis, trace eliminated
+  // the levels in the order the tables use: lvl[i] = position of the caller's
+  // level i (the most populated initial level is moved last, where the trace
+  // elimination puts it, so that it is never stored: an FP32 state then holds
+  // only populations it can resolve relative to their own size)
+  std::vector<int> lvl;
+  // quantum tables (FP64); states in the operator basis, trace eliminated
   std::vector<double> lam;        // N sorted eigenvalues of mu
   std::vector<cd> vec;            // N x N eigenvectors (columns), row-major
   std::vector<double> kappa;      // N-1: dt (lam_q - lam_{q+1}) / hbar
@@ -39,9 +47,14 @@ struct MaterialPlan {
   std::vector<double> gen_off;    // M
   std::vector<double> ah, bh;     // e^{L0 dt/2}: x -> ah x + bh
   std::vector<double> am, bf;     // e^{L0 dt} - I and its affine part
-  std::vector<double> at;         // M: p = at . y + p0
+  std::vector<double> t0, tm;     // K, K x M: eigenbasis coherences z = t0 + tm x
+  std::vector<double> sm;         // M x K: field increment d (eigenbasis) -> state coordinates
+  std::vector<double> bm;         // M x K: e^{L0 dt} sm
+  std::vector<double> at;         // M: p = at . y + p0, y = x + sm d
+  std::vector<double> as;         // K: at sm
   double p0 = 0;
   std::vector<double> aq;         // M: strong coupling, (n3D/dt) tr{mu rho} = aq . y + qc
+  std::vector<double> aqs;        // K: aq sm
   double qc = 0;
   double min_gram_eig = 0;        // complete-positivity check of the dephasing rates
 };
@@ -55,7 +68,7 @@ struct SourcePlan {
 struct RecordPlan {
   int quantity = 0, i = 0, j = 0;
   int64_t cell = 0, interval = 1, width = 1, n_samples = 0;
-  // density quantities: per material (M+1) doubles: value = r0 + r . y
+  // density quantities: per material M+1+K doubles: value = r0 + r . x + rs . d
   std::vector<double> readout;
 };
 
@@ -89,8 +102,8 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
 // Host linear algebra used by the plan (exposed for the state read-back).
 bool solve_linear(int n, std::vector<double> a, std::vector<double> &b);
 
-// rho (N x N complex, original basis) of the running state x of a material:
-// rho^{n-1/2} = inverse half-propagator of sigma, rotated back.
+// rho (N x N complex, operator basis) of the running state x of a material:
+// rho^{n-1/2} = inverse half-propagator of sigma.
 void state_to_rho(const MaterialPlan &mp, const double *sigma, cd *rho);
 
 }  // namespace mb

@@ -45,7 +45,7 @@ Layout layout_of(const SimPlan &p, int precision, bool plain) {
   const bool strong = p.coupling == MB_COUPLING_STRONG && p.n > 0;
   L.qs = take(strong ? 2 * nx * sizeof(double) : sizeof(double));
   L.init_q = take(strong ? nx * sizeof(double) : sizeof(double));
-  L.qtab = take(strong ? p.mats.size() * size_t(m + 1) * sizeof(double) : sizeof(double));
+  L.qtab = take(strong ? p.mats.size() * size_t(ro_len(p.n)) * sizeof(double) : sizeof(double));
   L.src = take(std::max<size_t>(1, p.sources.size()) * sizeof(DevSource));
   for (auto &s : p.sources) L.tab_off.push_back(take(s.table.size() * sizeof(double)));
   L.rec = take(std::max<size_t>(1, p.records.size()) * sizeof(DevRecord));
@@ -77,14 +77,22 @@ void fill_mtab(const SimPlan &p, R *out) {
     t[kCoefH] = R(mp.ch);
     if (n == 0) continue;
     t[kCoefQM] = mp.qm ? R(1) : R(0);
-    for (int q = 0; q < n - 1; ++q) t[kCoefKap + q] = mp.qm ? R(mp.kappa[q]) : R(0);
-    t[coef_p0(n)] = mp.qm ? R(mp.p0) : R(0);
+    if (!mp.qm) continue;  // the table is zero-initialised
+    const int k = mat_k(n), w = prop_w(n);
+    for (int q = 0; q < n - 1; ++q) t[kCoefKap + q] = R(mp.kappa[q]);
+    t[coef_p0(n)] = R(mp.p0);
     for (int a = 0; a < m; ++a) {
-      t[coef_at(n) + a] = mp.qm ? R(mp.at[a]) : R(0);
-      t[coef_bf(n) + a] = mp.qm ? R(mp.bf[a]) : R(0);
-      for (int b = 0; b < m; ++b) t[coef_am(n) + a * m + b] = mp.qm ? R(mp.am[size_t(a) * m + b]) : R(0);
+      t[coef_at(n) + a] = R(mp.at[a]);
+      t[coef_bf(n) + a] = R(mp.bf[a]);
+      for (int b = 0; b < m; ++b) t[coef_am(n) + a * w + b] = R(mp.am[size_t(a) * m + b]);
+      for (int r = 0; r < k; ++r) t[coef_am(n) + a * w + m + r] = R(mp.bm[size_t(a) * k + r]);
     }
-    for (int j = 0; j < n; ++j) t[coef_sg(n) + j] = mp.qm ? R(mp.sigma[j]) : R(0);
+    for (int r = 0; r < k; ++r) {
+      t[coef_as(n) + r] = R(mp.as[r]);
+      t[coef_t0(n) + r] = R(mp.t0[r]);
+      for (int b = 0; b < m; ++b) t[coef_tm(n) + r * m + b] = R(mp.tm[size_t(r) * m + b]);
+    }
+    for (int j = 0; j < n; ++j) t[coef_sg(n) + j] = R(mp.sigma[j]);
   }
 }
 
@@ -108,11 +116,12 @@ void fill_state(const SimPlan &p, char *head, const Layout &L) {
     double *iq = reinterpret_cast<double *>(head + L.init_q);
     for (size_t c = 0; c < nx; ++c) qs[c] = qs[nx + c] = iq[c] = p.q0[c];
     double *qt = reinterpret_cast<double *>(head + L.qtab);
-    const size_t m1 = size_t(p.m) + 1;
+    const size_t rl = size_t(ro_len(p.n)), k = size_t(mat_k(p.n));
     for (size_t i = 0; i < p.mats.size(); ++i) {
       const MaterialPlan &mp = p.mats[i];
-      qt[i * m1] = mp.qm ? mp.qc : 0.0;
-      for (int a = 0; a < p.m; ++a) qt[i * m1 + 1 + a] = mp.qm ? mp.aq[a] : 0.0;
+      qt[i * rl] = mp.qm ? mp.qc : 0.0;
+      for (int a = 0; a < p.m; ++a) qt[i * rl + 1 + a] = mp.qm ? mp.aq[a] : 0.0;
+      for (size_t r = 0; r < k; ++r) qt[i * rl + 1 + p.m + r] = mp.qm ? mp.aqs[r] : 0.0;
     }
   }
 }
@@ -224,7 +233,7 @@ int Engine::init(std::string &err) {
   }
   if (variant_ != MB_VARIANT_PLAIN) {
     if (!block_supported(block_) || halo_ < 1 || 2 * halo_ >= block_) {
-      err = "blocked variant needs block in {64,128,192,256,512,1024} and 1 <= depth < block/2";
+      err = "blocked variant needs block in {64,128,192,256,512} and 1 <= depth < block/2";
       return MB_ERR_ARG;
     }
     if (lanes_ != 0 && lanes_ != 1 && lanes_ != 2 && lanes_ != 4 && lanes_ != 8) {
@@ -271,6 +280,11 @@ int Engine::add(SimPlan &&plan, Arena *arena, hipStream_t st, std::string &err) 
   }
   if (plain && precision_ != 64) {
     err = "the two-launch variant runs in FP64 only";
+    return MB_ERR_UNSUPPORTED;
+  }
+  if (!plain && !shape_supported(plan.n, precision_, block_, 1)) {
+    err = "no tile of " + std::to_string(block_) + " cells is built for " + std::to_string(plan.n) +
+          " levels in this precision (5 and 6 levels: at most 256)";
     return MB_ERR_UNSUPPORTED;
   }
   if (free_slots_.empty()) {

@@ -71,23 +71,17 @@ std::vector<Shape> candidate_shapes(int levels, int precision) {
   // 64-cell one-wave tiles exchange neighbours inside the wave (no barriers);
   // larger tiles, and tiles with 2 or 4 waves per 64 cells, go through LDS
   // with a barrier per exchange
-  const std::vector<std::pair<int, int>> all = {{64, 8},    {64, 12},   {64, 16},   {64, 20},    {128, 16},
-                                                {128, 32},  {192, 32},  {192, 64},  {256, 32},   {256, 64},
-                                                {512, 64},  {512, 128}, {512, 192}, {1024, 128}, {1024, 256}};
+  const std::vector<std::pair<int, int>> all = {{64, 8},   {64, 12},  {64, 16},  {64, 20},  {128, 16}, {128, 32},
+                                                {192, 32}, {192, 64}, {256, 32}, {256, 64}, {512, 64}, {512, 128},
+                                                {512, 192}};
   const std::vector<std::pair<int, int>> split = {{64, 16},  {128, 16}, {128, 32}, {192, 16}, {192, 32},
                                                   {192, 48}, {256, 32}, {256, 64}, {512, 64}, {512, 128}};
   std::vector<Shape> out;
-  const bool regs = levels == 2 || levels == 3;
-  for (auto [b, h] : all) {
-    if (levels >= 5 && b > 512) continue;  // register pressure of the large matvec
-    out.push_back(Shape{b, h, false, 1});
-    if (regs) out.push_back(Shape{b, h, true, 1});
-  }
-  for (int lanes : {2, 4, 8})
-    for (auto [b, h] : split) {
+  for (int lanes : {1, 2, 4, 8})
+    for (auto [b, h] : lanes == 1 ? all : split) {
       if (!shape_supported(levels, precision, b, lanes)) continue;
       out.push_back(Shape{b, h, false, lanes});
-      if (regs) out.push_back(Shape{b, h, true, lanes});
+      if (regs_supported(levels, precision, b, lanes)) out.push_back(Shape{b, h, true, lanes});
     }
   return out;
 }

@@ -81,6 +81,8 @@ def test_small_random_fp64_plain_and_blocked_vs_oracle(case):
               (64, 7, 2), (128, 31, 2), (192, 64, 2), (256, 64, 2), (64, 20, 4), (128, 16, 4), (192, 32, 4),
               (256, 32, 4), (64, 20, 8)]
     for block, depth, lanes in shapes:
+        if not mb.tile_supported(case["N"], 64, block):
+            continue  # no such tile for 5 and 6 levels
         for variant in ("blocked", "blocked_regs"):
             blk = gpu_run(prob, precision=64, variant=variant, block=block, depth=depth, lanes=lanes)
             assert_same(blk, plain)
@@ -490,7 +492,7 @@ def test_qcl6_full_grid_prefix_vs_oracle():
     _say(f"qcl6 fp32 {errs32}")
     assert max(errs32.values()) <= TOL[32], errs32
     base = gpu_run(prob, precision=32, variant="blocked", block=256, depth=64, lanes=1)
-    for block, depth, lanes in ((256, 64, 2), (128, 32, 4), (64, 16, 4), (64, 16, 8)):
+    for block, depth, lanes in ((128, 32, 2), (64, 16, 4), (64, 16, 8)):
         _say(f"qcl6 prefix {block}/{depth} lanes {lanes}")
         assert_same(gpu_run(prob, precision=32, variant="blocked", block=block, depth=depth, lanes=lanes), base)
 
@@ -511,7 +513,7 @@ def test_qcl5_comb_prefix_vs_oracle():
     _say(f"qcl5 fp32 {errs32}")
     assert max(errs32.values()) <= TOL[32], errs32
     base = gpu_run(prob, precision=32, variant="blocked", block=256, depth=64, lanes=1)
-    for block, depth, lanes in ((128, 32, 4), (64, 16, 8)):
+    for block, depth, lanes in ((128, 32, 2), (64, 16, 4)):
         assert_same(gpu_run(prob, precision=32, variant="blocked", block=block, depth=depth, lanes=lanes), base)
 
 
@@ -529,6 +531,20 @@ def test_anharmonic_ladder_vs_oracle(n):
     assert max(errs32.values()) <= TOL[32], errs32
     for block, depth, lanes in ((128, 16, 2), (64, 8, 4), (64, 8, 8)):
         assert_same(gpu_run(prob, precision=32, variant="blocked", block=block, depth=depth, lanes=lanes), got32)
+
+
+@pytest.mark.parametrize("n", [2, 3, 6])
+def test_field_free_medium_stays_field_free(n):
+    """A medium left in its stationary ground state with no source produces no polarization
+    (the field factor is the identity at E = 0): E, recorded over the whole grid, stays
+    exactly zero in FP64 and FP32, as in the oracle, and the populations stay put."""
+    prob = W.ladder(n, nx=300, n_steps=200, rec_interval=10)
+    prob["sources"] = []
+    prob["records"] = [W.record("e_all", "e", -1, 10), W.record("pop0", "pop", 150, 10, i=0, j=0)]
+    for precision in (64, 32):
+        got = gpu_run(prob, precision=precision)
+        assert not np.any(got["e_all"]), precision
+        assert np.max(np.abs(got["pop0"] - 1.0)) <= (1e-15 if precision == 64 else 1e-7)
 
 
 STRONG = [
@@ -552,7 +568,8 @@ def test_strong_coupling_vs_oracle(case):
     errs = rel_errors(prob, got, ref)
     assert max(errs.values()) <= TOL[64], errs
     for block, depth in ((64, 7), (256, 32), (512, 100)):
-        assert_same(gpu_run(prob, precision=64, variant="blocked", block=block, depth=depth), got)
+        if mb.tile_supported(case["N"], 64, block):
+            assert_same(gpu_run(prob, precision=64, variant="blocked", block=block, depth=depth), got)
     got32 = gpu_run(prob, precision=32, variant="blocked", block=128, depth=16)
     errs32 = rel_errors(prob, got32, ref)
     assert max(errs32.values()) <= TOL[32], errs32

@@ -67,16 +67,17 @@ def _x_to_rho(x, n):
     return r
 
 
-def _rotate(y, e, kappa, n):
-    y = y.copy()
+def _increments(z, e, kappa, n):
+    """(e^{i theta_jk} - 1) z_jk for the eigenbasis pairs j < k, theta_jk = e sum kappa[j:k]."""
+    d = np.zeros_like(z)
     q = 0
-    for j in range(1, n):
-        for i in range(j):
-            th = e * sum(kappa[i:j])
-            z = (y[n - 1 + 2 * q] + 1j * y[n + 2 * q]) * np.exp(1j * th)
-            y[n - 1 + 2 * q], y[n + 2 * q] = z.real, z.imag
+    for k in range(1, n):
+        for j in range(k):
+            th = e * sum(kappa[j:k])
+            w = (z[2 * q] + 1j * z[2 * q + 1]) * (np.exp(1j * th) - 1.0)
+            d[2 * q], d[2 * q + 1] = w.real, w.imag
             q += 1
-    return y
+    return d
 
 
 def _random_ops(rng, n, k=3, rate=1e12):
@@ -99,18 +100,32 @@ def test_plan_tables_reproduce_oracle_single_point(n, seed, ops):
     t = mb.plan_material(prob, 0)
     orc = O.Oracle(prob)
     V = t["vec"]
+    lvl = t["lvl"]
+    # the tables order the levels so that the most populated initial one is last
+    assert lvl[int(np.argmax(rd))] == n - 1 and sorted(lvl) == list(range(n))
+    order = np.argsort(lvl)                  # internal level k is the caller's level order[k]
     rho0 = O.unpack_hermitian(rd, ro)
-    sigma = t["ah"] @ _rho_to_x(V.conj().T @ rho0 @ V, n) + t["bh"]
+    sigma = t["ah"] @ _rho_to_x(rho0[np.ix_(order, order)], n) + t["bh"]
     # eigen-decomposition of mu is the library's own
-    mu = O.describe(qm, C)[1]
+    mu = O.describe(qm, C)[1][np.ix_(order, order)]
     assert np.allclose(V @ np.diag(t["lam"]) @ V.conj().T, mu, rtol=0, atol=1e-12 * abs(mu).max())
     errs = []
     for step in range(nt):
         e = orc.e[0]
-        y = _rotate(sigma, e, t["kappa"], n)
+        z = t["t0"] + t["tm"] @ sigma
+        # z holds the coherences of V^+ rho V
+        if step == 0:
+            rs = V.conj().T @ _x_to_rho(sigma, n) @ V
+            zz = np.array([[rs[j, k].real, rs[j, k].imag] for k in range(1, n) for j in range(k)]).ravel()
+            assert np.allclose(z, zz, rtol=0, atol=1e-13)
+        d = _increments(z, e, t["kappa"], n)
+        y = sigma + t["sm"] @ d
         p = t["at"] @ y + t["p0"]
-        rho_half = V @ _x_to_rho(t["ah"] @ y + t["bh"], n) @ V.conj().T
+        assert abs(p - (t["at"] @ sigma + t["as"] @ d + t["p0"])) <= 1e-12 * max(1.0, abs(p))
+        rho_half = _x_to_rho(t["ah"] @ y + t["bh"], n)[np.ix_(lvl, lvl)]
+        new = sigma + t["am"] @ sigma + t["bm"] @ d + t["bf"]
         sigma = y + t["am"] @ y + t["bf"]
+        assert np.max(np.abs(new - sigma)) < 1e-13
         orc.step()
         ref = orc.full_density()[0]
         errs.append(np.max(np.abs(rho_half - ref)))
@@ -129,13 +144,15 @@ def test_plan_readouts_match_oracle_quantities():
                           e_init=np.array([2e9]), records=recs)
     t = mb.plan_material(prob, 0)
     orc = O.Oracle(prob)
-    V = t["vec"]
-    sigma = t["ah"] @ _rho_to_x(V.conj().T @ O.unpack_hermitian(rd, ro) @ V, n) + t["bh"]
-    y = _rotate(sigma, 2e9, t["kappa"], n)
+    M = n * n - 1
+    order = np.argsort(t["lvl"])
+    sigma = t["ah"] @ _rho_to_x(O.unpack_hermitian(rd, ro)[np.ix_(order, order)], n) + t["bh"]
+    d = _increments(t["t0"] + t["tm"] @ sigma, 2e9, t["kappa"], n)
     r = orc.run(1)
     for k, rec in enumerate(recs):
         ro_vec = mb.plan_readout(prob, k, 0)
-        val = ro_vec[0] + ro_vec[1:] @ y
+        assert ro_vec.size == M + 1 + n * (n - 1)
+        val = ro_vec[0] + ro_vec[1:1 + M] @ sigma + ro_vec[1 + M:] @ d
         assert abs(val - r[rec["name"]][0]) < 1e-13
 
 

@@ -79,6 +79,22 @@ def test_p1_single_channel_population_transfer(n):
 
 # ---------------------------------------------------------------- P2 / P3 Rabi
 
+@pytest.mark.parametrize("n", [2, 3, 5])
+def test_field_free_medium_in_a_stationary_state_stays_field_free(n):
+    """With no field the field factor is exp(0) = I (Sec. 2.2) and the ground state of a
+    ladder that only decays downward is stationary under L0 (eq:relax_pop: nothing leaves
+    level 1), so its polarization n3D tr{mu L0(rho)} vanishes (mu has no diagonal) and a
+    medium left alone in it radiates nothing: E stays exactly zero everywhere."""
+    prob = W.ladder(n, nx=120, n_steps=300, rec_interval=1)
+    prob["sources"] = []
+    orc = O.Oracle(prob)
+    for _ in range(prob["n_steps"]):
+        orc.step()
+        assert not np.any(orc.e) and not np.any(orc.p_cur)
+    rho = orc.groups[0]["rho"]
+    assert np.all(rho[:, 0, 0] == 1.0) and np.count_nonzero(rho) == rho.shape[0]
+
+
 def test_p2_resonant_rabi_exact_when_h0_vanishes():
     """H0 = 0, no relaxation, constant E: the splitting is exact and
     rho_22(t) = sin^2(mu12 E t / hbar)."""
