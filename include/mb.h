@@ -301,6 +301,23 @@ int mb_setup(int hip_device, const mb_device_desc *dev, const mb_scenario_desc *
  * captured into a HIP graph.  Results are the same bits either way. */
 int mb_run(mb_handle *h, int64_t n_steps, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): mb_run with the same
+ * arguments, results and kernels, that allocates nothing.  The run's group
+ * tables (the simulation's descriptor, its tile table and the neighbour flags
+ * of persistent launches: about 16 + 4 bytes per tile plus 256 per
+ * simulation) are written into the library's static device scratch of this
+ * GPU (1 MiB, held until the process ends) instead of buffers the handle
+ * allocates; its state, coefficient and record memory were placed by
+ * mb_setup.  The launches are direct (no graph) and the call returns once they
+ * are queued on `hip_stream`, after a synchronous upload of the tables; no
+ * elapsed time is recorded for mb_elapsed_ms.  MB_ERR_BUDGET when the tables
+ * exceed the scratch (grids of more than about 40000 tiles).  Every call on a
+ * GPU rewrites that GPU's scratch: calls that overlap on one GPU (from other
+ * threads, or queued on different streams) race and must be serialised by the
+ * caller. */
+int mb_run_static(mb_handle *h, int64_t n_steps, void *hip_stream);
+
 /* 1 when mb_run(h, n_steps) would run its full chunks as persistent launches
  * (one launch for up to 4096 chunks; tiles wait for their neighbours' flags
  * between chunks), 0 when every chunk is its own launch, negative on error.

@@ -29,7 +29,7 @@ VARIANT = {"auto": 0, "plain": 1, "blocked": 2, "blocked_regs": 3}
 FIELD_STEP = {"exact": 0, "cayley": 1}    # MB_FIELD_EXACT, MB_FIELD_CAYLEY
 
 EXPORTS = [
-    "mb_last_error", "mb_device_count", "mb_plan_material", "mb_plan_readout", "mb_plan_source", "mb_tile_supported", "mb_workspace_bytes", "mb_setup", "mb_run", "mb_run_mode", "mb_reset", "mb_batch_reset", "mb_shape", "mb_batch_shape", "mb_steps_done", "mb_record_shape",
+    "mb_last_error", "mb_device_count", "mb_plan_material", "mb_plan_readout", "mb_plan_source", "mb_tile_supported", "mb_workspace_bytes", "mb_setup", "mb_run", "mb_run_static", "mb_run_mode", "mb_reset", "mb_batch_reset", "mb_shape", "mb_batch_shape", "mb_steps_done", "mb_record_shape",
     "mb_read_records", "mb_read_state", "mb_elapsed_ms", "mb_destroy", "mb_batch_setup", "mb_batch_run",
     "mb_batch_record_shape", "mb_batch_read_records", "mb_batch_elapsed_ms", "mb_batch_destroy",
     "mb_server_create", "mb_server_submit", "mb_server_start", "mb_server_drain", "mb_server_cancel", "mb_server_poll",
@@ -133,6 +133,7 @@ def load():
         "mb_workspace_bytes": (C.c_int, [C.POINTER(mb_device_desc), C.POINTER(mb_scenario_desc),
                                          C.POINTER(C.c_size_t)]),
         "mb_run": (C.c_int, [P, C.c_int64, P]),
+        "mb_run_static": (C.c_int, [P, C.c_int64, P]),
         "mb_run_mode": (C.c_int, [P, C.c_int64]),
         "mb_reset": (C.c_int, [P, P]),
         "mb_batch_reset": (C.c_int, [P, P]),
@@ -400,6 +401,11 @@ class Solver:
 
     def run(self, n_steps=-1, stream=None):
         _check(load().mb_run(self._h, int(n_steps), _stream_ptr(stream)))
+        return self
+
+    def run_static(self, n_steps=-1, stream=None):
+        """run() through mb_run_static: no device allocation (tables in the library's static scratch)."""
+        _check(load().mb_run_static(self._h, int(n_steps), _stream_ptr(stream)))
         return self
 
     def reset(self, stream=None):

@@ -17,7 +17,8 @@ OBJ = os.path.join(HERE, "_build")
 SOURCES = [("kernels.hip", ["-DMB_PART=1"], "kernels_f32"), ("kernels.hip", ["-DMB_PART=2"], "kernels_f64"),
            ("kernels.hip", ["-DMB_PART=3"], "kernels_f32p"), ("kernels.hip", ["-DMB_PART=4"], "kernels_f64p"),
            ("kernels.hip", ["-DMB_PART=5"], "kernels_f32c"), ("kernels.hip", ["-DMB_PART=6"], "kernels_f64c"),
-           ("kernels.hip", ["-DMB_PART=7"], "kernels_f32pc"), ("kernels.hip", ["-DMB_PART=8"], "kernels_f64pc")] + [
+           ("kernels.hip", ["-DMB_PART=7"], "kernels_f32pc"), ("kernels.hip", ["-DMB_PART=8"], "kernels_f64pc"),
+           ("scratch.hip", [], "scratch")] + [
     (f, [], f) for f in ("plan.cpp", "runtime.cpp", "tune.cpp", "abi.cpp", "server.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("MB_OFFLOAD_ARCH", "gfx950")
@@ -33,7 +34,7 @@ def _deps(src: str):
     heads = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
     heads += [os.path.join(INCLUDE, f) for f in os.listdir(INCLUDE) if f.endswith(".h")]
     if src.endswith(".hip"):
-        heads = [h for h in heads if os.path.basename(h) in ("engine.hpp", "launch.hpp")]
+        heads = [h for h in heads if os.path.basename(h) in ("engine.hpp", "launch.hpp", "scratch.hpp")]
     return [os.path.join(CSRC, src)] + heads
 
 

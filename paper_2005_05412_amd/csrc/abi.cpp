@@ -11,6 +11,7 @@
 
 #include "mb.h"
 #include "launch.hpp"
+#include "scratch.hpp"
 #include "runtime.hpp"
 #include "tune.hpp"
 
@@ -347,6 +348,28 @@ int mb_run(mb_handle *h, int64_t n_steps, void *hip_stream) {
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   (void)hipEventRecord(b, st);
   h->events.emplace_back(a, b);
+  return MB_OK;
+  MB_GUARD_END
+}
+
+int mb_run_static(mb_handle *h, int64_t n_steps, void *hip_stream) {
+  MB_GUARD_BEGIN
+  if (!h) return fail(MB_ERR_ARG, "null handle");
+  if (hipSetDevice(h->device) != hipSuccess) return fail(MB_ERR_HIP, "hipSetDevice failed");
+  SimState &s = h->eng->sim(h->id);
+  int64_t remaining = s.plan.n_steps - s.done;
+  if (n_steps < 0 || n_steps > remaining) n_steps = remaining;
+  if (n_steps == 0) return MB_OK;
+  std::string err;
+  void *base = scratch_address(h->device, err);
+  if (!base) return fail(MB_ERR_HIP, err);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (h->last_stream != st) (void)hipStreamSynchronize(h->last_stream);
+  h->last_stream = st;
+  int rc = MB_OK;
+  hipError_t e = h->eng->run_in_tables(st, n_steps, static_cast<char *>(base), scratch_capacity(), rc, err);
+  if (rc < 0) return fail(rc, err);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return MB_OK;
   MB_GUARD_END
 }

@@ -6,6 +6,7 @@
 #include <numeric>
 
 #include "launch.hpp"
+#include "scratch.hpp"
 
 namespace mb {
 
@@ -451,9 +452,11 @@ void Engine::remove(int id, Arena *arena) {
   s.plan.sources.clear();
 }
 
-hipError_t Engine::upload_group(Group &g, hipStream_t st) {
-  std::vector<DevSim> hs;
-  std::vector<DevTile> ht;
+// the group's simulation descriptors and tiles (T owned cells each, chained
+// left/right within a simulation)
+void Engine::build_tables(const Group &g, std::vector<DevSim> &hs, std::vector<DevTile> &ht) const {
+  hs.clear();
+  ht.clear();
   const bool plain = variant_ == MB_VARIANT_PLAIN;
   const int span = plain ? plain_block() : block_ - 2 * halo_;
   for (int id : g.members) {
@@ -467,6 +470,12 @@ hipError_t Engine::upload_group(Group &g, hipStream_t st) {
       if (idx > first) ht[idx - 1].right = idx;
     }
   }
+}
+
+hipError_t Engine::upload_group(Group &g, hipStream_t st) {
+  std::vector<DevSim> hs;
+  std::vector<DevTile> ht;
+  build_tables(g, hs, ht);
   if (int(hs.size()) > g.cap_sims) {
     if (g.d_sims) (void)hipFree(g.d_sims);
     g.cap_sims = std::max<int>(int(hs.size()), 2 * g.cap_sims);
@@ -581,6 +590,104 @@ hipError_t Engine::run_persistent(hipStream_t st, int k, int64_t reps) {
     reps -= n;
   }
   return hipSuccess;
+}
+
+namespace {
+struct TableSpan {
+  size_t sims, tiles, flags, end;
+};
+TableSpan table_span(size_t at, size_t n_sims, size_t n_tiles) {
+  TableSpan t;
+  t.sims = align_up(at);
+  t.tiles = align_up(t.sims + n_sims * sizeof(DevSim));
+  t.flags = align_up(t.tiles + n_tiles * sizeof(DevTile));
+  t.end = t.flags + n_tiles * sizeof(uint32_t);
+  return t;
+}
+}  // namespace
+
+size_t Engine::table_bytes() const {
+  size_t at = 0;
+  std::vector<DevSim> hs;
+  std::vector<DevTile> ht;
+  for (const auto &g : groups_) {
+    if (g.members.empty()) continue;
+    build_tables(g, hs, ht);
+    at = table_span(at, hs.size(), ht.size()).end;
+  }
+  return at;
+}
+
+hipError_t Engine::run_in_tables(hipStream_t st, int64_t steps, char *base, size_t bytes, int &rc,
+                                 std::string &err) {
+  rc = MB_OK;
+  const size_t need = table_bytes();
+  if (need > bytes) {
+    rc = MB_ERR_BUDGET;
+    err = "the run's group tables need " + std::to_string(need) + " bytes; the static scratch holds " +
+          std::to_string(bytes);
+    return hipSuccess;
+  }
+  struct Saved {
+    Group *g;
+    DevSim *sims;
+    DevTile *tiles;
+    uint32_t *flags;
+    int n_tiles;
+  };
+  std::vector<Saved> saved;
+  hipError_t e = hipSuccess;
+  size_t at = 0;
+  // host images of every group's tables, alive until the copies completed
+  std::vector<std::vector<DevSim>> hsims;
+  std::vector<std::vector<DevTile>> htiles;
+  for (auto &g : groups_) {
+    if (g.members.empty()) continue;
+    hsims.emplace_back();
+    htiles.emplace_back();
+    std::vector<DevSim> &hs = hsims.back();
+    std::vector<DevTile> &ht = htiles.back();
+    build_tables(g, hs, ht);
+    const TableSpan t = table_span(at, hs.size(), ht.size());
+    at = t.end;
+    saved.push_back(Saved{&g, g.d_sims, g.d_tiles, g.d_flags, g.n_tiles});
+    g.d_sims = reinterpret_cast<DevSim *>(base + t.sims);
+    g.d_tiles = reinterpret_cast<DevTile *>(base + t.tiles);
+    g.d_flags = reinterpret_cast<uint32_t *>(base + t.flags);
+    g.n_tiles = int(ht.size());
+    if (e == hipSuccess && !hs.empty())
+      e = hipMemcpyAsync(g.d_sims, hs.data(), hs.size() * sizeof(DevSim), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !ht.empty())
+      e = hipMemcpyAsync(g.d_tiles, ht.data(), ht.size() * sizeof(DevTile), hipMemcpyHostToDevice, st);
+    // every tile's flag at the epoch of the next persistent launch (the
+    // scratch keeps whatever the last run on this GPU left there)
+    if (e == hipSuccess) e = fill_u32(g.d_flags, ht.size(), epoch_, st);
+  }
+  // the host vectors are copied before they go out of scope
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) {
+    dirty_ = false;
+    const int k = variant_ == MB_VARIANT_PLAIN ? 1 : chunk_steps();
+    if (variant_ != MB_VARIANT_PLAIN && persist_ok(k, steps / k)) {
+      e = run_persistent(st, k, steps / k);
+      steps %= k;
+    }
+    while (e == hipSuccess && steps > 0) {
+      const int kk = int(std::min<int64_t>(k, steps));
+      e = launch_only(st, kk);
+      if (e == hipSuccess) commit_chunk(kk);
+      steps -= kk;
+    }
+  }
+  // the engine's own tables are rebuilt at its next ordinary run
+  for (const Saved &sv : saved) {
+    sv.g->d_sims = sv.sims;
+    sv.g->d_tiles = sv.tiles;
+    sv.g->d_flags = sv.flags;
+    sv.g->n_tiles = sv.n_tiles;
+  }
+  dirty_ = true;
+  return e;
 }
 
 hipError_t Engine::launch_only(hipStream_t st, int k, int reps) {

@@ -129,6 +129,14 @@ class Engine {
   // chunk); only between chunks
   int reshape(int block, int halo, int lanes, std::string &err);
   int64_t total_cells() const;
+  // Runs `steps` steps like chunk()/run_persistent() -- persistent launches
+  // when the tiles fit, else one launch per chunk -- with the group tables
+  // (simulation descriptors, tiles, neighbour flags) written into the device
+  // region [base, base + bytes) instead of the engine's own table buffers:
+  // nothing is allocated or freed.  The region is rewritten by every such run
+  // (table_bytes() of it).  rc: MB_OK, or MB_ERR_BUDGET when the tables do not fit.
+  hipError_t run_in_tables(hipStream_t st, int64_t steps, char *base, size_t bytes, int &rc, std::string &err);
+  size_t table_bytes() const;
   hipError_t read_records(int id, int rec, std::vector<double> &out);
   hipError_t read_state(int id, double *e, double *h, double *rho);
   double cell_updates() const { return cell_updates_; }
@@ -147,6 +155,7 @@ class Engine {
   };
   Group &group_for(int levels, bool strong, bool cayley);
   hipError_t upload_group(Group &g, hipStream_t st);
+  void build_tables(const Group &g, std::vector<DevSim> &hs, std::vector<DevTile> &ht) const;
   hipError_t launch_group(Group &g, hipStream_t st, int k, int reps);
   int group_lanes(const Group &g) const;
 
