@@ -47,6 +47,15 @@ def flops_per_cell_update(n):
     return 8 + 6 * (n * (n - 1) // 2) + 2 * m + 2 * m * m + m
 
 
+def flops_issued_per_cell_update(n):
+    """Flops the kernels issue per cell-update: the state is kept in the basis of the
+    operators, so the field part goes through the eigenbasis coherences, z = t0 + T x
+    (2KM), their increments (6 per pair), p = p0 + at.x + as.d (2(M+K)) and
+    x += bf + (A - I) x + (A S) d (2M(M+K) + 2M), K = N(N-1), besides the Yee updates (8)."""
+    m, k = n * n - 1, n * (n - 1)
+    return 8 + 2 * k * m + 6 * (k // 2) + 2 * (m + k) + 2 * m * (m + k) + 2 * m
+
+
 def alu_tflops(n, cell_updates, ms):
     """Algorithmic TFLOP/s of cell_updates N-level cell-updates in ms milliseconds."""
     return flops_per_cell_update(n) * cell_updates / (ms * 1e-3) / 1e12
@@ -171,25 +180,107 @@ def timed_solves(hip, stream, solver, steps, warmup, n_launch):
     return wall, dev_ms
 
 
-def cpu_baseline(prob, budget_s):
-    """The FP64 oracle timed on one host thread over a bounded prefix of the workload."""
+def stored_lambda3_records(prob):
+    """The oracle's records of the full Lambda workload (tests/golden/oracle_lambda3.npz,
+    written by tests/golden/make_oracle_records.py; every stride-th sample), or None."""
+    path = os.path.join(ROOT, "tests", "golden", "oracle_lambda3.npz")
+    if not os.path.exists(path) or prob["nx"] != 32768 or prob["n_steps"] != 200000:
+        return None
+    d = np.load(path)
+    stride = int(d["lambda3/stride"])
+    return {r["name"]: d["lambda3/" + r["name"]] for r in prob["records"]}, stride
+
+
+def sweep_sub_batch(hip, stream, sims, log):
+    """The first members of the batched sweep as one batch in three forms, each timed
+    (HIP events, median of 3 after a warm-up): FP64 plain (two launches per step), FP64
+    temporally blocked, FP32 temporally blocked."""
+    cells = sum(p["nx"] * p["n_steps"] for p in sims)
+    out = {"sims": len(sims), "cell_updates": cells, "unit": "cell-updates/s"}
+    for key, prec, variant in (("fp64_plain", 64, "plain"), ("fp64_blocked", 64, "auto"),
+                               ("fp32_blocked", 32, "auto")):
+        log(f"[bench] sweep sub-batch of {len(sims)}: {key}")
+        probs = [dict(p, precision=prec) for p in sims]
+        bt = mb.Batch(probs, precision=prec, variant=variant)
+        bt.run(stream=stream, use_graph=True)
+        hip.sync()
+        ms = []
+        for _ in range(3):
+            bt.reset(stream)
+            a, b = hip.event(), hip.event()
+            hip.record(a, stream)
+            bt.run(stream=stream, use_graph=True)
+            hip.record(b, stream)
+            ms.append(hip.elapsed_ms(a, b))
+        bt.close()
+        out[key] = cells / (float(np.median(ms)) * 1e-3)
+    out["fp32_blocked_over_fp64_plain"] = out["fp32_blocked"] / out["fp64_plain"]
+    return out
+
+
+def _oracle_prefix(args):
+    """Worker: the FP64 oracle on the first n_steps of a workload (one BLAS thread);
+    returns (steps, seconds, records)."""
+    name, n_steps, budget_s = args
     from threadpoolctl import threadpool_limits
     from oracle import Oracle
 
+    prob = _cpu_workload(name)
     with threadpool_limits(limits=1):
         orc = Oracle(prob)
+        step_rec = max(r["interval"] for r in prob["records"])
         t0 = time.perf_counter()
         n = 0
-        step_rec = max(r["interval"] for r in prob["records"])
-        while True:
+        while n < min(n_steps, prob["n_steps"]):
             for _ in range(step_rec):
                 orc.step()
             n += step_rec
-            el = time.perf_counter() - t0
-            if el > budget_s or n >= prob["n_steps"]:
+            if budget_s is not None and time.perf_counter() - t0 > budget_s:
                 break
-    recs = {k: np.array(v) for k, v in orc.records.items()}
-    return n, el, recs
+        el = time.perf_counter() - t0
+    return n, el, {k: np.array(v) for k, v in orc.records.items()}
+
+
+def _cpu_workload(name):
+    if name == "lambda3":
+        return W.lambda3(precision=32)
+    if name == "sit":
+        return W.sit_2lvl()
+    raise ValueError(name)
+
+
+def host_cores():
+    """Host cores this process may use (the GPU machine's share is 16 cores per GPU)."""
+    return max(1, min(len(os.sched_getaffinity(0)), 16))
+
+
+def cpu_baselines(budget_s, log):
+    """The FP64 oracle on the host, before the GPU is touched (worker processes are
+    forked): the Lambda workload's prefix on one thread alone, then the same prefix as
+    independent solves on every host core at once, then the SIT workload in full on one
+    thread."""
+    import multiprocessing as mp
+
+    cores = host_cores()
+    log(f"[bench] oracle on the host: lambda3 prefix on 1 thread, then on {cores} cores; sit in full")
+    n1, t1, rec1 = _oracle_prefix(("lambda3", 10 ** 9, budget_s))
+    with mp.get_context("fork").Pool(cores) as pool:
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_prefix, [("lambda3", n1, None)] * cores)
+        tall = time.perf_counter() - t0
+    nx = W.lambda3(precision=32)["nx"]
+    n_sit, t_sit, rec_sit = _oracle_prefix(("sit", 10 ** 9, None))
+    sit = W.sit_2lvl()
+    return {
+        "value": cores * nx * n1 / tall, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+        "sample": (f"first {n1} of 200000 steps of the same workload (all {nx} cells), numpy FP64: "
+                   f"{cores} independent solves at once, one BLAS thread each, wall {tall:.1f} s"),
+        "value_1thread": nx * n1 / t1, "seconds_1thread": t1,
+        "per_process_s": [float(r[1]) for r in res],
+        "sit_full_run": {"value": sit["nx"] * n_sit / t_sit, "unit": "cell-updates/s", "cores": 1,
+                         "steps": n_sit, "seconds": t_sit,
+                         "sample": "the SIT workload in full (1500 cells x 20000 steps), one thread"},
+    }, n1, rec1, rec_sit
 
 
 def levels_of(prob):
@@ -201,8 +292,9 @@ def levels_of(prob):
     return 0
 
 
-def run_serving(n_requests, rate, log):
-    """Poisson trace through the continuous-batching server; latency = arrival to records on the host."""
+def run_serving(n_requests, rate, log, first_n=0):
+    """Poisson trace through the continuous-batching server; latency = arrival to records on
+    the host (also p50/p99 over the first first_n requests, for the FIFO comparison)."""
     log(f"[bench] serving {n_requests} requests at {rate:g}/s")
     trace = W.serve_trace(n_requests=n_requests, rate=rate, precision=32)
     srv = mb.Server(hbm_budget=16 << 30, max_slots=512, precision=32, chunk_steps=256)
@@ -222,94 +314,116 @@ def run_serving(n_requests, rate, log):
     cu, busy, chunks = srv.stats()
     srv.close()
     lat = np.array(lat)
+    if first_n:
+        sub = lat[:first_n]
+        first = {"requests": int(len(sub)), "p50_latency_s": float(np.percentile(sub, 50)),
+                 "p99_latency_s": float(np.percentile(sub, 99))}
     return {"requests": len(trace), "done": int(len(lat)), "arrival_rate_per_s": rate,
+            **({"first_requests": first} if first_n else {}),
             "offered_cell_updates_per_s": offered,
             "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
             "p50_latency_s_by_levels": {str(k): float(np.percentile(v, 50)) for k, v in sorted(by_levels.items())},
             "value": cu / tw, "unit": "cell-updates/s", "wall_s": tw, "busy_s": busy, "chunks": int(chunks)}
 
 
-def solve_once(hip, stream, prob, precision, variant="auto"):
-    """Setup, one untimed graph-capturing run, then one timed run from the restored initial state."""
+def solve_median(hip, stream, prob, precision, variant="auto", reps=5):
+    """Setup, one untimed (graph-capturing) run, then `reps` runs from the restored
+    initial state timed with HIP events on the stream; the median device time (ms),
+    the records of the last run and the tile shape."""
     s = mb.Solver(prob, precision=precision, variant=variant)
     s.run(-1, stream)
     hip.sync()
-    s.reset(stream)
-    a, b = hip.event(), hip.event()
-    hip.record(a, stream)
-    s.run(-1, stream)
-    hip.record(b, stream)
+    ms = []
+    for _ in range(reps):
+        s.reset(stream)
+        a, b = hip.event(), hip.event()
+        hip.record(a, stream)
+        s.run(-1, stream)
+        hip.record(b, stream)
+        ms.append(hip.elapsed_ms(a, b))
     hip.sync()
-    ms = hip.elapsed_ms(a, b)
     rec = s.records()
     shape = s.shape()
     s.close()
-    return ms, rec, shape
+    return float(np.median(ms)), rec, shape
 
 
-def other_configs(hip, stream, log):
-    """Throughput and FP32 error of the other scenario shapes."""
+def with_steps(prob, n_steps):
+    p = dict(prob)
+    p["n_steps"] = int(n_steps)
+    return p
+
+
+def crossing_step(prob, got, ref, tol):
+    """First recorded step at which the per-trace error of got against ref, taken over
+    the samples up to it, exceeds tol (None if it never does)."""
+    from workloads.errors import floor_of
+    first = None
+    for r in prob["records"]:
+        a, b = np.asarray(got[r["name"]]), np.asarray(ref[r["name"]])
+        n = min(len(a), len(b))
+        if n == 0:
+            continue
+        err = np.maximum.accumulate(np.abs(a[:n] - b[:n]))
+        scale = np.maximum(np.maximum.accumulate(np.abs(b[:n])), floor_of(prob, r["quantity"]))
+        bad = np.nonzero(err / scale > tol)[0]
+        if len(bad):
+            step = int((bad[0] + 1) * r["interval"])
+            first = step if first is None else min(first, step)
+    return first
+
+
+def leg(hip, stream, name, prob, log, timing_steps=None, error_steps=None, ref=None):
+    """FP32 and FP64 throughput of one workload (median of 5 event-timed solves of
+    timing_steps steps, default all), and the FP32 error against FP64 over error_steps
+    (default all) with the step at which it first exceeds 1e-4; ref: oracle records of
+    the workload (then the errors of both precisions against them as well)."""
+    tp = with_steps(prob, timing_steps) if timing_steps else prob
+    log(f"[bench] {name}: {tp['nx']} cells, {tp['n_steps']} steps, median of 5, fp32 / fp64")
+    ms32, r32, sh32 = solve_median(hip, stream, tp, 32)
+    ms64, r64, sh64 = solve_median(hip, stream, tp, 64)
+    cells = tp["nx"] * tp["n_steps"]
+    n = levels_of(prob)
+    out = {"nx": prob["nx"], "n_steps_timed": tp["n_steps"], "unit": "cell-updates/s",
+           "fp32": cells / (ms32 * 1e-3), "fp64": cells / (ms64 * 1e-3),
+           "fp32_ms_median": ms32, "fp64_ms_median": ms64,
+           "fp32_tflops_algorithmic": alu_tflops(n, cells, ms32) if n else None,
+           "shape_fp32": list(sh32), "shape_fp64": list(sh64)}
+    if error_steps != timing_steps:
+        ep = with_steps(prob, error_steps) if error_steps else prob
+        log(f"[bench] {name}: {ep['n_steps']}-step runs for the FP32 error")
+        _, r32, _ = solve_median(hip, stream, ep, 32, reps=1)
+        _, r64, _ = solve_median(hip, stream, ep, 64, reps=1)
+    else:
+        ep = tp
+    out["n_steps_error"] = ep["n_steps"]
+    out["fp32_vs_fp64_max_rel_err"] = max_error(ep, r32, r64)
+    out["fp32_vs_fp64_crosses_1e-4_at_step"] = crossing_step(ep, r32, r64, 1e-4)
+    if ref is not None:
+        out["fp32_vs_oracle_max_rel_err"] = rel_err(ep, r32, ref)
+        out["fp64_vs_oracle_max_rel_err"] = rel_err(ep, r64, ref)
+    return out
+
+
+def other_configs(hip, stream, log, sit_ref=None):
+    """Throughput (median of 5 event-timed solves) and FP32 error of the other scenario shapes."""
     res = {}
-    log("[bench] sit 2-level fp64/fp32")
-    p = W.sit_2lvl()
-    ms64, r64, sh64 = solve_once(hip, stream, p, 64)
-    ms32, r32, sh32 = solve_once(hip, stream, p, 32)
-    cells = p["nx"] * p["n_steps"]
-    res["sit_2lvl"] = {"nx": p["nx"], "n_steps": p["n_steps"], "fp64": cells / (ms64 * 1e-3),
-                       "fp32": cells / (ms32 * 1e-3), "unit": "cell-updates/s",
-                       "fp32_vs_fp64_max_rel_err": max_error(p, r32, r64), "shape_fp32": list(sh32)}
-    log("[bench] qcl-like 6-level fp32/fp64, 1e6 steps")
-    p = W.qcl6()
-    ms32, r32, sh32 = solve_once(hip, stream, p, 32)
-    ms64, r64, sh64 = solve_once(hip, stream, p, 64)
-    cells = p["nx"] * p["n_steps"]
-    res["qcl_6lvl"] = {"nx": p["nx"], "n_steps": p["n_steps"], "fp32": cells / (ms32 * 1e-3),
-                       "fp64": cells / (ms64 * 1e-3), "unit": "cell-updates/s",
-                       "fp32_vs_fp64_max_rel_err": max_error(p, r32, r64), "shape_fp32": list(sh32)}
-    log("[bench] paper's 5-level QCL comb (R = 0.8 mirrors) fp32/fp64, 200000 steps")
-    p = W.qcl5_comb()
-    ms32, r32, sh32 = solve_once(hip, stream, p, 32)
-    ms64, r64, sh64 = solve_once(hip, stream, p, 64)
-    cells = p["nx"] * p["n_steps"]
-    res["qcl_5lvl_comb"] = {"nx": p["nx"], "n_steps": p["n_steps"], "fp32": cells / (ms32 * 1e-3),
-                            "fp64": cells / (ms64 * 1e-3), "unit": "cell-updates/s",
-                            "fp32_vs_fp64_max_rel_err": max_error(p, r32, r64), "shape_fp32": list(sh32),
-                            "shape_fp64": list(sh64)}
-    log("[bench] lambda3 with strong coupling fp32/fp64")
+    res["sit_2lvl"] = leg(hip, stream, "sit 2-level", W.sit_2lvl(), log, ref=sit_ref)
+    # 1e6 steps: timed on 50000, FP32 against FP64 over 200000
+    res["qcl_6lvl"] = leg(hip, stream, "qcl-like 6-level", W.qcl6(), log, timing_steps=50000, error_steps=200000)
+    res["qcl_5lvl_comb"] = leg(hip, stream, "paper's 5-level comb (R = 0.8)", W.qcl5_comb(), log,
+                               timing_steps=50000, error_steps=200000)
     p = W.lambda3()
     p["coupling"] = "strong"
-    ms32, r32, sh32 = solve_once(hip, stream, p, 32)
-    ms64, r64, sh64 = solve_once(hip, stream, p, 64)
-    cells = p["nx"] * p["n_steps"]
-    res["lambda3_strong_coupling"] = {"nx": p["nx"], "n_steps": p["n_steps"], "fp32": cells / (ms32 * 1e-3),
-                                      "fp64": cells / (ms64 * 1e-3), "unit": "cell-updates/s",
-                                      "fp32_tflops_algorithmic": alu_tflops(3, cells, ms32),
-                                      "fp32_alu_frac": alu_tflops(3, cells, ms32) / PEAK["fp32_tflops"],
-                                      "fp32_vs_fp64_max_rel_err": max_error(p, r32, r64),
-                                      "shape_fp32": list(sh32)}
-    log("[bench] lambda3 with the Cayley field step fp32/fp64")
+    res["lambda3_strong_coupling"] = leg(hip, stream, "lambda3 strong coupling", p, log)
     p = W.lambda3()
     p["field_step"] = "cayley"
-    ms32, r32, sh32 = solve_once(hip, stream, p, 32)
-    ms64, r64, sh64 = solve_once(hip, stream, p, 64)
-    cells = p["nx"] * p["n_steps"]
-    res["lambda3_cayley_field_step"] = {"nx": p["nx"], "n_steps": p["n_steps"], "fp32": cells / (ms32 * 1e-3),
-                                        "fp64": cells / (ms64 * 1e-3), "unit": "cell-updates/s",
-                                        "fp32_tflops_algorithmic": alu_tflops(3, cells, ms32),
-                                        "fp32_alu_frac": alu_tflops(3, cells, ms32) / PEAK["fp32_tflops"],
-                                        "fp64_alu_frac": alu_tflops(3, cells, ms64) / PEAK["fp64_tflops"],
-                                        "fp32_vs_fp64_max_rel_err": max_error(p, r32, r64),
-                                        "shape_fp32": list(sh32), "shape_fp64": list(sh64)}
-    log("[bench] anharmonic ladder N = 2..6, 8192 cells, 20000 steps, fp32/fp64")
+    res["lambda3_cayley_field_step"] = leg(hip, stream, "lambda3 Cayley field step", p, log)
     scal = {}
     for n in range(2, 7):
-        p = W.ladder(n)
-        ms32, r32, sh32 = solve_once(hip, stream, p, 32)
-        ms64, r64, sh64 = solve_once(hip, stream, p, 64)
-        cells = p["nx"] * p["n_steps"]
-        scal[str(n)] = {"fp32": cells / (ms32 * 1e-3), "fp64": cells / (ms64 * 1e-3),
-                        "fp32_vs_fp64_max_rel_err": max_error(p, r32, r64),
-                        "flop_per_cell_update": flops_per_cell_update(n), "shape_fp32": list(sh32)}
+        r = leg(hip, stream, f"anharmonic ladder N={n}", W.ladder(n), log)
+        r["flop_per_cell_update"] = flops_per_cell_update(n)
+        scal[str(n)] = r
     res["ladder_n_scaling"] = {"nx": 8192, "n_steps": 20000, "unit": "cell-updates/s", "by_levels": scal}
     log("[bench] sweep x8: 2048 sims fp32 (state beyond the 256 MB last-level cache)")
     sims = W.sweep(n_sims=2048, precision=32, seed=W.SEED_BASE + 13)
@@ -327,10 +441,38 @@ def other_configs(hip, stream, log):
                for k, q in enumerate(sims)) / tb / 1e9
     state_bytes = sum(q["nx"] * (2 + (3 if k % 2 == 0 else 8)) * 4 for k, q in enumerate(sims))
     res["sweep_x8"] = {"sims": len(sims), "cell_updates": bcells, "value": bcells / tb, "unit": "cell-updates/s",
-                       "wall_s": tb, "state_bytes_one_buffer": state_bytes, "hbm_effective_gbs": beff,
-                       "hbm_effective_frac": beff / PEAK["hbm_gbs"], "shape": list(bt.shape())}
+                       "wall_s": tb, "state_bytes_one_buffer": state_bytes,
+                       "bytes_algorithmic_per_s": beff * 1e9, "shape": list(bt.shape())}
     bt.close()
     return res
+
+
+def plain_fifo(trace, log):
+    """The baseline server: requests one after another in arrival order, each solved by
+    the plain FP64 kernel (two launches per step); latency = arrival to records on the
+    host, arrivals replayed on the wall clock."""
+    log(f"[bench] FIFO plain FP64 serving of {len(trace)} requests")
+    lat, by_levels = [], {}
+    cu = 0
+    t0 = time.perf_counter()
+    for ta, p in trace:
+        now = time.perf_counter() - t0
+        if now < ta:
+            time.sleep(ta - now)
+        s = mb.Solver(p, precision=64, variant="plain")
+        s.run()
+        s.records()
+        s.close()
+        done = time.perf_counter() - t0
+        lat.append(done - ta)
+        by_levels.setdefault(levels_of(p), []).append(done - ta)
+        cu += p["nx"] * p["n_steps"]
+    tw = time.perf_counter() - t0
+    lat = np.array(lat)
+    return {"requests": len(trace), "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)),
+            "p50_latency_s_by_levels": {str(k): float(np.percentile(v, 50)) for k, v in sorted(by_levels.items())},
+            "value": cu / tw, "unit": "cell-updates/s", "wall_s": tw}
 
 
 def main(argv=None):
@@ -369,6 +511,11 @@ def main(argv=None):
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library has no multi-GPU path",
               file=sys.stderr)
         return 2
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    # ---- CPU baseline first: its worker processes are forked before the GPU is touched
+    cpu = None
+    if not args.no_cpu:
+        cpu, n_cpu, ref_prefix, ref_sit = cpu_baselines(args.cpu_seconds, log)
     hip = Hip()
     stream = hip.stream()
     if args.copy_bytes > 0:
@@ -378,7 +525,6 @@ def main(argv=None):
     wname = "lambda3-3lvl" + ("-cayley" if args.field_step == "cayley" else "")
     n_levels = 3
     cells = prob["nx"] * prob["n_steps"]
-    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
 
     # ---- main leg: FP32 temporally blocked -------------------------------------------
     log(f"[bench] lambda3 fp32 blocked nx={prob['nx']} nt={prob['n_steps']}")
@@ -426,9 +572,12 @@ def main(argv=None):
                      "launches_per_solve": n_launch, "steps_per_launch": steps_per_launch,
                      "chunk_us": chunk_us,
                      "flops_per_cell_update": flops_per_cell_update(n_levels),
+                     "flops_per_cell_update_issued": flops_issued_per_cell_update(n_levels),
                      "cell_updates_per_launch": prob["nx"] * steps_per_launch,
-                     "hbm_effective_gbs": eff_gbs, "hbm_effective_frac": eff_gbs / PEAK["hbm_gbs"]},
+                     "bytes_algorithmic_per_s": eff_gbs * 1e9},
     }
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
 
     # ---- FP64 legs ---------------------------------------------------------------------
     rec64 = None
@@ -437,7 +586,7 @@ def main(argv=None):
         s64 = mb.Solver(prob, precision=64, variant=variant, block=args.block, depth=args.depth,
                         lanes=args.lanes)
         b64, k64, r64, l64 = s64.shape()
-        w64, d64 = timed_solves(hip, stream, s64, 1, 1, math.ceil(prob["n_steps"] / k64))
+        w64, d64 = timed_solves(hip, stream, s64, 5, 1, math.ceil(prob["n_steps"] / k64))
         rec64 = s64.records()
         s64.close()
         log("[bench] lambda3 fp64 plain (two launches per step)")
@@ -449,25 +598,29 @@ def main(argv=None):
         recp = sp.records()
         sp.close()
         same = all(np.array_equal(recp[k], rec64[k]) for k in rec64)
-        out["fp64_blocked"] = {"value": cells / w64, "unit": "cell-updates/s", "device_ms": d64[0],
+        ms64 = float(np.median(d64))
+        out["fp64_blocked"] = {"value": cells / (ms64 * 1e-3), "unit": "cell-updates/s", "device_ms_median": ms64,
                                "block": b64, "depth": k64, "regs": r64, "lanes": l64,
-                               "tflops_algorithmic": alu_tflops(n_levels, cells, d64[0]),
-                               "alu_frac": alu_tflops(n_levels, cells, d64[0]) / PEAK["fp64_tflops"]}
+                               "tflops_algorithmic": alu_tflops(n_levels, cells, ms64),
+                               "alu_frac": alu_tflops(n_levels, cells, ms64) / PEAK["fp64_tflops"]}
         out["fp64_plain"] = {"value": cells / wp, "unit": "cell-updates/s", "wall_s": wp,
                              "bitwise_equal_to_fp64_blocked": bool(same)}
         out["fp32_vs_fp64_full_run_max_rel_err"] = rel_err(prob, rec32, rec64)
+        out["fp32_vs_fp64_full_run_crosses_1e-4_at_step"] = crossing_step(prob, rec32, rec64, 1e-4)
 
-    # ---- CPU baseline: the oracle on a bounded prefix, also the parity spot check -------
-    if not args.no_cpu:
-        log("[bench] oracle prefix on the host")
-        n_cpu, t_cpu, ref = cpu_baseline(prob, args.cpu_seconds)
-        out["cpu_baseline"] = {"value": prob["nx"] * n_cpu / t_cpu, "unit": "cell-updates/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": f"first {n_cpu} of {prob['n_steps']} steps of the same workload "
-                                         f"(all {prob['nx']} cells), numpy FP64, one thread"}
-        out["error_vs_oracle_prefix"] = {"steps": n_cpu, "fp32": rel_err(prob, rec32, ref)}
+    # ---- errors against the oracle: the prefix timed above, and the stored full run ----
+    if cpu is not None and args.nx == 32768:
+        out["error_vs_oracle_prefix"] = {"steps": n_cpu, "fp32": rel_err(prob, rec32, ref_prefix)}
         if rec64 is not None:
-            out["error_vs_oracle_prefix"]["fp64"] = rel_err(prob, rec64, ref)
+            out["error_vs_oracle_prefix"]["fp64"] = rel_err(prob, rec64, ref_prefix)
+    full_ref = stored_lambda3_records(prob)
+    if full_ref is not None:
+        ref, stride = full_ref
+        sub = lambda rec: {k: np.asarray(v)[stride - 1::stride] for k, v in rec.items()}  # noqa: E731
+        out["error_vs_oracle_full_run"] = {"steps": prob["n_steps"], "samples_per_trace": len(next(iter(ref.values()))),
+                                           "fp32": max_error(prob, sub(rec32), ref)}
+        if rec64 is not None:
+            out["error_vs_oracle_full_run"]["fp64"] = max_error(prob, sub(rec64), ref)
     s32.close()
 
     # ---- batched sweep ---------------------------------------------------------------
@@ -489,20 +642,29 @@ def main(argv=None):
                    for k, p in enumerate(sims)) / tb / 1e9
         bflop = sum(flops_per_cell_update(2 if k % 2 == 0 else 3) * p["nx"] * p["n_steps"]
                     for k, p in enumerate(sims)) / tb / 1e12
-        out["batched_sweep"] = {"tflops_algorithmic": bflop, "alu_frac": bflop / PEAK["fp32_tflops"],"value": bcells / tb, "unit": "cell-updates/s", "sims": len(sims),
-                                "cell_updates": bcells, "wall_s": tb, "hbm_effective_gbs": beff,
-                                "hbm_effective_frac": beff / PEAK["hbm_gbs"], "block": bblock, "depth": bdepth, "regs": bregs,
-                                "lanes": blanes}
+        out["batched_sweep"] = {"tflops_algorithmic": bflop, "alu_frac": bflop / PEAK["fp32_tflops"],
+                                "value": bcells / tb, "unit": "cell-updates/s", "sims": len(sims),
+                                "cell_updates": bcells, "wall_s": tb, "bytes_algorithmic_per_s": beff * 1e9,
+                                "block": bblock, "depth": bdepth, "regs": bregs, "lanes": blanes,
+                                "launch_form": "one kernel per level count and chunk, replayed from a HIP graph"}
         bt.close()
+        out["batched_sweep_sub32"] = sweep_sub_batch(hip, stream, sims[:32], log)
 
     # ---- other configurations --------------------------------------------------------
     if not args.no_configs:
-        out["configs"] = other_configs(hip, stream, log)
+        out["configs"] = other_configs(hip, stream, log, sit_ref=ref_sit if cpu is not None else None)
 
     # ---- serving ---------------------------------------------------------------------
     if not args.no_serve:
-        out["serving"] = run_serving(args.serve_requests, 200.0, log)
-        out["serving_low_load"] = [run_serving(n, rate, log) for rate, n in ((25.0, 50), (50.0, 100), (100.0, 150))]
+        n_fifo = 60
+        out["serving"] = run_serving(args.serve_requests, 200.0, log, first_n=n_fifo)
+        out["serving_low_load"] = [run_serving(n, rate, log, first_n=n)
+                                   for rate, n in ((25.0, 50), (50.0, 100), (100.0, 150))]
+        full = W.serve_trace(n_requests=args.serve_requests, rate=200.0, precision=32)
+        low = W.serve_trace(n_requests=50, rate=25.0, precision=32)
+        out["serving_fifo_plain_fp64"] = {
+            "rate_200": {**plain_fifo(full[:n_fifo], log), "trace": f"first {n_fifo} requests of the 200/s trace"},
+            "rate_25": {**plain_fifo(low, log), "trace": "the 50-request 25/s trace"}}
 
     line = json.dumps(out)
     print(line, flush=True)

@@ -76,16 +76,8 @@ namespace {
 
 // Advances the engine by `steps` steps in chunks of at most k.  With
 // use_graph the chunk launches are captured into one HIP graph (or the
-// cached graph of an identical earlier run is replayed).
-// Setting MB_GRAPHS=0 in the environment turns capture off (direct launches),
-// for tools that do not follow graph launches.
-bool graphs_enabled() {
-  static const bool on = [] {
-    const char *v = std::getenv("MB_GRAPHS");
-    return !(v && v[0] == '0');
-  }();
-  return on;
-}
+// cached graph of an identical earlier run is replayed); MB_GRAPHS=0 turns
+// capture off (graphs_enabled).
 
 hipError_t run_steps(Engine &eng, hipStream_t st, int64_t steps, int k, bool use_graph, GraphCache &gc) {
   hipError_t e = eng.sync_tables(st);
@@ -116,16 +108,11 @@ hipError_t run_steps(Engine &eng, hipStream_t st, int64_t steps, int k, bool use
   hipStream_t cap;
   if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) return e;
   e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-  // full chunks in one fork/join, then the shorter tail chunk
+  // full chunks in one fork/join, then the shorter tail chunk; the host step
+  // counters advance only once the graph has been launched
   const int64_t full = steps / k, tail = steps % k;
-  if (e == hipSuccess && full > 0) {
-    e = eng.launch_only(cap, k, int(full));
-    for (int64_t q = 0; q < full; ++q) eng.commit_chunk(k);
-  }
-  if (e == hipSuccess && tail > 0) {
-    e = eng.launch_only(cap, int(tail));
-    eng.commit_chunk(int(tail));
-  }
+  if (e == hipSuccess && full > 0) e = eng.launch_only(cap, k, int(full));
+  if (e == hipSuccess && tail > 0) e = eng.launch_only(cap, int(tail));
   hipGraph_t graph = nullptr;
   hipError_t e2 = hipStreamEndCapture(cap, &graph);
   (void)hipStreamDestroy(cap);
@@ -141,7 +128,14 @@ hipError_t run_steps(Engine &eng, hipStream_t st, int64_t steps, int k, bool use
   gc.n0 = n0;
   gc.steps = steps;
   gc.k = k;
-  return hipGraphLaunch(gc.exec, st);
+  e = hipGraphLaunch(gc.exec, st);
+  if (e != hipSuccess) {
+    gc.clear();
+    return e;
+  }
+  for (int64_t q = 0; q < full; ++q) eng.commit_chunk(k);
+  if (tail > 0) eng.commit_chunk(int(tail));
+  return hipSuccess;
 }
 
 #define MB_GUARD_BEGIN try {

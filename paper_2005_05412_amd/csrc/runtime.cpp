@@ -131,6 +131,14 @@ void fill_state(const SimPlan &p, char *head, const Layout &L) {
 
 size_t sim_bytes(const SimPlan &p, int precision, bool plain) { return layout_of(p, precision, plain).total; }
 
+bool graphs_enabled() {
+  static const bool on = [] {
+    const char *v = std::getenv("MB_GRAPHS");
+    return !(v && v[0] == '0');
+  }();
+  return on;
+}
+
 void default_shape(int levels, int precision, int &block, int &halo) {
   (void)precision;
   if (levels >= 5) {

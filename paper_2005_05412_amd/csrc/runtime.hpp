@@ -183,6 +183,11 @@ class Engine {
   double cell_updates_ = 0;
 };
 
+// false when MB_GRAPHS=0 is set in the environment: runs and the tuner launch
+// chunks directly instead of capturing them into HIP graphs (for tools that do
+// not follow graph launches)
+bool graphs_enabled();
+
 // default tile shape per level count and precision
 void default_shape(int levels, int precision, int &block, int &halo);
 

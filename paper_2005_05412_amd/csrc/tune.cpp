@@ -166,31 +166,45 @@ int tune_shape(int device, const std::vector<const SimPlan *> &plans, int precis
     int64_t timed = std::min<int64_t>(avail - 2, std::max<int64_t>(4, 8192 / k));
     hipError_t he = eng.sync_tables(st);
     for (int q = 0; q < 2 && he == hipSuccess; ++q) he = eng.chunk(st, k);
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    hipStream_t cap = nullptr;
-    if (he == hipSuccess) he = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-    if (he == hipSuccess) he = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (he == hipSuccess) {
-      for (int64_t q = 0; q < timed && he == hipSuccess; ++q) {
-        he = eng.launch_only(cap, k);
-        eng.commit_chunk(k);
-      }
-      hipError_t e2 = hipStreamEndCapture(cap, &graph);
-      if (he == hipSuccess) he = e2;
-    }
-    if (he == hipSuccess) he = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (he == hipSuccess) he = hipStreamSynchronize(st);
-    if (he == hipSuccess) {
+    if (he == hipSuccess && graphs_enabled()) {
+      // the chunks captured into one graph, as mb_run replays them
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      hipStream_t cap = nullptr;
+      he = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+      if (he == hipSuccess) he = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+      if (he == hipSuccess) {
+        he = eng.launch_only(cap, k, int(timed));
+        hipError_t e2 = hipStreamEndCapture(cap, &graph);
+        if (he == hipSuccess) he = e2;
+      }
+      if (he == hipSuccess) he = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (he == hipSuccess) {
+        (void)hipEventRecord(a, st);
+        he = hipGraphLaunch(exec, st);
+        (void)hipEventRecord(b, st);
+      }
+      if (he == hipSuccess) {
+        for (int64_t q = 0; q < timed; ++q) eng.commit_chunk(k);
+        he = hipEventSynchronize(b);
+      }
+      // destroyed once the replay has completed (or never started)
+      if (he != hipSuccess) (void)hipStreamSynchronize(st);
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (cap) (void)hipStreamDestroy(cap);
+    } else if (he == hipSuccess) {
+      // MB_GRAPHS=0: direct launches, one per chunk
       (void)hipEventRecord(a, st);
-      he = hipGraphLaunch(exec, st);
+      for (int64_t q = 0; q < timed && he == hipSuccess; ++q) he = eng.chunk(st, k);
       (void)hipEventRecord(b, st);
+      if (he == hipSuccess) he = hipEventSynchronize(b);
     }
-    if (he == hipSuccess) he = hipEventSynchronize(b);
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (cap) (void)hipStreamDestroy(cap);
-    if (he != hipSuccess) continue;
+    if (he != hipSuccess) {
+      (void)hipGetLastError();
+      continue;
+    }
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, a, b);
     double us = 1e3 * double(ms) / double(timed * k);
