@@ -232,7 +232,11 @@ int mb_device_count(void);
  * (the eigenvectors as the columns of a row-major complex N x N matrix V,
  * (re, im) pairs), kappa[N-1] (dt (lam_q - lam_{q+1}) / hbar), p0, at[M],
  * ah[M*M], bh[M], am[M*M], bf[M], t0[K], tm[K*M], sm[M*K], as[K], bm[M*K],
- * lvl[N] with M = N*N - 1 and K = N*(N-1).  The tables use the operator
+ * lvl[N], block with M = N*N - 1 and K = N*(N-1).  block is 1 when the
+ * kernels run the simulation's tables in the block form (every quantum
+ * material has a real dipole operator, H0 diagonal and relaxation in rate
+ * form: see engine.hpp; MB_BLOCK_FORM=0 in the environment turns it off), else 0.
+ * The tables use the operator
  * basis with the levels reordered: the caller's level i is level lvl[i] (the
  * most populated initial level is placed last, where the trace elimination
  * drops it).  The running state sigma (populations 0..N-2 and (Re, Im) of the

@@ -309,7 +309,7 @@ def plan_material(prob, material, precision=None):
         return d
     sizes = [("lam", lv), ("vec", 2 * lv * lv), ("kappa", lv - 1), ("p0", 1), ("at", M), ("ah", M * M), ("bh", M),
              ("am", M * M), ("bf", M), ("t0", K), ("tm", K * M), ("sm", M * K), ("as", K), ("bm", M * K),
-             ("lvl", lv)]
+             ("lvl", lv), ("block", 1)]
     k = 0
     for name, sz in sizes:
         d[name] = v[k:k + sz].copy()
@@ -322,6 +322,7 @@ def plan_material(prob, material, precision=None):
     d["sm"] = d["sm"].reshape(M, K)
     d["bm"] = d["bm"].reshape(M, K)
     d["lvl"] = d["lvl"].astype(int)
+    d["block"] = bool(d["block"][0])
     return d
 
 

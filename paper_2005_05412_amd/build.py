@@ -12,14 +12,11 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libmbhip.so")
 OBJ = os.path.join(HERE, "_build")
-# (source, extra flags, object name): the kernels are compiled in eight parts
-# (one-chunk and persistent tiles, exact and Cayley field step, FP32 and FP64)
-SOURCES = [("kernels.hip", ["-DMB_PART=1"], "kernels_f32"), ("kernels.hip", ["-DMB_PART=2"], "kernels_f64"),
-           ("kernels.hip", ["-DMB_PART=3"], "kernels_f32p"), ("kernels.hip", ["-DMB_PART=4"], "kernels_f64p"),
-           ("kernels.hip", ["-DMB_PART=5"], "kernels_f32c"), ("kernels.hip", ["-DMB_PART=6"], "kernels_f64c"),
-           ("kernels.hip", ["-DMB_PART=7"], "kernels_f32pc"), ("kernels.hip", ["-DMB_PART=8"], "kernels_f64pc"),
-           ("scratch.hip", [], "scratch")] + [
-    (f, [], f) for f in ("plan.cpp", "runtime.cpp", "tune.cpp", "abi.cpp", "server.cpp")]
+# (source, extra flags, object name): the kernels are compiled in sixteen parts
+# (FP32 and FP64, one-chunk and persistent tiles, exact and Cayley field step,
+# general and block form of the density tables)
+SOURCES = [("kernels.hip", [f"-DMB_PART={i + 1}"], f"kernels_{i:02d}") for i in range(16)] + [
+    ("scratch.hip", [], "scratch")] + [(f, [], f) for f in ("plan.cpp", "runtime.cpp", "tune.cpp", "abi.cpp", "server.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("MB_OFFLOAD_ARCH", "gfx950")
 

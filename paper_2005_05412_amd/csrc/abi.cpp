@@ -111,8 +111,11 @@ hipError_t run_steps(Engine &eng, hipStream_t st, int64_t steps, int k, bool use
   // full chunks in one fork/join, then the shorter tail chunk; the host step
   // counters advance only once the graph has been launched
   const int64_t full = steps / k, tail = steps % k;
+  const bool plain = eng.variant() == MB_VARIANT_PLAIN;
   if (e == hipSuccess && full > 0) e = eng.launch_only(cap, k, int(full));
-  if (e == hipSuccess && tail > 0) e = eng.launch_only(cap, int(tail));
+  // the tail starts after the full chunks, which are not committed yet
+  if (e == hipSuccess && tail > 0)
+    e = eng.launch_only(cap, int(tail), 1, full * k, int(plain ? (full * k) & 1 : full & 1));
   hipGraph_t graph = nullptr;
   hipError_t e2 = hipStreamEndCapture(cap, &graph);
   (void)hipStreamDestroy(cap);
@@ -210,6 +213,7 @@ int mb_plan_material(const mb_device_desc *dev, const mb_scenario_desc *scen, in
     for (auto *t : {&mp.at, &mp.ah, &mp.bh, &mp.am, &mp.bf, &mp.t0, &mp.tm, &mp.sm, &mp.as, &mp.bm})
       v.insert(v.end(), t->begin(), t->end());
     for (int l : mp.lvl) v.push_back(double(l));
+    v.push_back(plan.block_form ? 1.0 : 0.0);  // the form the kernels run for this simulation
   }
   if (int64_t(v.size()) > capacity) return fail(MB_ERR_ARG, "output buffer too small");
   if (!v.empty()) std::memcpy(out, v.data(), v.size() * sizeof(double));

@@ -31,6 +31,36 @@ __host__ __device__ constexpr int coef_t0(int n) { return coef_am(n) + mat_m(n) 
 __host__ __device__ constexpr int coef_tm(int n) { return coef_t0(n) + mat_k(n); }
 __host__ __device__ constexpr int coef_sg(int n) { return coef_tm(n) + mat_k(n) * mat_m(n); }
 __host__ __device__ constexpr int mat_stride(int n) { return n > 0 ? coef_sg(n) + n : kCoefKap; }
+// Block form of the same tables, for materials whose dipole operator is real
+// and whose free propagator e^{L0 dt} couples populations only among
+// themselves and each coherence only with itself (H0 diagonal, relaxation in
+// rate form): then z's real parts depend only on the populations and the real
+// parts of the coherences, its imaginary parts only on the imaginary parts,
+// the increment maps back the same way, and A - I is one population block and
+// a 2 x 2 block per pair.  P = N(N-1)/2 pairs, NP = N-1 stored populations:
+//   kappa[N-1], p0, at[M], as[K]   as above (same offsets)
+//   bfp[NP], ap[NP][NP]            populations: x <- y + bfp + ap y
+//   blk[P][4]                      pair r: (re, im) <- y + [[b0 b1] [b2 b3]] y
+//   t0r[P], tp[P][NP], tr[P][P], ti[P][P]    zr = t0r + tp x_pop + tr x_re, zi = ti x_im
+//   sp[NP][P], sr[P][P], si[P][P]  y_pop = x_pop + sp dr, y_re = x_re + sr dr, y_im = x_im + si di
+//   sigma[N]
+__host__ __device__ constexpr int pairs_of(int n) { return n > 0 ? n * (n - 1) / 2 : 0; }
+__host__ __device__ constexpr int bk_bf(int n) { return coef_as(n) + mat_k(n); }
+__host__ __device__ constexpr int bk_ap(int n) { return bk_bf(n) + (n > 0 ? n - 1 : 0); }
+__host__ __device__ constexpr int bk_blk(int n) { return bk_ap(n) + (n > 0 ? (n - 1) * (n - 1) : 0); }
+__host__ __device__ constexpr int bk_t0(int n) { return bk_blk(n) + 4 * pairs_of(n); }
+__host__ __device__ constexpr int bk_tp(int n) { return bk_t0(n) + pairs_of(n); }
+__host__ __device__ constexpr int bk_tr(int n) { return bk_tp(n) + pairs_of(n) * (n > 0 ? n - 1 : 0); }
+__host__ __device__ constexpr int bk_ti(int n) { return bk_tr(n) + pairs_of(n) * pairs_of(n); }
+__host__ __device__ constexpr int bk_sp(int n) { return bk_ti(n) + pairs_of(n) * pairs_of(n); }
+__host__ __device__ constexpr int bk_sr(int n) { return bk_sp(n) + (n > 0 ? n - 1 : 0) * pairs_of(n); }
+__host__ __device__ constexpr int bk_si(int n) { return bk_sr(n) + pairs_of(n) * pairs_of(n); }
+__host__ __device__ constexpr int bk_sg(int n) { return bk_si(n) + pairs_of(n) * pairs_of(n); }
+__host__ __device__ constexpr int bk_stride(int n) { return n > 0 ? bk_sg(n) + n : kCoefKap; }
+// coefficient stride and Cayley offset of a form
+__host__ __device__ constexpr int stride_of(int n, bool bk) { return bk ? bk_stride(n) : mat_stride(n); }
+__host__ __device__ constexpr int sigma_of(int n, bool bk) { return bk ? bk_sg(n) : coef_sg(n); }
+
 // FP64 readout row of a density record (and the strong-coupling trace) per
 // material: value = r0 + r . x + rs . d, length ro_len(N)
 __host__ __device__ constexpr int ro_len(int n) { return mat_m(n) + 1 + mat_k(n); }

@@ -159,20 +159,23 @@ __device__ __forceinline__ void phase(R t, R &cm, R &sn) {
 }
 
 // Work of a cell's density update shared out over L wave groups: the
-// eigenbasis coherence pairs (two rows of z each, M multiply-adds per row) and
-// the rows of the state (M + K multiply-adds each), each given in turn to the
-// least loaded group.
-template <int N, int L>
+// eigenbasis coherence pairs (their two rows of z), the stored populations and
+// the pairs of state rows (Re, Im of one coherence, kept together), each given
+// in turn to the least loaded group (costs in multiply-adds of the general or
+// the block form).
+template <int N, int L, bool BK = false>
 struct Split {
   static constexpr int M = mat_m(N);
+  static constexpr int K = mat_k(N);
   static constexpr int P = N > 0 ? N * (N - 1) / 2 : 0;
-  // item u < P: pair u; item P + a: state row a
+  static constexpr int NP = N > 0 ? N - 1 : 0;
+  // item u < P: z pair u; P + a: population row a; P + NP + r: rows of pair r
   static constexpr int owner(int item) {
     if (L == 1) return 0;
     int load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int who = 0;
     for (int u = 0; u <= item; ++u) {
-      const int cost = u < P ? 2 * M : M + 2 * P;
+      const int cost = u < P ? (BK ? NP + 2 * P : 2 * M) : u < P + NP ? (BK ? NP : M + K) : (BK ? 2 * P + 4 : 2 * (M + K));
       int best = 0;
       for (int g = 1; g < L; ++g)
         if (load[g] < load[best]) best = g;
@@ -181,31 +184,58 @@ struct Split {
     }
     return who;
   }
-  static constexpr bool owns(int sub, int a) { return L == 1 || owner(P + a) == sub; }
+  static constexpr int row_item(int a) { return a < NP ? P + a : P + NP + (a - NP) / 2; }
+  static constexpr bool owns(int sub, int a) { return L == 1 || owner(row_item(a)) == sub; }
   static constexpr bool owns_z(int sub, int r) { return L == 1 || owner(r / 2) == sub; }
+  static constexpr bool owns_pop(int sub) {
+    for (int a = 0; a < NP; ++a)
+      if (owns(sub, a)) return true;
+    return false;
+  }
 };
 
-template <int N, typename R>
+template <int N, typename R, bool BK = false>
 struct Cell {
   static constexpr int M = mat_m(N);
   static constexpr int MA = M > 0 ? M : 1;
   static constexpr int K = mat_k(N);
   static constexpr int KA = K > 0 ? K : 1;
+  static constexpr int P = K / 2;
+  static constexpr int NP = N > 0 ? N - 1 : 0;
 
   // entry t of the vector (x, d): the state, then the field increments
   static __device__ __forceinline__ R xd(const R (&x)[MA], const R (&d)[KA], int t) { return t < M ? x[t] : d[t - M]; }
 
   // z <- t0 + tm x: (Re, Im) of the coherences of the state in the dipole
-  // eigenbasis (with L > 1 the rows of the pairs owned by group SUB)
+  // eigenbasis (with L > 1 the rows of the pairs owned by group SUB); in the
+  // block form Re z from the populations and the real parts of x, Im z from
+  // the imaginary parts
   template <int L = 1, int SUB = 0, typename C>
   static __device__ __forceinline__ void coherences(const R (&x)[MA], R (&z)[KA], const C &mt) {
+    if constexpr (BK) {
 #pragma unroll
-    for (int r = 0; r < K; ++r) {
-      if (!Split<N, L>::owns_z(SUB, r)) continue;
-      R acc = mt[coef_t0(N) + r];
+      for (int q = 0; q < P; ++q) {
+        if (!Split<N, L, BK>::owns_z(SUB, 2 * q)) continue;
+        R zr = mt[bk_t0(N) + q], zi = R(0);
 #pragma unroll
-      for (int j = 0; j < M; ++j) acc = fma(mt[coef_tm(N) + r * M + j], x[j], acc);
-      z[r] = acc;
+        for (int a = 0; a < NP; ++a) zr = fma(mt[bk_tp(N) + q * NP + a], x[a], zr);
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+          zr = fma(mt[bk_tr(N) + q * P + r], x[NP + 2 * r], zr);
+          zi = fma(mt[bk_ti(N) + q * P + r], x[NP + 2 * r + 1], zi);
+        }
+        z[2 * q] = zr;
+        z[2 * q + 1] = zi;
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < K; ++r) {
+        if (!Split<N, L, BK>::owns_z(SUB, r)) continue;
+        R acc = mt[coef_t0(N) + r];
+#pragma unroll
+        for (int j = 0; j < M; ++j) acc = fma(mt[coef_tm(N) + r * M + j], x[j], acc);
+        z[r] = acc;
+      }
     }
   }
 
@@ -225,7 +255,7 @@ struct Cell {
       if (cay) {
 #pragma unroll
         for (int q = 0; q < N - 1; ++q) {
-          const R a = R(0.5) * e * mt[coef_sg(N) + q], b = R(0.5) * e * mt[coef_sg(N) + q + 1];
+          const R a = R(0.5) * e * mt[sigma_of(N, BK) + q], b = R(0.5) * e * mt[sigma_of(N, BK) + q + 1];
           const R dd = a - b, s = fma(a, b, R(1));
           const R inv = R(1) / fma(s, s, dd * dd);
           cm[q] = R(-2) * (dd * dd) * inv;
@@ -273,21 +303,61 @@ struct Cell {
 
   // sigma_{n+1} = e^{L0 dt} (x + S d): x_i <- x_i + (bf_i + (A - I)_i x +
   // (A S)_i d); with L > 1 the rows owned by group SUB (the others are left
-  // as they are)
+  // as they are).  Block form: y = x + S d by its real and imaginary parts,
+  // then x <- y + (bfp + ap y) on the populations and y + b y on each pair.
   template <int L = 1, int SUB = 0, typename C>
   static __device__ __forceinline__ void propagate(R (&x)[MA], const R (&d)[KA], const C &mt) {
-    R out[MA];
+    using SP = Split<N, L, BK>;
+    if constexpr (BK) {
+      // each row gains x + (increment): the small terms are summed on their own
+      if constexpr (SP::owns_pop(SUB)) {
+        R dp[NP > 0 ? NP : 1], yp[NP > 0 ? NP : 1];
 #pragma unroll
-    for (int i = 0; i < M; ++i) {
-      if (!Split<N, L>::owns(SUB, i)) continue;
-      R acc = mt[coef_bf(N) + i];
+        for (int a = 0; a < NP; ++a) {
+          R acc = R(0);
 #pragma unroll
-      for (int t = 0; t < M + K; ++t) acc = fma(mt[coef_am(N) + i * (M + K) + t], xd(x, d, t), acc);
-      out[i] = x[i] + acc;
+          for (int q = 0; q < P; ++q) acc = fma(mt[bk_sp(N) + a * P + q], d[2 * q], acc);
+          dp[a] = acc;
+          yp[a] = x[a] + acc;
+        }
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+          if (!SP::owns(SUB, a)) continue;
+          R acc = mt[bk_bf(N) + a];
+#pragma unroll
+          for (int b = 0; b < NP; ++b) acc = fma(mt[bk_ap(N) + a * NP + b], yp[b], acc);
+          x[a] = x[a] + (dp[a] + acc);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < P; ++r) {
+        if (!SP::owns(SUB, NP + 2 * r)) continue;
+        R dr = R(0), di = R(0);
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          dr = fma(mt[bk_sr(N) + r * P + q], d[2 * q], dr);
+          di = fma(mt[bk_si(N) + r * P + q], d[2 * q + 1], di);
+        }
+        const R yr = x[NP + 2 * r] + dr, yi = x[NP + 2 * r + 1] + di;
+        const R b0 = mt[bk_blk(N) + 4 * r], b1 = mt[bk_blk(N) + 4 * r + 1];
+        const R b2 = mt[bk_blk(N) + 4 * r + 2], b3 = mt[bk_blk(N) + 4 * r + 3];
+        x[NP + 2 * r] = x[NP + 2 * r] + (dr + fma(b0, yr, b1 * yi));
+        x[NP + 2 * r + 1] = x[NP + 2 * r + 1] + (di + fma(b2, yr, b3 * yi));
+      }
+    } else {
+      R out[MA];
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        if (!SP::owns(SUB, i)) continue;
+        R acc = mt[coef_bf(N) + i];
+#pragma unroll
+        for (int t = 0; t < M + K; ++t) acc = fma(mt[coef_am(N) + i * (M + K) + t], xd(x, d, t), acc);
+        out[i] = x[i] + acc;
+      }
+#pragma unroll
+      for (int i = 0; i < M; ++i)
+        if (SP::owns(SUB, i)) x[i] = out[i];
     }
-#pragma unroll
-    for (int i = 0; i < M; ++i)
-      if (Split<N, L>::owns(SUB, i)) x[i] = out[i];
   }
 
   // FP64 readout r0 + r . x + rs . d of a density quantity of rho^{n+1/2}
@@ -535,13 +605,13 @@ constexpr bool regs_fit() {
 
 // P: a persistent launch (several chunks, neighbour flags, device-coherent
 // exchange of the owned cells); without it one chunk, and none of that code
-template <int N, typename R, int B, int L, bool VC, int SUB, bool ST, bool P, bool CY>
+template <int N, typename R, int B, int L, bool VC, int SUB, bool ST, bool P, bool CY, bool BK>
 __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, const DevTile *__restrict__ tiles,
                                            int64_t n0, int parity, int halo, int k, const ChunkSync &cs,
                                            TileShared<N, R, B, L> &sm) {
-  using CL = Cell<N, R>;
-  using SP = Split<N, L>;
-  constexpr int M = CL::M, MA = CL::MA, S = mat_stride(N);
+  using CL = Cell<N, R, BK>;
+  using SP = Split<N, L, BK>;
+  constexpr int M = CL::M, MA = CL::MA, S = stride_of(N, BK);
   constexpr bool WAVE = B == 64 && L == 1;  // one wave per tile: neighbours by DPP, no barriers
   constexpr int SQ = S - kCoefKap;          // quantum part of a material's coefficients
   const DevTile tile = tiles[blockIdx.x];
@@ -665,8 +735,8 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
   // (those this wave group reads: phases, polarization, its propagator rows)
   auto coef_used = [](int i) {
     const int t = i + kCoefKap;
-    if (t >= coef_sg(N)) return CY;  // Cayley coefficients (every wave group rotates)
-    if (t < coef_bf(N)) return true;  // phases and polarization
+    if (t >= sigma_of(N, BK)) return CY;  // Cayley coefficients (every wave group rotates)
+    if (t < coef_bf(N) || BK) return true;  // phases and polarization; all of the (small) block form
     if (t < coef_am(N)) return SP::owns(SUB, t - coef_bf(N));
     if (t < coef_t0(N)) return SP::owns(SUB, (t - coef_am(N)) / prop_w(N));
     if (t < coef_tm(N)) return SP::owns_z(SUB, t - coef_t0(N));
@@ -957,31 +1027,32 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
 
 // runs the specialisation of wave group `sub` (wave-uniform); every group
 // executes the same sequence of barriers
-template <int N, typename R, int B, int L, bool VC, bool P, bool CY, int S = 0>
+template <int N, typename R, int B, int L, bool VC, bool P, bool CY, bool BK, int S = 0>
 __device__ __forceinline__ void run_group(int sub, const DevSim *__restrict__ sims, const DevTile *__restrict__ tiles,
                                           int64_t n0, int parity, int halo, int k, const ChunkSync &cs,
                                           TileShared<N, R, B, L> &sm) {
   if constexpr (S + 1 < L) {
     if (sub == S)
-      tile_steps<N, R, B, L, VC, S, false, P, CY>(sims, tiles, n0, parity, halo, k, cs, sm);
+      tile_steps<N, R, B, L, VC, S, false, P, CY, BK>(sims, tiles, n0, parity, halo, k, cs, sm);
     else
-      run_group<N, R, B, L, VC, P, CY, S + 1>(sub, sims, tiles, n0, parity, halo, k, cs, sm);
+      run_group<N, R, B, L, VC, P, CY, BK, S + 1>(sub, sims, tiles, n0, parity, halo, k, cs, sm);
   } else {
-    tile_steps<N, R, B, L, VC, S, false, P, CY>(sims, tiles, n0, parity, halo, k, cs, sm);
+    tile_steps<N, R, B, L, VC, S, false, P, CY, BK>(sims, tiles, n0, parity, halo, k, cs, sm);
   }
 }
 
-// ST: strong coupling (one wave per 64 cells only); CY: Cayley field step
-template <int N, typename R, int B, int L, bool VC, bool ST, bool P, bool CY>
+// ST: strong coupling (one wave per 64 cells only); CY: Cayley field step; BK:
+// the block form of the density tables
+template <int N, typename R, int B, int L, bool VC, bool ST, bool P, bool CY, bool BK>
 __global__ void __launch_bounds__(B * L) k_blocked(const DevSim *__restrict__ sims,
                                                    const DevTile *__restrict__ tiles, int64_t n0, int parity,
                                                    int halo, int k, ChunkSync cs) {
   __shared__ TileShared<N, R, B, L> sm;
   if constexpr (L == 1) {
-    tile_steps<N, R, B, 1, VC, 0, ST, P, CY>(sims, tiles, n0, parity, halo, k, cs, sm);
+    tile_steps<N, R, B, 1, VC, 0, ST, P, CY, BK>(sims, tiles, n0, parity, halo, k, cs, sm);
   } else {
-    run_group<N, R, B, L, VC, P, CY>(__builtin_amdgcn_readfirstlane(int(threadIdx.x) / B), sims, tiles, n0, parity, halo,
-                              k, cs, sm);
+    run_group<N, R, B, L, VC, P, CY, BK>(__builtin_amdgcn_readfirstlane(int(threadIdx.x) / B), sims, tiles, n0, parity,
+                                         halo, k, cs, sm);
   }
 }
 
@@ -992,13 +1063,13 @@ __global__ void __launch_bounds__(B * L) k_blocked(const DevSim *__restrict__ si
 // ---------------------------------------------------------------------------
 constexpr int kPlainBlock = 256;
 
-template <int N>
+template <int N, bool BK>
 __global__ void __launch_bounds__(kPlainBlock) k_plain_hd(const DevSim *__restrict__ sims,
                                                           const DevTile *__restrict__ tiles, int64_t n0,
                                                           int parity) {
   using R = double;
-  using CL = Cell<N, R>;
-  constexpr int M = CL::M, MA = CL::MA, S = mat_stride(N);
+  using CL = Cell<N, R, BK>;
+  constexpr int M = CL::M, MA = CL::MA, S = stride_of(N, BK);
   const DevTile tile = tiles[blockIdx.x];
   const DevSim &sim = sims[tile.sim];
   const int64_t n64 = n0 - sim.start;
@@ -1055,12 +1126,12 @@ __device__ __forceinline__ double plain_interior(const DevSim &sim, const double
   return fma(cbd, hh[c] - hh[c - 1], fma(ca, e_in[c], -(cbg * pp[c])));
 }
 
-template <int N>
+template <int N, bool BK>
 __global__ void __launch_bounds__(kPlainBlock) k_plain_e(const DevSim *__restrict__ sims,
                                                          const DevTile *__restrict__ tiles, int64_t n0,
                                                          int parity) {
   using R = double;
-  constexpr int S = mat_stride(N);
+  constexpr int S = stride_of(N, BK);
   const DevTile tile = tiles[blockIdx.x];
   const DevSim &sim = sims[tile.sim];
   const int64_t n64 = n0 - sim.start;
@@ -1107,15 +1178,15 @@ __global__ void __launch_bounds__(kPlainBlock) k_plain_e(const DevSim *__restric
 // tile resident at once for the neighbour flags to make progress: the caller
 // checks the tile count against the occupancy (and a tile that waits too long
 // gives up, so a launch that does not fit ends with an error, not a hang).
-template <int N, typename R, int B, int L, bool VC, bool ST, bool P, bool CY>
+template <int N, typename R, int B, int L, bool VC, bool ST, bool P, bool CY, bool BK>
 hipError_t launch_shape(const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo,
                         int k, const ChunkSync &cs, int *per_cu, hipStream_t st) {
   if constexpr (VC && !regs_fit<N, R, B, L>()) {
     // register coefficients are not built for this shape: the same arithmetic
     // with scalar coefficient loads
-    return launch_shape<N, R, B, L, false, ST, P, CY>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+    return launch_shape<N, R, B, L, false, ST, P, CY, BK>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
   } else if constexpr (shape_fits<N, R, B, L>() && (!ST || (L == 1 && !VC && N >= 2)) && (!CY || N >= 2)) {
-    auto kern = k_blocked<N, R, B, L, VC, ST, P, CY>;
+    auto kern = k_blocked<N, R, B, L, VC, ST, P, CY, BK>;
     if (per_cu) return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kern, B * L, 0);
     kern<<<n_tiles, B * L, 0, st>>>(sims, tiles, n0, parity, halo, k, cs);
     return hipGetLastError();
@@ -1124,22 +1195,22 @@ hipError_t launch_shape(const DevSim *sims, const DevTile *tiles, int n_tiles, i
   }
 }
 
-template <int N, typename R, int L, bool VC, bool ST, bool P, bool CY>
+template <int N, typename R, int L, bool VC, bool ST, bool P, bool CY, bool BK>
 hipError_t launch_blocked_b(int block, const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0,
                             int parity, int halo, int k, const ChunkSync &cs, int *per_cu, hipStream_t st) {
   switch (block) {
-    case 64: return launch_shape<N, R, 64, L, VC, ST, P, CY>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
-    case 128: return launch_shape<N, R, 128, L, VC, ST, P, CY>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
-    case 192: return launch_shape<N, R, 192, L, VC, ST, P, CY>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
-    case 256: return launch_shape<N, R, 256, L, VC, ST, P, CY>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
-    case 512: return launch_shape<N, R, 512, L, VC, ST, P, CY>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+    case 64: return launch_shape<N, R, 64, L, VC, ST, P, CY, BK>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+    case 128: return launch_shape<N, R, 128, L, VC, ST, P, CY, BK>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+    case 192: return launch_shape<N, R, 192, L, VC, ST, P, CY, BK>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+    case 256: return launch_shape<N, R, 256, L, VC, ST, P, CY, BK>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+    case 512: return launch_shape<N, R, 512, L, VC, ST, P, CY, BK>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
   }
   return hipErrorInvalidValue;
 }
 
 // register-resident coefficients are instantiated for the small level counts
 // only, split waves for the quantum level counts
-template <int N, typename R, bool P, bool CY>
+template <int N, typename R, bool P, bool CY, bool BK>
 hipError_t launch_blocked_nr(int block, int lanes, bool vc, bool strong, const DevSim *sims, const DevTile *tiles,
                              int n_tiles, int64_t n0, int parity, int halo, int k, const ChunkSync &cs, int *per_cu,
                              hipStream_t st) {
@@ -1150,46 +1221,50 @@ hipError_t launch_blocked_nr(int block, int lanes, bool vc, bool strong, const D
     if (lanes != 1 && !strong) return hipErrorInvalidValue;
   if (strong) {
     if constexpr (N >= 2)
-      return launch_blocked_b<N, R, 1, false, true, P, CY>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+      return launch_blocked_b<N, R, 1, false, true, P, CY, BK>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
     return hipErrorInvalidValue;
   }
   switch (lanes) {
     case 1:
       if constexpr (kVC)
-        if (vc) return launch_blocked_b<N, R, 1, kVC, false, P, CY>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
-      return launch_blocked_b<N, R, 1, false, false, P, CY>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+        if (vc) return launch_blocked_b<N, R, 1, kVC, false, P, CY, BK>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+      return launch_blocked_b<N, R, 1, false, false, P, CY, BK>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
     case 2:
     case 4:
       if constexpr (N >= 2) {
         if (lanes == 2) {
           if constexpr (kVC)
             if (vc)
-              return launch_blocked_b<N, R, 2, kVC, false, P, CY>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
-          return launch_blocked_b<N, R, 2, false, false, P, CY>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+              return launch_blocked_b<N, R, 2, kVC, false, P, CY, BK>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+          return launch_blocked_b<N, R, 2, false, false, P, CY, BK>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
         }
         if constexpr (kVC)
-          if (vc) return launch_blocked_b<N, R, 4, kVC, false, P, CY>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
-        return launch_blocked_b<N, R, 4, false, false, P, CY>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+          if (vc) return launch_blocked_b<N, R, 4, kVC, false, P, CY, BK>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+        return launch_blocked_b<N, R, 4, false, false, P, CY, BK>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
       }
       break;
     case 8:  // 64-cell tiles of the large density updates only
       if constexpr (N >= 4)
-        return launch_blocked_b<N, R, 8, false, false, P, CY>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+        return launch_blocked_b<N, R, 8, false, false, P, CY, BK>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
       break;
   }
   return hipErrorInvalidValue;
 }
 
-template <typename R, bool P, bool CY>
+template <typename R, bool P, bool CY, bool BK>
 hipError_t launch_blocked_r(int levels, int block, int lanes, bool vc, bool strong, const DevSim *sims,
                             const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo, int k,
                             const ChunkSync &cs, int *per_cu, hipStream_t st) {
   switch (levels) {
 #define MB_LEVELS_CASE(n)                                                                                       \
   case n:                                                                                                         \
-    return launch_blocked_nr<n, R, P, CY>(block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, \
+    return launch_blocked_nr<n, R, P, CY, BK>(block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, \
                                    st);
-    MB_LEVELS_CASE(0)
+    case 0:
+      if constexpr (!BK)
+        return launch_blocked_nr<0, R, P, CY, false>(block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k,
+                                                     cs, per_cu, st);
+      break;
     MB_LEVELS_CASE(2)
     MB_LEVELS_CASE(3)
     MB_LEVELS_CASE(4)
@@ -1247,23 +1322,22 @@ bool fits_r(int levels, int block, int lanes) {
   return false;
 }
 
-template <int N>
+template <int N, bool BK>
 hipError_t launch_plain_n(const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity,
                           hipStream_t st) {
-  k_plain_hd<N><<<n_tiles, kPlainBlock, 0, st>>>(sims, tiles, n0, parity);
+  k_plain_hd<N, BK><<<n_tiles, kPlainBlock, 0, st>>>(sims, tiles, n0, parity);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  k_plain_e<N><<<n_tiles, kPlainBlock, 0, st>>>(sims, tiles, n0, parity);
+  k_plain_e<N, BK><<<n_tiles, kPlainBlock, 0, st>>>(sims, tiles, n0, parity);
   return hipGetLastError();
 }
 
 }  // namespace
 
-// The kernels are built in eight parts so that the library compiles them in
-// parallel: MB_PART 1 holds the FP32 one-chunk tiles, 3 the FP32 persistent
-// tiles, 4 the FP64 persistent tiles, 5 and 6 the FP32 and FP64 one-chunk
-// Cayley tiles, 7 and 8 the persistent ones, 2 the FP64 one-chunk tiles, the
-// two-launch kernels and the dispatch; without MB_PART all are built here.
+// The kernels are built in sixteen parts so that the library compiles them in
+// parallel: MB_PART - 1 = id with bit 0 FP64, bit 1 persistent tiles, bit 2 the
+// Cayley field step, bit 3 the block form; part 2 also holds the two-launch
+// kernels and the dispatch; without MB_PART all are built here.
 #ifndef MB_PART
 #define MB_PART 0
 #endif
@@ -1273,45 +1347,74 @@ hipError_t launch_plain_n(const DevSim *sims, const DevTile *tiles, int n_tiles,
       int64_t n0, int parity, int halo, int k, const ChunkSync &cs, int *per_cu, hipStream_t st
 #define MB_LAUNCH_PASS levels, block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st
 
-hipError_t launch_blocked_f32(MB_LAUNCH_ARGS);
-hipError_t launch_blocked_f32p(MB_LAUNCH_ARGS);
-hipError_t launch_blocked_f64p(MB_LAUNCH_ARGS);
-hipError_t launch_blocked_f32c(MB_LAUNCH_ARGS);
-hipError_t launch_blocked_f64c(MB_LAUNCH_ARGS);
-hipError_t launch_blocked_f32pc(MB_LAUNCH_ARGS);
-hipError_t launch_blocked_f64pc(MB_LAUNCH_ARGS);
-bool fits_f32(int levels, int block, int lanes);
+#define MB_PART_DECLARE(ID) hipError_t launch_part_##ID(MB_LAUNCH_ARGS);
+MB_PART_DECLARE(0) MB_PART_DECLARE(1) MB_PART_DECLARE(2) MB_PART_DECLARE(3)
+MB_PART_DECLARE(4) MB_PART_DECLARE(5) MB_PART_DECLARE(6) MB_PART_DECLARE(7)
+MB_PART_DECLARE(8) MB_PART_DECLARE(9) MB_PART_DECLARE(10) MB_PART_DECLARE(11)
+MB_PART_DECLARE(12) MB_PART_DECLARE(13) MB_PART_DECLARE(14) MB_PART_DECLARE(15)
+#undef MB_PART_DECLARE
 
+#define MB_PART_DEFINE(ID)                                                                                  \
+  hipError_t launch_part_##ID(MB_LAUNCH_ARGS) {                                                             \
+    return launch_blocked_r<std::conditional_t<(ID & 1) != 0, double, float>, (ID & 2) != 0, (ID & 4) != 0, \
+                            (ID & 8) != 0>(MB_LAUNCH_PASS);                                                 \
+  }
 #if MB_PART == 0 || MB_PART == 1
-hipError_t launch_blocked_f32(MB_LAUNCH_ARGS) { return launch_blocked_r<float, false, false>(MB_LAUNCH_PASS); }
-bool fits_f32(int levels, int block, int lanes) { return fits_r<float>(levels, block, lanes); }
+MB_PART_DEFINE(0)
+#endif
+#if MB_PART == 0 || MB_PART == 2
+MB_PART_DEFINE(1)
 #endif
 #if MB_PART == 0 || MB_PART == 3
-hipError_t launch_blocked_f32p(MB_LAUNCH_ARGS) { return launch_blocked_r<float, true, false>(MB_LAUNCH_PASS); }
+MB_PART_DEFINE(2)
 #endif
 #if MB_PART == 0 || MB_PART == 4
-hipError_t launch_blocked_f64p(MB_LAUNCH_ARGS) { return launch_blocked_r<double, true, false>(MB_LAUNCH_PASS); }
+MB_PART_DEFINE(3)
 #endif
-// Cayley field step: one-chunk and persistent tiles
 #if MB_PART == 0 || MB_PART == 5
-hipError_t launch_blocked_f32c(MB_LAUNCH_ARGS) { return launch_blocked_r<float, false, true>(MB_LAUNCH_PASS); }
+MB_PART_DEFINE(4)
 #endif
 #if MB_PART == 0 || MB_PART == 6
-hipError_t launch_blocked_f64c(MB_LAUNCH_ARGS) { return launch_blocked_r<double, false, true>(MB_LAUNCH_PASS); }
+MB_PART_DEFINE(5)
 #endif
 #if MB_PART == 0 || MB_PART == 7
-hipError_t launch_blocked_f32pc(MB_LAUNCH_ARGS) { return launch_blocked_r<float, true, true>(MB_LAUNCH_PASS); }
+MB_PART_DEFINE(6)
 #endif
 #if MB_PART == 0 || MB_PART == 8
-hipError_t launch_blocked_f64pc(MB_LAUNCH_ARGS) { return launch_blocked_r<double, true, true>(MB_LAUNCH_PASS); }
+MB_PART_DEFINE(7)
 #endif
+#if MB_PART == 0 || MB_PART == 9
+MB_PART_DEFINE(8)
+#endif
+#if MB_PART == 0 || MB_PART == 10
+MB_PART_DEFINE(9)
+#endif
+#if MB_PART == 0 || MB_PART == 11
+MB_PART_DEFINE(10)
+#endif
+#if MB_PART == 0 || MB_PART == 12
+MB_PART_DEFINE(11)
+#endif
+#if MB_PART == 0 || MB_PART == 13
+MB_PART_DEFINE(12)
+#endif
+#if MB_PART == 0 || MB_PART == 14
+MB_PART_DEFINE(13)
+#endif
+#if MB_PART == 0 || MB_PART == 15
+MB_PART_DEFINE(14)
+#endif
+#if MB_PART == 0 || MB_PART == 16
+MB_PART_DEFINE(15)
+#endif
+#undef MB_PART_DEFINE
 
 #if MB_PART == 0 || MB_PART == 2
 bool block_supported(int block) { return block == 64 || block == 128 || block == 192 || block == 256 || block == 512; }
 
 bool shape_supported(int levels, int precision, int block, int lanes) {
   if (!block_supported(block)) return false;
-  return precision == 64 ? fits_r<double>(levels, block, lanes) : fits_f32(levels, block, lanes);
+  return precision == 64 ? fits_r<double>(levels, block, lanes) : fits_r<float>(levels, block, lanes);
 }
 
 int plain_block() { return kPlainBlock; }
@@ -1325,25 +1428,44 @@ bool regs_supported(int levels, int precision, int block, int lanes) {
   return false;
 }
 
-hipError_t launch_blocked(int levels, int precision, int block, int lanes, bool vc, bool strong, bool cayley,
+hipError_t launch_by_id(int id, MB_LAUNCH_ARGS) {
+  switch (id) {
+    case 0: return launch_part_0(MB_LAUNCH_PASS);
+    case 1: return launch_part_1(MB_LAUNCH_PASS);
+    case 2: return launch_part_2(MB_LAUNCH_PASS);
+    case 3: return launch_part_3(MB_LAUNCH_PASS);
+    case 4: return launch_part_4(MB_LAUNCH_PASS);
+    case 5: return launch_part_5(MB_LAUNCH_PASS);
+    case 6: return launch_part_6(MB_LAUNCH_PASS);
+    case 7: return launch_part_7(MB_LAUNCH_PASS);
+    case 8: return launch_part_8(MB_LAUNCH_PASS);
+    case 9: return launch_part_9(MB_LAUNCH_PASS);
+    case 10: return launch_part_10(MB_LAUNCH_PASS);
+    case 11: return launch_part_11(MB_LAUNCH_PASS);
+    case 12: return launch_part_12(MB_LAUNCH_PASS);
+    case 13: return launch_part_13(MB_LAUNCH_PASS);
+    case 14: return launch_part_14(MB_LAUNCH_PASS);
+    case 15: return launch_part_15(MB_LAUNCH_PASS);
+  }
+  return hipErrorInvalidValue;
+}
+
+int part_id(int precision, bool persistent, bool cayley, bool bk) {
+  return (precision == 64 ? 1 : 0) | (persistent ? 2 : 0) | (cayley ? 4 : 0) | (bk ? 8 : 0);
+}
+
+hipError_t launch_blocked(int levels, int precision, int block, int lanes, bool vc, bool strong, bool cayley, bool bk,
                           const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo,
                           int k, const ChunkSync &cs, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
   if (k < 1 || k > halo || k > kMaxChunk || 2 * halo >= block || cs.n_chunks < 1) return hipErrorInvalidValue;
   if (cs.n_chunks > 1 && (!cs.flags || k != halo || 3 * halo > block)) return hipErrorInvalidValue;
   int *per_cu = nullptr;
-  if (cayley) {
-    if (cs.n_chunks > 1)
-      return precision == 64 ? launch_blocked_f64pc(MB_LAUNCH_PASS) : launch_blocked_f32pc(MB_LAUNCH_PASS);
-    return precision == 64 ? launch_blocked_f64c(MB_LAUNCH_PASS) : launch_blocked_f32c(MB_LAUNCH_PASS);
-  }
-  if (cs.n_chunks > 1)
-    return precision == 64 ? launch_blocked_f64p(MB_LAUNCH_PASS) : launch_blocked_f32p(MB_LAUNCH_PASS);
-  return precision == 64 ? launch_blocked_r<double, false, false>(MB_LAUNCH_PASS) : launch_blocked_f32(MB_LAUNCH_PASS);
+  return launch_by_id(part_id(precision, cs.n_chunks > 1, cayley, bk && levels > 0), MB_LAUNCH_PASS);
 }
 
 // occupancy of the persistent form (the only one that needs every tile resident)
-int blocked_tiles_per_cu(int levels, int precision, int block, int lanes, bool vc, bool strong, bool cayley) {
+int blocked_tiles_per_cu(int levels, int precision, int block, int lanes, bool vc, bool strong, bool cayley, bool bk) {
   int per_cu_v = 0;
   int *per_cu = &per_cu_v;
   const ChunkSync cs{nullptr, 0u, 2, 0};
@@ -1352,22 +1474,30 @@ int blocked_tiles_per_cu(int levels, int precision, int block, int lanes, bool v
   const int n_tiles = 0, parity = 0, halo = 1, k = 1;
   const int64_t n0 = 0;
   hipStream_t st = nullptr;
-  const hipError_t e =
-      cayley ? (precision == 64 ? launch_blocked_f64pc(MB_LAUNCH_PASS) : launch_blocked_f32pc(MB_LAUNCH_PASS))
-             : (precision == 64 ? launch_blocked_f64p(MB_LAUNCH_PASS) : launch_blocked_f32p(MB_LAUNCH_PASS));
+  const hipError_t e = launch_by_id(part_id(precision, true, cayley, bk && levels > 0), MB_LAUNCH_PASS);
   return e == hipSuccess ? per_cu_v : 0;
 }
 
-hipError_t launch_plain(int levels, const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity,
-                        hipStream_t st) {
+hipError_t launch_plain(int levels, bool bk, const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0,
+                        int parity, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
+  if (bk) {
+    switch (levels) {
+      case 2: return launch_plain_n<2, true>(sims, tiles, n_tiles, n0, parity, st);
+      case 3: return launch_plain_n<3, true>(sims, tiles, n_tiles, n0, parity, st);
+      case 4: return launch_plain_n<4, true>(sims, tiles, n_tiles, n0, parity, st);
+      case 5: return launch_plain_n<5, true>(sims, tiles, n_tiles, n0, parity, st);
+      case 6: return launch_plain_n<6, true>(sims, tiles, n_tiles, n0, parity, st);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (levels) {
-    case 0: return launch_plain_n<0>(sims, tiles, n_tiles, n0, parity, st);
-    case 2: return launch_plain_n<2>(sims, tiles, n_tiles, n0, parity, st);
-    case 3: return launch_plain_n<3>(sims, tiles, n_tiles, n0, parity, st);
-    case 4: return launch_plain_n<4>(sims, tiles, n_tiles, n0, parity, st);
-    case 5: return launch_plain_n<5>(sims, tiles, n_tiles, n0, parity, st);
-    case 6: return launch_plain_n<6>(sims, tiles, n_tiles, n0, parity, st);
+    case 0: return launch_plain_n<0, false>(sims, tiles, n_tiles, n0, parity, st);
+    case 2: return launch_plain_n<2, false>(sims, tiles, n_tiles, n0, parity, st);
+    case 3: return launch_plain_n<3, false>(sims, tiles, n_tiles, n0, parity, st);
+    case 4: return launch_plain_n<4, false>(sims, tiles, n_tiles, n0, parity, st);
+    case 5: return launch_plain_n<5, false>(sims, tiles, n_tiles, n0, parity, st);
+    case 6: return launch_plain_n<6, false>(sims, tiles, n_tiles, n0, parity, st);
   }
   return hipErrorInvalidValue;
 }

@@ -24,16 +24,17 @@ int plain_block();
 // strong: strong-coupling simulations (one wave per 64 cells, no register coefficients)
 // cayley: simulations with the Cayley field step (persistent launches with
 // one wave per 64 cells only)
+// bk: simulations whose density tables are in the block form (engine.hpp)
 // cs.n_chunks > 1: a persistent launch of that many chunks of k = halo steps
 // (3*halo <= block, cs.flags per tile); all n_tiles tiles must fit on the
 // device at once (blocked_tiles_per_cu); cs.n_chunks == 1: one chunk, no flags.
-hipError_t launch_blocked(int levels, int precision, int block, int lanes, bool vc, bool strong, bool cayley,
+hipError_t launch_blocked(int levels, int precision, int block, int lanes, bool vc, bool strong, bool cayley, bool bk,
                           const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity,
                           int halo, int k, const ChunkSync &cs, hipStream_t st);
 // tiles of this shape one compute unit holds at once (0: no such kernel)
-int blocked_tiles_per_cu(int levels, int precision, int block, int lanes, bool vc, bool strong, bool cayley);
+int blocked_tiles_per_cu(int levels, int precision, int block, int lanes, bool vc, bool strong, bool cayley, bool bk);
 // One time step as two launches (FP64); tiles of plain_block() cells.
-hipError_t launch_plain(int levels, const DevSim *sims, const DevTile *tiles, int n_tiles,
+hipError_t launch_plain(int levels, bool bk, const DevSim *sims, const DevTile *tiles, int n_tiles,
                         int64_t n0, int parity, hipStream_t st);
 
 }  // namespace mb

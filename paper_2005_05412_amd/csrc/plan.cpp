@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <sstream>
 
@@ -416,6 +417,63 @@ std::vector<double> eig_coherences(int n, const std::vector<cd> &vec, const std:
   return z;
 }
 
+// The block layout of a material's tables when every entry outside the blocks
+// is an exact zero (engine.hpp); otherwise mp.block_form stays false.
+void build_block_form(MaterialPlan &mp) {
+  const int n = mp.n, m = state_dim(n), kd = coh_dim(n), np = n - 1, pc = pair_count(n);
+  auto re = [&](int r) { return np + 2 * r; };  // state row of Re/Im of pair r
+  auto im = [&](int r) { return np + 2 * r + 1; };
+  auto T = [&](int row, int col) { return mp.tm[size_t(row) * m + col]; };
+  auto S = [&](int row, int col) { return mp.sm[size_t(row) * kd + col]; };
+  auto A = [&](int row, int col) { return mp.am[size_t(row) * m + col]; };
+  bool ok = true;
+  for (int q = 0; q < pc && ok; ++q) {
+    ok = mp.t0[2 * q + 1] == 0.0;
+    for (int a = 0; a < np; ++a) ok = ok && T(2 * q + 1, a) == 0.0 && S(a, 2 * q + 1) == 0.0;
+    for (int r = 0; r < pc; ++r)
+      ok = ok && T(2 * q, im(r)) == 0.0 && T(2 * q + 1, re(r)) == 0.0 && S(re(r), 2 * q + 1) == 0.0 &&
+           S(im(r), 2 * q) == 0.0;
+  }
+  for (int a = 0; a < m && ok; ++a)
+    for (int b = 0; b < m && ok; ++b) {
+      const bool pa = a < np, pb = b < np;
+      const bool same_pair = !pa && !pb && (a - np) / 2 == (b - np) / 2;
+      if (!(pa && pb) && !same_pair) ok = A(a, b) == 0.0;
+    }
+  for (int a = np; a < m && ok; ++a) ok = mp.bf[a] == 0.0;
+  mp.block_form = ok;
+  if (!ok) return;
+  mp.bfp.assign(mp.bf.begin(), mp.bf.begin() + np);
+  mp.ap.assign(size_t(np) * np, 0.0);
+  for (int a = 0; a < np; ++a)
+    for (int b = 0; b < np; ++b) mp.ap[size_t(a) * np + b] = A(a, b);
+  mp.blk.assign(size_t(pc) * 4, 0.0);
+  mp.t0r.assign(pc, 0.0);
+  mp.tp.assign(size_t(pc) * np, 0.0);
+  mp.tr.assign(size_t(pc) * pc, 0.0);
+  mp.ti.assign(size_t(pc) * pc, 0.0);
+  mp.sp.assign(size_t(np) * pc, 0.0);
+  mp.sr.assign(size_t(pc) * pc, 0.0);
+  mp.si.assign(size_t(pc) * pc, 0.0);
+  for (int r = 0; r < pc; ++r) {
+    mp.blk[4 * r + 0] = A(re(r), re(r));
+    mp.blk[4 * r + 1] = A(re(r), im(r));
+    mp.blk[4 * r + 2] = A(im(r), re(r));
+    mp.blk[4 * r + 3] = A(im(r), im(r));
+  }
+  for (int q = 0; q < pc; ++q) {
+    mp.t0r[q] = mp.t0[2 * q];
+    for (int a = 0; a < np; ++a) mp.tp[size_t(q) * np + a] = T(2 * q, a);
+    for (int r = 0; r < pc; ++r) {
+      mp.tr[size_t(q) * pc + r] = T(2 * q, re(r));
+      mp.ti[size_t(q) * pc + r] = T(2 * q + 1, im(r));
+      mp.sr[size_t(r) * pc + q] = S(re(r), 2 * q);
+      mp.si[size_t(r) * pc + q] = S(im(r), 2 * q + 1);
+    }
+    for (int a = 0; a < np; ++a) mp.sp[size_t(a) * pc + q] = S(a, 2 * q);
+  }
+}
+
 void build_quantum(MaterialPlan &mp, const QmFull &q, double dt, const mb_consts &k) {
   int n = q.n, m = state_dim(n), nn = n * n, kd = coh_dim(n);
   mp.qm = true;
@@ -547,6 +605,7 @@ void build_quantum(MaterialPlan &mp, const QmFull &q, double dt, const mb_consts
   };
   mp.as = fold(mp.at);
   mp.aqs = fold(mp.aq);
+  build_block_form(mp);
   // complete positivity of the pure dephasing: Gram matrix -1/2 J D J, D_ij = 2 gamma_ij,p
   Mat d(size_t(n) * n, 0.0), jm(size_t(n) * n, 0.0);
   double dmax = 0.0;
@@ -836,11 +895,15 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
       if (scen->rho_diag[i] >= scen->rho_diag[top]) top = i;
     for (int i = 0, at = 0; i < levels; ++i) lvl.push_back(i == top ? levels - 1 : at++);
   }
+  // the block form wherever the tables allow it (MB_BLOCK_FORM=0: never)
+  const char *bf_env = std::getenv("MB_BLOCK_FORM");
+  plan.block_form = levels > 0 && !(bf_env && bf_env[0] == '0');
   for (int i = 0; i < dev->n_materials; ++i)
     if (dev->materials[i].qm) {
       permute_levels(qms[i], lvl);
       plan.mats[i].lvl = lvl;
       build_quantum(plan.mats[i], qms[i], plan.dt, k);
+      plan.block_form = plan.block_form && plan.mats[i].block_form;
       if (plan.mats[i].min_gram_eig < -1e-9) plan.warn = MB_WARN_NOT_CP;
     }
   // edges (Sec. 2.1): R = 1 perfect conductor, R = 0 first-order Mur, 0 < R < 1 a

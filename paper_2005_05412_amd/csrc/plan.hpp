@@ -56,6 +56,12 @@ struct MaterialPlan {
   std::vector<double> aq;         // M: strong coupling, (n3D/dt) tr{mu rho} = aq . y + qc
   std::vector<double> aqs;        // K: aq sm
   double qc = 0;
+  // block form (engine.hpp): the tables above have exact zeros outside the
+  // population block, the 2 x 2 pair blocks and the real/imaginary split of
+  // z and of the increment map (a real dipole operator, H0 diagonal,
+  // relaxation in rate form); then the same step in the block layout
+  bool block_form = false;
+  std::vector<double> bfp, ap, blk, t0r, tp, tr, ti, sp, sr, si;
   double min_gram_eig = 0;        // complete-positivity check of the dephasing rates
 };
 
@@ -81,6 +87,7 @@ struct SimPlan {
   int block = 0, depth = 0, lanes = 0;
   int coupling = MB_COUPLING_WEAK;
   int field_step = MB_FIELD_EXACT;
+  bool block_form = false;        // every quantum material in block form
   std::vector<uint8_t> mat_e, mat_h;
   std::vector<MaterialPlan> mats;
   int edge_l = 0, edge_r = 0;     // 0: PEC, 1: Mur, 2: impedance load (0 < R < 1)

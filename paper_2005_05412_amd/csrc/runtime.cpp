@@ -42,7 +42,7 @@ Layout layout_of(const SimPlan &p, int precision, bool plain) {
   L.p = take(plain ? nx * rs : rs);
   L.mat_e = take(nx);
   L.mat_h = take(nx);
-  L.mtab = take(p.mats.size() * size_t(mat_stride(p.n)) * rs);
+  L.mtab = take(p.mats.size() * size_t(stride_of(p.n, p.block_form)) * rs);
   const bool strong = p.coupling == MB_COUPLING_STRONG && p.n > 0;
   L.qs = take(strong ? 2 * nx * sizeof(double) : sizeof(double));
   L.init_q = take(strong ? nx * sizeof(double) : sizeof(double));
@@ -68,7 +68,7 @@ Layout layout_of(const SimPlan &p, int precision, bool plain) {
 
 template <typename R>
 void fill_mtab(const SimPlan &p, R *out) {
-  const int n = p.n, s = mat_stride(n), m = mat_m(n);
+  const int n = p.n, s = stride_of(n, p.block_form), m = mat_m(n);
   for (size_t i = 0; i < p.mats.size(); ++i) {
     const MaterialPlan &mp = p.mats[i];
     R *t = out + i * s;
@@ -82,14 +82,31 @@ void fill_mtab(const SimPlan &p, R *out) {
     const int k = mat_k(n), w = prop_w(n);
     for (int q = 0; q < n - 1; ++q) t[kCoefKap + q] = R(mp.kappa[q]);
     t[coef_p0(n)] = R(mp.p0);
+    for (int a = 0; a < m; ++a) t[coef_at(n) + a] = R(mp.at[a]);
+    for (int r = 0; r < k; ++r) t[coef_as(n) + r] = R(mp.as[r]);
+    if (p.block_form) {
+      auto put = [&](int off, const std::vector<double> &v) {
+        for (size_t j = 0; j < v.size(); ++j) t[off + int(j)] = R(v[j]);
+      };
+      put(bk_bf(n), mp.bfp);
+      put(bk_ap(n), mp.ap);
+      put(bk_blk(n), mp.blk);
+      put(bk_t0(n), mp.t0r);
+      put(bk_tp(n), mp.tp);
+      put(bk_tr(n), mp.tr);
+      put(bk_ti(n), mp.ti);
+      put(bk_sp(n), mp.sp);
+      put(bk_sr(n), mp.sr);
+      put(bk_si(n), mp.si);
+      put(bk_sg(n), mp.sigma);
+      continue;
+    }
     for (int a = 0; a < m; ++a) {
-      t[coef_at(n) + a] = R(mp.at[a]);
       t[coef_bf(n) + a] = R(mp.bf[a]);
       for (int b = 0; b < m; ++b) t[coef_am(n) + a * w + b] = R(mp.am[size_t(a) * m + b]);
       for (int r = 0; r < k; ++r) t[coef_am(n) + a * w + m + r] = R(mp.bm[size_t(a) * k + r]);
     }
     for (int r = 0; r < k; ++r) {
-      t[coef_as(n) + r] = R(mp.as[r]);
       t[coef_t0(n) + r] = R(mp.t0[r]);
       for (int b = 0; b < m; ++b) t[coef_tm(n) + r * m + b] = R(mp.tm[size_t(r) * m + b]);
     }
@@ -271,13 +288,14 @@ int Engine::init(std::string &err) {
   return MB_OK;
 }
 
-Engine::Group &Engine::group_for(int levels, bool strong, bool cayley) {
+Engine::Group &Engine::group_for(int levels, bool strong, bool cayley, bool bk) {
   for (auto &g : groups_)
-    if (g.levels == levels && g.strong == strong && g.cayley == cayley) return g;
+    if (g.levels == levels && g.strong == strong && g.cayley == cayley && g.bk == bk) return g;
   groups_.push_back(Group());
   groups_.back().levels = levels;
   groups_.back().strong = strong;
   groups_.back().cayley = cayley;
+  groups_.back().bk = bk;
   return groups_.back();
 }
 
@@ -427,7 +445,8 @@ int Engine::add(SimPlan &&plan, Arena *arena, hipStream_t st, std::string &err) 
   d.parity_off = s->parity_off;
   s->active = true;
   int id = int(sims_.size());
-  group_for(p.n, p.coupling == MB_COUPLING_STRONG && p.n > 0, p.field_step == MB_FIELD_CAYLEY && p.n > 0)
+  group_for(p.n, p.coupling == MB_COUPLING_STRONG && p.n > 0, p.field_step == MB_FIELD_CAYLEY && p.n > 0,
+            p.block_form && p.n > 0)
       .members.push_back(id);
   sims_.push_back(std::move(s));
   dirty_ = true;
@@ -540,19 +559,21 @@ int Engine::group_lanes(const Group &g) const {
   return 1;
 }
 
-hipError_t Engine::launch_group(Group &g, hipStream_t st, int k, int reps) {
+hipError_t Engine::launch_group(Group &g, hipStream_t st, int k, int reps, int64_t step_off, int par_off) {
   const int lanes = variant_ == MB_VARIANT_PLAIN ? 1 : group_lanes(g);
+  const int64_t n0 = n0_ + step_off;
+  const int par0 = parity_ ^ (par_off & 1);
   for (int r = 0; r < reps; ++r) {
     hipError_t e;
     if (variant_ == MB_VARIANT_PLAIN) {
       for (int s = 0; s < k; ++s) {
-        const int64_t step = n0_ + int64_t(r) * k + s;
-        if ((e = launch_plain(g.levels, g.d_sims, g.d_tiles, g.n_tiles, step, int((parity_ + r * k + s) & 1), st)) !=
+        const int64_t step = n0 + int64_t(r) * k + s;
+        if ((e = launch_plain(g.levels, g.bk, g.d_sims, g.d_tiles, g.n_tiles, step, int((par0 + r * k + s) & 1), st)) !=
             hipSuccess)
           return e;
       }
-    } else if ((e = launch_blocked(g.levels, precision_, block_, lanes, vc_, g.strong, g.cayley, g.d_sims, g.d_tiles, g.n_tiles,
-                                   n0_ + int64_t(r) * k, parity_ ^ (r & 1), halo_, k, ChunkSync{nullptr, 0u, 1, 0},
+    } else if ((e = launch_blocked(g.levels, precision_, block_, lanes, vc_, g.strong, g.cayley, g.bk, g.d_sims, g.d_tiles, g.n_tiles,
+                                   n0 + int64_t(r) * k, par0 ^ (r & 1), halo_, k, ChunkSync{nullptr, 0u, 1, 0},
                                    st)) != hipSuccess) {
       return e;
     }
@@ -574,7 +595,8 @@ bool Engine::persist_ok(int k, int64_t reps) {
   if (live->occ_block != block_ || live->occ_lanes != lanes) {
     live->occ_block = block_;
     live->occ_lanes = lanes;
-    live->occ_per_cu = blocked_tiles_per_cu(live->levels, precision_, block_, lanes, vc_, live->strong, live->cayley);
+    live->occ_per_cu = blocked_tiles_per_cu(live->levels, precision_, block_, lanes, vc_, live->strong, live->cayley,
+                                            live->bk);
   }
   return int64_t(live->n_tiles) <= int64_t(live->occ_per_cu) * n_cu_;
 }
@@ -590,7 +612,7 @@ hipError_t Engine::run_persistent(hipStream_t st, int k, int64_t reps) {
   while (reps > 0) {
     const int n = int(std::min<int64_t>(reps, kMaxPersistChunks));
     const ChunkSync cs{g->d_flags, epoch_, n, spin_ticks_};
-    e = launch_blocked(g->levels, precision_, block_, lanes, vc_, g->strong, g->cayley, g->d_sims, g->d_tiles, g->n_tiles, n0_,
+    e = launch_blocked(g->levels, precision_, block_, lanes, vc_, g->strong, g->cayley, g->bk, g->d_sims, g->d_tiles, g->n_tiles, n0_,
                        parity_, halo_, k, cs, st);
     if (e != hipSuccess) return e;
     epoch_ += uint32_t(n);
@@ -698,12 +720,12 @@ hipError_t Engine::run_in_tables(hipStream_t st, int64_t steps, char *base, size
   return e;
 }
 
-hipError_t Engine::launch_only(hipStream_t st, int k, int reps) {
+hipError_t Engine::launch_only(hipStream_t st, int k, int reps, int64_t step_off, int par_off) {
   std::vector<Group *> live;
   for (auto &g : groups_)
     if (!g.members.empty()) live.push_back(&g);
   if (live.empty()) return hipSuccess;
-  if (live.size() == 1) return launch_group(*live[0], st, k, reps);
+  if (live.size() == 1) return launch_group(*live[0], st, k, reps, step_off, par_off);
   hipError_t e = hipSuccess;
   if (!fork_) e = hipEventCreateWithFlags(&fork_, hipEventDisableTiming);
   while (e == hipSuccess && side_.size() + 1 < live.size()) {
@@ -718,10 +740,10 @@ hipError_t Engine::launch_only(hipStream_t st, int k, int reps) {
   if ((e = hipEventRecord(fork_, st)) != hipSuccess) return e;
   for (size_t i = 1; i < live.size() && e == hipSuccess; ++i) {
     e = hipStreamWaitEvent(side_[i - 1], fork_, 0);
-    if (e == hipSuccess) e = launch_group(*live[i], side_[i - 1], k, reps);
+    if (e == hipSuccess) e = launch_group(*live[i], side_[i - 1], k, reps, step_off, par_off);
     if (e == hipSuccess) e = hipEventRecord(side_done_[i - 1], side_[i - 1]);
   }
-  if (e == hipSuccess) e = launch_group(*live[0], st, k, reps);
+  if (e == hipSuccess) e = launch_group(*live[0], st, k, reps, step_off, par_off);
   // join every side stream that was forked, also after a failed launch
   for (size_t i = 1; i < live.size(); ++i) {
     hipError_t e2 = hipStreamWaitEvent(st, side_done_[i - 1], 0);

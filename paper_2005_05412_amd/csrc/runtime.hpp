@@ -94,8 +94,10 @@ class Engine {
 
   // Launches of reps chunks of k steps, for graph capture: tables must be
   // current.  Groups of different level counts run on their own streams,
-  // forked from and joined back into st, so their kernels overlap.
-  hipError_t launch_only(hipStream_t st, int k, int reps = 1);
+  // forked from and joined back into st, so their kernels overlap.  The first
+  // launch starts step_off steps and par_off buffer flips after the engine's
+  // committed step (chunks captured ahead of their commit_chunk calls).
+  hipError_t launch_only(hipStream_t st, int k, int reps = 1, int64_t step_off = 0, int par_off = 0);
   void commit_chunk(int k);  // host bookkeeping of a chunk launched via launch_only
   // Restores every simulation's initial state from its device image and
   // clears records (asynchronous copies on st, then table upload).
@@ -146,6 +148,7 @@ class Engine {
     int levels = 0;
     bool strong = false;  // strong-coupling simulations (their own kernel)
     bool cayley = false;  // Cayley field step (their own kernel)
+    bool bk = false;      // density tables in the block form (their own kernel)
     std::vector<int> members;
     DevSim *d_sims = nullptr;
     DevTile *d_tiles = nullptr;
@@ -153,10 +156,10 @@ class Engine {
     int n_tiles = 0, cap_sims = 0, cap_tiles = 0;
     int occ_block = 0, occ_lanes = 0, occ_per_cu = 0;  // cached occupancy of the group's kernel
   };
-  Group &group_for(int levels, bool strong, bool cayley);
+  Group &group_for(int levels, bool strong, bool cayley, bool bk);
   hipError_t upload_group(Group &g, hipStream_t st);
   void build_tables(const Group &g, std::vector<DevSim> &hs, std::vector<DevTile> &ht) const;
-  hipError_t launch_group(Group &g, hipStream_t st, int k, int reps);
+  hipError_t launch_group(Group &g, hipStream_t st, int k, int reps, int64_t step_off = 0, int par_off = 0);
   int group_lanes(const Group &g) const;
 
   int device_, precision_, variant_, block_, halo_;

@@ -94,18 +94,20 @@ std::string tune_key(int device, const std::vector<const SimPlan *> &plans, int 
     if (ch == ':' || ch == ' ') ch = '_';
   int levels = 0;
   uint64_t cells = 0;
-  bool strong = false, cayley = false;
+  bool strong = false, cayley = false, bk = !plans.empty();
   uint64_t steps = 1;
   for (auto *p : plans) {
     levels = std::max(levels, p->n);
     cells += uint64_t(p->nx);
     strong = strong || p->coupling == MB_COUPLING_STRONG;
     cayley = cayley || p->field_step == MB_FIELD_CAYLEY;  // kernels of their own
+    bk = bk && p->block_form;
     steps = std::max<uint64_t>(steps, uint64_t(p->n_steps));
   }
   // the step count matters: a short run cannot time the persistent form
   std::ostringstream os;
-  os << arch << "/v7/N" << levels << "/p" << precision << (strong ? "/strong" : "") << (cayley ? "/cayley" : "") << "/cells" << pow2_ceil(cells)
+  os << arch << "/v8/N" << levels << "/p" << precision << (strong ? "/strong" : "") << (cayley ? "/cayley" : "")
+     << (bk ? "/block" : "") << "/cells" << pow2_ceil(cells)
      << "/sims" << pow2_ceil(plans.size()) << "/steps" << pow2_ceil(steps);
   return os.str();
 }

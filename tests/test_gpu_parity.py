@@ -624,6 +624,34 @@ def test_field_free_medium_stays_field_free(n):
         assert np.max(np.abs(got["pop0"] - 1.0)) <= (1e-15 if precision == 64 else 1e-7)
 
 
+@pytest.mark.parametrize("n", [3, 6])
+def test_block_and_general_forms_vs_oracle(n):
+    """The ladder's tables are block structured (real dipoles, diagonal H0, rate-form
+    relaxation), so its kernels take the block form; forced into the general form
+    (MB_BLOCK_FORM=0) the same solve also matches the oracle: FP64 within 1e-10 and FP32
+    within 1e-4 per trace in both forms, each form bit for bit the same on every tile
+    shape.  The QCL-like material (tunnelling couplings in H0) takes the general form."""
+    prob = W.ladder(n, nx=300, n_steps=400, rec_interval=4)
+    assert mb.plan_material(prob, 1)["block"]
+    assert not mb.plan_material(W.qcl6(nx=64, n_steps=10), 0)["block"]
+    ref = O.run(prob)
+    for form in ("block", "general"):
+        if form == "general":
+            os.environ["MB_BLOCK_FORM"] = "0"
+        try:
+            assert mb.plan_material(prob, 1)["block"] == (form == "block")
+            for precision in (64, 32):
+                base = gpu_run(prob, precision=precision, variant="blocked", block=128, depth=16, lanes=1)
+                errs = rel_errors(prob, base, ref)
+                _say(f"ladder {n} {form} fp{precision} {worst(errs)}")
+                assert max(errs.values()) <= TOL[precision], (form, precision, worst(errs))
+                for block, depth, lanes in ((64, 8, 2), (64, 8, 4), (192, 32, 1)):
+                    assert_same(gpu_run(prob, precision=precision, variant="blocked", block=block, depth=depth,
+                                        lanes=lanes), base)
+        finally:
+            os.environ.pop("MB_BLOCK_FORM", None)
+
+
 STRONG = [
     dict(seed=41, N=2, nx=60, n_steps=80, refl=(0.0, 1.0)),
     dict(seed=42, N=3, nx=150, n_steps=90, refl=(0.64, 0.0), soft=True),
