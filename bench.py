@@ -420,7 +420,7 @@ def other_configs(hip, stream, log, sit_ref=None):
     p["field_step"] = "cayley"
     res["lambda3_cayley_field_step"] = leg(hip, stream, "lambda3 Cayley field step", p, log)
     scal = {}
-    for n in range(2, 7):
+    for n in range(2, 9):
         r = leg(hip, stream, f"anharmonic ladder N={n}", W.ladder(n), log)
         r["flop_per_cell_update"] = flops_per_cell_update(n)
         scal[str(n)] = r
@@ -439,7 +439,8 @@ def other_configs(hip, stream, log, sit_ref=None):
     tb = time.perf_counter() - t0
     beff = sum(bytes_per_cell_update(2 if k % 2 == 0 else 3, 32) * q["nx"] * q["n_steps"]
                for k, q in enumerate(sims)) / tb / 1e9
-    state_bytes = sum(q["nx"] * (2 + (3 if k % 2 == 0 else 8)) * 4 for k, q in enumerate(sims))
+    # E, H and the density entries with their FP32 compensation (3 and 8 entries)
+    state_bytes = sum(q["nx"] * (2 + 2 * (3 if k % 2 == 0 else 8)) * 4 for k, q in enumerate(sims))
     res["sweep_x8"] = {"sims": len(sims), "cell_updates": bcells, "value": bcells / tb, "unit": "cell-updates/s",
                        "wall_s": tb, "state_bytes_one_buffer": state_bytes,
                        "bytes_algorithmic_per_s": beff * 1e9, "shape": list(bt.shape())}
@@ -490,10 +491,11 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-sub32", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--only", default="",
-                    help="comma list of optional legs to run (fp64,cpu,batch,configs,serve); others are skipped")
+                    help="comma list of optional legs to run (fp64,cpu,batch,sub32,configs,serve); others are skipped")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the 200/s Poisson trace (2000 = the full 10 s trace)")
     ap.add_argument("--field-step", default="exact", choices=("exact", "cayley"),
@@ -504,7 +506,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
     if args.only:
         keep = set(args.only.split(","))
-        for leg in ("fp64", "cpu", "batch", "configs", "serve"):
+        for leg in ("fp64", "cpu", "batch", "sub32", "configs", "serve"):
             if leg not in keep:
                 setattr(args, "no_" + leg, True)
     if args.gpus != 1:
@@ -648,7 +650,8 @@ def main(argv=None):
                                 "block": bblock, "depth": bdepth, "regs": bregs, "lanes": blanes,
                                 "launch_form": "one kernel per level count and chunk, replayed from a HIP graph"}
         bt.close()
-        out["batched_sweep_sub32"] = sweep_sub_batch(hip, stream, sims[:32], log)
+        if not args.no_sub32:
+            out["batched_sweep_sub32"] = sweep_sub_batch(hip, stream, sims[:32], log)
 
     # ---- other configurations --------------------------------------------------------
     if not args.no_configs:

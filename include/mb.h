@@ -67,7 +67,7 @@ extern "C" {
 #define MB_WARN_NOT_CP 1        /* pure dephasing admits no positive semi-definite C (Sec. 3.1.1) */
 #define MB_ERR_ARG -1           /* invalid argument or inconsistent description */
 #define MB_ERR_CFL -2           /* c_max * dt > dx: time step beyond the Courant limit (Sec. 3.2) */
-#define MB_ERR_UNSUPPORTED -3   /* level count outside 2..6, plain variant in FP32, ... */
+#define MB_ERR_UNSUPPORTED -3   /* level count outside 2..8, plain variant in FP32, ... */
 #define MB_ERR_OOM -4           /* device allocation failed */
 #define MB_ERR_BUDGET -5        /* a request does not fit the server's device-memory budget */
 #define MB_ERR_HIP -6           /* a HIP runtime call failed */
@@ -116,7 +116,7 @@ extern "C" {
 
 /* ---- description ------------------------------------------------------- */
 typedef struct mb_qm {
-  int32_t levels;            /* N in 2..6 */
+  int32_t levels;            /* N in 2..8 */
   int32_t two_level;         /* 1: use the simplified two-level form below, 0: general form */
   double n3d;                /* density of quantum systems [1/m^3] */
   /* general form (two_level == 0) */
@@ -190,7 +190,9 @@ typedef struct mb_scenario_desc {
   int32_t precision;         /* 64 or 32: arithmetic of the bulk field and density updates */
   int32_t variant;           /* MB_VARIANT_* */
   int32_t block;             /* blocked variant: cells per tile, 64, 128, 192, 256 or 512
-                                (0 = default; 5 and 6 levels: block * lanes <= 256) */
+                                (0 = default; 5 and 6 levels: block * lanes <= 256;
+                                7 and 8 levels: 128 or 256 with one lane, weak coupling
+                                and MB_FIELD_EXACT only) */
   int32_t depth;             /* blocked variant: steps per launch = halo width (0 = default) */
   int32_t coupling;          /* MB_COUPLING_WEAK (rho half a step after E, Fig. 1) or
                                 MB_COUPLING_STRONG (rho at the times of E; Sec. 2.2) */
@@ -267,7 +269,7 @@ int mb_plan_source(const mb_device_desc *dev, const mb_scenario_desc *scen, int3
 
 /* 1 when the blocked kernel is built for tiles of `block` cells with `lanes`
  * waves per 64 cells (1, 2, 4 or 8) at this level count (0 = no quantum
- * cells, else 2..6) and precision (64 or 32), else 0.  A run asking for more
+ * cells, else 2..8) and precision (64 or 32), else 0.  A run asking for more
  * lanes than are built for its tile takes the largest built count below; a
  * block that is not built even with one lane is MB_ERR_UNSUPPORTED at set-up.
  * Host-only. */

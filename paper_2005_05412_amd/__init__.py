@@ -289,8 +289,8 @@ def _stream_ptr(stream):
     return C.c_void_p(stream.cuda_stream)  # torch.cuda.Stream
 
 
-# doubles of the largest mb_plan_material output (six levels)
-_PLAN_CAP = 8 * 36 * 36 + 256
+# doubles of the largest mb_plan_material output (eight levels: M = 63, K = 56)
+_PLAN_CAP = 2 * 63 * 63 + 3 * 63 * 56 + 1024
 
 
 def plan_material(prob, material, precision=None):

@@ -242,7 +242,7 @@ int mb_plan_readout(const mb_device_desc *dev, const mb_scenario_desc *scen, int
 }
 
 int mb_tile_supported(int32_t levels, int32_t precision, int32_t block, int32_t lanes) {
-  if ((levels != 0 && (levels < 2 || levels > 6)) || (precision != 32 && precision != 64)) return 0;
+  if ((levels != 0 && (levels < 2 || levels > 8)) || (precision != 32 && precision != 64)) return 0;
   if (lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8) return 0;
   return shape_supported(levels, precision, block, lanes) ? 1 : 0;
 }

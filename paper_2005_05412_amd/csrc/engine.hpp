@@ -64,6 +64,8 @@ __host__ __device__ constexpr int sigma_of(int n, bool bk) { return bk ? bk_sg(n
 // FP64 readout row of a density record (and the strong-coupling trace) per
 // material: value = r0 + r . x + rs . d, length ro_len(N)
 __host__ __device__ constexpr int ro_len(int n) { return mat_m(n) + 1 + mat_k(n); }
+// planes of one density state buffer: FP32 keeps a compensation plane per entry
+__host__ __device__ constexpr int state_planes(int n, int precision) { return (precision == 32 ? 2 : 1) * mat_m(n); }
 
 struct DevSource {
   int64_t cell;
@@ -88,8 +90,14 @@ struct DevSim {
   int32_t n_src;
   int32_t edge_l, edge_r;  // 0: perfect conductor, 1: first-order Mur, 2: impedance load
   double kap_l, kap_r;      // Mur coefficients
-  double load_g_l, load_d_l, load_g_r, load_d_r;  // load edges: E' = g E + d H_{1/2} (left), g E - d H_{nx-3/2} (right)
-  void *e[2], *h[2], *x[2];  // state buffers of element type R; x: M planes of nx
+  double load_g_l, load_d_l, load_g_r, load_d_r;  // load edges: E' = g E + d H'_{1/2} (left), g E - d H'_{nx-3/2} (right)
+  // the kernels advance E and eta0 H (eta0 = sqrt(mu0/eps0)): the update
+  // coefficients are then c0 dt/(eps_r dx) and c0 dt/(mu_r dx), which FP32
+  // holds exactly for the usual Courant numbers; H = h_scale x (stored value)
+  double h_scale;
+  // state buffers of element type R; x: M planes of nx (FP32: then M more
+  // planes, the compensation of each state entry, see Cell::propagate)
+  void *e[2], *h[2], *x[2];
   void *p;                   // polarization scratch of the two-launch path
   const uint8_t *mat_e, *mat_h;
   const void *mtab;

@@ -202,6 +202,24 @@ struct Cell {
   static constexpr int KA = K > 0 ? K : 1;
   static constexpr int P = K / 2;
   static constexpr int NP = N > 0 ? N - 1 : 0;
+  // FP32 keeps, beside each state entry, the part of its running sum that the
+  // FP32 rounding dropped (compensated summation): an entry that relaxes by
+  // increments far below its own ulp, as slow populations do over 1e4..1e6
+  // steps, would otherwise stall or drift by half an ulp per step
+  static constexpr bool KC = sizeof(R) == 4 && N > 0;
+  static constexpr int CA = KC ? MA : 1;
+
+  // x_a <- x_a + inc (FP32: with the compensation xc_a)
+  static __device__ __forceinline__ void add_inc(R &xa, R (&xc)[CA], int a, R inc) {
+    if constexpr (KC) {
+      const R y = inc - xc[a];
+      const R t = xa + y;
+      xc[a] = (t - xa) - y;
+      xa = t;
+    } else {
+      xa = xa + inc;
+    }
+  }
 
   // entry t of the vector (x, d): the state, then the field increments
   static __device__ __forceinline__ R xd(const R (&x)[MA], const R (&d)[KA], int t) { return t < M ? x[t] : d[t - M]; }
@@ -306,7 +324,7 @@ struct Cell {
   // as they are).  Block form: y = x + S d by its real and imaginary parts,
   // then x <- y + (bfp + ap y) on the populations and y + b y on each pair.
   template <int L = 1, int SUB = 0, typename C>
-  static __device__ __forceinline__ void propagate(R (&x)[MA], const R (&d)[KA], const C &mt) {
+  static __device__ __forceinline__ void propagate(R (&x)[MA], R (&xc)[CA], const R (&d)[KA], const C &mt) {
     using SP = Split<N, L, BK>;
     if constexpr (BK) {
       // each row gains x + (increment): the small terms are summed on their own
@@ -326,7 +344,7 @@ struct Cell {
           R acc = mt[bk_bf(N) + a];
 #pragma unroll
           for (int b = 0; b < NP; ++b) acc = fma(mt[bk_ap(N) + a * NP + b], yp[b], acc);
-          x[a] = x[a] + (dp[a] + acc);
+          add_inc(x[a], xc, a, dp[a] + acc);
         }
       }
 #pragma unroll
@@ -341,22 +359,22 @@ struct Cell {
         const R yr = x[NP + 2 * r] + dr, yi = x[NP + 2 * r + 1] + di;
         const R b0 = mt[bk_blk(N) + 4 * r], b1 = mt[bk_blk(N) + 4 * r + 1];
         const R b2 = mt[bk_blk(N) + 4 * r + 2], b3 = mt[bk_blk(N) + 4 * r + 3];
-        x[NP + 2 * r] = x[NP + 2 * r] + (dr + fma(b0, yr, b1 * yi));
-        x[NP + 2 * r + 1] = x[NP + 2 * r + 1] + (di + fma(b2, yr, b3 * yi));
+        add_inc(x[NP + 2 * r], xc, NP + 2 * r, dr + fma(b0, yr, b1 * yi));
+        add_inc(x[NP + 2 * r + 1], xc, NP + 2 * r + 1, di + fma(b2, yr, b3 * yi));
       }
     } else {
-      R out[MA];
+      R inc[MA];
 #pragma unroll
       for (int i = 0; i < M; ++i) {
         if (!SP::owns(SUB, i)) continue;
         R acc = mt[coef_bf(N) + i];
 #pragma unroll
         for (int t = 0; t < M + K; ++t) acc = fma(mt[coef_am(N) + i * (M + K) + t], xd(x, d, t), acc);
-        out[i] = x[i] + acc;
+        inc[i] = acc;
       }
 #pragma unroll
       for (int i = 0; i < M; ++i)
-        if (SP::owns(SUB, i)) x[i] = out[i];
+        if (SP::owns(SUB, i)) add_inc(x[i], xc, i, inc[i]);
     }
   }
 
@@ -398,15 +416,16 @@ __device__ __forceinline__ void record_density(const DevSim &sim, int c, uint32_
 }
 
 // value of a field record (E^{n+1}, H^{n+1/2}; density quantities read zero
-// outside quantum cells); false for density quantities of quantum cells
+// outside quantum cells); false for density quantities of quantum cells.  h is
+// H in A/m (the kernels carry eta0 H, see DevSim::h_scale)
 template <typename R>
-__device__ __forceinline__ bool field_value(int quantity, R e, R h, bool qm, double &v) {
+__device__ __forceinline__ bool field_value(int quantity, R e, double h, bool qm, double &v) {
   if (quantity == 0) {
     v = double(e);
     return true;
   }
   if (quantity == 1) {
-    v = double(h);
+    v = h;
     return true;
   }
   if (!qm) {
@@ -417,7 +436,7 @@ __device__ __forceinline__ bool field_value(int quantity, R e, R h, bool qm, dou
 }
 
 template <typename R>
-__device__ __forceinline__ void record_fields_all(const DevSim &sim, int c, uint32_t n1, R e, R h, bool qm) {
+__device__ __forceinline__ void record_fields_all(const DevSim &sim, int c, uint32_t n1, R e, double h, bool qm) {
   for (int32_t r = 0; r < sim.n_rec_all; ++r) {
     const DevRecord &rc = sim.rec[sim.rec_all[r]];
     double v;
@@ -427,7 +446,7 @@ __device__ __forceinline__ void record_fields_all(const DevSim &sim, int c, uint
 }
 
 template <typename R>
-__device__ __forceinline__ void record_fields(const DevSim &sim, int c, uint32_t n1, R e, R h, bool qm, int rb,
+__device__ __forceinline__ void record_fields(const DevSim &sim, int c, uint32_t n1, R e, double h, bool qm, int rb,
                                               int re) {
   for (int32_t r = rb; r < re; ++r) {
     const DevRecord &rc = sim.rec_cell[r];
@@ -493,7 +512,7 @@ struct TileRecs {
   }
 
   template <typename R>
-  __device__ __forceinline__ void fields(uint32_t q, R e, R h, bool qm, int rb, int re, int step) const {
+  __device__ __forceinline__ void fields(uint32_t q, R e, double h, bool qm, int rb, int re, int step) const {
     for (int r = rb; r < re; r += step) {
       const int qty = quantity[r];
       if (qty >= 2 && qm) continue;  // density record of a quantum cell: written by density()
@@ -726,6 +745,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
   const bool rec_fields_here = rec_here && (rec_fld || (SUB == 0 && sim.n_rec_all > 0));
   const bool rec_tile = sim.rec_first != nullptr || sim.n_rec_all > 0;  // uniform
   const uint32_t rec_every = uint32_t(sim.rec_every);
+  const double h_scale = sim.h_scale;
   const R kap_l = R(sim.kap_l), kap_r = R(sim.kap_r);
   // field part by the Cayley approximant (kernels of their own: the extra
   // phase code would cost the other kernels instruction-cache space)
@@ -776,6 +796,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
 
   R e = 0, h = 0, hl = 0;
   R x[MA];
+  R xc[CL::CA];     // FP32: the compensation of the owned state entries
   R z[CL::KA];      // eigenbasis coherences of x, then the field increments d
   double qn = 0.0;  // strong coupling: (n3D/dt) tr{mu rho^n} of the cell, carried in FP64
 
@@ -808,6 +829,8 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
 #pragma unroll
     for (int a = 0; a < MA; ++a) x[a] = 0;
 #pragma unroll
+    for (int a = 0; a < CL::CA; ++a) xc[a] = 0;
+#pragma unroll
     for (int a = 0; a < CL::KA; ++a) z[a] = 0;
     if (in) {
       e = ld(e_in + c);
@@ -817,6 +840,11 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
 #pragma unroll
           for (int a = 0; a < M; ++a)
             if (SP::owns(SUB, a)) x[a] = ld(x_in + a * nx + c);
+          if constexpr (CL::KC) {
+#pragma unroll
+            for (int a = 0; a < M; ++a)
+              if (SP::owns(SUB, a)) xc[a] = ld(x_in + (M + a) * nx + c);
+          }
         }
       }
     }
@@ -895,7 +923,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
               }
             }
           }
-          CL::template propagate<L, SUB>(x, z, mt);
+          CL::template propagate<L, SUB>(x, xc, z, mt);
         };
         if constexpr (L == 1) {
           per_material([&](const auto &mt, int mm) {
@@ -964,16 +992,16 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
               }
             }
           }
-          CL::propagate(x, z, mt);
+          CL::propagate(x, xc, z, mt);
         });
       }
       if (rec_step) {
         if (rec_fields_here) {
           if (rec_lds) {
-            sm.trec.fields(rq, e, hcell ? h : R(0), qm, rb + SUB, re, RS);
-            if (SUB == 0) record_fields_all(sim, c, n1, e, hcell ? h : R(0), qm);
+            sm.trec.fields(rq, e, hcell ? double(h) * h_scale : 0.0, qm, rb + SUB, re, RS);
+            if (SUB == 0) record_fields_all(sim, c, n1, e, hcell ? double(h) * h_scale : 0.0, qm);
           } else {
-            record_fields(sim, c, n1, e, hcell ? h : R(0), qm, rb, re);
+            record_fields(sim, c, n1, e, hcell ? double(h) * h_scale : 0.0, qm, rb, re);
           }
         }
       }
@@ -1000,6 +1028,11 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
 #pragma unroll
           for (int a = 0; a < M; ++a)
             if (SP::owns(SUB, a)) st(x_out + a * nx + c, x[a]);
+          if constexpr (CL::KC) {
+#pragma unroll
+            for (int a = 0; a < M; ++a)
+              if (SP::owns(SUB, a)) st(x_out + (M + a) * nx + c, xc[a]);
+          }
           if constexpr (ST) st(sim.qs[par ^ 1] + c, qn);
         }
       }
@@ -1100,14 +1133,14 @@ __global__ void __launch_bounds__(kPlainBlock) k_plain_hd(const DevSim *__restri
       const bool mine = qm && me == mm;
       if (mine) {
         const cptr<R> mt = mtab + __builtin_amdgcn_readfirstlane(mm * S);  // uniform: scalar loads
-        R x[MA], z[CL::KA];
+        R x[MA], z[CL::KA], xc[CL::CA];  // FP64: no compensation
 #pragma unroll
         for (int a = 0; a < M; ++a) x[a] = xx[a * nx + c];
         CL::coherences(x, z, mt);
         CL::increments(z, e, mt, sim.cayley != 0);
         p = CL::polar(x, z, mt);
         if (rec_now) record_density<N, R>(sim, c, n1, mm, x, z, rb, re);
-        CL::propagate(x, z, mt);
+        CL::propagate(x, xc, z, mt);
 #pragma unroll
         for (int a = 0; a < M; ++a) xx[a * nx + c] = x[a];
       }
@@ -1168,7 +1201,7 @@ __global__ void __launch_bounds__(kPlainBlock) k_plain_e(const DevSim *__restric
     if constexpr (N > 0) qm = mtab[sim.mat_e[c] * S + kCoefQM] != 0.0;
     int rb, re;
     record_range(sim, c, rb, re);
-    record_fields(sim, c, n1, e, c <= nx - 2 ? hh[c] : 0.0, qm, rb, re);
+    record_fields(sim, c, n1, e, c <= nx - 2 ? hh[c] * sim.h_scale : 0.0, qm, rb, re);
   }
   if (!isfinite(e)) atomicOr(sim.status, kStatusNonFinite);
 }
@@ -1251,6 +1284,22 @@ hipError_t launch_blocked_nr(int block, int lanes, bool vc, bool strong, const D
   return hipErrorInvalidValue;
 }
 
+// seven and eight levels: one wave per 64 cells on tiles of 128 or 256 cells,
+// weak coupling and the exact field step (a cell's state and increments, 90
+// and 119 numbers, fill most of a wave's registers; the host refuses the
+// other forms at these level counts)
+template <int N, typename R, bool P, bool BK>
+hipError_t launch_blocked_big(int block, int lanes, bool strong, const DevSim *sims, const DevTile *tiles, int n_tiles,
+                              int64_t n0, int parity, int halo, int k, const ChunkSync &cs, int *per_cu,
+                              hipStream_t st) {
+  if (strong || lanes != 1) return hipErrorInvalidValue;
+  switch (block) {
+    case 128: return launch_shape<N, R, 128, 1, false, false, P, false, BK>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+    case 256: return launch_shape<N, R, 256, 1, false, false, P, false, BK>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <typename R, bool P, bool CY, bool BK>
 hipError_t launch_blocked_r(int levels, int block, int lanes, bool vc, bool strong, const DevSim *sims,
                             const DevTile *tiles, int n_tiles, int64_t n0, int parity, int halo, int k,
@@ -1271,6 +1320,14 @@ hipError_t launch_blocked_r(int levels, int block, int lanes, bool vc, bool stro
     MB_LEVELS_CASE(5)
     MB_LEVELS_CASE(6)
 #undef MB_LEVELS_CASE
+    case 7:
+      if constexpr (!CY)
+        return launch_blocked_big<7, R, P, BK>(block, lanes, strong, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+      break;
+    case 8:
+      if constexpr (!CY)
+        return launch_blocked_big<8, R, P, BK>(block, lanes, strong, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
+      break;
   }
   return hipErrorInvalidValue;
 }
@@ -1318,6 +1375,8 @@ bool fits_r(int levels, int block, int lanes) {
     case 4: return fits_n<4, R>(block, lanes);
     case 5: return fits_n<5, R>(block, lanes);
     case 6: return fits_n<6, R>(block, lanes);
+    case 7: return (block == 128 || block == 256) && lanes == 1 && fits_n<7, R>(block, 1);
+    case 8: return (block == 128 || block == 256) && lanes == 1 && fits_n<8, R>(block, 1);
   }
   return false;
 }
@@ -1488,6 +1547,8 @@ hipError_t launch_plain(int levels, bool bk, const DevSim *sims, const DevTile *
       case 4: return launch_plain_n<4, true>(sims, tiles, n_tiles, n0, parity, st);
       case 5: return launch_plain_n<5, true>(sims, tiles, n_tiles, n0, parity, st);
       case 6: return launch_plain_n<6, true>(sims, tiles, n_tiles, n0, parity, st);
+      case 7: return launch_plain_n<7, true>(sims, tiles, n_tiles, n0, parity, st);
+      case 8: return launch_plain_n<8, true>(sims, tiles, n_tiles, n0, parity, st);
     }
     return hipErrorInvalidValue;
   }
@@ -1498,6 +1559,8 @@ hipError_t launch_plain(int levels, bool bk, const DevSim *sims, const DevTile *
     case 4: return launch_plain_n<4, false>(sims, tiles, n_tiles, n0, parity, st);
     case 5: return launch_plain_n<5, false>(sims, tiles, n_tiles, n0, parity, st);
     case 6: return launch_plain_n<6, false>(sims, tiles, n_tiles, n0, parity, st);
+    case 7: return launch_plain_n<7, false>(sims, tiles, n_tiles, n0, parity, st);
+    case 8: return launch_plain_n<8, false>(sims, tiles, n_tiles, n0, parity, st);
   }
   return hipErrorInvalidValue;
 }

@@ -216,7 +216,7 @@ void permute_levels(QmFull &q, const std::vector<int> &to) {
 int describe(const mb_qm &q, const mb_consts &k, QmFull &out, std::string &err) {
   int n = q.levels;
   if (n < 2 || n > kMaxLevels) {
-    err = "level count must be 2..6";
+    err = "level count must be 2..8";
     return MB_ERR_UNSUPPORTED;
   }
   out.n = n;
@@ -858,13 +858,18 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
     mp.alpha0 = mt.alpha0;
     mp.overlap = mt.overlap;
     double eps = k.eps0 * mt.eps_r, mu = k.mu0 * mt.mu_r;
+    const double eta0 = std::sqrt(k.mu0 / k.eps0);
     double sigma = 2.0 * mt.alpha0 * std::sqrt(eps / mu);
     double q = plan.dt * sigma / (2.0 * eps);
     double bb = (plan.dt / eps) / (1.0 + q);
     mp.ca = (1.0 - q) / (1.0 + q);
     mp.cbg = bb * mt.overlap;
-    mp.cbd = nx > 1 ? bb / plan.dx : 0.0;
-    mp.ch = nx > 1 ? plan.dt / (plan.dx * mu) : 0.0;
+    // E and eta0 H: the curl coefficients become c0 dt/(eps_r dx (1 + q)) and
+    // c0 dt/(mu_r dx), exact in FP32 for Courant numbers such as 1/2 (with the
+    // SI coefficients their FP32 roundings change the wave speed by ~1e-8,
+    // a phase error of ~1e-4 after 1e4 cells of propagation)
+    mp.cbd = nx > 1 ? bb / (plan.dx * eta0) : 0.0;
+    mp.ch = nx > 1 ? plan.dt * eta0 / (plan.dx * mu) : 0.0;
     mp.c_light = 1.0 / std::sqrt(eps * mu);
     c_max = std::max(c_max, mp.c_light);
     if (mt.qm) {
@@ -880,6 +885,11 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
   if (nx > 1 && c_max * plan.dt > plan.dx * (1.0 + 1e-12)) {
     err = "time step exceeds the Courant limit dx / c_max";
     return MB_ERR_CFL;
+  }
+  if (levels >= 7 && scen->variant != MB_VARIANT_PLAIN &&
+      (scen->coupling == MB_COUPLING_STRONG || scen->field_step == MB_FIELD_CAYLEY)) {
+    err = "7 and 8 levels run with weak coupling and the exact field step";
+    return MB_ERR_UNSUPPORTED;
   }
   plan.n = levels;
   plan.m = levels ? state_dim(levels) : 0;
@@ -912,6 +922,7 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
   // current at t_{n+1/2} gives E' = g E +- d H_inner, a = dt/(eps dx Z_L),
   // g = (1 - a)/(1 + a), d = 2 dt/(eps dx)/(1 + a)
   auto edge_kind = [](double r) { return r == 1.0 ? 0 : r == 0.0 ? 1 : 2; };
+  plan.h_scale = 1.0 / std::sqrt(k.mu0 / k.eps0);
   plan.edge_l = edge_kind(dev->refl_left);
   plan.edge_r = edge_kind(dev->refl_right);
   if (nx > 1) {
@@ -923,7 +934,7 @@ int build_plan(const mb_device_desc *dev, const mb_scenario_desc *scen, SimPlan 
       const double sr = std::sqrt(r), zl = std::sqrt(mu / eps) * (1.0 - sr) / (1.0 + sr);
       const double a = plan.dt / (eps * plan.dx * zl);
       g = (1.0 - a) / (1.0 + a);
-      d = 2.0 * plan.dt / (eps * plan.dx) / (1.0 + a);
+      d = 2.0 * plan.dt / (eps * plan.dx) / (1.0 + a) / std::sqrt(k.mu0 / k.eps0);  // acts on eta0 H
     };
     if (plan.edge_l == 2) load(plan.mats[plan.mat_e[0]], dev->refl_left, plan.load_g_l, plan.load_d_l);
     if (plan.edge_r == 2) load(plan.mats[plan.mat_e[nx - 1]], dev->refl_right, plan.load_g_r, plan.load_d_r);

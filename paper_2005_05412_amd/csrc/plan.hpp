@@ -13,7 +13,7 @@ namespace mb {
 
 using cd = std::complex<double>;
 
-constexpr int kMaxLevels = 6;
+constexpr int kMaxLevels = 8;
 constexpr int kMaxLindbladOps = 64;
 
 // Real parametrisation of an N x N Hermitian density matrix in the basis the
@@ -92,7 +92,9 @@ struct SimPlan {
   std::vector<MaterialPlan> mats;
   int edge_l = 0, edge_r = 0;     // 0: PEC, 1: Mur, 2: impedance load (0 < R < 1)
   double kap_l = 0, kap_r = 0;    // Mur coefficients
-  double load_g_l = 0, load_d_l = 0, load_g_r = 0, load_d_r = 0;  // E' = g E +- d H_inner
+  double load_g_l = 0, load_d_l = 0, load_g_r = 0, load_d_r = 0;  // E' = g E +- d H'_inner
+  // E and H' = eta0 H are advanced (eta0 = sqrt(mu0/eps0)); H = h_scale H'
+  double h_scale = 1.0;
   std::vector<SourcePlan> sources;
   std::vector<RecordPlan> records;
   std::vector<double> e0;         // nx

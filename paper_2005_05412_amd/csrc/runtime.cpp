@@ -36,7 +36,8 @@ Layout layout_of(const SimPlan &p, int precision, bool plain) {
   };
   L.e = take(2 * nx * rs);
   L.h = take(2 * nx * rs);
-  L.x = take(std::max<size_t>(1, 2 * m * nx) * rs);
+  const size_t planes = size_t(state_planes(p.n, precision));
+  L.x = take(std::max<size_t>(1, 2 * planes * nx) * rs);
   L.init_e = take(nx * rs);
   L.init_x = take(std::max<size_t>(1, m * nx) * rs);
   L.p = take(plain ? nx * rs : rs);
@@ -127,7 +128,9 @@ void fill_state(const SimPlan &p, char *head, const Layout &L) {
     h[c] = h[nx + c] = R(0);
   }
   const size_t mn = size_t(p.m) * nx;
-  for (size_t q = 0; q < mn; ++q) x[q] = x[mn + q] = ix[q] = R(p.x0[q]);
+  const size_t pn = size_t(state_planes(p.n, sizeof(R) == 4 ? 32 : 64)) * nx;  // planes of one buffer
+  for (size_t q = 0; q < mn; ++q) x[q] = x[pn + q] = ix[q] = R(p.x0[q]);
+  for (size_t q = mn; q < pn; ++q) x[q] = x[pn + q] = R(0);  // FP32 compensation
   fill_mtab<R>(p, reinterpret_cast<R *>(head + L.mtab));
   if (p.coupling == MB_COUPLING_STRONG && p.n > 0) {
     double *qs = reinterpret_cast<double *>(head + L.qs);
@@ -311,7 +314,11 @@ int Engine::add(SimPlan &&plan, Arena *arena, hipStream_t st, std::string &err) 
   }
   if (!plain && !shape_supported(plan.n, precision_, block_, 1)) {
     err = "no tile of " + std::to_string(block_) + " cells is built for " + std::to_string(plan.n) +
-          " levels in this precision (5 and 6 levels: at most 256)";
+          " levels in this precision (5 and 6 levels: at most 256; 7 and 8 levels: 128 or 256)";
+    return MB_ERR_UNSUPPORTED;
+  }
+  if (!plain && plan.n >= 7 && (plan.coupling == MB_COUPLING_STRONG || plan.field_step == MB_FIELD_CAYLEY)) {
+    err = "7 and 8 levels run with weak coupling and the exact field step";
     return MB_ERR_UNSUPPORTED;
   }
   if (free_slots_.empty()) {
@@ -409,12 +416,13 @@ int Engine::add(SimPlan &&plan, Arena *arena, hipStream_t st, std::string &err) 
   d.load_d_l = p.load_d_l;
   d.load_g_r = p.load_g_r;
   d.load_d_r = p.load_d_r;
+  d.h_scale = p.h_scale;
   d.e[0] = dev + L.e;
   d.e[1] = dev + L.e + nx * rs;
   d.h[0] = dev + L.h;
   d.h[1] = dev + L.h + nx * rs;
   d.x[0] = dev + L.x;
-  d.x[1] = dev + L.x + size_t(p.m) * nx * rs;
+  d.x[1] = dev + L.x + size_t(state_planes(p.n, precision_)) * nx * rs;
   d.qs[0] = reinterpret_cast<double *>(dev + L.qs);
   d.qs[1] = p.coupling == MB_COUPLING_STRONG && p.n > 0 ? d.qs[0] + nx : d.qs[0];
   d.qtab = reinterpret_cast<const double *>(dev + L.qtab);
@@ -767,6 +775,8 @@ hipError_t Engine::reset(hipStream_t st) {
       if (e == hipSuccess) e = hipMemsetAsync(s.ds.h[b], 0, nx * rs, st);
       if (e == hipSuccess && m)
         e = hipMemcpyAsync(s.ds.x[b], s.block + s.init_x, m * nx * rs, hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess && m && precision_ == 32)  // the compensation planes start at zero
+        e = hipMemsetAsync(static_cast<char *>(s.ds.x[b]) + m * nx * rs, 0, m * nx * rs, st);
       if (e == hipSuccess && s.plan.coupling == MB_COUPLING_STRONG && m)
         e = hipMemcpyAsync(s.ds.qs[b], s.block + s.init_q, nx * sizeof(double), hipMemcpyDeviceToDevice, st);
     }
@@ -897,20 +907,23 @@ hipError_t Engine::read_state(int id, double *e, double *h, double *rho) {
   }
   if (h) {
     if ((er = fetch(s.ds.h[s.cur_h], nx, buf)) != hipSuccess) return er;
-    std::copy(buf.begin(), buf.end(), h);
+    for (size_t c = 0; c < nx; ++c) h[c] = buf[c] * p.h_scale;  // the kernels hold eta0 H
     if (nx) h[nx - 1] = 0.0;
   }
   if (rho) {
     const int n = p.n;
     std::fill(rho, rho + nx * n * n * 2, 0.0);
     if (n > 0) {
-      if ((er = fetch(s.ds.x[s.cur_x], m * nx, buf)) != hipSuccess) return er;
+      // FP32: the entries and their compensation planes (the running sum lacks
+      // the compensation: its value is entry - compensation)
+      const size_t planes = size_t(state_planes(n, precision_));
+      if ((er = fetch(s.ds.x[s.cur_x], planes * nx, buf)) != hipSuccess) return er;
       std::vector<double> sig(m);
       std::vector<cd> r(size_t(n) * n);
       for (size_t c = 0; c < nx; ++c) {
         const MaterialPlan &mp = p.mats[p.mat_e[c]];
         if (!mp.qm) continue;
-        for (size_t a = 0; a < m; ++a) sig[a] = buf[a * nx + c];
+        for (size_t a = 0; a < m; ++a) sig[a] = buf[a * nx + c] - (planes > m ? buf[(m + a) * nx + c] : 0.0);
         state_to_rho(mp, sig.data(), r.data());
         for (int q = 0; q < n * n; ++q) {
           rho[(c * n * n + q) * 2] = r[q].real();

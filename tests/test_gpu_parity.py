@@ -60,6 +60,8 @@ SMALL = [
     dict(seed=18, N=2, nx=3, n_steps=25, refl=(0.0, 0.0)),
     dict(seed=25, N=3, nx=120, n_steps=80, refl=(0.64, 0.3)),       # semi-transparent ends
     dict(seed=26, N=5, nx=70, n_steps=40, refl=(0.8, 0.8), e_noise=1e6),
+    dict(seed=27, N=7, nx=40, n_steps=30, refl=(0.0, 1.0)),
+    dict(seed=28, N=8, nx=35, n_steps=25, refl=(1.0, 0.0), e_noise=1e6),
 ]
 
 
@@ -608,6 +610,37 @@ def test_anharmonic_ladder_vs_oracle(n):
     assert max(errs32.values()) <= TOL[32], errs32
     for block, depth, lanes in ((128, 16, 2), (64, 8, 4), (64, 8, 8)):
         assert_same(gpu_run(prob, precision=32, variant="blocked", block=block, depth=depth, lanes=lanes), got32)
+
+
+@pytest.mark.parametrize("n", [7, 8])
+def test_ladder_seven_and_eight_levels_vs_oracle(n):
+    """The level-count benchmark of Sec. 4.3 (any N >= 2) beyond six levels: the anharmonic
+    ladder at 7 and 8 levels, 300 cells x 400 steps, in the block form (the ladder's) and
+    forced into the general form: FP64 within 1e-10 and FP32 within 1e-4 per trace; both
+    built tiles (128 and 256 cells, one wave per 64 cells) bit for bit the same, a request
+    for two waves per 64 cells runs the one built, and the two-launch FP64 kernel matches
+    the blocked one bit for bit."""
+    prob = W.ladder(n, nx=300, n_steps=400, rec_interval=4)
+    _say(f"ladder {n}")
+    assert mb.tile_supported(n, 32, 128) and mb.tile_supported(n, 64, 256)
+    assert not mb.tile_supported(n, 32, 64) and not mb.tile_supported(n, 32, 128, lanes=2)
+    ref = O.run(prob)
+    for form in ("block", "general"):
+        if form == "general":
+            os.environ["MB_BLOCK_FORM"] = "0"
+        try:
+            assert mb.plan_material(prob, 1)["block"] == (form == "block")
+            for precision in (64, 32):
+                base = gpu_run(prob, precision=precision, variant="blocked", block=128, depth=16, lanes=1)
+                errs = rel_errors(prob, base, ref)
+                _say(f"ladder {n} {form} fp{precision} {worst(errs)}")
+                assert max(errs.values()) <= TOL[precision], (form, precision, worst(errs))
+                assert_same(gpu_run(prob, precision=precision, variant="blocked", block=256, depth=32, lanes=1), base)
+                assert_same(gpu_run(prob, precision=precision, variant="blocked", block=128, depth=16, lanes=2), base)
+                if precision == 64:
+                    assert_same(gpu_run(prob, precision=64, variant="plain"), base)
+        finally:
+            os.environ.pop("MB_BLOCK_FORM", None)
 
 
 @pytest.mark.parametrize("n", [2, 3, 6])

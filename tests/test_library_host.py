@@ -86,7 +86,7 @@ def _random_ops(rng, n, k=3, rate=1e12):
 
 
 @pytest.mark.parametrize("n,seed,ops", [(2, 1, False), (3, 2, False), (4, 3, False), (5, 4, False), (6, 5, False),
-                                        (3, 6, True), (5, 7, True)])
+                                        (7, 8, False), (8, 9, False), (3, 6, True), (5, 7, True)])
 def test_plan_tables_reproduce_oracle_single_point(n, seed, ops):
     rng = np.random.default_rng(seed)
     qm = W.random_qm(rng, n, dipole=3e-29)
@@ -189,9 +189,16 @@ def test_status_codes():
             mb.plan_status(_vac(refl=bad_r))
         assert ex.value.code == -1
     rng = np.random.default_rng(1)
+    assert mb.plan_status(_vac(levels_qm=W.random_qm(rng, 8))) == 0
     with pytest.raises(mb.MBError) as ex:
-        mb.plan_status(_vac(levels_qm=W.random_qm(rng, 7)))
+        mb.plan_status(_vac(levels_qm=W.random_qm(rng, 9)))
     assert ex.value.code == -3
+    for key, val in (("coupling", "strong"), ("field_step", "cayley")):
+        big = _vac(levels_qm=W.random_qm(rng, 7))   # 7 and 8 levels: weak coupling, exact field step
+        big[key] = val
+        with pytest.raises(mb.MBError) as ex:
+            mb.plan_status(big)
+        assert ex.value.code == -3
     bad = _vac()
     bad["regions"] = [dict(x_start=0.0, x_end=0.5e-5, material=0)]
     with pytest.raises(mb.MBError) as ex:
