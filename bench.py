@@ -302,7 +302,15 @@ def run_serving(n_requests, rate, log, first_n=0):
     offered = sum(p["nx"] * p["n_steps"] for _, p in trace) / max(trace[-1][0], 1e-9)
     t0 = time.perf_counter()
     srv.start()
-    srv.drain(timeout_s=600)
+    # progress every 20 s while the trace drains (poll: tickets that became final)
+    n_final, t_log = 0, t0
+    while n_final < len(tickets) and time.perf_counter() - t0 < 600:
+        time.sleep(0.05)
+        n_final += len(srv.poll(4096))
+        if time.perf_counter() - t_log >= 20:
+            t_log = time.perf_counter()
+            log(f"[bench] serving: {n_final} of {len(tickets)} requests final after {t_log - t0:.0f} s")
+    srv.drain(timeout_s=max(1.0, 600 - (time.perf_counter() - t0)))
     tw = time.perf_counter() - t0
     lat = []
     by_levels = {}
@@ -429,6 +437,7 @@ def other_configs(hip, stream, log, sit_ref=None):
     sims = W.sweep(n_sims=2048, precision=32, seed=W.SEED_BASE + 13)
     bcells = sum(q["nx"] * q["n_steps"] for q in sims)
     bt = mb.Batch(sims, precision=32, variant="auto")
+    x8mode = bt.run_mode()
     bt.run(stream=stream, use_graph=True)
     hip.sync()
     bt.reset(stream)
@@ -442,6 +451,7 @@ def other_configs(hip, stream, log, sit_ref=None):
     # E, H and the density entries with their FP32 compensation (3 and 8 entries)
     state_bytes = sum(q["nx"] * (2 + 2 * (3 if k % 2 == 0 else 8)) * 4 for k, q in enumerate(sims))
     res["sweep_x8"] = {"sims": len(sims), "cell_updates": bcells, "value": bcells / tb, "unit": "cell-updates/s",
+                       "launch_form": x8mode,
                        "wall_s": tb, "state_bytes_one_buffer": state_bytes,
                        "bytes_algorithmic_per_s": beff * 1e9, "shape": list(bt.shape())}
     bt.close()
@@ -468,6 +478,8 @@ def plain_fifo(trace, log):
         lat.append(done - ta)
         by_levels.setdefault(levels_of(p), []).append(done - ta)
         cu += p["nx"] * p["n_steps"]
+        if len(lat) % 10 == 0:
+            log(f"[bench] FIFO: {len(lat)} of {len(trace)} requests done after {done:.0f} s")
     tw = time.perf_counter() - t0
     lat = np.array(lat)
     return {"requests": len(trace), "p50_latency_s": float(np.percentile(lat, 50)),
@@ -632,6 +644,7 @@ def main(argv=None):
         bcells = sum(p["nx"] * p["n_steps"] for p in sims)
         bt = mb.Batch(sims, precision=32, variant="auto")
         bblock, bdepth, bregs, blanes = bt.shape()
+        bmode = bt.run_mode()
         bt.run(stream=stream, use_graph=True)
         hip.sync()
         bt.reset(stream)
@@ -648,7 +661,9 @@ def main(argv=None):
                                 "value": bcells / tb, "unit": "cell-updates/s", "sims": len(sims),
                                 "cell_updates": bcells, "wall_s": tb, "bytes_algorithmic_per_s": beff * 1e9,
                                 "block": bblock, "depth": bdepth, "regs": bregs, "lanes": blanes,
-                                "launch_form": "one kernel per level count and chunk, replayed from a HIP graph"}
+                                "launch_form": {"queue": "work-queue persistent launches of both level counts",
+                                                "flags": "persistent launches with neighbour flags",
+                                                "chunks": "one kernel per level count and chunk, replayed from a HIP graph"}[bmode]}
         bt.close()
         if not args.no_sub32:
             out["batched_sweep_sub32"] = sweep_sub_batch(hip, stream, sims[:32], log)

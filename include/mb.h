@@ -326,8 +326,9 @@ int mb_run_static(mb_handle *h, int64_t n_steps, void *hip_stream);
 
 /* 1 when mb_run(h, n_steps) would run its full chunks as persistent launches
  * (one launch for up to 4096 chunks; tiles wait for their neighbours' flags
- * between chunks), 0 when every chunk is its own launch, negative on error.
- * Uploads pending simulation tables (synchronously). */
+ * between chunks), 2 when as work-queue persistent launches (see
+ * mb_batch_run_mode), 0 when every chunk is its own launch, negative on
+ * error.  Uploads pending simulation tables (synchronously). */
 int mb_run_mode(mb_handle *h, int64_t n_steps);
 
 /* Restores the initial state (from a device-resident copy made at setup),
@@ -370,8 +371,10 @@ int mb_destroy(mb_handle *h);
 /* ---- batches: many independent simulations in one launch sequence -------- */
 
 /* All simulations share precision and variant; the blocked variant runs
- * every level count in its own kernel per chunk.  Tables and state of all
- * members live in one device allocation. */
+ * every level count in its own kernel per chunk, or all chunks of a two- and
+ * a three-level group in one work-queue persistent launch (the batched
+ * parameter sweep; see mb_batch_run_mode).  Tables and state of all members
+ * live in one device allocation. */
 int mb_batch_setup(int hip_device, int32_t n, const mb_device_desc *devs,
                    const mb_scenario_desc *scens, mb_batch **out);
 /* Runs every member to its own n_steps (uneven lengths allowed).  When
@@ -380,6 +383,16 @@ int mb_batch_setup(int hip_device, int32_t n, const mb_device_desc *devs,
 int mb_batch_run(mb_batch *b, void *hip_stream, int32_t use_graph);
 /* Restores every member's initial state and clears the records (as mb_reset). */
 int mb_batch_reset(mb_batch *b, void *hip_stream);
+/* How mb_batch_run would run the full chunks of the members' remaining steps:
+ * 1 persistent launches with neighbour flags (one level-count group, every
+ * tile resident at once), 2 work-queue persistent launches (weak coupling and
+ * the exact field step, two- and/or three-level members, one wave per 64
+ * cells on tiles of 128, 192 (FP32) or 256 cells: each workgroup takes
+ * (chunk, tile) items in chunk-major order from a counter and waits for the
+ * tile's and its neighbours' previous chunk, so the tiles need not all be
+ * resident; MB_QUEUE=0 disables it), 0 one launch per chunk and level count;
+ * negative on error.  Uploads pending tables (synchronously). */
+int mb_batch_run_mode(mb_batch *b);
 /* Tile shape in use (as mb_shape; tuned over the whole batch). */
 int mb_batch_shape(const mb_batch *b, int32_t *block, int32_t *depth, int32_t *regs, int32_t *lanes);
 int mb_batch_record_shape(const mb_batch *b, int32_t sim, int record_id, int64_t *n_samples,

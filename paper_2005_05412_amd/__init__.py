@@ -29,7 +29,7 @@ VARIANT = {"auto": 0, "plain": 1, "blocked": 2, "blocked_regs": 3}
 FIELD_STEP = {"exact": 0, "cayley": 1}    # MB_FIELD_EXACT, MB_FIELD_CAYLEY
 
 EXPORTS = [
-    "mb_last_error", "mb_device_count", "mb_plan_material", "mb_plan_readout", "mb_plan_source", "mb_tile_supported", "mb_workspace_bytes", "mb_setup", "mb_run", "mb_run_static", "mb_run_mode", "mb_reset", "mb_batch_reset", "mb_shape", "mb_batch_shape", "mb_steps_done", "mb_record_shape",
+    "mb_last_error", "mb_device_count", "mb_plan_material", "mb_plan_readout", "mb_plan_source", "mb_tile_supported", "mb_workspace_bytes", "mb_setup", "mb_run", "mb_run_static", "mb_run_mode", "mb_batch_run_mode", "mb_reset", "mb_batch_reset", "mb_shape", "mb_batch_shape", "mb_steps_done", "mb_record_shape",
     "mb_read_records", "mb_read_state", "mb_elapsed_ms", "mb_destroy", "mb_batch_setup", "mb_batch_run",
     "mb_batch_record_shape", "mb_batch_read_records", "mb_batch_elapsed_ms", "mb_batch_destroy",
     "mb_server_create", "mb_server_submit", "mb_server_start", "mb_server_drain", "mb_server_cancel", "mb_server_poll",
@@ -135,6 +135,7 @@ def load():
         "mb_run": (C.c_int, [P, C.c_int64, P]),
         "mb_run_static": (C.c_int, [P, C.c_int64, P]),
         "mb_run_mode": (C.c_int, [P, C.c_int64]),
+        "mb_batch_run_mode": (C.c_int, [P]),
         "mb_reset": (C.c_int, [P, P]),
         "mb_batch_reset": (C.c_int, [P, P]),
         "mb_shape": (C.c_int, [P] + [C.POINTER(C.c_int32)] * 4),
@@ -424,7 +425,7 @@ class Solver:
         n = self.prob["n_steps"] if n_steps is None else int(n_steps)
         r = load().mb_run_mode(self._h, n)
         _check(min(r, 0))
-        return r == 1
+        return r != 0
 
     @property
     def steps_done(self):
@@ -506,6 +507,13 @@ class Batch:
         b, d, r, n = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
         _check(load().mb_batch_shape(self._h, C.byref(b), C.byref(d), C.byref(r), C.byref(n)))
         return b.value, d.value, bool(r.value), n.value
+
+    def run_mode(self):
+        """How run() advances the full chunks: "flags" (one persistent launch, every tile
+        resident), "queue" (work-queue persistent launch), or "chunks" (a launch per chunk)."""
+        r = load().mb_batch_run_mode(self._h)
+        _check(min(r, 0))
+        return {0: "chunks", 1: "flags", 2: "queue"}[r]
 
     def record(self, sim, k):
         lib = load()

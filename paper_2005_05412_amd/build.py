@@ -12,10 +12,10 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libmbhip.so")
 OBJ = os.path.join(HERE, "_build")
-# (source, extra flags, object name): the kernels are compiled in sixteen parts
+# (source, extra flags, object name): the kernels are compiled in eighteen parts
 # (FP32 and FP64, one-chunk and persistent tiles, exact and Cayley field step,
-# general and block form of the density tables)
-SOURCES = [("kernels.hip", [f"-DMB_PART={i + 1}"], f"kernels_{i:02d}") for i in range(16)] + [
+# general and block form of the density tables; the work-queue kernels)
+SOURCES = [("kernels.hip", [f"-DMB_PART={i + 1}"], f"kernels_{i:02d}") for i in range(18)] + [
     ("scratch.hip", [], "scratch")] + [(f, [], f) for f in ("plan.cpp", "runtime.cpp", "tune.cpp", "abi.cpp", "server.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("MB_OFFLOAD_ARCH", "gfx950")

@@ -380,7 +380,7 @@ int mb_run_mode(mb_handle *h, int64_t n_steps) {
   hipError_t e = h->eng->sync_tables(h->last_stream);
   if (e != hipSuccess) return hip_fail(e, "table upload");
   const int k = h->eng->chunk_steps();
-  return h->eng->persist_ok(k, n_steps / k) ? 1 : 0;
+  return h->eng->persist_form(k, n_steps / k);
   MB_GUARD_END
 }
 
@@ -561,6 +561,24 @@ int mb_batch_run(mb_batch *b, void *hip_stream, int32_t use_graph) {
   (void)hipEventRecord(eb, st);
   b->events.emplace_back(ea, eb);
   return MB_OK;
+  MB_GUARD_END
+}
+
+int mb_batch_run_mode(mb_batch *b) {
+  MB_GUARD_BEGIN
+  if (!b) return fail(MB_ERR_ARG, "null batch");
+  if (hipSetDevice(b->device) != hipSuccess) return fail(MB_ERR_HIP, "hipSetDevice failed");
+  Engine &eng = *b->eng;
+  if (eng.variant() == MB_VARIANT_PLAIN) return 0;
+  int64_t remaining = 0;
+  for (int id : b->ids) {
+    const SimState &s = eng.sim(id);
+    remaining = std::max<int64_t>(remaining, s.plan.n_steps - s.done);
+  }
+  hipError_t e = eng.sync_tables(b->last_stream);
+  if (e != hipSuccess) return hip_fail(e, "table upload");
+  const int k = eng.chunk_steps();
+  return eng.persist_form(k, remaining / k);
   MB_GUARD_END
 }
 

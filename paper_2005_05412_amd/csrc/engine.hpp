@@ -133,6 +133,22 @@ struct ChunkSync {
   int64_t spin_ticks;  // device wall-clock ticks a tile waits for a neighbour before giving up
 };
 
+// A work-queue persistent launch of a two-level and a three-level tile group
+// (either may be empty): items (chunk c, tile t) in chunk-major order, handed
+// out by an atomic counter; an item waits for its own tile's and both
+// neighbours' items of chunk c - 1, which were handed out earlier and so are
+// held by running workgroups (or done): every wait ends, whatever the grid.
+struct QueueArgs {
+  const DevSim *sims[2];
+  const DevTile *tiles[2];
+  uint32_t *flags[2];   // one per tile of each group, as in ChunkSync
+  int32_t n_tiles[2];
+  uint32_t *counter;    // items handed out; zero before the launch
+  uint32_t epoch;       // epoch of the launch's first chunk
+  int32_t n_chunks;     // chunks of k steps in this launch
+  int64_t spin_ticks;
+};
+
 // bits of DevSim::status
 constexpr int32_t kStatusNonFinite = 1;    // a non-finite field value was seen
 constexpr int32_t kStatusWaitTimeout = 2;  // a tile gave up waiting for a neighbour tile

@@ -587,14 +587,17 @@ __device__ __forceinline__ void store_coherent(T *p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// true once both neighbour tiles have finished the chunk of epoch `target`;
-// false after cs.spin_ticks of the device wall clock (the launch is then
-// abandoned and the simulation's status reports it)
-__device__ __forceinline__ bool neighbours_reached(const ChunkSync &cs, const DevTile &tile, uint32_t target) {
+// true once both neighbour tiles (and tile `self` when >= 0) have finished
+// the chunk of epoch `target`; false after cs.spin_ticks of the device wall
+// clock (the launch is then abandoned and the simulation's status reports it)
+__device__ __forceinline__ bool neighbours_reached(const ChunkSync &cs, const DevTile &tile, uint32_t target,
+                                                   int self = -1) {
   const int64_t t0 = wall_clock64();
   for (;;) {
     bool ok = true;
-    if (tile.left >= 0)
+    if (self >= 0)
+      ok = int32_t(__hip_atomic_load(cs.flags + self, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) >= 0;
+    if (ok && tile.left >= 0)
       ok = int32_t(__hip_atomic_load(cs.flags + tile.left, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) >= 0;
     if (ok && tile.right >= 0)
       ok = int32_t(__hip_atomic_load(cs.flags + tile.right, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) >= 0;
@@ -623,17 +626,21 @@ constexpr bool regs_fit() {
 }
 
 // P: a persistent launch (several chunks, neighbour flags, device-coherent
-// exchange of the owned cells); without it one chunk, and none of that code
-template <int N, typename R, int B, int L, bool VC, int SUB, bool ST, bool P, bool CY, bool BK>
+// exchange of the owned cells); without it one chunk, and none of that code.
+// tix: the tile.  Q: one item of a work-queue launch (P false), chunk qchunk
+// of the launch: the tile first waits until it and both neighbours have
+// finished chunk qchunk - 1, reads its cells with device-coherent loads and
+// raises its flag when its stores are done.
+template <int N, typename R, int B, int L, bool VC, int SUB, bool ST, bool P, bool CY, bool BK, bool Q = false>
 __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, const DevTile *__restrict__ tiles,
-                                           int64_t n0, int parity, int halo, int k, const ChunkSync &cs,
-                                           TileShared<N, R, B, L> &sm) {
+                                           int tix, int qchunk, int64_t n0, int parity, int halo, int k,
+                                           const ChunkSync &cs, TileShared<N, R, B, L> &sm) {
   using CL = Cell<N, R, BK>;
   using SP = Split<N, L, BK>;
   constexpr int M = CL::M, MA = CL::MA, S = stride_of(N, BK);
   constexpr bool WAVE = B == 64 && L == 1;  // one wave per tile: neighbours by DPP, no barriers
   constexpr int SQ = S - kCoefKap;          // quantum part of a material's coefficients
-  const DevTile tile = tiles[blockIdx.x];
+  const DevTile tile = tiles[tix];
   // fields used inside the step loop are copied to locals below, so stores to
   // records cannot force them to be reloaded
   const DevSim &sim = sims[tile.sim];
@@ -821,9 +828,21 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
     const R *__restrict__ e_in = static_cast<const R *>(sim.e[par]);
     const R *__restrict__ h_in = static_cast<const R *>(sim.h[par]);
     const R *__restrict__ x_in = static_cast<const R *>(sim.x[par]);
+    if (Q && qchunk > 0 && ls64 >= k) {
+      // work-queue item whose simulation ran the previous chunk in this
+      // launch: the tile's own and both neighbours' stores of that chunk
+      // (other workgroups, handed out earlier) are complete first
+      if (threadIdx.x == 0) {
+        const bool ok = neighbours_reached(cs, tile, cs.epoch + uint32_t(qchunk), tix);
+        sm.stop = !ok;
+        if (!ok) atomicOr(sim.status, kStatusWaitTimeout);
+      }
+      __syncthreads();
+      if (sm.stop) return;
+    }
     // after the first chunk of a persistent launch the cells come from
     // neighbour tiles' stores of this launch: device-coherent loads
-    const bool fresh = P && chunk > 0;
+    const bool fresh = Q || (P && chunk > 0);
     auto ld = [fresh](const auto *ptr) { return fresh ? load_coherent(ptr) : *ptr; };
     e = h = hl = 0;
 #pragma unroll
@@ -1012,7 +1031,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
       R *__restrict__ h_out = static_cast<R *>(sim.h[par ^ 1]);
       R *__restrict__ x_out = static_cast<R *>(sim.x[par ^ 1]);
       // persistent launches: device-coherent stores, read by the neighbours
-      constexpr bool share = P;
+      constexpr bool share = P || Q;
       auto st = [share](auto *ptr, auto v) {
         if (share)
           store_coherent(ptr, v);
@@ -1038,7 +1057,14 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
       }
       if (SUB == 0 && (!isfinite(double(e)) || !isfinite(double(h)))) atomicOr(sim.status, kStatusNonFinite);
     }
-    if (P && chunk + 1 < n_chunks) {
+    if (Q) {
+      // work-queue item done: every wave's coherent stores are complete
+      // before the tile's flag is raised
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (threadIdx.x == 0) store_coherent(cs.flags + tix, cs.epoch + uint32_t(qchunk) + 1u);
+    } else if (P && chunk + 1 < n_chunks) {
       // every wave's coherent stores of its owned cells are complete before
       // the tile's flag is raised; the next chunk's cells are read (coherent
       // loads) after both neighbours have raised theirs
@@ -1047,7 +1073,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
       __syncthreads();
       if (threadIdx.x == 0) {
         const uint32_t target = cs.epoch + uint32_t(chunk) + 1u;
-        store_coherent(cs.flags + blockIdx.x, target);
+        store_coherent(cs.flags + tix, target);
         const bool ok = neighbours_reached(cs, tile, target);
         sm.stop = !ok;
         if (!ok) atomicOr(sim.status, kStatusWaitTimeout);
@@ -1066,11 +1092,11 @@ __device__ __forceinline__ void run_group(int sub, const DevSim *__restrict__ si
                                           TileShared<N, R, B, L> &sm) {
   if constexpr (S + 1 < L) {
     if (sub == S)
-      tile_steps<N, R, B, L, VC, S, false, P, CY, BK>(sims, tiles, n0, parity, halo, k, cs, sm);
+      tile_steps<N, R, B, L, VC, S, false, P, CY, BK>(sims, tiles, blockIdx.x, -1, n0, parity, halo, k, cs, sm);
     else
       run_group<N, R, B, L, VC, P, CY, BK, S + 1>(sub, sims, tiles, n0, parity, halo, k, cs, sm);
   } else {
-    tile_steps<N, R, B, L, VC, S, false, P, CY, BK>(sims, tiles, n0, parity, halo, k, cs, sm);
+    tile_steps<N, R, B, L, VC, S, false, P, CY, BK>(sims, tiles, blockIdx.x, -1, n0, parity, halo, k, cs, sm);
   }
 }
 
@@ -1082,7 +1108,7 @@ __global__ void __launch_bounds__(B * L) k_blocked(const DevSim *__restrict__ si
                                                    int halo, int k, ChunkSync cs) {
   __shared__ TileShared<N, R, B, L> sm;
   if constexpr (L == 1) {
-    tile_steps<N, R, B, 1, VC, 0, ST, P, CY, BK>(sims, tiles, n0, parity, halo, k, cs, sm);
+    tile_steps<N, R, B, 1, VC, 0, ST, P, CY, BK>(sims, tiles, blockIdx.x, -1, n0, parity, halo, k, cs, sm);
   } else {
     run_group<N, R, B, L, VC, P, CY, BK>(__builtin_amdgcn_readfirstlane(int(threadIdx.x) / B), sims, tiles, n0, parity,
                                          halo, k, cs, sm);
@@ -1381,6 +1407,68 @@ bool fits_r(int levels, int block, int lanes) {
   return false;
 }
 
+// Work-queue persistent launch of a two- and a three-level tile group (the
+// batched parameter sweep): each workgroup takes items (chunk, tile) from the
+// counter until none is left and runs one chunk of that tile with the tile
+// code of its level count (one wave per 64 cells), so tiles of both level
+// counts and of simulations of any length share one launch even when they do
+// not all fit on the device at once.
+// (waves per SIMD held at 4 for FP32 without register coefficients: the two
+// tile bodies together would otherwise take 163 registers, 3 waves, where one
+// body alone takes 82 or 121; the 128-register bound costs 8..16 bytes of
+// spill per lane)
+template <typename R, int B, bool VC, bool BK>
+__global__ void __launch_bounds__(B, (sizeof(R) == 4 && !VC) ? 4 : 2)
+    k_queue(QueueArgs qa, int64_t n0, int parity, int halo, int k) {
+  union Shared {
+    TileShared<2, R, B, 1> two;
+    TileShared<3, R, B, 1> three;
+  };
+  __shared__ Shared sm;
+  __shared__ uint32_t item_s;
+  const uint32_t per_chunk = uint32_t(qa.n_tiles[0]) + uint32_t(qa.n_tiles[1]);
+  const uint32_t total = per_chunk * uint32_t(qa.n_chunks);
+  for (;;) {
+    __syncthreads();  // the previous item is done with the shared memory
+    if (threadIdx.x == 0) item_s = atomicAdd(qa.counter, 1u);
+    __syncthreads();
+    const uint32_t item = item_s;
+    if (item >= total) return;
+    const int c = int(item / per_chunk), r = int(item % per_chunk);
+    const int64_t nc = n0 + int64_t(c) * k;
+    const int par = parity ^ (c & 1);
+    if (r < qa.n_tiles[0]) {
+      const ChunkSync cs{qa.flags[0], qa.epoch, 1, qa.spin_ticks};
+      tile_steps<2, R, B, 1, VC, 0, false, false, false, BK, true>(qa.sims[0], qa.tiles[0], r, c, nc, par, halo, k,
+                                                                  cs, sm.two);
+    } else {
+      const ChunkSync cs{qa.flags[1], qa.epoch, 1, qa.spin_ticks};
+      tile_steps<3, R, B, 1, VC, 0, false, false, false, BK, true>(qa.sims[1], qa.tiles[1], r - qa.n_tiles[0], c, nc,
+                                                                  par, halo, k, cs, sm.three);
+    }
+  }
+}
+
+// launch (per_cu null) or occupancy query of the work-queue kernel: FP32
+// tiles of 128, 192 or 256 cells, FP64 of 128 or 256
+template <typename R, bool VC, bool BK>
+hipError_t launch_queue_r(int block, int grid, const QueueArgs &qa, int64_t n0, int parity, int halo, int k,
+                          int *per_cu, hipStream_t st) {
+  auto go = [&](auto kern) -> hipError_t {
+    if (per_cu) return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kern, block, 0);
+    kern<<<grid, block, 0, st>>>(qa, n0, parity, halo, k);
+    return hipGetLastError();
+  };
+  switch (block) {
+    case 128: return go(k_queue<R, 128, VC, BK>);
+    case 192:
+      if constexpr (sizeof(R) == 4) return go(k_queue<R, 192, VC, BK>);
+      break;
+    case 256: return go(k_queue<R, 256, VC, BK>);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <int N, bool BK>
 hipError_t launch_plain_n(const DevSim *sims, const DevTile *tiles, int n_tiles, int64_t n0, int parity,
                           hipStream_t st) {
@@ -1393,10 +1481,11 @@ hipError_t launch_plain_n(const DevSim *sims, const DevTile *tiles, int n_tiles,
 
 }  // namespace
 
-// The kernels are built in sixteen parts so that the library compiles them in
-// parallel: MB_PART - 1 = id with bit 0 FP64, bit 1 persistent tiles, bit 2 the
-// Cayley field step, bit 3 the block form; part 2 also holds the two-launch
-// kernels and the dispatch; without MB_PART all are built here.
+// The kernels are built in eighteen parts so that the library compiles them in
+// parallel: for parts 1..16, MB_PART - 1 = id with bit 0 FP64, bit 1
+// persistent tiles, bit 2 the Cayley field step, bit 3 the block form; part 2
+// also holds the two-launch kernels and the dispatch; parts 17 and 18 the
+// work-queue kernels (FP32, FP64); without MB_PART all are built here.
 #ifndef MB_PART
 #define MB_PART 0
 #endif
@@ -1405,6 +1494,11 @@ hipError_t launch_plain_n(const DevSim *sims, const DevTile *tiles, int n_tiles,
   int levels, int block, int lanes, bool vc, bool strong, const DevSim *sims, const DevTile *tiles, int n_tiles, \
       int64_t n0, int parity, int halo, int k, const ChunkSync &cs, int *per_cu, hipStream_t st
 #define MB_LAUNCH_PASS levels, block, lanes, vc, strong, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st
+
+hipError_t launch_queue_f32(int block, bool vc, bool bk, int grid, const QueueArgs &qa, int64_t n0, int parity,
+                            int halo, int k, int *per_cu, hipStream_t st);
+hipError_t launch_queue_f64(int block, bool vc, bool bk, int grid, const QueueArgs &qa, int64_t n0, int parity,
+                            int halo, int k, int *per_cu, hipStream_t st);
 
 #define MB_PART_DECLARE(ID) hipError_t launch_part_##ID(MB_LAUNCH_ARGS);
 MB_PART_DECLARE(0) MB_PART_DECLARE(1) MB_PART_DECLARE(2) MB_PART_DECLARE(3)
@@ -1563,6 +1657,44 @@ hipError_t launch_plain(int levels, bool bk, const DevSim *sims, const DevTile *
     case 8: return launch_plain_n<8, false>(sims, tiles, n_tiles, n0, parity, st);
   }
   return hipErrorInvalidValue;
+}
+#endif
+
+// the work-queue kernels: part 17 FP32, part 18 FP64
+#if MB_PART == 0 || MB_PART == 17
+hipError_t launch_queue_f32(int block, bool vc, bool bk, int grid, const QueueArgs &qa, int64_t n0, int parity,
+                            int halo, int k, int *per_cu, hipStream_t st) {
+  if (vc)
+    return bk ? launch_queue_r<float, true, true>(block, grid, qa, n0, parity, halo, k, per_cu, st)
+              : launch_queue_r<float, true, false>(block, grid, qa, n0, parity, halo, k, per_cu, st);
+  return bk ? launch_queue_r<float, false, true>(block, grid, qa, n0, parity, halo, k, per_cu, st)
+            : launch_queue_r<float, false, false>(block, grid, qa, n0, parity, halo, k, per_cu, st);
+}
+#endif
+#if MB_PART == 0 || MB_PART == 18
+hipError_t launch_queue_f64(int block, bool vc, bool bk, int grid, const QueueArgs &qa, int64_t n0, int parity,
+                            int halo, int k, int *per_cu, hipStream_t st) {
+  if (vc)
+    return bk ? launch_queue_r<double, true, true>(block, grid, qa, n0, parity, halo, k, per_cu, st)
+              : launch_queue_r<double, true, false>(block, grid, qa, n0, parity, halo, k, per_cu, st);
+  return bk ? launch_queue_r<double, false, true>(block, grid, qa, n0, parity, halo, k, per_cu, st)
+            : launch_queue_r<double, false, false>(block, grid, qa, n0, parity, halo, k, per_cu, st);
+}
+#endif
+#if MB_PART == 0 || MB_PART == 2
+hipError_t launch_queue(int precision, int block, bool vc, bool bk, int grid, const QueueArgs &qa, int64_t n0,
+                        int parity, int halo, int k, hipStream_t st) {
+  if (grid <= 0 || qa.n_chunks < 1 || k < 1 || k != halo || 3 * halo > block || k > kMaxChunk) return hipErrorInvalidValue;
+  return precision == 64 ? launch_queue_f64(block, vc, bk, grid, qa, n0, parity, halo, k, nullptr, st)
+                         : launch_queue_f32(block, vc, bk, grid, qa, n0, parity, halo, k, nullptr, st);
+}
+
+int queue_tiles_per_cu(int precision, int block, bool vc, bool bk) {
+  int per_cu = 0;
+  const QueueArgs qa{};
+  const hipError_t e = precision == 64 ? launch_queue_f64(block, vc, bk, 0, qa, 0, 0, 1, 1, &per_cu, nullptr)
+                                       : launch_queue_f32(block, vc, bk, 0, qa, 0, 0, 1, 1, &per_cu, nullptr);
+  return e == hipSuccess ? per_cu : 0;
 }
 #endif
 

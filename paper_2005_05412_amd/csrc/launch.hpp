@@ -37,4 +37,13 @@ int blocked_tiles_per_cu(int levels, int precision, int block, int lanes, bool v
 hipError_t launch_plain(int levels, bool bk, const DevSim *sims, const DevTile *tiles, int n_tiles,
                         int64_t n0, int parity, hipStream_t st);
 
+// Work-queue persistent launch of a two- and a three-level group (QueueArgs,
+// either group may be empty) with `grid` workgroups: one chunk of k = halo
+// steps per item, 3*halo <= block, one wave per 64 cells; FP32 tiles of 128,
+// 192 or 256 cells, FP64 of 128 or 256.  qa.counter must read zero.
+hipError_t launch_queue(int precision, int block, bool vc, bool bk, int grid, const QueueArgs &qa, int64_t n0,
+                        int parity, int halo, int k, hipStream_t st);
+// workgroups of the work-queue kernel one compute unit holds at once (0: none built)
+int queue_tiles_per_cu(int precision, int block, bool vc, bool bk);
+
 }  // namespace mb

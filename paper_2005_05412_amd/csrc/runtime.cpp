@@ -274,6 +274,7 @@ int Engine::init(std::string &err) {
   if (hipGetDeviceProperties(&prop, device_) == hipSuccess && prop.multiProcessorCount > 0)
     n_cu_ = prop.multiProcessorCount;
   if (const char *v = std::getenv("MB_PERSIST")) persist_ = std::string(v) != "0";
+  if (const char *v = std::getenv("MB_QUEUE")) queue_ = std::string(v) != "0";
   int clock_khz = 0;
   if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, device_) != hipSuccess || clock_khz <= 0)
     persist_ = false;
@@ -522,7 +523,7 @@ hipError_t Engine::upload_group(Group &g, hipStream_t st) {
     g.d_flags = nullptr;
     g.cap_tiles = std::max<int>(int(ht.size()), 2 * g.cap_tiles);
     if (hipMalloc(&g.d_tiles, size_t(g.cap_tiles) * sizeof(DevTile)) != hipSuccess) return hipErrorOutOfMemory;
-    if (hipMalloc(&g.d_flags, size_t(g.cap_tiles) * sizeof(uint32_t)) != hipSuccess) return hipErrorOutOfMemory;
+    if (hipMalloc(&g.d_flags, size_t(g.cap_tiles + 1) * sizeof(uint32_t)) != hipSuccess) return hipErrorOutOfMemory;
   }
   hipError_t e = hipSuccess;
   if (!hs.empty()) e = hipMemcpyAsync(g.d_sims, hs.data(), hs.size() * sizeof(DevSim), hipMemcpyHostToDevice, st);
@@ -589,7 +590,70 @@ hipError_t Engine::launch_group(Group &g, hipStream_t st, int k, int reps, int64
   return hipSuccess;
 }
 
-bool Engine::persist_ok(int k, int64_t reps) {
+bool Engine::persist_ok(int k, int64_t reps) { return persist_form(k, reps) != 0; }
+
+int Engine::persist_form(int k, int64_t reps) { return flags_ok(k, reps) ? 1 : queue_ok(k, reps) ? 2 : 0; }
+
+bool Engine::queue_ok(int k, int64_t reps) {
+  if (!persist_ || !queue_ || variant_ == MB_VARIANT_PLAIN || reps < 2 || k != halo_ || 3 * halo_ > block_ || dirty_)
+    return false;
+  const Group *two = nullptr, *three = nullptr;
+  for (auto &g : groups_) {
+    if (g.members.empty()) continue;
+    if (g.strong || g.cayley || (g.levels != 2 && g.levels != 3) || group_lanes(g) != 1 || !g.d_flags) return false;
+    const Group *&slot = g.levels == 2 ? two : three;
+    if (slot) return false;
+    slot = &g;
+  }
+  if (!two && !three) return false;
+  if (two && three && two->bk != three->bk) return false;
+  const bool bk = two ? two->bk : three->bk;
+  if (q_block_ != block_ || q_vc_ != int(vc_) || q_bk_ != int(bk)) {
+    q_block_ = block_;
+    q_vc_ = int(vc_);
+    q_bk_ = int(bk);
+    q_per_cu_ = queue_tiles_per_cu(precision_, block_, vc_, bk);
+  }
+  return q_per_cu_ > 0;
+}
+
+hipError_t Engine::run_queue(hipStream_t st, int k, int64_t reps) {
+  Group *two = nullptr, *three = nullptr;
+  for (auto &g : groups_)
+    if (!g.members.empty()) (g.levels == 2 ? two : three) = &g;
+  Group *first = two ? two : three;
+  const int64_t per_chunk = int64_t(two ? two->n_tiles : 0) + int64_t(three ? three->n_tiles : 0);
+  // items of one launch stay below 2^31
+  const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(kMaxPersistChunks, (int64_t(1) << 31) / std::max<int64_t>(1, per_chunk)));
+  const int grid = int(std::min<int64_t>(int64_t(q_per_cu_) * n_cu_, per_chunk * std::min<int64_t>(reps, cap)));
+  hipError_t e = hipSuccess;
+  while (reps > 0 && e == hipSuccess) {
+    const int n = int(std::min<int64_t>(reps, cap));
+    QueueArgs qa{};
+    qa.sims[0] = two ? two->d_sims : nullptr;
+    qa.tiles[0] = two ? two->d_tiles : nullptr;
+    qa.flags[0] = two ? two->d_flags : nullptr;
+    qa.n_tiles[0] = two ? two->n_tiles : 0;
+    qa.sims[1] = three ? three->d_sims : nullptr;
+    qa.tiles[1] = three ? three->d_tiles : nullptr;
+    qa.flags[1] = three ? three->d_flags : nullptr;
+    qa.n_tiles[1] = three ? three->n_tiles : 0;
+    qa.counter = first->d_flags + first->n_tiles;
+    qa.epoch = epoch_;
+    qa.n_chunks = n;
+    qa.spin_ticks = spin_ticks_;
+    e = fill_u32(qa.counter, 1, 0u, st);
+    if (e == hipSuccess)
+      e = launch_queue(precision_, block_, vc_, first->bk, grid, qa, n0_, parity_, halo_, k, st);
+    if (e != hipSuccess) return e;
+    epoch_ += uint32_t(n);
+    for (int r = 0; r < n; ++r) commit_chunk(k);
+    reps -= n;
+  }
+  return e;
+}
+
+bool Engine::flags_ok(int k, int64_t reps) {
   if (!persist_ || variant_ == MB_VARIANT_PLAIN || reps < 2 || k != halo_ || 3 * halo_ > block_ || dirty_)
     return false;
   Group *live = nullptr;
@@ -612,7 +676,9 @@ bool Engine::persist_ok(int k, int64_t reps) {
 hipError_t Engine::run_persistent(hipStream_t st, int k, int64_t reps) {
   hipError_t e = sync_tables(st);
   if (e != hipSuccess) return e;
-  if (!persist_ok(k, reps)) return hipErrorInvalidValue;
+  const int form = persist_form(k, reps);
+  if (form == 2) return run_queue(st, k, reps);
+  if (form != 1) return hipErrorInvalidValue;
   Group *g = nullptr;
   for (auto &q : groups_)
     if (!q.members.empty()) g = &q;
@@ -639,7 +705,7 @@ TableSpan table_span(size_t at, size_t n_sims, size_t n_tiles) {
   t.sims = align_up(at);
   t.tiles = align_up(t.sims + n_sims * sizeof(DevSim));
   t.flags = align_up(t.tiles + n_tiles * sizeof(DevTile));
-  t.end = t.flags + n_tiles * sizeof(uint32_t);
+  t.end = t.flags + (n_tiles + 1) * sizeof(uint32_t);  // flags and the work-queue counter
   return t;
 }
 }  // namespace

@@ -81,13 +81,18 @@ class Engine {
   // Uploads group tables if membership changed (synchronous copy).
   hipError_t sync_tables(hipStream_t st);
 
-  // Whether reps chunks of k steps can run as persistent launches: one group
-  // of simulations, k equal to the halo, every tile resident at once, not
-  // switched off (MB_PERSIST=0).  Tables must be current.
+  // Whether reps chunks of k steps can run as persistent launches (k equal to
+  // the halo, not switched off by MB_PERSIST=0): one group whose tiles are all
+  // resident at once (neighbour flags, each tile runs every chunk), or else
+  // a two-level and/or a three-level group of weak coupling and the exact
+  // field step with one wave per 64 cells on a tile with a work-queue kernel
+  // (MB_QUEUE=0 switches that form off).  Tables must be current.
   bool persist_ok(int k, int64_t reps);
   // reps chunks of k steps as persistent launches (at most kMaxPersistChunks
   // chunks each); asynchronous, not capturable into graphs
   hipError_t run_persistent(hipStream_t st, int k, int64_t reps);
+  // the form persist_ok found: 1 neighbour flags, 2 work queue, 0 none
+  int persist_form(int k, int64_t reps);
   // allows (on) or forbids persistent launches (MB_PERSIST=0 forbids them regardless)
   void set_persist(bool on) { persist_ = persist_ && on; }
   static constexpr int kMaxPersistChunks = 4096;
@@ -152,7 +157,9 @@ class Engine {
     std::vector<int> members;
     DevSim *d_sims = nullptr;
     DevTile *d_tiles = nullptr;
-    uint32_t *d_flags = nullptr;  // per tile: epoch of the last finished chunk (persistent launches)
+    // per tile: epoch of the last finished chunk (persistent launches), then
+    // one more word: the item counter of a work-queue launch
+    uint32_t *d_flags = nullptr;
     int n_tiles = 0, cap_sims = 0, cap_tiles = 0;
     int occ_block = 0, occ_lanes = 0, occ_per_cu = 0;  // cached occupancy of the group's kernel
   };
@@ -161,6 +168,9 @@ class Engine {
   void build_tables(const Group &g, std::vector<DevSim> &hs, std::vector<DevTile> &ht) const;
   hipError_t launch_group(Group &g, hipStream_t st, int k, int reps, int64_t step_off = 0, int par_off = 0);
   int group_lanes(const Group &g) const;
+  bool flags_ok(int k, int64_t reps);
+  bool queue_ok(int k, int64_t reps);
+  hipError_t run_queue(hipStream_t st, int k, int64_t reps);
 
   int device_, precision_, variant_, block_, halo_;
   bool vc_ = false;
@@ -181,6 +191,8 @@ class Engine {
   int64_t n0_ = 0;
   int parity_ = 0;
   bool persist_ = true;        // persistent launches allowed
+  bool queue_ = true;          // work-queue persistent launches allowed
+  int q_block_ = 0, q_vc_ = -1, q_bk_ = -1, q_per_cu_ = 0;  // cached occupancy of the work-queue kernel
   uint32_t epoch_ = 0;         // chunk epoch of the next persistent launch
   int64_t spin_ticks_ = 0;     // device wall-clock ticks of a neighbour wait before giving up
   double cell_updates_ = 0;

@@ -222,6 +222,74 @@ def test_lambda3_full_run_vs_stored_oracle_records():
     assert len(driven_probes) >= 20, sorted(driven_probes)
 
 
+def _uneven_sweep(n_sims, n_steps0, step, nx_range, precision=32):
+    """Sweep members (even index two levels, odd three) of uneven lengths."""
+    sims = W.sweep(n_sims=n_sims, n_steps=n_steps0 + step * n_sims, precision=precision, nx_range=nx_range)
+    for k, p in enumerate(sims):
+        p["n_steps"] = n_steps0 + step * k
+    return sims
+
+
+def _batch_records(sims, precision, queue, **shape):
+    if not queue:
+        os.environ["MB_QUEUE"] = "0"
+    try:
+        b = mb.Batch([dict(p, precision=precision) for p in sims], precision=precision, **shape)
+        mode = b.run_mode()
+        b.run(use_graph=False)
+        recs = [b.records(k) for k in range(len(sims))]
+        b.close()
+    finally:
+        os.environ.pop("MB_QUEUE", None)
+    return mode, recs
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_mixed_level_uneven_batch_in_one_work_queue_launch(precision):
+    """Many uneven-length simulations of two and three levels in one persistent launch:
+    the batch's full chunks run as one work-queue launch (each workgroup takes (chunk,
+    tile) items of either level count until none is left), with results bit for bit
+    those of one launch per chunk and level count; two members (one of each level count)
+    against the oracle: FP64 within 1e-10, FP32 within 1e-4 per trace."""
+    sims = _uneven_sweep(24, 1000, 90, (300, 4000))
+    _say(f"work-queue batch fp{precision}")
+    shape = dict(block=256, depth=32, lanes=1)
+    mode_q, rec_q = _batch_records(sims, precision, True, **shape)
+    mode_c, rec_c = _batch_records(sims, precision, False, **shape)
+    assert (mode_q, mode_c) == ("queue", "chunks")
+    for a, b in zip(rec_q, rec_c):
+        assert_same(a, b)
+    small = sorted(range(len(sims)), key=lambda k: sims[k]["nx"] * sims[k]["n_steps"])
+    for k in (next(k for k in small if k % 2 == 0), next(k for k in small if k % 2 == 1)):
+        ref = O.run(dict(sims[k], precision=64))
+        errs = trace_errors(sims[k], rec_q[k], ref)
+        _say(f"work-queue member {k} nx={sims[k]['nx']} steps={sims[k]['n_steps']} {worst(errs)}")
+        assert max(errs.values()) <= TOL[precision], (k, worst(errs))
+
+
+def test_single_grid_beyond_residency_takes_the_work_queue():
+    """A three-level grid of 3e6 cells has more 256-cell tiles than the device holds at
+    once: the neighbour-flag persistent form does not apply, the work-queue form does,
+    and gives the bits of one launch per chunk."""
+    prob = W.lambda3(nx=3_000_000, n_steps=256, precision=32)
+    prob["records"] = prob["records"][:12]
+    _say("work-queue single grid")
+    out = {}
+    for queue in (True, False):
+        if not queue:
+            os.environ["MB_QUEUE"] = "0"
+        try:
+            s = mb.Solver(prob, precision=32, variant="blocked", block=256, depth=32, lanes=1)
+            mode = s.persistent()
+            s.run()
+            out[queue] = (mode, s.records())
+            s.close()
+        finally:
+            os.environ.pop("MB_QUEUE", None)
+    assert out[True][0] and not out[False][0]
+    assert_same(out[True][1], out[False][1])
+
+
 @pytest.mark.parametrize("precision", [64, 32])
 def test_sweep_members_full_length_vs_stored_oracle_records(precision):
     """The 256-member sweep as one batch; its 8 seeded spot-check members over their full
