@@ -581,6 +581,8 @@ def main(argv=None):
                    "step": "one full solve of the workload"},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK["fp32_tflops"],
                      "unit": "TFLOP/s", "frac": achieved_tflops / PEAK["fp32_tflops"], "traffic": traffic,
+                     # the kernels issue unpacked FP32 (packed FP32 is disabled): their own ceiling
+                     "frac_of_unpacked_fp32": achieved_tflops / PEAK["fp64_tflops"],
                      "traffic_unit": "bytes per launch (HBM, counter-measured)",
                      "kernel": kname, "avg_kernel_us": avg_kernel_us, "persistent": persistent,
                      "launches_per_solve": n_launch, "steps_per_launch": steps_per_launch,
@@ -665,6 +667,27 @@ def main(argv=None):
                                                 "flags": "persistent launches with neighbour flags",
                                                 "chunks": "one kernel per level count and chunk, replayed from a HIP graph"}[bmode]}
         bt.close()
+        # the same sweep as one work-queue persistent launch on the tuned tile
+        log("[bench] batched sweep as one work-queue launch")
+        os.environ["MB_QUEUE"] = "1"
+        try:
+            bq = mb.Batch(sims, precision=32, variant="blocked_regs" if bregs else "blocked", block=bblock,
+                          depth=bdepth, lanes=1)
+        finally:
+            os.environ.pop("MB_QUEUE", None)
+        qmode = bq.run_mode()
+        bq.run(stream=stream)
+        hip.sync()
+        bq.reset(stream)
+        hip.sync()
+        t0 = time.perf_counter()
+        bq.run(stream=stream)
+        hip.sync()
+        tq = time.perf_counter() - t0
+        bq.close()
+        out["batched_sweep_one_launch"] = {"value": bcells / tq, "unit": "cell-updates/s", "wall_s": tq,
+                                           "launch_form": qmode, "block": bblock, "depth": bdepth,
+                                           "regs": bregs}
         if not args.no_sub32:
             out["batched_sweep_sub32"] = sweep_sub_batch(hip, stream, sims[:32], log)
 

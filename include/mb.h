@@ -390,7 +390,8 @@ int mb_batch_reset(mb_batch *b, void *hip_stream);
  * cells on tiles of 128, 192 (FP32) or 256 cells: each workgroup takes
  * (chunk, tile) items in chunk-major order from a counter and waits for the
  * tile's and its neighbours' previous chunk, so the tiles need not all be
- * resident; MB_QUEUE=0 disables it), 0 one launch per chunk and level count;
+ * resident; taken when MB_QUEUE=1 is set in the environment at set-up), 0 one
+ * launch per chunk and level count;
  * negative on error.  Uploads pending tables (synchronously). */
 int mb_batch_run_mode(mb_batch *b);
 /* Tile shape in use (as mb_shape; tuned over the whole batch). */

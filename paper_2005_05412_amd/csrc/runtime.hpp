@@ -86,7 +86,7 @@ class Engine {
   // resident at once (neighbour flags, each tile runs every chunk), or else
   // a two-level and/or a three-level group of weak coupling and the exact
   // field step with one wave per 64 cells on a tile with a work-queue kernel
-  // (MB_QUEUE=0 switches that form off).  Tables must be current.
+  // (with MB_QUEUE=1 set at set-up).  Tables must be current.
   bool persist_ok(int k, int64_t reps);
   // reps chunks of k steps as persistent launches (at most kMaxPersistChunks
   // chunks each); asynchronous, not capturable into graphs
@@ -191,7 +191,7 @@ class Engine {
   int64_t n0_ = 0;
   int parity_ = 0;
   bool persist_ = true;        // persistent launches allowed
-  bool queue_ = true;          // work-queue persistent launches allowed
+  bool queue_ = false;         // work-queue persistent launches allowed (MB_QUEUE=1)
   int q_block_ = 0, q_vc_ = -1, q_bk_ = -1, q_per_cu_ = 0;  // cached occupancy of the work-queue kernel
   uint32_t epoch_ = 0;         // chunk epoch of the next persistent launch
   int64_t spin_ticks_ = 0;     // device wall-clock ticks of a neighbour wait before giving up

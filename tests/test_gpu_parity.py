@@ -231,8 +231,8 @@ def _uneven_sweep(n_sims, n_steps0, step, nx_range, precision=32):
 
 
 def _batch_records(sims, precision, queue, **shape):
-    if not queue:
-        os.environ["MB_QUEUE"] = "0"
+    if queue:
+        os.environ["MB_QUEUE"] = "1"
     try:
         b = mb.Batch([dict(p, precision=precision) for p in sims], precision=precision, **shape)
         mode = b.run_mode()
@@ -276,8 +276,8 @@ def test_single_grid_beyond_residency_takes_the_work_queue():
     _say("work-queue single grid")
     out = {}
     for queue in (True, False):
-        if not queue:
-            os.environ["MB_QUEUE"] = "0"
+        if queue:
+            os.environ["MB_QUEUE"] = "1"
         try:
             s = mb.Solver(prob, precision=32, variant="blocked", block=256, depth=32, lanes=1)
             mode = s.persistent()
