@@ -110,8 +110,10 @@ struct DevSim {
   int32_t *status;           // kStatus* bits
   int32_t rec_every;         // gcd of the record intervals (1 when there are no records)
   int32_t cayley;            // field part by the Cayley approximant (MB_FIELD_CAYLEY)
-  // strong coupling: (n3D/dt) tr{mu rho^n} per cell (FP64 ping-pong like x) and per
-  // material its readout (qc, aq[M], aqs[K]) from the state and the field increments
+  // strong coupling: (n3D/dt) tr{mu rho^n} per cell (FP64 ping-pong like x), each
+  // buffer followed two planes on by the cell's last polarization current (the
+  // start of the next step's field iteration), and per material the readout
+  // (qc, aq[M], aqs[K]) from the state and the field increments
   double *qs[2];
   const double *qtab;
 };

@@ -18,7 +18,12 @@ namespace {
 
 constexpr int kTileSources = 4;  // sources per tile staged in LDS
 constexpr int kMaxChunk = 256;   // steps per blocked launch
-constexpr int kStrongIters = 3;  // fixed-point iterations of a strong-coupling E update
+// fixed-point iterations of a strong-coupling E update, started from the
+// cell's previous polarization current: each iteration gains about 4.5
+// decimal digits on the Lambda workload (oracle: 4e-3, 2e-7, 9e-12, 5e-16
+// relative changes from a zero start), so two reach FP32 and three FP64
+template <typename R>
+constexpr int strong_iters() { return sizeof(R) == 4 ? 2 : 3; }
 
 // Neighbour values within one wave by DPP wavefront shifts (lane l receives
 // lane l+1, respectively l-1; the lane at the end of the wave receives 0).
@@ -266,8 +271,11 @@ struct Cell {
   // pair (q, q+1) turns by u/conj(u), u = 1 + x_q x_{q+1} + i (x_q - x_{q+1}):
   // cos - 1 = -2 d^2/|u|^2 and sin = 2 s d/|u|^2 with d = x_q - x_{q+1} and
   // s = 1 + x_q x_{q+1} (no cancellation for small angles).
+  static constexpr int PA = P > 0 ? P : 1;
+
+  // (cos - 1, sin) of every pair's angle, pair index k(k-1)/2 + j
   template <typename C>
-  static __device__ __forceinline__ void increments(R (&z)[KA], R e, const C &mt, bool cay = false) {
+  static __device__ __forceinline__ void pair_phases(R e, const C &mt, bool cay, R (&pcq)[PA], R (&psq)[PA]) {
     if constexpr (N >= 2) {
       R cm[N - 1], sn[N - 1];
       if (cay) {
@@ -296,12 +304,38 @@ struct Cell {
             pc = nc;
             ps = ns;
           }
-          const int ir = 2 * (k * (k - 1) / 2 + j), ii = ir + 1;
-          const R re = z[ir], im = z[ii];
-          z[ir] = fma(re, pc, -(im * ps));
-          z[ii] = fma(re, ps, im * pc);
+          pcq[k * (k - 1) / 2 + j] = pc;
+          psq[k * (k - 1) / 2 + j] = ps;
         }
       }
+    }
+  }
+
+  // z <- d = (e^{i theta_jk} - 1) z_jk with the pairs' (cos - 1, sin)
+  static __device__ __forceinline__ void rotate_by(R (&z)[KA], const R (&pcq)[PA], const R (&psq)[PA]) {
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const R re = z[2 * q], im = z[2 * q + 1];
+      z[2 * q] = fma(re, pcq[q], -(im * psq[q]));
+      z[2 * q + 1] = fma(re, psq[q], im * pcq[q]);
+    }
+  }
+
+  // z <- d = (e^{i theta_jk} - 1) z_jk: the change of eigenbasis coherence
+  // (j, k), j < k, under the field conjugation, theta_jk = dt E (lam_j -
+  // lam_k)/hbar, the sum of the consecutive angles E kappa_q; each phase is
+  // carried as (cos - 1, sin), so the increment has no cancellation.
+  // cay: the Cayley approximant of the field exponential instead: level j's
+  // factor (1 + i x_j)/(1 - i x_j), x_j = E sigma_j / 2, so the consecutive
+  // pair (q, q+1) turns by u/conj(u), u = 1 + x_q x_{q+1} + i (x_q - x_{q+1}):
+  // cos - 1 = -2 d^2/|u|^2 and sin = 2 s d/|u|^2 with d = x_q - x_{q+1} and
+  // s = 1 + x_q x_{q+1} (no cancellation for small angles).
+  template <typename C>
+  static __device__ __forceinline__ void increments(R (&z)[KA], R e, const C &mt, bool cay = false) {
+    if constexpr (N >= 2) {
+      R pcq[PA], psq[PA];
+      pair_phases(e, mt, cay, pcq, psq);
+      rotate_by(z, pcq, psq);
     }
   }
 
@@ -806,6 +840,10 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
   R xc[CL::CA];     // FP32: the compensation of the owned state entries
   R z[CL::KA];      // eigenbasis coherences of x, then the field increments d
   double qn = 0.0;  // strong coupling: (n3D/dt) tr{mu rho^n} of the cell, carried in FP64
+  R pprev = 0;      // strong coupling: the cell's last polarization current
+  // strong coupling: tr{mu rho^{n+1}} as a function of the field angle,
+  // sA + sum_q (sal_q (cos - 1) + sbe_q sin) over the pairs q
+  double sA = 0.0, sal[ST ? CL::PA : 1], sbe[ST ? CL::PA : 1];
 
   // density rows of this wave group published for the other groups (L > 1);
   // they are read after the next step's E exchange barrier
@@ -868,7 +906,10 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
       }
     }
     if constexpr (ST) {
-      if (qm) qn = ld(sim.qs[par] + c);
+      if (qm) {
+        qn = ld(sim.qs[par] + c);
+        pprev = R(ld(sim.qs[par] + 2 * nx + c));
+      }
     }
     if (hleft) hl = ld(h_in + c - 1);
     for (int t = 0; t < n_ts; ++t)
@@ -910,24 +951,35 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
       if constexpr (ST && N > 0) {
         // strong coupling: the E update of an interior quantum cell depends on
         // rho^{n+1}, driven by (E^n + E^{n+1})/2; fixed-point iteration from the
-        // field without polarization
+        // cell's previous polarization current.  The FP64 readout qt of (x, d),
+        // d_q = (e^{i theta_q} - 1) z_q, is written out per pair once per step,
+        // so an iteration costs the phases and 2 FP64 multiply-adds per pair.
         per_material([&](const auto &mt, int mm) {
           const cptr<double> qt = kconst<double>(sim.qtab) + __builtin_amdgcn_readfirstlane(mm * ro_len(N));
           CL::coherences(x, z, mt);
-          R pi = 0;
-          for (int it = 0; it < kStrongIters; ++it) {
+          sA = qt[0];
+#pragma unroll
+          for (int t = 0; t < M; ++t) sA = fma(qt[1 + t], double(x[t]), sA);
+#pragma unroll
+          for (int q = 0; q < CL::P; ++q) {
+            const double zr = double(z[2 * q]), zi = double(z[2 * q + 1]);
+            const double qr = qt[1 + M + 2 * q], qi = qt[2 + M + 2 * q];
+            sal[q] = fma(qr, zr, qi * zi);
+            sbe[q] = fma(qi, zr, -(qr * zi));
+          }
+          R pi = pprev;
+          for (int it = 0; it < strong_iters<R>(); ++it) {
             const R es = fma(cbd, h - hl, fma(ca, e, -(cbg * pi)));
-            R dv[CL::KA];
+            R pcq[CL::PA], psq[CL::PA];
+            CL::pair_phases(R(0.5) * (e + es), mt, cay, pcq, psq);
+            double tq = sA;
 #pragma unroll
-            for (int a = 0; a < CL::KA; ++a) dv[a] = z[a];
-            CL::increments(dv, R(0.5) * (e + es), mt, cay);
-            double tq = qt[0];
-#pragma unroll
-            for (int t = 0; t < M + CL::K; ++t) tq = fma(qt[1 + t], double(CL::xd(x, dv, t)), tq);
+            for (int q = 0; q < CL::P; ++q) tq = fma(sal[q], double(pcq[q]), fma(sbe[q], double(psq[q]), tq));
             pi = R(tq - qn);
           }
           p = pi;
         });
+        pprev = p;
       } else if constexpr (N > 0) {
         auto finish = [&](const auto &mt, int mm) {
           CL::increments(z, e, mt, cay);
@@ -995,12 +1047,13 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
         // rho^{n+1} with the final E^{n+1}: rotation by the midpoint field, the
         // new tr{mu rho}, records of rho^{n+1}, propagation of the running state
         per_material([&](const auto &mt, int mm) {
-          const cptr<double> qt = kconst<double>(sim.qtab) + __builtin_amdgcn_readfirstlane(mm * ro_len(N));
-          CL::increments(z, R(0.5) * (eo + e), mt, cay);
-          double tq = qt[0];
+          R pcq[CL::PA], psq[CL::PA];
+          CL::pair_phases(R(0.5) * (eo + e), mt, cay, pcq, psq);
+          double tq = sA;
 #pragma unroll
-          for (int t = 0; t < M + CL::K; ++t) tq = fma(qt[1 + t], double(CL::xd(x, z, t)), tq);
+          for (int q = 0; q < CL::P; ++q) tq = fma(sal[q], double(pcq[q]), fma(sbe[q], double(psq[q]), tq));
           qn = tq;
+          CL::rotate_by(z, pcq, psq);
           if (rec_step) {
             if (rec_here) {
               if (rec_lds) {
@@ -1052,7 +1105,10 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
             for (int a = 0; a < M; ++a)
               if (SP::owns(SUB, a)) st(x_out + (M + a) * nx + c, xc[a]);
           }
-          if constexpr (ST) st(sim.qs[par ^ 1] + c, qn);
+          if constexpr (ST) {
+            st(sim.qs[par ^ 1] + c, qn);
+            st(sim.qs[par ^ 1] + 2 * nx + c, double(pprev));
+          }
         }
       }
       if (SUB == 0 && (!isfinite(double(e)) || !isfinite(double(h)))) atomicOr(sim.status, kStatusNonFinite);

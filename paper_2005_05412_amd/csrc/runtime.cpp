@@ -45,7 +45,7 @@ Layout layout_of(const SimPlan &p, int precision, bool plain) {
   L.mat_h = take(nx);
   L.mtab = take(p.mats.size() * size_t(stride_of(p.n, p.block_form)) * rs);
   const bool strong = p.coupling == MB_COUPLING_STRONG && p.n > 0;
-  L.qs = take(strong ? 2 * nx * sizeof(double) : sizeof(double));
+  L.qs = take(strong ? 4 * nx * sizeof(double) : sizeof(double));  // tr{mu rho} x 2, then p x 2
   L.init_q = take(strong ? nx * sizeof(double) : sizeof(double));
   L.qtab = take(strong ? p.mats.size() * size_t(ro_len(p.n)) * sizeof(double) : sizeof(double));
   L.src = take(std::max<size_t>(1, p.sources.size()) * sizeof(DevSource));
@@ -135,7 +135,10 @@ void fill_state(const SimPlan &p, char *head, const Layout &L) {
   if (p.coupling == MB_COUPLING_STRONG && p.n > 0) {
     double *qs = reinterpret_cast<double *>(head + L.qs);
     double *iq = reinterpret_cast<double *>(head + L.init_q);
-    for (size_t c = 0; c < nx; ++c) qs[c] = qs[nx + c] = iq[c] = p.q0[c];
+    for (size_t c = 0; c < nx; ++c) {
+      qs[c] = qs[nx + c] = iq[c] = p.q0[c];
+      qs[2 * nx + c] = qs[3 * nx + c] = 0.0;  // no polarization current before the first step
+    }
     double *qt = reinterpret_cast<double *>(head + L.qtab);
     const size_t rl = size_t(ro_len(p.n)), k = size_t(mat_k(p.n));
     for (size_t i = 0; i < p.mats.size(); ++i) {
@@ -847,6 +850,8 @@ hipError_t Engine::reset(hipStream_t st) {
         e = hipMemsetAsync(static_cast<char *>(s.ds.x[b]) + m * nx * rs, 0, m * nx * rs, st);
       if (e == hipSuccess && s.plan.coupling == MB_COUPLING_STRONG && m)
         e = hipMemcpyAsync(s.ds.qs[b], s.block + s.init_q, nx * sizeof(double), hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess && s.plan.coupling == MB_COUPLING_STRONG && m)
+        e = hipMemsetAsync(s.ds.qs[b] + 2 * nx, 0, nx * sizeof(double), st);
     }
     if (e == hipSuccess && s.bytes > s.out_begin) e = hipMemsetAsync(s.block + s.out_begin, 0, s.bytes - s.out_begin, st);
     if (e == hipSuccess) e = hipMemsetAsync(s.ds.status, 0, sizeof(int32_t), st);
