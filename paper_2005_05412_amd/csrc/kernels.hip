@@ -174,22 +174,29 @@ struct Split {
   static constexpr int K = mat_k(N);
   static constexpr int P = N > 0 ? N * (N - 1) / 2 : 0;
   static constexpr int NP = N > 0 ? N - 1 : 0;
+  static constexpr int kItems = 2 * P + NP;
   // item u < P: z pair u; P + a: population row a; P + NP + r: rows of pair r
-  static constexpr int owner(int item) {
-    if (L == 1) return 0;
+  struct Table {
+    int who[kItems > 0 ? kItems : 1];
+  };
+  static constexpr Table make_table() {
+    Table t{};
     int load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int who = 0;
-    for (int u = 0; u <= item; ++u) {
+    for (int u = 0; u < kItems; ++u) {
       const int cost = u < P ? (BK ? NP + 2 * P : 2 * M) : u < P + NP ? (BK ? NP : M + K) : (BK ? 2 * P + 4 : 2 * (M + K));
       int best = 0;
       for (int g = 1; g < L; ++g)
         if (load[g] < load[best]) best = g;
       load[best] += cost;
-      who = best;
+      t.who[u] = best;
     }
-    return who;
+    return t;
   }
+  static constexpr Table kTable = make_table();
+  static constexpr int owner(int item) { return L == 1 ? 0 : kTable.who[item]; }
   static constexpr int row_item(int a) { return a < NP ? P + a : P + NP + (a - NP) / 2; }
+  // sub: the wave group (a constant, or a wave-uniform value for kernels
+  // whose wave groups share one copy of the code)
   static constexpr bool owns(int sub, int a) { return L == 1 || owner(row_item(a)) == sub; }
   static constexpr bool owns_z(int sub, int r) { return L == 1 || owner(r / 2) == sub; }
   static constexpr bool owns_pop(int sub) {
@@ -233,12 +240,12 @@ struct Cell {
   // eigenbasis (with L > 1 the rows of the pairs owned by group SUB); in the
   // block form Re z from the populations and the real parts of x, Im z from
   // the imaginary parts
-  template <int L = 1, int SUB = 0, typename C>
-  static __device__ __forceinline__ void coherences(const R (&x)[MA], R (&z)[KA], const C &mt) {
+  template <int L = 1, typename C>
+  static __device__ __forceinline__ void coherences(const R (&x)[MA], R (&z)[KA], const C &mt, int sub = 0) {
     if constexpr (BK) {
 #pragma unroll
       for (int q = 0; q < P; ++q) {
-        if (!Split<N, L, BK>::owns_z(SUB, 2 * q)) continue;
+        if (!Split<N, L, BK>::owns_z(sub, 2 * q)) continue;
         R zr = mt[bk_t0(N) + q], zi = R(0);
 #pragma unroll
         for (int a = 0; a < NP; ++a) zr = fma(mt[bk_tp(N) + q * NP + a], x[a], zr);
@@ -253,7 +260,7 @@ struct Cell {
     } else {
 #pragma unroll
       for (int r = 0; r < K; ++r) {
-        if (!Split<N, L, BK>::owns_z(SUB, r)) continue;
+        if (!Split<N, L, BK>::owns_z(sub, r)) continue;
         R acc = mt[coef_t0(N) + r];
 #pragma unroll
         for (int j = 0; j < M; ++j) acc = fma(mt[coef_tm(N) + r * M + j], x[j], acc);
@@ -357,12 +364,13 @@ struct Cell {
   // (A S)_i d); with L > 1 the rows owned by group SUB (the others are left
   // as they are).  Block form: y = x + S d by its real and imaginary parts,
   // then x <- y + (bfp + ap y) on the populations and y + b y on each pair.
-  template <int L = 1, int SUB = 0, typename C>
-  static __device__ __forceinline__ void propagate(R (&x)[MA], R (&xc)[CA], const R (&d)[KA], const C &mt) {
+  template <int L = 1, typename C>
+  static __device__ __forceinline__ void propagate(R (&x)[MA], R (&xc)[CA], const R (&d)[KA], const C &mt,
+                                                   int sub = 0) {
     using SP = Split<N, L, BK>;
     if constexpr (BK) {
       // each row gains x + (increment): the small terms are summed on their own
-      if constexpr (SP::owns_pop(SUB)) {
+      if (SP::owns_pop(sub)) {
         R dp[NP > 0 ? NP : 1], yp[NP > 0 ? NP : 1];
 #pragma unroll
         for (int a = 0; a < NP; ++a) {
@@ -374,7 +382,7 @@ struct Cell {
         }
 #pragma unroll
         for (int a = 0; a < NP; ++a) {
-          if (!SP::owns(SUB, a)) continue;
+          if (!SP::owns(sub, a)) continue;
           R acc = mt[bk_bf(N) + a];
 #pragma unroll
           for (int b = 0; b < NP; ++b) acc = fma(mt[bk_ap(N) + a * NP + b], yp[b], acc);
@@ -383,7 +391,7 @@ struct Cell {
       }
 #pragma unroll
       for (int r = 0; r < P; ++r) {
-        if (!SP::owns(SUB, NP + 2 * r)) continue;
+        if (!SP::owns(sub, NP + 2 * r)) continue;
         R dr = R(0), di = R(0);
 #pragma unroll
         for (int q = 0; q < P; ++q) {
@@ -400,7 +408,7 @@ struct Cell {
       R inc[MA];
 #pragma unroll
       for (int i = 0; i < M; ++i) {
-        if (!SP::owns(SUB, i)) continue;
+        if (!SP::owns(sub, i)) continue;
         R acc = mt[coef_bf(N) + i];
 #pragma unroll
         for (int t = 0; t < M + K; ++t) acc = fma(mt[coef_am(N) + i * (M + K) + t], xd(x, d, t), acc);
@@ -408,7 +416,7 @@ struct Cell {
       }
 #pragma unroll
       for (int i = 0; i < M; ++i)
-        if (SP::owns(SUB, i)) add_inc(x[i], xc, i, inc[i]);
+        if (SP::owns(sub, i)) add_inc(x[i], xc, i, inc[i]);
     }
   }
 
@@ -641,6 +649,18 @@ __device__ __forceinline__ bool neighbours_reached(const ChunkSync &cs, const De
   }
 }
 
+// wave groups (L > 1) that share one copy of the step code, the group being a
+// wave-uniform run-time value: six or more levels in the general form, whose
+// step (thousands of instructions) is too long for a copy per group to stay
+// in the instruction cache (six-level QCL-like FP32 with a copy per group:
+// 32 and 300 us per step with 2 and 4 groups against 11.9 us with one; with
+// one shared copy 10.7 and 7.7 us).  Five levels keep a copy per group: the
+// comb's 4-group tiles take 3.2 us per step so, 5.5 us with a shared copy.
+template <int N, int L, bool BK>
+constexpr bool shared_split() {
+  return L > 1 && N >= 6 && !BK;
+}
+
 // tiles stay at <= 512 threads (a 1024-thread workgroup caps a wave at 128
 // registers, below what most density updates need), except split FP32 tiles
 // with up to 3 levels, whose waves fit in 128; five and six levels use at most
@@ -668,11 +688,15 @@ constexpr bool regs_fit() {
 template <int N, typename R, int B, int L, bool VC, int SUB, bool ST, bool P, bool CY, bool BK, bool Q = false>
 __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, const DevTile *__restrict__ tiles,
                                            int tix, int qchunk, int64_t n0, int parity, int halo, int k,
-                                           const ChunkSync &cs, TileShared<N, R, B, L> &sm) {
+                                           const ChunkSync &cs, TileShared<N, R, B, L> &sm, int rt_sub = 0) {
   using CL = Cell<N, R, BK>;
   using SP = Split<N, L, BK>;
   constexpr int M = CL::M, MA = CL::MA, S = stride_of(N, BK);
   constexpr bool WAVE = B == 64 && L == 1;  // one wave per tile: neighbours by DPP, no barriers
+  // the wave group: SUB, or (kernels whose wave groups share one copy of the
+  // step code, RT) the wave-uniform rt_sub
+  constexpr bool RT = shared_split<N, L, BK>();
+  const int sub = RT ? rt_sub : SUB;
   constexpr int SQ = S - kCoefKap;          // quantum part of a material's coefficients
   const DevTile tile = tiles[tix];
   // fields used inside the step loop are copied to locals below, so stores to
@@ -685,7 +709,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
   }
   const int nx = int(sim.nx);
   const cptr<R> mtab = kconst<R>(sim.mtab);
-  const int l = int(threadIdx.x) - SUB * B;  // cell lane
+  const int l = int(threadIdx.x) - sub * B;  // cell lane
   const int lo = tile.c0 - halo;
   const int c = lo + l;
   const bool in = c >= 0 && c < nx;
@@ -770,9 +794,9 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
     const int rbase = sim.rec_first[o0], n_tr = sim.rec_first[o1] - rbase;
     rec_lds = n_tr <= kTileRecs;
     if (rec_lds && int(threadIdx.x) < n_tr) sm.trec.stage(sim, int(threadIdx.x), rbase + int(threadIdx.x));
-    if (own && (rec_lds ? SUB < RS : SUB == 0)) {
+    if (own && (rec_lds ? sub < RS : sub == 0)) {
       record_range(sim, c, rb, re);
-      for (int r = rb + (rec_lds ? SUB : 0); r < re; r += rec_lds ? RS : 1) {
+      for (int r = rb + (rec_lds ? sub : 0); r < re; r += rec_lds ? RS : 1) {
         const int qty = sim.rec_cell[r].quantity;
         rec_fld = rec_fld || qty < 2 || !qm;  // E or H, or a density quantity outside the medium
       }
@@ -782,8 +806,8 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
       }
     }
   }
-  const bool rec_here = SUB < RS && own && (re > rb || (SUB == 0 && sim.n_rec_all > 0));
-  const bool rec_fields_here = rec_here && (rec_fld || (SUB == 0 && sim.n_rec_all > 0));
+  const bool rec_here = sub < RS && own && (re > rb || (sub == 0 && sim.n_rec_all > 0));
+  const bool rec_fields_here = rec_here && (rec_fld || (sub == 0 && sim.n_rec_all > 0));
   const bool rec_tile = sim.rec_first != nullptr || sim.n_rec_all > 0;  // uniform
   const uint32_t rec_every = uint32_t(sim.rec_every);
   const double h_scale = sim.h_scale;
@@ -851,7 +875,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
     if constexpr (L > 1 && N > 0) {
 #pragma unroll
       for (int a = 0; a < M; ++a)
-        if (SP::owns(SUB, a)) sm.sx[a][l] = x[a];
+        if (SP::owns(sub, a)) sm.sx[a][l] = x[a];
     }
   };
 
@@ -896,11 +920,11 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
         if (qm) {
 #pragma unroll
           for (int a = 0; a < M; ++a)
-            if (SP::owns(SUB, a)) x[a] = ld(x_in + a * nx + c);
+            if (SP::owns(sub, a)) x[a] = ld(x_in + a * nx + c);
           if constexpr (CL::KC) {
 #pragma unroll
             for (int a = 0; a < M; ++a)
-              if (SP::owns(SUB, a)) xc[a] = ld(x_in + (M + a) * nx + c);
+              if (SP::owns(sub, a)) xc[a] = ld(x_in + (M + a) * nx + c);
           }
         }
       }
@@ -933,7 +957,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
         er = lane_from_right(e);
         el = lane_from_left(e);
       } else {
-        if (SUB == 0) sm.se[buf][l] = e;
+        if (sub == 0) sm.se[buf][l] = e;
         __syncthreads();
         er = l + 1 < B ? sm.se[buf][l + 1] : R(0);
         el = l > 0 ? sm.se[buf][l - 1] : R(0);
@@ -942,7 +966,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
         if (qm) {
 #pragma unroll
           for (int a = 0; a < M; ++a)
-            if (!SP::owns(SUB, a)) x[a] = sm.sx[a][l];
+            if (!SP::owns(sub, a)) x[a] = sm.sx[a][l];
         }
       }
       h = hcell ? fma(ch, er - e, h) : h;
@@ -987,14 +1011,14 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
           if (rec_step) {
             if (rec_here) {
               if (rec_lds) {
-                sm.trec.density(rq, x, z, rb + SUB, re, RS);
-                if (SUB == 0) record_density_all<N, R>(sim, c, n1, mm, x, z);
+                sm.trec.density(rq, x, z, rb + sub, re, RS);
+                if (sub == 0) record_density_all<N, R>(sim, c, n1, mm, x, z);
               } else {
                 record_density<N, R>(sim, c, n1, mm, x, z, rb, re);
               }
             }
           }
-          CL::template propagate<L, SUB>(x, xc, z, mt);
+          CL::template propagate<L>(x, xc, z, mt, sub);
         };
         if constexpr (L == 1) {
           per_material([&](const auto &mt, int mm) {
@@ -1003,15 +1027,15 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
           });
         } else {
           // this group's coherence rows, exchanged through LDS
-          per_material([&](const auto &mt, int) { CL::template coherences<L, SUB>(x, z, mt); });
+          per_material([&](const auto &mt, int) { CL::template coherences<L>(x, z, mt, sub); });
 #pragma unroll
           for (int r = 0; r < CL::K; ++r)
-            if (SP::owns_z(SUB, r)) sm.sz[r][l] = z[r];
+            if (SP::owns_z(sub, r)) sm.sz[r][l] = z[r];
           __syncthreads();
           if (qm) {
 #pragma unroll
             for (int r = 0; r < CL::K; ++r)
-              if (!SP::owns_z(SUB, r)) z[r] = sm.sz[r][l];
+              if (!SP::owns_z(sub, r)) z[r] = sm.sz[r][l];
           }
           per_material(finish);
         }
@@ -1024,7 +1048,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
           enr = lane_from_right(e);
           enl = lane_from_left(e);
         } else {
-          if (SUB == 0) sm.se2[l] = e;
+          if (sub == 0) sm.se2[l] = e;
           __syncthreads();
           enr = l + 1 < B ? sm.se2[l + 1] : R(0);
           enl = l > 0 ? sm.se2[l - 1] : R(0);
@@ -1057,8 +1081,8 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
           if (rec_step) {
             if (rec_here) {
               if (rec_lds) {
-                sm.trec.density(rq, x, z, rb + SUB, re, RS);
-                if (SUB == 0) record_density_all<N, R>(sim, c, n1, mm, x, z);
+                sm.trec.density(rq, x, z, rb + sub, re, RS);
+                if (sub == 0) record_density_all<N, R>(sim, c, n1, mm, x, z);
               } else {
                 record_density<N, R>(sim, c, n1, mm, x, z, rb, re);
               }
@@ -1070,8 +1094,8 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
       if (rec_step) {
         if (rec_fields_here) {
           if (rec_lds) {
-            sm.trec.fields(rq, e, hcell ? double(h) * h_scale : 0.0, qm, rb + SUB, re, RS);
-            if (SUB == 0) record_fields_all(sim, c, n1, e, hcell ? double(h) * h_scale : 0.0, qm);
+            sm.trec.fields(rq, e, hcell ? double(h) * h_scale : 0.0, qm, rb + sub, re, RS);
+            if (sub == 0) record_fields_all(sim, c, n1, e, hcell ? double(h) * h_scale : 0.0, qm);
           } else {
             record_fields(sim, c, n1, e, hcell ? double(h) * h_scale : 0.0, qm, rb, re);
           }
@@ -1091,7 +1115,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
         else
           *ptr = v;
       };
-      if (SUB == 0) {
+      if (sub == 0) {
         st(e_out + c, e);
         st(h_out + c, h);
       }
@@ -1099,11 +1123,11 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
         if (qm) {
 #pragma unroll
           for (int a = 0; a < M; ++a)
-            if (SP::owns(SUB, a)) st(x_out + a * nx + c, x[a]);
+            if (SP::owns(sub, a)) st(x_out + a * nx + c, x[a]);
           if constexpr (CL::KC) {
 #pragma unroll
             for (int a = 0; a < M; ++a)
-              if (SP::owns(SUB, a)) st(x_out + (M + a) * nx + c, xc[a]);
+              if (SP::owns(sub, a)) st(x_out + (M + a) * nx + c, xc[a]);
           }
           if constexpr (ST) {
             st(sim.qs[par ^ 1] + c, qn);
@@ -1111,7 +1135,7 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
           }
         }
       }
-      if (SUB == 0 && (!isfinite(double(e)) || !isfinite(double(h)))) atomicOr(sim.status, kStatusNonFinite);
+      if (sub == 0 && (!isfinite(double(e)) || !isfinite(double(h)))) atomicOr(sim.status, kStatusNonFinite);
     }
     if (Q) {
       // work-queue item done: every wave's coherent stores are complete
@@ -1146,7 +1170,9 @@ template <int N, typename R, int B, int L, bool VC, bool P, bool CY, bool BK, in
 __device__ __forceinline__ void run_group(int sub, const DevSim *__restrict__ sims, const DevTile *__restrict__ tiles,
                                           int64_t n0, int parity, int halo, int k, const ChunkSync &cs,
                                           TileShared<N, R, B, L> &sm) {
-  if constexpr (S + 1 < L) {
+  if constexpr (shared_split<N, L, BK>()) {
+    tile_steps<N, R, B, L, VC, 0, false, P, CY, BK>(sims, tiles, blockIdx.x, -1, n0, parity, halo, k, cs, sm, sub);
+  } else if constexpr (S + 1 < L) {
     if (sub == S)
       tile_steps<N, R, B, L, VC, S, false, P, CY, BK>(sims, tiles, blockIdx.x, -1, n0, parity, halo, k, cs, sm);
     else

@@ -107,14 +107,18 @@ struct mb_server {
 };
 
 // Tile shape of one lane for the cells it holds.  Few cells: latency
-// shapes (deep halos, large density updates on 128-cell tiles split over up
-// to 4 waves per 64 cells); many cells: 256-cell tiles with shallow halos,
-// which redo fewer halo cells.  The split itself follows the tile count.
+// shapes (deep halos; large density updates on 128-cell tiles split over up
+// to 2 waves per 64 cells, six levels on 64-cell tiles over 4); many cells:
+// 256-cell tiles with shallow halos, which redo fewer halo cells.  The split
+// itself follows the tile count.
 static void server_shape(int levels, int64_t cells, int chunk_steps, int &block, int &halo) {
   const bool busy = cells > (levels >= 4 ? 65536 : 196608);
   if (busy) {
     block = 256;
     halo = 32;
+  } else if (levels >= 6) {
+    block = 64;  // with 4 wave groups per 64 cells
+    halo = 16;
   } else if (levels >= 4) {
     block = 128;
     halo = 32;
