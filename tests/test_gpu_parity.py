@@ -198,7 +198,8 @@ def _stored(name):
 def test_lambda3_full_run_vs_stored_oracle_records():
     """The Lambda workload over all 200000 steps (Alg. 1 on the full 32768-cell grid, the
     Gaussian train of Sec. 4-style drive crossing the first probes) against the oracle's
-    records, every 100th step of each of the 192 traces: FP64 within 1e-10 per trace.
+    records, every 100th step of each of the 192 traces: FP64 within 1e-10 and FP32 within
+    1e-4 per trace.
     The records see the drive: an undriven run differs from them by far more than 1e-4 on
     at least 20 probes."""
     d, fingerprint = _stored("oracle_lambda3.npz")
@@ -214,7 +215,8 @@ def test_lambda3_full_run_vs_stored_oracle_records():
     assert max(errs.values()) <= TOL[64], worst(errs)
     got32 = sub(gpu_run(prob, precision=32))
     errs32 = rel_errors(prob, got32, ref)
-    _say(f"lambda3 full fp32 worst {worst(errs32)} (tolerance not asserted over 200000 steps)")
+    _say(f"lambda3 full fp32 worst {worst(errs32)}")
+    assert max(errs32.values()) <= TOL[32], worst(errs32)
     quiet = dict(prob)
     quiet["sources"] = [dict(src, amp=0.0) for src in prob["sources"]]
     undriven = rel_errors(prob, sub(gpu_run(quiet, precision=64)), ref)
