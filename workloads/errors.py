@@ -12,7 +12,7 @@ divided by its own rounding noise:
 * density-matrix quantities (populations, inversions, coherences): 1e-3.  They
   are numbers in [-1, 1] computed with the O(1) elements of the same state, so
   their rounding is absolute, of the size of the state's unit roundoff; a level
-  that stays (nearly) empty is judged on 1e-3.
+  that stays (nearly) empty is measured against 1e-3.
 * E: 1 V/m, the smallest field scale of any workload here (the noise that
   starts a laser cavity); H: 1 V/m over the vacuum impedance.
 
