@@ -510,6 +510,8 @@ def main(argv=None):
                     help="comma list of optional legs to run (fp64,cpu,batch,sub32,configs,serve); others are skipped")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the 200/s Poisson trace (2000 = the full 10 s trace)")
+    ap.add_argument("--coupling", default="weak", choices=("weak", "strong"),
+                    help="coupling of the main workload's density step to E (weak: rho half a step after E)")
     ap.add_argument("--field-step", default="exact", choices=("exact", "cayley"),
                     help="field part of the density step of the main workload (exact exponential or Cayley)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -536,7 +538,9 @@ def main(argv=None):
         hip.copy_calibration(args.copy_bytes)
     prob = W.lambda3(nx=args.nx, n_steps=args.nt, precision=32)
     prob["field_step"] = args.field_step
-    wname = "lambda3-3lvl" + ("-cayley" if args.field_step == "cayley" else "")
+    prob["coupling"] = args.coupling
+    wname = "lambda3-3lvl" + ("-cayley" if args.field_step == "cayley" else "") + \
+        ("-strong" if args.coupling == "strong" else "")
     n_levels = 3
     cells = prob["nx"] * prob["n_steps"]
 
@@ -568,14 +572,15 @@ def main(argv=None):
     log(f"[bench] fp32 blocked: {value:.3e} cell-updates/s, {n_launch} launch(es) of {steps_per_launch} steps "
         f"(persistent={persistent}), {avg_kernel_us:.2f} us per launch, {chunk_us:.2f} us per {depth}-step chunk")
 
-    kname = f"k_blocked<3,float,{block},{lanes},{str(regs).lower()}>"
+    kname = f"k_blocked<3,float,{block},{lanes},{str(regs).lower()}" + (",strong>" if args.coupling == "strong" else ">")
     traffic = measured_traffic(kname, f"{wname}/nx{prob['nx']}", depth, steps_per_launch)
     out = {
         "metric": "cell-updates/s (FP64 plain vs FP32 batched) at stated error; p50/p99 solve latency",
         "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": wname, "field_step": args.field_step, "nx": prob["nx"], "n_steps": prob["n_steps"], "levels": 3,
+        "config": {"workload": wname, "field_step": args.field_step, "coupling": args.coupling,
+                   "nx": prob["nx"], "n_steps": prob["n_steps"], "levels": 3,
                    "materials": len(prob["materials"]), "records": len(prob["records"]),
                    "variant": "blocked", "block": block, "depth": depth, "regs": regs, "lanes": lanes, "setup_s": t_setup,
                    "step": "one full solve of the workload"},
