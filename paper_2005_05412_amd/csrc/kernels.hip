@@ -979,18 +979,28 @@ __device__ __forceinline__ void tile_steps(const DevSim *__restrict__ sims, cons
         // d_q = (e^{i theta_q} - 1) z_q, is written out per pair once per step,
         // so an iteration costs the phases and 2 FP64 multiply-adds per pair.
         per_material([&](const auto &mt, int mm) {
-          const cptr<double> qt = kconst<double>(sim.qtab) + __builtin_amdgcn_readfirstlane(mm * ro_len(N));
           CL::coherences(x, z, mt);
-          sA = qt[0];
+          auto readout_terms = [&](const cptr<double> qt) {
+            sA = qt[0];
 #pragma unroll
-          for (int t = 0; t < M; ++t) sA = fma(qt[1 + t], double(x[t]), sA);
+            for (int t = 0; t < M; ++t) sA = fma(qt[1 + t], double(x[t]), sA);
 #pragma unroll
-          for (int q = 0; q < CL::P; ++q) {
-            const double zr = double(z[2 * q]), zi = double(z[2 * q + 1]);
-            const double qr = qt[1 + M + 2 * q], qi = qt[2 + M + 2 * q];
-            sal[q] = fma(qr, zr, qi * zi);
-            sbe[q] = fma(qi, zr, -(qr * zi));
-          }
+            for (int q = 0; q < CL::P; ++q) {
+              const double zr = double(z[2 * q]), zi = double(z[2 * q + 1]);
+              const double qr = qt[1 + M + 2 * q], qi = qt[2 + M + 2 * q];
+              sal[q] = fma(qr, zr, qi * zi);
+              sbe[q] = fma(qi, zr, -(qr * zi));
+            }
+          };
+          // the material's readout row: scalar loads when the wave's quantum
+          // lanes share one material (always with scalar coefficient loads),
+          // else the lane's own row (register coefficients: a wave may cross a
+          // material boundary)
+          const int m0 = __builtin_amdgcn_readfirstlane(mm);
+          if (!VC || __builtin_amdgcn_ballot_w64(mm != m0) == 0)
+            readout_terms(kconst<double>(sim.qtab) + m0 * ro_len(N));
+          else
+            readout_terms(kconst<double>(sim.qtab) + mm * ro_len(N));
           R pi = pprev;
           for (int it = 0; it < strong_iters<R>(); ++it) {
             const R es = fma(cbd, h - hl, fma(ca, e, -(cbg * pi)));
@@ -1326,7 +1336,8 @@ hipError_t launch_shape(const DevSim *sims, const DevTile *tiles, int n_tiles, i
     // register coefficients are not built for this shape: the same arithmetic
     // with scalar coefficient loads
     return launch_shape<N, R, B, L, false, ST, P, CY, BK>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
-  } else if constexpr (shape_fits<N, R, B, L>() && (!ST || (L == 1 && !VC && N >= 2)) && (!CY || N >= 2)) {
+  } else if constexpr (shape_fits<N, R, B, L>() && (!ST || (L == 1 && N >= 2 && (!VC || (N == 3 && B == 256)))) &&
+                       (!CY || N >= 2)) {
     auto kern = k_blocked<N, R, B, L, VC, ST, P, CY, BK>;
     if (per_cu) return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kern, B * L, 0);
     kern<<<n_tiles, B * L, 0, st>>>(sims, tiles, n0, parity, halo, k, cs);
@@ -1361,6 +1372,11 @@ hipError_t launch_blocked_nr(int block, int lanes, bool vc, bool strong, const D
   if constexpr (P && CY)
     if (lanes != 1 && !strong) return hipErrorInvalidValue;
   if (strong) {
+    // register coefficients for three-level FP32 tiles of 256 cells (the
+    // strong step's field iteration otherwise waits on scalar coefficient loads)
+    if constexpr (N == 3 && sizeof(R) == 4)
+      if (vc && block == 256)
+        return launch_shape<N, R, 256, 1, true, true, P, CY, BK>(sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
     if constexpr (N >= 2)
       return launch_blocked_b<N, R, 1, false, true, P, CY, BK>(block, sims, tiles, n_tiles, n0, parity, halo, k, cs, per_cu, st);
     return hipErrorInvalidValue;

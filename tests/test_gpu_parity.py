@@ -781,6 +781,8 @@ def test_strong_coupling_vs_oracle(case):
     got32 = gpu_run(prob, precision=32, variant="blocked", block=128, depth=16)
     errs32 = rel_errors(prob, got32, ref)
     assert max(errs32.values()) <= TOL[32], errs32
+    # three-level FP32 256-cell tiles also run with register coefficients: same bits
+    assert_same(gpu_run(prob, precision=32, variant="blocked_regs", block=256, depth=32), got32)
 
 
 def test_strong_coupling_sit_prefix_and_mixed_batch():
