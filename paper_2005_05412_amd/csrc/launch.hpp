@@ -21,7 +21,8 @@ int plain_block();
 // block*lanes threads.
 // vc: quantum coefficients of single-material waves held in registers
 // (used for 2 and 3 levels, ignored otherwise).
-// strong: strong-coupling simulations (one wave per 64 cells, no register coefficients)
+// strong: strong-coupling simulations (one wave per 64 cells; register
+// coefficients only on three-level FP32 tiles of 256 cells)
 // cayley: simulations with the Cayley field step (persistent launches with
 // one wave per 64 cells only)
 // bk: simulations whose density tables are in the block form (engine.hpp)
