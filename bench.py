@@ -186,6 +186,9 @@ def stored_lambda3_records(prob):
     path = os.path.join(ROOT, "tests", "golden", "oracle_lambda3.npz")
     if not os.path.exists(path) or prob["nx"] != 32768 or prob["n_steps"] != 200000:
         return None
+    # the records are those of weak coupling and the exact field step
+    if prob.get("coupling", "weak") != "weak" or prob.get("field_step", "exact") != "exact":
+        return None
     d = np.load(path)
     stride = int(d["lambda3/stride"])
     return {r["name"]: d["lambda3/" + r["name"]] for r in prob["records"]}, stride
