@@ -785,6 +785,28 @@ def test_strong_coupling_vs_oracle(case):
     assert_same(gpu_run(prob, precision=32, variant="blocked_regs", block=256, depth=32), got32)
 
 
+def test_strong_coupling_dense_medium():
+    """Strong coupling in a medium 4000 times denser than the random cases: there the field
+    update depends on the polarization enough (the oracle's fixed-point iteration contracts
+    by about 1e-3 per pass) that the FP64 bound of 1e-10 needs the Newton steps' derivative.
+    An FP64 emulation on the host of the same warm start (previous polarization current)
+    differs from the converged oracle by 1.3e-4 / 1.2e-7 / 1.2e-10 (worst trace) after one /
+    two / three fixed-point passes, and by 1.7e-6 / 2e-15 after one / two Newton steps (the
+    FP32 and FP64 kernels' counts)."""
+    prob = W.random_small(42, N=3, nx=150, n_steps=90, refl=(0.64, 0.0), soft=True)
+    prob["coupling"] = "strong"
+    for m in prob["materials"]:
+        if m.get("qm"):
+            m["qm"]["n3d"] *= 4000.0
+    _say("strong dense")
+    ref = O.run(prob)
+    for block, depth in ((128, 16), (256, 32)):
+        errs = rel_errors(prob, gpu_run(prob, precision=64, variant="blocked", block=block, depth=depth), ref)
+        assert max(errs.values()) <= TOL[64], worst(errs)
+    errs32 = rel_errors(prob, gpu_run(prob, precision=32, variant="blocked_regs", block=256, depth=32), ref)
+    assert max(errs32.values()) <= TOL[32], worst(errs32)
+
+
 def test_strong_coupling_sit_prefix_and_mixed_batch():
     """Two-level SIT with strong coupling, first 4000 steps against the oracle; a batch that
     mixes weakly and strongly coupled simulations gives each one's solo records."""
