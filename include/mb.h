@@ -102,9 +102,11 @@ extern "C" {
  * rho at t_{n+1/2} (the default), strong coupling at t_n with E; there the
  * step is driven by the midpoint field (E^n + E^{n+1})/2 and the
  * polarization current is n3D tr{mu (rho^{n+1} - rho^n)}/dt, the E update of
- * a quantum cell being solved by fixed-point iteration (3 iterations on the
- * GPU).  Strong coupling runs on the blocked variant only, with one wave per
- * 64 cells. */
+ * a quantum cell being an implicit equation, solved on the GPU from the cell's
+ * previous polarization current by Newton steps (one in FP32, two in FP64;
+ * with the Cayley field step by fixed-point iterations, two and three).
+ * Strong coupling runs on the blocked variant only, with one wave per 64
+ * cells. */
 #define MB_COUPLING_WEAK 0
 #define MB_COUPLING_STRONG 1
 
